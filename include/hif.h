@@ -1,0 +1,209 @@
+/*
+ * hif.h -- C ABI of the MI355X (gfx950) HIF-IE library.
+ *
+ * Hierarchical interpolative factorization for integral equations
+ * (K. L. Ho and L. Ying, arXiv 1307.2666).  The library factors the dense
+ * matrix of the discretized integral equation
+ *
+ *     a(x) u(x) + b(x) int K(|x - y|) c(y) u(y) dy = f(x)          (eqn 1.1)
+ *
+ * on collocation points x_i:  A = diag(a) + diag(b) K diag(c), with
+ * K_ij = G(|x_i - x_j|) w_j for i != j (one-point rule, Section 5) and K_ii the
+ * integral of G over the element of x_i (eqn kernel-integral, Section 3.1).
+ * G is the Laplace fundamental solution (eqn laplace-kernel): -log(r)/(2 pi)
+ * in 2D, 1/(4 pi r) in 3D.  The factorization F ~ A is the generalized LU
+ * decomposition of eqns (hifie2) / (hifie3) built by Algorithms 4.1 / 4.2
+ * (or the RSF of Algorithm 3.1, eqn rskelf); F and F^{-1} are applied in
+ * factored form.
+ *
+ * Conventions for every call:
+ *  - Pointers to arrays are DEVICE pointers on the current HIP device unless
+ *    stated otherwise.  All floating point arrays are IEEE double.
+ *  - points: [n][dim] row-major (point i at points[i*dim .. i*dim+dim-1]),
+ *    inside the closed unit box [0,1]^dim.
+ *  - a, b, c, weights, self: [n], in the caller's point order.
+ *  - Right-hand sides and solutions: [nrhs][n], each vector contiguous,
+ *    caller's point order.  In-place calls (x == y, f == u) are allowed.
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream).
+ *  - Inputs are borrowed for the duration of the call only; hif_factor copies
+ *    what later calls need into the handle.  The handle owns all device
+ *    memory it allocates until hif_free.  A handle serves one stream at a
+ *    time.
+ *  - Errors: every call returns a hif_status; negative values are errors and
+ *    hif_last_error() gives a message (thread-local).  Nothing is thrown
+ *    across the ABI.  Argument checks that need no device data (NULL
+ *    pointers, sizes, dim, eps, leaf, option ranges) run on the host before
+ *    any device work.
+ */
+#ifndef HIF_H
+#define HIF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hif_factor_s* hif_handle;  /* opaque, library-owned */
+typedef void* hif_stream;                 /* hipStream_t */
+
+typedef enum {
+  HIF_OK = 0,
+  HIF_EINVAL = -1,        /* bad argument, non-finite input, point outside [0,1]^d, coincident points */
+  HIF_ENOMEM = -2,        /* device allocation failed or opts.max_bytes exceeded */
+  HIF_ESINGULAR = -3,     /* zero pivot in a redundant block B_rr or the top block (Lemma 2.1) */
+  HIF_EDEVICE = -4,       /* HIP runtime error */
+  HIF_EUNSUPPORTED = -5   /* valid request this build does not handle (e.g. non-uniform tree depth) */
+} hif_status;
+
+enum { HIF_FP64 = 0, HIF_FP32_MIXED = 1 };
+enum { HIF_VARIANT_HIFIE = 0, HIF_VARIANT_RSF = 1 };
+
+/*
+ * Kernel description (Laplace only).  Off-diagonal weight w_j = weights[j]
+ * if given, else h^dim.  Diagonal K_ii = self[i] if given, else the closed
+ * form of the integral of G over the cube of side h centred at x_i:
+ *   2D: -(h^2/(2 pi)) (log(h/sqrt 2) - 3/2 + pi/4),
+ *   3D: h^2 (3 log(2 + sqrt 3) - pi/2) / (4 pi).
+ */
+typedef struct {
+  double h;                 /* grid step (> 0 unless both arrays are given) */
+  const double* weights;    /* optional [n] device */
+  const double* self;       /* optional [n] device */
+} hif_kernel;
+
+/*
+ * Factorization options.  hif_opts_default fills the defaults.
+ *  precision:    HIF_FP64 (only value supported in this build).
+ *  second_kind:  1 = Section 4.4 modification (rho-scaled local tolerance and
+ *                split compression by SCI sparsity pattern; "hifie2x/3x"),
+ *                0 = plain compression, -1 = auto (1).
+ *  symmetric:    1 = compress only the column block Y'_c (Section 5; valid
+ *                when A is symmetric), 0 = full Y_c of eqn proxy-id,
+ *                -1 = auto (symmetric iff b_i == s c_i w_i for one scalar s).
+ *  variant:      HIF_VARIANT_HIFIE (Algorithms 4.1/4.2) or HIF_VARIANT_RSF
+ *                (Algorithm 3.1, cells only).
+ *  n_proxy:      proxy points, 0 = 64 (2D circle) / 512 (3D sphere) (Section 3.3).
+ *  proxy_radius: proxy radius in units of the cell width, 0 = 1.5 (Section 3.3).
+ *  max_bytes:    cap on device memory the factorization may hold, 0 = none.
+ */
+typedef struct {
+  int precision;
+  int second_kind;
+  int symmetric;
+  int variant;
+  int n_proxy;
+  double proxy_radius;
+  size_t max_bytes;
+} hif_opts;
+
+#define HIF_MAX_SUBLEVELS 64
+
+/* Statistics of a factorization (the quantities of Section 5 plus timings). */
+typedef struct {
+  int64_t n;
+  int32_t dim;
+  int32_t levels;                 /* tree depth L */
+  int32_t n_sublevels;            /* 2L (2D) or 3L (3D); L for RSF */
+  int64_t top_size;               /* |s_L| */
+  int64_t factor_bytes;           /* m_f: bytes of stored factors */
+  double t_factor_ms;             /* wall time of hif_factor */
+  double t_phase_ms[8];           /* partition+near field, assembly, ID, elimination,
+                                     SCI update, top LU, host sync/alloc, other */
+  int32_t sub_kind[HIF_MAX_SUBLEVELS];     /* 0 cell, 1 face, 2 edge */
+  int32_t sub_groups[HIF_MAX_SUBLEVELS];   /* nonempty groups */
+  int64_t sub_active[HIF_MAX_SUBLEVELS];   /* active DOFs entering the sub-level */
+  int64_t sub_skel[HIF_MAX_SUBLEVELS];     /* sum of skeleton sizes */
+  int64_t sub_near[HIF_MAX_SUBLEVELS];     /* sum of near-field sizes */
+  int64_t sub_classes[HIF_MAX_SUBLEVELS];  /* ID problems solved (split classes) */
+  double sub_id_flops[HIF_MAX_SUBLEVELS];  /* algorithmic flops of the IDs */
+  double sub_elim_flops[HIF_MAX_SUBLEVELS];/* algorithmic flops of the eliminations */
+} hif_stats_t;
+
+/* Fill *opts with the defaults listed above.  Returns HIF_EINVAL if opts is NULL. */
+hif_status hif_opts_default(hif_opts* opts);
+
+/*
+ * Build F ~ A by HIF-IE (Algorithms 4.1/4.2) or RSF (Algorithm 3.1).
+ *   points, n, dim: collocation points (see conventions), dim in {2, 3}.
+ *   k:    kernel weights / self terms (must not be NULL).
+ *   a:    [n] or NULL (a = 0, first kind);  b, c: [n] or NULL (= 1).
+ *   eps:  relative ID precision, 0 < eps < 1 (Section 2.2).
+ *   leaf: maximum points per leaf box (>= 1); the adaptive tree must have
+ *         all its leaves at one depth, else HIF_EUNSUPPORTED.
+ *   opts: NULL for defaults.
+ *   out:  receives the handle (set to NULL on error).
+ * Host-blocking: sizes that depend on the ranks are read back once per
+ * sub-level.  Coincident points, non-finite values or points outside the
+ * unit box give HIF_EINVAL; a singular B_rr or top block HIF_ESINGULAR.
+ */
+hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel* k,
+                      const double* a, const double* b, const double* c,
+                      double eps, int32_t leaf, const hif_opts* opts,
+                      hif_stream stream, hif_handle* out);
+
+/* y = F x (generalized FMM; eqn hifie2/hifie3 first line).  x, y: [nrhs][n]. Stream-ordered. */
+hif_status hif_apply(hif_handle h, const double* x, double* y, int64_t nrhs, hif_stream stream);
+/* y = F^T x. */
+hif_status hif_apply_T(hif_handle h, const double* x, double* y, int64_t nrhs, hif_stream stream);
+/* u = F^{-1} f (direct solver / preconditioner; eqn hifie2/hifie3 second line). */
+hif_status hif_solve(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream stream);
+/* u = F^{-T} f. */
+hif_status hif_solve_T(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream stream);
+
+/*
+ * y = A x evaluated exactly on the fly in O(n^2) (the operator of eqn 1.1
+ * under the discretization of Section 3.1; no factorization involved).
+ * Arguments as in hif_factor; x, y: [nrhs][n], y must not alias x.
+ * Stream-ordered.
+ */
+hif_status hif_matvec(const double* points, int64_t n, int dim, const hif_kernel* k,
+                      const double* a, const double* b, const double* c,
+                      const double* x, double* y, int64_t nrhs, hif_stream stream);
+
+/* Copy the statistics of a factorization into *out (host memory). */
+hif_status hif_stats(hif_handle h, hif_stats_t* out);
+
+/* Release a handle and all its device memory (NULL is a no-op). */
+void hif_free(hif_handle h);
+
+/* Message of the last error on this thread ("" if none). */
+const char* hif_last_error(void);
+
+/*
+ * Batched interpolative decomposition (Lemma 2.2 with the adaptive rank rule
+ * of Section 2.2): the kernel hif_factor uses for every compression, exposed
+ * on its own.  For p = 0..batch-1, matrix p is Y_p = mats + off[p], row-major
+ * with rows[p] rows, cols[p] columns and leading dimension cols[p].
+ * Pivot i is kept iff |R_ii| > tol[p] |R_00| (column-pivoted Householder QR,
+ * norms recomputed each step, ties to the lowest column index).
+ * Outputs (device): rank[p]; perm + off_perm[p]: cols[p] entries, the skeleton
+ * columns in pivot order followed by the redundant columns in ascending order;
+ * T + off_t[p]: rank x (cols - rank) row-major interpolation matrix with
+ * Y[:, redundant] ~= Y[:, skeleton] T.  mats is overwritten.  All offset and
+ * size arrays are device arrays of length batch (int64 offsets, int32 sizes).
+ */
+hif_status hif_id_batched(double* mats, const int64_t* off, const int32_t* rows,
+                          const int32_t* cols, const double* tol, int32_t batch,
+                          int32_t max_cols, int32_t* rank, int32_t* perm,
+                          const int64_t* off_perm, double* T, const int64_t* off_t,
+                          hif_stream stream);
+
+/*
+ * Group assignment of one sub-level (Sections 3.1, 4.1, 4.2): for every
+ * active point (active[i] != 0), group[i] = index of its cell (kind 0,
+ * containing box, first coordinate slowest), face (kind 1, 3D) or edge
+ * (kind 2) centre among the interior centres of a grid of S boxes per side,
+ * enumerated family by family in the paper's order with the first index
+ * slowest; nearest centre by squared distance, ties to the lowest index.
+ * Inactive points get -1.  group: [n] int32 device.
+ */
+hif_status hif_partition(const double* points, int64_t n, int dim, const uint8_t* active,
+                         int kind, int32_t S, int32_t* group, hif_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIF_H */

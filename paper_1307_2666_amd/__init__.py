@@ -1,0 +1,12 @@
+"""MI355X-native HIF-IE (hierarchical interpolative factorization for integral
+equations, Ho & Ying, arXiv 1307.2666): Python binding of the HIP library.
+
+``factor`` builds ``F ~ A`` on the GPU (Algorithms 4.1 / 4.2, or the RSF of
+Algorithm 3.1); the returned handle applies ``F``, ``F^T``, ``F^{-1}``,
+``F^{-T}``.  ``matvec`` is the exact on-the-fly ``A x``.
+"""
+from ._binding import (EXPORTS, HIF_FP32_MIXED, HIF_FP64, Factorization, HifError, LIB_PATH,  # noqa: F401
+                       default_opts, factor, id_batched, load_library, matvec, partition)
+
+__all__ = ["factor", "matvec", "id_batched", "partition", "Factorization", "HifError", "load_library",
+           "default_opts", "LIB_PATH", "EXPORTS"]

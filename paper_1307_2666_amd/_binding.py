@@ -1,0 +1,278 @@
+"""ctypes binding of ``libhif.so`` (the C ABI in ``include/hif.h``).
+
+Argument marshalling only: every step of the factorization and of the
+sweeps runs in the library's HIP kernels.  PyTorch supplies device memory
+and the current stream.  The library must be built (``build.py``); nothing
+here falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhif.so")
+
+HIF_OK, HIF_EINVAL, HIF_ENOMEM, HIF_ESINGULAR, HIF_EDEVICE, HIF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+HIF_FP64, HIF_FP32_MIXED = 0, 1
+HIF_VARIANT_HIFIE, HIF_VARIANT_RSF = 0, 1
+MAX_SUB = 64
+PHASES = ("partition", "assembly", "id", "elimination", "sci", "top", "host", "other")
+_STATUS = {0: "HIF_OK", -1: "HIF_EINVAL", -2: "HIF_ENOMEM", -3: "HIF_ESINGULAR", -4: "HIF_EDEVICE",
+           -5: "HIF_EUNSUPPORTED"}
+
+
+class HifError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class hif_kernel(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("weights", ctypes.c_void_p), ("self", ctypes.c_void_p)]
+
+
+class hif_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("second_kind", ctypes.c_int), ("symmetric", ctypes.c_int),
+                ("variant", ctypes.c_int), ("n_proxy", ctypes.c_int), ("proxy_radius", ctypes.c_double),
+                ("max_bytes", ctypes.c_size_t)]
+
+
+class hif_stats_t(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("n_sublevels", ctypes.c_int32), ("top_size", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
+                ("t_factor_ms", ctypes.c_double), ("t_phase_ms", ctypes.c_double * 8),
+                ("sub_kind", ctypes.c_int32 * MAX_SUB), ("sub_groups", ctypes.c_int32 * MAX_SUB),
+                ("sub_active", ctypes.c_int64 * MAX_SUB), ("sub_skel", ctypes.c_int64 * MAX_SUB),
+                ("sub_near", ctypes.c_int64 * MAX_SUB), ("sub_classes", ctypes.c_int64 * MAX_SUB),
+                ("sub_id_flops", ctypes.c_double * MAX_SUB), ("sub_elim_flops", ctypes.c_double * MAX_SUB)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_INT = ctypes.c_int
+_DBL = ctypes.c_double
+
+EXPORTS = {
+    "hif_opts_default": (_INT, [_VP]),
+    "hif_factor": (_INT, [_VP, _I64, _INT, _VP, _VP, _VP, _VP, _DBL, _I32, _VP, _VP, _VP]),
+    "hif_apply": (_INT, [_VP, _VP, _VP, _I64, _VP]),
+    "hif_apply_T": (_INT, [_VP, _VP, _VP, _I64, _VP]),
+    "hif_solve": (_INT, [_VP, _VP, _VP, _I64, _VP]),
+    "hif_solve_T": (_INT, [_VP, _VP, _VP, _I64, _VP]),
+    "hif_matvec": (_INT, [_VP, _I64, _INT, _VP, _VP, _VP, _VP, _VP, _VP, _I64, _VP]),
+    "hif_stats": (_INT, [_VP, _VP]),
+    "hif_free": (None, [_VP]),
+    "hif_last_error": (ctypes.c_char_p, []),
+    "hif_id_batched": (_INT, [_VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "hif_partition": (_INT, [_VP, _I64, _INT, _VP, _INT, _I32, _VP, _VP]),
+}
+
+
+def load_library():
+    """Load ``libhif.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != HIF_OK:
+        raise HifError(status, load_library().hif_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, n=None, name="array"):
+    """Contiguous float64 CUDA tensor (host tensors are copied to the device)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    t = t.to(device="cuda", dtype=torch.float64).contiguous()
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} entries")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _kernel(h, weights, selfk):
+    return hif_kernel(float(h) if h is not None else 0.0, _ptr(weights), _ptr(selfk))
+
+
+def default_opts() -> hif_opts:
+    o = hif_opts()
+    _check(load_library().hif_opts_default(ctypes.byref(o)))
+    return o
+
+
+class Factorization:
+    """Handle of ``F ~ A`` on the device; ``solve`` / ``apply`` run the factored sweeps."""
+
+    def __init__(self, handle, n, dim, keep):
+        self._h = handle
+        self.n = n
+        self.dim = dim
+        self._keep = keep
+
+    def _run(self, fn, x, out=None, stream=None):
+        if self._h is None:
+            raise RuntimeError("factorization has been freed")
+        x = _dev(x)
+        vec = x.dim() == 1
+        X = x.reshape(1, -1) if vec else x
+        if X.shape[-1] != self.n:
+            raise ValueError(f"last dimension must be n = {self.n}")
+        Y = torch.empty_like(X) if out is None else out.reshape(X.shape)
+        _check(fn(self._h, _ptr(X), _ptr(Y), X.shape[0], _stream(stream)))
+        return Y.reshape(x.shape)
+
+    def solve(self, f, out=None, stream=None):
+        """``u = F^{-1} f``; ``f`` is ``(n,)`` or ``(nrhs, n)``."""
+        return self._run(load_library().hif_solve, f, out, stream)
+
+    def solve_T(self, f, out=None, stream=None):
+        return self._run(load_library().hif_solve_T, f, out, stream)
+
+    def apply(self, x, out=None, stream=None):
+        """``y = F x``."""
+        return self._run(load_library().hif_apply, x, out, stream)
+
+    def apply_T(self, x, out=None, stream=None):
+        return self._run(load_library().hif_apply_T, x, out, stream)
+
+    def stats(self) -> dict:
+        s = hif_stats_t()
+        _check(load_library().hif_stats(self._h, ctypes.byref(s)))
+        ns = s.n_sublevels
+        return {
+            "n": s.n, "dim": s.dim, "levels": s.levels, "n_sublevels": ns, "top_size": s.top_size,
+            "factor_bytes": s.factor_bytes, "t_factor_ms": s.t_factor_ms,
+            "t_phase_ms": dict(zip(PHASES, list(s.t_phase_ms))),
+            "sub_kind": list(s.sub_kind[:ns]), "sub_groups": list(s.sub_groups[:ns]),
+            "sub_active": list(s.sub_active[:ns]), "sub_skel": list(s.sub_skel[:ns]),
+            "sub_near": list(s.sub_near[:ns]), "sub_classes": list(s.sub_classes[:ns]),
+            "sub_id_flops": list(s.sub_id_flops[:ns]), "sub_elim_flops": list(s.sub_elim_flops[:ns]),
+        }
+
+    def free(self):
+        if self._h is not None:
+            load_library().hif_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, selfk=None,
+           second_kind=-1, symmetric=-1, variant="hifie", n_proxy=0, proxy_radius=0.0,
+           max_bytes=0, precision=HIF_FP64, stream=None) -> Factorization:
+    """``hif_factor``: build ``F ~ A`` for points ``(n, d)`` in the unit box."""
+    lib = load_library()
+    P = _dev(points)
+    if P.dim() != 2 or P.shape[1] not in (2, 3):
+        raise ValueError("points must be (n, 2) or (n, 3)")
+    n, d = P.shape
+    av, bv, cv = _dev(a, n, "a"), _dev(b, n, "b"), _dev(c, n, "c")
+    wv, sv = _dev(weights, n, "weights"), _dev(selfk, n, "selfk")
+    k = _kernel(h, wv, sv)
+    o = default_opts()
+    o.precision = precision
+    o.second_kind = second_kind
+    o.symmetric = symmetric
+    o.variant = HIF_VARIANT_RSF if variant == "rskel" else HIF_VARIANT_HIFIE
+    o.n_proxy = n_proxy
+    o.proxy_radius = proxy_radius
+    o.max_bytes = max_bytes
+    handle = ctypes.c_void_p()
+    _check(lib.hif_factor(_ptr(P), n, d, ctypes.byref(k), _ptr(av), _ptr(bv), _ptr(cv), float(eps), int(leaf),
+                          ctypes.byref(o), _stream(stream), ctypes.byref(handle)))
+    return Factorization(handle, n, d, None)
+
+
+def matvec(points, x, *, a=None, b=None, c=None, h=None, weights=None, selfk=None, out=None, stream=None):
+    """``hif_matvec``: exact ``y = A x`` on the fly; ``x`` is ``(n,)`` or ``(nrhs, n)``."""
+    lib = load_library()
+    P = _dev(points)
+    n, d = P.shape
+    x = _dev(x)
+    X = x.reshape(1, -1) if x.dim() == 1 else x
+    if X.shape[-1] != n:
+        raise ValueError("last dimension of x must be n")
+    av, bv, cv = _dev(a, n, "a"), _dev(b, n, "b"), _dev(c, n, "c")
+    wv, sv = _dev(weights, n, "weights"), _dev(selfk, n, "selfk")
+    k = _kernel(h, wv, sv)
+    Y = torch.empty_like(X) if out is None else out.reshape(X.shape)
+    _check(lib.hif_matvec(_ptr(P), n, d, ctypes.byref(k), _ptr(av), _ptr(bv), _ptr(cv), _ptr(X), _ptr(Y),
+                          X.shape[0], _stream(stream)))
+    return Y.reshape(x.shape)
+
+
+def id_batched(mats, tols, stream=None):
+    """``hif_id_batched`` on a list of 2-D matrices; returns ``[(sk, rd, T), ...]`` as CPU tensors."""
+    lib = load_library()
+    shapes = [tuple(m.shape) for m in mats]
+    flat = torch.cat([_dev(m).reshape(-1) for m in mats]) if mats else torch.zeros(0, device="cuda",
+                                                                                    dtype=torch.float64)
+    offs, poffs, toffs = [], [], []
+    o = po = to = 0
+    for (m, nc) in shapes:
+        offs.append(o)
+        poffs.append(po)
+        toffs.append(to)
+        o += m * nc
+        po += nc
+        to += nc * nc
+    dev = dict(device="cuda")
+    off = torch.tensor(offs, dtype=torch.int64, **dev)
+    rows = torch.tensor([s[0] for s in shapes], dtype=torch.int32, **dev)
+    cols = torch.tensor([s[1] for s in shapes], dtype=torch.int32, **dev)
+    tol = torch.tensor(list(tols), dtype=torch.float64, **dev)
+    rank = torch.zeros(len(mats), dtype=torch.int32, **dev)
+    perm = torch.zeros(max(po, 1), dtype=torch.int32, **dev)
+    poff = torch.tensor(poffs, dtype=torch.int64, **dev)
+    T = torch.zeros(max(to, 1), dtype=torch.float64, **dev)
+    toff = torch.tensor(toffs, dtype=torch.int64, **dev)
+    maxc = max([s[1] for s in shapes] + [1])
+    _check(lib.hif_id_batched(_ptr(flat), _ptr(off), _ptr(rows), _ptr(cols), _ptr(tol), len(mats), maxc,
+                              _ptr(rank), _ptr(perm), _ptr(poff), _ptr(T), _ptr(toff), _stream(stream)))
+    rank, perm, T = rank.cpu(), perm.cpu(), T.cpu()
+    out = []
+    for q, (m, nc) in enumerate(shapes):
+        k = int(rank[q])
+        p = perm[poffs[q]:poffs[q] + nc]
+        out.append((p[:k].clone(), p[k:].clone(), T[toffs[q]:toffs[q] + k * (nc - k)].reshape(k, nc - k).clone()))
+    return out
+
+
+def partition(points, active, kind, S, stream=None):
+    """``hif_partition``: group index of every active point at one sub-level (-1 if inactive)."""
+    lib = load_library()
+    P = _dev(points)
+    n, d = P.shape
+    act = torch.as_tensor(active).to(device="cuda", dtype=torch.uint8).contiguous()
+    grp = torch.empty(n, dtype=torch.int32, device="cuda")
+    _check(lib.hif_partition(_ptr(P), n, d, _ptr(act), int(kind), int(S), _ptr(grp), _stream(stream)))
+    return grp

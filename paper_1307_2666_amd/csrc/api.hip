@@ -1,0 +1,186 @@
+// C ABI entry points (include/hif.h): argument checks on the host, handle
+// lifecycle, error mapping.  No exception crosses the ABI.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "common.h"
+
+namespace hif {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(hif_status s, const std::string& msg) {
+  (void)s;
+  g_last_error = msg;
+}
+
+hif_status fail(hif_status s, const std::string& msg) {
+  set_error(s, msg);
+  return s;
+}
+
+template <class F>
+hif_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    f();
+    return HIF_OK;
+  } catch (const Error& e) {
+    return fail(e.status, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(HIF_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(HIF_EDEVICE, e.what());
+  } catch (...) {
+    return fail(HIF_EDEVICE, "unknown error");
+  }
+}
+
+static hif_status check_kernel(const hif_kernel* k) {
+  if (!k) return fail(HIF_EINVAL, "kernel description is NULL");
+  if (!(k->weights && k->self) && !(std::isfinite(k->h) && k->h > 0.0))
+    return fail(HIF_EINVAL, "kernel.h must be finite and > 0 unless weights and self are both given");
+  return HIF_OK;
+}
+
+}  // namespace hif
+
+using namespace hif;
+
+extern "C" {
+
+hif_status hif_opts_default(hif_opts* o) {
+  if (!o) return fail(HIF_EINVAL, "opts is NULL");
+  o->precision = HIF_FP64;
+  o->second_kind = -1;
+  o->symmetric = -1;
+  o->variant = HIF_VARIANT_HIFIE;
+  o->n_proxy = 0;
+  o->proxy_radius = 0.0;
+  o->max_bytes = 0;
+  return HIF_OK;
+}
+
+const char* hif_last_error(void) { return g_last_error.c_str(); }
+
+hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel* k, const double* a,
+                      const double* b, const double* c, double eps, int32_t leaf, const hif_opts* opts,
+                      hif_stream stream, hif_handle* out) {
+  if (!out) return fail(HIF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!points) return fail(HIF_EINVAL, "points is NULL");
+  if (n < 1) return fail(HIF_EINVAL, "n must be >= 1");
+  if (n > int64_t(INT32_MAX) - 1) return fail(HIF_EINVAL, "n must fit in int32");
+  if (dim != 2 && dim != 3) return fail(HIF_EINVAL, "dim must be 2 or 3");
+  if (hif_status s = check_kernel(k); s != HIF_OK) return s;
+  if (!(eps > 0.0 && eps < 1.0)) return fail(HIF_EINVAL, "eps must satisfy 0 < eps < 1");
+  if (leaf < 1) return fail(HIF_EINVAL, "leaf must be >= 1");
+  hif_opts o;
+  hif_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.precision != HIF_FP64 && o.precision != HIF_FP32_MIXED)
+    return fail(HIF_EINVAL, "opts.precision must be HIF_FP64 or HIF_FP32_MIXED");
+  if (o.precision == HIF_FP32_MIXED)
+    return fail(HIF_EUNSUPPORTED, "HIF_FP32_MIXED is not available in this build");
+  if (o.second_kind < -1 || o.second_kind > 1) return fail(HIF_EINVAL, "opts.second_kind must be -1, 0 or 1");
+  if (o.symmetric < -1 || o.symmetric > 1) return fail(HIF_EINVAL, "opts.symmetric must be -1, 0 or 1");
+  if (o.variant != HIF_VARIANT_HIFIE && o.variant != HIF_VARIANT_RSF)
+    return fail(HIF_EINVAL, "opts.variant must be HIF_VARIANT_HIFIE or HIF_VARIANT_RSF");
+  if (o.n_proxy < 0 || o.n_proxy > 8192) return fail(HIF_EINVAL, "opts.n_proxy must be in [0, 8192]");
+  if (!(o.proxy_radius == 0.0 || (std::isfinite(o.proxy_radius) && o.proxy_radius > 0.5)))
+    return fail(HIF_EINVAL, "opts.proxy_radius must be 0 (default) or > 0.5 cell widths");
+  if (o.second_kind < 0) o.second_kind = 1;
+  hif_handle H = nullptr;
+  hif_status st = guarded([&] {
+    std::unique_ptr<hif_factor_s> h(new hif_factor_s());
+    h->n = n;
+    h->dim = dim;
+    h->eps = eps;
+    h->leaf = leaf;
+    h->opts = o;
+    h->nproxy = o.n_proxy ? o.n_proxy : (dim == 2 ? 64 : 512);
+    h->proxy_r = o.proxy_radius > 0.0 ? o.proxy_radius : 1.5;
+    h->mem.cap = o.max_bytes;
+    factor_impl(h.get(), points, k, a, b, c, hipStream_t(stream));
+    H = h.release();
+  });
+  if (st == HIF_OK) *out = H;
+  return st;
+}
+
+static hif_status sweep(hif_handle h, int op, const double* x, double* y, int64_t nrhs, hif_stream s) {
+  if (!h) return fail(HIF_EINVAL, "handle is NULL");
+  if (!x || !y) return fail(HIF_EINVAL, "vector pointer is NULL");
+  if (nrhs < 1) return fail(HIF_EINVAL, "nrhs must be >= 1");
+  return guarded([&] { sweep_impl(h, op, x, y, nrhs, hipStream_t(s)); });
+}
+
+hif_status hif_solve(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream s) {
+  return sweep(h, 0, f, u, nrhs, s);
+}
+hif_status hif_solve_T(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream s) {
+  return sweep(h, 1, f, u, nrhs, s);
+}
+hif_status hif_apply(hif_handle h, const double* x, double* y, int64_t nrhs, hif_stream s) {
+  return sweep(h, 2, x, y, nrhs, s);
+}
+hif_status hif_apply_T(hif_handle h, const double* x, double* y, int64_t nrhs, hif_stream s) {
+  return sweep(h, 3, x, y, nrhs, s);
+}
+
+hif_status hif_matvec(const double* points, int64_t n, int dim, const hif_kernel* k, const double* a,
+                      const double* b, const double* c, const double* x, double* y, int64_t nrhs, hif_stream s) {
+  if (!points || !x || !y) return fail(HIF_EINVAL, "NULL pointer argument");
+  if (x == y) return fail(HIF_EINVAL, "y must not alias x");
+  if (n < 1) return fail(HIF_EINVAL, "n must be >= 1");
+  if (dim != 2 && dim != 3) return fail(HIF_EINVAL, "dim must be 2 or 3");
+  if (nrhs < 1) return fail(HIF_EINVAL, "nrhs must be >= 1");
+  if (hif_status st = check_kernel(k); st != HIF_OK) return st;
+  return guarded([&] {
+    const double wc = k->weights ? 0.0 : std::pow(k->h, dim);
+    const double sc = k->self ? 0.0 : self_integral(k->h, dim);
+    matvec_impl(points, n, dim, a, b, c, k->weights, wc, k->self, sc, x, y, nrhs, hipStream_t(s));
+  });
+}
+
+hif_status hif_stats(hif_handle h, hif_stats_t* out) {
+  if (!h || !out) return fail(HIF_EINVAL, "NULL argument");
+  *out = h->stats;
+  return HIF_OK;
+}
+
+void hif_free(hif_handle h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  delete h;
+}
+
+hif_status hif_id_batched(double* mats, const int64_t* off, const int32_t* rows, const int32_t* cols,
+                          const double* tol, int32_t batch, int32_t max_cols, int32_t* rank, int32_t* perm,
+                          const int64_t* off_perm, double* T, const int64_t* off_t, hif_stream s) {
+  if (batch < 0) return fail(HIF_EINVAL, "batch must be >= 0");
+  if (batch == 0) return HIF_OK;
+  if (!mats || !off || !rows || !cols || !tol || !rank || !perm || !off_perm)
+    return fail(HIF_EINVAL, "NULL pointer argument");
+  if ((T == nullptr) != (off_t == nullptr)) return fail(HIF_EINVAL, "T and off_t must both be given or both NULL");
+  if (max_cols < 1 || max_cols > 4096) return fail(HIF_EINVAL, "max_cols must be in [1, 4096]");
+  return guarded([&] {
+    id_batched_impl(mats, off, rows, cols, tol, batch, max_cols, rank, perm, off_perm, T, off_t, hipStream_t(s));
+  });
+}
+
+hif_status hif_partition(const double* points, int64_t n, int dim, const uint8_t* active, int kind, int32_t S,
+                         int32_t* group, hif_stream s) {
+  if (!points || !active || !group) return fail(HIF_EINVAL, "NULL pointer argument");
+  if (n < 1) return fail(HIF_EINVAL, "n must be >= 1");
+  if (dim != 2 && dim != 3) return fail(HIF_EINVAL, "dim must be 2 or 3");
+  if (kind < 0 || kind > 2 || (kind == 1 && dim != 3)) return fail(HIF_EINVAL, "kind must be 0 (cell), 1 (face, 3D) or 2 (edge)");
+  if (S < 1 || S > (1 << 20)) return fail(HIF_EINVAL, "S must be in [1, 2^20]");
+  return guarded([&] { partition_impl(points, n, dim, active, kind, S, group, hipStream_t(s)); });
+}
+
+}  // extern "C"

@@ -1,0 +1,238 @@
+// Internal declarations shared by the HIF-IE library sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "hif.h"
+
+namespace hif {
+
+// ---------------------------------------------------------------------------
+// Errors: a status plus a thread-local message; no exceptions cross the ABI.
+// ---------------------------------------------------------------------------
+struct Error {
+  hif_status status;
+  std::string msg;
+};
+
+void set_error(hif_status s, const std::string& msg);
+hif_status fail(hif_status s, const std::string& msg);
+
+#define HIF_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      throw ::hif::Error{HIF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    }                                                                              \
+  } while (0)
+
+#define HIF_REQUIRE(cond, status, msg)                   \
+  do {                                                   \
+    if (!(cond)) throw ::hif::Error{(status), (msg)};    \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device memory owned by the library, with an optional cap on the total.
+// ---------------------------------------------------------------------------
+struct MemTracker {
+  size_t held = 0;
+  size_t peak = 0;
+  size_t cap = 0;  // 0 = no cap
+};
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;        // elements allocated
+  MemTracker* mt = nullptr;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), mt(o.mt) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; mt = o.mt; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p) {
+      (void)hipFree(p);
+      if (mt) mt->held -= n * sizeof(T);
+    }
+    p = nullptr;
+    n = 0;
+  }
+  // Allocate exactly n elements (contents undefined); frees what was held.
+  void alloc(size_t cnt, MemTracker* tracker) {
+    release();
+    mt = tracker;
+    if (cnt == 0) return;
+    size_t bytes = cnt * sizeof(T);
+    if (mt && mt->cap && mt->held + bytes > mt->cap)
+      throw Error{HIF_ENOMEM, "device memory cap (opts.max_bytes) exceeded"};
+    hipError_t e = hipMalloc((void**)&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw Error{HIF_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    n = cnt;
+    if (mt) { mt->held += bytes; if (mt->held > mt->peak) mt->peak = mt->held; }
+  }
+  // Grow-only: keep the allocation if it already holds cnt elements.
+  void ensure(size_t cnt, MemTracker* tracker) {
+    if (cnt <= n && p) return;
+    alloc(cnt < 16 ? 16 : cnt + cnt / 8, tracker);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Factor records (Lemma 2.4): one per skeletonized index set with r > 0.
+//  iarena + idx : rd[r], sk[k], piv[r]           (int32, global DOF ids / pivots)
+//  darena + off : T (k x r), E (k x r), G (r x k), LU(B_rr) (r x r), all row-major.
+// ---------------------------------------------------------------------------
+struct GroupRec {
+  int32_t r, k;
+  int64_t idx;
+  int64_t off;
+};
+
+struct SubLevel {
+  int level = 0;
+  int kind = 0;  // 0 cell, 1 face, 2 edge
+  int nrec = 0;
+  int max_r = 0, max_k = 0;
+  std::vector<GroupRec> hrec;
+  DBuf<GroupRec> rec;
+  DBuf<int32_t> iarena;
+  DBuf<double> darena;
+};
+
+}  // namespace hif
+
+struct hif_factor_s {
+  int64_t n = 0;
+  int dim = 2;
+  int L = 0;
+  double eps = 0;
+  int leaf = 64;
+  hif_opts opts{};
+  int symmetric = 1;
+  int nproxy = 64;
+  double proxy_r = 1.5;
+  hif::MemTracker mem;
+  // Operator data, caller order.
+  hif::DBuf<double> pts, a, b, c, w, selfk;
+  // Factors.
+  std::vector<hif::SubLevel> subs;
+  int64_t ntop = 0;
+  hif::DBuf<int32_t> top_idx, top_piv;
+  hif::DBuf<double> top_lu;
+  // Sweep scratch.
+  hif::DBuf<double> work;
+  hif_stats_t stats{};
+};
+
+namespace hif {
+
+// ---------------------------------------------------------------------------
+// Kernel functions (eqn laplace-kernel).
+// ---------------------------------------------------------------------------
+constexpr double kInv2Pi = 0.15915494309189533577;  // 1 / (2 pi)
+constexpr double kInv4Pi = 0.07957747154594766788;  // 1 / (4 pi)
+
+// G as a function of the squared distance r2 > 0.
+template <int D>
+__device__ __forceinline__ double green_r2(double r2) {
+  if constexpr (D == 2) {
+    return -0.5 * kInv2Pi * log(r2);
+  } else {
+    return kInv4Pi * rsqrt(r2);
+  }
+}
+
+// Closed-form integral of G over the element [-h/2, h/2]^d.
+inline double self_integral(double h, int d) {
+  if (d == 2) return -(h * h / (2.0 * M_PI)) * (std::log(h / std::sqrt(2.0)) - 1.5 + M_PI / 4.0);
+  return h * h * (3.0 * std::log(2.0 + std::sqrt(3.0)) - M_PI / 2.0) / (4.0 * M_PI);
+}
+
+// Squared distance summed in coordinate order with every product and sum
+// rounded separately (no FMA contraction), so equal inputs give the same
+// value on any IEEE implementation; on dyadic grids it is exact, so Voronoi
+// ties and the strict near-field test are decided exactly.
+template <int D>
+__device__ __forceinline__ double dist2_exact(const double* x, const double* z) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double t = x[k] - z[k];
+    const double p = t * t;
+    s = s + p;
+  }
+  return s;
+}
+
+// Wave / block reductions (wave64).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers implemented in the .hip sources.
+// ---------------------------------------------------------------------------
+struct Prim;  // rocPRIM wrappers (prim.hip)
+
+// Sort (u64 key) ascending, in place via a double buffer; returns nothing.
+void sort_u64(uint64_t* keys, uint64_t* tmp, size_t n, int end_bit, hipStream_t s,
+              DBuf<unsigned char>& scratch, MemTracker* mt);
+// Sort pairs (u64 key, int32 value) ascending by key (stable).
+void sort_u64_i32(uint64_t* keys, uint64_t* ktmp, int32_t* vals, int32_t* vtmp, size_t n,
+                  int end_bit, hipStream_t s, DBuf<unsigned char>& scratch, MemTracker* mt);
+// Sort pairs (int32 key, int32 value) ascending by key (stable).
+void sort_i32_i32(int32_t* keys, int32_t* ktmp, int32_t* vals, int32_t* vtmp, size_t n,
+                  int end_bit, hipStream_t s, DBuf<unsigned char>& scratch, MemTracker* mt);
+// Exclusive prefix sum of int64 counts; out has n+1 entries (out[n] = total).
+void exclusive_scan_i64(const int64_t* in, int64_t* out, size_t n, hipStream_t s,
+                        DBuf<unsigned char>& scratch, MemTracker* mt);
+void exclusive_scan_i32(const int32_t* in, int32_t* out, size_t n, hipStream_t s,
+                        DBuf<unsigned char>& scratch, MemTracker* mt);
+
+// Factorization driver (factor.hip).
+void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* k, const double* a,
+                 const double* b, const double* c, hipStream_t s);
+
+// Sweeps (sweep.hip): op 0 solve, 1 solve_T, 2 apply, 3 apply_T.
+void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s);
+
+// Exact O(n^2) matvec (matvec.hip).
+void matvec_impl(const double* pts, int64_t n, int dim, const double* a, const double* b,
+                 const double* c, const double* w, double w_const, const double* selfk,
+                 double self_const, const double* x, double* y, int64_t nrhs, hipStream_t s);
+
+// Batched ID (dense.hip), the same kernel hif_factor uses.
+void id_batched_impl(double* mats, const int64_t* off, const int32_t* rows, const int32_t* cols,
+                     const double* tol, int32_t batch, int32_t max_cols, int32_t* rank,
+                     int32_t* perm, const int64_t* off_perm, double* T, const int64_t* off_t,
+                     hipStream_t s);
+
+// Group assignment (factor.hip).
+void partition_impl(const double* pts, int64_t n, int dim, const uint8_t* active, int kind,
+                    int32_t S, int32_t* group, hipStream_t s);
+
+inline int ceil_log2(uint64_t v) {
+  int b = 0;
+  while ((uint64_t(1) << b) < v) ++b;
+  return b;
+}
+
+}  // namespace hif

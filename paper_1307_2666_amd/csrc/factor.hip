@@ -1,0 +1,1308 @@
+// HIF-IE / RSF factorization driver (Algorithms 3.1, 4.1, 4.2) and the index
+// bookkeeping kernels it needs: tree depth, cell / face / edge partitions,
+// near fields, split classes, and the store of Schur-complement interactions
+// (SCIs).  The host only sequences launches and turns per-group sizes that
+// depend on the ranks into offsets (one read-back per stage of a sub-level).
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <numeric>
+
+#include "kernels.h"
+
+namespace hif {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned nblocks(int64_t n, int t = kThreads) {
+  int64_t b = (n + t - 1) / t;
+  if (b < 1) b = 1;
+  if (b > (1 << 20)) b = 1 << 20;
+  return unsigned(b);
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < (n); i += int64_t(gridDim.x) * blockDim.x)
+
+// ---------------------------------------------------------------------------
+// Small utility kernels.
+// ---------------------------------------------------------------------------
+__global__ void k_iota(int32_t* a, int64_t n) { GRID_STRIDE(i, n) a[i] = int32_t(i); }
+__global__ void k_fill_u8(uint8_t* a, int64_t n, uint8_t v) { GRID_STRIDE(i, n) a[i] = v; }
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) { GRID_STRIDE(i, n) a[i] = v; }
+__global__ void k_fill_i64(int64_t* a, int64_t n, int64_t v) { GRID_STRIDE(i, n) a[i] = v; }
+__global__ void k_fill_f64(double* a, int64_t n, double v) { GRID_STRIDE(i, n) a[i] = v; }
+__global__ void k_copy_f64(const double* x, double* y, int64_t n) { GRID_STRIDE(i, n) y[i] = x[i]; }
+
+// Input checks: bit 1 non-finite point, bit 2 point outside [0,1]^d,
+// bit 4 non-finite coefficient / weight / self term.
+__global__ void k_validate(const double* pts, int64_t n, int dim, const double* a, const double* b,
+                           const double* c, const double* w, const double* sf, int32_t* flags) {
+  GRID_STRIDE(i, n) {
+    int f = 0;
+    for (int k = 0; k < dim; ++k) {
+      double x = pts[i * dim + k];
+      if (!isfinite(x)) f |= 1;
+      else if (x < 0.0 || x > 1.0) f |= 2;
+    }
+    if (!isfinite(a[i]) || !isfinite(b[i]) || !isfinite(c[i]) || !isfinite(w[i]) || !isfinite(sf[i])) f |= 4;
+    if (f) atomicOr(flags, f);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void box_of(const double* x, int S, int* j) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    int v = int(floor(x[k] * double(S)));
+    j[k] = v < 0 ? 0 : (v > S - 1 ? S - 1 : v);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ int flat_box(const int* j, int S) {
+  int f = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) f = f * S + j[k];
+  return f;
+}
+
+template <int D>
+__global__ void k_box_count(const double* pts, int64_t n, int S, int32_t* counts) {
+  GRID_STRIDE(i, n) {
+    int j[D];
+    box_of<D>(pts + i * D, S, j);
+    atomicAdd(&counts[flat_box<D>(j, S)], 1);
+  }
+}
+
+__global__ void k_minmax(const int32_t* counts, int64_t m, int32_t* mm) {
+  GRID_STRIDE(i, m) {
+    atomicMin(&mm[0], counts[i]);
+    atomicMax(&mm[1], counts[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Partitions (Sections 3.1, 4.1, 4.2).  Centre families in the paper's order:
+// 2D edges: x-integer, y-integer; 3D faces: x-, y-, z-integer; 3D edges:
+// (x,y)-, (x,z)-, (y,z)-integer.  An integer coordinate takes m w for
+// m = 1..S-1, a half coordinate (m + 1/2) w for m = 0..S-1; within a family
+// the index is lexicographic with the first coordinate slowest.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ int family_mask(int kind, int fam) {
+  if (kind == 1) return 1 << fam;  // faces
+  if (D == 2) return 1 << fam;     // 2D edges
+  return fam == 0 ? 3 : (fam == 1 ? 5 : 6);
+}
+
+template <int D>
+__device__ __forceinline__ int family_count(int kind) {
+  return kind == 0 ? 1 : (D == 2 ? 2 : 3);
+}
+
+template <int D>
+__device__ int group_key(const double* x, int kind, int S) {
+#pragma clang fp contract(off)
+  int j[D];
+  box_of<D>(x, S, j);
+  if (kind == 0) return flat_box<D>(j, S);
+  const double w = 1.0 / double(S);
+  double best = INFINITY;
+  int bidx = -1, off = 0;
+  const int nf = family_count<D>(kind);
+  for (int fam = 0; fam < nf; ++fam) {
+    const int mask = family_mask<D>(kind, fam);
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, base[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+    int fsize = 1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const bool integ = (mask >> k) & 1;
+      base[k] = integ ? 1 : 0;
+      cnt[k] = integ ? S - 1 : S;
+      lo[k] = integ ? max(1, j[k] - 2) : max(0, j[k] - 2);
+      hi[k] = integ ? min(S - 1, j[k] + 3) : min(S - 1, j[k] + 2);
+      fsize *= cnt[k];
+    }
+    if (fsize > 0) {
+      for (int m0 = lo[0]; m0 <= hi[0]; ++m0)
+        for (int m1 = lo[1]; m1 <= hi[1]; ++m1)
+          for (int m2 = (D == 3 ? lo[2] : 0); m2 <= (D == 3 ? hi[2] : 0); ++m2) {
+            const int mm[3] = {m0, m1, m2};
+            double z[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+              z[k] = ((mask >> k) & 1) ? double(mm[k]) * w : (double(mm[k]) + 0.5) * w;
+            const double d2 = dist2_exact<D>(x, z);
+            if (d2 < best) {
+              best = d2;
+              int idx = 0;
+#pragma unroll
+              for (int k = 0; k < D; ++k) idx = idx * cnt[k] + (mm[k] - base[k]);
+              bidx = off + idx;
+            }
+          }
+    }
+    off += fsize;
+  }
+  return bidx;
+}
+
+template <int D>
+__device__ void centre_of(int key, int kind, int S, double* z) {
+#pragma clang fp contract(off)
+  const double w = 1.0 / double(S);
+  if (kind == 0) {
+    int r = key;
+    for (int k = D - 1; k >= 0; --k) {
+      z[k] = (double(r % S) + 0.5) * w;
+      r /= S;
+    }
+    return;
+  }
+  const int nf = family_count<D>(kind);
+  int off = 0;
+  for (int fam = 0; fam < nf; ++fam) {
+    const int mask = family_mask<D>(kind, fam);
+    int cnt[D], fsize = 1;
+    for (int k = 0; k < D; ++k) {
+      cnt[k] = ((mask >> k) & 1) ? S - 1 : S;
+      fsize *= cnt[k];
+    }
+    if (key < off + fsize) {
+      int r = key - off;
+      for (int k = D - 1; k >= 0; --k) {
+        const int m = r % cnt[k];
+        r /= cnt[k];
+        z[k] = ((mask >> k) & 1) ? double(m + 1) * w : (double(m) + 0.5) * w;
+      }
+      return;
+    }
+    off += fsize;
+  }
+}
+
+template <int D>
+__global__ void k_group_key(const double* pts, const int32_t* act, int64_t nact, int kind, int S,
+                            int32_t* key, int32_t* dof) {
+  GRID_STRIDE(i, nact) {
+    const int j = act[i];
+    key[i] = group_key<D>(pts + int64_t(j) * D, kind, S);
+    dof[i] = j;
+  }
+}
+
+template <int D>
+__global__ void k_partition(const double* pts, int64_t n, const uint8_t* active, int kind, int S,
+                            int32_t* group) {
+  GRID_STRIDE(i, n) group[i] = active[i] ? group_key<D>(pts + i * D, kind, S) : -1;
+}
+
+__global__ void k_heads(const int32_t* skey, int64_t n, int32_t* head) {
+  GRID_STRIDE(i, n) head[i] = (i == 0 || skey[i] != skey[i - 1]) ? 1 : 0;
+}
+
+// After an exclusive scan of the heads: group index of every position.
+__global__ void k_group_setup(const int32_t* skey, const int32_t* sdof, int64_t n, const int32_t* head,
+                              const int32_t* hscan, int64_t* gstart, int32_t* gkey, int32_t* grp_of) {
+  GRID_STRIDE(i, n) {
+    const int g = hscan[i] + head[i] - 1;
+    if (head[i]) {
+      gstart[g] = i;
+      gkey[g] = skey[i];
+    }
+    if (i == n - 1) gstart[g + 1] = n;
+    grp_of[sdof[i]] = g;
+  }
+}
+
+template <int D>
+__global__ void k_centres(const int32_t* gkey, int G, int kind, int S, double* zc) {
+  GRID_STRIDE(g, G) centre_of<D>(gkey[g], kind, S, zc + g * D);
+}
+
+__global__ void k_cell_table(const int32_t* ckey, int64_t n, int32_t* lo, int32_t* hi) {
+  GRID_STRIDE(i, n) {
+    const int c = ckey[i];
+    if (i == 0 || ckey[i - 1] != c) lo[c] = int32_t(i);
+    if (i == n - 1 || ckey[i + 1] != c) hi[c] = int32_t(i + 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Near field c^N (Section 3.3, expanded by SCI partners per Section 4.3):
+// DOFs of other groups strictly inside the proxy sphere about the group
+// centre, plus every DOF sharing a stored SCI with the group.  Candidates are
+// counted, emitted as (group, DOF) keys, sorted and deduplicated.
+// ---------------------------------------------------------------------------
+struct NfArgs {
+  const double* pts;
+  const int32_t* sdof;
+  const int64_t* gstart;
+  const double* zc;
+  int G, S;
+  double R, R2;
+  const int32_t* cdof;
+  const int32_t* cell_lo;
+  const int32_t* cell_hi;
+  const int32_t* grp_of;
+  const int64_t* srow;
+  const uint64_t* skey;
+  int64_t* cnt;
+  uint64_t* cand;
+  const int64_t* cand_off;
+  int shift;
+};
+
+template <int D, bool FILL>
+__global__ void k_nearfield(NfArgs A) {
+  const int g = blockIdx.x;
+  double z[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) z[k] = A.zc[int64_t(g) * D + k];
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    lo[k] = max(0, int(floor((z[k] - A.R) * double(A.S))) - 1);
+    hi[k] = min(A.S - 1, int(floor((z[k] + A.R) * double(A.S))) + 1);
+  }
+  __shared__ unsigned long long s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  int64_t local = 0;
+  uint64_t* out = FILL ? A.cand + A.cand_off[g] : nullptr;
+  const unsigned long long cap = FILL ? (unsigned long long)(A.cand_off[g + 1] - A.cand_off[g]) : 0ull;
+  auto emit = [&](int j) {
+    if (FILL) {
+      unsigned long long slot = atomicAdd(&s_cnt, 1ull);
+      if (slot < cap) out[slot] = (uint64_t(g) << A.shift) | uint64_t(uint32_t(j));
+    } else {
+      ++local;
+    }
+  };
+  for (int c0 = lo[0]; c0 <= hi[0]; ++c0)
+    for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
+      for (int c2 = (D == 3 ? lo[2] : 0); c2 <= (D == 3 ? hi[2] : 0); ++c2) {
+        const int cc[3] = {c0, c1, c2};
+        int cid = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) cid = cid * A.S + cc[k];
+        const int b = A.cell_lo[cid], e = A.cell_hi[cid];
+        for (int i = b + threadIdx.x; i < e; i += blockDim.x) {
+          const int j = A.cdof[i];
+          if (A.grp_of[j] == g) continue;
+          if (dist2_exact<D>(A.pts + int64_t(j) * D, z) < A.R2) emit(j);
+        }
+      }
+  for (int64_t p = A.gstart[g] + threadIdx.x; p < A.gstart[g + 1]; p += blockDim.x) {
+    const int i = A.sdof[p];
+    for (int64_t e = A.srow[i]; e < A.srow[i + 1]; ++e) {
+      const int j = int(A.skey[e] & 0xffffffffu);
+      if (A.grp_of[j] != g) emit(j);
+    }
+  }
+  if (!FILL) {
+    __shared__ long long sp[16];
+    long long v = local;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sp[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long t = 0;
+      for (int k = 0; k < int(blockDim.x + 63) / 64; ++k) t += sp[k];
+      A.cnt[g] = t;
+    }
+  }
+}
+
+__global__ void k_unique_flags(const uint64_t* keys, int64_t n, int64_t* flag) {
+  GRID_STRIDE(i, n) flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_unique_compact(const uint64_t* keys, int64_t n, const int64_t* flag, const int64_t* pos,
+                                 int shift, int32_t* nf_idx, int32_t* nfc) {
+  GRID_STRIDE(i, n) {
+    if (flag[i]) {
+      const uint64_t key = keys[i];
+      nf_idx[pos[i]] = int32_t(key & ((uint64_t(1) << shift) - 1));
+      atomicAdd(&nfc[int(key >> shift)], 1);
+    }
+  }
+}
+
+__global__ void k_i32_to_i64(const int32_t* a, int64_t* b, int64_t n) { GRID_STRIDE(i, n) b[i] = a[i]; }
+
+// ---------------------------------------------------------------------------
+// Split classes (Section 4.4, Lemma 4.2): columns with the same structural
+// SCI pattern over the near field.  Pattern sets are compared through two
+// order-independent 64-bit hashes plus their size; classes are ordered by
+// their first column and keep ascending column order inside.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+struct ClsArgs {
+  const int32_t* sdof;
+  const int64_t* gstart;
+  const int32_t* grp_of;
+  const int64_t* srow;
+  const uint64_t* skey;
+  uint64_t* h1;
+  uint64_t* h2;
+  int32_t* hc;
+  int32_t* rep;
+  int32_t* newpos;
+  int32_t* cord;
+  int32_t* pos_of;
+  int32_t* ncls;
+  int split;
+  // fill pass
+  const int32_t* cls_first;
+  int32_t* cls_col0;
+  int32_t* cls_n;
+  int32_t* cls_group;
+};
+
+__global__ void k_class_prep(ClsArgs A) {
+  const int g = blockIdx.x;
+  const int64_t c0 = A.gstart[g];
+  const int n = int(A.gstart[g + 1] - c0);
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    uint64_t a = 0, b = 0;
+    int c = 0;
+    if (A.split) {
+      const int j = A.sdof[c0 + p];
+      for (int64_t e = A.srow[j]; e < A.srow[j + 1]; ++e) {
+        const int i = int(A.skey[e] & 0xffffffffu);
+        if (A.grp_of[i] != g) {
+          a += mix64(uint64_t(i));
+          b ^= mix64(uint64_t(i) * 0x2545f4914f6cdd1dull + 17);
+          ++c;
+        }
+      }
+    }
+    A.h1[c0 + p] = a;
+    A.h2[c0 + p] = b;
+    A.hc[c0 + p] = c;
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    const uint64_t a = A.h1[c0 + p], b = A.h2[c0 + p];
+    const int c = A.hc[c0 + p];
+    int r = p;
+    for (int q = 0; q < p; ++q)
+      if (A.h1[c0 + q] == a && A.h2[c0 + q] == b && A.hc[c0 + q] == c) {
+        r = q;
+        break;
+      }
+    A.rep[c0 + p] = r;
+  }
+  __syncthreads();
+  int local = 0;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    const int r = A.rep[c0 + p];
+    int np = 0;
+    for (int q = 0; q < n; ++q) {
+      const int rq = A.rep[c0 + q];
+      np += (rq < r) || (rq == r && q < p);
+    }
+    A.newpos[c0 + p] = np;
+    const int j = A.sdof[c0 + p];
+    A.cord[c0 + np] = j;
+    A.pos_of[j] = np;
+    local += (r == p);
+  }
+  __shared__ int s_n;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  atomicAdd(&s_n, local);
+  __syncthreads();
+  if (threadIdx.x == 0) A.ncls[g] = s_n;
+}
+
+__global__ void k_class_fill(ClsArgs A) {
+  const int g = blockIdx.x;
+  const int64_t c0 = A.gstart[g];
+  const int n = int(A.gstart[g + 1] - c0);
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    if (A.rep[c0 + p] != p) continue;
+    int ci = 0, cnt = 0;
+    for (int q = 0; q < n; ++q) {
+      const int rq = A.rep[c0 + q];
+      ci += (rq == q && q < p);
+      cnt += (rq == p);
+    }
+    const int slot = A.cls_first[g] + ci;
+    A.cls_col0[slot] = A.newpos[c0 + p];
+    A.cls_n[slot] = cnt;
+    A.cls_group[slot] = g;
+  }
+}
+
+// Per class: local tolerance rho eps with rho = min(1, |Y^K| / |Y^S|) (Section 4.4).
+__global__ void k_class_tol(int nc, const int32_t* cls_group, const int32_t* cls_col0, const int32_t* cls_n,
+                            const int64_t* gstart, const double* colK2, const double* colS2, double eps,
+                            int second_kind, const int64_t* yoff, const int64_t* nf_start, int sym,
+                            int nproxy, int64_t* moff, int32_t* ld, int32_t* rows, double* tol,
+                            int64_t* poff) {
+  GRID_STRIDE(q, nc) {
+    const int g = cls_group[q];
+    const int64_t c0 = gstart[g];
+    const int n = int(gstart[g + 1] - c0);
+    const int col0 = cls_col0[q], nq = cls_n[q];
+    double k2 = 0.0, s2 = 0.0;
+    for (int j = 0; j < nq; ++j) {
+      k2 += colK2[c0 + col0 + j];
+      s2 += colS2[c0 + col0 + j];
+    }
+    double rho = 1.0;
+    if (second_kind && s2 > 0.0) rho = fmin(1.0, sqrt(k2) / sqrt(s2));
+    tol[q] = rho * eps;
+    const int nf = int(nf_start[g + 1] - nf_start[g]);
+    moff[q] = yoff[g] + col0;
+    ld[q] = n;
+    rows[q] = sym ? nf + nproxy : 2 * nf + 2 * nproxy;
+    poff[q] = c0 + col0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// SCI store maintenance.
+// ---------------------------------------------------------------------------
+__global__ void k_mark_inactive(const GroupRec* recs, int nrec, const int32_t* iarena, uint8_t* active) {
+  const int ri = blockIdx.x;
+  if (ri >= nrec) return;
+  const GroupRec R = recs[ri];
+  for (int b = threadIdx.x; b < R.r; b += blockDim.x) active[iarena[R.idx + b]] = 0;
+}
+
+__global__ void k_sci_keep(const uint64_t* key, int64_t nnz, const uint8_t* active, const int32_t* grp_of,
+                           const int32_t* grec, int64_t* keep) {
+  GRID_STRIDE(e, nnz) {
+    const int i = int(key[e] >> 32), j = int(key[e] & 0xffffffffu);
+    int kp = 0;
+    if (active[i] && active[j]) {
+      const int gi = grp_of[i], gj = grp_of[j];
+      kp = (gi != gj) || (grec[gi] < 0);
+    }
+    keep[e] = kp;
+  }
+}
+
+__global__ void k_sci_compact(const uint64_t* key, const double2* val, int64_t nnz, const int64_t* keep,
+                              const int64_t* pos, uint64_t* okey, double2* oval, int32_t* oidx) {
+  GRID_STRIDE(e, nnz) {
+    if (keep[e]) {
+      const int64_t p = pos[e];
+      okey[p] = key[e];
+      oval[p] = val[e];
+      oidx[p] = int32_t(p);
+    }
+  }
+}
+
+__global__ void k_append(const uint64_t* nkey, const double2* nval, int64_t nn, int64_t base, uint64_t* okey,
+                         double2* oval, int32_t* oidx) {
+  GRID_STRIDE(e, nn) {
+    okey[base + e] = nkey[e];
+    oval[base + e] = nval[e];
+    oidx[base + e] = int32_t(base + e);
+  }
+}
+
+__global__ void k_gather_val(const double2* in, const int32_t* idx, int64_t n, double2* out) {
+  GRID_STRIDE(e, n) out[e] = in[idx[e]];
+}
+
+__global__ void k_row_count(const uint64_t* key, int64_t nnz, int64_t* cnt) {
+  GRID_STRIDE(e, nnz) atomicAdd((unsigned long long*)&cnt[key[e] >> 32], 1ull);
+}
+
+__global__ void k_active_keep(const int32_t* act, int64_t nact, const uint8_t* active, int32_t* keep) {
+  GRID_STRIDE(i, nact) keep[i] = active[act[i]] ? 1 : 0;
+}
+
+__global__ void k_active_compact(const int32_t* act, int64_t nact, const int32_t* keep, const int32_t* pos,
+                                 int32_t* out) {
+  GRID_STRIDE(i, nact) if (keep[i]) out[pos[i]] = act[i];
+}
+
+__global__ void k_pos_scatter(const int32_t* idx, int64_t n, int32_t* pos_of) {
+  GRID_STRIDE(i, n) pos_of[idx[i]] = int32_t(i);
+}
+
+// Coincident points: pairwise comparison inside each leaf box (boxes with
+// more than 4096 points are skipped).
+__global__ void k_coincident(const double* pts, int D, const int32_t* cdof, const int32_t* lo, const int32_t* hi,
+                             int32_t* flag) {
+  const int b = lo[blockIdx.x], e = hi[blockIdx.x];
+  const int n = e - b;
+  if (n < 2 || n > 4096) return;
+  const int64_t pairs = int64_t(n) * (n - 1) / 2;
+  for (int64_t t = threadIdx.x; t < pairs; t += blockDim.x) {
+    // t -> (i, j), i < j
+    int i = int((sqrt(8.0 * double(t) + 1.0) - 1.0) / 2.0);
+    while (int64_t(i + 1) * (i + 2) / 2 <= t) ++i;
+    while (int64_t(i) * (i + 1) / 2 > t) --i;
+    const int j = int(t - int64_t(i) * (i + 1) / 2);
+    const int pi = cdof[b + i + 1], pj = cdof[b + j];
+    bool same = true;
+    for (int k = 0; k < D; ++k) same = same && (pts[int64_t(pi) * D + k] == pts[int64_t(pj) * D + k]);
+    if (same) atomicOr(flag, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+template <class T>
+void to_host(std::vector<T>& h, const T* d, size_t n, hipStream_t s) {
+  h.resize(n);
+  if (n) HIF_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  HIF_HIP(hipStreamSynchronize(s));
+}
+
+template <class T>
+void to_dev(T* d, const std::vector<T>& h, hipStream_t s) {
+  if (!h.empty()) HIF_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+template <class T>
+T scalar_at(const T* d, hipStream_t s) {
+  T v{};
+  HIF_HIP(hipMemcpyAsync(&v, d, sizeof(T), hipMemcpyDeviceToHost, s));
+  HIF_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+struct Timer {
+  hipStream_t s;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> phase;
+  void mark(int ph) {
+    hipEvent_t e;
+    HIF_HIP(hipEventCreate(&e));
+    HIF_HIP(hipEventRecord(e, s));
+    ev.push_back(e);
+    phase.push_back(ph);
+  }
+  void flush(double* acc) {
+    if (ev.size() >= 2) {
+      HIF_HIP(hipEventSynchronize(ev.back()));
+      for (size_t i = 1; i < ev.size(); ++i) {
+        float ms = 0.f;
+        HIF_HIP(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
+        acc[phase[i]] += ms;
+      }
+    }
+    for (auto e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    phase.clear();
+  }
+  ~Timer() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+enum { PH_PART = 0, PH_ASM = 1, PH_ID = 2, PH_ELIM = 3, PH_SCI = 4, PH_TOP = 5, PH_HOST = 6, PH_OTHER = 7 };
+
+struct Factorizer {
+  hif_factor_s* H;
+  hipStream_t s;
+  int D;
+  int64_t N;
+  MemTracker* mt;
+  Timer tm;
+  // operator (owned for the duration of the factorization)
+  const double *pts, *a, *b, *c, *w, *sf;
+  // state
+  DBuf<uint8_t> active;
+  DBuf<int32_t> act, act2;
+  int64_t nact = 0;
+  DBuf<int32_t> grp_of, pos_of;
+  DBuf<uint64_t> skey, skey2;
+  DBuf<double2> sval, sval2;
+  DBuf<int64_t> srow;
+  int64_t snnz = 0;
+  DBuf<double> proxy_u;
+  // scratch
+  DBuf<unsigned char> prim;
+  DBuf<int32_t> key, dof, ktmp, vtmp, head, hscan, gkey, cell_lo, cell_hi, ckey, cdof;
+  DBuf<int64_t> gstart, cnt, cand_off, flag64, pos64, nf_start;
+  DBuf<double> zc;
+  DBuf<uint64_t> cand, cand2;
+  DBuf<int32_t> nf_idx, nfc;
+  DBuf<uint64_t> h1, h2;
+  DBuf<int32_t> hc, rep, newpos, cord, ncls;
+  DBuf<int32_t> cls_first, cls_col0, cls_n, cls_group, cls_rank, cls_skoff, cls_rdoff, cls_ld, cls_rows, perm;
+  DBuf<int64_t> cls_moff, cls_poff, yoff, aoff, newoff;
+  DBuf<double> cls_tol, Y, Acc, Scc, colK2, colS2;
+  DBuf<int32_t> grec, loc, rlo, rhi, status, sidx, sidx2;
+  DBuf<uint64_t> newkey;
+  DBuf<double2> newval;
+  DBuf<int32_t> akeep, apos;
+
+  void sublevel(int lvl, int kind);
+  void top();
+};
+
+void Factorizer::sublevel(int lvl, int kind) {
+  const int L = H->L;
+  const int S = 1 << (L - lvl);
+  const double w_l = 1.0 / double(S);
+  const double R = H->proxy_r * w_l;
+  const double R2 = R * R;
+  const int P = H->nproxy;
+  const int sym = H->symmetric;
+  const int split = H->opts.second_kind ? 1 : 0;
+  const int si = int(H->subs.size());
+  SubLevel sub;
+  sub.level = lvl;
+  sub.kind = kind;
+  hif_stats_t& st = H->stats;
+  st.sub_kind[si] = kind;
+  st.sub_active[si] = nact;
+  if (nact == 0) {
+    H->subs.push_back(std::move(sub));
+    return;
+  }
+  tm.mark(PH_OTHER);
+
+  // ---- partition of the active DOFs into groups -------------------------
+  key.ensure(nact, mt);
+  dof.ensure(nact, mt);
+  ktmp.ensure(nact, mt);
+  vtmp.ensure(nact, mt);
+  head.ensure(nact, mt);
+  hscan.ensure(nact + 1, mt);
+  if (D == 2)
+    hipLaunchKernelGGL(k_group_key<2>, dim3(nblocks(nact)), dim3(kThreads), 0, s, pts, act.p, nact, kind, S, key.p, dof.p);
+  else
+    hipLaunchKernelGGL(k_group_key<3>, dim3(nblocks(nact)), dim3(kThreads), 0, s, pts, act.p, nact, kind, S, key.p, dof.p);
+  HIF_HIP(hipGetLastError());
+  int ncent = 1;
+  for (int k = 0; k < D; ++k) ncent *= S;
+  ncent *= (kind == 0 ? 1 : 3);
+  sort_i32_i32(key.p, ktmp.p, dof.p, vtmp.p, nact, ceil_log2(uint64_t(ncent) + 1), s, prim, mt);
+  hipLaunchKernelGGL(k_heads, dim3(nblocks(nact)), dim3(kThreads), 0, s, key.p, nact, head.p);
+  exclusive_scan_i32(head.p, hscan.p, nact, s, prim, mt);
+  const int G = scalar_at(hscan.p + nact, s);
+  gstart.ensure(G + 1, mt);
+  gkey.ensure(G, mt);
+  hipLaunchKernelGGL(k_group_setup, dim3(nblocks(nact)), dim3(kThreads), 0, s, key.p, dof.p, nact, head.p, hscan.p,
+                     gstart.p, gkey.p, grp_of.p);
+  zc.ensure(int64_t(G) * D, mt);
+  if (D == 2)
+    hipLaunchKernelGGL(k_centres<2>, dim3(nblocks(G)), dim3(kThreads), 0, s, gkey.p, G, kind, S, zc.p);
+  else
+    hipLaunchKernelGGL(k_centres<3>, dim3(nblocks(G)), dim3(kThreads), 0, s, gkey.p, G, kind, S, zc.p);
+  HIF_HIP(hipGetLastError());
+  st.sub_groups[si] = G;
+
+  // ---- level-l cell binning of the active DOFs (geometric candidates) ----
+  ckey.ensure(nact, mt);
+  cdof.ensure(nact, mt);
+  int ncell = 1;
+  for (int k = 0; k < D; ++k) ncell *= S;
+  cell_lo.ensure(ncell, mt);
+  cell_hi.ensure(ncell, mt);
+  if (D == 2)
+    hipLaunchKernelGGL(k_group_key<2>, dim3(nblocks(nact)), dim3(kThreads), 0, s, pts, act.p, nact, 0, S, ckey.p, cdof.p);
+  else
+    hipLaunchKernelGGL(k_group_key<3>, dim3(nblocks(nact)), dim3(kThreads), 0, s, pts, act.p, nact, 0, S, ckey.p, cdof.p);
+  sort_i32_i32(ckey.p, ktmp.p, cdof.p, vtmp.p, nact, ceil_log2(uint64_t(ncell) + 1), s, prim, mt);
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(ncell)), dim3(kThreads), 0, s, cell_lo.p, int64_t(ncell), 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(ncell)), dim3(kThreads), 0, s, cell_hi.p, int64_t(ncell), 0);
+  hipLaunchKernelGGL(k_cell_table, dim3(nblocks(nact)), dim3(kThreads), 0, s, ckey.p, nact, cell_lo.p, cell_hi.p);
+  HIF_HIP(hipGetLastError());
+
+  // ---- near fields --------------------------------------------------------
+  const int shift = ceil_log2(uint64_t(N) + 1);
+  const int gbits = ceil_log2(uint64_t(G) + 1);
+  NfArgs nfa{};
+  nfa.pts = pts;
+  nfa.sdof = dof.p;
+  nfa.gstart = gstart.p;
+  nfa.zc = zc.p;
+  nfa.G = G;
+  nfa.S = S;
+  nfa.R = R;
+  nfa.R2 = R2;
+  nfa.cdof = cdof.p;
+  nfa.cell_lo = cell_lo.p;
+  nfa.cell_hi = cell_hi.p;
+  nfa.grp_of = grp_of.p;
+  nfa.srow = srow.p;
+  nfa.skey = skey.p;
+  cnt.ensure(G, mt);
+  cand_off.ensure(G + 1, mt);
+  nfa.cnt = cnt.p;
+  nfa.shift = shift;
+  if (D == 2)
+    hipLaunchKernelGGL((k_nearfield<2, false>), dim3(G), dim3(kThreads), 0, s, nfa);
+  else
+    hipLaunchKernelGGL((k_nearfield<3, false>), dim3(G), dim3(kThreads), 0, s, nfa);
+  HIF_HIP(hipGetLastError());
+  exclusive_scan_i64(cnt.p, cand_off.p, G, s, prim, mt);
+  const int64_t ncand = scalar_at(cand_off.p + G, s);
+  cand.ensure(ncand, mt);
+  cand2.ensure(ncand, mt);
+  nfa.cand = cand.p;
+  nfa.cand_off = cand_off.p;
+  if (D == 2)
+    hipLaunchKernelGGL((k_nearfield<2, true>), dim3(G), dim3(kThreads), 0, s, nfa);
+  else
+    hipLaunchKernelGGL((k_nearfield<3, true>), dim3(G), dim3(kThreads), 0, s, nfa);
+  HIF_HIP(hipGetLastError());
+  sort_u64(cand.p, cand2.p, ncand, shift + gbits, s, prim, mt);
+  flag64.ensure(ncand, mt);
+  pos64.ensure(ncand + 1, mt);
+  nfc.ensure(G, mt);
+  nf_start.ensure(G + 1, mt);
+  hipLaunchKernelGGL(k_unique_flags, dim3(nblocks(ncand)), dim3(kThreads), 0, s, cand.p, ncand, flag64.p);
+  exclusive_scan_i64(flag64.p, pos64.p, ncand, s, prim, mt);
+  const int64_t nnf = scalar_at(pos64.p + ncand, s);
+  nf_idx.ensure(nnf, mt);
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(G)), dim3(kThreads), 0, s, nfc.p, int64_t(G), 0);
+  hipLaunchKernelGGL(k_unique_compact, dim3(nblocks(ncand)), dim3(kThreads), 0, s, cand.p, ncand, flag64.p, pos64.p,
+                     shift, nf_idx.p, nfc.p);
+  hipLaunchKernelGGL(k_i32_to_i64, dim3(nblocks(G)), dim3(kThreads), 0, s, nfc.p, cnt.p, int64_t(G));
+  exclusive_scan_i64(cnt.p, nf_start.p, G, s, prim, mt);
+  HIF_HIP(hipGetLastError());
+  st.sub_near[si] = nnf;
+
+  // ---- split classes and class-ordered group DOFs -------------------------
+  h1.ensure(nact, mt);
+  h2.ensure(nact, mt);
+  hc.ensure(nact, mt);
+  rep.ensure(nact, mt);
+  newpos.ensure(nact, mt);
+  cord.ensure(nact, mt);
+  ncls.ensure(G, mt);
+  ClsArgs ca{};
+  ca.sdof = dof.p;
+  ca.gstart = gstart.p;
+  ca.grp_of = grp_of.p;
+  ca.srow = srow.p;
+  ca.skey = skey.p;
+  ca.h1 = h1.p;
+  ca.h2 = h2.p;
+  ca.hc = hc.p;
+  ca.rep = rep.p;
+  ca.newpos = newpos.p;
+  ca.cord = cord.p;
+  ca.pos_of = pos_of.p;
+  ca.ncls = ncls.p;
+  ca.split = split;
+  hipLaunchKernelGGL(k_class_prep, dim3(G), dim3(kThreads), 0, s, ca);
+  HIF_HIP(hipGetLastError());
+  tm.mark(PH_PART);
+  std::vector<int32_t> h_ncls;
+  std::vector<int64_t> h_gstart, h_nf;
+  to_host(h_ncls, ncls.p, G, s);
+  to_host(h_gstart, gstart.p, G + 1, s);
+  to_host(h_nf, nf_start.p, G + 1, s);
+  std::vector<int32_t> h_cls_first(G + 1, 0);
+  std::vector<int64_t> h_yoff(G), h_aoff(G);
+  int64_t ytot = 0, atot = 0;
+  int maxn = 1;
+  for (int g = 0; g < G; ++g) {
+    h_cls_first[g + 1] = h_cls_first[g] + h_ncls[g];
+    const int64_t n = h_gstart[g + 1] - h_gstart[g];
+    const int64_t nf = h_nf[g + 1] - h_nf[g];
+    const int64_t m = sym ? nf + P : 2 * nf + 2 * P;
+    h_yoff[g] = ytot;
+    h_aoff[g] = atot;
+    ytot += m * n;
+    atot += n * n;
+    maxn = std::max<int>(maxn, int(n));
+  }
+  const int NC = h_cls_first[G];
+  st.sub_classes[si] = NC;
+  cls_first.ensure(G + 1, mt);
+  to_dev(cls_first.p, h_cls_first, s);
+  yoff.ensure(G, mt);
+  aoff.ensure(G, mt);
+  to_dev(yoff.p, h_yoff, s);
+  to_dev(aoff.p, h_aoff, s);
+  cls_col0.ensure(NC, mt);
+  cls_n.ensure(NC, mt);
+  cls_group.ensure(NC, mt);
+  ca.cls_first = cls_first.p;
+  ca.cls_col0 = cls_col0.p;
+  ca.cls_n = cls_n.p;
+  ca.cls_group = cls_group.p;
+  hipLaunchKernelGGL(k_class_fill, dim3(G), dim3(kThreads), 0, s, ca);
+  HIF_HIP(hipGetLastError());
+  tm.mark(PH_HOST);
+
+  // ---- assembly of Y_c and A_cc -------------------------------------------
+  Y.ensure(ytot, mt);
+  Acc.ensure(atot, mt);
+  Scc.ensure(atot, mt);
+  colK2.ensure(nact, mt);
+  colS2.ensure(nact, mt);
+  AsmArgs aa{};
+  aa.dim = D;
+  aa.sym = sym;
+  aa.nproxy = P;
+  aa.ngroups = G;
+  aa.R = R;
+  aa.pts = pts;
+  aa.a = a;
+  aa.b = b;
+  aa.c = c;
+  aa.w = w;
+  aa.selfk = sf;
+  aa.proxy_u = proxy_u.p;
+  aa.cord = cord.p;
+  aa.gstart = gstart.p;
+  aa.nf_idx = nf_idx.p;
+  aa.nf_start = nf_start.p;
+  aa.zc = zc.p;
+  aa.yoff = yoff.p;
+  aa.aoff = aoff.p;
+  aa.Y = Y.p;
+  aa.Acc = Acc.p;
+  aa.Scc = Scc.p;
+  aa.colK2 = colK2.p;
+  aa.colS2 = colS2.p;
+  aa.grp_of = grp_of.p;
+  aa.pos_of = pos_of.p;
+  aa.srow = srow.p;
+  aa.skey = skey.p;
+  aa.sval = sval.p;
+  int ablock = 64;
+  while (ablock < maxn && ablock < 256) ablock *= 2;
+  launch_assemble(aa, ablock, s);
+  cls_tol.ensure(NC, mt);
+  cls_moff.ensure(NC, mt);
+  cls_ld.ensure(NC, mt);
+  cls_rows.ensure(NC, mt);
+  cls_poff.ensure(NC, mt);
+  cls_rank.ensure(NC, mt);
+  perm.ensure(nact, mt);
+  hipLaunchKernelGGL(k_class_tol, dim3(nblocks(NC)), dim3(kThreads), 0, s, NC, cls_group.p, cls_col0.p, cls_n.p,
+                     gstart.p, colK2.p, colS2.p, H->eps, split, yoff.p, nf_start.p, sym, P, cls_moff.p, cls_ld.p,
+                     cls_rows.p, cls_tol.p, cls_poff.p);
+  HIF_HIP(hipGetLastError());
+  tm.mark(PH_ASM);
+
+  // ---- interpolative decompositions (one per class) -----------------------
+  std::vector<int32_t> h_cls_n, h_cls_col0;
+  to_host(h_cls_n, cls_n.p, NC, s);
+  to_host(h_cls_col0, cls_col0.p, NC, s);
+  int maxq = 1;
+  for (int q = 0; q < NC; ++q) maxq = std::max(maxq, h_cls_n[q]);
+  tm.mark(PH_HOST);
+  IdArgs ia{};
+  ia.base = Y.p;
+  ia.moff = cls_moff.p;
+  ia.ld = cls_ld.p;
+  ia.rows = cls_rows.p;
+  ia.cols = cls_n.p;
+  ia.tol = cls_tol.p;
+  ia.rank = cls_rank.p;
+  ia.perm = perm.p;
+  ia.poff = cls_poff.p;
+  ia.Tout = nullptr;
+  ia.toff = nullptr;
+  ia.nprob = NC;
+  launch_id(ia, maxq, s);
+  tm.mark(PH_ID);
+
+  // ---- records: sizes from the ranks ---------------------------------------
+  std::vector<int32_t> h_rank;
+  to_host(h_rank, cls_rank.p, NC, s);
+  std::vector<int32_t> h_grec(G, -1), h_skoff(NC), h_rdoff(NC);
+  std::vector<int64_t> h_newoff(G, 0);
+  int64_t itot = 0, dtot = 0, ntot_new = 0, skel = 0;
+  double idfl = 0.0, elfl = 0.0;
+  for (int g = 0; g < G; ++g) {
+    int kk = 0, rr = 0;
+    const int64_t nf = h_nf[g + 1] - h_nf[g];
+    const int64_t m = sym ? nf + P : 2 * nf + 2 * P;
+    for (int q = h_cls_first[g]; q < h_cls_first[g + 1]; ++q) {
+      h_skoff[q] = kk;
+      h_rdoff[q] = rr;
+      kk += h_rank[q];
+      rr += h_cls_n[q] - h_rank[q];
+      const double nq = h_cls_n[q], kq = h_rank[q];
+      idfl += 4.0 * m * nq * kq - 2.0 * kq * kq * (m + nq) + 4.0 * kq * kq * kq / 3.0 + kq * kq * (nq - kq);
+    }
+    skel += kk;
+    h_newoff[g] = ntot_new;
+    if (rr > 0) {
+      GroupRec R;
+      R.r = rr;
+      R.k = kk;
+      R.idx = itot;
+      R.off = dtot;
+      h_grec[g] = int32_t(sub.hrec.size());
+      sub.hrec.push_back(R);
+      itot += 2 * int64_t(rr) + kk;
+      dtot += 3 * int64_t(kk) * rr + int64_t(rr) * rr;
+      ntot_new += int64_t(kk) * kk;
+      sub.max_r = std::max(sub.max_r, rr);
+      sub.max_k = std::max(sub.max_k, kk);
+      const double r3 = rr, k3 = kk;
+      elfl += 6.0 * r3 * r3 * k3 + 4.0 * k3 * k3 * r3 + 2.0 / 3.0 * r3 * r3 * r3 + 4.0 * r3 * r3 * k3 + 2.0 * k3 * k3 * r3;
+    }
+  }
+  st.sub_skel[si] = skel;
+  st.sub_id_flops[si] = idfl;
+  st.sub_elim_flops[si] = elfl;
+  sub.nrec = int(sub.hrec.size());
+  sub.rec.alloc(sub.nrec, mt);
+  to_dev(sub.rec.p, sub.hrec, s);
+  sub.iarena.alloc(itot, mt);
+  sub.darena.alloc(dtot, mt);
+  grec.ensure(G, mt);
+  to_dev(grec.p, h_grec, s);
+  cls_skoff.ensure(NC, mt);
+  cls_rdoff.ensure(NC, mt);
+  to_dev(cls_skoff.p, h_skoff, s);
+  to_dev(cls_rdoff.p, h_rdoff, s);
+  newoff.ensure(G, mt);
+  to_dev(newoff.p, h_newoff, s);
+  newkey.ensure(ntot_new, mt);
+  newval.ensure(ntot_new, mt);
+  loc.ensure(nact, mt);
+  rlo.ensure(nact, mt);
+  rhi.ensure(nact, mt);
+  tm.mark(PH_HOST);
+
+  // ---- skeletonization and elimination -------------------------------------
+  ElimArgs ea{};
+  ea.ngroups = G;
+  ea.cord = cord.p;
+  ea.gstart = gstart.p;
+  ea.grec = grec.p;
+  ea.recs = sub.rec.p;
+  ea.iarena = sub.iarena.p;
+  ea.darena = sub.darena.p;
+  ea.Y = Y.p;
+  ea.yoff = yoff.p;
+  ea.Acc = Acc.p;
+  ea.Scc = Scc.p;
+  ea.aoff = aoff.p;
+  ea.cls_first = cls_first.p;
+  ea.cls_col0 = cls_col0.p;
+  ea.cls_n = cls_n.p;
+  ea.cls_rank = cls_rank.p;
+  ea.cls_skoff = cls_skoff.p;
+  ea.cls_rdoff = cls_rdoff.p;
+  ea.perm = perm.p;
+  ea.loc = loc.p;
+  ea.rlo = rlo.p;
+  ea.rhi = rhi.p;
+  ea.newkey = newkey.p;
+  ea.newval = newval.p;
+  ea.newoff = newoff.p;
+  ea.status = status.p;
+  launch_eliminate(ea, s);
+  tm.mark(PH_ELIM);
+
+  // ---- SCI store update, active set ----------------------------------------
+  if (sub.nrec > 0) {
+    hipLaunchKernelGGL(k_mark_inactive, dim3(sub.nrec), dim3(64), 0, s, sub.rec.p, sub.nrec, sub.iarena.p, active.p);
+    HIF_HIP(hipGetLastError());
+  }
+  int64_t kept = 0;
+  if (snnz > 0) {
+    flag64.ensure(snnz, mt);
+    pos64.ensure(snnz + 1, mt);
+    hipLaunchKernelGGL(k_sci_keep, dim3(nblocks(snnz)), dim3(kThreads), 0, s, skey.p, snnz, active.p, grp_of.p, grec.p,
+                       flag64.p);
+    exclusive_scan_i64(flag64.p, pos64.p, snnz, s, prim, mt);
+    kept = scalar_at(pos64.p + snnz, s);
+  }
+  const int64_t nnz2 = kept + ntot_new;
+  skey2.ensure(nnz2, mt);
+  sval2.ensure(nnz2, mt);
+  sidx.ensure(nnz2, mt);
+  sidx2.ensure(nnz2, mt);
+  if (snnz > 0 && kept > 0)
+    hipLaunchKernelGGL(k_sci_compact, dim3(nblocks(snnz)), dim3(kThreads), 0, s, skey.p, sval.p, snnz, flag64.p,
+                       pos64.p, skey2.p, sval2.p, sidx.p);
+  if (ntot_new > 0)
+    hipLaunchKernelGGL(k_append, dim3(nblocks(ntot_new)), dim3(kThreads), 0, s, newkey.p, newval.p, ntot_new, kept,
+                       skey2.p, sval2.p, sidx.p);
+  HIF_HIP(hipGetLastError());
+  skey.ensure(nnz2, mt);
+  sval.ensure(nnz2, mt);
+  // sort (key, idx) then gather values; keys land back in skey2 / skey
+  if (nnz2 > 0) {
+    sort_u64_i32(skey2.p, skey.p, sidx.p, sidx2.p, nnz2, 32 + shift, s, prim, mt);
+    HIF_HIP(hipMemcpyAsync(skey.p, skey2.p, nnz2 * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_gather_val, dim3(nblocks(nnz2)), dim3(kThreads), 0, s, sval2.p, sidx.p, nnz2, sval.p);
+  }
+  snnz = nnz2;
+  cnt.ensure(N, mt);
+  hipLaunchKernelGGL(k_fill_i64, dim3(nblocks(N)), dim3(kThreads), 0, s, cnt.p, N, int64_t(0));
+  if (snnz > 0) hipLaunchKernelGGL(k_row_count, dim3(nblocks(snnz)), dim3(kThreads), 0, s, skey.p, snnz, cnt.p);
+  exclusive_scan_i64(cnt.p, srow.p, N, s, prim, mt);
+  HIF_HIP(hipGetLastError());
+  // active list
+  akeep.ensure(nact, mt);
+  apos.ensure(nact + 1, mt);
+  hipLaunchKernelGGL(k_active_keep, dim3(nblocks(nact)), dim3(kThreads), 0, s, act.p, nact, active.p, akeep.p);
+  exclusive_scan_i32(akeep.p, apos.p, nact, s, prim, mt);
+  const int64_t nact2 = scalar_at(apos.p + nact, s);
+  act2.ensure(nact2, mt);
+  hipLaunchKernelGGL(k_active_compact, dim3(nblocks(nact)), dim3(kThreads), 0, s, act.p, nact, akeep.p, apos.p, act2.p);
+  HIF_HIP(hipGetLastError());
+  std::swap(act, act2);
+  nact = nact2;
+  tm.mark(PH_SCI);
+  tm.flush(st.t_phase_ms);
+  const int32_t bad = scalar_at(status.p, s);
+  HIF_REQUIRE(bad == 0, HIF_ESINGULAR, "zero pivot in a redundant block B_rr (Lemma 2.1 needs it nonsingular)");
+  H->subs.push_back(std::move(sub));
+}
+
+void Factorizer::top() {
+  tm.mark(PH_OTHER);
+  H->ntop = nact;
+  const int64_t n = nact;
+  H->top_idx.alloc(n, mt);
+  H->top_piv.alloc(n, mt);
+  H->top_lu.alloc(n * n, mt);
+  if (n > 0) {
+    HIF_HIP(hipMemcpyAsync(H->top_idx.p, act.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_pos_scatter, dim3(nblocks(n)), dim3(kThreads), 0, s, act.p, n, pos_of.p);
+    TopArgs ta{};
+    ta.dim = D;
+    ta.n = n;
+    ta.pts = pts;
+    ta.a = a;
+    ta.b = b;
+    ta.c = c;
+    ta.w = w;
+    ta.selfk = sf;
+    ta.idx = H->top_idx.p;
+    ta.pos_of = pos_of.p;
+    ta.srow = srow.p;
+    ta.skey = skey.p;
+    ta.sval = sval.p;
+    ta.A = H->top_lu.p;
+    ta.piv = H->top_piv.p;
+    ta.status = status.p;
+    launch_top(ta, s);
+  }
+  tm.mark(PH_TOP);
+  tm.flush(H->stats.t_phase_ms);
+  const int32_t bad = scalar_at(status.p, s);
+  HIF_REQUIRE(bad == 0, HIF_ESINGULAR, "zero pivot in the top block A_L (Lemma 2.1 needs it nonsingular)");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* kr, const double* a_in,
+                 const double* b_in, const double* c_in, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int D = H->dim;
+  const int64_t N = H->n;
+  MemTracker* mt = &H->mem;
+  Factorizer F{};
+  F.H = H;
+  F.s = s;
+  F.D = D;
+  F.N = N;
+  F.mt = mt;
+  F.tm.s = s;
+
+  // Operator copies: a (0 if absent), b, c (1 if absent), w (h^d), self term.
+  DBuf<double> op;
+  op.alloc(int64_t(N) * (D + 5), mt);
+  double* pts = op.p;
+  double* a = pts + N * D;
+  double* b = a + N;
+  double* c = b + N;
+  double* w = c + N;
+  double* sf = w + N;
+  HIF_HIP(hipMemcpyAsync(pts, points, sizeof(double) * N * D, hipMemcpyDeviceToDevice, s));
+  auto fill_or_copy = [&](double* dst, const double* src, double v) {
+    if (src)
+      HIF_HIP(hipMemcpyAsync(dst, src, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    else
+      hipLaunchKernelGGL(k_fill_f64, dim3(nblocks(N)), dim3(kThreads), 0, s, dst, N, v);
+  };
+  fill_or_copy(a, a_in, 0.0);
+  fill_or_copy(b, b_in, 1.0);
+  fill_or_copy(c, c_in, 1.0);
+  fill_or_copy(w, kr->weights, std::pow(kr->h, D));
+  fill_or_copy(sf, kr->self, kr->self ? 0.0 : self_integral(kr->h, D));
+  HIF_HIP(hipGetLastError());
+  F.pts = pts;
+  F.a = a;
+  F.b = b;
+  F.c = c;
+  F.w = w;
+  F.sf = sf;
+
+  F.status.alloc(2, mt);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, F.status.p, int64_t(2), 0);
+  hipLaunchKernelGGL(k_validate, dim3(nblocks(N)), dim3(kThreads), 0, s, pts, N, D, a, b, c, w, sf, F.status.p);
+  HIF_HIP(hipGetLastError());
+  const int32_t vflags = scalar_at(F.status.p, s);
+  HIF_REQUIRE(!(vflags & 1), HIF_EINVAL, "non-finite point coordinate");
+  HIF_REQUIRE(!(vflags & 2), HIF_EINVAL, "point outside the unit box [0,1]^d");
+  HIF_REQUIRE(!(vflags & 4), HIF_EINVAL, "non-finite a, b, c, weight or self term");
+
+  // Symmetric compression (Section 5) iff b_i = s c_i w_i for one scalar s.
+  if (H->opts.symmetric < 0) {
+    std::vector<double> hb, hc, hw;
+    to_host(hb, b, N, s);
+    to_host(hc, c, N, s);
+    to_host(hw, w, N, s);
+    bool sym = true;
+    const double cw0 = hc[0] * hw[0], b0 = hb[0];
+    for (int64_t i = 0; i < N && sym; ++i) sym = (hb[i] * cw0 == hc[i] * hw[i] * b0);
+    H->symmetric = sym ? 1 : 0;
+  } else {
+    H->symmetric = H->opts.symmetric;
+  }
+
+  // Tree depth: split boxes holding more than leaf points; only trees whose
+  // leaves all sit at one depth are handled (Section 3.1, uniform grids).
+  {
+    DBuf<int32_t> counts, mm;
+    mm.alloc(2, mt);
+    int L = 0;
+    int32_t prev_min = INT_MAX;
+    for (;;) {
+      const int64_t S = int64_t(1) << L;
+      int64_t nb = 1;
+      for (int k = 0; k < D; ++k) nb *= S;
+      HIF_REQUIRE(nb <= 64 * N + 4096 && L <= 24, HIF_EUNSUPPORTED,
+                  "adaptive tree too deep for a uniform-depth factorization (clustered or coincident points)");
+      counts.ensure(nb, mt);
+      hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(nb)), dim3(kThreads), 0, s, counts.p, nb, 0);
+      if (D == 2)
+        hipLaunchKernelGGL(k_box_count<2>, dim3(nblocks(N)), dim3(kThreads), 0, s, pts, N, int(S), counts.p);
+      else
+        hipLaunchKernelGGL(k_box_count<3>, dim3(nblocks(N)), dim3(kThreads), 0, s, pts, N, int(S), counts.p);
+      std::vector<int32_t> init = {INT_MAX, 0};
+      to_dev(mm.p, init, s);
+      hipLaunchKernelGGL(k_minmax, dim3(nblocks(nb)), dim3(kThreads), 0, s, counts.p, nb, mm.p);
+      HIF_HIP(hipGetLastError());
+      std::vector<int32_t> h;
+      to_host(h, mm.p, 2, s);
+      if (h[1] <= H->leaf) break;
+      prev_min = h[0];
+      ++L;
+    }
+    HIF_REQUIRE(L == 0 || prev_min > H->leaf, HIF_EUNSUPPORTED,
+                "adaptive tree leaves are not all at one depth (non-uniform point distribution)");
+    H->L = L;
+  }
+  HIF_REQUIRE(H->L <= HIF_MAX_SUBLEVELS / 3, HIF_EUNSUPPORTED, "tree deeper than the statistics arrays allow");
+
+  // Coincident points: compare pairs inside every leaf box.
+  F.active.alloc(N, mt);
+  F.act.alloc(N, mt);
+  F.grp_of.alloc(N, mt);
+  F.pos_of.alloc(N, mt);
+  F.srow.alloc(N + 1, mt);
+  hipLaunchKernelGGL(k_fill_u8, dim3(nblocks(N)), dim3(kThreads), 0, s, F.active.p, N, uint8_t(1));
+  hipLaunchKernelGGL(k_iota, dim3(nblocks(N)), dim3(kThreads), 0, s, F.act.p, N);
+  hipLaunchKernelGGL(k_fill_i64, dim3(nblocks(N + 1)), dim3(kThreads), 0, s, F.srow.p, N + 1, int64_t(0));
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(N)), dim3(kThreads), 0, s, F.grp_of.p, N, -1);
+  HIF_HIP(hipGetLastError());
+  F.nact = N;
+  {
+    const int S = 1 << H->L;
+    int ncell = 1;
+    for (int k = 0; k < D; ++k) ncell *= S;
+    F.ckey.ensure(N, mt);
+    F.cdof.ensure(N, mt);
+    F.ktmp.ensure(N, mt);
+    F.vtmp.ensure(N, mt);
+    F.cell_lo.ensure(ncell, mt);
+    F.cell_hi.ensure(ncell, mt);
+    if (D == 2)
+      hipLaunchKernelGGL(k_group_key<2>, dim3(nblocks(N)), dim3(kThreads), 0, s, pts, F.act.p, N, 0, S, F.ckey.p, F.cdof.p);
+    else
+      hipLaunchKernelGGL(k_group_key<3>, dim3(nblocks(N)), dim3(kThreads), 0, s, pts, F.act.p, N, 0, S, F.ckey.p, F.cdof.p);
+    sort_i32_i32(F.ckey.p, F.ktmp.p, F.cdof.p, F.vtmp.p, N, ceil_log2(uint64_t(ncell) + 1), s, F.prim, mt);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(ncell)), dim3(kThreads), 0, s, F.cell_lo.p, int64_t(ncell), 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(ncell)), dim3(kThreads), 0, s, F.cell_hi.p, int64_t(ncell), 0);
+    hipLaunchKernelGGL(k_cell_table, dim3(nblocks(N)), dim3(kThreads), 0, s, F.ckey.p, N, F.cell_lo.p, F.cell_hi.p);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, F.status.p, int64_t(2), 0);
+    hipLaunchKernelGGL(k_coincident, dim3(ncell), dim3(kThreads), 0, s, pts, D, F.cdof.p, F.cell_lo.p, F.cell_hi.p,
+                       F.status.p);
+    HIF_HIP(hipGetLastError());
+    const int32_t dup = scalar_at(F.status.p, s);
+    HIF_REQUIRE(dup == 0, HIF_EINVAL, "coincident points (the kernel is singular at r = 0)");
+  }
+
+  // Proxy directions (Section 3.3): circle p -> (cos 2 pi p / P, sin 2 pi p / P);
+  // sphere: spherical Fibonacci points z = 1 - (2p+1)/P, phi = p pi (3 - sqrt 5).
+  {
+    const int P = H->nproxy;
+    std::vector<double> u(size_t(P) * D);
+    for (int p = 0; p < P; ++p) {
+      if (D == 2) {
+        const double t = 2.0 * M_PI * double(p) / double(P);
+        u[2 * p] = std::cos(t);
+        u[2 * p + 1] = std::sin(t);
+      } else {
+        const double z = 1.0 - (2.0 * p + 1.0) / double(P);
+        const double rho = std::sqrt(1.0 - z * z);
+        const double phi = double(p) * M_PI * (3.0 - std::sqrt(5.0));
+        u[3 * p] = rho * std::cos(phi);
+        u[3 * p + 1] = rho * std::sin(phi);
+        u[3 * p + 2] = z;
+      }
+    }
+    F.proxy_u.alloc(u.size(), mt);
+    to_dev(F.proxy_u.p, u, s);
+  }
+
+  // Levels: cells, then (faces and) edges; RSF: cells only.
+  std::vector<int> kinds;
+  if (H->opts.variant == HIF_VARIANT_RSF) kinds = {0};
+  else if (D == 2) kinds = {0, 2};
+  else kinds = {0, 1, 2};
+  for (int lvl = 0; lvl < H->L; ++lvl)
+    for (int kind : kinds) F.sublevel(lvl, kind);
+  F.top();
+
+  // Statistics.
+  hif_stats_t& st = H->stats;
+  st.n = N;
+  st.dim = D;
+  st.levels = H->L;
+  st.n_sublevels = int32_t(H->subs.size());
+  st.top_size = H->ntop;
+  int64_t fb = 0;
+  for (auto& sub : H->subs) {
+    for (auto& R : sub.hrec) fb += 8 * (3 * int64_t(R.k) * R.r + int64_t(R.r) * R.r) + 4 * (2 * int64_t(R.r) + R.k);
+  }
+  fb += 8 * H->ntop * H->ntop + 8 * H->ntop;
+  st.factor_bytes = fb;
+  HIF_HIP(hipStreamSynchronize(s));
+  st.t_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void partition_impl(const double* pts, int64_t n, int dim, const uint8_t* active, int kind, int32_t S,
+                    int32_t* group, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(k_partition<2>, dim3(nblocks(n)), dim3(kThreads), 0, s, pts, n, active, kind, S, group);
+  else
+    hipLaunchKernelGGL(k_partition<3>, dim3(nblocks(n)), dim3(kThreads), 0, s, pts, n, active, kind, S, group);
+  HIF_HIP(hipGetLastError());
+  HIF_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace hif

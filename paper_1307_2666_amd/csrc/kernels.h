@@ -1,0 +1,99 @@
+// Launch interfaces of the per-group dense kernels (dense.hip) used by the
+// factorization driver (factor.hip).  Internal, not part of the ABI.
+#pragma once
+
+#include "common.h"
+
+namespace hif {
+
+// Batched assembly of the compressed blocks Y_c (eqn proxy-id; the column
+// block Y'_c of Section 5 when symmetric) and of A_cc, one workgroup per group.
+struct AsmArgs {
+  int dim = 2, sym = 1, nproxy = 64, ngroups = 0;
+  double R = 0;                 // absolute proxy radius of this sub-level
+  const double *pts, *a, *b, *c, *w, *selfk;
+  const double* proxy_u;        // [nproxy][dim] unit directions
+  const int32_t* cord;          // group DOFs, class order, groups concatenated
+  const int64_t* gstart;        // [G+1]
+  const int32_t* nf_idx;        // near-field DOFs (ascending per group)
+  const int64_t* nf_start;      // [G+1]
+  const double* zc;             // [G][dim] group centres
+  const int64_t* yoff;          // [G] offset of Y_c (row-major m x n)
+  const int64_t* aoff;          // [G] offset of A_cc / S_cc (row-major n x n)
+  double *Y, *Acc, *Scc;
+  double *colK2, *colS2;        // per cord position: squared norms of kernel / SCI part of Y
+  const int32_t* grp_of;        // per DOF: group of this sub-level (-1 inactive)
+  const int32_t* pos_of;        // per DOF: position within its group (class order)
+  const int64_t* srow;          // SCI store CSR row pointer [N+1]
+  const uint64_t* skey;         // (i << 32 | j)
+  const double2* sval;          // (S_ij, S_ji)
+};
+void launch_assemble(const AsmArgs& A, int block, hipStream_t s);
+
+// Batched interpolative decomposition by column-pivoted Householder QR
+// (Lemma 2.2, Section 2.2), one workgroup per problem, in place.
+struct IdArgs {
+  double* base;
+  const int64_t* moff;   // offset of element (0,0) of problem q
+  const int32_t* ld;     // row stride (row-major)
+  const int32_t* rows;
+  const int32_t* cols;
+  const double* tol;
+  int32_t* rank;
+  int32_t* perm;         // per problem: cols entries (skeleton pivots, then redundant ascending)
+  const int64_t* poff;
+  double* Tout;          // optional compact copy of T (k x r row-major)
+  const int64_t* toff;
+  int nprob = 0;
+};
+void launch_id(const IdArgs& A, int max_cols, hipStream_t s);
+
+// Batched skeletonization + elimination (Lemma 2.4 with Lemma 2.1), one
+// workgroup per group with a record.
+struct ElimArgs {
+  int ngroups = 0;
+  const int32_t* cord;
+  const int64_t* gstart;
+  const int32_t* grec;          // [G] record index or -1
+  const GroupRec* recs;
+  int32_t* iarena;
+  double* darena;
+  const double* Y;              // IDs in place (T_q in rows 0..k_q-1)
+  const int64_t* yoff;
+  double* Acc;                  // destroyed (reused as scratch)
+  const double* Scc;
+  const int64_t* aoff;
+  const int32_t* cls_first;     // [G+1] classes of group g
+  const int32_t* cls_col0;      // group-local first column of class q
+  const int32_t* cls_n;         // columns of class q
+  const int32_t* cls_rank;      // skeleton size of class q
+  const int32_t* cls_skoff;     // offset of class q within the group's skeleton list
+  const int32_t* cls_rdoff;     // offset of class q within the group's redundant list
+  const int32_t* perm;          // class perms, slot at gstart[g] + col0
+  int32_t* loc;                 // scratch [total group size]: rd_loc then sk_loc
+  int32_t* rlo;                 // scratch [total group size]
+  int32_t* rhi;
+  uint64_t* newkey;             // new SCI entries (k x k per group)
+  double2* newval;
+  const int64_t* newoff;        // [G]
+  int32_t* status;              // set to 1 on a zero pivot
+};
+void launch_eliminate(const ElimArgs& A, hipStream_t s);
+
+// Top block A_L(s_L, s_L) = diag(a) + bKc + S, then LU with partial pivoting.
+struct TopArgs {
+  int dim = 2;
+  int64_t n = 0;
+  const double *pts, *a, *b, *c, *w, *selfk;
+  const int32_t* idx;           // top DOFs ascending
+  const int32_t* pos_of;        // per DOF: position in idx
+  const int64_t* srow;
+  const uint64_t* skey;
+  const double2* sval;
+  double* A;                    // n x n row-major
+  int32_t* piv;
+  int32_t* status;
+};
+void launch_top(const TopArgs& A, hipStream_t s);
+
+}  // namespace hif

@@ -1,0 +1,265 @@
+// Factored apply / solve sweeps: F = U_0^{-T} ... D ... V_0^{-1} and
+// F^{-1} = V_0 ... D^{-1} ... U_0^T (eqns rskelf, hifie2, hifie3) and their
+// transposes.  Per group (Lemma 2.4 with Lemma 2.1), with Q = [I 0; -T I] in
+// (redundant, skeleton) order:
+//   solve   up:  u_r -= T^T u_s; u_s -= E u_r     mid: u_r = B_rr^{-1} u_r   down: u_r -= G u_s; u_s -= T u_r
+//   solve_T up:  u_r -= T^T u_s; u_s -= G^T u_r   mid: B_rr^{-T}             down: u_r -= E^T u_s; u_s -= T u_r
+//   apply   up:  x_s += T x_r;   x_r += G x_s     mid: x_r = B_rr x_r        down: y_s += E y_r; y_r += T^T y_s
+//   apply_T up:  x_s += T x_r;   x_r += E^T x_s   mid: B_rr^T                down: y_s += G^T y_r; y_r += T^T y_s
+// "up" visits sub-levels finest first, "down" in reverse; the groups of one
+// sub-level touch disjoint DOFs and run as one launch, one workgroup each.
+// Vectors are [nrhs][N] in the caller's order; every product works in place
+// through the records' global DOF indices.
+#include "common.h"
+
+namespace hif {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+struct SwArgs {
+  const GroupRec* recs;
+  const int32_t* iarena;
+  const double* darena;
+  double* u;
+  double* work;
+  int64_t N;
+  int nrhs;
+  int op;
+};
+
+// u[yi[i]] += sgn * sum_j M[i*ld + j] u[xi[j]]   (one wave per row)
+__device__ void gemv_rows(const double* M, int nrow, int ncol, int ld, const int32_t* yi, const int32_t* xi,
+                          double* u, int64_t N, int nrhs, double sgn) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = wv; i < nrow; i += nw) {
+    const double* mr = M + int64_t(i) * ld;
+    for (int v = 0; v < nrhs; ++v) {
+      const double* uv = u + v * N;
+      double s = 0.0;
+      for (int j = lane; j < ncol; j += 64) s += mr[j] * uv[xi[j]];
+      s = wave_sum(s);
+      if (lane == 0) u[v * N + yi[i]] += sgn * s;
+    }
+  }
+}
+
+// u[yi[j]] += sgn * sum_i M[i*ld + j] u[xi[i]]   (one thread per column and RHS)
+__device__ void gemv_cols(const double* M, int nrow, int ncol, int ld, const int32_t* yi, const int32_t* xi,
+                          double* u, int64_t N, int nrhs, double sgn) {
+  for (int e = threadIdx.x; e < ncol * nrhs; e += blockDim.x) {
+    const int j = e % ncol, v = e / ncol;
+    const double* uv = u + v * N;
+    double s = 0.0;
+    for (int i = 0; i < nrow; ++i) s += M[int64_t(i) * ld + j] * uv[xi[i]];
+    u[v * N + yi[j]] += sgn * s;
+  }
+}
+
+__global__ void k_up(SwArgs A) {
+  const GroupRec R = A.recs[blockIdx.x];
+  const int r = R.r, k = R.k;
+  const int32_t* rd = A.iarena + R.idx;
+  const int32_t* sk = rd + r;
+  const double* T = A.darena + R.off;
+  const double* E = T + int64_t(k) * r;
+  const double* Gm = E + int64_t(k) * r;
+  if (k == 0) return;
+  if (A.op <= 1) {
+    gemv_cols(T, k, r, r, rd, sk, A.u, A.N, A.nrhs, -1.0);  // u_r -= T^T u_s
+    __syncthreads();
+    if (A.op == 0)
+      gemv_rows(E, k, r, r, sk, rd, A.u, A.N, A.nrhs, -1.0);  // u_s -= E u_r
+    else
+      gemv_cols(Gm, r, k, k, sk, rd, A.u, A.N, A.nrhs, -1.0);  // u_s -= G^T u_r
+  } else {
+    gemv_rows(T, k, r, r, sk, rd, A.u, A.N, A.nrhs, 1.0);  // x_s += T x_r
+    __syncthreads();
+    if (A.op == 2)
+      gemv_rows(Gm, r, k, k, rd, sk, A.u, A.N, A.nrhs, 1.0);  // x_r += G x_s
+    else
+      gemv_cols(E, k, r, r, rd, sk, A.u, A.N, A.nrhs, 1.0);  // x_r += E^T x_s
+  }
+}
+
+__global__ void k_down(SwArgs A) {
+  const GroupRec R = A.recs[blockIdx.x];
+  const int r = R.r, k = R.k;
+  const int32_t* rd = A.iarena + R.idx;
+  const int32_t* sk = rd + r;
+  const double* T = A.darena + R.off;
+  const double* E = T + int64_t(k) * r;
+  const double* Gm = E + int64_t(k) * r;
+  if (k == 0) return;
+  if (A.op <= 1) {
+    if (A.op == 0)
+      gemv_rows(Gm, r, k, k, rd, sk, A.u, A.N, A.nrhs, -1.0);  // u_r -= G u_s
+    else
+      gemv_cols(E, k, r, r, rd, sk, A.u, A.N, A.nrhs, -1.0);  // u_r -= E^T u_s
+    __syncthreads();
+    gemv_rows(T, k, r, r, sk, rd, A.u, A.N, A.nrhs, -1.0);  // u_s -= T u_r
+  } else {
+    if (A.op == 2)
+      gemv_rows(E, k, r, r, sk, rd, A.u, A.N, A.nrhs, 1.0);  // y_s += E y_r
+    else
+      gemv_cols(Gm, r, k, k, sk, rd, A.u, A.N, A.nrhs, 1.0);  // y_s += G^T y_r
+    __syncthreads();
+    gemv_cols(T, k, r, r, rd, sk, A.u, A.N, A.nrhs, 1.0);  // y_r += T^T y_s
+  }
+}
+
+// Block solve / multiply with an LU factorization P B = L U (row interchanges
+// j <-> piv[j] applied in order j = 0..n-1), on the entries u[v*N + idx[i]].
+__device__ void lu_op(const double* LU, const int32_t* piv, int n, const int32_t* idx, double* u, double* work,
+                      int64_t N, int nrhs, int op) {
+  const int tid = threadIdx.x, B = blockDim.x;
+  auto X = [&](int i, int v) -> double& { return u[v * N + idx[i]]; };
+  auto W = [&](int i, int v) -> double& { return work[v * N + idx[i]]; };
+  if (op == 0) {  // x = B^{-1} x = U^{-1} L^{-1} P x
+    for (int v = tid; v < nrhs; v += B)
+      for (int j = 0; j < n; ++j)
+        if (piv[j] != j) { double t = X(j, v); X(j, v) = X(piv[j], v); X(piv[j], v) = t; }
+    __syncthreads();
+    for (int j = 0; j < n - 1; ++j) {
+      const int w = n - 1 - j;
+      for (int e = tid; e < w * nrhs; e += B) {
+        const int i = j + 1 + e % w, v = e / w;
+        X(i, v) -= LU[int64_t(i) * n + j] * X(j, v);
+      }
+      __syncthreads();
+    }
+    for (int j = n - 1; j >= 0; --j) {
+      const double inv = 1.0 / LU[int64_t(j) * n + j];
+      for (int e = tid; e < j * nrhs; e += B) {
+        const int i = e % j, v = e / j;
+        X(i, v) -= LU[int64_t(i) * n + j] * (X(j, v) * inv);
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < n * nrhs; e += B) {
+      const int i = e % n, v = e / n;
+      X(i, v) /= LU[int64_t(i) * n + i];
+    }
+  } else if (op == 1) {  // x = B^{-T} x = P^T L^{-T} U^{-T} x
+    for (int j = 0; j < n; ++j) {
+      const double inv = 1.0 / LU[int64_t(j) * n + j];
+      const int w = n - 1 - j;
+      for (int e = tid; e < w * nrhs; e += B) {
+        const int i = j + 1 + e % w, v = e / w;
+        X(i, v) -= LU[int64_t(j) * n + i] * (X(j, v) * inv);
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < n * nrhs; e += B) {
+      const int i = e % n, v = e / n;
+      X(i, v) /= LU[int64_t(i) * n + i];
+    }
+    __syncthreads();
+    for (int j = n - 1; j > 0; --j) {
+      for (int e = tid; e < j * nrhs; e += B) {
+        const int i = e % j, v = e / j;
+        X(i, v) -= LU[int64_t(j) * n + i] * X(j, v);
+      }
+      __syncthreads();
+    }
+    for (int v = tid; v < nrhs; v += B)
+      for (int j = n - 1; j >= 0; --j)
+        if (piv[j] != j) { double t = X(j, v); X(j, v) = X(piv[j], v); X(piv[j], v) = t; }
+  } else if (op == 2) {  // x = B x = P^T L U x
+    for (int e = tid; e < n * nrhs; e += B) {
+      const int i = e % n, v = e / n;
+      double s = 0.0;
+      for (int j = i; j < n; ++j) s += LU[int64_t(i) * n + j] * X(j, v);
+      W(i, v) = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * nrhs; e += B) {
+      const int i = e % n, v = e / n;
+      double s = W(i, v);
+      for (int j = 0; j < i; ++j) s += LU[int64_t(i) * n + j] * W(j, v);
+      X(i, v) = s;
+    }
+    __syncthreads();
+    for (int v = tid; v < nrhs; v += B)
+      for (int j = n - 1; j >= 0; --j)
+        if (piv[j] != j) { double t = X(j, v); X(j, v) = X(piv[j], v); X(piv[j], v) = t; }
+  } else {  // x = B^T x = U^T L^T P x
+    for (int v = tid; v < nrhs; v += B)
+      for (int j = 0; j < n; ++j)
+        if (piv[j] != j) { double t = X(j, v); X(j, v) = X(piv[j], v); X(piv[j], v) = t; }
+    __syncthreads();
+    for (int e = tid; e < n * nrhs; e += B) {
+      const int i = e % n, v = e / n;
+      double s = X(i, v);
+      for (int j = i + 1; j < n; ++j) s += LU[int64_t(j) * n + i] * X(j, v);
+      W(i, v) = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * nrhs; e += B) {
+      const int i = e % n, v = e / n;
+      double s = 0.0;
+      for (int j = 0; j <= i; ++j) s += LU[int64_t(j) * n + i] * W(j, v);
+      X(i, v) = s;
+    }
+  }
+}
+
+__global__ void k_mid(SwArgs A) {
+  const GroupRec R = A.recs[blockIdx.x];
+  const int r = R.r, k = R.k;
+  const int32_t* rd = A.iarena + R.idx;
+  const int32_t* piv = rd + r + k;
+  const double* LU = A.darena + R.off + 3 * int64_t(k) * r;
+  lu_op(LU, piv, r, rd, A.u, A.work, A.N, A.nrhs, A.op);
+}
+
+__global__ void k_top(const double* LU, const int32_t* piv, int n, const int32_t* idx, double* u, double* work,
+                      int64_t N, int nrhs, int op) {
+  lu_op(LU, piv, n, idx, u, work, N, nrhs, op);
+}
+
+__global__ void k_copy(const double* x, double* y, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = x[i];
+}
+
+}  // namespace
+
+void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s) {
+  const int64_t N = H->n;
+  const int64_t tot = N * nrhs;
+  if (x != y) {
+    int64_t blocks = (tot + 255) / 256;
+    if (blocks > (1 << 20)) blocks = 1 << 20;
+    hipLaunchKernelGGL(k_copy, dim3(unsigned(blocks)), dim3(256), 0, s, x, y, tot);
+    HIF_HIP(hipGetLastError());
+  }
+  if (op >= 2) H->work.ensure(tot, &H->mem);
+  for (int64_t v0 = 0; v0 < nrhs; v0 += 8) {
+    const int nv = int(std::min<int64_t>(8, nrhs - v0));
+    double* u = y + v0 * N;
+    double* wk = op >= 2 ? H->work.p + v0 * N : nullptr;
+    for (auto& sub : H->subs) {
+      if (sub.nrec == 0) continue;
+      SwArgs A{sub.rec.p, sub.iarena.p, sub.darena.p, u, wk, N, nv, op};
+      hipLaunchKernelGGL(k_up, dim3(sub.nrec), dim3(kBlock), 0, s, A);
+    }
+    for (auto& sub : H->subs) {
+      if (sub.nrec == 0) continue;
+      SwArgs A{sub.rec.p, sub.iarena.p, sub.darena.p, u, wk, N, nv, op};
+      hipLaunchKernelGGL(k_mid, dim3(sub.nrec), dim3(kBlock), 0, s, A);
+    }
+    if (H->ntop > 0)
+      hipLaunchKernelGGL(k_top, dim3(1), dim3(1024), 0, s, H->top_lu.p, H->top_piv.p, int(H->ntop), H->top_idx.p, u,
+                         wk, N, nv, op);
+    for (auto it = H->subs.rbegin(); it != H->subs.rend(); ++it) {
+      if (it->nrec == 0) continue;
+      SwArgs A{it->rec.p, it->iarena.p, it->darena.p, u, wk, N, nv, op};
+      hipLaunchKernelGGL(k_down, dim3(it->nrec), dim3(kBlock), 0, s, A);
+    }
+    HIF_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace hif

@@ -1,0 +1,114 @@
+"""C ABI checks that need no GPU: the library loads, exports every call the
+header declares, and rejects bad arguments on the host before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1307_2666_amd as hif
+from paper_1307_2666_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hif.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hif_[a-z_A-Z]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hif.load_library()
+    names = _declared()
+    assert "hif_factor" in names and "hif_solve_T" in names and "hif_matvec" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_opts_default():
+    o = hif.default_opts()
+    assert (o.precision, o.second_kind, o.symmetric, o.variant, o.n_proxy, o.proxy_radius, o.max_bytes) == \
+        (0, -1, -1, 0, 0, 0.0, 0)
+    assert hif.load_library().hif_opts_default(None) == B.HIF_EINVAL
+
+
+def _factor_raw(points=1, n=16, dim=2, kern=True, h=0.25, eps=1e-6, leaf=4, opts=None, out=True):
+    lib = hif.load_library()
+    k = B.hif_kernel(h, None, None)
+    handle = ctypes.c_void_p()
+    pts = ctypes.c_void_p(0x1000) if points else None  # never dereferenced: checks fail first
+    st = lib.hif_factor(pts, n, dim, ctypes.byref(k) if kern else None, None, None, None, eps, leaf,
+                        ctypes.byref(opts) if opts is not None else None, None,
+                        ctypes.byref(handle) if out else None)
+    return st, lib.hif_last_error().decode(), handle
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(points=0), "points"),
+    (dict(n=0), "n must"),
+    (dict(dim=4), "dim"),
+    (dict(kern=False), "kernel"),
+    (dict(h=0.0), "kernel.h"),
+    (dict(h=float("nan")), "kernel.h"),
+    (dict(eps=0.0), "eps"),
+    (dict(eps=1.0), "eps"),
+    (dict(eps=float("nan")), "eps"),
+    (dict(leaf=0), "leaf"),
+    (dict(out=False), "out"),
+])
+def test_factor_rejects_bad_arguments(kw, needle):
+    st, msg, handle = _factor_raw(**kw)
+    assert st == B.HIF_EINVAL
+    assert needle in msg
+    assert not handle.value
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("precision", 7, B.HIF_EINVAL),
+    ("second_kind", 2, B.HIF_EINVAL),
+    ("symmetric", -2, B.HIF_EINVAL),
+    ("variant", 5, B.HIF_EINVAL),
+    ("n_proxy", -1, B.HIF_EINVAL),
+    ("proxy_radius", 0.25, B.HIF_EINVAL),
+])
+def test_factor_rejects_bad_options(field, value, status):
+    o = hif.default_opts()
+    setattr(o, field, value)
+    st, msg, _ = _factor_raw(opts=o)
+    assert st == status and field.split("_")[0] in msg
+
+
+def test_sweeps_reject_null_handle():
+    lib = hif.load_library()
+    for name in ("hif_solve", "hif_solve_T", "hif_apply", "hif_apply_T"):
+        assert getattr(lib, name)(None, None, None, 1, None) == B.HIF_EINVAL
+    assert lib.hif_stats(None, None) == B.HIF_EINVAL
+    lib.hif_free(None)  # no-op
+
+
+def test_matvec_rejects_bad_arguments():
+    lib = hif.load_library()
+    k = B.hif_kernel(0.1, None, None)
+    p = ctypes.c_void_p(0x1000)
+    x = ctypes.c_void_p(0x2000)
+    y = ctypes.c_void_p(0x3000)
+    assert lib.hif_matvec(None, 4, 2, ctypes.byref(k), None, None, None, x, y, 1, None) == B.HIF_EINVAL
+    assert lib.hif_matvec(p, 4, 2, ctypes.byref(k), None, None, None, x, x, 1, None) == B.HIF_EINVAL
+    assert lib.hif_matvec(p, 4, 5, ctypes.byref(k), None, None, None, x, y, 1, None) == B.HIF_EINVAL
+    assert lib.hif_matvec(p, 4, 2, ctypes.byref(k), None, None, None, x, y, 0, None) == B.HIF_EINVAL
+    assert lib.hif_matvec(p, 4, 2, None, None, None, None, x, y, 1, None) == B.HIF_EINVAL
+
+
+def test_partition_and_id_reject_bad_arguments():
+    lib = hif.load_library()
+    p = ctypes.c_void_p(0x1000)
+    assert lib.hif_partition(p, 4, 2, p, 1, 2, p, None) == B.HIF_EINVAL  # faces need 3D
+    assert lib.hif_partition(p, 4, 2, p, 0, 0, p, None) == B.HIF_EINVAL
+    assert lib.hif_partition(None, 4, 2, p, 0, 2, p, None) == B.HIF_EINVAL
+    assert lib.hif_id_batched(p, p, p, p, p, -1, 4, p, p, p, None, None, None) == B.HIF_EINVAL
+    assert lib.hif_id_batched(p, p, p, p, p, 0, 4, p, p, p, None, None, None) == B.HIF_OK
+    assert lib.hif_id_batched(p, p, p, p, p, 2, 5000, p, p, p, None, None, None) == B.HIF_EINVAL
+    assert lib.hif_id_batched(p, p, p, p, p, 2, 4, p, p, p, p, None, None) == B.HIF_EINVAL

@@ -1,0 +1,248 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU FP64 oracle.
+
+* Exact operator: hif_matvec vs the oracle's dense / on-the-fly A x.
+* Integer work: hif_partition bit-exact vs the oracle's brute-force Voronoi
+  assignment.
+* ID: hif_id_batched vs the oracle's ID (same rank; same pivots when the
+  column norms are well separated; the reconstruction bound of Section 2.2).
+* Factorization: F_gpu against dense A and dense LU (|A - F| / |A| and the
+  solve error <= 10 eps), against the oracle's F (|F_gpu x - F_orc x| <= 10 eps
+  |F_orc x|), sweep identities (F^{-1} F = I, transposes) to rounding.
+Skeleton sets and ranks are not unique (floating-point ties in the pivoted
+QR), so factorizations are compared at the operator level.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1307_2666_amd as hif
+from oracle.estimators import gmres
+from oracle.factor import factorize
+from oracle.idqr import interp_decomp
+from oracle.kernels import Operator
+from oracle.tree import CELL, EDGE, FACE, assign
+from workloads import grid_points, workload
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(x):
+    return torch.tensor(np.ascontiguousarray(x), device=DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _op(n, d, a=1.0, nonsym=False, seed=0):
+    pts = grid_points(n, d)
+    N = pts.shape[0]
+    b = c = None
+    if nonsym:
+        rng = np.random.default_rng(seed)
+        b = 1.0 + 0.5 * rng.uniform(size=N)
+        c = 1.0 + 0.5 * rng.uniform(size=N)
+    return Operator.uniform(pts, 1.0 / n, a=np.full(N, a), b=b, c=c)
+
+
+def _gpu_factor(op, eps, leaf, **kw):
+    bb = None if np.all(op.b == 1.0) else _t(op.b)
+    cc = None if np.all(op.c == 1.0) else _t(op.c)
+    return hif.factor(_t(op.points), eps, leaf, a=_t(op.a), b=bb, c=cc, h=1.0 / round(op.N ** (1 / op.d)), **kw)
+
+
+def _dense_F(F, N, which="apply"):
+    I = torch.eye(N, dtype=torch.float64, device=DEV)
+    return _np(getattr(F, which)(I)).T
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,d,nrhs,nonsym", [(64, 2, 1, False), (33, 2, 3, True), (12, 3, 2, False),
+                                             (16, 3, 9, True)])
+def test_matvec_matches_dense(n, d, nrhs, nonsym):
+    op = _op(n, d, a=0.7, nonsym=nonsym, seed=n)
+    X = np.random.default_rng(1).standard_normal((nrhs, op.N))
+    want = X @ op.dense().T
+    got = _np(hif.matvec(_t(op.points), _t(X), a=_t(op.a), b=_t(op.b), c=_t(op.c), h=1.0 / n))
+    assert np.linalg.norm(got - want) <= 1e-13 * np.linalg.norm(want)
+
+
+def test_matvec_sq512_sampled_rows():
+    # Full 512 x 512 size, 8 right-hand sides; 200 rows checked one by one by the oracle.
+    wl = workload("sq512")
+    pts = wl.points()
+    N = wl.N
+    op = Operator.uniform(pts, wl.h, a=np.ones(N))
+    X = wl.rhs()
+    got = _np(hif.matvec(_t(pts), _t(X), a=torch.ones(N, dtype=torch.float64, device=DEV), h=wl.h))
+    rows = np.random.default_rng(5).choice(N, 200, replace=False)
+    want = op.matvec(X, rows=rows)
+    assert np.linalg.norm(got[:, rows] - want) <= 1e-13 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("n,d,kind,S", [(64, 2, EDGE, 8), (64, 2, EDGE, 2), (64, 2, CELL, 8), (32, 3, FACE, 8),
+                                        (32, 3, EDGE, 8), (32, 3, FACE, 2), (96, 2, EDGE, 16), (24, 3, EDGE, 4)])
+def test_partition_bit_exact(n, d, kind, S):
+    pts = grid_points(n, d)
+    rng = np.random.default_rng(n + S)
+    active = rng.uniform(size=pts.shape[0]) < 0.5
+    want = assign(pts, active, kind, S)
+    kid = {CELL: 0, FACE: 1, EDGE: 2}[kind]
+    got = _np(hif.partition(_t(pts), torch.tensor(active.astype(np.uint8)), kid, S))
+    assert np.all(got[~active] == -1)
+    assert np.array_equal(got[active], want)
+
+
+def _id_cases():
+    rng = np.random.default_rng(3)
+    cases = []
+    # well-separated column norms: pivots are unique
+    for m, n in [(448, 64), (120, 37), (30, 100), (700, 260)]:
+        Y = rng.standard_normal((m, n)) * (1.5 ** -np.arange(n))[rng.permutation(n)]
+        cases.append((Y, 1e-6, True))
+    # numerically low rank: smooth kernel block
+    x = np.linspace(0, 1, 300)
+    y = np.linspace(2, 3, 90)
+    cases.append((np.log(np.abs(x[:, None] - y[None, :])), 1e-9, False))
+    cases.append((np.zeros((20, 10)), 1e-6, True))
+    cases.append((rng.standard_normal((50, 8)) @ rng.standard_normal((8, 40)), 1e-12, False))
+    return cases
+
+
+def test_id_batched_matches_oracle():
+    cases = _id_cases()
+    out = hif.id_batched([torch.tensor(Y) for Y, _, _ in cases], [t for _, t, _ in cases])
+    for (Y, tol, unique), (sk, rd, T) in zip(cases, out):
+        sk, rd, T = sk.numpy(), rd.numpy(), T.numpy()
+        osk, ord_, oT = interp_decomp(Y, tol)
+        assert abs(sk.size - osk.size) <= 1, (Y.shape, sk.size, osk.size)
+        assert np.array_equal(np.sort(np.concatenate([sk, rd])), np.arange(Y.shape[1]))
+        assert np.all(np.diff(rd) > 0)
+        if unique:
+            assert np.array_equal(sk, osk)
+            if T.size:
+                assert np.allclose(T, oT, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(oT).max()))
+        r00 = np.max(np.linalg.norm(Y, axis=0))
+        if rd.size:
+            err = np.linalg.norm(Y[:, rd] - Y[:, sk] @ T)
+            assert err <= np.sqrt(rd.size) * tol * r00 * 1.01 + 1e-14 * r00
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("eps", [1e-3, 1e-6, 1e-9])
+def test_factor_small_2d_vs_dense(eps):
+    op = _op(32, 2)
+    F = _gpu_factor(op, eps, 16)
+    A = op.dense()
+    Fd = _dense_F(F, op.N)
+    assert np.linalg.norm(A - Fd, 2) <= 10 * eps * np.linalg.norm(A, 2)
+    Fi = _dense_F(F, op.N, "solve")
+    assert np.linalg.norm(Fi @ Fd - np.eye(op.N)) <= 1e-11
+    st = F.stats()
+    assert st["levels"] == 3 and st["n_sublevels"] == 6 and st["top_size"] > 0
+
+
+def test_factor_sweep_transposes():
+    op = _op(32, 2, nonsym=True)
+    F = _gpu_factor(op, 1e-6, 16)
+    Fd = _dense_F(F, op.N)
+    FT = _dense_F(F, op.N, "apply_T")
+    Fi = _dense_F(F, op.N, "solve")
+    FiT = _dense_F(F, op.N, "solve_T")
+    assert np.abs(FT - Fd.T).max() <= 1e-13 * np.abs(Fd).max()
+    assert np.abs(FiT - Fi.T).max() <= 1e-12 * np.abs(Fi).max()
+    A = op.dense()
+    assert np.linalg.norm(A - Fd, 2) <= 1e-5 * np.linalg.norm(A, 2)
+
+
+def test_factor_rsf_and_first_kind():
+    op = _op(32, 2)
+    F = _gpu_factor(op, 1e-6, 16, variant="rskel")
+    A = op.dense()
+    assert np.linalg.norm(A - _dense_F(F, op.N), 2) <= 1e-5 * np.linalg.norm(A, 2)
+    assert F.stats()["n_sublevels"] == 3
+    op0 = _op(32, 2, a=0.0)
+    F0 = _gpu_factor(op0, 1e-6, 16, second_kind=0)
+    A0 = op0.dense()
+    assert np.linalg.norm(A0 - _dense_F(F0, op0.N), 2) <= 1e-5 * np.linalg.norm(A0, 2)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_factor_3d_vs_dense(eps):
+    op = _op(12, 3)
+    F = _gpu_factor(op, eps, 27)
+    A = op.dense()
+    assert np.linalg.norm(A - _dense_F(F, op.N), 2) <= 10 * eps * np.linalg.norm(A, 2)
+    assert F.stats()["sub_kind"] == [0, 1, 2, 0, 1, 2]
+
+
+def test_factor_sq64_solve_and_apply_vs_oracle():
+    # The 64 x 64 workload (N = 4096, leaf 64, eps 1e-6).
+    wl = workload("sq64")
+    op = Operator.uniform(wl.points(), wl.h, a=np.ones(wl.N))
+    f = wl.rhs()[0]
+    F = hif.factor(_t(op.points), wl.eps, wl.leaf, a=_t(op.a), h=wl.h)
+    A = op.dense()
+    u_ref = np.linalg.solve(A, f)
+    u = _np(F.solve(_t(f)))
+    assert np.linalg.norm(u - u_ref) <= 10 * wl.eps * np.linalg.norm(u_ref)
+    x = np.random.default_rng(9).standard_normal(wl.N)
+    y = _np(F.apply(_t(x)))
+    assert np.linalg.norm(y - A @ x) <= 10 * wl.eps * np.linalg.norm(A @ x)
+    Fo = factorize(op, wl.eps, wl.leaf)
+    yo = Fo.apply(x)
+    assert np.linalg.norm(y - yo) <= 10 * wl.eps * np.linalg.norm(yo)
+    assert np.linalg.norm(u - Fo.solve(f)) <= 10 * wl.eps * np.linalg.norm(u_ref)
+    st = F.stats()
+    assert st["levels"] == 3 and st["sub_groups"][:2] == [64, 112]
+    # ranks within a few percent of the oracle's (ties in pivoting make them non-unique)
+    skel_o = [int(np.sum(s.ranks)) for s in Fo.stats]
+    assert all(abs(a - b) <= 0.05 * b + 2 for a, b in zip(st["sub_skel"], skel_o))
+
+
+def test_factor_deterministic():
+    op = _op(32, 2)
+    x = _t(np.random.default_rng(2).standard_normal(op.N))
+    y1 = _np(_gpu_factor(op, 1e-6, 16).solve(x))
+    y2 = _np(_gpu_factor(op, 1e-6, 16).solve(x))
+    assert np.array_equal(y1, y2)
+
+
+def test_factor_errors():
+    # coincident points
+    pts = np.vstack([grid_points(8, 2), grid_points(8, 2)[:1]])
+    with pytest.raises(hif.HifError) as e:
+        hif.factor(_t(pts), 1e-6, 64, h=0.125)
+    assert e.value.status == -1
+    # point outside the unit box
+    pts = grid_points(8, 2).copy()
+    pts[3, 0] = 1.5
+    with pytest.raises(hif.HifError) as e:
+        hif.factor(_t(pts), 1e-6, 64, h=0.125)
+    assert e.value.status == -1
+    # singular 2 x 2 system: a_1 = b_1 = 0 makes the second row of A exactly zero
+    pts = np.array([[0.25, 0.5], [0.75, 0.5]])
+    with pytest.raises(hif.HifError) as e:
+        hif.factor(_t(pts), 1e-6, 64, a=_t([1.0, 0.0]), b=_t([1.0, 0.0]), h=0.5)
+    assert e.value.status == -3
+    # memory cap
+    op = _op(32, 2)
+    with pytest.raises(hif.HifError) as e:
+        _gpu_factor(op, 1e-6, 16, max_bytes=1 << 16)
+    assert e.value.status == -2
+
+
+def test_gmres_with_gpu_preconditioner():
+    # Right-preconditioned GMRES with F_gpu^{-1} against the exact on-the-fly
+    # matvec reaches 1e-10 in a few iterations (Lemma 5.1), plain hifie2 (x off).
+    op = _op(64, 2)
+    F = _gpu_factor(op, 1e-3, 64, second_kind=0)
+    P = _t(op.points)
+    a = _t(op.a)
+    f = np.random.default_rng(4).standard_normal(op.N)
+    A_mv = lambda v: _np(hif.matvec(P, _t(v), a=a, h=1.0 / 64))
+    M = lambda v: _np(F.solve(_t(v)))
+    u, it, hist = gmres(A_mv, f, M=M, tol=1e-10, maxit=30)
+    assert hist[-1] <= 1e-10 and it <= 10
+    assert np.linalg.norm(op.dense() @ u - f) <= 1e-9 * np.linalg.norm(f)
