@@ -149,6 +149,7 @@ def main():
         "solve_unknowns_per_s": N * nrhs / t_solve,
         "factor_ms": float(np.mean([s["t_factor_ms"] for s in stats])),
         "phase_ms": ph,
+        "sub_ms": [{k: round(v, 3) for k, v in d.items() if v > 0} for d in st["sub_t_ms"]],
         "top_size": st["top_size"],
         "factor_bytes": st["factor_bytes"],
         "roofline": {"kernel": "k_id (batched column-pivoted QR ID)", "bound": "alu",

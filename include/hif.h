@@ -109,8 +109,9 @@ typedef struct {
   int64_t top_size;               /* |s_L| */
   int64_t factor_bytes;           /* m_f: bytes of stored factors */
   double t_factor_ms;             /* wall time of hif_factor */
-  double t_phase_ms[8];           /* partition+near field, assembly, ID, elimination,
-                                     SCI update, top LU, host sync/alloc, other */
+  double t_phase_ms[8];           /* partition+near field, assembly, ID (pivoted QR),
+                                     elimination, SCI update, top LU, host sync/alloc,
+                                     row compression before the ID */
   int32_t sub_kind[HIF_MAX_SUBLEVELS];     /* 0 cell, 1 face, 2 edge */
   int32_t sub_groups[HIF_MAX_SUBLEVELS];   /* nonempty groups */
   int64_t sub_active[HIF_MAX_SUBLEVELS];   /* active DOFs entering the sub-level */
@@ -119,6 +120,7 @@ typedef struct {
   int64_t sub_classes[HIF_MAX_SUBLEVELS];  /* ID problems solved (split classes) */
   double sub_id_flops[HIF_MAX_SUBLEVELS];  /* algorithmic flops of the IDs */
   double sub_elim_flops[HIF_MAX_SUBLEVELS];/* algorithmic flops of the eliminations */
+  double sub_t_ms[HIF_MAX_SUBLEVELS][8];   /* per sub-level split of t_phase_ms */
 } hif_stats_t;
 
 /* Fill *opts with the defaults listed above.  Returns HIF_EINVAL if opts is NULL. */

@@ -19,7 +19,7 @@ HIF_OK, HIF_EINVAL, HIF_ENOMEM, HIF_ESINGULAR, HIF_EDEVICE, HIF_EUNSUPPORTED = 0
 HIF_FP64, HIF_FP32_MIXED = 0, 1
 HIF_VARIANT_HIFIE, HIF_VARIANT_RSF = 0, 1
 MAX_SUB = 64
-PHASES = ("partition", "assembly", "id", "elimination", "sci", "top", "host", "other")
+PHASES = ("partition", "assembly", "id", "elimination", "sci", "top", "host", "rowqr")
 _STATUS = {0: "HIF_OK", -1: "HIF_EINVAL", -2: "HIF_ENOMEM", -3: "HIF_ESINGULAR", -4: "HIF_EDEVICE",
            -5: "HIF_EUNSUPPORTED"}
 
@@ -47,7 +47,8 @@ class hif_stats_t(ctypes.Structure):
                 ("sub_kind", ctypes.c_int32 * MAX_SUB), ("sub_groups", ctypes.c_int32 * MAX_SUB),
                 ("sub_active", ctypes.c_int64 * MAX_SUB), ("sub_skel", ctypes.c_int64 * MAX_SUB),
                 ("sub_near", ctypes.c_int64 * MAX_SUB), ("sub_classes", ctypes.c_int64 * MAX_SUB),
-                ("sub_id_flops", ctypes.c_double * MAX_SUB), ("sub_elim_flops", ctypes.c_double * MAX_SUB)]
+                ("sub_id_flops", ctypes.c_double * MAX_SUB), ("sub_elim_flops", ctypes.c_double * MAX_SUB),
+                ("sub_t_ms", (ctypes.c_double * 8) * MAX_SUB)]
 
 
 _lib = None
@@ -172,6 +173,7 @@ class Factorization:
             "sub_active": list(s.sub_active[:ns]), "sub_skel": list(s.sub_skel[:ns]),
             "sub_near": list(s.sub_near[:ns]), "sub_classes": list(s.sub_classes[:ns]),
             "sub_id_flops": list(s.sub_id_flops[:ns]), "sub_elim_flops": list(s.sub_elim_flops[:ns]),
+            "sub_t_ms": [dict(zip(PHASES, list(s.sub_t_ms[i]))) for i in range(ns)],
         }
 
     def free(self):

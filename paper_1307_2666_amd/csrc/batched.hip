@@ -1,0 +1,468 @@
+// Per-panel batched kernels for the coarse sub-levels, where a few large
+// problems would leave most compute units idle if each ran in one workgroup:
+// the row compression before the ID (blocked Householder QR) and the partial
+// LU of the elimination (and of the top block) are split into a panel kernel
+// (one workgroup per problem) and a trailing-update kernel (one workgroup per
+// 64-column tile per problem) launched once per panel of 16 columns.  The
+// updates run on the matrix cores (v_mfma_f64_16x16x4f64) with operands read
+// straight from device memory in the instruction's lane layout.
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "batched.h"
+#include "gemm.h"
+
+namespace hif {
+
+namespace {
+
+constexpr int kNb = 16;     // panel width
+constexpr int kTileN = 64;  // columns per update workgroup
+
+struct AM {
+  double v;
+  int i;
+};
+__device__ __forceinline__ AM am_better(AM a, AM b) {
+  if (b.v > a.v || (b.v == a.v && b.i < a.i)) return b;
+  return a;
+}
+__device__ AM block_argmax256(AM x) {
+  __shared__ double sv[4];
+  __shared__ int si[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    AM y{__shfl_xor(x.v, o, 64), __shfl_xor(x.i, o, 64)};
+    x = am_better(x, y);
+  }
+  if (lane == 0) { sv[wv] = x.v; si[wv] = x.i; }
+  __syncthreads();
+  AM r{-1.0, INT_MAX};
+  for (int k = 0; k < 4; ++k) r = am_better(r, AM{sv[k], si[k]});
+  __syncthreads();
+  return r;
+}
+
+constexpr int kQrThreads = 1024;            // trailing-update workgroup
+constexpr int kQrWaves = kQrThreads / 64;
+constexpr int kQpThreads = 512;             // panel workgroup (register budget of 256 VGPRs)
+constexpr int kQpWaves = kQpThreads / 64;
+
+__device__ __forceinline__ double bsumQ(double v, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kQpWaves; ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Row compression, panel j0 of every problem: Householder vectors of columns
+// j0..j0+jb-1 (rows j0..m-1) into V (m x 16, zero above the diagonal), R's
+// diagonal into the block, and T of the compact WY form I - V T V^T into Tq.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kQpThreads) void k_qr_panel(QrBatch A, int j0) {
+  const int q = blockIdx.x;
+  const int m = A.rows[q], n = A.cols[q];
+  if (m <= n || j0 >= n) return;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  double* V = A.scratch + A.soff[q];
+  double* Tq = V + int64_t(m) * kNb;
+  const int jb = min(kNb, n - j0);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ double red[kQpWaves];
+  __shared__ double sred[kQpWaves][kNb + 1];
+  __shared__ double sbeta[kNb];
+  __shared__ double sG[kQpWaves][kNb * kNb];
+  for (int r = j0 + tid; r < m; r += kQpThreads)
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) V[int64_t(r - j0) * kNb + c] = 0.0;
+  double s0 = 0.0;
+  for (int r = j0 + tid; r < m; r += kQpThreads) {
+    const double y = M[int64_t(r) * ld + j0];
+    s0 += y * y;
+  }
+  double ss = bsumQ(s0, red);
+  for (int jj = 0; jj < jb; ++jj) {
+    const int j = j0 + jj;
+    const int nc = jb - jj - 1;
+    const double x0 = M[int64_t(j) * ld + j];
+    const double nrm = sqrt(ss);
+    const double alpha = nrm > 0.0 ? -copysign(nrm, x0) : 0.0;
+    const double v0 = x0 - alpha;
+    const double vtv = ss - x0 * x0 + v0 * v0;
+    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    double part[kNb];
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) part[c] = 0.0;
+    for (int r0 = j + tid; r0 < m; r0 += 4 * kQpThreads) {
+      double vr[4], y[4][kNb];
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int r = r0 + qq * kQpThreads;
+        vr[qq] = 0.0;
+        if (r < m) vr[qq] = r == j ? v0 : M[int64_t(r) * ld + j];
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) y[qq][c] = (r < m && c < nc) ? M[int64_t(r) * ld + j + 1 + c] : 0.0;
+      }
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int r = r0 + qq * kQpThreads;
+        if (r < m) V[int64_t(r - j0) * kNb + jj] = vr[qq];
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) part[c] += vr[qq] * y[qq][c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) {
+      if (c >= nc) break;
+      const double t = wave_sum(part[c]);
+      if (lane == 0) sred[wv][c] = t;
+    }
+    __syncthreads();
+    double wc[kNb];
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kQpWaves; ++w) t += sred[w][c];
+      wc[c] = c < nc ? beta * t : 0.0;
+    }
+    __syncthreads();
+    double snext = 0.0;
+    for (int r0 = j + tid; r0 < m; r0 += 4 * kQpThreads) {
+      double vr[4], y[4][kNb];
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int r = r0 + qq * kQpThreads;
+        vr[qq] = 0.0;
+        if (r < m) vr[qq] = r == j ? v0 : M[int64_t(r) * ld + j];
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) y[qq][c] = (r < m && c < nc) ? M[int64_t(r) * ld + j + 1 + c] : 0.0;
+      }
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int r = r0 + qq * kQpThreads;
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) y[qq][c] -= wc[c] * vr[qq];
+        if (r > j && r < m && nc > 0) snext += y[qq][0] * y[qq][0];
+        if (r < m) {
+#pragma unroll
+          for (int c = 0; c < kNb; ++c)
+            if (c < nc) M[int64_t(r) * ld + j + 1 + c] = y[qq][c];
+        }
+      }
+    }
+    if (tid == 0) sbeta[jj] = beta;
+    ss = bsumQ(snext, red);
+    if (tid == 0) M[int64_t(j) * ld + j] = alpha;
+  }
+  // G = V^T V on the matrix cores: every wave sums its own 4-row slices.
+  {
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    const int mp = m - j0;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int kb = wv * 4; kb < mp; kb += 4 * kQpWaves) {
+      const int r = kb + lk;
+      const double a = r < mp ? V[int64_t(r) * kNb + li] : 0.0;
+      acc = mfma_f64(a, a, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sG[wv][(4 * v + lk) * kNb + li] = acc[v];
+  }
+  __syncthreads();
+  __shared__ double T[kNb][kNb];
+  for (int e = tid; e < kNb * kNb; e += kQpThreads) T[e / kNb][e % kNb] = 0.0;
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 0; i < jb; ++i) {
+      T[i][i] = sbeta[i];
+      for (int p = 0; p < i; ++p) {
+        double t = 0.0;
+        for (int l = p; l < i; ++l) {
+          const int e = l * kNb + i;
+          double gsum = 0.0;
+          for (int w = 0; w < kQpWaves; ++w) gsum += sG[w][e];
+          t += T[p][l] * gsum;
+        }
+        T[p][i] = -sbeta[i] * t;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < kNb * kNb; e += kQpThreads) Tq[e] = T[e / kNb][e % kNb];
+}
+
+// Trailing update of one 64-column tile: W = T^T V^T Y_t (split over the
+// waves along the rows), then Y_t -= V W.
+__global__ __launch_bounds__(kQrThreads) void k_qr_update(QrBatch A, int j0) {
+  const int q = blockIdx.y;
+  const int m = A.rows[q], n = A.cols[q];
+  if (m <= n || j0 >= n) return;
+  const int jb = min(kNb, n - j0);
+  const int c0 = j0 + jb + blockIdx.x * kTileN;
+  if (c0 >= n) return;
+  const int nt = min(kTileN, n - c0);
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const double* V = A.scratch + A.soff[q];
+  const double* Tq = V + int64_t(m) * kNb;
+  const int mp = m - j0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  __shared__ double sW[kQrWaves][kNb][kTileN + 1];
+  __shared__ double sW2[kNb][kTileN + 1];
+  // 1. partial W per wave over rows kb = 4*wv, 4*wv + 16, ...
+  double4_t acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = double4_t{0.0, 0.0, 0.0, 0.0};
+  for (int kb = wv * 4; kb < mp; kb += 4 * kQrWaves) {
+    const int r = kb + lk;
+    const bool ok = r < mp;
+    const double a = ok ? V[int64_t(r) * kNb + li] : 0.0;
+    const double* yr = M + int64_t(j0 + (ok ? r : 0)) * ld + c0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int col = t * 16 + li;
+      const double b = (ok && col < nt) ? yr[col] : 0.0;
+      acc[t] = mfma_f64(a, b, acc[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sW[wv][4 * v + lk][t * 16 + li] = acc[t][v];
+  __syncthreads();
+  // 2. W = T^T (sum of the partials), T upper triangular.
+  for (int e = tid; e < kNb * kTileN; e += kQrThreads) {
+    const int i = e / kTileN, c = e % kTileN;
+    double s = 0.0;
+    for (int p = 0; p <= i; ++p) {
+      double w = 0.0;
+#pragma unroll
+      for (int q2 = 0; q2 < kQrWaves; ++q2) w += sW[q2][p][c];
+      s += Tq[p * kNb + i] * w;
+    }
+    sW2[i][c] = s;
+  }
+  __syncthreads();
+  // 3. Y_t -= V W, 16-row tiles spread over the waves.
+  for (int rt = wv * 16; rt < mp; rt += 16 * kQrWaves) {
+    double4_t d[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) d[t] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < kNb; ks += 4) {
+      const int r = rt + li;
+      const double a = r < mp ? V[int64_t(r) * kNb + ks + lk] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) d[t] = mfma_f64(a, sW2[ks + lk][t * 16 + li], d[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rt + 4 * v + lk, col = t * 16 + li;
+        if (r < mp && col < nt) M[int64_t(j0 + r) * ld + c0 + col] -= d[t][v];
+      }
+  }
+}
+
+__global__ void k_qr_clear_lower(QrBatch A) {
+  const int q = blockIdx.y;
+  const int m = A.rows[q], n = A.cols[q];
+  if (m <= n) return;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < int64_t(n) * n;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int r = int(e / n), c = int(e % n);
+    if (c < r) M[int64_t(r) * ld + c] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Partial LU (Lemma 2.1) of the n x n problems over their first r columns,
+// pivoting among rows < r: panel j0 = columns j0..j0+jb-1 with row swaps over
+// whole rows, then U12 = L11^{-1} A12 for the panel rows.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_lu_panel(LuBatch A, int j0) {
+  const int q = blockIdx.x;
+  const int n = A.n[q], r = A.r[q];
+  if (j0 >= r) return;
+  double* M = A.base + A.moff[q];
+  int32_t* piv = A.piv + A.poff[q];
+  const int jb = min(kNb, r - j0);
+  const int tid = threadIdx.x;
+  for (int j = j0; j < j0 + jb; ++j) {
+    AM loc{-1.0, INT_MAX};
+    for (int i = j + tid; i < r; i += 256) loc = am_better(loc, AM{fabs(M[int64_t(i) * n + j]), i});
+    const AM best = block_argmax256(loc);
+    if (!(best.v > 0.0)) {
+      if (tid == 0) atomicOr(A.status, 1);
+      return;
+    }
+    const int p = best.i;
+    if (tid == 0) piv[j] = p;
+    if (p != j)
+      for (int col = tid; col < n; col += 256) {
+        const double t = M[int64_t(j) * n + col];
+        M[int64_t(j) * n + col] = M[int64_t(p) * n + col];
+        M[int64_t(p) * n + col] = t;
+      }
+    __syncthreads();
+    const double inv = 1.0 / M[int64_t(j) * n + j];
+    const int w = j0 + jb - j - 1;
+    double prow[kNb];
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) prow[c] = c < w ? M[int64_t(j) * n + j + 1 + c] : 0.0;
+    for (int i0 = j + 1 + tid; i0 < n; i0 += 4 * 256) {
+      double y[4][kNb + 1];
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int i = i0 + qq * 256;
+#pragma unroll
+        for (int c = 0; c <= kNb; ++c) y[qq][c] = (i < n && c <= w) ? M[int64_t(i) * n + j + c] : 0.0;
+      }
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int i = i0 + qq * 256;
+        if (i >= n) continue;
+        const double l = y[qq][0] * inv;
+        M[int64_t(i) * n + j] = l;
+#pragma unroll
+        for (int c = 0; c < kNb; ++c)
+          if (c < w) M[int64_t(i) * n + j + 1 + c] = y[qq][c + 1] - l * prow[c];
+      }
+    }
+    __syncthreads();
+  }
+  // U12 = L11^{-1} A12 (rows j0..j0+jb-1, columns j0+jb..n-1)
+  for (int c = j0 + jb + tid; c < n; c += 256) {
+    double x[kNb];
+#pragma unroll
+    for (int i = 0; i < kNb; ++i) x[i] = i < jb ? M[int64_t(j0 + i) * n + c] : 0.0;
+#pragma unroll
+    for (int i = 1; i < kNb; ++i) {
+      if (i >= jb) break;
+      double v = x[i];
+#pragma unroll
+      for (int p = 0; p < kNb; ++p)
+        if (p < i) v -= M[int64_t(j0 + i) * n + j0 + p] * x[p];
+      x[i] = v;
+    }
+#pragma unroll
+    for (int i = 1; i < kNb; ++i)
+      if (i < jb) M[int64_t(j0 + i) * n + c] = x[i];
+  }
+}
+
+// Trailing update A22 -= L21 U12 of one 64 x 64 tile (K = panel width).
+__global__ __launch_bounds__(256) void k_lu_update(LuBatch A, int j0) {
+  const int q = blockIdx.z;
+  const int n = A.n[q], r = A.r[q];
+  if (j0 >= r) return;
+  const int jb = min(kNb, r - j0);
+  const int s0 = j0 + jb;
+  const int rt0 = s0 + blockIdx.y * 64, ct0 = s0 + blockIdx.x * 64;
+  if (rt0 >= n || ct0 >= n) return;
+  double* M = A.base + A.moff[q];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = wv >> 1, wc = wv & 1;
+  double4_t d[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) d[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < kNb; ks += 4) {
+    const int k = ks + lk;
+    double af[2], bf[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int i = rt0 + wr * 32 + a * 16 + li;
+      af[a] = (i < n && k < jb) ? M[int64_t(i) * n + j0 + k] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int c = ct0 + wc * 32 + b * 16 + li;
+      bf[b] = (c < n && k < jb) ? M[int64_t(j0 + k) * n + c] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) d[a][b] = mfma_f64(af[a], bf[b], d[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = rt0 + wr * 32 + a * 16 + 4 * v + lk;
+        const int c = ct0 + wc * 32 + b * 16 + li;
+        if (i < n && c < n) M[int64_t(i) * n + c] -= d[a][b][v];
+      }
+}
+
+// Batched general GEMM, one 64 x 64 tile of C per workgroup:
+// C = beta C + alpha op(A) op(B) for every entry of a problem table.
+__global__ __launch_bounds__(256) void k_gemm_tiles(const GemmDesc* D, int nd) {
+  const int q = blockIdx.z;
+  if (q >= nd) return;
+  const GemmDesc g = D[q];
+  const int tm = blockIdx.y * kGemmTile, tn = blockIdx.x * kGemmTile;
+  if (tm >= g.M || tn >= g.N) return;
+  __shared__ double lds[kGemmLds];
+  const int Mt = min(kGemmTile, g.M - tm), Nt = min(kGemmTile, g.N - tn);
+  const double* Ap = g.ta ? g.A + tm : g.A + int64_t(tm) * g.lda;
+  const double* Bp = g.tb ? g.B + int64_t(tn) * g.ldb : g.B + tn;
+  wg_gemm(Mt, Nt, g.K, g.alpha, Ap, g.lda, g.ta, Bp, g.ldb, g.tb, g.beta, g.C + int64_t(tm) * g.ldc + tn, g.ldc,
+          lds);
+}
+
+}  // namespace
+
+void launch_qr_batched(const QrBatch& A, int max_cols, hipStream_t s) {
+  if (A.nprob == 0) return;
+  for (int j0 = 0; j0 < max_cols; j0 += kNb) {
+    hipLaunchKernelGGL(k_qr_panel, dim3(A.nprob), dim3(kQpThreads), 0, s, A, j0);
+    const int rem = max_cols - j0 - kNb;
+    if (rem > 0) {
+      const unsigned tiles = unsigned((rem + kTileN - 1) / kTileN);
+      hipLaunchKernelGGL(k_qr_update, dim3(tiles, A.nprob), dim3(kQrThreads), 0, s, A, j0);
+    }
+  }
+  hipLaunchKernelGGL(k_qr_clear_lower, dim3(64, A.nprob), dim3(256), 0, s, A);
+  HIF_HIP(hipGetLastError());
+}
+
+void launch_lu_batched(const LuBatch& A, int max_r, int max_n, hipStream_t s) {
+  if (A.nprob == 0) return;
+  for (int j0 = 0; j0 < max_r; j0 += kNb) {
+    hipLaunchKernelGGL(k_lu_panel, dim3(A.nprob), dim3(256), 0, s, A, j0);
+    const int rem = max_n - j0 - 1;
+    if (rem > 0) {
+      const unsigned tiles = unsigned((rem + 63) / 64);
+      hipLaunchKernelGGL(k_lu_update, dim3(tiles, tiles, A.nprob), dim3(256), 0, s, A, j0);
+    }
+  }
+  HIF_HIP(hipGetLastError());
+}
+
+void launch_gemm_tiles(const GemmDesc* D, int nd, int max_m, int max_n, hipStream_t s) {
+  if (nd == 0 || max_m <= 0 || max_n <= 0) return;
+  const unsigned tx = unsigned((max_n + kGemmTile - 1) / kGemmTile), ty = unsigned((max_m + kGemmTile - 1) / kGemmTile);
+  hipLaunchKernelGGL(k_gemm_tiles, dim3(tx, ty, nd), dim3(256), 0, s, D, nd);
+  HIF_HIP(hipGetLastError());
+}
+
+}  // namespace hif

@@ -4,8 +4,12 @@
 //
 // All kernels run one workgroup per independent problem (the groups of one
 // sub-level commute, Section 2.3), on row-major blocks in device memory.
+#include <algorithm>
 #include <climits>
+#include <vector>
 
+#include "batched.h"
+#include "gemm.h"
 #include "kernels.h"
 
 namespace hif {
@@ -211,8 +215,11 @@ void launch_assemble(const AsmArgs& A, int block, hipStream_t s) {
 // Trailing column norms are recomputed after every reflection.  On exit the
 // block holds T in rows 0..k-1 of the redundant columns.
 // ---------------------------------------------------------------------------
+constexpr int kIdMaxRows = 4096;  // rows of the block the pivoted QR runs on (after row compression)
+constexpr int kChunk = 8;
+
 template <int U>
-__global__ void k_id(IdArgs A) {
+__global__ __launch_bounds__(1024) void k_id(IdArgs A) {
   const int q = blockIdx.x;
   double* M = A.base + A.moff[q];
   const int ld = A.ld[q], m = A.rows[q], n = A.cols[q];
@@ -221,6 +228,7 @@ __global__ void k_id(IdArgs A) {
   const int tid = threadIdx.x, B = blockDim.x;
   __shared__ double s_alpha, s_v0, s_beta;
   __shared__ int s_p, s_k;
+  __shared__ double sv[kIdMaxRows];  // Householder vector of the current step (rows i..m-1)
 
   double nrm[U];
   int state[U];  // -2 absent, -1 trailing, >= 0 pivot step
@@ -229,11 +237,20 @@ __global__ void k_id(IdArgs A) {
     const int col = tid + u * B;
     state[u] = col < n ? -1 : -2;
     double s = 0.0;
-    if (col < n)
-      for (int r = 0; r < m; ++r) {
-        double y = M[int64_t(r) * ld + col];
+    if (col < n) {
+      int r = 0;
+      for (; r + kChunk <= m; r += kChunk) {
+        double y[kChunk];
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) y[c] = M[int64_t(r + c) * ld + col];
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) s += y[c] * y[c];
+      }
+      for (; r < m; ++r) {
+        const double y = M[int64_t(r) * ld + col];
         s += y * y;
       }
+    }
     nrm[u] = s;
   }
   const int kmax = m < n ? m : n;
@@ -252,6 +269,8 @@ __global__ void k_id(IdArgs A) {
       break;
     }
     const int p = best.i;
+    // stage the pivot column below row i
+    for (int r = i + 1 + tid; r < m; r += B) sv[r] = M[int64_t(r) * ld + p];
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (tid + u * B == p) {
@@ -272,15 +291,41 @@ __global__ void k_id(IdArgs A) {
     for (int u = 0; u < U; ++u) {
       if (state[u] != -1) continue;
       const int col = tid + u * B;
-      double w = v0 * M[int64_t(i) * ld + col];
-      for (int r = i + 1; r < m; ++r) w += M[int64_t(r) * ld + p] * M[int64_t(r) * ld + col];
+      double* Mc = M + col;
+      double w = v0 * Mc[int64_t(i) * ld];
+      {
+        int r = i + 1;
+        for (; r + kChunk <= m; r += kChunk) {
+          double y[kChunk];
+#pragma unroll
+          for (int c = 0; c < kChunk; ++c) y[c] = Mc[int64_t(r + c) * ld];
+#pragma unroll
+          for (int c = 0; c < kChunk; ++c) w += sv[r + c] * y[c];
+        }
+        for (; r < m; ++r) w += sv[r] * Mc[int64_t(r) * ld];
+      }
       w *= beta;
-      M[int64_t(i) * ld + col] -= w * v0;
+      Mc[int64_t(i) * ld] -= w * v0;
       double s = 0.0;
-      for (int r = i + 1; r < m; ++r) {
-        double y = M[int64_t(r) * ld + col] - w * M[int64_t(r) * ld + p];
-        M[int64_t(r) * ld + col] = y;
-        s += y * y;
+      {
+        int r = i + 1;
+        for (; r + kChunk <= m; r += kChunk) {
+          double y[kChunk];
+#pragma unroll
+          for (int c = 0; c < kChunk; ++c) y[c] = Mc[int64_t(r + c) * ld];
+#pragma unroll
+          for (int c = 0; c < kChunk; ++c) {
+            y[c] -= w * sv[r + c];
+            s += y[c] * y[c];
+          }
+#pragma unroll
+          for (int c = 0; c < kChunk; ++c) Mc[int64_t(r + c) * ld] = y[c];
+        }
+        for (; r < m; ++r) {
+          const double y = Mc[int64_t(r) * ld] - w * sv[r];
+          Mc[int64_t(r) * ld] = y;
+          s += y * y;
+        }
       }
       nrm[u] = s;
     }
@@ -327,8 +372,10 @@ __global__ void k_id(IdArgs A) {
 
 void launch_id(const IdArgs& A, int max_cols, hipStream_t s) {
   if (A.nprob == 0) return;
+  // the pivoted QR runs on min(m, n) <= max_cols rows, staged in LDS
+  if (max_cols > kIdMaxRows) throw Error{HIF_EUNSUPPORTED, "ID problem with more than 4096 columns"};
   int block = 64;
-  while (block < max_cols && block < 256) block *= 2;
+  while (block < max_cols && block < 1024) block *= 2;
   int U = (max_cols + block - 1) / block;
   if (U <= 1)
     hipLaunchKernelGGL(k_id<1>, dim3(A.nprob), dim3(block), 0, s, A);
@@ -341,7 +388,180 @@ void launch_id(const IdArgs& A, int max_cols, hipStream_t s) {
   else if (U <= 16)
     hipLaunchKernelGGL(k_id<16>, dim3(A.nprob), dim3(block), 0, s, A);
   else
-    throw Error{HIF_EUNSUPPORTED, "ID problem with more than 4096 columns"};
+    throw Error{HIF_EUNSUPPORTED, "ID problem with more than 16384 columns"};
+  HIF_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Row compression before the ID.  By Lemma 3.1 an ID of any matrix with the
+// same row space is an ID of Y; with Y = Q R0 (Householder, no pivoting) the
+// n x n upper-triangular R0 has exactly the column norms and pivot sequence of
+// Y, so the pivoted QR then runs on R0 instead of the tall m x n block.
+// Blocked right-looking Householder QR: panels of kRqNb columns factored in
+// place, H = I - V T V^T (compact WY), trailing update W = T^T V^T Y_t,
+// Y_t -= V W on the matrix cores.  Scratch per problem: V (m x kRqNb),
+// W (kRqNb x n), G (kRqNb x kRqNb).
+// ---------------------------------------------------------------------------
+constexpr int kRqNb = 16;
+
+__global__ __launch_bounds__(256) void k_rowqr(RowQrArgs A) {
+  const int q = blockIdx.x;
+  const int m = A.rows[q], n = A.cols[q];
+  if (m <= n) return;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  double* V = A.scratch + A.soff[q];
+  double* W = V + int64_t(m) * kRqNb;
+  double* Gm = W + int64_t(kRqNb) * n;
+  __shared__ double lds[kGemmLds];
+  __shared__ double sT[kRqNb][kRqNb];
+  __shared__ double sbeta[kRqNb];
+  __shared__ double sred[4][kRqNb + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int j0 = 0; j0 < n; j0 += kRqNb) {
+    const int jb = min(kRqNb, n - j0);
+    // --- panel factorization (rows j0..m-1, columns j0..j0+jb-1) ---
+    // Two passes over the rows per column: dot products (writing V), then the
+    // update, which also accumulates the next column's norm.  Rows go in
+    // chunks of 4 per thread so that many loads are in flight.
+    double ss = 0.0;
+    {
+      double s0 = 0.0;
+      for (int r = j0 + tid; r < m; r += 256) {
+        const double y = M[int64_t(r) * ld + j0];
+        s0 += y * y;
+      }
+      s0 = wave_sum(s0);
+      if (lane == 0) sred[wv][0] = s0;
+      __syncthreads();
+      ss = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
+      __syncthreads();
+    }
+    for (int r = j0 + tid; r < m; r += 256)
+      for (int c = 0; c < kRqNb; ++c) V[int64_t(r - j0) * kRqNb + c] = 0.0;
+    for (int jj = 0; jj < jb; ++jj) {
+      const int j = j0 + jj;
+      const int nc = jb - jj - 1;  // remaining panel columns
+      const double x0 = M[int64_t(j) * ld + j];
+      const double nrm = sqrt(ss);
+      const double alpha = nrm > 0.0 ? -copysign(nrm, x0) : 0.0;
+      const double v0 = x0 - alpha;
+      const double vtv = ss - x0 * x0 + v0 * v0;
+      const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+      double part[kRqNb];
+#pragma unroll
+      for (int c = 0; c < kRqNb; ++c) part[c] = 0.0;
+      for (int r0 = j + tid; r0 < m; r0 += 4 * 256) {
+        double vr[4], y[4][kRqNb];
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int r = r0 + qq * 256;
+          vr[qq] = 0.0;
+          if (r < m) vr[qq] = r == j ? v0 : M[int64_t(r) * ld + j];
+#pragma unroll
+          for (int c = 0; c < kRqNb; ++c) y[qq][c] = (r < m && c < nc) ? M[int64_t(r) * ld + j + 1 + c] : 0.0;
+        }
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int r = r0 + qq * 256;
+          if (r < m) V[int64_t(r - j0) * kRqNb + jj] = vr[qq];
+#pragma unroll
+          for (int c = 0; c < kRqNb; ++c) part[c] += vr[qq] * y[qq][c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kRqNb; ++c) {
+        if (c >= nc) break;
+        const double t = wave_sum(part[c]);
+        if (lane == 0) sred[wv][c] = t;
+      }
+      __syncthreads();
+      double wc[kRqNb];
+#pragma unroll
+      for (int c = 0; c < kRqNb; ++c)
+        wc[c] = c < nc ? beta * (sred[0][c] + sred[1][c] + sred[2][c] + sred[3][c]) : 0.0;
+      __syncthreads();
+      double snext = 0.0;
+      for (int r0 = j + tid; r0 < m; r0 += 4 * 256) {
+        double vr[4], y[4][kRqNb];
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int r = r0 + qq * 256;
+          vr[qq] = 0.0;
+          if (r < m) vr[qq] = r == j ? v0 : M[int64_t(r) * ld + j];
+#pragma unroll
+          for (int c = 0; c < kRqNb; ++c) y[qq][c] = (r < m && c < nc) ? M[int64_t(r) * ld + j + 1 + c] : 0.0;
+        }
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int r = r0 + qq * 256;
+#pragma unroll
+          for (int c = 0; c < kRqNb; ++c) y[qq][c] -= wc[c] * vr[qq];
+          if (r > j && r < m && nc > 0) snext += y[qq][0] * y[qq][0];
+          if (r < m) {
+#pragma unroll
+            for (int c = 0; c < kRqNb; ++c)
+              if (c < nc) M[int64_t(r) * ld + j + 1 + c] = y[qq][c];
+          }
+        }
+      }
+      if (tid == 0) sbeta[jj] = beta;
+      snext = wave_sum(snext);
+      if (lane == 0) sred[wv][0] = snext;
+      __syncthreads();
+      ss = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
+      if (tid == 0) M[int64_t(j) * ld + j] = alpha;
+      __syncthreads();
+    }
+    const int nt = n - j0 - jb;
+    if (nt <= 0) break;
+    const int mp = m - j0;
+    // --- T of the compact WY form: T_ii = beta_i, T(0:i, i) = -beta_i T(0:i,0:i) V(:,0:i)^T v_i ---
+    wg_gemm(jb, jb, mp, 1.0, V, kRqNb, true, V, kRqNb, false, 0.0, Gm, kRqNb, lds);
+    if (tid == 0) {
+      for (int i = 0; i < jb; ++i) {
+        sT[i][i] = sbeta[i];
+        for (int p = 0; p < i; ++p) {
+          double t = 0.0;
+          for (int l = p; l < i; ++l) t += sT[p][l] * Gm[l * kRqNb + i];
+          sT[p][i] = -sbeta[i] * t;
+        }
+        for (int p = i + 1; p < jb; ++p) sT[p][i] = 0.0;
+      }
+    }
+    __syncthreads();
+    // --- trailing update of columns j0+jb..n-1 ---
+    double* Yt = M + int64_t(j0) * ld + j0 + jb;
+    wg_gemm(jb, nt, mp, 1.0, V, kRqNb, true, Yt, ld, false, 0.0, W, nt, lds);
+    for (int c = tid; c < nt; c += 256) {  // W <- T^T W (lower triangular T^T), bottom row first
+      for (int i = jb - 1; i >= 0; --i) {
+        double t = 0.0;
+        for (int p = 0; p <= i; ++p) t += sT[p][i] * W[int64_t(p) * nt + c];
+        W[int64_t(i) * nt + c] = t;
+      }
+    }
+    __syncthreads();
+    wg_gemm(mp, nt, jb, -1.0, V, kRqNb, false, W, nt, false, 1.0, Yt, ld, lds);
+  }
+  // R0 = upper triangle of the leading n x n block; clear what lies below it.
+  for (int64_t e = tid; e < int64_t(n) * n; e += 256) {
+    const int r = int(e / n), c = int(e % n);
+    if (c < r) M[int64_t(r) * ld + c] = 0.0;
+  }
+}
+
+void launch_rowqr_auto(const RowQrArgs& A, int max_cols, hipStream_t s) {
+  // Few large problems: per-panel launches spread each problem over many
+  // workgroups; many small ones: one fused workgroup per problem.
+  if (A.nprob < 1024 && max_cols >= 96)
+    launch_qr_batched(A, max_cols, s);
+  else
+    launch_rowqr(A, s);
+}
+
+void launch_rowqr(const RowQrArgs& A, hipStream_t s) {
+  if (A.nprob == 0) return;
+  hipLaunchKernelGGL(k_rowqr, dim3(A.nprob), dim3(256), 0, s, A);
   HIF_HIP(hipGetLastError());
 }
 
@@ -383,157 +603,229 @@ __device__ void block_lu(double* A, int n, int ld, int32_t* piv, int32_t* status
 
 // ---------------------------------------------------------------------------
 // Skeletonization of one group (Lemma 2.4) and elimination of its redundant
-// DOFs (Lemma 2.1):
-//   B_sr = A_sr - A_ss T,  B_rs = A_rs - T^T A_ss,
-//   B_rr = A_rr - A_rs T - T^T B_sr,
-//   LU(B_rr), G = B_rr^{-1} B_rs, E = B_sr B_rr^{-1},
-//   new S(s,s) = S_old(s,s) - B_sr G.
-// T = diag(T_q) over the split classes, so every product over the skeleton
-// index runs only over the class of the redundant column.
+// DOFs (Lemma 2.1).  In (redundant, skeleton) order, Q^T A_cc Q has the blocks
+//   B_sr = A_sr - A_ss T,  B_rs = A_rs - T^T A_ss,  B_rr = A_rr - A_rs T - T^T B_sr,
+// and B_ss = A_ss.  A partial LU of M = [B_rr B_rs; B_sr S_ss] over its first
+// r columns, pivoting among the redundant rows only, gives
+//   P B_rr = L U,  U_rs = L^{-1} P B_rs,  L_sr = B_sr U^{-1},
+// and leaves S_ss - L_sr U_rs = S_old(s,s) - B_sr B_rr^{-1} B_rs, the updated
+// SCI block, in the trailing corner (M's skeleton block starts as the old
+// SCI block S_old(s,s) instead of A_ss).  These are the factors R_p and S_p
+// of Lemma 2.1 with the block LDU folded into (L, U).  The four products with
+// T and the trailing updates of the blocked LU run on the matrix cores.
 // ---------------------------------------------------------------------------
-__global__ void k_eliminate(ElimArgs A) {
+constexpr int kLuNb = 16;
+
+struct ElimView {
+  int r, k, n;
+  int64_t c0;
+  int32_t *rd, *sk, *piv;
+  double *T, *Lsr, *Urs, *LU, *M;
+  const double *Y, *Acc, *Scc;
+  int32_t *rdl, *skl, *rlo, *rhi;
+  const int32_t* cord;
+};
+
+__device__ ElimView elim_view(const ElimArgs& A, int g, const GroupRec& R) {
+  ElimView v;
+  v.r = R.r;
+  v.k = R.k;
+  v.c0 = A.gstart[g];
+  v.n = int(A.gstart[g + 1] - v.c0);
+  v.rd = A.iarena + R.idx;
+  v.sk = v.rd + v.r;
+  v.piv = v.sk + v.k;
+  v.T = A.darena + R.off;
+  v.Lsr = v.T + int64_t(v.k) * v.r;
+  v.Urs = v.Lsr + int64_t(v.k) * v.r;
+  v.LU = v.Urs + int64_t(v.r) * v.k;
+  v.Y = A.Y + A.yoff[g];
+  v.Acc = A.Acc + A.aoff[g];
+  v.Scc = A.Scc + A.aoff[g];
+  v.M = A.Mw + A.aoff[g];
+  v.rdl = A.loc + v.c0;  // rd_loc (r) then sk_loc (k): the (redundant, skeleton) order
+  v.skl = v.rdl + v.r;
+  v.rlo = A.rlo + v.c0;
+  v.rhi = A.rhi + v.c0;
+  v.cord = A.cord + v.c0;
+  return v;
+}
+
+// Skeleton / redundant lists in class order, T (k x r, block diagonal over
+// the classes) and M = A_cc in (redundant, skeleton) order.
+__device__ void elim_setup(const ElimArgs& A, int g, const ElimView& v) {
+  const int tid = threadIdx.x, B = blockDim.x;
+  const int r = v.r, k = v.k, n = v.n;
+  for (int q = A.cls_first[g]; q < A.cls_first[g + 1]; ++q) {
+    const int col0 = A.cls_col0[q], nq = A.cls_n[q], kq = A.cls_rank[q];
+    const int so = A.cls_skoff[q], ro = A.cls_rdoff[q];
+    const int32_t* pq = A.perm + v.c0 + col0;
+    for (int j = tid; j < nq; j += B) {
+      const int gl = col0 + pq[j];
+      if (j < kq) {
+        v.skl[so + j] = gl;
+        v.sk[so + j] = v.cord[gl];
+      } else {
+        const int bb = ro + (j - kq);
+        v.rdl[bb] = gl;
+        v.rd[bb] = v.cord[gl];
+        v.rlo[bb] = so;
+        v.rhi[bb] = so + kq;
+      }
+    }
+  }
+  __syncthreads();
+  for (int64_t e = tid; e < int64_t(k) * r; e += B) {
+    const int a = int(e / r), bb = int(e % r);
+    const int lo = v.rlo[bb];
+    v.T[e] = (a >= lo && a < v.rhi[bb]) ? v.Y[int64_t(a - lo) * n + v.rdl[bb]] : 0.0;
+  }
+  for (int64_t e = tid; e < int64_t(n) * n; e += B) {
+    const int i = int(e / n), j = int(e % n);
+    v.M[e] = v.Acc[int64_t(v.rdl[i]) * n + v.rdl[j]];
+  }
+  __syncthreads();
+}
+
+// The skeleton block of M starts as the old SCI block S_old(s,s).
+__device__ void elim_sss(const ElimView& v) {
+  const int n = v.n, r = v.r, k = v.k;
+  double* Mss = v.M + int64_t(r) * n + r;
+  for (int64_t e = threadIdx.x; e < int64_t(k) * k; e += blockDim.x) {
+    const int a = int(e / k), a2 = int(e % k);
+    Mss[int64_t(a) * n + a2] = v.Scc[int64_t(v.skl[a]) * n + v.skl[a2]];
+  }
+  __syncthreads();
+}
+
+// Factors into the record, the updated SCI block into the new entries.
+__device__ void elim_finish(const ElimArgs& A, int g, const ElimView& v) {
+  const int tid = threadIdx.x, B = blockDim.x;
+  const int n = v.n, r = v.r, k = v.k;
+  const double* Mss = v.M + int64_t(r) * n + r;
+  for (int64_t e = tid; e < int64_t(r) * r; e += B) v.LU[e] = v.M[(e / r) * n + e % r];
+  for (int64_t e = tid; e < int64_t(r) * k; e += B) v.Urs[e] = v.M[(e / k) * n + r + e % k];
+  for (int64_t e = tid; e < int64_t(k) * r; e += B) v.Lsr[e] = v.M[(r + e / r) * n + e % r];
+  uint64_t* nk = A.newkey + A.newoff[g];
+  double2* nv = A.newval + A.newoff[g];
+  for (int64_t e = tid; e < int64_t(k) * k; e += B) {
+    const int a = int(e / k), a2 = int(e % k);
+    nk[e] = (uint64_t(uint32_t(v.sk[a])) << 32) | uint32_t(v.sk[a2]);
+    nv[e] = make_double2(Mss[int64_t(a) * n + a2], Mss[int64_t(a2) * n + a]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_eliminate(ElimArgs A) {
   const int g = blockIdx.x;
   const int ri = A.grec[g];
   if (ri < 0) return;
   const GroupRec R = A.recs[ri];
-  const int r = R.r, k = R.k;
-  const int64_t c0 = A.gstart[g];
-  const int n = int(A.gstart[g + 1] - c0);
+  const ElimView v = elim_view(A, g, R);
+  const int r = v.r, k = v.k, n = v.n;
   const int tid = threadIdx.x, B = blockDim.x;
-  int32_t* rd = A.iarena + R.idx;
-  int32_t* sk = rd + r;
-  int32_t* piv = sk + k;
-  double* T = A.darena + R.off;
-  double* E = T + int64_t(k) * r;
-  double* Gm = E + int64_t(k) * r;
-  double* LU = Gm + int64_t(r) * k;
-  const double* Y = A.Y + A.yoff[g];
-  double* Acc = A.Acc + A.aoff[g];
-  const double* Scc = A.Scc + A.aoff[g];
-  int32_t* rdl = A.loc + c0;
-  int32_t* skl = rdl + r;
-  int32_t* rlo = A.rlo + c0;
-  int32_t* rhi = A.rhi + c0;
-  const int32_t* cord = A.cord + c0;
+  __shared__ double lds[kGemmLds];
+  double* M = v.M;
+  int32_t* piv = v.piv;
+  elim_setup(A, g, v);
+  // the skeletonization transform Q^T A_cc Q
+  double* Mrr = M;
+  double* Mrs = M + r;
+  double* Msr = M + int64_t(r) * n;
+  double* Mss = Msr + r;
+  if (k > 0) {
+    wg_gemm(r, r, k, -1.0, Mrs, n, false, v.T, r, false, 1.0, Mrr, n, lds);   // A_rr - A_rs T
+    wg_gemm(k, r, k, -1.0, Mss, n, false, v.T, r, false, 1.0, Msr, n, lds);   // B_sr
+    wg_gemm(r, r, k, -1.0, v.T, r, true, Msr, n, false, 1.0, Mrr, n, lds);    // B_rr
+    wg_gemm(r, k, k, -1.0, v.T, r, true, Mss, n, false, 1.0, Mrs, n, lds);    // B_rs
+    elim_sss(v);
+  }
+  // blocked partial LU over the first r columns
+  for (int j0 = 0; j0 < r; j0 += kLuNb) {
+    const int jb = min(kLuNb, r - j0);
+    for (int j = j0; j < j0 + jb; ++j) {
+      ArgMax loc2{-1.0, INT_MAX};
+      for (int i = j + tid; i < r; i += B) loc2 = better(loc2, ArgMax{fabs(M[int64_t(i) * n + j]), i});
+      const ArgMax best = block_argmax(loc2);
+      if (!(best.v > 0.0)) {
+        if (tid == 0) atomicOr(A.status, 1);
+        return;
+      }
+      const int p = best.i;
+      if (tid == 0) piv[j] = p;
+      if (p != j)
+        for (int col = tid; col < n; col += B) {
+          const double t = M[int64_t(j) * n + col];
+          M[int64_t(j) * n + col] = M[int64_t(p) * n + col];
+          M[int64_t(p) * n + col] = t;
+        }
+      __syncthreads();
+      const double inv = 1.0 / M[int64_t(j) * n + j];
+      const int w = j0 + jb - j - 1;
+      for (int i = j + 1 + tid; i < n; i += B) {
+        double* row = M + int64_t(i) * n;
+        const double l = row[j] * inv;
+        row[j] = l;
+        for (int c = 1; c <= w; ++c) row[j + c] -= l * M[int64_t(j) * n + j + c];
+      }
+      __syncthreads();
+    }
+    const int nt = n - j0 - jb;
+    if (nt > 0) {
+      for (int c = j0 + jb + tid; c < n; c += B)
+        for (int i = j0 + 1; i < j0 + jb; ++i) {
+          double val = M[int64_t(i) * n + c];
+          for (int p = j0; p < i; ++p) val -= M[int64_t(i) * n + p] * M[int64_t(p) * n + c];
+          M[int64_t(i) * n + c] = val;
+        }
+      __syncthreads();
+      wg_gemm(n - j0 - jb, nt, jb, -1.0, M + int64_t(j0 + jb) * n + j0, n, false, M + int64_t(j0) * n + j0 + jb, n,
+              false, 1.0, M + int64_t(j0 + jb) * n + j0 + jb, n, lds);
+    }
+  }
+  elim_finish(A, g, v);
+}
 
-  // 1. skeleton / redundant lists in class order.
-  for (int q = A.cls_first[g]; q < A.cls_first[g + 1]; ++q) {
-    const int col0 = A.cls_col0[q], nq = A.cls_n[q], kq = A.cls_rank[q];
-    const int so = A.cls_skoff[q], ro = A.cls_rdoff[q];
-    const int32_t* pq = A.perm + c0 + col0;
-    for (int j = tid; j < nq; j += B) {
-      const int gl = col0 + pq[j];
-      if (j < kq) {
-        skl[so + j] = gl;
-        sk[so + j] = cord[gl];
-      } else {
-        const int bb = ro + (j - kq);
-        rdl[bb] = gl;
-        rd[bb] = cord[gl];
-        rlo[bb] = so;
-        rhi[bb] = so + kq;
-      }
-    }
-  }
-  __syncthreads();
-  // 2. dense block-diagonal T (k x r).
-  for (int64_t e = tid; e < int64_t(k) * r; e += B) {
-    const int a = int(e / r), bb = int(e % r);
-    const int lo = rlo[bb];
-    T[e] = (a >= lo && a < rhi[bb]) ? Y[int64_t(a - lo) * n + rdl[bb]] : 0.0;
-  }
-  __syncthreads();
-  // 3. B_sr (into E) and B_rs (into G).
-  for (int64_t e = tid; e < int64_t(k) * r; e += B) {
-    const int a = int(e / r), bb = int(e % r);
-    const double* arow = Acc + int64_t(skl[a]) * n;
-    double v = arow[rdl[bb]];
-    for (int l = rlo[bb]; l < rhi[bb]; ++l) v -= arow[skl[l]] * T[int64_t(l) * r + bb];
-    E[e] = v;
-  }
-  for (int64_t e = tid; e < int64_t(r) * k; e += B) {
-    const int bb = int(e / k), a = int(e % k);
-    double v = Acc[int64_t(rdl[bb]) * n + skl[a]];
-    for (int l = rlo[bb]; l < rhi[bb]; ++l) v -= T[int64_t(l) * r + bb] * Acc[int64_t(skl[l]) * n + skl[a]];
-    Gm[e] = v;
-  }
-  __syncthreads();
-  // 4. B_rr (into LU).
-  for (int64_t e = tid; e < int64_t(r) * r; e += B) {
-    const int bb = int(e / r), ee = int(e % r);
-    const double* arow = Acc + int64_t(rdl[bb]) * n;
-    double v = arow[rdl[ee]];
-    for (int l = rlo[ee]; l < rhi[ee]; ++l) v -= arow[skl[l]] * T[int64_t(l) * r + ee];
-    for (int l = rlo[bb]; l < rhi[bb]; ++l) v -= T[int64_t(l) * r + bb] * E[int64_t(l) * r + ee];
-    LU[e] = v;
-  }
-  __syncthreads();
-  // 5. LU(B_rr).
-  block_lu(LU, r, r, piv, A.status);
-  __syncthreads();
-  // 6. G = B_rr^{-1} B_rs, one column of G per thread.
-  for (int a = tid; a < k; a += B) {
-    for (int j = 0; j < r; ++j) {
-      const int p = piv[j];
-      if (p != j) {
-        double t = Gm[int64_t(j) * k + a];
-        Gm[int64_t(j) * k + a] = Gm[int64_t(p) * k + a];
-        Gm[int64_t(p) * k + a] = t;
-      }
-    }
-    for (int i = 1; i < r; ++i) {
-      double v = Gm[int64_t(i) * k + a];
-      for (int j = 0; j < i; ++j) v -= LU[int64_t(i) * r + j] * Gm[int64_t(j) * k + a];
-      Gm[int64_t(i) * k + a] = v;
-    }
-    for (int i = r - 1; i >= 0; --i) {
-      double v = Gm[int64_t(i) * k + a];
-      for (int j = i + 1; j < r; ++j) v -= LU[int64_t(i) * r + j] * Gm[int64_t(j) * k + a];
-      Gm[int64_t(i) * k + a] = v / LU[int64_t(i) * r + i];
-    }
-  }
-  __syncthreads();
-  // 7. new S block (k x k) = S_old(s,s) - B_sr G, staged in the A_cc scratch.
-  double* NS = Acc;
-  for (int64_t e = tid; e < int64_t(k) * k; e += B) {
-    const int a = int(e / k), a2 = int(e % k);
-    double v = Scc[int64_t(skl[a]) * n + skl[a2]];
-    const double* er = E + int64_t(a) * r;
-    for (int bb = 0; bb < r; ++bb) v -= er[bb] * Gm[int64_t(bb) * k + a2];
-    NS[e] = v;
-  }
-  __syncthreads();
-  {
-    uint64_t* nk = A.newkey + A.newoff[g];
-    double2* nv = A.newval + A.newoff[g];
-    for (int64_t e = tid; e < int64_t(k) * k; e += B) {
-      const int a = int(e / k), a2 = int(e % k);
-      nk[e] = (uint64_t(uint32_t(sk[a])) << 32) | uint32_t(sk[a2]);
-      nv[e] = make_double2(NS[e], NS[int64_t(a2) * k + a]);
-    }
-  }
-  // 8. E = B_sr B_rr^{-1}, one row per thread: x P^T L U = b.
-  for (int a = tid; a < k; a += B) {
-    double* x = E + int64_t(a) * r;
-    for (int j = 0; j < r; ++j) {  // y U = b
-      double v = x[j];
-      for (int i = 0; i < j; ++i) v -= x[i] * LU[int64_t(i) * r + j];
-      x[j] = v / LU[int64_t(j) * r + j];
-    }
-    for (int j = r - 2; j >= 0; --j) {  // z L = y (unit lower)
-      double v = x[j];
-      for (int i = j + 1; i < r; ++i) v -= x[i] * LU[int64_t(i) * r + j];
-      x[j] = v;
-    }
-    for (int j = r - 1; j >= 0; --j) {  // x = z P
-      const int p = piv[j];
-      if (p != j) {
-        double t = x[j];
-        x[j] = x[p];
-        x[p] = t;
-      }
-    }
-  }
+// Split path for sub-levels with few, large groups: setup, M_ss, finish as
+// kernels of their own; the transform and the partial LU run as batched
+// multi-workgroup launches in between.
+__global__ __launch_bounds__(256) void k_elim_setup(ElimArgs A) {
+  const int g = blockIdx.x;
+  const int ri = A.grec[g];
+  if (ri < 0) return;
+  const GroupRec R = A.recs[ri];
+  elim_setup(A, g, elim_view(A, g, R));
+}
+
+__global__ __launch_bounds__(256) void k_elim_sss(ElimArgs A) {
+  const int g = blockIdx.x;
+  const int ri = A.grec[g];
+  if (ri < 0) return;
+  const GroupRec R = A.recs[ri];
+  if (R.k > 0) elim_sss(elim_view(A, g, R));
+}
+
+__global__ __launch_bounds__(256) void k_elim_finish(ElimArgs A) {
+  const int g = blockIdx.x;
+  const int ri = A.grec[g];
+  if (ri < 0) return;
+  const GroupRec R = A.recs[ri];
+  elim_finish(A, g, elim_view(A, g, R));
+}
+
+void launch_elim_setup(const ElimArgs& A, hipStream_t s) {
+  if (A.ngroups == 0) return;
+  hipLaunchKernelGGL(k_elim_setup, dim3(A.ngroups), dim3(256), 0, s, A);
+  HIF_HIP(hipGetLastError());
+}
+void launch_elim_sss(const ElimArgs& A, hipStream_t s) {
+  if (A.ngroups == 0) return;
+  hipLaunchKernelGGL(k_elim_sss, dim3(A.ngroups), dim3(256), 0, s, A);
+  HIF_HIP(hipGetLastError());
+}
+void launch_elim_finish(const ElimArgs& A, hipStream_t s) {
+  if (A.ngroups == 0) return;
+  hipLaunchKernelGGL(k_elim_finish, dim3(A.ngroups), dim3(256), 0, s, A);
+  HIF_HIP(hipGetLastError());
 }
 
 void launch_eliminate(const ElimArgs& A, hipStream_t s) {
@@ -592,8 +884,10 @@ void launch_top(const TopArgs& A, hipStream_t s) {
   HIF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_top_sci, dim3(unsigned(A.n)), dim3(64), 0, s, A);
   HIF_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_top_lu, dim3(1), dim3(1024), 0, s, A);
-  HIF_HIP(hipGetLastError());
+  if (A.n <= 256) {
+    hipLaunchKernelGGL(k_top_lu, dim3(1), dim3(1024), 0, s, A);
+    HIF_HIP(hipGetLastError());
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -612,11 +906,44 @@ void id_batched_impl(double* mats, const int64_t* off, const int32_t* rows, cons
   ld.alloc(size_t(batch), nullptr);
   hipLaunchKernelGGL(k_copy_ld, dim3((batch + 255) / 256), dim3(256), 0, s, cols, ld.p, batch);
   HIF_HIP(hipGetLastError());
+  // Row compression first, as in the factorization.
+  std::vector<int32_t> hr(batch), hc(batch);
+  HIF_HIP(hipMemcpyAsync(hr.data(), rows, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, s));
+  HIF_HIP(hipMemcpyAsync(hc.data(), cols, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, s));
+  HIF_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> hr2(batch);
+  std::vector<int64_t> hso(batch);
+  int64_t qt = 0;
+  for (int p = 0; p < batch; ++p) {
+    HIF_REQUIRE(hc[p] >= 1 && hc[p] <= max_cols && hr[p] >= 1, HIF_EINVAL,
+                "every matrix needs 1 <= cols <= max_cols and rows >= 1");
+    hr2[p] = std::min(hr[p], hc[p]);
+    hso[p] = qt;
+    if (hr[p] > hc[p]) qt += int64_t(hr[p]) * 16 + 16 * int64_t(hc[p]) + 256;
+  }
+  DBuf<int32_t> rows2;
+  DBuf<int64_t> soff;
+  DBuf<double> scratch;
+  rows2.alloc(batch, nullptr);
+  soff.alloc(batch, nullptr);
+  scratch.alloc(qt + 1, nullptr);
+  HIF_HIP(hipMemcpyAsync(rows2.p, hr2.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice, s));
+  HIF_HIP(hipMemcpyAsync(soff.p, hso.data(), sizeof(int64_t) * batch, hipMemcpyHostToDevice, s));
+  RowQrArgs Q;
+  Q.base = mats;
+  Q.moff = off;
+  Q.ld = ld.p;
+  Q.rows = rows;
+  Q.cols = cols;
+  Q.scratch = scratch.p;
+  Q.soff = soff.p;
+  Q.nprob = batch;
+  launch_rowqr_auto(Q, max_cols, s);
   IdArgs A;
   A.base = mats;
   A.moff = off;
   A.ld = ld.p;
-  A.rows = rows;
+  A.rows = rows2.p;
   A.cols = cols;
   A.tol = tol;
   A.rank = rank;

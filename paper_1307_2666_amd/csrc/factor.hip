@@ -8,6 +8,7 @@
 #include <climits>
 #include <numeric>
 
+#include "batched.h"
 #include "kernels.h"
 
 namespace hif {
@@ -594,13 +595,14 @@ struct Timer {
     ev.push_back(e);
     phase.push_back(ph);
   }
-  void flush(double* acc) {
+  void flush(double* acc, double* acc2 = nullptr) {
     if (ev.size() >= 2) {
       HIF_HIP(hipEventSynchronize(ev.back()));
       for (size_t i = 1; i < ev.size(); ++i) {
         float ms = 0.f;
         HIF_HIP(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
         acc[phase[i]] += ms;
+        if (acc2) acc2[phase[i]] += ms;
       }
     }
     for (auto e : ev) (void)hipEventDestroy(e);
@@ -612,7 +614,7 @@ struct Timer {
   }
 };
 
-enum { PH_PART = 0, PH_ASM = 1, PH_ID = 2, PH_ELIM = 3, PH_SCI = 4, PH_TOP = 5, PH_HOST = 6, PH_OTHER = 7 };
+enum { PH_PART = 0, PH_ASM = 1, PH_ID = 2, PH_ELIM = 3, PH_SCI = 4, PH_TOP = 5, PH_HOST = 6, PH_QR = 7 };
 
 struct Factorizer {
   hif_factor_s* H;
@@ -644,7 +646,12 @@ struct Factorizer {
   DBuf<int32_t> hc, rep, newpos, cord, ncls;
   DBuf<int32_t> cls_first, cls_col0, cls_n, cls_group, cls_rank, cls_skoff, cls_rdoff, cls_ld, cls_rows, perm;
   DBuf<int64_t> cls_moff, cls_poff, yoff, aoff, newoff;
-  DBuf<double> cls_tol, Y, Acc, Scc, colK2, colS2;
+  DBuf<double> cls_tol, Y, Acc, Scc, Mw, colK2, colS2, qr_scratch;
+  DBuf<int32_t> cls_rows2;
+  DBuf<int64_t> cls_soff;
+  DBuf<GemmDesc> gdesc;
+  DBuf<int64_t> lu_moff, lu_poff;
+  DBuf<int32_t> lu_n, lu_r;
   DBuf<int32_t> grec, loc, rlo, rhi, status, sidx, sidx2;
   DBuf<uint64_t> newkey;
   DBuf<double2> newval;
@@ -674,7 +681,7 @@ void Factorizer::sublevel(int lvl, int kind) {
     H->subs.push_back(std::move(sub));
     return;
   }
-  tm.mark(PH_OTHER);
+  tm.mark(PH_HOST);
 
   // ---- partition of the active DOFs into groups -------------------------
   key.ensure(nact, mt);
@@ -848,6 +855,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   Y.ensure(ytot, mt);
   Acc.ensure(atot, mt);
   Scc.ensure(atot, mt);
+  Mw.ensure(atot, mt);
   colK2.ensure(nact, mt);
   colS2.ensure(nact, mt);
   AsmArgs aa{};
@@ -902,12 +910,41 @@ void Factorizer::sublevel(int lvl, int kind) {
   to_host(h_cls_col0, cls_col0.p, NC, s);
   int maxq = 1;
   for (int q = 0; q < NC; ++q) maxq = std::max(maxq, h_cls_n[q]);
+  std::vector<int32_t> h_rows2(NC);
+  std::vector<int64_t> h_soff(NC);
+  int64_t qtot = 0;
+  for (int g = 0; g < G; ++g) {
+    const int64_t nf = h_nf[g + 1] - h_nf[g];
+    const int64_t m = sym ? nf + P : 2 * nf + 2 * P;
+    for (int q = h_cls_first[g]; q < h_cls_first[g + 1]; ++q) {
+      const int64_t nq = h_cls_n[q];
+      h_rows2[q] = int32_t(std::min<int64_t>(m, nq));
+      h_soff[q] = qtot;
+      if (m > nq) qtot += m * 16 + 16 * nq + 256;
+    }
+  }
+  cls_rows2.ensure(NC, mt);
+  cls_soff.ensure(NC, mt);
+  to_dev(cls_rows2.p, h_rows2, s);
+  to_dev(cls_soff.p, h_soff, s);
+  qr_scratch.ensure(qtot + 1, mt);
   tm.mark(PH_HOST);
+  RowQrArgs qa{};
+  qa.base = Y.p;
+  qa.moff = cls_moff.p;
+  qa.ld = cls_ld.p;
+  qa.rows = cls_rows.p;
+  qa.cols = cls_n.p;
+  qa.scratch = qr_scratch.p;
+  qa.soff = cls_soff.p;
+  qa.nprob = NC;
+  launch_rowqr_auto(qa, maxq, s);
+  tm.mark(PH_QR);
   IdArgs ia{};
   ia.base = Y.p;
   ia.moff = cls_moff.p;
   ia.ld = cls_ld.p;
-  ia.rows = cls_rows.p;
+  ia.rows = cls_rows2.p;
   ia.cols = cls_n.p;
   ia.tol = cls_tol.p;
   ia.rank = cls_rank.p;
@@ -923,6 +960,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   std::vector<int32_t> h_rank;
   to_host(h_rank, cls_rank.p, NC, s);
   std::vector<int32_t> h_grec(G, -1), h_skoff(NC), h_rdoff(NC);
+  std::vector<int> rec_g;
   std::vector<int64_t> h_newoff(G, 0);
   int64_t itot = 0, dtot = 0, ntot_new = 0, skel = 0;
   double idfl = 0.0, elfl = 0.0;
@@ -948,6 +986,7 @@ void Factorizer::sublevel(int lvl, int kind) {
       R.off = dtot;
       h_grec[g] = int32_t(sub.hrec.size());
       sub.hrec.push_back(R);
+      rec_g.push_back(g);
       itot += 2 * int64_t(rr) + kk;
       dtot += 3 * int64_t(kk) * rr + int64_t(rr) * rr;
       ntot_new += int64_t(kk) * kk;
@@ -993,6 +1032,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   ea.yoff = yoff.p;
   ea.Acc = Acc.p;
   ea.Scc = Scc.p;
+  ea.Mw = Mw.p;
   ea.aoff = aoff.p;
   ea.cls_first = cls_first.p;
   ea.cls_col0 = cls_col0.p;
@@ -1008,7 +1048,68 @@ void Factorizer::sublevel(int lvl, int kind) {
   ea.newval = newval.p;
   ea.newoff = newoff.p;
   ea.status = status.p;
-  launch_eliminate(ea, s);
+  int max_nrec = 0;
+  for (int g : rec_g) max_nrec = std::max<int>(max_nrec, int(h_gstart[g + 1] - h_gstart[g]));
+  if (sub.nrec > 0 && (max_nrec > 256 || (sub.nrec < 256 && max_nrec > 96))) {
+    // split path: setup, transform GEMMs, M_ss, batched partial LU, finish
+    launch_elim_setup(ea, s);
+    std::vector<GemmDesc> d1, d2;
+    int mm = 1, mn = 1;
+    std::vector<int64_t> hm, hp;
+    std::vector<int32_t> hn, hr;
+    for (int i = 0; i < sub.nrec; ++i) {
+      const GroupRec& R = sub.hrec[i];
+      const int g = rec_g[i];
+      const int n = int(h_gstart[g + 1] - h_gstart[g]);
+      double* M = Mw.p + h_aoff[g];
+      double* T = sub.darena.p + R.off;
+      const int r = R.r, k = R.k;
+      if (k > 0) {
+        d1.push_back(GemmDesc{r, r, k, 0, 0, n, r, n, -1.0, 1.0, M + r, T, M});                      // A_rr - A_rs T
+        d1.push_back(GemmDesc{k, r, k, 0, 0, n, r, n, -1.0, 1.0, M + int64_t(r) * n + r, T,
+                              M + int64_t(r) * n});                                                  // B_sr
+        d2.push_back(GemmDesc{r, r, k, 1, 0, r, n, n, -1.0, 1.0, T, M + int64_t(r) * n, M});        // B_rr
+        d2.push_back(GemmDesc{r, k, k, 1, 0, r, n, n, -1.0, 1.0, T, M + int64_t(r) * n + r, M + r}); // B_rs
+        mm = std::max(mm, std::max(r, k));
+        mn = std::max(mn, std::max(r, k));
+      }
+      hm.push_back(h_aoff[g]);
+      hp.push_back(R.idx + r + k);
+      hn.push_back(n);
+      hr.push_back(r);
+    }
+    if (!d1.empty()) {
+      gdesc.ensure(d1.size() + d2.size(), mt);
+      std::vector<GemmDesc> all(d1);
+      all.insert(all.end(), d2.begin(), d2.end());
+      to_dev(gdesc.p, all, s);
+      launch_gemm_tiles(gdesc.p, int(d1.size()), mm, mn, s);
+      launch_gemm_tiles(gdesc.p + d1.size(), int(d2.size()), mm, mn, s);
+      launch_elim_sss(ea, s);
+    }
+    lu_moff.ensure(sub.nrec, mt);
+    lu_poff.ensure(sub.nrec, mt);
+    lu_n.ensure(sub.nrec, mt);
+    lu_r.ensure(sub.nrec, mt);
+    to_dev(lu_moff.p, hm, s);
+    to_dev(lu_poff.p, hp, s);
+    to_dev(lu_n.p, hn, s);
+    to_dev(lu_r.p, hr, s);
+    LuBatch lb{};
+    lb.base = Mw.p;
+    lb.moff = lu_moff.p;
+    lb.n = lu_n.p;
+    lb.r = lu_r.p;
+    lb.piv = sub.iarena.p;
+    lb.poff = lu_poff.p;
+    lb.status = status.p;
+    lb.nprob = sub.nrec;
+    launch_lu_batched(lb, sub.max_r, max_nrec, s);
+    launch_elim_finish(ea, s);
+    HIF_HIP(hipStreamSynchronize(s));  // descriptor tables are host vectors
+  } else {
+    launch_eliminate(ea, s);
+  }
   tm.mark(PH_ELIM);
 
   // ---- SCI store update, active set ----------------------------------------
@@ -1063,14 +1164,14 @@ void Factorizer::sublevel(int lvl, int kind) {
   std::swap(act, act2);
   nact = nact2;
   tm.mark(PH_SCI);
-  tm.flush(st.t_phase_ms);
+  tm.flush(st.t_phase_ms, st.sub_t_ms[si]);
   const int32_t bad = scalar_at(status.p, s);
   HIF_REQUIRE(bad == 0, HIF_ESINGULAR, "zero pivot in a redundant block B_rr (Lemma 2.1 needs it nonsingular)");
   H->subs.push_back(std::move(sub));
 }
 
 void Factorizer::top() {
-  tm.mark(PH_OTHER);
+  tm.mark(PH_HOST);
   H->ntop = nact;
   const int64_t n = nact;
   H->top_idx.alloc(n, mt);
@@ -1097,6 +1198,29 @@ void Factorizer::top() {
     ta.piv = H->top_piv.p;
     ta.status = status.p;
     launch_top(ta, s);
+    if (n > 256) {  // blocked LU spread over the whole GPU
+      lu_moff.ensure(1, mt);
+      lu_poff.ensure(1, mt);
+      lu_n.ensure(1, mt);
+      lu_r.ensure(1, mt);
+      std::vector<int64_t> z = {0};
+      std::vector<int32_t> nn = {int32_t(n)};
+      to_dev(lu_moff.p, z, s);
+      to_dev(lu_poff.p, z, s);
+      to_dev(lu_n.p, nn, s);
+      to_dev(lu_r.p, nn, s);
+      LuBatch lb{};
+      lb.base = H->top_lu.p;
+      lb.moff = lu_moff.p;
+      lb.n = lu_n.p;
+      lb.r = lu_r.p;
+      lb.piv = H->top_piv.p;
+      lb.poff = lu_poff.p;
+      lb.status = status.p;
+      lb.nprob = 1;
+      launch_lu_batched(lb, int(n), int(n), s);
+      HIF_HIP(hipStreamSynchronize(s));
+    }
   }
   tm.mark(PH_TOP);
   tm.flush(H->stats.t_phase_ms);

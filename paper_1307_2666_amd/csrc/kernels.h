@@ -48,6 +48,21 @@ struct IdArgs {
 };
 void launch_id(const IdArgs& A, int max_cols, hipStream_t s);
 
+// Row compression Y = Q R0 (blocked Householder, no pivoting) before the ID;
+// R0 overwrites the leading n x n block of each problem with m > n.
+struct RowQrArgs {
+  double* base;
+  const int64_t* moff;
+  const int32_t* ld;
+  const int32_t* rows;
+  const int32_t* cols;
+  double* scratch;       // per problem: m*16 + 16*n + 256 doubles
+  const int64_t* soff;
+  int nprob = 0;
+};
+void launch_rowqr(const RowQrArgs& A, hipStream_t s);
+void launch_rowqr_auto(const RowQrArgs& A, int max_cols, hipStream_t s);
+
 // Batched skeletonization + elimination (Lemma 2.4 with Lemma 2.1), one
 // workgroup per group with a record.
 struct ElimArgs {
@@ -60,8 +75,9 @@ struct ElimArgs {
   double* darena;
   const double* Y;              // IDs in place (T_q in rows 0..k_q-1)
   const int64_t* yoff;
-  double* Acc;                  // destroyed (reused as scratch)
+  const double* Acc;
   const double* Scc;
+  double* Mw;                   // workspace, same layout as Acc
   const int64_t* aoff;
   const int32_t* cls_first;     // [G+1] classes of group g
   const int32_t* cls_col0;      // group-local first column of class q
@@ -79,6 +95,9 @@ struct ElimArgs {
   int32_t* status;              // set to 1 on a zero pivot
 };
 void launch_eliminate(const ElimArgs& A, hipStream_t s);
+void launch_elim_setup(const ElimArgs& A, hipStream_t s);
+void launch_elim_sss(const ElimArgs& A, hipStream_t s);
+void launch_elim_finish(const ElimArgs& A, hipStream_t s);
 
 // Top block A_L(s_L, s_L) = diag(a) + bKc + S, then LU with partial pivoting.
 struct TopArgs {

@@ -1,11 +1,18 @@
 // Factored apply / solve sweeps: F = U_0^{-T} ... D ... V_0^{-1} and
 // F^{-1} = V_0 ... D^{-1} ... U_0^T (eqns rskelf, hifie2, hifie3) and their
-// transposes.  Per group (Lemma 2.4 with Lemma 2.1), with Q = [I 0; -T I] in
-// (redundant, skeleton) order:
-//   solve   up:  u_r -= T^T u_s; u_s -= E u_r     mid: u_r = B_rr^{-1} u_r   down: u_r -= G u_s; u_s -= T u_r
-//   solve_T up:  u_r -= T^T u_s; u_s -= G^T u_r   mid: B_rr^{-T}             down: u_r -= E^T u_s; u_s -= T u_r
-//   apply   up:  x_s += T x_r;   x_r += G x_s     mid: x_r = B_rr x_r        down: y_s += E y_r; y_r += T^T y_s
-//   apply_T up:  x_s += T x_r;   x_r += E^T x_s   mid: B_rr^T                down: y_s += G^T y_r; y_r += T^T y_s
+// transposes.  A group record holds T, the row-pivoted LU of B_rr
+// (P B_rr = L U), L_sr = B_sr U^{-1} and U_rs = L^{-1} P B_rs (the operators
+// R_p, S_p of Lemma 2.1 with Q = [I 0; -T I] of Lemma 2.4, (redundant,
+// skeleton) order).  Per group:
+//   solve   up:   u_r -= T^T u_s;  u_r = L^{-1} P u_r;     u_s -= L_sr u_r
+//           down: u_r -= U_rs u_s; u_r = U^{-1} u_r;       u_s -= T u_r
+//   solve_T up:   u_r -= T^T u_s;  u_r = U^{-T} u_r;       u_s -= U_rs^T u_r
+//           down: u_r -= L_sr^T u_s; u_r = P^T L^{-T} u_r; u_s -= T u_r
+//   apply   up:   x_s += T x_r;    x_r = U x_r + U_rs x_s
+//           down: y_s += L_sr y_r; y_r = P^T L y_r;        y_r += T^T y_s
+//   apply_T up:   x_s += T x_r;    x_r = L^T P x_r + L_sr^T x_s
+//           down: y_s += U_rs^T y_r; y_r = U^T y_r;        y_r += T^T y_s
+// with the top block A_L (LU with pivoting) solved or applied in between.
 // "up" visits sub-levels finest first, "down" in reverse; the groups of one
 // sub-level touch disjoint DOFs and run as one launch, one workgroup each.
 // Vectors are [nrhs][N] in the caller's order; every product works in place
@@ -57,29 +64,147 @@ __device__ void gemv_cols(const double* M, int nrow, int ncol, int ld, const int
   }
 }
 
+// Triangular pieces on u_r = u[v*N + idx[i]], i < n, all RHS; LU is n x n
+// row-major holding unit-lower L and upper U; piv the row interchanges.
+__device__ void swaps_fwd(const int32_t* piv, int n, const int32_t* idx, double* u, int64_t N, int nrhs) {
+  for (int v = threadIdx.x; v < nrhs; v += blockDim.x)
+    for (int j = 0; j < n; ++j)
+      if (piv[j] != j) {
+        double* a = u + v * N + idx[j];
+        double* b = u + v * N + idx[piv[j]];
+        const double t = *a; *a = *b; *b = t;
+      }
+  __syncthreads();
+}
+__device__ void swaps_rev(const int32_t* piv, int n, const int32_t* idx, double* u, int64_t N, int nrhs) {
+  for (int v = threadIdx.x; v < nrhs; v += blockDim.x)
+    for (int j = n - 1; j >= 0; --j)
+      if (piv[j] != j) {
+        double* a = u + v * N + idx[j];
+        double* b = u + v * N + idx[piv[j]];
+        const double t = *a; *a = *b; *b = t;
+      }
+  __syncthreads();
+}
+// x = L^{-1} x (unit lower), column oriented
+__device__ void solve_L(const double* LU, int n, const int32_t* idx, double* u, int64_t N, int nrhs) {
+  for (int j = 0; j < n - 1; ++j) {
+    const int w = n - 1 - j;
+    for (int e = threadIdx.x; e < w * nrhs; e += blockDim.x) {
+      const int i = j + 1 + e % w, v = e / w;
+      u[v * N + idx[i]] -= LU[int64_t(i) * n + j] * u[v * N + idx[j]];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+}
+// x = U^{-1} x
+__device__ void solve_U(const double* LU, int n, const int32_t* idx, double* u, int64_t N, int nrhs) {
+  for (int j = n - 1; j >= 0; --j) {
+    const double inv = 1.0 / LU[int64_t(j) * n + j];
+    for (int e = threadIdx.x; e < j * nrhs; e += blockDim.x) {
+      const int i = e % j, v = e / j;
+      u[v * N + idx[i]] -= LU[int64_t(i) * n + j] * (u[v * N + idx[j]] * inv);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n * nrhs; e += blockDim.x) {
+    const int i = e % n, v = e / n;
+    u[v * N + idx[i]] /= LU[int64_t(i) * n + i];
+  }
+  __syncthreads();
+}
+// x = U^{-T} x (U^T lower)
+__device__ void solve_UT(const double* LU, int n, const int32_t* idx, double* u, int64_t N, int nrhs) {
+  for (int j = 0; j < n; ++j) {
+    const double inv = 1.0 / LU[int64_t(j) * n + j];
+    const int w = n - 1 - j;
+    for (int e = threadIdx.x; e < w * nrhs; e += blockDim.x) {
+      const int i = j + 1 + e % w, v = e / w;
+      u[v * N + idx[i]] -= LU[int64_t(j) * n + i] * (u[v * N + idx[j]] * inv);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n * nrhs; e += blockDim.x) {
+    const int i = e % n, v = e / n;
+    u[v * N + idx[i]] /= LU[int64_t(i) * n + i];
+  }
+  __syncthreads();
+}
+// x = L^{-T} x (L^T unit upper)
+__device__ void solve_LT(const double* LU, int n, const int32_t* idx, double* u, int64_t N, int nrhs) {
+  for (int j = n - 1; j > 0; --j) {
+    for (int e = threadIdx.x; e < j * nrhs; e += blockDim.x) {
+      const int i = e % j, v = e / j;
+      u[v * N + idx[i]] -= LU[int64_t(j) * n + i] * u[v * N + idx[j]];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+}
+// x = op(x) through the work buffer: mode 0: U x, 1: L x, 2: L^T x, 3: U^T x
+__device__ void tri_mul(const double* LU, int n, const int32_t* idx, double* u, double* work, int64_t N, int nrhs,
+                        int mode) {
+  for (int e = threadIdx.x; e < n * nrhs; e += blockDim.x) {
+    const int i = e % n, v = e / n;
+    const double* uv = u + v * N;
+    double s = 0.0;
+    if (mode == 0) {
+      for (int j = i; j < n; ++j) s += LU[int64_t(i) * n + j] * uv[idx[j]];
+    } else if (mode == 1) {
+      s = uv[idx[i]];
+      for (int j = 0; j < i; ++j) s += LU[int64_t(i) * n + j] * uv[idx[j]];
+    } else if (mode == 2) {
+      s = uv[idx[i]];
+      for (int j = i + 1; j < n; ++j) s += LU[int64_t(j) * n + i] * uv[idx[j]];
+    } else {
+      for (int j = 0; j <= i; ++j) s += LU[int64_t(j) * n + i] * uv[idx[j]];
+    }
+    work[v * N + idx[i]] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * nrhs; e += blockDim.x) {
+    const int i = e % n, v = e / n;
+    u[v * N + idx[i]] = work[v * N + idx[i]];
+  }
+  __syncthreads();
+}
+
 __global__ void k_up(SwArgs A) {
   const GroupRec R = A.recs[blockIdx.x];
   const int r = R.r, k = R.k;
   const int32_t* rd = A.iarena + R.idx;
   const int32_t* sk = rd + r;
+  const int32_t* piv = sk + k;
   const double* T = A.darena + R.off;
-  const double* E = T + int64_t(k) * r;
-  const double* Gm = E + int64_t(k) * r;
-  if (k == 0) return;
+  const double* Lsr = T + int64_t(k) * r;
+  const double* Urs = Lsr + int64_t(k) * r;
+  const double* LU = Urs + int64_t(r) * k;
+  double* u = A.u;
+  const int64_t N = A.N;
+  const int nr = A.nrhs;
   if (A.op <= 1) {
-    gemv_cols(T, k, r, r, rd, sk, A.u, A.N, A.nrhs, -1.0);  // u_r -= T^T u_s
+    if (k > 0) gemv_cols(T, k, r, r, rd, sk, u, N, nr, -1.0);  // u_r -= T^T u_s
     __syncthreads();
-    if (A.op == 0)
-      gemv_rows(E, k, r, r, sk, rd, A.u, A.N, A.nrhs, -1.0);  // u_s -= E u_r
-    else
-      gemv_cols(Gm, r, k, k, sk, rd, A.u, A.N, A.nrhs, -1.0);  // u_s -= G^T u_r
+    if (A.op == 0) {
+      swaps_fwd(piv, r, rd, u, N, nr);
+      solve_L(LU, r, rd, u, N, nr);
+      if (k > 0) gemv_rows(Lsr, k, r, r, sk, rd, u, N, nr, -1.0);  // u_s -= L_sr u_r
+    } else {
+      solve_UT(LU, r, rd, u, N, nr);
+      if (k > 0) gemv_cols(Urs, r, k, k, sk, rd, u, N, nr, -1.0);  // u_s -= U_rs^T u_r
+    }
   } else {
-    gemv_rows(T, k, r, r, sk, rd, A.u, A.N, A.nrhs, 1.0);  // x_s += T x_r
+    if (k > 0) gemv_rows(T, k, r, r, sk, rd, u, N, nr, 1.0);  // x_s += T x_r
     __syncthreads();
-    if (A.op == 2)
-      gemv_rows(Gm, r, k, k, rd, sk, A.u, A.N, A.nrhs, 1.0);  // x_r += G x_s
-    else
-      gemv_cols(E, k, r, r, rd, sk, A.u, A.N, A.nrhs, 1.0);  // x_r += E^T x_s
+    if (A.op == 2) {
+      tri_mul(LU, r, rd, u, A.work, N, nr, 0);                     // x_r = U x_r
+      if (k > 0) gemv_rows(Urs, r, k, k, rd, sk, u, N, nr, 1.0);   //      + U_rs x_s
+    } else {
+      swaps_fwd(piv, r, rd, u, N, nr);
+      tri_mul(LU, r, rd, u, A.work, N, nr, 2);                     // x_r = L^T P x_r
+      if (k > 0) gemv_cols(Lsr, k, r, r, rd, sk, u, N, nr, 1.0);   //      + L_sr^T x_s
+    }
   }
 }
 
@@ -88,24 +213,38 @@ __global__ void k_down(SwArgs A) {
   const int r = R.r, k = R.k;
   const int32_t* rd = A.iarena + R.idx;
   const int32_t* sk = rd + r;
+  const int32_t* piv = sk + k;
   const double* T = A.darena + R.off;
-  const double* E = T + int64_t(k) * r;
-  const double* Gm = E + int64_t(k) * r;
-  if (k == 0) return;
+  const double* Lsr = T + int64_t(k) * r;
+  const double* Urs = Lsr + int64_t(k) * r;
+  const double* LU = Urs + int64_t(r) * k;
+  double* u = A.u;
+  const int64_t N = A.N;
+  const int nr = A.nrhs;
   if (A.op <= 1) {
-    if (A.op == 0)
-      gemv_rows(Gm, r, k, k, rd, sk, A.u, A.N, A.nrhs, -1.0);  // u_r -= G u_s
-    else
-      gemv_cols(E, k, r, r, rd, sk, A.u, A.N, A.nrhs, -1.0);  // u_r -= E^T u_s
-    __syncthreads();
-    gemv_rows(T, k, r, r, sk, rd, A.u, A.N, A.nrhs, -1.0);  // u_s -= T u_r
+    if (A.op == 0) {
+      if (k > 0) gemv_rows(Urs, r, k, k, rd, sk, u, N, nr, -1.0);  // u_r -= U_rs u_s
+      __syncthreads();
+      solve_U(LU, r, rd, u, N, nr);
+    } else {
+      if (k > 0) gemv_cols(Lsr, k, r, r, rd, sk, u, N, nr, -1.0);  // u_r -= L_sr^T u_s
+      __syncthreads();
+      solve_LT(LU, r, rd, u, N, nr);
+      swaps_rev(piv, r, rd, u, N, nr);
+    }
+    if (k > 0) gemv_rows(T, k, r, r, sk, rd, u, N, nr, -1.0);  // u_s -= T u_r
   } else {
-    if (A.op == 2)
-      gemv_rows(E, k, r, r, sk, rd, A.u, A.N, A.nrhs, 1.0);  // y_s += E y_r
-    else
-      gemv_cols(Gm, r, k, k, sk, rd, A.u, A.N, A.nrhs, 1.0);  // y_s += G^T y_r
-    __syncthreads();
-    gemv_cols(T, k, r, r, rd, sk, A.u, A.N, A.nrhs, 1.0);  // y_r += T^T y_s
+    if (A.op == 2) {
+      if (k > 0) gemv_rows(Lsr, k, r, r, sk, rd, u, N, nr, 1.0);  // y_s += L_sr y_r
+      __syncthreads();
+      tri_mul(LU, r, rd, u, A.work, N, nr, 1);                    // y_r = P^T L y_r
+      swaps_rev(piv, r, rd, u, N, nr);
+    } else {
+      if (k > 0) gemv_cols(Urs, r, k, k, sk, rd, u, N, nr, 1.0);  // y_s += U_rs^T y_r
+      __syncthreads();
+      tri_mul(LU, r, rd, u, A.work, N, nr, 3);                    // y_r = U^T y_r
+    }
+    if (k > 0) gemv_cols(T, k, r, r, rd, sk, u, N, nr, 1.0);  // y_r += T^T y_s
   }
 }
 
@@ -205,15 +344,6 @@ __device__ void lu_op(const double* LU, const int32_t* piv, int n, const int32_t
   }
 }
 
-__global__ void k_mid(SwArgs A) {
-  const GroupRec R = A.recs[blockIdx.x];
-  const int r = R.r, k = R.k;
-  const int32_t* rd = A.iarena + R.idx;
-  const int32_t* piv = rd + r + k;
-  const double* LU = A.darena + R.off + 3 * int64_t(k) * r;
-  lu_op(LU, piv, r, rd, A.u, A.work, A.N, A.nrhs, A.op);
-}
-
 __global__ void k_top(const double* LU, const int32_t* piv, int n, const int32_t* idx, double* u, double* work,
                       int64_t N, int nrhs, int op) {
   lu_op(LU, piv, n, idx, u, work, N, nrhs, op);
@@ -235,20 +365,15 @@ void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrh
     hipLaunchKernelGGL(k_copy, dim3(unsigned(blocks)), dim3(256), 0, s, x, y, tot);
     HIF_HIP(hipGetLastError());
   }
-  if (op >= 2) H->work.ensure(tot, &H->mem);
+  H->work.ensure(tot, &H->mem);
   for (int64_t v0 = 0; v0 < nrhs; v0 += 8) {
     const int nv = int(std::min<int64_t>(8, nrhs - v0));
     double* u = y + v0 * N;
-    double* wk = op >= 2 ? H->work.p + v0 * N : nullptr;
+    double* wk = H->work.p + v0 * N;
     for (auto& sub : H->subs) {
       if (sub.nrec == 0) continue;
       SwArgs A{sub.rec.p, sub.iarena.p, sub.darena.p, u, wk, N, nv, op};
       hipLaunchKernelGGL(k_up, dim3(sub.nrec), dim3(kBlock), 0, s, A);
-    }
-    for (auto& sub : H->subs) {
-      if (sub.nrec == 0) continue;
-      SwArgs A{sub.rec.p, sub.iarena.p, sub.darena.p, u, wk, N, nv, op};
-      hipLaunchKernelGGL(k_mid, dim3(sub.nrec), dim3(kBlock), 0, s, A);
     }
     if (H->ntop > 0)
       hipLaunchKernelGGL(k_top, dim3(1), dim3(1024), 0, s, H->top_lu.p, H->top_piv.p, int(H->ntop), H->top_idx.p, u,
