@@ -108,6 +108,11 @@ struct SubLevel {
   int kind = 0;  // 0 cell, 1 face, 2 edge
   int nrec = 0;
   int max_r = 0, max_k = 0;
+  int max_2rk = 0;  // max over records of 2r + k (LDS need of the staged sweeps, per RHS)
+  // Record layout: iarena + idx = [rd (r) | sk (k) | piv (r) | perm (r)], where
+  // piv are the LU row interchanges and perm the same permutation as a gather
+  // index, (P x)[i] = x[perm[i]]; darena + off = [T (k x r) | L_sr (k x r) |
+  // U_rs (r x k) | LU (r x r)], row-major.
   std::vector<GroupRec> hrec;
   DBuf<GroupRec> rec;
   DBuf<int32_t> iarena;
@@ -132,7 +137,7 @@ struct hif_factor_s {
   // Factors.
   std::vector<hif::SubLevel> subs;
   int64_t ntop = 0;
-  hif::DBuf<int32_t> top_idx, top_piv;
+  hif::DBuf<int32_t> top_idx, top_piv, top_perm;
   hif::DBuf<double> top_lu;
   // Sweep scratch.
   hif::DBuf<double> work;
@@ -210,6 +215,10 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, size_t n, hipStream_t s
 // Factorization driver (factor.hip).
 void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* k, const double* a,
                  const double* b, const double* c, hipStream_t s);
+
+// Gather form of the LU row interchanges of every record (sweep.hip).
+void launch_make_perm(const GroupRec* recs, int nrec, int32_t* iarena, int max_r, hipStream_t s);
+void launch_make_perm_top(const int32_t* piv, int32_t* perm, int n, hipStream_t s);
 
 // Sweeps (sweep.hip): op 0 solve, 1 solve_T, 2 apply, 3 apply_T.
 void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s);

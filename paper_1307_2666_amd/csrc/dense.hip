@@ -67,14 +67,101 @@ __device__ int block_excl_scan(int flag, int* total) {
 
 // ---------------------------------------------------------------------------
 // Assembly (eqn proxy-id, Section 3.3; SCI-expanded near field, Section 4.3).
-// Thread t owns columns t, t+B, ...; each column is filled top to bottom so
-// consecutive threads write consecutive addresses of a row.
+// Pass 1 fills the kernel entries: workgroup (x, g) owns rows
+// [64x, 64x + 64) of the stacked block [Y_c; A_cc] of group g, and thread t
+// columns t, t + 256, ... so that consecutive threads write consecutive
+// addresses of a row.  Pass 2 (one thread per column) sums the squared
+// kernel part of each column of Y_c in row order and then adds the SCI
+// entries, so the results do not depend on the launch shape.
 // ---------------------------------------------------------------------------
+constexpr int kAsmRows = 64;
+constexpr int kAsmThreads = 256;
+
 template <int D>
-__global__ void k_assemble(AsmArgs A) {
-  const int g = blockIdx.x;
+__global__ __launch_bounds__(kAsmThreads) void k_asm_fill(AsmArgs A) {
+  const int g = blockIdx.y;
   const int64_t c0 = A.gstart[g];
   const int n = int(A.gstart[g + 1] - c0);
+  const int64_t f0 = A.nf_start[g];
+  const int nf = int(A.nf_start[g + 1] - f0);
+  const int P = A.nproxy;
+  const int m = A.sym ? nf + P : 2 * nf + 2 * P;
+  const int r0 = blockIdx.x * kAsmRows;
+  if (r0 >= m + n) return;
+  const int r1 = min(r0 + kAsmRows, m + n);
+  double* Y = A.Y + A.yoff[g];
+  double* Acc = A.Acc + A.aoff[g];
+  double* Scc = A.Scc + A.aoff[g];
+  const int32_t* cols = A.cord + c0;
+  const int32_t* nfi = A.nf_idx + f0;
+  const int roff = A.sym ? nf : 2 * nf;  // first proxy row
+
+  for (int r = r0; r < r1; ++r) {
+    // row description: source point x_i (or proxy point) and its factors
+    double xi[D];
+    int kind;  // 0 near-field kernel row, 1 transposed row block, 2 proxy, 3 proxy (row side), 4 A_cc
+    int i = -1;
+    if (r < nf) {
+      kind = 0;
+      i = nfi[r];
+    } else if (!A.sym && r < 2 * nf) {
+      kind = 1;
+      i = nfi[r - nf];
+    } else if (r < m) {
+      const int p = A.sym ? r - roff : (r - roff) % P;
+      kind = (A.sym || r - roff < P) ? 2 : 3;
+#pragma unroll
+      for (int k = 0; k < D; ++k) xi[k] = A.zc[int64_t(g) * D + k] + A.R * A.proxy_u[p * D + k];
+    } else {
+      kind = 4;
+      i = cols[r - m];
+    }
+    if (i >= 0) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) xi[k] = A.pts[int64_t(i) * D + k];
+    }
+    const double bi = i >= 0 ? A.b[i] : 0.0;
+    const double wci = i >= 0 ? A.w[i] * A.c[i] : 0.0;
+    for (int col = threadIdx.x; col < n; col += kAsmThreads) {
+      const int j = cols[col];
+      double r2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const double t = xi[k] - A.pts[int64_t(j) * D + k];
+        r2 += t * t;
+      }
+      if (kind == 4) {
+        double v;
+        if (i == j)
+          v = A.a[j] + A.b[j] * A.selfk[j] * A.c[j];
+        else
+          v = bi * green_r2<D>(r2) * A.w[j] * A.c[j];
+        const int rr = r - m;
+        Acc[int64_t(rr) * n + col] = v;
+        Scc[int64_t(rr) * n + col] = 0.0;
+      } else {
+        const double gk = green_r2<D>(r2);
+        double v;
+        if (kind == 0)
+          v = bi * gk * A.w[j] * A.c[j];       // b_i G w_j c_j
+        else if (kind == 1)
+          v = A.b[j] * gk * wci;               // b_j G w_i c_i
+        else if (kind == 2)
+          v = gk * A.w[j] * A.c[j];            // G(|x_p - x_j|) w_j c_j
+        else
+          v = A.b[j] * gk * A.w[j];            // b_j G(|x_p - x_j|) w_j
+        Y[int64_t(r) * n + col] = v;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_asm_finish(AsmArgs A) {
+  const int g = blockIdx.y;
+  const int64_t c0 = A.gstart[g];
+  const int n = int(A.gstart[g + 1] - c0);
+  const int col = blockIdx.x * 64 + threadIdx.x;
+  if (col >= n) return;
   const int64_t f0 = A.nf_start[g];
   const int nf = int(A.nf_start[g + 1] - f0);
   const int P = A.nproxy;
@@ -82,128 +169,53 @@ __global__ void k_assemble(AsmArgs A) {
   double* Y = A.Y + A.yoff[g];
   double* Acc = A.Acc + A.aoff[g];
   double* Scc = A.Scc + A.aoff[g];
-  const int32_t* cols = A.cord + c0;
   const int32_t* nfi = A.nf_idx + f0;
-  double z[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) z[k] = A.zc[int64_t(g) * D + k];
-
-  for (int col = threadIdx.x; col < n; col += blockDim.x) {
-    const int j = cols[col];
-    double xj[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) xj[k] = A.pts[int64_t(j) * D + k];
-    const double wcj = A.w[j] * A.c[j];
-    const double bj = A.b[j];
-    double k2 = 0.0;
-    // near-field kernel rows: b_i G(|x_i - x_j|) w_j c_j
-    for (int r = 0; r < nf; ++r) {
-      const int i = nfi[r];
-      double r2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        double t = A.pts[int64_t(i) * D + k] - xj[k];
-        r2 += t * t;
-      }
-      double v = A.b[i] * green_r2<D>(r2) * wcj;
-      Y[int64_t(r) * n + col] = v;
-      k2 += v * v;
-    }
-    int roff = nf;
-    if (!A.sym) {
-      // transposed row block A(c, c^N)^T: b_j G w_i c_i
-      for (int r = 0; r < nf; ++r) {
-        const int i = nfi[r];
-        double r2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          double t = A.pts[int64_t(i) * D + k] - xj[k];
-          r2 += t * t;
-        }
-        double v = bj * green_r2<D>(r2) * A.w[i] * A.c[i];
-        Y[int64_t(nf + r) * n + col] = v;
-        k2 += v * v;
-      }
-      roff = 2 * nf;
-    }
-    // proxy rows: G(|x_p - x_j|) w_j c_j  (and b_j G w_j for the row side)
-    for (int p = 0; p < P; ++p) {
-      double r2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        double xp = z[k] + A.R * A.proxy_u[p * D + k];
-        double t = xp - xj[k];
-        r2 += t * t;
-      }
-      const double gk = green_r2<D>(r2);
-      double v = gk * wcj;
-      Y[int64_t(roff + p) * n + col] = v;
-      k2 += v * v;
-      if (!A.sym) {
-        double v2 = bj * gk * A.w[j];
-        Y[int64_t(roff + P + p) * n + col] = v2;
-        k2 += v2 * v2;
-      }
-    }
-    // A_cc column: a_j delta + b_i K_ij c_j
-    for (int r = 0; r < n; ++r) {
-      const int i = cols[r];
-      double v;
-      if (i == j) {
-        v = A.a[j] + A.b[j] * A.selfk[j] * A.c[j];
-      } else {
-        double r2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          double t = A.pts[int64_t(i) * D + k] - xj[k];
-          r2 += t * t;
-        }
-        v = A.b[i] * green_r2<D>(r2) * wcj;
-      }
-      Acc[int64_t(r) * n + col] = v;
-      Scc[int64_t(r) * n + col] = 0.0;
-    }
-    // SCI part: row j of the store holds (j, i) with values (S_ji, S_ij).
-    double s2 = 0.0;
-    const int64_t e0 = A.srow[j], e1 = A.srow[j + 1];
-    for (int64_t e = e0; e < e1; ++e) {
-      const int i = int(A.skey[e] & 0xffffffffu);
-      const double2 sv = A.sval[e];
-      if (A.grp_of[i] == g) {
-        const int pr = A.pos_of[i];
-        Acc[int64_t(pr) * n + col] += sv.y;
-        Scc[int64_t(pr) * n + col] = sv.y;
-      } else {
-        // position of i in the (ascending) near-field list
-        int lo = 0, hi = nf;
-        while (lo < hi) {
-          int mid = (lo + hi) >> 1;
-          if (nfi[mid] < i) lo = mid + 1; else hi = mid;
-        }
-        if (lo < nf && nfi[lo] == i) {
-          double yk = Y[int64_t(lo) * n + col];
-          double yt = yk + sv.y;
-          Y[int64_t(lo) * n + col] = yt;
-          s2 += sv.y * sv.y;
-          if (!A.sym) {
-            double yk2 = Y[int64_t(nf + lo) * n + col];
-            Y[int64_t(nf + lo) * n + col] = yk2 + sv.x;
-            s2 += sv.x * sv.x;
-          }
-        }
-      }
-    }
-    A.colK2[c0 + col] = k2;
-    A.colS2[c0 + col] = s2;
+  const int j = A.cord[c0 + col];
+  double k2 = 0.0;
+  for (int r = 0; r < m; ++r) {
+    const double v = Y[int64_t(r) * n + col];
+    k2 += v * v;
   }
+  // SCI part: row j of the store holds (j, i) with values (S_ji, S_ij).
+  double s2 = 0.0;
+  const int64_t e0 = A.srow[j], e1 = A.srow[j + 1];
+  for (int64_t e = e0; e < e1; ++e) {
+    const int i = int(A.skey[e] & 0xffffffffu);
+    const double2 sv = A.sval[e];
+    if (A.grp_of[i] == g) {
+      const int pr = A.pos_of[i];
+      Acc[int64_t(pr) * n + col] += sv.y;
+      Scc[int64_t(pr) * n + col] = sv.y;
+    } else {
+      // position of i in the (ascending) near-field list
+      int lo = 0, hi = nf;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (nfi[mid] < i) lo = mid + 1; else hi = mid;
+      }
+      if (lo < nf && nfi[lo] == i) {
+        Y[int64_t(lo) * n + col] += sv.y;
+        s2 += sv.y * sv.y;
+        if (!A.sym) {
+          Y[int64_t(nf + lo) * n + col] += sv.x;
+          s2 += sv.x * sv.x;
+        }
+      }
+    }
+  }
+  A.colK2[c0 + col] = k2;
+  A.colS2[c0 + col] = s2;
 }
 
-void launch_assemble(const AsmArgs& A, int block, hipStream_t s) {
+void launch_assemble(const AsmArgs& A, hipStream_t s) {
   if (A.ngroups == 0) return;
+  const dim3 g1(unsigned((A.max_rows + kAsmRows - 1) / kAsmRows), unsigned(A.ngroups));
   if (A.dim == 2)
-    hipLaunchKernelGGL(k_assemble<2>, dim3(A.ngroups), dim3(block), 0, s, A);
+    hipLaunchKernelGGL(k_asm_fill<2>, g1, dim3(kAsmThreads), 0, s, A);
   else
-    hipLaunchKernelGGL(k_assemble<3>, dim3(A.ngroups), dim3(block), 0, s, A);
+    hipLaunchKernelGGL(k_asm_fill<3>, g1, dim3(kAsmThreads), 0, s, A);
+  const dim3 g2(unsigned((A.max_cols + 63) / 64), unsigned(A.ngroups));
+  hipLaunchKernelGGL(k_asm_finish, g2, dim3(64), 0, s, A);
   HIF_HIP(hipGetLastError());
 }
 

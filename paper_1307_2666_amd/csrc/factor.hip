@@ -820,7 +820,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   std::vector<int32_t> h_cls_first(G + 1, 0);
   std::vector<int64_t> h_yoff(G), h_aoff(G);
   int64_t ytot = 0, atot = 0;
-  int maxn = 1;
+  int maxn = 1, maxmn = 1;
   for (int g = 0; g < G; ++g) {
     h_cls_first[g + 1] = h_cls_first[g] + h_ncls[g];
     const int64_t n = h_gstart[g + 1] - h_gstart[g];
@@ -831,6 +831,7 @@ void Factorizer::sublevel(int lvl, int kind) {
     ytot += m * n;
     atot += n * n;
     maxn = std::max<int>(maxn, int(n));
+    maxmn = std::max<int>(maxmn, int(m + n));
   }
   const int NC = h_cls_first[G];
   st.sub_classes[si] = NC;
@@ -888,9 +889,9 @@ void Factorizer::sublevel(int lvl, int kind) {
   aa.srow = srow.p;
   aa.skey = skey.p;
   aa.sval = sval.p;
-  int ablock = 64;
-  while (ablock < maxn && ablock < 256) ablock *= 2;
-  launch_assemble(aa, ablock, s);
+  aa.max_rows = maxmn;
+  aa.max_cols = maxn;
+  launch_assemble(aa, s);
   cls_tol.ensure(NC, mt);
   cls_moff.ensure(NC, mt);
   cls_ld.ensure(NC, mt);
@@ -987,11 +988,12 @@ void Factorizer::sublevel(int lvl, int kind) {
       h_grec[g] = int32_t(sub.hrec.size());
       sub.hrec.push_back(R);
       rec_g.push_back(g);
-      itot += 2 * int64_t(rr) + kk;
+      itot += 3 * int64_t(rr) + kk;
       dtot += 3 * int64_t(kk) * rr + int64_t(rr) * rr;
       ntot_new += int64_t(kk) * kk;
       sub.max_r = std::max(sub.max_r, rr);
       sub.max_k = std::max(sub.max_k, kk);
+      sub.max_2rk = std::max(sub.max_2rk, 2 * rr + kk);
       const double r3 = rr, k3 = kk;
       elfl += 6.0 * r3 * r3 * k3 + 4.0 * k3 * k3 * r3 + 2.0 / 3.0 * r3 * r3 * r3 + 4.0 * r3 * r3 * k3 + 2.0 * k3 * k3 * r3;
     }
@@ -1110,6 +1112,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   } else {
     launch_eliminate(ea, s);
   }
+  if (sub.nrec > 0) launch_make_perm(sub.rec.p, sub.nrec, sub.iarena.p, sub.max_r, s);
   tm.mark(PH_ELIM);
 
   // ---- SCI store update, active set ----------------------------------------
@@ -1176,6 +1179,7 @@ void Factorizer::top() {
   const int64_t n = nact;
   H->top_idx.alloc(n, mt);
   H->top_piv.alloc(n, mt);
+  H->top_perm.alloc(n, mt);
   H->top_lu.alloc(n * n, mt);
   if (n > 0) {
     HIF_HIP(hipMemcpyAsync(H->top_idx.p, act.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
@@ -1221,6 +1225,7 @@ void Factorizer::top() {
       launch_lu_batched(lb, int(n), int(n), s);
       HIF_HIP(hipStreamSynchronize(s));
     }
+    launch_make_perm_top(H->top_piv.p, H->top_perm.p, int(n), s);
   }
   tm.mark(PH_TOP);
   tm.flush(H->stats.t_phase_ms);

@@ -10,6 +10,7 @@ namespace hif {
 // block Y'_c of Section 5 when symmetric) and of A_cc, one workgroup per group.
 struct AsmArgs {
   int dim = 2, sym = 1, nproxy = 64, ngroups = 0;
+  int max_rows = 0, max_cols = 0;  // max over groups of rows(Y_c) + n_c, and of n_c
   double R = 0;                 // absolute proxy radius of this sub-level
   const double *pts, *a, *b, *c, *w, *selfk;
   const double* proxy_u;        // [nproxy][dim] unit directions
@@ -28,7 +29,7 @@ struct AsmArgs {
   const uint64_t* skey;         // (i << 32 | j)
   const double2* sval;          // (S_ij, S_ji)
 };
-void launch_assemble(const AsmArgs& A, int block, hipStream_t s);
+void launch_assemble(const AsmArgs& A, hipStream_t s);
 
 // Batched interpolative decomposition by column-pivoted Householder QR
 // (Lemma 2.2, Section 2.2), one workgroup per problem, in place.

@@ -349,12 +349,359 @@ __global__ void k_top(const double* LU, const int32_t* piv, int n, const int32_t
   lu_op(LU, piv, n, idx, u, work, N, nrhs, op);
 }
 
+// ---------------------------------------------------------------------------
+// LDS-staged solve / solve_T.  The entries u_r, u_s of a group (or the top
+// block's entries) are gathered into LDS once; the products and the blocked
+// triangular solves (64-column diagonal blocks solved by one wave with
+// shuffles, then one update of the remaining rows) run there, and the results
+// are scattered back.  The row interchanges use the gather index perm,
+// (P x)[i] = x[perm[i]].
+// ---------------------------------------------------------------------------
+constexpr int kNbT = 64;
+constexpr int kMaxV = 8;       // right-hand sides per pass
+constexpr int kCapS = 4096;    // LDS doubles, small groups
+constexpr int kCapL = 16384;   // LDS doubles, large groups and the top block
+
+// y[v*ys + i] += sgn * sum_j M[i*ld + j] x[v*xs + j]   (one wave per row)
+__device__ void l_gemv_n(const double* __restrict__ M, int nrow, int ncol, int ld, const double* x, int xs, double* y,
+                         int ys, int nv, double sgn) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = wv; i < nrow; i += nw) {
+    const double* mr = M + int64_t(i) * ld;
+    double acc[kMaxV];
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+    for (int j = lane; j < ncol; j += 64) {
+      const double mv = mr[j];
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v)
+        if (v < nv) acc[v] += mv * x[v * xs + j];
+    }
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv) {
+        const double t = wave_sum(acc[v]);
+        if (lane == 0) y[v * ys + i] += sgn * t;
+      }
+  }
+}
+
+// y[v*ys + j] += sgn * sum_i M[i*ld + j] x[v*xs + i]   (one thread per column)
+__device__ void l_gemv_t(const double* __restrict__ M, int nrow, int ncol, int ld, const double* x, int xs, double* y,
+                         int ys, int nv, double sgn) {
+  for (int j = threadIdx.x; j < ncol; j += blockDim.x) {
+    double acc[kMaxV];
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+    for (int i = 0; i < nrow; ++i) {
+      const double mv = M[int64_t(i) * ld + j];
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v)
+        if (v < nv) acc[v] += mv * x[v * xs + i];
+    }
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv) y[v * ys + j] += sgn * acc[v];
+  }
+}
+
+// x = L^{-1} x, L the unit lower triangle of the row-major n x n LU.
+__device__ void l_solve_L(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  for (int j0 = 0; j0 < n; j0 += kNbT) {
+    const int nb = min(kNbT, n - j0);
+    const double* Lr = LU + int64_t(j0 + min(lane, nb - 1)) * n + j0;
+    for (int v = wv; v < nv; v += nw) {
+      double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
+      for (int c = 0; c < nb - 1; ++c) {
+        const double xc = __shfl(xi, c, 64);
+        if (lane > c && lane < nb) xi -= Lr[c] * xc;
+      }
+      if (lane < nb) x[v * xs + j0 + lane] = xi;
+    }
+    __syncthreads();
+    for (int i = j0 + nb + tid; i < n; i += blockDim.x) {
+      const double* row = LU + int64_t(i) * n + j0;
+      double acc[kMaxV];
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+      for (int c = 0; c < nb; ++c) {
+        const double l = row[c];
+#pragma unroll
+        for (int v = 0; v < kMaxV; ++v)
+          if (v < nv) acc[v] += l * x[v * xs + j0 + c];
+      }
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v)
+        if (v < nv) x[v * xs + i] -= acc[v];
+    }
+    __syncthreads();
+  }
+}
+
+// x = U^{-1} x, U the upper triangle of the LU.
+__device__ void l_solve_U(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  if (n <= 0) return;
+  for (int j0 = ((n - 1) / kNbT) * kNbT; j0 >= 0; j0 -= kNbT) {
+    const int nb = min(kNbT, n - j0);
+    const double* Ur = LU + int64_t(j0 + min(lane, nb - 1)) * n + j0;
+    for (int v = wv; v < nv; v += nw) {
+      double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
+      for (int c = nb - 1; c >= 0; --c) {
+        if (lane == c) xi = xi / Ur[c];
+        const double xc = __shfl(xi, c, 64);
+        if (lane < c) xi -= Ur[c] * xc;
+      }
+      if (lane < nb) x[v * xs + j0 + lane] = xi;
+    }
+    __syncthreads();
+    for (int i = tid; i < j0; i += blockDim.x) {
+      const double* row = LU + int64_t(i) * n + j0;
+      double acc[kMaxV];
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+      for (int c = 0; c < nb; ++c) {
+        const double u = row[c];
+#pragma unroll
+        for (int v = 0; v < kMaxV; ++v)
+          if (v < nv) acc[v] += u * x[v * xs + j0 + c];
+      }
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v)
+        if (v < nv) x[v * xs + i] -= acc[v];
+    }
+    __syncthreads();
+  }
+}
+
+// x = U^{-T} x (U^T lower with diagonal U_jj), forward over column blocks.
+__device__ void l_solve_UT(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  for (int j0 = 0; j0 < n; j0 += kNbT) {
+    const int nb = min(kNbT, n - j0);
+    const int cl = j0 + min(lane, nb - 1);
+    for (int v = wv; v < nv; v += nw) {
+      double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
+      for (int c = 0; c < nb; ++c) {
+        const double* Uc = LU + int64_t(j0 + c) * n;
+        if (lane == c) xi = xi / Uc[j0 + c];
+        const double xc = __shfl(xi, c, 64);
+        if (lane > c && lane < nb) xi -= Uc[cl] * xc;
+      }
+      if (lane < nb) x[v * xs + j0 + lane] = xi;
+    }
+    __syncthreads();
+    for (int i = j0 + nb + tid; i < n; i += blockDim.x) {
+      double acc[kMaxV];
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+      for (int c = 0; c < nb; ++c) {
+        const double u = LU[int64_t(j0 + c) * n + i];
+#pragma unroll
+        for (int v = 0; v < kMaxV; ++v)
+          if (v < nv) acc[v] += u * x[v * xs + j0 + c];
+      }
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v)
+        if (v < nv) x[v * xs + i] -= acc[v];
+    }
+    __syncthreads();
+  }
+}
+
+// x = L^{-T} x (L^T unit upper), backward over column blocks.
+__device__ void l_solve_LT(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  if (n <= 0) return;
+  for (int j0 = ((n - 1) / kNbT) * kNbT; j0 >= 0; j0 -= kNbT) {
+    const int nb = min(kNbT, n - j0);
+    const int cl = j0 + min(lane, nb - 1);
+    for (int v = wv; v < nv; v += nw) {
+      double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
+      for (int c = nb - 1; c > 0; --c) {
+        const double xc = __shfl(xi, c, 64);
+        if (lane < c) xi -= LU[int64_t(j0 + c) * n + cl] * xc;
+      }
+      if (lane < nb) x[v * xs + j0 + lane] = xi;
+    }
+    __syncthreads();
+    for (int i = tid; i < j0; i += blockDim.x) {
+      double acc[kMaxV];
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+      for (int c = 0; c < nb; ++c) {
+        const double l = LU[int64_t(j0 + c) * n + i];
+#pragma unroll
+        for (int v = 0; v < kMaxV; ++v)
+          if (v < nv) acc[v] += l * x[v * xs + j0 + c];
+      }
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v)
+        if (v < nv) x[v * xs + i] -= acc[v];
+    }
+    __syncthreads();
+  }
+}
+
+// x = P x (fwd) or P^T x through the scratch tp, both [nv][n] in LDS.
+__device__ void l_permute(const int32_t* perm, int n, double* x, double* tp, int nv, bool fwd) {
+  for (int e = threadIdx.x; e < nv * n; e += blockDim.x) {
+    const int v = e / n, i = e % n;
+    if (fwd)
+      tp[e] = x[v * n + perm[i]];
+    else
+      tp[v * n + perm[i]] = x[e];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nv * n; e += blockDim.x) x[e] = tp[e];
+  __syncthreads();
+}
+
+// One group per workgroup; op 0 solve, 1 solve_T; down = 0 for the upward
+// sweep (finest sub-level first), 1 for the downward one.  The caller
+// guarantees 2r + k <= CAP.
+template <int CAP>
+__global__ __launch_bounds__(kBlock) void k_sweep_lds(SwArgs A, int down) {
+  __shared__ double sm[CAP];
+  const GroupRec R = A.recs[blockIdx.x];
+  const int r = R.r, k = R.k;
+  const int32_t* rd = A.iarena + R.idx;
+  const int32_t* sk = rd + r;
+  const int32_t* perm = sk + k + r;
+  const double* T = A.darena + R.off;
+  const double* Lsr = T + int64_t(k) * r;
+  const double* Urs = Lsr + int64_t(k) * r;
+  const double* LU = Urs + int64_t(r) * k;
+  const int64_t N = A.N;
+  const int tid = threadIdx.x;
+  const int nvb = max(1, min(A.nrhs, CAP / (2 * r + k)));
+  for (int v0 = 0; v0 < A.nrhs; v0 += nvb) {
+    const int nv = min(nvb, A.nrhs - v0);
+    double* xr = sm;           // [nv][r]
+    double* xs = sm + nv * r;  // [nv][k]
+    double* tp = xs + nv * k;  // [nv][r]
+    double* u = A.u + v0 * N;
+    for (int e = tid; e < nv * r; e += kBlock) xr[e] = u[(e / r) * N + rd[e % r]];
+    for (int e = tid; e < nv * k; e += kBlock) xs[e] = u[(e / k) * N + sk[e % k]];
+    __syncthreads();
+    if (A.op == 0 && !down) {
+      if (k > 0) l_gemv_t(T, k, r, r, xs, k, xr, r, nv, -1.0);  // u_r -= T^T u_s
+      __syncthreads();
+      l_permute(perm, r, xr, tp, nv, true);                     // u_r = P u_r
+      l_solve_L(LU, r, xr, r, nv);                              // u_r = L^{-1} u_r
+      if (k > 0) l_gemv_n(Lsr, k, r, r, xr, r, xs, k, nv, -1.0);  // u_s -= L_sr u_r
+    } else if (A.op == 0) {
+      if (k > 0) l_gemv_n(Urs, r, k, k, xs, k, xr, r, nv, -1.0);  // u_r -= U_rs u_s
+      __syncthreads();
+      l_solve_U(LU, r, xr, r, nv);                                 // u_r = U^{-1} u_r
+      if (k > 0) l_gemv_n(T, k, r, r, xr, r, xs, k, nv, -1.0);    // u_s -= T u_r
+    } else if (!down) {
+      if (k > 0) l_gemv_t(T, k, r, r, xs, k, xr, r, nv, -1.0);    // u_r -= T^T u_s
+      __syncthreads();
+      l_solve_UT(LU, r, xr, r, nv);                                // u_r = U^{-T} u_r
+      if (k > 0) l_gemv_t(Urs, r, k, k, xr, r, xs, k, nv, -1.0);  // u_s -= U_rs^T u_r
+    } else {
+      if (k > 0) l_gemv_t(Lsr, k, r, r, xs, k, xr, r, nv, -1.0);  // u_r -= L_sr^T u_s
+      __syncthreads();
+      l_solve_LT(LU, r, xr, r, nv);                                // u_r = L^{-T} u_r
+      l_permute(perm, r, xr, tp, nv, false);                       // u_r = P^T u_r
+      if (k > 0) l_gemv_n(T, k, r, r, xr, r, xs, k, nv, -1.0);    // u_s -= T u_r
+    }
+    __syncthreads();
+    for (int e = tid; e < nv * r; e += kBlock) u[(e / r) * N + rd[e % r]] = xr[e];
+    for (int e = tid; e < nv * k; e += kBlock) u[(e / k) * N + sk[e % k]] = xs[e];
+    __syncthreads();
+  }
+}
+
+// Top block: x = A_L^{-1} x (op 0) or A_L^{-T} x (op 1); requires 2n <= kCapL.
+__global__ __launch_bounds__(1024) void k_top_lds(const double* LU, const int32_t* perm, int n, const int32_t* idx,
+                                                  double* u, int64_t N, int nrhs, int op) {
+  __shared__ double sm[kCapL];
+  const int tid = threadIdx.x, B = blockDim.x;
+  const int nvb = max(1, min(nrhs, kCapL / (2 * n)));
+  for (int v0 = 0; v0 < nrhs; v0 += nvb) {
+    const int nv = min(nvb, nrhs - v0);
+    double* x = sm;
+    double* tp = sm + nv * n;
+    double* uu = u + v0 * N;
+    for (int e = tid; e < nv * n; e += B) x[e] = uu[(e / n) * N + idx[e % n]];
+    __syncthreads();
+    if (op == 0) {
+      l_permute(perm, n, x, tp, nv, true);
+      l_solve_L(LU, n, x, n, nv);
+      l_solve_U(LU, n, x, n, nv);
+    } else {
+      l_solve_UT(LU, n, x, n, nv);
+      l_solve_LT(LU, n, x, n, nv);
+      l_permute(perm, n, x, tp, nv, false);
+    }
+    for (int e = tid; e < nv * n; e += B) uu[(e / n) * N + idx[e % n]] = x[e];
+    __syncthreads();
+  }
+}
+
+// Gather form of the row interchanges j <-> piv[j], j = 0..n-1 (in order).
+constexpr int kPermLds = 8192;
+__device__ void make_perm(const int32_t* piv, int32_t* perm, int n) {
+  __shared__ int32_t sp[kPermLds];
+  __shared__ int32_t spv[kPermLds];
+  if (n <= kPermLds) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      sp[i] = i;
+      spv[i] = piv[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int j = 0; j < n; ++j) {
+        const int p = spv[j];
+        const int t = sp[j];
+        sp[j] = sp[p];
+        sp[p] = t;
+      }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = sp[i];
+  } else {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = i;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int j = 0; j < n; ++j) {
+        const int p = piv[j];
+        const int t = perm[j];
+        perm[j] = perm[p];
+        perm[p] = t;
+      }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_make_perm(const GroupRec* recs, int32_t* iarena) {
+  const GroupRec R = recs[blockIdx.x];
+  int32_t* piv = iarena + R.idx + R.r + R.k;
+  make_perm(piv, piv + R.r, R.r);
+}
+
+__global__ __launch_bounds__(64) void k_make_perm_top(const int32_t* piv, int32_t* perm, int n) {
+  make_perm(piv, perm, n);
+}
+
 __global__ void k_copy(const double* x, double* y, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     y[i] = x[i];
 }
 
 }  // namespace
+
+void launch_make_perm(const GroupRec* recs, int nrec, int32_t* iarena, int max_r, hipStream_t s) {
+  (void)max_r;
+  hipLaunchKernelGGL(k_make_perm, dim3(nrec), dim3(64), 0, s, recs, iarena);
+  HIF_HIP(hipGetLastError());
+}
+
+void launch_make_perm_top(const int32_t* piv, int32_t* perm, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_make_perm_top, dim3(1), dim3(64), 0, s, piv, perm, n);
+  HIF_HIP(hipGetLastError());
+}
 
 void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s) {
   const int64_t N = H->n;
@@ -370,19 +717,30 @@ void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrh
     const int nv = int(std::min<int64_t>(8, nrhs - v0));
     double* u = y + v0 * N;
     double* wk = H->work.p + v0 * N;
-    for (auto& sub : H->subs) {
-      if (sub.nrec == 0) continue;
+    // solve / solve_T of a sub-level go through LDS when a group fits
+    auto sweep = [&](const SubLevel& sub, int down) {
       SwArgs A{sub.rec.p, sub.iarena.p, sub.darena.p, u, wk, N, nv, op};
-      hipLaunchKernelGGL(k_up, dim3(sub.nrec), dim3(kBlock), 0, s, A);
+      if (op <= 1 && int64_t(sub.max_2rk) * nv <= kCapS)
+        hipLaunchKernelGGL(k_sweep_lds<kCapS>, dim3(sub.nrec), dim3(kBlock), 0, s, A, down);
+      else if (op <= 1 && sub.max_2rk <= kCapL)
+        hipLaunchKernelGGL(k_sweep_lds<kCapL>, dim3(sub.nrec), dim3(kBlock), 0, s, A, down);
+      else if (down)
+        hipLaunchKernelGGL(k_down, dim3(sub.nrec), dim3(kBlock), 0, s, A);
+      else
+        hipLaunchKernelGGL(k_up, dim3(sub.nrec), dim3(kBlock), 0, s, A);
+    };
+    for (auto& sub : H->subs)
+      if (sub.nrec > 0) sweep(sub, 0);
+    if (H->ntop > 0) {
+      if (op <= 1 && 2 * H->ntop <= kCapL)
+        hipLaunchKernelGGL(k_top_lds, dim3(1), dim3(1024), 0, s, H->top_lu.p, H->top_perm.p, int(H->ntop),
+                           H->top_idx.p, u, N, nv, op);
+      else
+        hipLaunchKernelGGL(k_top, dim3(1), dim3(1024), 0, s, H->top_lu.p, H->top_piv.p, int(H->ntop), H->top_idx.p,
+                           u, wk, N, nv, op);
     }
-    if (H->ntop > 0)
-      hipLaunchKernelGGL(k_top, dim3(1), dim3(1024), 0, s, H->top_lu.p, H->top_piv.p, int(H->ntop), H->top_idx.p, u,
-                         wk, N, nv, op);
-    for (auto it = H->subs.rbegin(); it != H->subs.rend(); ++it) {
-      if (it->nrec == 0) continue;
-      SwArgs A{it->rec.p, it->iarena.p, it->darena.p, u, wk, N, nv, op};
-      hipLaunchKernelGGL(k_down, dim3(it->nrec), dim3(kBlock), 0, s, A);
-    }
+    for (auto it = H->subs.rbegin(); it != H->subs.rend(); ++it)
+      if (it->nrec > 0) sweep(*it, 1);
     HIF_HIP(hipGetLastError());
   }
 }
