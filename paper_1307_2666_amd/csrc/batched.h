@@ -6,10 +6,39 @@
 
 namespace hif {
 
-// Row compression problems (same fields as RowQrArgs); scratch per problem:
-// V (m x 16) followed by T (16 x 16).
+// Row compression problems (same fields as RowQrArgs).
 using QrBatch = RowQrArgs;
-void launch_qr_batched(const QrBatch& A, int max_cols, hipStream_t s);
+// Few large problems: max_rows/max_cols bound rows/cols over the batch.
+void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t s);
+
+// Communication-avoiding panels of the row compression: panel width, rows per
+// chunk (one per thread) and the largest stack of chunk R factors.
+constexpr int kTsqrNb = 32;
+constexpr int kTsqrRows = 256;
+constexpr int kTsqrStack = 1024;
+__host__ __device__ inline int tsqr_chunks(int mp) { return (mp + kTsqrRows - 1) / kTsqrRows; }
+// Scratch of one problem with m rows (doubles): V (m x nb) | T per chunk |
+// stacked R | stacked V | stack T.
+struct TsqrLayout {
+  int64_t V, Tc, S, Vs, Ts, total;
+};
+__host__ __device__ inline TsqrLayout tsqr_layout(int m) {
+  const int64_t nm = tsqr_chunks(m), b2 = int64_t(kTsqrNb) * kTsqrNb;
+  TsqrLayout L;
+  L.V = 0;
+  L.Tc = int64_t(m) * kTsqrNb;
+  L.S = L.Tc + nm * b2;
+  L.Vs = L.S + nm * b2;
+  L.Ts = L.Vs + nm * b2;
+  L.total = L.Ts + b2;
+  return L;
+}
+// Scratch doubles every row-compression path needs for an m x n problem (m > n).
+inline int64_t rowqr_scratch(int64_t m, int64_t n) {
+  const int64_t fused = m * 16 + 16 * n + 256;
+  const int64_t tsqr = tsqr_layout(int(m)).total;
+  return fused > tsqr ? fused : tsqr;
+}
 
 // Partial LU problems: n x n row-major blocks (leading dimension n) factored
 // over their first r columns with pivots among rows < r.

@@ -289,6 +289,329 @@ __global__ void k_qr_clear_lower(QrBatch A) {
 }
 
 // ---------------------------------------------------------------------------
+// Communication-avoiding row compression (TSQR panels).  Panel j0 (columns
+// j0..j0+jb-1, rows j0..m-1) is split into nck balanced chunks of at most
+// kTsqrRows rows.  Each chunk is factored by its own workgroup (one row per
+// thread, in registers); with nck > 1 the chunk R factors are stacked and the
+// stack is factored again.  The trailing columns are then updated chunk by
+// chunk with the chunk's compact WY form, and the chunk top rows with the
+// stack's.  The final R rows of the panel land in rows j0..j0+jb-1; all that
+// later steps read is R (the orthogonal factor is never formed).
+// ---------------------------------------------------------------------------
+constexpr int kTb = kTsqrNb;
+
+struct PanelGeom {
+  int mp, jb, nck;
+};
+__device__ __forceinline__ PanelGeom panel_geom(int m, int n, int j0) {
+  PanelGeom g;
+  g.mp = m - j0;
+  g.jb = min(kTb, n - j0);
+  g.nck = tsqr_chunks(g.mp);
+  return g;
+}
+__device__ __forceinline__ int chunk_lo(int c, int mp, int nck) { return (c * mp) / nck; }
+
+__device__ __forceinline__ double pick(const double (&y)[kTb], int j) {
+  double r = 0.0;
+#pragma unroll
+  for (int c = 0; c < kTb; ++c)
+    if (c == j) r = y[c];
+  return r;
+}
+
+// Sum of p[c] over the 64 lanes for all kTb = 32 indices at once
+// (reduce-scatter: at each step a lane keeps one half of its values, sends the
+// other half to its partner and adds what it receives).  Returns the total of
+// index lane >> 1; p is destroyed.
+template <int H>
+__device__ __forceinline__ void rs_step(double (&p)[kTb], int lane) {
+  const bool up = (lane & (2 * H)) != 0;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const double send = up ? p[i] : p[i + H];
+    const double keep = up ? p[i + H] : p[i];
+    p[i] = keep + __shfl_xor(send, 2 * H, 64);
+  }
+}
+__device__ __forceinline__ double wave_rs32(double (&p)[kTb]) {
+  const int lane = threadIdx.x & 63;
+  rs_step<16>(p, lane);
+  rs_step<8>(p, lane);
+  rs_step<4>(p, lane);
+  rs_step<2>(p, lane);
+  rs_step<1>(p, lane);
+  return p[0] + __shfl_xor(p[0], 1, 64);
+}
+
+// Householder QR of a block of at most blockDim.x rows and jb <= kTb columns
+// held one row per thread (thread t: row t; rows past the block are zero).
+// One reduction round per column gives the norm of the column below the
+// diagonal and its products with the later columns.  On return rows t < jb
+// hold R (upper part) and rows t > jj hold the Householder vector of column
+// jj below the diagonal; v0 (its diagonal entry) and beta = 2 / v^T v are in
+// sv0 / sbeta.
+template <int NW>
+__device__ void rowblock_qr(double (&y)[kTb], int t, int jb, double* sred, double* srow, double* sfin, double* sv0,
+                            double* sbeta) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int jj = 0; jj < jb; ++jj) {
+    const int b = jj & 1;  // double-buffered so one barrier pair per column suffices
+    double* red = sred + b * NW * kTb;
+    double* row = srow + b * kTb;
+    double* fin = sfin + b * kTb;
+    const double yj = pick(y, jj);
+    if (t == jj) {
+#pragma unroll
+      for (int c = 0; c < kTb; ++c) row[c] = y[c];
+    }
+    double p[kTb];
+#pragma unroll
+    for (int c = 0; c < kTb; ++c) p[c] = (t > jj || (t == jj && c == jj)) ? yj * y[c] : 0.0;
+    const double w = wave_rs32(p);
+    if ((lane & 1) == 0) red[wv * kTb + (lane >> 1)] = w;
+    __syncthreads();
+    if (threadIdx.x < kTb) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s2 += red[w * kTb + threadIdx.x];
+      fin[threadIdx.x] = s2;
+    }
+    __syncthreads();
+    const double ss = fin[jj], x0 = row[jj];
+    const double nrm = sqrt(ss);
+    const double alpha = nrm > 0.0 ? -copysign(nrm, x0) : 0.0;
+    const double v0 = x0 - alpha;
+    const double vtv = ss - x0 * x0 + v0 * v0;
+    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    if (t >= jj) {
+      const double vt = t == jj ? v0 : yj;
+#pragma unroll
+      for (int c = 0; c < kTb; ++c)
+        if (c > jj && c < jb) y[c] -= beta * (v0 * row[c] + fin[c]) * vt;
+      if (t == jj) {
+#pragma unroll
+        for (int c = 0; c < kTb; ++c)
+          if (c == jj) y[c] = alpha;
+      }
+    }
+    if (threadIdx.x == 0) {
+      sv0[jj] = v0;
+      sbeta[jj] = beta;
+    }
+  }
+  __syncthreads();
+}
+
+// Row t of V (rows x kTb, zero above the diagonal and past column jb).
+__device__ __forceinline__ void store_vrow(const double (&y)[kTb], int t, int jb, const double* sv0, double* Vrow) {
+#pragma unroll
+  for (int c = 0; c < kTb; ++c) Vrow[c] = (c < jb && t > c) ? y[c] : ((c < jb && t == c) ? sv0[c] : 0.0);
+}
+
+// T of the compact WY form I - V T V^T (T upper triangular) from beta and
+// G = V^T V (matrix cores, 4 waves), V row-major rows x kTb in global memory.
+__device__ void build_T(const double* V, int rows, const double* sbeta, double* sG, double* sT, double* Tout) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  if (wv < 4) {
+    const int p0 = (wv >> 1) * 16, p1 = (wv & 1) * 16;
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < rows; kb += 32) {  // 8 steps of 4 rows, loads issued first
+      double a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int r = kb + 4 * u + lk;
+        a[u] = r < rows ? V[int64_t(r) * kTb + p0 + li] : 0.0;
+        b[u] = r < rows ? V[int64_t(r) * kTb + p1 + li] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = mfma_f64(a[u], b[u], acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sG[(p0 + 4 * v + lk) * (kTb + 1) + p1 + li] = acc[v];
+  }
+  __syncthreads();
+  for (int i = 0; i < kTb; ++i) {
+    const int p = threadIdx.x;
+    if (p < i) {
+      double acc = 0.0;
+      for (int l = p; l < i; ++l) acc += sT[p * kTb + l] * sG[l * (kTb + 1) + i];
+      sT[p * kTb + i] = -sbeta[i] * acc;
+    } else if (p < kTb) {
+      sT[p * kTb + i] = p == i ? sbeta[i] : 0.0;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < kTb * kTb; e += blockDim.x) Tout[e] = sT[e];
+}
+
+// K1: QR of one chunk of the panel.
+__global__ __launch_bounds__(kTsqrRows) void k_tsqr_chunk(QrBatch A, int j0) {
+  const int q = blockIdx.y, c = blockIdx.x;
+  const int m = A.rows[q], n = A.cols[q];
+  if (m <= n || j0 >= n) return;
+  const PanelGeom g = panel_geom(m, n, j0);
+  if (c >= g.nck) return;
+  const int lo = chunk_lo(c, g.mp, g.nck), rows = chunk_lo(c + 1, g.mp, g.nck) - lo;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  double* S0 = A.scratch + A.soff[q];
+  const TsqrLayout L = tsqr_layout(m);
+  const int t = threadIdx.x;
+  __shared__ double sred[2 * (kTsqrRows / 64) * kTb], srow[2 * kTb], sfin[2 * kTb], sv0[kTb], sbeta[kTb];
+  __shared__ double sG[kTb * (kTb + 1)], sT[kTb * kTb];
+  double y[kTb];
+  const double* src = M + int64_t(j0 + lo + (t < rows ? t : 0)) * ld + j0;
+#pragma unroll
+  for (int cc = 0; cc < kTb; ++cc) y[cc] = (t < rows && cc < g.jb) ? src[cc] : 0.0;
+  rowblock_qr<kTsqrRows / 64>(y, t, g.jb, sred, srow, sfin, sv0, sbeta);
+  double* V = S0 + L.V + int64_t(lo) * kTb;
+  if (t < rows) store_vrow(y, t, g.jb, sv0, V + int64_t(t) * kTb);
+  if (g.nck == 1) {
+    if (t < g.jb) {
+      double* dst = M + int64_t(j0 + t) * ld + j0;
+#pragma unroll
+      for (int cc = 0; cc < kTb; ++cc)
+        if (cc < g.jb) dst[cc] = cc >= t ? y[cc] : 0.0;
+    }
+  } else if (t < kTb) {
+    double* dst = S0 + L.S + int64_t(c * kTb + t) * kTb;
+#pragma unroll
+    for (int cc = 0; cc < kTb; ++cc) dst[cc] = (t < g.jb && cc >= t && cc < g.jb) ? y[cc] : 0.0;
+  }
+  __syncthreads();
+  build_T(V, rows, sbeta, sG, sT, S0 + L.Tc + int64_t(c) * kTb * kTb);
+}
+
+// K2: QR of the stacked chunk R factors (nck > 1); writes the panel's R.
+__global__ __launch_bounds__(kTsqrStack) void k_tsqr_stack(QrBatch A, int j0) {
+  const int q = blockIdx.x;
+  const int m = A.rows[q], n = A.cols[q];
+  if (m <= n || j0 >= n) return;
+  const PanelGeom g = panel_geom(m, n, j0);
+  if (g.nck < 2) return;
+  const int srows = g.nck * kTb;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  double* S0 = A.scratch + A.soff[q];
+  const TsqrLayout L = tsqr_layout(m);
+  const int t = threadIdx.x;
+  __shared__ double sred[2 * (kTsqrStack / 64) * kTb], srow[2 * kTb], sfin[2 * kTb], sv0[kTb], sbeta[kTb];
+  __shared__ double sG[kTb * (kTb + 1)], sT[kTb * kTb];
+  double y[kTb];
+  const double* src = S0 + L.S + int64_t(t < srows ? t : 0) * kTb;
+#pragma unroll
+  for (int cc = 0; cc < kTb; ++cc) y[cc] = t < srows ? src[cc] : 0.0;
+  rowblock_qr<kTsqrStack / 64>(y, t, g.jb, sred, srow, sfin, sv0, sbeta);
+  double* V = S0 + L.Vs;
+  if (t < srows) store_vrow(y, t, g.jb, sv0, V + int64_t(t) * kTb);
+  if (t < g.jb) {
+    double* dst = M + int64_t(j0 + t) * ld + j0;
+#pragma unroll
+    for (int cc = 0; cc < kTb; ++cc)
+      if (cc < g.jb) dst[cc] = cc >= t ? y[cc] : 0.0;
+  }
+  __syncthreads();
+  build_T(V, srows, sbeta, sG, sT, S0 + L.Ts);
+}
+
+// Y <- (I - V T V^T)^T Y for one 64-column tile: P = V^T Y, W = T^T P,
+// Y -= V W.  rowp(r) gives the address of row r of the tile.
+template <class RowP>
+__device__ void apply_wy_tile(const double* V, int rows, const double* Tm, RowP rowp, int nt, double* sP, double* sW) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  // 1. P (kTb x 64): 8 tiles of 16 x 16, K = rows
+  for (int tile = wv; tile < 8; tile += nw) {
+    const int p0 = (tile >> 2) * 16, ct = (tile & 3) * 16;
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < rows; kb += 32) {  // 8 steps of 4 rows, loads issued first
+      double a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int r = kb + 4 * u + lk;
+        const bool ok = r < rows;
+        a[u] = ok ? V[int64_t(r) * kTb + p0 + li] : 0.0;
+        b[u] = (ok && ct + li < nt) ? rowp(r)[ct + li] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = mfma_f64(a[u], b[u], acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sP[(p0 + 4 * v + lk) * 65 + ct + li] = acc[v];
+  }
+  __syncthreads();
+  // 2. W = T^T P, T upper triangular
+  for (int e = tid; e < kTb * 64; e += blockDim.x) {
+    const int i = e >> 6, c = e & 63;
+    double acc = 0.0;
+    for (int p = 0; p <= i; ++p) acc += Tm[p * kTb + i] * sP[p * 65 + c];
+    sW[i * 65 + c] = acc;
+  }
+  __syncthreads();
+  // 3. Y -= V W, 16 x 16 output tiles
+  const int ntr = (rows + 15) >> 4;
+  for (int tile = wv; tile < ntr * 4; tile += nw) {
+    const int rt = (tile >> 2) * 16, ct = (tile & 3) * 16;
+    double4_t d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < kTb; ks += 4) {
+      const int r = rt + li;
+      const double a = r < rows ? V[int64_t(r) * kTb + ks + lk] : 0.0;
+      d = mfma_f64(a, sW[(ks + lk) * 65 + ct + li], d);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = rt + 4 * v + lk, col = ct + li;
+      if (r < rows && col < nt) rowp(r)[col] -= d[v];
+    }
+  }
+}
+
+// K3: trailing update of chunk blockIdx.y, column tile blockIdx.x.
+__global__ __launch_bounds__(256) void k_tsqr_apply_chunk(QrBatch A, int j0) {
+  const int q = blockIdx.z, c = blockIdx.y;
+  const int m = A.rows[q], n = A.cols[q];
+  if (m <= n || j0 >= n) return;
+  const PanelGeom g = panel_geom(m, n, j0);
+  if (c >= g.nck) return;
+  const int c0 = j0 + g.jb + blockIdx.x * 64;
+  if (c0 >= n) return;
+  const int nt = min(64, n - c0);
+  const int lo = chunk_lo(c, g.mp, g.nck), rows = chunk_lo(c + 1, g.mp, g.nck) - lo;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const double* S0 = A.scratch + A.soff[q];
+  const TsqrLayout L = tsqr_layout(m);
+  __shared__ double sP[kTb * 65], sW[kTb * 65];
+  double* Y0 = M + int64_t(j0 + lo) * ld + c0;
+  apply_wy_tile(S0 + L.V + int64_t(lo) * kTb, rows, S0 + L.Tc + int64_t(c) * kTb * kTb,
+                [=](int r) { return Y0 + int64_t(r) * ld; }, nt, sP, sW);
+}
+
+// K4: trailing update of the chunk top rows with the stack's WY form.
+__global__ __launch_bounds__(256) void k_tsqr_apply_stack(QrBatch A, int j0) {
+  const int q = blockIdx.y;
+  const int m = A.rows[q], n = A.cols[q];
+  if (m <= n || j0 >= n) return;
+  const PanelGeom g = panel_geom(m, n, j0);
+  if (g.nck < 2) return;
+  const int c0 = j0 + g.jb + blockIdx.x * 64;
+  if (c0 >= n) return;
+  const int nt = min(64, n - c0);
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const double* S0 = A.scratch + A.soff[q];
+  const TsqrLayout L = tsqr_layout(m);
+  __shared__ double sP[kTb * 65], sW[kTb * 65];
+  const int mp = g.mp, nck = g.nck;
+  double* Mc = M + int64_t(j0) * ld + c0;
+  apply_wy_tile(S0 + L.Vs, nck * kTb, S0 + L.Ts,
+                [=](int r) { return Mc + int64_t(chunk_lo(r / kTb, mp, nck) + r % kTb) * ld; }, nt, sP, sW);
+}
+
+// ---------------------------------------------------------------------------
 // Partial LU (Lemma 2.1) of the n x n problems over their first r columns,
 // pivoting among rows < r: panel j0 = columns j0..j0+jb-1 with row swaps over
 // whole rows, then U12 = L11^{-1} A12 for the panel rows.
@@ -431,8 +754,25 @@ __global__ __launch_bounds__(256) void k_gemm_tiles(const GemmDesc* D, int nd) {
 
 }  // namespace
 
-void launch_qr_batched(const QrBatch& A, int max_cols, hipStream_t s) {
+void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t s) {
   if (A.nprob == 0) return;
+  if (tsqr_chunks(max_rows) * kTsqrNb <= kTsqrStack) {
+    const unsigned nckmax = unsigned(tsqr_chunks(max_rows));
+    for (int j0 = 0; j0 < max_cols; j0 += kTsqrNb) {
+      hipLaunchKernelGGL(k_tsqr_chunk, dim3(nckmax, A.nprob), dim3(kTsqrRows), 0, s, A, j0);
+      hipLaunchKernelGGL(k_tsqr_stack, dim3(A.nprob), dim3(kTsqrStack), 0, s, A, j0);
+      const int rem = max_cols - j0 - kTsqrNb;
+      if (rem > 0) {
+        const unsigned tiles = unsigned((rem + 63) / 64);
+        hipLaunchKernelGGL(k_tsqr_apply_chunk, dim3(tiles, nckmax, A.nprob), dim3(256), 0, s, A, j0);
+        hipLaunchKernelGGL(k_tsqr_apply_stack, dim3(tiles, A.nprob), dim3(256), 0, s, A, j0);
+      }
+    }
+    hipLaunchKernelGGL(k_qr_clear_lower, dim3(64, A.nprob), dim3(256), 0, s, A);
+    HIF_HIP(hipGetLastError());
+    return;
+  }
+  // taller problems: one workgroup per problem for the panel
   for (int j0 = 0; j0 < max_cols; j0 += kNb) {
     hipLaunchKernelGGL(k_qr_panel, dim3(A.nprob), dim3(kQpThreads), 0, s, A, j0);
     const int rem = max_cols - j0 - kNb;

@@ -172,9 +172,19 @@ __global__ __launch_bounds__(64) void k_asm_finish(AsmArgs A) {
   const int32_t* nfi = A.nf_idx + f0;
   const int j = A.cord[c0 + col];
   double k2 = 0.0;
-  for (int r = 0; r < m; ++r) {
-    const double v = Y[int64_t(r) * n + col];
-    k2 += v * v;
+  {
+    int r = 0;
+    for (; r + 8 <= m; r += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = Y[int64_t(r + u) * n + col];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) k2 += v[u] * v[u];
+    }
+    for (; r < m; ++r) {
+      const double v = Y[int64_t(r) * n + col];
+      k2 += v * v;
+    }
   }
   // SCI part: row j of the store holds (j, i) with values (S_ji, S_ij).
   double s2 = 0.0;
@@ -416,6 +426,18 @@ void launch_id(const IdArgs& A, int max_cols, hipStream_t s) {
 // ---------------------------------------------------------------------------
 constexpr int kRqNb = 16;
 
+// One step of a wave reduce-scatter of 16 values (see k_rowqr).
+template <int H>
+__device__ __forceinline__ void rs16_step(double (&p)[kRqNb], int lane) {
+  const bool up = (lane & (4 * H)) != 0;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const double send = up ? p[i] : p[i + H];
+    const double keep = up ? p[i + H] : p[i];
+    p[i] = keep + __shfl_xor(send, 4 * H, 64);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_rowqr(RowQrArgs A) {
   const int q = blockIdx.x;
   const int m = A.rows[q], n = A.cols[q];
@@ -481,11 +503,15 @@ __global__ __launch_bounds__(256) void k_rowqr(RowQrArgs A) {
           for (int c = 0; c < kRqNb; ++c) part[c] += vr[qq] * y[qq][c];
         }
       }
-#pragma unroll
-      for (int c = 0; c < kRqNb; ++c) {
-        if (c >= nc) break;
-        const double t = wave_sum(part[c]);
-        if (lane == 0) sred[wv][c] = t;
+      {
+        // all 16 sums at once: lane pairs reduce-scatter, lane l ends with index l >> 2
+        rs16_step<8>(part, lane);
+        rs16_step<4>(part, lane);
+        rs16_step<2>(part, lane);
+        rs16_step<1>(part, lane);
+        double t = part[0] + __shfl_xor(part[0], 1, 64);
+        t += __shfl_xor(t, 2, 64);
+        if ((lane & 3) == 0) sred[wv][lane >> 2] = t;
       }
       __syncthreads();
       double wc[kRqNb];
@@ -562,11 +588,11 @@ __global__ __launch_bounds__(256) void k_rowqr(RowQrArgs A) {
   }
 }
 
-void launch_rowqr_auto(const RowQrArgs& A, int max_cols, hipStream_t s) {
+void launch_rowqr_auto(const RowQrArgs& A, int max_rows, int max_cols, hipStream_t s) {
   // Few large problems: per-panel launches spread each problem over many
   // workgroups; many small ones: one fused workgroup per problem.
   if (A.nprob < 1024 && max_cols >= 96)
-    launch_qr_batched(A, max_cols, s);
+    launch_qr_batched(A, max_rows, max_cols, s);
   else
     launch_rowqr(A, s);
 }
@@ -663,11 +689,9 @@ __device__ ElimView elim_view(const ElimArgs& A, int g, const GroupRec& R) {
   return v;
 }
 
-// Skeleton / redundant lists in class order, T (k x r, block diagonal over
-// the classes) and M = A_cc in (redundant, skeleton) order.
-__device__ void elim_setup(const ElimArgs& A, int g, const ElimView& v) {
+// Skeleton / redundant lists in class order.
+__device__ void elim_lists(const ElimArgs& A, int g, const ElimView& v) {
   const int tid = threadIdx.x, B = blockDim.x;
-  const int r = v.r, k = v.k, n = v.n;
   for (int q = A.cls_first[g]; q < A.cls_first[g + 1]; ++q) {
     const int col0 = A.cls_col0[q], nq = A.cls_n[q], kq = A.cls_rank[q];
     const int so = A.cls_skoff[q], ro = A.cls_rdoff[q];
@@ -686,41 +710,53 @@ __device__ void elim_setup(const ElimArgs& A, int g, const ElimView& v) {
       }
     }
   }
-  __syncthreads();
-  for (int64_t e = tid; e < int64_t(k) * r; e += B) {
+}
+
+// T (k x r, block diagonal over the classes) and M = A_cc in (redundant,
+// skeleton) order; this workgroup does share `part` of `nparts`.
+__device__ void elim_gather(const ElimView& v, int part, int nparts) {
+  const int B = blockDim.x;
+  const int64_t e0 = int64_t(part) * B + threadIdx.x, es = int64_t(nparts) * B;
+  const int r = v.r, k = v.k, n = v.n;
+  for (int64_t e = e0; e < int64_t(k) * r; e += es) {
     const int a = int(e / r), bb = int(e % r);
     const int lo = v.rlo[bb];
     v.T[e] = (a >= lo && a < v.rhi[bb]) ? v.Y[int64_t(a - lo) * n + v.rdl[bb]] : 0.0;
   }
-  for (int64_t e = tid; e < int64_t(n) * n; e += B) {
+  for (int64_t e = e0; e < int64_t(n) * n; e += es) {
     const int i = int(e / n), j = int(e % n);
     v.M[e] = v.Acc[int64_t(v.rdl[i]) * n + v.rdl[j]];
   }
+}
+
+__device__ void elim_setup(const ElimArgs& A, int g, const ElimView& v) {
+  elim_lists(A, g, v);
+  __syncthreads();
+  elim_gather(v, 0, 1);
   __syncthreads();
 }
 
 // The skeleton block of M starts as the old SCI block S_old(s,s).
-__device__ void elim_sss(const ElimView& v) {
+__device__ void elim_sss(const ElimView& v, int part, int nparts) {
   const int n = v.n, r = v.r, k = v.k;
   double* Mss = v.M + int64_t(r) * n + r;
-  for (int64_t e = threadIdx.x; e < int64_t(k) * k; e += blockDim.x) {
+  for (int64_t e = int64_t(part) * blockDim.x + threadIdx.x; e < int64_t(k) * k; e += int64_t(nparts) * blockDim.x) {
     const int a = int(e / k), a2 = int(e % k);
     Mss[int64_t(a) * n + a2] = v.Scc[int64_t(v.skl[a]) * n + v.skl[a2]];
   }
-  __syncthreads();
 }
 
 // Factors into the record, the updated SCI block into the new entries.
-__device__ void elim_finish(const ElimArgs& A, int g, const ElimView& v) {
-  const int tid = threadIdx.x, B = blockDim.x;
+__device__ void elim_finish(const ElimArgs& A, int g, const ElimView& v, int part, int nparts) {
+  const int64_t e0 = int64_t(part) * blockDim.x + threadIdx.x, es = int64_t(nparts) * blockDim.x;
   const int n = v.n, r = v.r, k = v.k;
   const double* Mss = v.M + int64_t(r) * n + r;
-  for (int64_t e = tid; e < int64_t(r) * r; e += B) v.LU[e] = v.M[(e / r) * n + e % r];
-  for (int64_t e = tid; e < int64_t(r) * k; e += B) v.Urs[e] = v.M[(e / k) * n + r + e % k];
-  for (int64_t e = tid; e < int64_t(k) * r; e += B) v.Lsr[e] = v.M[(r + e / r) * n + e % r];
+  for (int64_t e = e0; e < int64_t(r) * r; e += es) v.LU[e] = v.M[(e / r) * n + e % r];
+  for (int64_t e = e0; e < int64_t(r) * k; e += es) v.Urs[e] = v.M[(e / k) * n + r + e % k];
+  for (int64_t e = e0; e < int64_t(k) * r; e += es) v.Lsr[e] = v.M[(r + e / r) * n + e % r];
   uint64_t* nk = A.newkey + A.newoff[g];
   double2* nv = A.newval + A.newoff[g];
-  for (int64_t e = tid; e < int64_t(k) * k; e += B) {
+  for (int64_t e = e0; e < int64_t(k) * k; e += es) {
     const int a = int(e / k), a2 = int(e % k);
     nk[e] = (uint64_t(uint32_t(v.sk[a])) << 32) | uint32_t(v.sk[a2]);
     nv[e] = make_double2(Mss[int64_t(a) * n + a2], Mss[int64_t(a2) * n + a]);
@@ -749,7 +785,8 @@ __global__ __launch_bounds__(256) void k_eliminate(ElimArgs A) {
     wg_gemm(k, r, k, -1.0, Mss, n, false, v.T, r, false, 1.0, Msr, n, lds);   // B_sr
     wg_gemm(r, r, k, -1.0, v.T, r, true, Msr, n, false, 1.0, Mrr, n, lds);    // B_rr
     wg_gemm(r, k, k, -1.0, v.T, r, true, Mss, n, false, 1.0, Mrs, n, lds);    // B_rs
-    elim_sss(v);
+    elim_sss(v, 0, 1);
+    __syncthreads();
   }
   // blocked partial LU over the first r columns
   for (int j0 = 0; j0 < r; j0 += kLuNb) {
@@ -794,49 +831,64 @@ __global__ __launch_bounds__(256) void k_eliminate(ElimArgs A) {
               false, 1.0, M + int64_t(j0 + jb) * n + j0 + jb, n, lds);
     }
   }
-  elim_finish(A, g, v);
+  elim_finish(A, g, v, 0, 1);
 }
 
 // Split path for sub-levels with few, large groups: setup, M_ss, finish as
 // kernels of their own; the transform and the partial LU run as batched
 // multi-workgroup launches in between.
-__global__ __launch_bounds__(256) void k_elim_setup(ElimArgs A) {
+__global__ __launch_bounds__(256) void k_elim_lists(ElimArgs A) {
   const int g = blockIdx.x;
   const int ri = A.grec[g];
   if (ri < 0) return;
   const GroupRec R = A.recs[ri];
-  elim_setup(A, g, elim_view(A, g, R));
+  elim_lists(A, g, elim_view(A, g, R));
+}
+
+__global__ __launch_bounds__(256) void k_elim_gather(ElimArgs A) {
+  const int g = blockIdx.y;
+  const int ri = A.grec[g];
+  if (ri < 0) return;
+  const GroupRec R = A.recs[ri];
+  elim_gather(elim_view(A, g, R), blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void k_elim_sss(ElimArgs A) {
-  const int g = blockIdx.x;
+  const int g = blockIdx.y;
   const int ri = A.grec[g];
   if (ri < 0) return;
   const GroupRec R = A.recs[ri];
-  if (R.k > 0) elim_sss(elim_view(A, g, R));
+  if (R.k > 0) elim_sss(elim_view(A, g, R), blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void k_elim_finish(ElimArgs A) {
-  const int g = blockIdx.x;
+  const int g = blockIdx.y;
   const int ri = A.grec[g];
   if (ri < 0) return;
   const GroupRec R = A.recs[ri];
-  elim_finish(A, g, elim_view(A, g, R));
+  elim_finish(A, g, elim_view(A, g, R), blockIdx.x, gridDim.x);
+}
+
+// Workgroups per group for the copy kernels: about 16K entries each.
+static unsigned elim_parts(const ElimArgs& A) {
+  const int64_t n = A.max_n;
+  return unsigned(std::min<int64_t>(256, std::max<int64_t>(1, n * n / 16384)));
 }
 
 void launch_elim_setup(const ElimArgs& A, hipStream_t s) {
   if (A.ngroups == 0) return;
-  hipLaunchKernelGGL(k_elim_setup, dim3(A.ngroups), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_elim_lists, dim3(A.ngroups), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_elim_gather, dim3(elim_parts(A), A.ngroups), dim3(256), 0, s, A);
   HIF_HIP(hipGetLastError());
 }
 void launch_elim_sss(const ElimArgs& A, hipStream_t s) {
   if (A.ngroups == 0) return;
-  hipLaunchKernelGGL(k_elim_sss, dim3(A.ngroups), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_elim_sss, dim3(elim_parts(A), A.ngroups), dim3(256), 0, s, A);
   HIF_HIP(hipGetLastError());
 }
 void launch_elim_finish(const ElimArgs& A, hipStream_t s) {
   if (A.ngroups == 0) return;
-  hipLaunchKernelGGL(k_elim_finish, dim3(A.ngroups), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_elim_finish, dim3(elim_parts(A), A.ngroups), dim3(256), 0, s, A);
   HIF_HIP(hipGetLastError());
 }
 
@@ -926,12 +978,14 @@ void id_batched_impl(double* mats, const int64_t* off, const int32_t* rows, cons
   std::vector<int32_t> hr2(batch);
   std::vector<int64_t> hso(batch);
   int64_t qt = 0;
+  int max_rows = 1;
   for (int p = 0; p < batch; ++p) {
     HIF_REQUIRE(hc[p] >= 1 && hc[p] <= max_cols && hr[p] >= 1, HIF_EINVAL,
                 "every matrix needs 1 <= cols <= max_cols and rows >= 1");
     hr2[p] = std::min(hr[p], hc[p]);
     hso[p] = qt;
-    if (hr[p] > hc[p]) qt += int64_t(hr[p]) * 16 + 16 * int64_t(hc[p]) + 256;
+    max_rows = std::max(max_rows, hr[p]);
+    if (hr[p] > hc[p]) qt += rowqr_scratch(hr[p], hc[p]);
   }
   DBuf<int32_t> rows2;
   DBuf<int64_t> soff;
@@ -950,7 +1004,7 @@ void id_batched_impl(double* mats, const int64_t* off, const int32_t* rows, cons
   Q.scratch = scratch.p;
   Q.soff = soff.p;
   Q.nprob = batch;
-  launch_rowqr_auto(Q, max_cols, s);
+  launch_rowqr_auto(Q, max_rows, max_cols, s);
   IdArgs A;
   A.base = mats;
   A.moff = off;

@@ -914,14 +914,16 @@ void Factorizer::sublevel(int lvl, int kind) {
   std::vector<int32_t> h_rows2(NC);
   std::vector<int64_t> h_soff(NC);
   int64_t qtot = 0;
+  int maxm = 1;
   for (int g = 0; g < G; ++g) {
     const int64_t nf = h_nf[g + 1] - h_nf[g];
     const int64_t m = sym ? nf + P : 2 * nf + 2 * P;
+    maxm = std::max<int>(maxm, int(m));
     for (int q = h_cls_first[g]; q < h_cls_first[g + 1]; ++q) {
       const int64_t nq = h_cls_n[q];
       h_rows2[q] = int32_t(std::min<int64_t>(m, nq));
       h_soff[q] = qtot;
-      if (m > nq) qtot += m * 16 + 16 * nq + 256;
+      if (m > nq) qtot += rowqr_scratch(m, nq);
     }
   }
   cls_rows2.ensure(NC, mt);
@@ -939,7 +941,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   qa.scratch = qr_scratch.p;
   qa.soff = cls_soff.p;
   qa.nprob = NC;
-  launch_rowqr_auto(qa, maxq, s);
+  launch_rowqr_auto(qa, maxm, maxq, s);
   tm.mark(PH_QR);
   IdArgs ia{};
   ia.base = Y.p;
@@ -1052,6 +1054,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   ea.status = status.p;
   int max_nrec = 0;
   for (int g : rec_g) max_nrec = std::max<int>(max_nrec, int(h_gstart[g + 1] - h_gstart[g]));
+  ea.max_n = max_nrec;
   if (sub.nrec > 0 && (max_nrec > 256 || (sub.nrec < 256 && max_nrec > 96))) {
     // split path: setup, transform GEMMs, M_ss, batched partial LU, finish
     launch_elim_setup(ea, s);

@@ -57,17 +57,18 @@ struct RowQrArgs {
   const int32_t* ld;
   const int32_t* rows;
   const int32_t* cols;
-  double* scratch;       // per problem: m*16 + 16*n + 256 doubles
+  double* scratch;       // per problem: rowqr_scratch(m, n) doubles
   const int64_t* soff;
   int nprob = 0;
 };
 void launch_rowqr(const RowQrArgs& A, hipStream_t s);
-void launch_rowqr_auto(const RowQrArgs& A, int max_cols, hipStream_t s);
+void launch_rowqr_auto(const RowQrArgs& A, int max_rows, int max_cols, hipStream_t s);
 
 // Batched skeletonization + elimination (Lemma 2.4 with Lemma 2.1), one
 // workgroup per group with a record.
 struct ElimArgs {
   int ngroups = 0;
+  int max_n = 0;               // largest group of the sub-level (sizes the copy grids)
   const int32_t* cord;
   const int64_t* gstart;
   const int32_t* grec;          // [G] record index or -1
