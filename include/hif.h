@@ -164,6 +164,25 @@ hif_status hif_matvec(const double* points, int64_t n, int dim, const hif_kernel
                       const double* a, const double* b, const double* c,
                       const double* x, double* y, int64_t nrhs, hif_stream stream);
 
+/*
+ * Iterative refinement by GMRES (Section 6): solve A u = f with A the exact
+ * operator of this handle (as hif_matvec, from the points and coefficients
+ * given to hif_factor) and F^{-1} (hif_solve) as right preconditioner:
+ * GMRES on A F^{-1} y = f, u = F^{-1} y, starting from zero, no restart.
+ *   f, u:   [nrhs][n] device, must not alias; u receives the solution.
+ *   nrhs:   1..64; all right-hand sides iterate together.
+ *   tol:    stop a right-hand side once its Arnoldi residual estimate is
+ *           <= tol |f| (0 < tol < 1).
+ *   maxit:  iteration cap, 1..200; the Krylov basis takes
+ *           nrhs * (maxit + 1) * n doubles of device memory during the call.
+ *   iters:  optional host [nrhs]: iterations used.
+ *   relres: optional host [nrhs]: true relative residual |f - A u| / |f|
+ *           recomputed with the exact operator at the end.
+ * Host-blocking.  Non-convergence within maxit is not an error (check relres).
+ */
+hif_status hif_gmres(hif_handle h, const double* f, double* u, int64_t nrhs, double tol, int32_t maxit,
+                     int32_t* iters, double* relres, hif_stream stream);
+
 /* Copy the statistics of a factorization into *out (host memory). */
 hif_status hif_stats(hif_handle h, hif_stats_t* out);
 

@@ -71,6 +71,7 @@ EXPORTS = {
     "hif_last_error": (ctypes.c_char_p, []),
     "hif_id_batched": (_INT, [_VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]),
     "hif_partition": (_INT, [_VP, _I64, _INT, _VP, _INT, _I32, _VP, _VP]),
+    "hif_gmres": (_INT, [_VP, _VP, _VP, _I64, _DBL, _I32, _VP, _VP, _VP]),
 }
 
 
@@ -160,6 +161,24 @@ class Factorization:
 
     def apply_T(self, x, out=None, stream=None):
         return self._run(load_library().hif_apply_T, x, out, stream)
+
+    def gmres(self, f, tol=1e-10, maxit=50, out=None, stream=None):
+        """Solve ``A u = f`` by GMRES right-preconditioned with ``F^{-1}`` and the exact
+        operator given to ``factor``; returns ``(u, iterations, true relative residuals)``."""
+        if self._h is None:
+            raise RuntimeError("factorization has been freed")
+        f = _dev(f)
+        vec = f.dim() == 1
+        Fm = (f.reshape(1, -1) if vec else f).contiguous()
+        if Fm.shape[-1] != self.n:
+            raise ValueError(f"last dimension must be n = {self.n}")
+        U = torch.empty_like(Fm) if out is None else out.reshape(Fm.shape)
+        nr = Fm.shape[0]
+        its = (ctypes.c_int32 * nr)()
+        rr = (ctypes.c_double * nr)()
+        _check(load_library().hif_gmres(self._h, _ptr(Fm), _ptr(U), nr, float(tol), int(maxit),
+                                        ctypes.cast(its, _VP), ctypes.cast(rr, _VP), _stream(stream)))
+        return U.reshape(f.shape), list(its), list(rr)
 
     def stats(self) -> dict:
         s = hif_stats_t()

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhif.so")
 
-SOURCES = ["api.hip", "factor.hip", "dense.hip", "batched.hip", "sweep.hip", "matvec.hip", "prim.hip"]
+SOURCES = ["api.hip", "factor.hip", "dense.hip", "batched.hip", "sweep.hip", "matvec.hip", "gmres.hip", "prim.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

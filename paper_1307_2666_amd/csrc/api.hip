@@ -147,6 +147,17 @@ hif_status hif_matvec(const double* points, int64_t n, int dim, const hif_kernel
   });
 }
 
+hif_status hif_gmres(hif_handle h, const double* f, double* u, int64_t nrhs, double tol, int32_t maxit,
+                     int32_t* iters, double* relres, hif_stream s) {
+  if (!h) return fail(HIF_EINVAL, "handle is NULL");
+  if (!f || !u) return fail(HIF_EINVAL, "vector pointer is NULL");
+  if (f == u) return fail(HIF_EINVAL, "u must not alias f");
+  if (nrhs < 1 || nrhs > 64) return fail(HIF_EINVAL, "nrhs must be in [1, 64]");
+  if (!(tol > 0.0 && tol < 1.0)) return fail(HIF_EINVAL, "tol must satisfy 0 < tol < 1");
+  if (maxit < 1 || maxit > 200) return fail(HIF_EINVAL, "maxit must be in [1, 200]");
+  return guarded([&] { gmres_impl(h, f, u, nrhs, tol, maxit, iters, relres, hipStream_t(s)); });
+}
+
 hif_status hif_stats(hif_handle h, hif_stats_t* out) {
   if (!h || !out) return fail(HIF_EINVAL, "NULL argument");
   *out = h->stats;

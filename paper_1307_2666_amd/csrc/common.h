@@ -132,8 +132,9 @@ struct hif_factor_s {
   int nproxy = 64;
   double proxy_r = 1.5;
   hif::MemTracker mem;
-  // Operator data, caller order.
-  hif::DBuf<double> pts, a, b, c, w, selfk;
+  // Operator data, caller order: points [n][dim], then a, b, c, w, self [n] each.
+  hif::DBuf<double> op;
+  const double *pts = nullptr, *a = nullptr, *b = nullptr, *c = nullptr, *w = nullptr, *selfk = nullptr;
   // Factors.
   std::vector<hif::SubLevel> subs;
   int64_t ntop = 0;
@@ -222,6 +223,10 @@ void launch_make_perm_top(const int32_t* piv, int32_t* perm, int n, hipStream_t 
 
 // Sweeps (sweep.hip): op 0 solve, 1 solve_T, 2 apply, 3 apply_T.
 void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s);
+
+// Right-preconditioned GMRES with the factorization and the exact matvec (gmres.hip).
+void gmres_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, double tol, int maxit,
+                int32_t* iters, double* relres, hipStream_t s);
 
 // Exact O(n^2) matvec (matvec.hip).
 void matvec_impl(const double* pts, int64_t n, int dim, const double* a, const double* b,

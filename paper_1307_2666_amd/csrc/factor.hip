@@ -1253,8 +1253,9 @@ void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* kr, co
   F.mt = mt;
   F.tm.s = s;
 
-  // Operator copies: a (0 if absent), b, c (1 if absent), w (h^d), self term.
-  DBuf<double> op;
+  // Operator copies, kept in the handle: a (0 if absent), b, c (1 if absent),
+  // w (h^d), self term.
+  DBuf<double>& op = H->op;
   op.alloc(int64_t(N) * (D + 5), mt);
   double* pts = op.p;
   double* a = pts + N * D;
@@ -1275,6 +1276,12 @@ void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* kr, co
   fill_or_copy(w, kr->weights, std::pow(kr->h, D));
   fill_or_copy(sf, kr->self, kr->self ? 0.0 : self_integral(kr->h, D));
   HIF_HIP(hipGetLastError());
+  H->pts = pts;
+  H->a = a;
+  H->b = b;
+  H->c = c;
+  H->w = w;
+  H->selfk = sf;
   F.pts = pts;
   F.a = a;
   F.b = b;

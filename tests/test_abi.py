@@ -89,6 +89,15 @@ def test_sweeps_reject_null_handle():
     lib.hif_free(None)  # no-op
 
 
+def test_gmres_rejects_bad_arguments():
+    lib = hif.load_library()
+    buf = ctypes.c_double(0.0)
+    p = ctypes.cast(ctypes.pointer(buf), ctypes.c_void_p)
+    q = ctypes.cast(ctypes.pointer(ctypes.c_double(0.0)), ctypes.c_void_p)
+    assert lib.hif_gmres(None, p, q, 1, 1e-10, 10, None, None, None) == B.HIF_EINVAL
+    assert b"handle" in lib.hif_last_error()
+
+
 def test_matvec_rejects_bad_arguments():
     lib = hif.load_library()
     k = B.hif_kernel(0.1, None, None)

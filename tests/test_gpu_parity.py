@@ -246,3 +246,42 @@ def test_gmres_with_gpu_preconditioner():
     u, it, hist = gmres(A_mv, f, M=M, tol=1e-10, maxit=30)
     assert hist[-1] <= 1e-10 and it <= 10
     assert np.linalg.norm(op.dense() @ u - f) <= 1e-9 * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("second_kind", [0, 1])
+def test_gmres_native_matches_dense_solve(second_kind):
+    # hif_gmres (a12): GMRES on A F^{-1} with the exact operator reaches the
+    # requested true residual; the solution matches a dense FP64 solve, and
+    # the iteration count matches the oracle's GMRES driven by the same
+    # preconditioner (Section 6, Lemma 5.1).
+    op = _op(64, 2)
+    F = _gpu_factor(op, 1e-3, 64, second_kind=second_kind)
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal((3, op.N))
+    u, its, rr = F.gmres(_t(f), tol=1e-10, maxit=40)
+    u = _np(u)
+    A = op.dense()
+    uref = np.linalg.solve(A, f.T).T
+    P = _t(op.points)
+    a = _t(op.a)
+    A_mv = lambda v: _np(hif.matvec(P, _t(v), a=a, h=1.0 / 64))
+    M = lambda v: _np(F.solve(_t(v)))
+    for v in range(3):
+        assert rr[v] <= 1.5e-10, rr
+        res = np.linalg.norm(A @ u[v] - f[v]) / np.linalg.norm(f[v])
+        assert res <= 1.5e-10
+        assert np.linalg.norm(u[v] - uref[v]) <= 1e-9 * np.linalg.norm(uref[v])
+        _, it_o, _ = gmres(A_mv, f[v], M=M, tol=1e-10, maxit=40)
+        assert abs(its[v] - it_o) <= 1, (its, it_o)
+
+
+def test_gmres_native_zero_rhs_and_single_iteration():
+    op = _op(32, 2)
+    F = _gpu_factor(op, 1e-6, 16)
+    f = np.zeros((2, op.N))
+    f[1] = np.random.default_rng(6).standard_normal(op.N)
+    u, its, rr = F.gmres(_t(f), tol=1e-3, maxit=5)
+    u = _np(u)
+    assert its[0] == 0 and np.all(u[0] == 0.0) and rr[0] == 0.0
+    # eps = 1e-6 preconditioner: one iteration already meets 1e-3
+    assert its[1] == 1 and rr[1] <= 1e-3
