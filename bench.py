@@ -38,6 +38,8 @@ def parse():
     p.add_argument("--eps", type=float, default=None)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", default="sq128")
+    p.add_argument("--no-refine", action="store_true",
+                   help="skip the FP64 vs FP32-mixed comparison with GMRES refinement")
     return p.parse_args()
 
 
@@ -63,6 +65,44 @@ def cpu_baseline(sample: str, eps: float):
     return {"value": N / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle hifie2x factor + 8-RHS solve of the {n}x{n} grid (N={N}, same kernel, "
                       f"leaf 64, eps {eps:g}), {dt:.1f} s on 1 host core"}
+
+
+def refinement(hif, P, a, Fr, wl, tol=1e-10):
+    """FP64 vs FP32-mixed factorization as GMRES preconditioner, to a true relative
+    residual of ``tol`` against the exact FP64 operator (hif_gmres).  Total time =
+    factor + GMRES (each iteration one solve and one exact matvec, plus the final
+    residual check), best over eps in {1e-3, 1e-6} for each precision; one warm run
+    per configuration, the second one timed."""
+    import torch
+
+    runs = []
+    for prec, pname, sk in ((hif.HIF_FP64, "fp64", -1), (hif.HIF_FP32_MIXED, "fp32_mixed", -1),
+                            (hif.HIF_FP32_MIXED, "fp32_mixed_x", 1)):
+        for e in (1e-3, 1e-6):
+            if pname == "fp32_mixed_x" and e != 1e-3:
+                continue
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                F = hif.factor(P, e, wl.leaf, a=a, h=wl.h, precision=prec, second_kind=sk)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, its, rr = F.gmres(Fr, tol=tol, maxit=40)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                F.free()
+            runs.append({"precision": pname, "eps": e, "factor_s": t1 - t0, "gmres_s": t2 - t1,
+                         "total_s": t2 - t0, "iterations": max(its), "rel_residual_max": max(rr),
+                         "converged": bool(max(rr) <= 1.5 * tol)})
+    ok = [r for r in runs if r["converged"]]
+    best = {}
+    for pname in ("fp64", "fp32_mixed"):
+        cand = [r for r in ok if r["precision"].startswith(pname)]
+        if cand:
+            best[pname] = min(cand, key=lambda r: r["total_s"])
+    speedup = (best["fp64"]["total_s"] / best["fp32_mixed"]["total_s"]
+               if "fp64" in best and "fp32_mixed" in best else None)
+    return {"target_residual": tol, "runs": runs, "best": best, "mixed_vs_fp64_speedup": speedup}
 
 
 def main():
@@ -162,6 +202,8 @@ def main():
                                                     "hardware": "MATLAB R2010b, 1 core Xeon E7-4820 2.0 GHz, "
                                                                 "FP64, adaptive leaf"}},
     }
+    if not args.no_refine:
+        line["refinement"] = refinement(hif, P, a, Fr, wl)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample, eps)
     print(json.dumps(line), flush=True)

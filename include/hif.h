@@ -75,10 +75,16 @@ typedef struct {
 
 /*
  * Factorization options.  hif_opts_default fills the defaults.
- *  precision:    HIF_FP64 (only value supported in this build).
+ *  precision:    HIF_FP64, or HIF_FP32_MIXED: kernel entries evaluated and
+ *                rounded in FP32, the skeletonization GEMMs and the Schur
+ *                update of the skeleton block on FP32 matrix cores with FP32
+ *                accumulation; the row compression, pivoted QR (rank
+ *                decisions), the LU of the redundant blocks and of the top
+ *                block, the SCI store and the sweeps stay FP64.  Meant as a
+ *                preconditioner for hif_gmres.
  *  second_kind:  1 = Section 4.4 modification (rho-scaled local tolerance and
  *                split compression by SCI sparsity pattern; "hifie2x/3x"),
- *                0 = plain compression, -1 = auto (1).
+ *                0 = plain compression, -1 = auto (1 in FP64, 0 in FP32_MIXED).
  *  symmetric:    1 = compress only the column block Y'_c (Section 5; valid
  *                when A is symmetric), 0 = full Y_c of eqn proxy-id,
  *                -1 = auto (symmetric iff b_i == s c_i w_i for one scalar s).

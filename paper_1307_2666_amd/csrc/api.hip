@@ -84,8 +84,6 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
   if (opts) o = *opts;
   if (o.precision != HIF_FP64 && o.precision != HIF_FP32_MIXED)
     return fail(HIF_EINVAL, "opts.precision must be HIF_FP64 or HIF_FP32_MIXED");
-  if (o.precision == HIF_FP32_MIXED)
-    return fail(HIF_EUNSUPPORTED, "HIF_FP32_MIXED is not available in this build");
   if (o.second_kind < -1 || o.second_kind > 1) return fail(HIF_EINVAL, "opts.second_kind must be -1, 0 or 1");
   if (o.symmetric < -1 || o.symmetric > 1) return fail(HIF_EINVAL, "opts.symmetric must be -1, 0 or 1");
   if (o.variant != HIF_VARIANT_HIFIE && o.variant != HIF_VARIANT_RSF)
@@ -93,7 +91,9 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
   if (o.n_proxy < 0 || o.n_proxy > 8192) return fail(HIF_EINVAL, "opts.n_proxy must be in [0, 8192]");
   if (!(o.proxy_radius == 0.0 || (std::isfinite(o.proxy_radius) && o.proxy_radius > 0.5)))
     return fail(HIF_EINVAL, "opts.proxy_radius must be 0 (default) or > 0.5 cell widths");
-  if (o.second_kind < 0) o.second_kind = 1;
+  // second-kind modification by default in FP64 only: in FP32 the SCI-scaled
+  // tolerance rho * eps falls below single-precision resolution
+  if (o.second_kind < 0) o.second_kind = o.precision == HIF_FP64 ? 1 : 0;
   hif_handle H = nullptr;
   hif_status st = guarded([&] {
     std::unique_ptr<hif_factor_s> h(new hif_factor_s());

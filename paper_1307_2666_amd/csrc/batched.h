@@ -51,6 +51,7 @@ struct LuBatch {
   const int64_t* poff;
   int32_t* status;
   int nprob = 0;
+  int fp32 = 0;  // mixed precision: trailing tiles inside the skeleton block on FP32 matrix cores
 };
 void launch_lu_batched(const LuBatch& A, int max_r, int max_n, hipStream_t s);
 
@@ -63,6 +64,7 @@ struct GemmDesc {
   const double* A;
   const double* B;
   double* C;
+  int fp32 = 0;  // mixed precision: FP32 matrix cores, FP32 accumulation
 };
 void launch_gemm_tiles(const GemmDesc* D, int nd, int max_m, int max_n, hipStream_t s);
 

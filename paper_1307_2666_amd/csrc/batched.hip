@@ -700,6 +700,44 @@ __global__ __launch_bounds__(256) void k_lu_update(LuBatch A, int j0) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wr = wv >> 1, wc = wv & 1;
+  if (A.fp32 && rt0 >= r && ct0 >= r) {
+    // Schur update of the skeleton block (rows and columns >= r) in FP32
+    float4_t d[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) d[a][b] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kNb; ks += 4) {
+      const int k = ks + lk;
+      float af[2], bf[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = rt0 + wr * 32 + a * 16 + li;
+        af[a] = (i < n && k < jb) ? float(M[int64_t(i) * n + j0 + k]) : 0.f;
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int c = ct0 + wc * 32 + b * 16 + li;
+        bf[b] = (c < n && k < jb) ? float(M[int64_t(j0 + k) * n + c]) : 0.f;
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) d[a][b] = mfma_f32(af[a], bf[b], d[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = rt0 + wr * 32 + a * 16 + 4 * lk + v;
+          const int c = ct0 + wc * 32 + b * 16 + li;
+          if (i < n && c < n) M[int64_t(i) * n + c] -= double(d[a][b][v]);
+        }
+    return;
+  }
   double4_t d[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -748,8 +786,12 @@ __global__ __launch_bounds__(256) void k_gemm_tiles(const GemmDesc* D, int nd) {
   const int Mt = min(kGemmTile, g.M - tm), Nt = min(kGemmTile, g.N - tn);
   const double* Ap = g.ta ? g.A + tm : g.A + int64_t(tm) * g.lda;
   const double* Bp = g.tb ? g.B + int64_t(tn) * g.ldb : g.B + tn;
-  wg_gemm(Mt, Nt, g.K, g.alpha, Ap, g.lda, g.ta, Bp, g.ldb, g.tb, g.beta, g.C + int64_t(tm) * g.ldc + tn, g.ldc,
-          lds);
+  if (g.fp32)
+    wg_gemm_f32(Mt, Nt, g.K, g.alpha, Ap, g.lda, g.ta, Bp, g.ldb, g.tb, g.beta, g.C + int64_t(tm) * g.ldc + tn, g.ldc,
+                lds);
+  else
+    wg_gemm(Mt, Nt, g.K, g.alpha, Ap, g.lda, g.ta, Bp, g.ldb, g.tb, g.beta, g.C + int64_t(tm) * g.ldc + tn, g.ldc,
+            lds);
 }
 
 }  // namespace

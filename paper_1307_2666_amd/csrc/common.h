@@ -163,6 +163,25 @@ __device__ __forceinline__ double green_r2(double r2) {
   }
 }
 
+// Single-precision G for the mixed-precision assembly.
+template <int D>
+__device__ __forceinline__ float green_r2f(float r2) {
+  if constexpr (D == 2) {
+    return -0.5f * float(kInv2Pi) * logf(r2);
+  } else {
+    return float(kInv4Pi) * rsqrtf(r2);
+  }
+}
+
+// Kernel value G(r) (r2 = r^2) in the precision of the factorization: FP64,
+// or FP32 evaluation in the mixed-precision mode.
+template <int D>
+__device__ __forceinline__ double green_mixed(double r2, bool f32) {
+  return f32 ? double(green_r2f<D>(float(r2))) : green_r2<D>(r2);
+}
+// An assembled entry, rounded to FP32 in the mixed-precision mode.
+__device__ __forceinline__ double entry_prec(double v, bool f32) { return f32 ? double(float(v)) : v; }
+
 // Closed-form integral of G over the element [-h/2, h/2]^d.
 inline double self_integral(double h, int d) {
   if (d == 2) return -(h * h / (2.0 * M_PI)) * (std::log(h / std::sqrt(2.0)) - 1.5 + M_PI / 4.0);

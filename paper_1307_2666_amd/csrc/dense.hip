@@ -130,17 +130,18 @@ __global__ __launch_bounds__(kAsmThreads) void k_asm_fill(AsmArgs A) {
         const double t = xi[k] - A.pts[int64_t(j) * D + k];
         r2 += t * t;
       }
+      const bool f32 = A.fp32 != 0;
       if (kind == 4) {
         double v;
         if (i == j)
           v = A.a[j] + A.b[j] * A.selfk[j] * A.c[j];
         else
-          v = bi * green_r2<D>(r2) * A.w[j] * A.c[j];
+          v = bi * green_mixed<D>(r2, f32) * A.w[j] * A.c[j];
         const int rr = r - m;
-        Acc[int64_t(rr) * n + col] = v;
+        Acc[int64_t(rr) * n + col] = entry_prec(v, f32);
         Scc[int64_t(rr) * n + col] = 0.0;
       } else {
-        const double gk = green_r2<D>(r2);
+        const double gk = green_mixed<D>(r2, f32);
         double v;
         if (kind == 0)
           v = bi * gk * A.w[j] * A.c[j];       // b_i G w_j c_j
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(kAsmThreads) void k_asm_fill(AsmArgs A) {
           v = gk * A.w[j] * A.c[j];            // G(|x_p - x_j|) w_j c_j
         else
           v = A.b[j] * gk * A.w[j];            // b_j G(|x_p - x_j|) w_j
-        Y[int64_t(r) * n + col] = v;
+        Y[int64_t(r) * n + col] = entry_prec(v, f32);
       }
     }
   }
@@ -781,10 +782,17 @@ __global__ __launch_bounds__(256) void k_eliminate(ElimArgs A) {
   double* Msr = M + int64_t(r) * n;
   double* Mss = Msr + r;
   if (k > 0) {
-    wg_gemm(r, r, k, -1.0, Mrs, n, false, v.T, r, false, 1.0, Mrr, n, lds);   // A_rr - A_rs T
-    wg_gemm(k, r, k, -1.0, Mss, n, false, v.T, r, false, 1.0, Msr, n, lds);   // B_sr
-    wg_gemm(r, r, k, -1.0, v.T, r, true, Msr, n, false, 1.0, Mrr, n, lds);    // B_rr
-    wg_gemm(r, k, k, -1.0, v.T, r, true, Mss, n, false, 1.0, Mrs, n, lds);    // B_rs
+    if (A.fp32) {
+      wg_gemm_f32(r, r, k, -1.0, Mrs, n, false, v.T, r, false, 1.0, Mrr, n, lds);
+      wg_gemm_f32(k, r, k, -1.0, Mss, n, false, v.T, r, false, 1.0, Msr, n, lds);
+      wg_gemm_f32(r, r, k, -1.0, v.T, r, true, Msr, n, false, 1.0, Mrr, n, lds);
+      wg_gemm_f32(r, k, k, -1.0, v.T, r, true, Mss, n, false, 1.0, Mrs, n, lds);
+    } else {
+      wg_gemm(r, r, k, -1.0, Mrs, n, false, v.T, r, false, 1.0, Mrr, n, lds);   // A_rr - A_rs T
+      wg_gemm(k, r, k, -1.0, Mss, n, false, v.T, r, false, 1.0, Msr, n, lds);   // B_sr
+      wg_gemm(r, r, k, -1.0, v.T, r, true, Msr, n, false, 1.0, Mrr, n, lds);    // B_rr
+      wg_gemm(r, k, k, -1.0, v.T, r, true, Mss, n, false, 1.0, Mrs, n, lds);    // B_rs
+    }
     elim_sss(v, 0, 1);
     __syncthreads();
   }
@@ -919,9 +927,9 @@ __global__ void k_top_assemble(TopArgs A) {
         double t = A.pts[int64_t(i) * D + k] - A.pts[int64_t(j) * D + k];
         r2 += t * t;
       }
-      v = A.b[i] * green_r2<D>(r2) * A.w[j] * A.c[j];
+      v = A.b[i] * green_mixed<D>(r2, A.fp32 != 0) * A.w[j] * A.c[j];
     }
-    A.A[e] = v;
+    A.A[e] = entry_prec(v, A.fp32 != 0);
   }
 }
 

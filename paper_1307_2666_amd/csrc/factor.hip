@@ -889,6 +889,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   aa.srow = srow.p;
   aa.skey = skey.p;
   aa.sval = sval.p;
+  aa.fp32 = H->opts.precision == HIF_FP32_MIXED;
   aa.max_rows = maxmn;
   aa.max_cols = maxn;
   launch_assemble(aa, s);
@@ -1055,6 +1056,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   int max_nrec = 0;
   for (int g : rec_g) max_nrec = std::max<int>(max_nrec, int(h_gstart[g + 1] - h_gstart[g]));
   ea.max_n = max_nrec;
+  ea.fp32 = H->opts.precision == HIF_FP32_MIXED;
   if (sub.nrec > 0 && (max_nrec > 256 || (sub.nrec < 256 && max_nrec > 96))) {
     // split path: setup, transform GEMMs, M_ss, batched partial LU, finish
     launch_elim_setup(ea, s);
@@ -1087,6 +1089,7 @@ void Factorizer::sublevel(int lvl, int kind) {
       gdesc.ensure(d1.size() + d2.size(), mt);
       std::vector<GemmDesc> all(d1);
       all.insert(all.end(), d2.begin(), d2.end());
+      for (auto& d : all) d.fp32 = ea.fp32;
       to_dev(gdesc.p, all, s);
       launch_gemm_tiles(gdesc.p, int(d1.size()), mm, mn, s);
       launch_gemm_tiles(gdesc.p + d1.size(), int(d2.size()), mm, mn, s);
@@ -1109,6 +1112,7 @@ void Factorizer::sublevel(int lvl, int kind) {
     lb.poff = lu_poff.p;
     lb.status = status.p;
     lb.nprob = sub.nrec;
+    lb.fp32 = ea.fp32;
     launch_lu_batched(lb, sub.max_r, max_nrec, s);
     launch_elim_finish(ea, s);
     HIF_HIP(hipStreamSynchronize(s));  // descriptor tables are host vectors
@@ -1189,6 +1193,7 @@ void Factorizer::top() {
     hipLaunchKernelGGL(k_pos_scatter, dim3(nblocks(n)), dim3(kThreads), 0, s, act.p, n, pos_of.p);
     TopArgs ta{};
     ta.dim = D;
+    ta.fp32 = H->opts.precision == HIF_FP32_MIXED;
     ta.n = n;
     ta.pts = pts;
     ta.a = a;

@@ -11,6 +11,7 @@ namespace hif {
 struct AsmArgs {
   int dim = 2, sym = 1, nproxy = 64, ngroups = 0;
   int max_rows = 0, max_cols = 0;  // max over groups of rows(Y_c) + n_c, and of n_c
+  int fp32 = 0;                 // mixed precision: kernel entries evaluated and rounded in FP32
   double R = 0;                 // absolute proxy radius of this sub-level
   const double *pts, *a, *b, *c, *w, *selfk;
   const double* proxy_u;        // [nproxy][dim] unit directions
@@ -69,6 +70,7 @@ void launch_rowqr_auto(const RowQrArgs& A, int max_rows, int max_cols, hipStream
 struct ElimArgs {
   int ngroups = 0;
   int max_n = 0;               // largest group of the sub-level (sizes the copy grids)
+  int fp32 = 0;                // mixed precision: transform GEMMs on FP32 matrix cores
   const int32_t* cord;
   const int64_t* gstart;
   const int32_t* grec;          // [G] record index or -1
@@ -104,6 +106,7 @@ void launch_elim_finish(const ElimArgs& A, hipStream_t s);
 // Top block A_L(s_L, s_L) = diag(a) + bKc + S, then LU with partial pivoting.
 struct TopArgs {
   int dim = 2;
+  int fp32 = 0;                 // mixed precision: kernel entries in FP32
   int64_t n = 0;
   const double *pts, *a, *b, *c, *w, *selfk;
   const int32_t* idx;           // top DOFs ascending

@@ -285,3 +285,36 @@ def test_gmres_native_zero_rhs_and_single_iteration():
     assert its[0] == 0 and np.all(u[0] == 0.0) and rr[0] == 0.0
     # eps = 1e-6 preconditioner: one iteration already meets 1e-3
     assert its[1] == 1 and rr[1] <= 1e-3
+
+
+# ---------------------------------------------------------------------------
+# FP32-mixed factorization: FP32 kernel entries and FP32 matrix-core GEMMs,
+# FP64 ID / LU.  Its error is single-precision level; GMRES against the
+# exact FP64 operator recovers full accuracy.
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_mixed_factor_error_matches_fp32_oracle(eps):
+    op = _op(32, 2)
+    A = op.dense()
+    F = _gpu_factor(op, eps, 16, precision=hif.HIF_FP32_MIXED)
+    e_gpu = np.linalg.norm(A - _dense_F(F, op.N), 2) / np.linalg.norm(A, 2)
+    Fo = factorize(op, eps, 16, second_kind=False, fp32_blocks=True)
+    Ad = np.eye(op.N)
+    e_orc = np.linalg.norm(A - np.column_stack([Fo.apply(Ad[:, i]) for i in range(op.N)]), 2) / np.linalg.norm(A, 2)
+    assert e_gpu <= 10 * max(eps, e_orc), (e_gpu, e_orc)
+    # the mixed mode really rounds: a tiny tolerance leaves single-precision error
+    if eps == 1e-6:
+        Ft = _gpu_factor(op, 1e-13, 16, precision=hif.HIF_FP32_MIXED)
+        et = np.linalg.norm(A - _dense_F(Ft, op.N), 2) / np.linalg.norm(A, 2)
+        assert 1e-10 < et < 1e-5
+
+
+def test_mixed_gmres_reaches_fp64_residual():
+    op = _op(64, 2)
+    F = _gpu_factor(op, 1e-3, 64, precision=hif.HIF_FP32_MIXED)
+    f = np.random.default_rng(8).standard_normal((2, op.N))
+    u, its, rr = F.gmres(_t(f), tol=1e-10, maxit=40)
+    u = _np(u)
+    A = op.dense()
+    for v in range(2):
+        assert rr[v] <= 1.5e-10 and its[v] <= 15
+        assert np.linalg.norm(u[v] - np.linalg.solve(A, f[v])) <= 1e-9 * np.linalg.norm(u[v])

@@ -157,3 +157,15 @@ def test_factor_records_partition_the_dofs():
         for r in recs:
             assert r.T.shape == (r.sk.size, r.rd.size)
             assert r.E.shape == (r.sk.size, r.rd.size) and r.G.shape == (r.rd.size, r.sk.size)
+
+
+def test_fp32_emulation_error_is_single_precision_level():
+    # With a tiny ID tolerance the only error left is the float32 rounding of
+    # the assembled blocks and Schur updates: far above FP64 rounding, at or
+    # below single-precision level relative to |A|.
+    op = _op(32, 2)
+    A = op.dense()
+    e64 = _rel2(A - _dense_F(factorize(op, 1e-13, leaf=16, second_kind=False), op.N), A)
+    e32 = _rel2(A - _dense_F(factorize(op, 1e-13, leaf=16, second_kind=False, fp32_blocks=True), op.N), A)
+    assert e64 < 1e-11
+    assert 1e-9 < e32 < 1e-6
