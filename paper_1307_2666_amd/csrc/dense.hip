@@ -393,8 +393,236 @@ __global__ __launch_bounds__(1024) void k_id(IdArgs A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Multi-workgroup ID for few large problems: the same column-pivoted
+// Householder QR as k_id (recomputed norms, ties to the lowest column, rank
+// rule of Section 2.2), one launch per pivot step.  Workgroup (b, q) owns
+// columns 64b..64b+63 of problem q; every workgroup finds the pivot from the
+// norms of the previous step (double-buffered, so no workgroup reads what
+// another writes in the same launch), applies the reflector to its columns
+// and recomputes their norms.  The pivot column keeps its Householder vector
+// below the diagonal and R_ii goes to alpha.  State of problem q lives at
+// q * stride.
+// ---------------------------------------------------------------------------
+struct IdmState {
+  double* nrm;    // [2][nprob * stride] squared norms of the rows below the step
+  int32_t* st;    // [2][nprob * stride] -2 absent, -1 trailing, >= 0 pivot step
+  double* alpha;  // [nprob * stride] R_ii
+  double* r00;    // [nprob]
+  int32_t* done;  // [nprob]
+  int64_t stride;
+  int64_t total;  // nprob * stride
+};
+constexpr int kIdmCols = 64;
+constexpr int kIdmThreads = 256;
+
+__global__ __launch_bounds__(kIdmThreads) void k_idm_init(IdArgs A, IdmState S) {
+  const int q = blockIdx.y;
+  const int m = A.rows[q], n = A.cols[q];
+  const int c0 = blockIdx.x * kIdmCols;
+  if (c0 >= n) return;
+  const double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const int lc = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int col = c0 + lc;
+  __shared__ double sp[4][kIdmCols];
+  double s = 0.0;
+  if (col < n)
+    for (int r = rg; r < m; r += 4) {
+      const double y = M[int64_t(r) * ld + col];
+      s += y * y;
+    }
+  sp[rg][lc] = s;
+  __syncthreads();
+  if (rg == 0 && col < n) {
+    const int64_t o = q * S.stride + col;
+    S.nrm[o] = sp[0][lc] + sp[1][lc] + sp[2][lc] + sp[3][lc];
+    S.st[o] = -1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S.done[q] = 0;
+    A.rank[q] = min(m, n);
+  }
+}
+
+__global__ __launch_bounds__(kIdmThreads) void k_idm_step(IdArgs A, IdmState S, int i) {
+  const int q = blockIdx.y;
+  const int m = A.rows[q], n = A.cols[q];
+  const int c0 = blockIdx.x * kIdmCols;
+  if (c0 >= n || i >= min(m, n) || S.done[q]) return;
+  const int cur = i & 1, nxt = cur ^ 1;
+  const double* nrm = S.nrm + cur * S.total + q * S.stride;
+  const int32_t* st = S.st + cur * S.total + q * S.stride;
+  ArgMax loc{-1.0, INT_MAX};
+  for (int c = threadIdx.x; c < n; c += kIdmThreads)
+    if (st[c] == -1) loc = better(loc, ArgMax{nrm[c], c});
+  const ArgMax best = block_argmax(loc);
+  const double nb = sqrt(best.v > 0.0 ? best.v : 0.0);
+  const double r00 = i == 0 ? nb : S.r00[q];
+  if (!(best.v > 0.0) || !(nb > A.tol[q] * r00)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      A.rank[q] = i;
+      S.done[q] = 1;
+    }
+    return;
+  }
+  if (i == 0 && blockIdx.x == 0 && threadIdx.x == 0) S.r00[q] = nb;
+  const int p = best.i;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const double x0 = M[int64_t(i) * ld + p];
+  const double alpha = -copysign(nb, x0);
+  const double v0 = x0 - alpha;
+  const double vtv = best.v - x0 * x0 + v0 * v0;
+  const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+  const int lc = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int col = c0 + lc;
+  const int state = col < n ? st[col] : -2;
+  const bool upd = state == -1 && col != p;
+  __shared__ double sp[4][kIdmCols];
+  const double* vp = M + p;   // pivot column, rows > i hold the vector
+  double* yc = M + col;
+  double dot = 0.0;
+  if (upd) {
+    if (rg == 0) dot = v0 * yc[int64_t(i) * ld];
+    int r = i + 1 + rg;
+    for (; r + 28 < m; r += 32) {
+      double vv[8], yy[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        vv[u] = vp[int64_t(r + 4 * u) * ld];
+        yy[u] = yc[int64_t(r + 4 * u) * ld];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) dot += vv[u] * yy[u];
+    }
+    for (; r < m; r += 4) dot += vp[int64_t(r) * ld] * yc[int64_t(r) * ld];
+  }
+  sp[rg][lc] = dot;
+  __syncthreads();
+  const double w = beta * (sp[0][lc] + sp[1][lc] + sp[2][lc] + sp[3][lc]);
+  __syncthreads();
+  double s2 = 0.0;
+  if (upd) {
+    if (rg == 0) yc[int64_t(i) * ld] -= w * v0;
+    int r = i + 1 + rg;
+    for (; r + 28 < m; r += 32) {
+      double vv[8], yy[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        vv[u] = vp[int64_t(r + 4 * u) * ld];
+        yy[u] = yc[int64_t(r + 4 * u) * ld];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        yy[u] -= w * vv[u];
+        s2 += yy[u] * yy[u];
+        yc[int64_t(r + 4 * u) * ld] = yy[u];
+      }
+    }
+    for (; r < m; r += 4) {
+      const double y = yc[int64_t(r) * ld] - w * vp[int64_t(r) * ld];
+      yc[int64_t(r) * ld] = y;
+      s2 += y * y;
+    }
+  }
+  sp[rg][lc] = s2;
+  __syncthreads();
+  if (rg == 0 && col < n) {
+    const int64_t o = nxt * S.total + q * S.stride + col;
+    if (upd) {
+      S.nrm[o] = sp[0][lc] + sp[1][lc] + sp[2][lc] + sp[3][lc];
+      S.st[o] = -1;
+    } else if (col == p) {
+      S.st[o] = i;
+      S.alpha[q * S.stride + i] = alpha;
+      A.perm[A.poff[q] + i] = p;
+    } else {
+      S.st[o] = state;
+    }
+  }
+}
+
+// Redundant columns in ascending order after the skeleton (one workgroup per problem).
+__global__ __launch_bounds__(1024) void k_idm_perm(IdArgs A, IdmState S) {
+  const int q = blockIdx.x;
+  const int n = A.cols[q];
+  const int k = A.rank[q];
+  const int32_t* st = S.st + (k & 1) * S.total + q * S.stride;
+  int32_t* perm = A.perm + A.poff[q];
+  int base = 0;
+  for (int c0 = 0; c0 < n; c0 += blockDim.x) {
+    const int c = c0 + threadIdx.x;
+    const int flag = (c < n && st[c] == -1) ? 1 : 0;
+    int tot = 0;
+    const int pre = block_excl_scan(flag, &tot);
+    if (flag) perm[k + base + pre] = c;
+    base += tot;
+  }
+}
+
+// T = R11^{-1} R12 in place over R12 (and the optional compact copy), one
+// thread per redundant column; R11[a][b] = M[a][perm[b]] above the diagonal,
+// R11[a][a] = alpha[a].
+__global__ __launch_bounds__(256) void k_idm_T(IdArgs A, IdmState S) {
+  const int q = blockIdx.y;
+  const int n = A.cols[q], k = A.rank[q];
+  const int nr = n - k;
+  const int b2 = blockIdx.x * 256 + threadIdx.x;
+  if (b2 >= nr) return;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const int32_t* perm = A.perm + A.poff[q];
+  const double* al = S.alpha + q * S.stride;
+  const int col = perm[k + b2];
+  for (int a = k - 1; a >= 0; --a) {
+    const double* Ra = M + int64_t(a) * ld;
+    double t = Ra[col];
+    for (int b = a + 1; b < k; ++b) t -= Ra[perm[b]] * M[int64_t(b) * ld + col];
+    M[int64_t(a) * ld + col] = t / al[a];
+  }
+  if (A.Tout) {
+    double* T = A.Tout + A.toff[q];
+    for (int a = 0; a < k; ++a) T[int64_t(a) * nr + b2] = M[int64_t(a) * ld + col];
+  }
+}
+
+static void launch_id_multi(const IdArgs& A, int max_cols, hipStream_t s) {
+  const int64_t stride = max_cols;
+  const int64_t total = stride * A.nprob;
+  DBuf<double> nrm, alpha, r00;
+  DBuf<int32_t> st, done;
+  nrm.alloc(2 * total, nullptr);
+  st.alloc(2 * total, nullptr);
+  alpha.alloc(total, nullptr);
+  r00.alloc(A.nprob, nullptr);
+  done.alloc(A.nprob, nullptr);
+  IdmState S{nrm.p, st.p, alpha.p, r00.p, done.p, stride, total};
+  const dim3 grid(unsigned((max_cols + kIdmCols - 1) / kIdmCols), unsigned(A.nprob));
+  hipLaunchKernelGGL(k_idm_init, grid, dim3(kIdmThreads), 0, s, A, S);
+  std::vector<int32_t> hd(A.nprob);
+  for (int i = 0; i < max_cols; ++i) {
+    hipLaunchKernelGGL(k_idm_step, grid, dim3(kIdmThreads), 0, s, A, S, i);
+    if ((i & 15) == 15) {  // stop launching once every problem has met the rank rule
+      HIF_HIP(hipMemcpyAsync(hd.data(), done.p, sizeof(int32_t) * A.nprob, hipMemcpyDeviceToHost, s));
+      HIF_HIP(hipStreamSynchronize(s));
+      bool all = true;
+      for (int v : hd) all = all && v;
+      if (all) break;
+    }
+  }
+  hipLaunchKernelGGL(k_idm_perm, dim3(A.nprob), dim3(1024), 0, s, A, S);
+  hipLaunchKernelGGL(k_idm_T, dim3(unsigned((max_cols + 255) / 256), unsigned(A.nprob)), dim3(256), 0, s, A, S);
+  HIF_HIP(hipGetLastError());
+  HIF_HIP(hipStreamSynchronize(s));  // the state buffers are released on return
+}
+
 void launch_id(const IdArgs& A, int max_cols, hipStream_t s) {
   if (A.nprob == 0) return;
+  if (A.nprob <= 1024 && max_cols >= 384) {
+    launch_id_multi(A, max_cols, s);
+    return;
+  }
   // the pivoted QR runs on min(m, n) <= max_cols rows, staged in LDS
   if (max_cols > kIdMaxRows) throw Error{HIF_EUNSUPPORTED, "ID problem with more than 4096 columns"};
   int block = 64;

@@ -129,6 +129,30 @@ def test_id_batched_matches_oracle():
             assert err <= np.sqrt(rd.size) * tol * r00 * 1.01 + 1e-14 * r00
 
 
+def test_id_batched_large_matches_oracle():
+    # >= 384 columns: the multi-workgroup pivoted QR (one launch per pivot step)
+    rng = np.random.default_rng(9)
+    cases = []
+    Y = rng.standard_normal((900, 500)) * (1.05 ** -np.arange(500))[rng.permutation(500)]
+    cases.append((Y, 1e-6, True))
+    x = np.linspace(0, 1, 700)
+    y = np.linspace(1.5, 2.5, 450)
+    cases.append((np.log(np.abs(x[:, None] - y[None, :])) + 1e-9 * rng.standard_normal((700, 450)), 1e-7, False))
+    out = hif.id_batched([torch.tensor(Y) for Y, _, _ in cases], [t for _, t, _ in cases])
+    for (Y, tol, unique), (sk, rd, T) in zip(cases, out):
+        sk, rd, T = sk.numpy(), rd.numpy(), T.numpy()
+        osk, ord_, oT = interp_decomp(Y, tol)
+        assert abs(sk.size - osk.size) <= 1, (Y.shape, sk.size, osk.size)
+        assert np.array_equal(np.sort(np.concatenate([sk, rd])), np.arange(Y.shape[1]))
+        assert np.all(np.diff(rd) > 0)
+        if unique:
+            assert np.array_equal(sk, osk)
+            assert np.allclose(T, oT, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(oT).max()))
+        r00 = np.max(np.linalg.norm(Y, axis=0))
+        err = np.linalg.norm(Y[:, rd] - Y[:, sk] @ T)
+        assert err <= np.sqrt(rd.size) * tol * r00 * 1.01 + 1e-14 * r00
+
+
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("eps", [1e-3, 1e-6, 1e-9])
 def test_factor_small_2d_vs_dense(eps):
