@@ -303,11 +303,11 @@ constexpr int kTb = kTsqrNb;
 struct PanelGeom {
   int mp, jb, nck;
 };
-__device__ __forceinline__ PanelGeom panel_geom(int m, int n, int j0) {
+__device__ __forceinline__ PanelGeom panel_geom(int m, int n, int j0, int cr) {
   PanelGeom g;
   g.mp = m - j0;
   g.jb = min(kTb, n - j0);
-  g.nck = tsqr_chunks(g.mp);
+  g.nck = (g.mp + cr - 1) / cr;
   return g;
 }
 __device__ __forceinline__ int chunk_lo(int c, int mp, int nck) { return (c * mp) / nck; }
@@ -344,37 +344,48 @@ __device__ __forceinline__ double wave_rs32(double (&p)[kTb]) {
   return p[0] + __shfl_xor(p[0], 1, 64);
 }
 
-// Householder QR of a block of at most blockDim.x rows and jb <= kTb columns
-// held one row per thread (thread t: row t; rows past the block are zero).
-// One reduction round per column gives the norm of the column below the
-// diagonal and its products with the later columns.  On return rows t < jb
-// hold R (upper part) and rows t > jj hold the Householder vector of column
-// jj below the diagonal; v0 (its diagonal entry) and beta = 2 / v^T v are in
-// sv0 / sbeta.
-template <int NW>
-__device__ void rowblock_qr(double (&y)[kTb], int t, int jb, double* sred, double* srow, double* sfin, double* sv0,
+// Householder QR of a block of at most RPT * blockDim.x rows and jb <= kTb
+// columns held RPT rows per thread (thread t: rows t + u * blockDim.x; rows
+// past the block are zero).  One reduction round per column gives the norm of
+// the column below the diagonal and its products with the later columns.  On
+// return rows < jb hold R (upper part) and rows > jj hold the Householder
+// vector of column jj below the diagonal; v0 (its diagonal entry) and
+// beta = 2 / v^T v are in sv0 / sbeta.
+template <int NW, int RPT>
+__device__ void rowblock_qr(double (&y)[RPT][kTb], int jb, double* sred, double* srow, double* sfin, double* sv0,
                             double* sbeta) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t0 = threadIdx.x, B = blockDim.x;
   for (int jj = 0; jj < jb; ++jj) {
     const int b = jj & 1;  // double-buffered so one barrier pair per column suffices
     double* red = sred + b * NW * kTb;
     double* row = srow + b * kTb;
     double* fin = sfin + b * kTb;
-    const double yj = pick(y, jj);
-    if (t == jj) {
+    double yj[RPT];
 #pragma unroll
-      for (int c = 0; c < kTb; ++c) row[c] = y[c];
+    for (int u = 0; u < RPT; ++u) yj[u] = pick(y[u], jj);
+    if (t0 == jj) {  // jj < kTb <= B: row jj is slot 0 of thread jj
+#pragma unroll
+      for (int c = 0; c < kTb; ++c) row[c] = y[0][c];
     }
     double p[kTb];
 #pragma unroll
-    for (int c = 0; c < kTb; ++c) p[c] = (t > jj || (t == jj && c == jj)) ? yj * y[c] : 0.0;
+    for (int c = 0; c < kTb; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int t = t0 + u * B;
+        acc += (t > jj || (t == jj && c == jj)) ? yj[u] * y[u][c] : 0.0;
+      }
+      p[c] = acc;
+    }
     const double w = wave_rs32(p);
     if ((lane & 1) == 0) red[wv * kTb + (lane >> 1)] = w;
     __syncthreads();
     if (threadIdx.x < kTb) {
       double s2 = 0.0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) s2 += red[w * kTb + threadIdx.x];
+      for (int w2 = 0; w2 < NW; ++w2) s2 += red[w2 * kTb + threadIdx.x];
       fin[threadIdx.x] = s2;
     }
     __syncthreads();
@@ -384,15 +395,19 @@ __device__ void rowblock_qr(double (&y)[kTb], int t, int jb, double* sred, doubl
     const double v0 = x0 - alpha;
     const double vtv = ss - x0 * x0 + v0 * v0;
     const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
-    if (t >= jj) {
-      const double vt = t == jj ? v0 : yj;
 #pragma unroll
-      for (int c = 0; c < kTb; ++c)
-        if (c > jj && c < jb) y[c] -= beta * (v0 * row[c] + fin[c]) * vt;
-      if (t == jj) {
+    for (int u = 0; u < RPT; ++u) {
+      const int t = t0 + u * B;
+      if (t >= jj) {
+        const double vt = t == jj ? v0 : yj[u];
 #pragma unroll
         for (int c = 0; c < kTb; ++c)
-          if (c == jj) y[c] = alpha;
+          if (c > jj && c < jb) y[u][c] -= beta * (v0 * row[c] + fin[c]) * vt;
+        if (t == jj) {
+#pragma unroll
+          for (int c = 0; c < kTb; ++c)
+            if (c == jj) y[u][c] = alpha;
+        }
       }
     }
     if (threadIdx.x == 0) {
@@ -446,50 +461,61 @@ __device__ void build_T(const double* V, int rows, const double* sbeta, double* 
   for (int e = threadIdx.x; e < kTb * kTb; e += blockDim.x) Tout[e] = sT[e];
 }
 
-// K1: QR of one chunk of the panel.
-__global__ __launch_bounds__(kTsqrRows) void k_tsqr_chunk(QrBatch A, int j0) {
+// K1: QR of one chunk of the panel (chunks of at most cr = RPT * blockDim.x rows).
+template <int RPT>
+__global__ __launch_bounds__(kTsqrRows * RPT) void k_tsqr_chunk(QrBatch A, int j0, int cr) {
+  constexpr int kB = kTsqrRows * RPT;
   const int q = blockIdx.y, c = blockIdx.x;
   const int m = A.rows[q], n = A.cols[q];
   if (m <= n || j0 >= n) return;
-  const PanelGeom g = panel_geom(m, n, j0);
+  const PanelGeom g = panel_geom(m, n, j0, cr);
   if (c >= g.nck) return;
   const int lo = chunk_lo(c, g.mp, g.nck), rows = chunk_lo(c + 1, g.mp, g.nck) - lo;
   double* M = A.base + A.moff[q];
   const int ld = A.ld[q];
   double* S0 = A.scratch + A.soff[q];
   const TsqrLayout L = tsqr_layout(m);
-  const int t = threadIdx.x;
-  __shared__ double sred[2 * (kTsqrRows / 64) * kTb], srow[2 * kTb], sfin[2 * kTb], sv0[kTb], sbeta[kTb];
+  const int t0 = threadIdx.x;
+  __shared__ double sred[2 * (kB / 64) * kTb], srow[2 * kTb], sfin[2 * kTb], sv0[kTb], sbeta[kTb];
   __shared__ double sG[kTb * (kTb + 1)], sT[kTb * kTb];
-  double y[kTb];
-  const double* src = M + int64_t(j0 + lo + (t < rows ? t : 0)) * ld + j0;
+  double y[RPT][kTb];
 #pragma unroll
-  for (int cc = 0; cc < kTb; ++cc) y[cc] = (t < rows && cc < g.jb) ? src[cc] : 0.0;
-  rowblock_qr<kTsqrRows / 64>(y, t, g.jb, sred, srow, sfin, sv0, sbeta);
+  for (int u = 0; u < RPT; ++u) {
+    const int t = t0 + u * kB;
+    const double* src = M + int64_t(j0 + lo + (t < rows ? t : 0)) * ld + j0;
+#pragma unroll
+    for (int cc = 0; cc < kTb; ++cc) y[u][cc] = (t < rows && cc < g.jb) ? src[cc] : 0.0;
+  }
+  rowblock_qr<kB / 64, RPT>(y, g.jb, sred, srow, sfin, sv0, sbeta);
   double* V = S0 + L.V + int64_t(lo) * kTb;
-  if (t < rows) store_vrow(y, t, g.jb, sv0, V + int64_t(t) * kTb);
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int t = t0 + u * kB;
+    if (t < rows) store_vrow(y[u], t, g.jb, sv0, V + int64_t(t) * kTb);
+  }
   if (g.nck == 1) {
-    if (t < g.jb) {
-      double* dst = M + int64_t(j0 + t) * ld + j0;
+    if (t0 < g.jb) {
+      double* dst = M + int64_t(j0 + t0) * ld + j0;
 #pragma unroll
       for (int cc = 0; cc < kTb; ++cc)
-        if (cc < g.jb) dst[cc] = cc >= t ? y[cc] : 0.0;
+        if (cc < g.jb) dst[cc] = cc >= t0 ? y[0][cc] : 0.0;
     }
-  } else if (t < kTb) {
-    double* dst = S0 + L.S + int64_t(c * kTb + t) * kTb;
+  } else if (t0 < kTb) {
+    double* dst = S0 + L.S + int64_t(c * kTb + t0) * kTb;
 #pragma unroll
-    for (int cc = 0; cc < kTb; ++cc) dst[cc] = (t < g.jb && cc >= t && cc < g.jb) ? y[cc] : 0.0;
+    for (int cc = 0; cc < kTb; ++cc) dst[cc] = (t0 < g.jb && cc >= t0 && cc < g.jb) ? y[0][cc] : 0.0;
   }
   __syncthreads();
   build_T(V, rows, sbeta, sG, sT, S0 + L.Tc + int64_t(c) * kTb * kTb);
 }
 
 // K2: QR of the stacked chunk R factors (nck > 1); writes the panel's R.
-__global__ __launch_bounds__(kTsqrStack) void k_tsqr_stack(QrBatch A, int j0) {
+template <int BS>
+__global__ __launch_bounds__(BS) void k_tsqr_stack(QrBatch A, int j0, int cr) {
   const int q = blockIdx.x;
   const int m = A.rows[q], n = A.cols[q];
   if (m <= n || j0 >= n) return;
-  const PanelGeom g = panel_geom(m, n, j0);
+  const PanelGeom g = panel_geom(m, n, j0, cr);
   if (g.nck < 2) return;
   const int srows = g.nck * kTb;
   double* M = A.base + A.moff[q];
@@ -497,20 +523,20 @@ __global__ __launch_bounds__(kTsqrStack) void k_tsqr_stack(QrBatch A, int j0) {
   double* S0 = A.scratch + A.soff[q];
   const TsqrLayout L = tsqr_layout(m);
   const int t = threadIdx.x;
-  __shared__ double sred[2 * (kTsqrStack / 64) * kTb], srow[2 * kTb], sfin[2 * kTb], sv0[kTb], sbeta[kTb];
+  __shared__ double sred[2 * (BS / 64) * kTb], srow[2 * kTb], sfin[2 * kTb], sv0[kTb], sbeta[kTb];
   __shared__ double sG[kTb * (kTb + 1)], sT[kTb * kTb];
-  double y[kTb];
+  double y[1][kTb];
   const double* src = S0 + L.S + int64_t(t < srows ? t : 0) * kTb;
 #pragma unroll
-  for (int cc = 0; cc < kTb; ++cc) y[cc] = t < srows ? src[cc] : 0.0;
-  rowblock_qr<kTsqrStack / 64>(y, t, g.jb, sred, srow, sfin, sv0, sbeta);
+  for (int cc = 0; cc < kTb; ++cc) y[0][cc] = t < srows ? src[cc] : 0.0;
+  rowblock_qr<BS / 64, 1>(y, g.jb, sred, srow, sfin, sv0, sbeta);
   double* V = S0 + L.Vs;
-  if (t < srows) store_vrow(y, t, g.jb, sv0, V + int64_t(t) * kTb);
+  if (t < srows) store_vrow(y[0], t, g.jb, sv0, V + int64_t(t) * kTb);
   if (t < g.jb) {
     double* dst = M + int64_t(j0 + t) * ld + j0;
 #pragma unroll
     for (int cc = 0; cc < kTb; ++cc)
-      if (cc < g.jb) dst[cc] = cc >= t ? y[cc] : 0.0;
+      if (cc < g.jb) dst[cc] = cc >= t ? y[0][cc] : 0.0;
   }
   __syncthreads();
   build_T(V, srows, sbeta, sG, sT, S0 + L.Ts);
@@ -570,11 +596,11 @@ __device__ void apply_wy_tile(const double* V, int rows, const double* Tm, RowP 
 }
 
 // K3: trailing update of chunk blockIdx.y, column tile blockIdx.x.
-__global__ __launch_bounds__(256) void k_tsqr_apply_chunk(QrBatch A, int j0) {
+__global__ __launch_bounds__(256) void k_tsqr_apply_chunk(QrBatch A, int j0, int cr) {
   const int q = blockIdx.z, c = blockIdx.y;
   const int m = A.rows[q], n = A.cols[q];
   if (m <= n || j0 >= n) return;
-  const PanelGeom g = panel_geom(m, n, j0);
+  const PanelGeom g = panel_geom(m, n, j0, cr);
   if (c >= g.nck) return;
   const int c0 = j0 + g.jb + blockIdx.x * 64;
   if (c0 >= n) return;
@@ -591,11 +617,11 @@ __global__ __launch_bounds__(256) void k_tsqr_apply_chunk(QrBatch A, int j0) {
 }
 
 // K4: trailing update of the chunk top rows with the stack's WY form.
-__global__ __launch_bounds__(256) void k_tsqr_apply_stack(QrBatch A, int j0) {
+__global__ __launch_bounds__(256) void k_tsqr_apply_stack(QrBatch A, int j0, int cr) {
   const int q = blockIdx.y;
   const int m = A.rows[q], n = A.cols[q];
   if (m <= n || j0 >= n) return;
-  const PanelGeom g = panel_geom(m, n, j0);
+  const PanelGeom g = panel_geom(m, n, j0, cr);
   if (g.nck < 2) return;
   const int c0 = j0 + g.jb + blockIdx.x * 64;
   if (c0 >= n) return;
@@ -798,16 +824,32 @@ __global__ __launch_bounds__(256) void k_gemm_tiles(const GemmDesc* D, int nd) {
 
 void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t s) {
   if (A.nprob == 0) return;
-  if (tsqr_chunks(max_rows) * kTsqrNb <= kTsqrStack) {
-    const unsigned nckmax = unsigned(tsqr_chunks(max_rows));
+  // chunks of 256 rows (one per thread), or of 1024 rows (two per thread)
+  // when the stack of 256-row chunk factors would exceed kTsqrStack rows
+  int rpt = 0;
+  if (tsqr_chunks(max_rows) * kTsqrNb <= kTsqrStack)
+    rpt = 1;
+  else if (((max_rows + 4 * kTsqrRows - 1) / (4 * kTsqrRows)) * kTsqrNb <= kTsqrStack)
+    rpt = 2;
+  if (rpt > 0) {
+    const int cr = rpt == 1 ? kTsqrRows : 4 * kTsqrRows;
+    const unsigned nckmax = unsigned((max_rows + cr - 1) / cr);
     for (int j0 = 0; j0 < max_cols; j0 += kTsqrNb) {
-      hipLaunchKernelGGL(k_tsqr_chunk, dim3(nckmax, A.nprob), dim3(kTsqrRows), 0, s, A, j0);
-      hipLaunchKernelGGL(k_tsqr_stack, dim3(A.nprob), dim3(kTsqrStack), 0, s, A, j0);
+      if (rpt == 1)
+        hipLaunchKernelGGL(k_tsqr_chunk<1>, dim3(nckmax, A.nprob), dim3(kTsqrRows), 0, s, A, j0, cr);
+      else
+        hipLaunchKernelGGL(k_tsqr_chunk<2>, dim3(nckmax, A.nprob), dim3(2 * kTsqrRows), 0, s, A, j0, cr);
+      if (nckmax * kTsqrNb <= 256)  // block sized to the tallest stack (one row per thread)
+        hipLaunchKernelGGL(k_tsqr_stack<256>, dim3(A.nprob), dim3(256), 0, s, A, j0, cr);
+      else if (nckmax * kTsqrNb <= 512)
+        hipLaunchKernelGGL(k_tsqr_stack<512>, dim3(A.nprob), dim3(512), 0, s, A, j0, cr);
+      else
+        hipLaunchKernelGGL(k_tsqr_stack<kTsqrStack>, dim3(A.nprob), dim3(kTsqrStack), 0, s, A, j0, cr);
       const int rem = max_cols - j0 - kTsqrNb;
       if (rem > 0) {
         const unsigned tiles = unsigned((rem + 63) / 64);
-        hipLaunchKernelGGL(k_tsqr_apply_chunk, dim3(tiles, nckmax, A.nprob), dim3(256), 0, s, A, j0);
-        hipLaunchKernelGGL(k_tsqr_apply_stack, dim3(tiles, A.nprob), dim3(256), 0, s, A, j0);
+        hipLaunchKernelGGL(k_tsqr_apply_chunk, dim3(tiles, nckmax, A.nprob), dim3(256), 0, s, A, j0, cr);
+        hipLaunchKernelGGL(k_tsqr_apply_stack, dim3(tiles, A.nprob), dim3(256), 0, s, A, j0, cr);
       }
     }
     hipLaunchKernelGGL(k_qr_clear_lower, dim3(64, A.nprob), dim3(256), 0, s, A);

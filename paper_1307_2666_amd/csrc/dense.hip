@@ -561,30 +561,103 @@ __global__ __launch_bounds__(1024) void k_idm_perm(IdArgs A, IdmState S) {
   }
 }
 
-// T = R11^{-1} R12 in place over R12 (and the optional compact copy), one
-// thread per redundant column; R11[a][b] = M[a][perm[b]] above the diagonal,
+// T = R11^{-1} R12 in place over R12, by blocks of 64 rows from the bottom
+// (one launch per row block a0..a0+63): workgroup (tile, q) takes 64
+// redundant columns, subtracts R11[a0:a1, a1:k] T[a1:k, :] on the matrix
+// cores (pivot columns gathered through perm), then solves with the 64 x 64
+// diagonal block in LDS.  R11[a][b] = M[a][perm[b]] above the diagonal,
 // R11[a][a] = alpha[a].
-__global__ __launch_bounds__(256) void k_idm_T(IdArgs A, IdmState S) {
+constexpr int kTb64 = 64;
+__global__ __launch_bounds__(256) void k_idm_T_block(IdArgs A, IdmState S, int a0) {
+  const int q = blockIdx.y;
+  const int n = A.cols[q], k = A.rank[q];
+  if (a0 >= k) return;
+  const int nr = n - k;
+  const int c0 = blockIdx.x * kTb64;
+  if (c0 >= nr) return;
+  const int a1 = min(a0 + kTb64, k), nb = a1 - a0, nc = min(kTb64, nr - c0);
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const int32_t* perm = A.perm + A.poff[q];
+  const double* al = S.alpha + q * S.stride;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = wv >> 1, wc = wv & 1;
+  __shared__ int scol[kTb64];
+  __shared__ double sA[kTb64][17], sB[16][kTb64 + 1];
+  __shared__ double sX[kTb64][kTb64 + 1];  // right-hand sides, then the solution
+  __shared__ double sU[kTb64][kTb64 + 1];  // diagonal block
+  if (tid < kTb64) scol[tid] = tid < nc ? perm[k + c0 + tid] : perm[k + c0];
+  __syncthreads();
+  // 1. acc = R11[a0:a1, a1:k] T[a1:k, cols]
+  double4_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = double4_t{0.0, 0.0, 0.0, 0.0};
+  for (int b0 = a1; b0 < k; b0 += 16) {
+    for (int e = tid; e < kTb64 * 16; e += 256) {
+      const int i = e >> 4, kk = e & 15;
+      const int b = b0 + kk;
+      sA[i][kk] = (i < nb && b < k) ? M[int64_t(a0 + i) * ld + perm[b]] : 0.0;
+      const int kk2 = e >> 6, j = e & 63;
+      const int b2 = b0 + kk2;
+      sB[kk2][j] = (b2 < k && j < nc) ? M[int64_t(b2) * ld + scol[j]] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) af[x] = sA[wr * 32 + x * 16 + li][kk + lk];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bf[y] = sB[kk + lk][wc * 32 + y * 16 + li];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = mfma_f64(af[x], bf[y], acc[x][y]);
+    }
+    __syncthreads();
+  }
+  // 2. right-hand sides R12[a0:a1, cols] - acc and the diagonal block
+  for (int e = tid; e < kTb64 * kTb64; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    sX[i][j] = (i < nb && j < nc) ? M[int64_t(a0 + i) * ld + scol[j]] : 0.0;
+    sU[i][j] = (i < nb && j < nb) ? (i == j ? al[a0 + i] : (j > i ? M[int64_t(a0 + i) * ld + perm[a0 + j]] : 0.0))
+                                  : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sX[wr * 32 + x * 16 + 4 * v + lk][wc * 32 + y * 16 + li] -= acc[x][y][v];
+  __syncthreads();
+  // 3. back substitution with the diagonal block, one thread per column
+  if (tid < nc) {
+    const int j = tid;
+    for (int i = nb - 1; i >= 0; --i) {
+      double t = sX[i][j];
+      for (int b = i + 1; b < nb; ++b) t -= sU[i][b] * sX[b][j];
+      sX[i][j] = t / sU[i][i];
+    }
+    for (int i = 0; i < nb; ++i) M[int64_t(a0 + i) * ld + scol[j]] = sX[i][j];
+  }
+}
+
+// Compact copy of T (k x r row-major) for callers that ask for it.
+__global__ __launch_bounds__(256) void k_idm_Tcopy(IdArgs A) {
   const int q = blockIdx.y;
   const int n = A.cols[q], k = A.rank[q];
   const int nr = n - k;
   const int b2 = blockIdx.x * 256 + threadIdx.x;
   if (b2 >= nr) return;
-  double* M = A.base + A.moff[q];
+  const double* M = A.base + A.moff[q];
   const int ld = A.ld[q];
-  const int32_t* perm = A.perm + A.poff[q];
-  const double* al = S.alpha + q * S.stride;
-  const int col = perm[k + b2];
-  for (int a = k - 1; a >= 0; --a) {
-    const double* Ra = M + int64_t(a) * ld;
-    double t = Ra[col];
-    for (int b = a + 1; b < k; ++b) t -= Ra[perm[b]] * M[int64_t(b) * ld + col];
-    M[int64_t(a) * ld + col] = t / al[a];
-  }
-  if (A.Tout) {
-    double* T = A.Tout + A.toff[q];
-    for (int a = 0; a < k; ++a) T[int64_t(a) * nr + b2] = M[int64_t(a) * ld + col];
-  }
+  const int col = A.perm[A.poff[q] + k + b2];
+  double* T = A.Tout + A.toff[q];
+  for (int a = 0; a < k; ++a) T[int64_t(a) * nr + b2] = M[int64_t(a) * ld + col];
 }
 
 static void launch_id_multi(const IdArgs& A, int max_cols, hipStream_t s) {
@@ -612,7 +685,17 @@ static void launch_id_multi(const IdArgs& A, int max_cols, hipStream_t s) {
     }
   }
   hipLaunchKernelGGL(k_idm_perm, dim3(A.nprob), dim3(1024), 0, s, A, S);
-  hipLaunchKernelGGL(k_idm_T, dim3(unsigned((max_cols + 255) / 256), unsigned(A.nprob)), dim3(256), 0, s, A, S);
+  // ranks bound the row blocks of the triangular solve
+  std::vector<int32_t> hk(A.nprob);
+  HIF_HIP(hipMemcpyAsync(hk.data(), A.rank, sizeof(int32_t) * A.nprob, hipMemcpyDeviceToHost, s));
+  HIF_HIP(hipStreamSynchronize(s));
+  int kmax = 0;
+  for (int v : hk) kmax = std::max(kmax, v);
+  const dim3 tg(unsigned((max_cols + kTb64 - 1) / kTb64), unsigned(A.nprob));
+  for (int a0 = ((kmax - 1) / kTb64) * kTb64; kmax > 0 && a0 >= 0; a0 -= kTb64)
+    hipLaunchKernelGGL(k_idm_T_block, tg, dim3(256), 0, s, A, S, a0);
+  if (A.Tout)
+    hipLaunchKernelGGL(k_idm_Tcopy, dim3(unsigned((max_cols + 255) / 256), unsigned(A.nprob)), dim3(256), 0, s, A);
   HIF_HIP(hipGetLastError());
   HIF_HIP(hipStreamSynchronize(s));  // the state buffers are released on return
 }
@@ -820,7 +903,7 @@ __global__ __launch_bounds__(256) void k_rowqr(RowQrArgs A) {
 void launch_rowqr_auto(const RowQrArgs& A, int max_rows, int max_cols, hipStream_t s) {
   // Few large problems: per-panel launches spread each problem over many
   // workgroups; many small ones: one fused workgroup per problem.
-  if (A.nprob < 1024 && max_cols >= 96)
+  if (max_rows <= 32 * kTsqrStack || (A.nprob < 1024 && max_cols >= 96))
     launch_qr_batched(A, max_rows, max_cols, s);
   else
     launch_rowqr(A, s);
