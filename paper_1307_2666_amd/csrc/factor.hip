@@ -1322,7 +1322,12 @@ void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* kr, co
   {
     DBuf<int32_t> counts, mm;
     mm.alloc(2, mt);
-    int L = 0;
+    // Depths with fewer than N / leaf boxes always hold a box with more than
+    // leaf points; start one depth before the first that could satisfy the
+    // rule (its minimum count decides uniformity when the rule holds at once).
+    int L0 = 0;
+    while (L0 < 24 && (int64_t(1) << (D * L0)) * int64_t(H->leaf) < N) ++L0;
+    int L = L0 > 0 ? L0 - 1 : 0;
     int32_t prev_min = INT_MAX;
     for (;;) {
       const int64_t S = int64_t(1) << L;

@@ -362,8 +362,13 @@ constexpr int kMaxV = 8;       // right-hand sides per pass
 constexpr int kCapS = 4096;    // LDS doubles, small groups
 constexpr int kCapL = 16384;   // LDS doubles, large groups and the top block
 
+// The helpers below issue their global loads eight at a time before using
+// them, so that a single workgroup (one per large group) keeps many requests
+// in flight.  Indices past a block are guarded on both factors.
+constexpr int kU = 8;
+
 // y[v*ys + i] += sgn * sum_j M[i*ld + j] x[v*xs + j]   (one wave per row)
-__device__ void l_gemv_n(const double* __restrict__ M, int nrow, int ncol, int ld, const double* x, int xs, double* y,
+__device__ __forceinline__ void l_gemv_n(const double* __restrict__ M, int nrow, int ncol, int ld, const double* x, int xs, double* y,
                          int ys, int nv, double sgn) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int i = wv; i < nrow; i += nw) {
@@ -371,11 +376,22 @@ __device__ void l_gemv_n(const double* __restrict__ M, int nrow, int ncol, int l
     double acc[kMaxV];
 #pragma unroll
     for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
-    for (int j = lane; j < ncol; j += 64) {
-      const double mv = mr[j];
+    for (int j0 = 0; j0 < ncol; j0 += 64 * kU) {
+      double mv[kU];
 #pragma unroll
-      for (int v = 0; v < kMaxV; ++v)
-        if (v < nv) acc[v] += mv * x[v * xs + j];
+      for (int u = 0; u < kU; ++u) {
+        const int j = j0 + u * 64 + lane;
+        mv[u] = j < ncol ? mr[j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = j0 + u * 64 + lane;
+        if (j < ncol) {
+#pragma unroll
+          for (int v = 0; v < kMaxV; ++v)
+            if (v < nv) acc[v] += mv[u] * x[v * xs + j];
+        }
+      }
     }
 #pragma unroll
     for (int v = 0; v < kMaxV; ++v)
@@ -387,17 +403,23 @@ __device__ void l_gemv_n(const double* __restrict__ M, int nrow, int ncol, int l
 }
 
 // y[v*ys + j] += sgn * sum_i M[i*ld + j] x[v*xs + i]   (one thread per column)
-__device__ void l_gemv_t(const double* __restrict__ M, int nrow, int ncol, int ld, const double* x, int xs, double* y,
+__device__ __forceinline__ void l_gemv_t(const double* __restrict__ M, int nrow, int ncol, int ld, const double* x, int xs, double* y,
                          int ys, int nv, double sgn) {
   for (int j = threadIdx.x; j < ncol; j += blockDim.x) {
     double acc[kMaxV];
 #pragma unroll
     for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
-    for (int i = 0; i < nrow; ++i) {
-      const double mv = M[int64_t(i) * ld + j];
+    for (int i0 = 0; i0 < nrow; i0 += kU) {
+      double mv[kU];
 #pragma unroll
-      for (int v = 0; v < kMaxV; ++v)
-        if (v < nv) acc[v] += mv * x[v * xs + i];
+      for (int u = 0; u < kU; ++u) mv[u] = i0 + u < nrow ? M[int64_t(i0 + u) * ld + j] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (i0 + u < nrow) {
+#pragma unroll
+          for (int v = 0; v < kMaxV; ++v)
+            if (v < nv) acc[v] += mv[u] * x[v * xs + i0 + u];
+        }
     }
 #pragma unroll
     for (int v = 0; v < kMaxV; ++v)
@@ -405,32 +427,52 @@ __device__ void l_gemv_t(const double* __restrict__ M, int nrow, int ncol, int l
   }
 }
 
+// acc[v] = sum_{c < nb} seg[c * cs] x[v*xs + x0 + c]  (a row or column segment of LU)
+__device__ __forceinline__ void seg_dot(const double* seg, int64_t cs, int nb, const double* x, int xs, int x0, int nv,
+                                        double (&acc)[kMaxV]) {
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+  for (int c0 = 0; c0 < nb; c0 += kU) {
+    double l[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) l[u] = c0 + u < nb ? seg[(c0 + u) * cs] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (c0 + u < nb) {
+#pragma unroll
+        for (int v = 0; v < kMaxV; ++v)
+          if (v < nv) acc[v] += l[u] * x[v * xs + x0 + c0 + u];
+      }
+  }
+}
+
 // x = L^{-1} x, L the unit lower triangle of the row-major n x n LU.
-__device__ void l_solve_L(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
+__device__ __forceinline__ void l_solve_L(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   for (int j0 = 0; j0 < n; j0 += kNbT) {
     const int nb = min(kNbT, n - j0);
     const double* Lr = LU + int64_t(j0 + min(lane, nb - 1)) * n + j0;
     for (int v = wv; v < nv; v += nw) {
       double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
-      for (int c = 0; c < nb - 1; ++c) {
-        const double xc = __shfl(xi, c, 64);
-        if (lane > c && lane < nb) xi -= Lr[c] * xc;
+      for (int c0 = 0; c0 < nb - 1; c0 += kU) {
+        double lr[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) lr[u] = c0 + u < nb ? Lr[c0 + u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int c = c0 + u;
+          if (c < nb - 1) {
+            const double xc = __shfl(xi, c, 64);
+            if (lane > c && lane < nb) xi -= lr[u] * xc;
+          }
+        }
       }
       if (lane < nb) x[v * xs + j0 + lane] = xi;
     }
     __syncthreads();
     for (int i = j0 + nb + tid; i < n; i += blockDim.x) {
-      const double* row = LU + int64_t(i) * n + j0;
       double acc[kMaxV];
-#pragma unroll
-      for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
-      for (int c = 0; c < nb; ++c) {
-        const double l = row[c];
-#pragma unroll
-        for (int v = 0; v < kMaxV; ++v)
-          if (v < nv) acc[v] += l * x[v * xs + j0 + c];
-      }
+      seg_dot(LU + int64_t(i) * n + j0, 1, nb, x, xs, j0, nv, acc);
 #pragma unroll
       for (int v = 0; v < kMaxV; ++v)
         if (v < nv) x[v * xs + i] -= acc[v];
@@ -440,7 +482,7 @@ __device__ void l_solve_L(const double* __restrict__ LU, int n, double* x, int x
 }
 
 // x = U^{-1} x, U the upper triangle of the LU.
-__device__ void l_solve_U(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
+__device__ __forceinline__ void l_solve_U(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   if (n <= 0) return;
   for (int j0 = ((n - 1) / kNbT) * kNbT; j0 >= 0; j0 -= kNbT) {
@@ -448,25 +490,26 @@ __device__ void l_solve_U(const double* __restrict__ LU, int n, double* x, int x
     const double* Ur = LU + int64_t(j0 + min(lane, nb - 1)) * n + j0;
     for (int v = wv; v < nv; v += nw) {
       double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
-      for (int c = nb - 1; c >= 0; --c) {
-        if (lane == c) xi = xi / Ur[c];
-        const double xc = __shfl(xi, c, 64);
-        if (lane < c) xi -= Ur[c] * xc;
+      for (int cb = ((nb - 1) / kU) * kU; cb >= 0; cb -= kU) {
+        double ur[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) ur[u] = cb + u < nb ? Ur[cb + u] : 1.0;
+#pragma unroll
+        for (int u = kU - 1; u >= 0; --u) {
+          const int c = cb + u;
+          if (c < nb) {
+            if (lane == c) xi = xi / ur[u];
+            const double xc = __shfl(xi, c, 64);
+            if (lane < c) xi -= ur[u] * xc;
+          }
+        }
       }
       if (lane < nb) x[v * xs + j0 + lane] = xi;
     }
     __syncthreads();
     for (int i = tid; i < j0; i += blockDim.x) {
-      const double* row = LU + int64_t(i) * n + j0;
       double acc[kMaxV];
-#pragma unroll
-      for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
-      for (int c = 0; c < nb; ++c) {
-        const double u = row[c];
-#pragma unroll
-        for (int v = 0; v < kMaxV; ++v)
-          if (v < nv) acc[v] += u * x[v * xs + j0 + c];
-      }
+      seg_dot(LU + int64_t(i) * n + j0, 1, nb, x, xs, j0, nv, acc);
 #pragma unroll
       for (int v = 0; v < kMaxV; ++v)
         if (v < nv) x[v * xs + i] -= acc[v];
@@ -476,32 +519,37 @@ __device__ void l_solve_U(const double* __restrict__ LU, int n, double* x, int x
 }
 
 // x = U^{-T} x (U^T lower with diagonal U_jj), forward over column blocks.
-__device__ void l_solve_UT(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
+__device__ __forceinline__ void l_solve_UT(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   for (int j0 = 0; j0 < n; j0 += kNbT) {
     const int nb = min(kNbT, n - j0);
     const int cl = j0 + min(lane, nb - 1);
     for (int v = wv; v < nv; v += nw) {
       double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
-      for (int c = 0; c < nb; ++c) {
-        const double* Uc = LU + int64_t(j0 + c) * n;
-        if (lane == c) xi = xi / Uc[j0 + c];
-        const double xc = __shfl(xi, c, 64);
-        if (lane > c && lane < nb) xi -= Uc[cl] * xc;
+      for (int c0 = 0; c0 < nb; c0 += kU) {
+        double uc[kU], ud[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int c = c0 + u < nb ? c0 + u : nb - 1;
+          uc[u] = LU[int64_t(j0 + c) * n + cl];
+          ud[u] = LU[int64_t(j0 + c) * n + j0 + c];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int c = c0 + u;
+          if (c < nb) {
+            if (lane == c) xi = xi / ud[u];
+            const double xc = __shfl(xi, c, 64);
+            if (lane > c && lane < nb) xi -= uc[u] * xc;
+          }
+        }
       }
       if (lane < nb) x[v * xs + j0 + lane] = xi;
     }
     __syncthreads();
     for (int i = j0 + nb + tid; i < n; i += blockDim.x) {
       double acc[kMaxV];
-#pragma unroll
-      for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
-      for (int c = 0; c < nb; ++c) {
-        const double u = LU[int64_t(j0 + c) * n + i];
-#pragma unroll
-        for (int v = 0; v < kMaxV; ++v)
-          if (v < nv) acc[v] += u * x[v * xs + j0 + c];
-      }
+      seg_dot(LU + int64_t(j0) * n + i, n, nb, x, xs, j0, nv, acc);
 #pragma unroll
       for (int v = 0; v < kMaxV; ++v)
         if (v < nv) x[v * xs + i] -= acc[v];
@@ -511,7 +559,7 @@ __device__ void l_solve_UT(const double* __restrict__ LU, int n, double* x, int 
 }
 
 // x = L^{-T} x (L^T unit upper), backward over column blocks.
-__device__ void l_solve_LT(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
+__device__ __forceinline__ void l_solve_LT(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   if (n <= 0) return;
   for (int j0 = ((n - 1) / kNbT) * kNbT; j0 >= 0; j0 -= kNbT) {
@@ -519,23 +567,28 @@ __device__ void l_solve_LT(const double* __restrict__ LU, int n, double* x, int 
     const int cl = j0 + min(lane, nb - 1);
     for (int v = wv; v < nv; v += nw) {
       double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
-      for (int c = nb - 1; c > 0; --c) {
-        const double xc = __shfl(xi, c, 64);
-        if (lane < c) xi -= LU[int64_t(j0 + c) * n + cl] * xc;
+      for (int cb = ((nb - 1) / kU) * kU; cb >= 0; cb -= kU) {
+        double lc[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int c = cb + u < nb ? cb + u : nb - 1;
+          lc[u] = LU[int64_t(j0 + c) * n + cl];
+        }
+#pragma unroll
+        for (int u = kU - 1; u >= 0; --u) {
+          const int c = cb + u;
+          if (c < nb && c > 0) {
+            const double xc = __shfl(xi, c, 64);
+            if (lane < c) xi -= lc[u] * xc;
+          }
+        }
       }
       if (lane < nb) x[v * xs + j0 + lane] = xi;
     }
     __syncthreads();
     for (int i = tid; i < j0; i += blockDim.x) {
       double acc[kMaxV];
-#pragma unroll
-      for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
-      for (int c = 0; c < nb; ++c) {
-        const double l = LU[int64_t(j0 + c) * n + i];
-#pragma unroll
-        for (int v = 0; v < kMaxV; ++v)
-          if (v < nv) acc[v] += l * x[v * xs + j0 + c];
-      }
+      seg_dot(LU + int64_t(j0) * n + i, n, nb, x, xs, j0, nv, acc);
 #pragma unroll
       for (int v = 0; v < kMaxV; ++v)
         if (v < nv) x[v * xs + i] -= acc[v];
@@ -545,7 +598,7 @@ __device__ void l_solve_LT(const double* __restrict__ LU, int n, double* x, int 
 }
 
 // x = P x (fwd) or P^T x through the scratch tp, both [nv][n] in LDS.
-__device__ void l_permute(const int32_t* perm, int n, double* x, double* tp, int nv, bool fwd) {
+__device__ __forceinline__ void l_permute(const int32_t* perm, int n, double* x, double* tp, int nv, bool fwd) {
   for (int e = threadIdx.x; e < nv * n; e += blockDim.x) {
     const int v = e / n, i = e % n;
     if (fwd)
