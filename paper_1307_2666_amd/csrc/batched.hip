@@ -334,10 +334,36 @@ __device__ __forceinline__ void rs_step(double (&p)[kTb], int lane) {
     p[i] = keep + __shfl_xor(send, 2 * H, 64);
   }
 }
+// Pair sums across lane halves with the gfx950 lane-swap instructions:
+// (a, b) = this lane's values of indices i and i + h; the result is the sum
+// of index i over lanes l and l ^ 2h for the lower lane of each pair and of
+// index i + h for the upper one (h = 16: halves of the wave, h = 8: rows of
+// 16 lanes).  The sum does not depend on which output holds which half.
+template <int H>
+__device__ __forceinline__ double swap_pair_sum(double a, double b) {
+  const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  const unsigned alo = unsigned(ua), ahi = unsigned(ua >> 32), blo = unsigned(ub), bhi = unsigned(ub >> 32);
+  unsigned r0l, r1l, r0h, r1h;
+  if constexpr (H == 16) {
+    const auto rl = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    r0l = rl[0]; r1l = rl[1]; r0h = rh[0]; r1h = rh[1];
+  } else {
+    const auto rl = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    r0l = rl[0]; r1l = rl[1]; r0h = rh[0]; r1h = rh[1];
+  }
+  const double r0 = __longlong_as_double((static_cast<long long>(r0h) << 32) | r0l);
+  const double r1 = __longlong_as_double((static_cast<long long>(r1h) << 32) | r1l);
+  return r0 + r1;
+}
+
 __device__ __forceinline__ double wave_rs32(double (&p)[kTb]) {
   const int lane = threadIdx.x & 63;
-  rs_step<16>(p, lane);
-  rs_step<8>(p, lane);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) p[i] = swap_pair_sum<16>(p[i], p[i + 16]);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) p[i] = swap_pair_sum<8>(p[i], p[i + 8]);
   rs_step<4>(p, lane);
   rs_step<2>(p, lane);
   rs_step<1>(p, lane);
@@ -346,21 +372,24 @@ __device__ __forceinline__ double wave_rs32(double (&p)[kTb]) {
 
 // Householder QR of a block of at most RPT * blockDim.x rows and jb <= kTb
 // columns held RPT rows per thread (thread t: rows t + u * blockDim.x; rows
-// past the block are zero).  One reduction round per column gives the norm of
-// the column below the diagonal and its products with the later columns.  On
-// return rows < jb hold R (upper part) and rows > jj hold the Householder
-// vector of column jj below the diagonal; v0 (its diagonal entry) and
-// beta = 2 / v^T v are in sv0 / sbeta.
+// past the block are zero).  Per column one reduction round gives, over the
+// rows below the diagonal, the squared norm and the products with the later
+// columns; the first kTb threads then turn them into the reflector (alpha,
+// v0, beta) and the update coefficient of every column, which all threads
+// read back from LDS.  On return rows < jb hold R (upper part) and rows > jj
+// hold the Householder vector of column jj below the diagonal; v0 (its
+// diagonal entry) and beta = 2 / v^T v are in sv0 / sbeta.
+// LDS: sred [2][NW][kTb], srow [2][kTb], scf [2][kTb + 2].
 template <int NW, int RPT>
-__device__ void rowblock_qr(double (&y)[RPT][kTb], int jb, double* sred, double* srow, double* sfin, double* sv0,
+__device__ void rowblock_qr(double (&y)[RPT][kTb], int jb, double* sred, double* srow, double* scf, double* sv0,
                             double* sbeta) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t0 = threadIdx.x, B = blockDim.x;
   for (int jj = 0; jj < jb; ++jj) {
-    const int b = jj & 1;  // double-buffered so one barrier pair per column suffices
+    const int b = jj & 1;  // double-buffered: one barrier pair per column
     double* red = sred + b * NW * kTb;
     double* row = srow + b * kTb;
-    double* fin = sfin + b * kTb;
+    double* cf = scf + b * (kTb + 2);
     double yj[RPT];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) yj[u] = pick(y[u], jj);
@@ -369,50 +398,62 @@ __device__ void rowblock_qr(double (&y)[RPT][kTb], int jb, double* sred, double*
       for (int c = 0; c < kTb; ++c) row[c] = y[0][c];
     }
     double p[kTb];
+    {
+      double e[RPT];
 #pragma unroll
-    for (int c = 0; c < kTb; ++c) {
-      double acc = 0.0;
+      for (int u = 0; u < RPT; ++u) e[u] = t0 + u * B > jj ? yj[u] : 0.0;
 #pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        const int t = t0 + u * B;
-        acc += (t > jj || (t == jj && c == jj)) ? yj[u] * y[u][c] : 0.0;
+      for (int c = 0; c < kTb; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) acc += e[u] * y[u][c];
+        p[c] = acc;
       }
-      p[c] = acc;
     }
     const double w = wave_rs32(p);
     if ((lane & 1) == 0) red[wv * kTb + (lane >> 1)] = w;
     __syncthreads();
-    if (threadIdx.x < kTb) {
-      double s2 = 0.0;
+    if (t0 < kTb) {
+      const int c = t0;
+      double sc = 0.0, sj = 0.0;
 #pragma unroll
-      for (int w2 = 0; w2 < NW; ++w2) s2 += red[w2 * kTb + threadIdx.x];
-      fin[threadIdx.x] = s2;
+      for (int w2 = 0; w2 < NW; ++w2) {
+        sc += red[w2 * kTb + c];
+        sj += red[w2 * kTb + jj];
+      }
+      const double x0 = row[jj];
+      const double ss = sj + x0 * x0;
+      const double nrm = sqrt(ss);
+      const double alpha = nrm > 0.0 ? -copysign(nrm, x0) : 0.0;
+      const double v0 = x0 - alpha;
+      const double vtv = sj + v0 * v0;
+      const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+      cf[c] = (c > jj && c < jb) ? beta * (v0 * row[c] + sc) : 0.0;
+      if (c == 0) {
+        cf[kTb] = alpha;
+        cf[kTb + 1] = v0;
+        sv0[jj] = v0;
+        sbeta[jj] = beta;
+      }
     }
     __syncthreads();
-    const double ss = fin[jj], x0 = row[jj];
-    const double nrm = sqrt(ss);
-    const double alpha = nrm > 0.0 ? -copysign(nrm, x0) : 0.0;
-    const double v0 = x0 - alpha;
-    const double vtv = ss - x0 * x0 + v0 * v0;
-    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    const double alpha = cf[kTb], v0 = cf[kTb + 1];
+    double coef[kTb];
+#pragma unroll
+    for (int c = 0; c < kTb; ++c) coef[c] = cf[c];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       const int t = t0 + u * B;
       if (t >= jj) {
         const double vt = t == jj ? v0 : yj[u];
 #pragma unroll
-        for (int c = 0; c < kTb; ++c)
-          if (c > jj && c < jb) y[u][c] -= beta * (v0 * row[c] + fin[c]) * vt;
-        if (t == jj) {
+        for (int c = 0; c < kTb; ++c) y[u][c] -= coef[c] * vt;
+        if (u == 0 && t == jj) {  // row jj < kTb lives in slot 0
 #pragma unroll
           for (int c = 0; c < kTb; ++c)
             if (c == jj) y[u][c] = alpha;
         }
       }
-    }
-    if (threadIdx.x == 0) {
-      sv0[jj] = v0;
-      sbeta[jj] = beta;
     }
   }
   __syncthreads();
@@ -429,8 +470,9 @@ __device__ __forceinline__ void store_vrow(const double (&y)[kTb], int t, int jb
 __device__ void build_T(const double* V, int rows, const double* sbeta, double* sG, double* sT, double* Tout) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  if (wv < 4) {
-    const int p0 = (wv >> 1) * 16, p1 = (wv & 1) * 16;
+  const int nw = blockDim.x >> 6;
+  for (int tile = wv; tile < 4; tile += nw) {
+    const int p0 = (tile >> 1) * 16, p1 = (tile & 1) * 16;
     double4_t acc = {0.0, 0.0, 0.0, 0.0};
     for (int kb = 0; kb < rows; kb += 32) {  // 8 steps of 4 rows, loads issued first
       double a[8], b[8];
@@ -461,10 +503,9 @@ __device__ void build_T(const double* V, int rows, const double* sbeta, double* 
   for (int e = threadIdx.x; e < kTb * kTb; e += blockDim.x) Tout[e] = sT[e];
 }
 
-// K1: QR of one chunk of the panel (chunks of at most cr = RPT * blockDim.x rows).
-template <int RPT>
-__global__ __launch_bounds__(kTsqrRows * RPT) void k_tsqr_chunk(QrBatch A, int j0, int cr) {
-  constexpr int kB = kTsqrRows * RPT;
+// K1: QR of one chunk of the panel (chunks of at most cr = BS * RPT rows).
+template <int BS, int RPT>
+__global__ __launch_bounds__(BS) void k_tsqr_chunk(QrBatch A, int j0, int cr) {
   const int q = blockIdx.y, c = blockIdx.x;
   const int m = A.rows[q], n = A.cols[q];
   if (m <= n || j0 >= n) return;
@@ -476,21 +517,21 @@ __global__ __launch_bounds__(kTsqrRows * RPT) void k_tsqr_chunk(QrBatch A, int j
   double* S0 = A.scratch + A.soff[q];
   const TsqrLayout L = tsqr_layout(m);
   const int t0 = threadIdx.x;
-  __shared__ double sred[2 * (kB / 64) * kTb], srow[2 * kTb], sfin[2 * kTb], sv0[kTb], sbeta[kTb];
+  __shared__ double sred[2 * (BS / 64) * kTb], srow[2 * kTb], scf[2 * (kTb + 2)], sv0[kTb], sbeta[kTb];
   __shared__ double sG[kTb * (kTb + 1)], sT[kTb * kTb];
   double y[RPT][kTb];
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
-    const int t = t0 + u * kB;
+    const int t = t0 + u * BS;
     const double* src = M + int64_t(j0 + lo + (t < rows ? t : 0)) * ld + j0;
 #pragma unroll
     for (int cc = 0; cc < kTb; ++cc) y[u][cc] = (t < rows && cc < g.jb) ? src[cc] : 0.0;
   }
-  rowblock_qr<kB / 64, RPT>(y, g.jb, sred, srow, sfin, sv0, sbeta);
+  rowblock_qr<BS / 64, RPT>(y, g.jb, sred, srow, scf, sv0, sbeta);
   double* V = S0 + L.V + int64_t(lo) * kTb;
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
-    const int t = t0 + u * kB;
+    const int t = t0 + u * BS;
     if (t < rows) store_vrow(y[u], t, g.jb, sv0, V + int64_t(t) * kTb);
   }
   if (g.nck == 1) {
@@ -510,7 +551,7 @@ __global__ __launch_bounds__(kTsqrRows * RPT) void k_tsqr_chunk(QrBatch A, int j
 }
 
 // K2: QR of the stacked chunk R factors (nck > 1); writes the panel's R.
-template <int BS>
+template <int BS, int RPT>
 __global__ __launch_bounds__(BS) void k_tsqr_stack(QrBatch A, int j0, int cr) {
   const int q = blockIdx.x;
   const int m = A.rows[q], n = A.cols[q];
@@ -523,15 +564,23 @@ __global__ __launch_bounds__(BS) void k_tsqr_stack(QrBatch A, int j0, int cr) {
   double* S0 = A.scratch + A.soff[q];
   const TsqrLayout L = tsqr_layout(m);
   const int t = threadIdx.x;
-  __shared__ double sred[2 * (BS / 64) * kTb], srow[2 * kTb], sfin[2 * kTb], sv0[kTb], sbeta[kTb];
+  __shared__ double sred[2 * (BS / 64) * kTb], srow[2 * kTb], scf[2 * (kTb + 2)], sv0[kTb], sbeta[kTb];
   __shared__ double sG[kTb * (kTb + 1)], sT[kTb * kTb];
-  double y[1][kTb];
-  const double* src = S0 + L.S + int64_t(t < srows ? t : 0) * kTb;
+  double y[RPT][kTb];
 #pragma unroll
-  for (int cc = 0; cc < kTb; ++cc) y[0][cc] = t < srows ? src[cc] : 0.0;
-  rowblock_qr<BS / 64, 1>(y, g.jb, sred, srow, sfin, sv0, sbeta);
+  for (int u = 0; u < RPT; ++u) {
+    const int tu = t + u * BS;
+    const double* src = S0 + L.S + int64_t(tu < srows ? tu : 0) * kTb;
+#pragma unroll
+    for (int cc = 0; cc < kTb; ++cc) y[u][cc] = tu < srows ? src[cc] : 0.0;
+  }
+  rowblock_qr<BS / 64, RPT>(y, g.jb, sred, srow, scf, sv0, sbeta);
   double* V = S0 + L.Vs;
-  if (t < srows) store_vrow(y[0], t, g.jb, sv0, V + int64_t(t) * kTb);
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int tu = t + u * BS;
+    if (tu < srows) store_vrow(y[u], tu, g.jb, sv0, V + int64_t(tu) * kTb);
+  }
   if (t < g.jb) {
     double* dst = M + int64_t(j0 + t) * ld + j0;
 #pragma unroll
@@ -835,16 +884,17 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
     const int cr = rpt == 1 ? kTsqrRows : 4 * kTsqrRows;
     const unsigned nckmax = unsigned((max_rows + cr - 1) / cr);
     for (int j0 = 0; j0 < max_cols; j0 += kTsqrNb) {
+      // two rows per thread: 128 threads per 256-row chunk, 512 per 1024-row chunk
       if (rpt == 1)
-        hipLaunchKernelGGL(k_tsqr_chunk<1>, dim3(nckmax, A.nprob), dim3(kTsqrRows), 0, s, A, j0, cr);
+        hipLaunchKernelGGL((k_tsqr_chunk<128, 2>), dim3(nckmax, A.nprob), dim3(128), 0, s, A, j0, cr);
       else
-        hipLaunchKernelGGL(k_tsqr_chunk<2>, dim3(nckmax, A.nprob), dim3(2 * kTsqrRows), 0, s, A, j0, cr);
-      if (nckmax * kTsqrNb <= 256)  // block sized to the tallest stack (one row per thread)
-        hipLaunchKernelGGL(k_tsqr_stack<256>, dim3(A.nprob), dim3(256), 0, s, A, j0, cr);
+        hipLaunchKernelGGL((k_tsqr_chunk<512, 2>), dim3(nckmax, A.nprob), dim3(512), 0, s, A, j0, cr);
+      if (nckmax * kTsqrNb <= 256)  // block sized to the tallest stack (two rows per thread)
+        hipLaunchKernelGGL((k_tsqr_stack<128, 2>), dim3(A.nprob), dim3(128), 0, s, A, j0, cr);
       else if (nckmax * kTsqrNb <= 512)
-        hipLaunchKernelGGL(k_tsqr_stack<512>, dim3(A.nprob), dim3(512), 0, s, A, j0, cr);
+        hipLaunchKernelGGL((k_tsqr_stack<256, 2>), dim3(A.nprob), dim3(256), 0, s, A, j0, cr);
       else
-        hipLaunchKernelGGL(k_tsqr_stack<kTsqrStack>, dim3(A.nprob), dim3(kTsqrStack), 0, s, A, j0, cr);
+        hipLaunchKernelGGL((k_tsqr_stack<512, 2>), dim3(A.nprob), dim3(512), 0, s, A, j0, cr);
       const int rem = max_cols - j0 - kTsqrNb;
       if (rem > 0) {
         const unsigned tiles = unsigned((rem + 63) / 64);
