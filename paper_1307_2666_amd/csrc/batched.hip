@@ -28,6 +28,32 @@ __device__ __forceinline__ AM am_better(AM a, AM b) {
   if (b.v > a.v || (b.v == a.v && b.i < a.i)) return b;
   return a;
 }
+__device__ __forceinline__ double pick16(const double (&y)[kNb], int j) {
+  double r = 0.0;
+#pragma unroll
+  for (int c = 0; c < kNb; ++c)
+    if (c == j) r = y[c];
+  return r;
+}
+
+// Block-wide argmax (larger value, ties to the lower index) for up to 1024 threads.
+__device__ AM block_argmax_n(AM x) {
+  __shared__ double sv[16];
+  __shared__ int si[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    AM y{__shfl_xor(x.v, o, 64), __shfl_xor(x.i, o, 64)};
+    x = am_better(x, y);
+  }
+  if (lane == 0) { sv[wv] = x.v; si[wv] = x.i; }
+  __syncthreads();
+  AM r{-1.0, INT_MAX};
+  for (int k = 0; k < nw; ++k) r = am_better(r, AM{sv[k], si[k]});
+  __syncthreads();
+  return r;
+}
+
 __device__ AM block_argmax256(AM x) {
   __shared__ double sv[4];
   __shared__ int si[4];
@@ -762,6 +788,131 @@ __global__ __launch_bounds__(256) void k_lu_panel(LuBatch A, int j0) {
   }
 }
 
+// Register-resident panel for panels of at most kLpRows rows (rows j0..n-1):
+// thread t holds rows j0 + t and j0 + t + kLpThreads of the kNb panel
+// columns for all kNb elimination steps; the pivot row is exchanged and
+// broadcast through LDS.  The row interchanges are then applied in order to
+// the columns outside the panel (one thread per column) and U12 is formed.
+constexpr int kLpThreads = 1024;
+constexpr int kLpRows = 2 * kLpThreads;
+
+__global__ __launch_bounds__(kLpThreads) void k_lu_panel_reg(LuBatch A, int j0) {
+  const int q = blockIdx.x;
+  const int n = A.n[q], r = A.r[q];
+  if (j0 >= r) return;
+  double* M = A.base + A.moff[q];
+  int32_t* piv = A.piv + A.poff[q];
+  const int jb = min(kNb, r - j0);
+  const int tid = threadIdx.x;
+  __shared__ double sA[kNb], sB[kNb];
+  __shared__ int spiv[kNb];
+  double y[2][kNb];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int R = j0 + tid + u * kLpThreads;
+    const double* src = M + int64_t(R < n ? R : j0) * n + j0;
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) y[u][c] = (R < n && c < jb) ? src[c] : 0.0;
+  }
+  for (int jj = 0; jj < jb; ++jj) {
+    const int j = j0 + jj;
+    AM loc{-1.0, INT_MAX};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int R = j0 + tid + u * kLpThreads;
+      if (R >= j && R < r) loc = am_better(loc, AM{fabs(pick16(y[u], jj)), R});
+    }
+    const AM best = block_argmax_n(loc);
+    if (!(best.v > 0.0)) {
+      if (tid == 0) atomicOr(A.status, 1);
+      return;
+    }
+    const int p = best.i;
+    // rows j (slot 0 of thread jj) and p trade places; everyone reads the new row j
+    const int tp = (p - j0) % kLpThreads, up = (p - j0) / kLpThreads;
+    if (tid == jj) {
+#pragma unroll
+      for (int c = 0; c < kNb; ++c) sA[c] = y[0][c];
+    }
+    if (tid == tp) {
+#pragma unroll
+      for (int c = 0; c < kNb; ++c) sB[c] = up == 0 ? y[0][c] : y[1][c];
+    }
+    if (tid == 0) spiv[jj] = p;
+    __syncthreads();
+    const double* prow = sB;  // the new row j, read from LDS
+    if (p != j) {
+      if (tid == jj) {
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) y[0][c] = prow[c];
+      }
+      if (tid == tp) {
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) {
+          if (up == 0) y[0][c] = sA[c]; else y[1][c] = sA[c];
+        }
+      }
+    }
+    const double inv = 1.0 / prow[jj];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int R = j0 + tid + u * kLpThreads;
+      if (R > j && R < n) {
+        const double l = pick16(y[u], jj) * inv;
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) {
+          if (c == jj) y[u][c] = l;
+          else if (c > jj) y[u][c] -= l * prow[c];
+        }
+      }
+    }
+    __syncthreads();  // sA / sB are rewritten by the next step
+  }
+  // panel back to memory
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int R = j0 + tid + u * kLpThreads;
+    if (R < n) {
+      double* dst = M + int64_t(R) * n + j0;
+#pragma unroll
+      for (int c = 0; c < kNb; ++c)
+        if (c < jb) dst[c] = y[u][c];
+    }
+  }
+  if (tid < jb) piv[j0 + tid] = spiv[tid];
+  // interchanges on the columns outside the panel, in order
+  for (int col = tid; col < n; col += kLpThreads) {
+    if (col >= j0 && col < j0 + jb) continue;
+    for (int jj = 0; jj < jb; ++jj) {
+      const int pj = spiv[jj];
+      if (pj != j0 + jj) {
+        const double t = M[int64_t(j0 + jj) * n + col];
+        M[int64_t(j0 + jj) * n + col] = M[int64_t(pj) * n + col];
+        M[int64_t(pj) * n + col] = t;
+      }
+    }
+  }
+  __syncthreads();
+  // U12 = L11^{-1} A12 (rows j0..j0+jb-1, columns j0+jb..n-1)
+  for (int c = j0 + jb + tid; c < n; c += kLpThreads) {
+    double x[kNb];
+#pragma unroll
+    for (int i = 0; i < kNb; ++i) x[i] = i < jb ? M[int64_t(j0 + i) * n + c] : 0.0;
+#pragma unroll
+    for (int i = 1; i < kNb; ++i) {
+      if (i >= jb) break;
+      double v = x[i];
+#pragma unroll
+      for (int p2 = 0; p2 < kNb; ++p2)
+        if (p2 < i) v -= M[int64_t(j0 + i) * n + j0 + p2] * x[p2];
+      x[i] = v;
+    }
+#pragma unroll
+    for (int i = 1; i < kNb; ++i)
+      if (i < jb) M[int64_t(j0 + i) * n + c] = x[i];
+  }
+}
+
 // Trailing update A22 -= L21 U12 of one 64 x 64 tile (K = panel width).
 __global__ __launch_bounds__(256) void k_lu_update(LuBatch A, int j0) {
   const int q = blockIdx.z;
@@ -922,7 +1073,10 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
 void launch_lu_batched(const LuBatch& A, int max_r, int max_n, hipStream_t s) {
   if (A.nprob == 0) return;
   for (int j0 = 0; j0 < max_r; j0 += kNb) {
-    hipLaunchKernelGGL(k_lu_panel, dim3(A.nprob), dim3(256), 0, s, A, j0);
+    if (max_n - j0 <= kLpRows)
+      hipLaunchKernelGGL(k_lu_panel_reg, dim3(A.nprob), dim3(kLpThreads), 0, s, A, j0);
+    else
+      hipLaunchKernelGGL(k_lu_panel, dim3(A.nprob), dim3(256), 0, s, A, j0);
     const int rem = max_n - j0 - 1;
     if (rem > 0) {
       const unsigned tiles = unsigned((rem + 63) / 64);

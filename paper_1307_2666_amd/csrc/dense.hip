@@ -702,7 +702,7 @@ static void launch_id_multi(const IdArgs& A, int max_cols, hipStream_t s) {
 
 void launch_id(const IdArgs& A, int max_cols, hipStream_t s) {
   if (A.nprob == 0) return;
-  if (A.nprob <= 1024 && max_cols >= 384) {
+  if (A.nprob <= 2048 && max_cols >= 128) {
     launch_id_multi(A, max_cols, s);
     return;
   }
