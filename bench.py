@@ -27,6 +27,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6  # MI355X: 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per factorization moved by the ID step kernel on this workload,
+# from rocprofv3 FETCH_SIZE + WRITE_SIZE runs of `bench.py --steps 1 --warmup 0
+# --no-cpu-baseline --no-refine --calib-copy`, each scaled by what the counter
+# reads for a 256 MiB copy kernel.  Valid for the current k_idm_step only.
+ID_STEP_TRAFFIC_BYTES = 5.868e11
 
 
 def parse():
@@ -38,6 +43,8 @@ def parse():
     p.add_argument("--eps", type=float, default=None)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", default="sq128")
+    p.add_argument("--calib-copy", action="store_true",
+                   help="after the timed region, run one plain 256 MiB device copy kernel (scale for HBM counters)")
     p.add_argument("--no-refine", action="store_true",
                    help="skip the FP64 vs FP32-mixed comparison with GMRES refinement")
     return p.parse_args()
@@ -160,14 +167,18 @@ def main():
     st = F.stats()
     F.free()
 
-    # Dominant kernel: the batched ID (FP64 vector ALU); algorithmic flops from
-    # the realized (m, n_c, k) of every class, time from HIP events on the
-    # library's stream around its launches.
+    # Dominant kernel: the pivoted-QR ID (k_idm_step, one launch per pivot step
+    # over all large classes, and k_id for many small ones).  Each step reads
+    # and writes the trailing block, so it is bound by HBM; algorithmic bytes
+    # from the realized rows, columns and ranks of every class, time from the
+    # HIP events the library records on its own stream around those launches.
     ph = {k: float(np.mean([s["t_phase_ms"][k] for s in stats])) for k in stats[0]["t_phase_ms"]}
     id_flops = float(np.sum(st["sub_id_flops"]))
+    id_bytes = float(np.sum(st["sub_id_bytes"]))
     id_ms = ph["id"]
     el_flops = float(np.sum(st["sub_elim_flops"]))
-    achieved = id_flops / (id_ms * 1e-3) / 1e12 if id_ms > 0 else 0.0
+    rq_flops = float(np.sum(st["sub_rowqr_flops"]))
+    achieved = id_bytes / (id_ms * 1e-3) / 1e9 if id_ms > 0 else 0.0
     line = {
         "metric": "factor+solve unknowns/s at rel.err <=1e-6 vs oracle",
         "value": N / dt,
@@ -192,16 +203,28 @@ def main():
         "sub_ms": [{k: round(v, 3) for k, v in d.items() if v > 0} for d in st["sub_t_ms"]],
         "top_size": st["top_size"],
         "factor_bytes": st["factor_bytes"],
-        "roofline": {"kernel": "k_id (batched column-pivoted QR ID)", "bound": "alu",
-                     "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
-                     "flops_per_step": id_flops, "ms_per_step": id_ms},
+        "roofline": {"kernel": "k_idm_step + k_id (column-pivoted QR of the IDs, all launches of a step)",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": ID_STEP_TRAFFIC_BYTES if wl.name == "sq512" and abs(eps - 1e-6) < 1e-12 else None,
+                     "bytes_per_step": id_bytes, "ms_per_step": id_ms,
+                     "flops_per_step": id_flops,
+                     "fp64_tflops": id_flops / (id_ms * 1e-3) / 1e12 if id_ms > 0 else 0.0},
+        "row_compression": {"flops_per_step": rq_flops, "ms_per_step": ph["rowqr"],
+                            "tflops": rq_flops / (ph["rowqr"] * 1e-3) / 1e12 if ph["rowqr"] > 0 else 0.0,
+                            "fp64_peak_tflops": PEAK_FP64_VECTOR_TFLOPS},
         "elimination": {"flops_per_step": el_flops, "ms_per_step": ph["elimination"],
                         "tflops": el_flops / (ph["elimination"] * 1e-3) / 1e12 if ph["elimination"] > 0 else 0.0},
         "paper_context": {"hifie2x_512sq_eps1e-6": {"t_f_s": 470.0, "t_as_s": 1.0, "unknowns_per_s_f8": 548,
                                                     "hardware": "MATLAB R2010b, 1 core Xeon E7-4820 2.0 GHz, "
                                                                 "FP64, adaptive leaf"}},
     }
+    if args.calib_copy:  # 256 MiB read + 256 MiB written by one elementwise kernel
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_refine:
         line["refinement"] = refinement(hif, P, a, Fr, wl)
     if not args.no_cpu_baseline:

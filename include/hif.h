@@ -127,6 +127,10 @@ typedef struct {
   double sub_id_flops[HIF_MAX_SUBLEVELS];  /* algorithmic flops of the IDs */
   double sub_elim_flops[HIF_MAX_SUBLEVELS];/* algorithmic flops of the eliminations */
   double sub_t_ms[HIF_MAX_SUBLEVELS][8];   /* per sub-level split of t_phase_ms */
+  double sub_id_bytes[HIF_MAX_SUBLEVELS];  /* pivoted-QR traffic: every step reads and writes the
+                                              trailing block, sum over classes and steps i < k of
+                                              16 (m' - i)(n - i), m' = rows after row compression */
+  double sub_rowqr_flops[HIF_MAX_SUBLEVELS]; /* row compression: 2 m n^2 - 2 n^3 / 3 per class with m > n */
 } hif_stats_t;
 
 /* Fill *opts with the defaults listed above.  Returns HIF_EINVAL if opts is NULL. */

@@ -48,7 +48,8 @@ class hif_stats_t(ctypes.Structure):
                 ("sub_active", ctypes.c_int64 * MAX_SUB), ("sub_skel", ctypes.c_int64 * MAX_SUB),
                 ("sub_near", ctypes.c_int64 * MAX_SUB), ("sub_classes", ctypes.c_int64 * MAX_SUB),
                 ("sub_id_flops", ctypes.c_double * MAX_SUB), ("sub_elim_flops", ctypes.c_double * MAX_SUB),
-                ("sub_t_ms", (ctypes.c_double * 8) * MAX_SUB)]
+                ("sub_t_ms", (ctypes.c_double * 8) * MAX_SUB),
+                ("sub_id_bytes", ctypes.c_double * MAX_SUB), ("sub_rowqr_flops", ctypes.c_double * MAX_SUB)]
 
 
 _lib = None
@@ -193,6 +194,7 @@ class Factorization:
             "sub_near": list(s.sub_near[:ns]), "sub_classes": list(s.sub_classes[:ns]),
             "sub_id_flops": list(s.sub_id_flops[:ns]), "sub_elim_flops": list(s.sub_elim_flops[:ns]),
             "sub_t_ms": [dict(zip(PHASES, list(s.sub_t_ms[i]))) for i in range(ns)],
+            "sub_id_bytes": list(s.sub_id_bytes[:ns]), "sub_rowqr_flops": list(s.sub_rowqr_flops[:ns]),
         }
 
     def free(self):

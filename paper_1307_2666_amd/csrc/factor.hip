@@ -967,7 +967,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   std::vector<int> rec_g;
   std::vector<int64_t> h_newoff(G, 0);
   int64_t itot = 0, dtot = 0, ntot_new = 0, skel = 0;
-  double idfl = 0.0, elfl = 0.0;
+  double idfl = 0.0, elfl = 0.0, idby = 0.0, rqfl = 0.0;
   for (int g = 0; g < G; ++g) {
     int kk = 0, rr = 0;
     const int64_t nf = h_nf[g + 1] - h_nf[g];
@@ -979,6 +979,10 @@ void Factorizer::sublevel(int lvl, int kind) {
       rr += h_cls_n[q] - h_rank[q];
       const double nq = h_cls_n[q], kq = h_rank[q];
       idfl += 4.0 * m * nq * kq - 2.0 * kq * kq * (m + nq) + 4.0 * kq * kq * kq / 3.0 + kq * kq * (nq - kq);
+      // sum_{i<k} (a - i)(b - i) with a = rows after compression, b = columns
+      const double a2 = double(std::min<int64_t>(m, h_cls_n[q]));
+      idby += 16.0 * (kq * a2 * nq - (a2 + nq) * kq * (kq - 1.0) / 2.0 + (kq - 1.0) * kq * (2.0 * kq - 1.0) / 6.0);
+      if (m > h_cls_n[q]) rqfl += 2.0 * m * nq * nq - 2.0 * nq * nq * nq / 3.0;
     }
     skel += kk;
     h_newoff[g] = ntot_new;
@@ -1003,6 +1007,8 @@ void Factorizer::sublevel(int lvl, int kind) {
   }
   st.sub_skel[si] = skel;
   st.sub_id_flops[si] = idfl;
+  st.sub_id_bytes[si] = idby;
+  st.sub_rowqr_flops[si] = rqfl;
   st.sub_elim_flops[si] = elfl;
   sub.nrec = int(sub.hrec.size());
   sub.rec.alloc(sub.nrec, mt);
