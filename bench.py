@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per factorization moved by the ID step kernel on this workload,
 # from rocprofv3 FETCH_SIZE + WRITE_SIZE runs of `bench.py --steps 1 --warmup 0
 # --no-cpu-baseline --no-refine --calib-copy`, each scaled by what the counter
-# reads for a 256 MiB copy kernel.  Valid for the current k_idm_step only.
-ID_STEP_TRAFFIC_BYTES = 5.868e11
+# reads for a 256 MiB copy kernel.  Valid for the current k_idm_step_reg only.
+ID_STEP_TRAFFIC_BYTES = 4.231e+11
 
 
 def parse():
@@ -206,7 +206,8 @@ def main():
         "roofline": {"kernel": "k_idm_step + k_id (column-pivoted QR of the IDs, all launches of a step)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": ID_STEP_TRAFFIC_BYTES if wl.name == "sq512" and abs(eps - 1e-6) < 1e-12 else None,
+                     "traffic": (ID_STEP_TRAFFIC_BYTES if ID_STEP_TRAFFIC_BYTES and wl.name == "sq512"
+                                 and abs(eps - 1e-6) < 1e-12 else None),
                      "bytes_per_step": id_bytes, "ms_per_step": id_ms,
                      "flops_per_step": id_flops,
                      "fp64_tflops": id_flops / (id_ms * 1e-3) / 1e12 if id_ms > 0 else 0.0},

@@ -543,6 +543,113 @@ __global__ __launch_bounds__(kIdmThreads) void k_idm_step(IdArgs A, IdmState S, 
   }
 }
 
+// Same step when at most kIrRows * kIrGroups rows are left below it:
+// workgroup (b, q) owns 32 columns, thread (c, g) = (tid % 32, tid / 32)
+// keeps rows i + g + 32u (u < kIrRows) of column c in registers between the
+// dot product and the update, so every entry is read and written once per
+// step; the Householder vector is staged in LDS.
+constexpr int kIrCols = 32;
+constexpr int kIrGroups = 32;
+constexpr int kIrRows = 28;
+constexpr int kIrMaxRows = kIrRows * kIrGroups;
+
+__global__ __launch_bounds__(1024) void k_idm_step_reg(IdArgs A, IdmState S, int i) {
+  const int q = blockIdx.y;
+  const int m = A.rows[q], n = A.cols[q];
+  const int c0 = blockIdx.x * kIrCols;
+  if (c0 >= n || i >= min(m, n) || S.done[q]) return;
+  const int cur = i & 1, nxt = cur ^ 1;
+  const double* nrm = S.nrm + cur * S.total + q * S.stride;
+  const int32_t* st = S.st + cur * S.total + q * S.stride;
+  ArgMax loc{-1.0, INT_MAX};
+  for (int c = threadIdx.x; c < n; c += 1024)
+    if (st[c] == -1) loc = better(loc, ArgMax{nrm[c], c});
+  const ArgMax best = block_argmax(loc);
+  const double nb = sqrt(best.v > 0.0 ? best.v : 0.0);
+  const double r00 = i == 0 ? nb : S.r00[q];
+  if (!(best.v > 0.0) || !(nb > A.tol[q] * r00)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      A.rank[q] = i;
+      S.done[q] = 1;
+    }
+    return;
+  }
+  if (i == 0 && blockIdx.x == 0 && threadIdx.x == 0) S.r00[q] = nb;
+  const int p = best.i;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const double x0 = M[int64_t(i) * ld + p];
+  const double alpha = -copysign(nb, x0);
+  const double v0 = x0 - alpha;
+  const double vtv = best.v - x0 * x0 + v0 * v0;
+  const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+  const int mr = m - i;  // <= kIrMaxRows (checked on the host)
+  __shared__ double sv[kIrMaxRows];
+  __shared__ double sp[16][kIrCols];
+  const int tid = threadIdx.x, c = tid & 31, g = tid >> 5, wv = tid >> 6;
+  for (int rr = tid; rr < mr; rr += 1024) sv[rr] = rr == 0 ? v0 : M[int64_t(i + rr) * ld + p];
+  const int col = c0 + c;
+  const int state = col < n ? st[col] : -2;
+  const bool upd = state == -1 && col != p;
+  double* yc = M + int64_t(i) * ld + col;  // row i of this column
+  double y[kIrRows];
+#pragma unroll
+  for (int u = 0; u < kIrRows; ++u) {
+    const int rr = g + kIrGroups * u;
+    y[u] = (upd && rr < mr) ? yc[int64_t(rr) * ld] : 0.0;
+  }
+  __syncthreads();
+  double dot = 0.0;
+#pragma unroll
+  for (int u = 0; u < kIrRows; ++u) {
+    const int rr = g + kIrGroups * u;
+    if (rr < mr) dot += sv[rr] * y[u];
+  }
+  dot += __shfl_xor(dot, 32, 64);
+  if ((tid & 63) < 32) sp[wv][c] = dot;
+  __syncthreads();
+  double tdot = 0.0;
+#pragma unroll
+  for (int w2 = 0; w2 < 16; ++w2) tdot += sp[w2][c];
+  const double w = beta * tdot;
+  __syncthreads();
+  double s2 = 0.0;
+#pragma unroll
+  for (int u = 0; u < kIrRows; ++u) {
+    const int rr = g + kIrGroups * u;
+    if (rr < mr) {
+      y[u] -= w * sv[rr];
+      if (rr > 0) s2 += y[u] * y[u];
+    }
+  }
+  if (upd) {
+#pragma unroll
+    for (int u = 0; u < kIrRows; ++u) {
+      const int rr = g + kIrGroups * u;
+      if (rr < mr) yc[int64_t(rr) * ld] = y[u];
+    }
+  }
+  s2 += __shfl_xor(s2, 32, 64);
+  if ((tid & 63) < 32) sp[wv][c] = s2;
+  __syncthreads();
+  if (g == 0 && col < n) {
+    const int64_t o = nxt * S.total + q * S.stride + col;
+    if (upd) {
+      double t = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < 16; ++w2) t += sp[w2][c];
+      S.nrm[o] = t;
+      S.st[o] = -1;
+    } else if (col == p) {
+      S.st[o] = i;
+      S.alpha[q * S.stride + i] = alpha;
+      A.perm[A.poff[q] + i] = p;
+    } else {
+      S.st[o] = state;
+    }
+  }
+}
+
 // Redundant columns in ascending order after the skeleton (one workgroup per problem).
 __global__ __launch_bounds__(1024) void k_idm_perm(IdArgs A, IdmState S) {
   const int q = blockIdx.x;
@@ -672,10 +779,16 @@ static void launch_id_multi(const IdArgs& A, int max_cols, hipStream_t s) {
   done.alloc(A.nprob, nullptr);
   IdmState S{nrm.p, st.p, alpha.p, r00.p, done.p, stride, total};
   const dim3 grid(unsigned((max_cols + kIdmCols - 1) / kIdmCols), unsigned(A.nprob));
+  const dim3 grid_reg(unsigned((max_cols + kIrCols - 1) / kIrCols), unsigned(A.nprob));
   hipLaunchKernelGGL(k_idm_init, grid, dim3(kIdmThreads), 0, s, A, S);
   std::vector<int32_t> hd(A.nprob);
+  // the ID runs on the compressed block (rows <= cols <= max_cols): steps
+  // with at most kIrMaxRows rows left keep the columns in registers
   for (int i = 0; i < max_cols; ++i) {
-    hipLaunchKernelGGL(k_idm_step, grid, dim3(kIdmThreads), 0, s, A, S, i);
+    if (max_cols - i <= kIrMaxRows)
+      hipLaunchKernelGGL(k_idm_step_reg, grid_reg, dim3(1024), 0, s, A, S, i);
+    else
+      hipLaunchKernelGGL(k_idm_step, grid, dim3(kIdmThreads), 0, s, A, S, i);
     if ((i & 15) == 15) {  // stop launching once every problem has met the rank rule
       HIF_HIP(hipMemcpyAsync(hd.data(), done.p, sizeof(int32_t) * A.nprob, hipMemcpyDeviceToHost, s));
       HIF_HIP(hipStreamSynchronize(s));
