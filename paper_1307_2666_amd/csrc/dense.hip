@@ -68,11 +68,13 @@ __device__ int block_excl_scan(int flag, int* total) {
 // ---------------------------------------------------------------------------
 // Assembly (eqn proxy-id, Section 3.3; SCI-expanded near field, Section 4.3).
 // Pass 1 fills the kernel entries: workgroup (x, g) owns rows
-// [64x, 64x + 64) of the stacked block [Y_c; A_cc] of group g, and thread t
-// columns t, t + 256, ... so that consecutive threads write consecutive
-// addresses of a row.  Pass 2 (one thread per column) sums the squared
-// kernel part of each column of Y_c in row order and then adds the SCI
-// entries, so the results do not depend on the launch shape.
+// [64x, 64x + 64) of the stacked block [Y_c; A_cc] of group g (row
+// descriptions staged in LDS), thread t columns t, t + 256, ..., so that
+// consecutive threads write consecutive addresses of a row; it also writes
+// the partial squared norm of every column over its rows of Y_c.  Pass 2
+// (one wave per column) sums those partials in chunk order and adds the SCI
+// entries of the column, lanes over the entries; the results do not depend
+// on the launch shape.
 // ---------------------------------------------------------------------------
 constexpr int kAsmRows = 64;
 constexpr int kAsmThreads = 256;
@@ -88,19 +90,22 @@ __global__ __launch_bounds__(kAsmThreads) void k_asm_fill(AsmArgs A) {
   const int m = A.sym ? nf + P : 2 * nf + 2 * P;
   const int r0 = blockIdx.x * kAsmRows;
   if (r0 >= m + n) return;
-  const int r1 = min(r0 + kAsmRows, m + n);
+  const int r1 = min(r0 + kAsmRows, m + n), nr = r1 - r0;
   double* Y = A.Y + A.yoff[g];
   double* Acc = A.Acc + A.aoff[g];
   double* Scc = A.Scc + A.aoff[g];
   const int32_t* cols = A.cord + c0;
   const int32_t* nfi = A.nf_idx + f0;
   const int roff = A.sym ? nf : 2 * nf;  // first proxy row
-
-  for (int r = r0; r < r1; ++r) {
-    // row description: source point x_i (or proxy point) and its factors
+  const bool f32 = A.fp32 != 0;
+  // row descriptions: source point (or proxy point), kind, point index, factors
+  __shared__ double sx[kAsmRows][D];
+  __shared__ double sb[kAsmRows], swc[kAsmRows];
+  __shared__ int skind[kAsmRows], sidx[kAsmRows];
+  if (threadIdx.x < nr) {
+    const int r = r0 + threadIdx.x;
+    int kind, i = -1;
     double xi[D];
-    int kind;  // 0 near-field kernel row, 1 transposed row block, 2 proxy, 3 proxy (row side), 4 A_cc
-    int i = -1;
     if (r < nf) {
       kind = 0;
       i = nfi[r];
@@ -120,49 +125,67 @@ __global__ __launch_bounds__(kAsmThreads) void k_asm_fill(AsmArgs A) {
 #pragma unroll
       for (int k = 0; k < D; ++k) xi[k] = A.pts[int64_t(i) * D + k];
     }
-    const double bi = i >= 0 ? A.b[i] : 0.0;
-    const double wci = i >= 0 ? A.w[i] * A.c[i] : 0.0;
-    for (int col = threadIdx.x; col < n; col += kAsmThreads) {
-      const int j = cols[col];
+#pragma unroll
+    for (int k = 0; k < D; ++k) sx[threadIdx.x][k] = xi[k];
+    sb[threadIdx.x] = i >= 0 ? A.b[i] : 0.0;
+    swc[threadIdx.x] = i >= 0 ? A.w[i] * A.c[i] : 0.0;
+    skind[threadIdx.x] = kind;
+    sidx[threadIdx.x] = i;
+  }
+  __syncthreads();
+  for (int col = threadIdx.x; col < n; col += kAsmThreads) {
+    const int j = cols[col];
+    double xj[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xj[k] = A.pts[int64_t(j) * D + k];
+    const double aj = A.a[j], bj = A.b[j], cj = A.c[j], wj = A.w[j], sj = A.selfk[j];
+    double k2 = 0.0;
+    for (int rr = 0; rr < nr; ++rr) {
+      const int r = r0 + rr;
+      const int kind = skind[rr];
       double r2 = 0.0;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        const double t = xi[k] - A.pts[int64_t(j) * D + k];
+        const double t = sx[rr][k] - xj[k];
         r2 += t * t;
       }
-      const bool f32 = A.fp32 != 0;
       if (kind == 4) {
+        const int i = sidx[rr];
         double v;
         if (i == j)
-          v = A.a[j] + A.b[j] * A.selfk[j] * A.c[j];
+          v = aj + bj * sj * cj;
         else
-          v = bi * green_mixed<D>(r2, f32) * A.w[j] * A.c[j];
-        const int rr = r - m;
-        Acc[int64_t(rr) * n + col] = entry_prec(v, f32);
-        Scc[int64_t(rr) * n + col] = 0.0;
+          v = sb[rr] * green_mixed<D>(r2, f32) * wj * cj;
+        const int rc = r - m;
+        Acc[int64_t(rc) * n + col] = entry_prec(v, f32);
+        Scc[int64_t(rc) * n + col] = 0.0;
       } else {
         const double gk = green_mixed<D>(r2, f32);
         double v;
         if (kind == 0)
-          v = bi * gk * A.w[j] * A.c[j];       // b_i G w_j c_j
+          v = sb[rr] * gk * wj * cj;           // b_i G w_j c_j
         else if (kind == 1)
-          v = A.b[j] * gk * wci;               // b_j G w_i c_i
+          v = bj * gk * swc[rr];               // b_j G w_i c_i
         else if (kind == 2)
-          v = gk * A.w[j] * A.c[j];            // G(|x_p - x_j|) w_j c_j
+          v = gk * wj * cj;                    // G(|x_p - x_j|) w_j c_j
         else
-          v = A.b[j] * gk * A.w[j];            // b_j G(|x_p - x_j|) w_j
-        Y[int64_t(r) * n + col] = entry_prec(v, f32);
+          v = bj * gk * wj;                    // b_j G(|x_p - x_j|) w_j
+        v = entry_prec(v, f32);
+        Y[int64_t(r) * n + col] = v;
+        k2 += v * v;
       }
     }
+    if (r0 < m) A.kpart[int64_t(blockIdx.x) * A.kstride + c0 + col] = k2;
   }
 }
 
-__global__ __launch_bounds__(64) void k_asm_finish(AsmArgs A) {
+__global__ __launch_bounds__(256) void k_asm_finish(AsmArgs A) {
   const int g = blockIdx.y;
   const int64_t c0 = A.gstart[g];
   const int n = int(A.gstart[g + 1] - c0);
-  const int col = blockIdx.x * 64 + threadIdx.x;
-  if (col >= n) return;
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (col >= n) return;  // uniform per wave
   const int64_t f0 = A.nf_start[g];
   const int nf = int(A.nf_start[g + 1] - f0);
   const int P = A.nproxy;
@@ -172,25 +195,16 @@ __global__ __launch_bounds__(64) void k_asm_finish(AsmArgs A) {
   double* Scc = A.Scc + A.aoff[g];
   const int32_t* nfi = A.nf_idx + f0;
   const int j = A.cord[c0 + col];
+  // squared norm of the kernel part: chunk partials in chunk order
+  const int nch = (m + kAsmRows - 1) / kAsmRows;
   double k2 = 0.0;
-  {
-    int r = 0;
-    for (; r + 8 <= m; r += 8) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = Y[int64_t(r + u) * n + col];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) k2 += v[u] * v[u];
-    }
-    for (; r < m; ++r) {
-      const double v = Y[int64_t(r) * n + col];
-      k2 += v * v;
-    }
-  }
-  // SCI part: row j of the store holds (j, i) with values (S_ji, S_ij).
+  for (int x = lane; x < nch; x += 64) k2 += A.kpart[int64_t(x) * A.kstride + c0 + col];
+  k2 = wave_sum(k2);
+  // SCI part: row j of the store holds (j, i) with values (S_ji, S_ij); the
+  // entries of a row have distinct i, so the lanes write distinct rows.
   double s2 = 0.0;
   const int64_t e0 = A.srow[j], e1 = A.srow[j + 1];
-  for (int64_t e = e0; e < e1; ++e) {
+  for (int64_t e = e0 + lane; e < e1; e += 64) {
     const int i = int(A.skey[e] & 0xffffffffu);
     const double2 sv = A.sval[e];
     if (A.grp_of[i] == g) {
@@ -214,8 +228,11 @@ __global__ __launch_bounds__(64) void k_asm_finish(AsmArgs A) {
       }
     }
   }
-  A.colK2[c0 + col] = k2;
-  A.colS2[c0 + col] = s2;
+  s2 = wave_sum(s2);
+  if (lane == 0) {
+    A.colK2[c0 + col] = k2;
+    A.colS2[c0 + col] = s2;
+  }
 }
 
 void launch_assemble(const AsmArgs& A, hipStream_t s) {
@@ -225,8 +242,8 @@ void launch_assemble(const AsmArgs& A, hipStream_t s) {
     hipLaunchKernelGGL(k_asm_fill<2>, g1, dim3(kAsmThreads), 0, s, A);
   else
     hipLaunchKernelGGL(k_asm_fill<3>, g1, dim3(kAsmThreads), 0, s, A);
-  const dim3 g2(unsigned((A.max_cols + 63) / 64), unsigned(A.ngroups));
-  hipLaunchKernelGGL(k_asm_finish, g2, dim3(64), 0, s, A);
+  const dim3 g2(unsigned((A.max_cols + 3) / 4), unsigned(A.ngroups));
+  hipLaunchKernelGGL(k_asm_finish, g2, dim3(256), 0, s, A);
   HIF_HIP(hipGetLastError());
 }
 

@@ -260,47 +260,54 @@ struct NfArgs {
 
 template <int D, bool FILL>
 __global__ void k_nearfield(NfArgs A) {
-  const int g = blockIdx.x;
+  // group g is split over gridDim.x workgroups (slot g * gridDim.x + part):
+  // the cells of its bounding box go round-robin to the parts, and each wave
+  // takes one DOF of the group with its lanes over that DOF's SCI entries.
+  // Candidates are sorted and de-duplicated afterwards, so the split and the
+  // order of emission do not show in the result.
+  const int g = blockIdx.y, part = blockIdx.x, NP = gridDim.x;
+  const int64_t slot = int64_t(g) * NP + part;
   double z[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) z[k] = A.zc[int64_t(g) * D + k];
-  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     lo[k] = max(0, int(floor((z[k] - A.R) * double(A.S))) - 1);
-    hi[k] = min(A.S - 1, int(floor((z[k] + A.R) * double(A.S))) + 1);
+    const int hi = min(A.S - 1, int(floor((z[k] + A.R) * double(A.S))) + 1);
+    ext[k] = hi - lo[k] + 1;
   }
   __shared__ unsigned long long s_cnt;
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
   int64_t local = 0;
-  uint64_t* out = FILL ? A.cand + A.cand_off[g] : nullptr;
-  const unsigned long long cap = FILL ? (unsigned long long)(A.cand_off[g + 1] - A.cand_off[g]) : 0ull;
+  uint64_t* out = FILL ? A.cand + A.cand_off[slot] : nullptr;
+  const unsigned long long cap = FILL ? (unsigned long long)(A.cand_off[slot + 1] - A.cand_off[slot]) : 0ull;
   auto emit = [&](int j) {
     if (FILL) {
-      unsigned long long slot = atomicAdd(&s_cnt, 1ull);
-      if (slot < cap) out[slot] = (uint64_t(g) << A.shift) | uint64_t(uint32_t(j));
+      unsigned long long pos = atomicAdd(&s_cnt, 1ull);
+      if (pos < cap) out[pos] = (uint64_t(g) << A.shift) | uint64_t(uint32_t(j));
     } else {
       ++local;
     }
   };
-  for (int c0 = lo[0]; c0 <= hi[0]; ++c0)
-    for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
-      for (int c2 = (D == 3 ? lo[2] : 0); c2 <= (D == 3 ? hi[2] : 0); ++c2) {
-        const int cc[3] = {c0, c1, c2};
-        int cid = 0;
+  const int ncell = ext[0] * ext[1] * ext[2];
+  for (int cl = part; cl < ncell; cl += NP) {
+    const int cc[3] = {lo[0] + cl / (ext[1] * ext[2]), lo[1] + (cl / ext[2]) % ext[1], lo[2] + cl % ext[2]};
+    int cid = 0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) cid = cid * A.S + cc[k];
-        const int b = A.cell_lo[cid], e = A.cell_hi[cid];
-        for (int i = b + threadIdx.x; i < e; i += blockDim.x) {
-          const int j = A.cdof[i];
-          if (A.grp_of[j] == g) continue;
-          if (dist2_exact<D>(A.pts + int64_t(j) * D, z) < A.R2) emit(j);
-        }
-      }
-  for (int64_t p = A.gstart[g] + threadIdx.x; p < A.gstart[g + 1]; p += blockDim.x) {
+    for (int k = 0; k < D; ++k) cid = cid * A.S + cc[k];
+    const int b = A.cell_lo[cid], e = A.cell_hi[cid];
+    for (int i = b + threadIdx.x; i < e; i += blockDim.x) {
+      const int j = A.cdof[i];
+      if (A.grp_of[j] == g) continue;
+      if (dist2_exact<D>(A.pts + int64_t(j) * D, z) < A.R2) emit(j);
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int64_t p = A.gstart[g] + int64_t(part) * nw + wv; p < A.gstart[g + 1]; p += int64_t(NP) * nw) {
     const int i = A.sdof[p];
-    for (int64_t e = A.srow[i]; e < A.srow[i + 1]; ++e) {
+    for (int64_t e = A.srow[i] + lane; e < A.srow[i + 1]; e += 64) {
       const int j = int(A.skey[e] & 0xffffffffu);
       if (A.grp_of[j] != g) emit(j);
     }
@@ -315,7 +322,7 @@ __global__ void k_nearfield(NfArgs A) {
     if (threadIdx.x == 0) {
       long long t = 0;
       for (int k = 0; k < int(blockDim.x + 63) / 64; ++k) t += sp[k];
-      A.cnt[g] = t;
+      A.cnt[slot] = t;
     }
   }
 }
@@ -325,13 +332,26 @@ __global__ void k_unique_flags(const uint64_t* keys, int64_t n, int64_t* flag) {
 }
 
 __global__ void k_unique_compact(const uint64_t* keys, int64_t n, const int64_t* flag, const int64_t* pos,
-                                 int shift, int32_t* nf_idx, int32_t* nfc) {
+                                 int shift, int32_t* nf_idx) {
   GRID_STRIDE(i, n) {
-    if (flag[i]) {
-      const uint64_t key = keys[i];
-      nf_idx[pos[i]] = int32_t(key & ((uint64_t(1) << shift) - 1));
-      atomicAdd(&nfc[int(key >> shift)], 1);
-    }
+    if (flag[i]) nf_idx[pos[i]] = int32_t(keys[i] & ((uint64_t(1) << shift) - 1));
+  }
+}
+
+// Offsets out[0..nseg] of the segments (key >> shift) of n > 0 sorted keys:
+// out[s] = index (pos[e] if pos is given) of the first key of segment >= s,
+// out[nseg] = total.  Every entry is written exactly once: each boundary
+// fills the offsets of the segments it passes, so no atomics are needed.
+__global__ void k_csr_from_sorted(const uint64_t* keys, int64_t n, int shift, int64_t nseg, const int64_t* pos,
+                                  int64_t total, int64_t* out) {
+  GRID_STRIDE(e, n) {
+    const int64_t sg = int64_t(keys[e] >> shift);
+    const int64_t val = pos ? pos[e] : e;
+    const int64_t prev = e == 0 ? -1 : int64_t(keys[e - 1] >> shift);
+    if (prev != sg)
+      for (int64_t t = prev + 1; t <= sg; ++t) out[t] = val;
+    if (e == n - 1)
+      for (int64_t t = sg + 1; t <= nseg; ++t) out[t] = total;
   }
 }
 
@@ -523,9 +543,6 @@ __global__ void k_gather_val(const double2* in, const int32_t* idx, int64_t n, d
   GRID_STRIDE(e, n) out[e] = in[idx[e]];
 }
 
-__global__ void k_row_count(const uint64_t* key, int64_t nnz, int64_t* cnt) {
-  GRID_STRIDE(e, nnz) atomicAdd((unsigned long long*)&cnt[key[e] >> 32], 1ull);
-}
 
 __global__ void k_active_keep(const int32_t* act, int64_t nact, const uint8_t* active, int32_t* keep) {
   GRID_STRIDE(i, nact) keep[i] = active[act[i]] ? 1 : 0;
@@ -641,12 +658,12 @@ struct Factorizer {
   DBuf<int64_t> gstart, cnt, cand_off, flag64, pos64, nf_start;
   DBuf<double> zc;
   DBuf<uint64_t> cand, cand2;
-  DBuf<int32_t> nf_idx, nfc;
+  DBuf<int32_t> nf_idx;
   DBuf<uint64_t> h1, h2;
   DBuf<int32_t> hc, rep, newpos, cord, ncls;
   DBuf<int32_t> cls_first, cls_col0, cls_n, cls_group, cls_rank, cls_skoff, cls_rdoff, cls_ld, cls_rows, perm;
   DBuf<int64_t> cls_moff, cls_poff, yoff, aoff, newoff;
-  DBuf<double> cls_tol, Y, Acc, Scc, Mw, colK2, colS2, qr_scratch;
+  DBuf<double> cls_tol, Y, Acc, Scc, Mw, colK2, colS2, kpart, qr_scratch;
   DBuf<int32_t> cls_rows2;
   DBuf<int64_t> cls_soff;
   DBuf<GemmDesc> gdesc;
@@ -749,40 +766,45 @@ void Factorizer::sublevel(int lvl, int kind) {
   nfa.grp_of = grp_of.p;
   nfa.srow = srow.p;
   nfa.skey = skey.p;
-  cnt.ensure(G, mt);
-  cand_off.ensure(G + 1, mt);
+  // workgroups per group: enough to fill the GPU when groups are few
+  const int NP = int(std::min<int64_t>(64, std::max<int64_t>(1, 2048 / G)));
+  const int64_t nslot = int64_t(G) * NP;
+  cnt.ensure(nslot, mt);
+  cand_off.ensure(nslot + 1, mt);
   nfa.cnt = cnt.p;
   nfa.shift = shift;
   if (D == 2)
-    hipLaunchKernelGGL((k_nearfield<2, false>), dim3(G), dim3(kThreads), 0, s, nfa);
+    hipLaunchKernelGGL((k_nearfield<2, false>), dim3(NP, G), dim3(kThreads), 0, s, nfa);
   else
-    hipLaunchKernelGGL((k_nearfield<3, false>), dim3(G), dim3(kThreads), 0, s, nfa);
+    hipLaunchKernelGGL((k_nearfield<3, false>), dim3(NP, G), dim3(kThreads), 0, s, nfa);
   HIF_HIP(hipGetLastError());
-  exclusive_scan_i64(cnt.p, cand_off.p, G, s, prim, mt);
-  const int64_t ncand = scalar_at(cand_off.p + G, s);
+  exclusive_scan_i64(cnt.p, cand_off.p, nslot, s, prim, mt);
+  const int64_t ncand = scalar_at(cand_off.p + nslot, s);
   cand.ensure(ncand, mt);
   cand2.ensure(ncand, mt);
   nfa.cand = cand.p;
   nfa.cand_off = cand_off.p;
   if (D == 2)
-    hipLaunchKernelGGL((k_nearfield<2, true>), dim3(G), dim3(kThreads), 0, s, nfa);
+    hipLaunchKernelGGL((k_nearfield<2, true>), dim3(NP, G), dim3(kThreads), 0, s, nfa);
   else
-    hipLaunchKernelGGL((k_nearfield<3, true>), dim3(G), dim3(kThreads), 0, s, nfa);
+    hipLaunchKernelGGL((k_nearfield<3, true>), dim3(NP, G), dim3(kThreads), 0, s, nfa);
   HIF_HIP(hipGetLastError());
   sort_u64(cand.p, cand2.p, ncand, shift + gbits, s, prim, mt);
   flag64.ensure(ncand, mt);
   pos64.ensure(ncand + 1, mt);
-  nfc.ensure(G, mt);
   nf_start.ensure(G + 1, mt);
   hipLaunchKernelGGL(k_unique_flags, dim3(nblocks(ncand)), dim3(kThreads), 0, s, cand.p, ncand, flag64.p);
   exclusive_scan_i64(flag64.p, pos64.p, ncand, s, prim, mt);
   const int64_t nnf = scalar_at(pos64.p + ncand, s);
   nf_idx.ensure(nnf, mt);
-  hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(G)), dim3(kThreads), 0, s, nfc.p, int64_t(G), 0);
   hipLaunchKernelGGL(k_unique_compact, dim3(nblocks(ncand)), dim3(kThreads), 0, s, cand.p, ncand, flag64.p, pos64.p,
-                     shift, nf_idx.p, nfc.p);
-  hipLaunchKernelGGL(k_i32_to_i64, dim3(nblocks(G)), dim3(kThreads), 0, s, nfc.p, cnt.p, int64_t(G));
-  exclusive_scan_i64(cnt.p, nf_start.p, G, s, prim, mt);
+                     shift, nf_idx.p);
+  if (ncand > 0)
+    hipLaunchKernelGGL(k_csr_from_sorted, dim3(nblocks(ncand)), dim3(kThreads), 0, s, cand.p, ncand, shift,
+                       int64_t(G), pos64.p, nnf, nf_start.p);
+  else
+    hipLaunchKernelGGL(k_fill_i64, dim3(nblocks(G + 1)), dim3(kThreads), 0, s, nf_start.p, int64_t(G + 1),
+                       int64_t(0));
   HIF_HIP(hipGetLastError());
   st.sub_near[si] = nnf;
 
@@ -891,6 +913,9 @@ void Factorizer::sublevel(int lvl, int kind) {
   aa.sval = sval.p;
   aa.fp32 = H->opts.precision == HIF_FP32_MIXED;
   aa.max_rows = maxmn;
+  aa.kstride = nact;
+  kpart.ensure(size_t((maxmn + 63) / 64) * size_t(nact), mt);
+  aa.kpart = kpart.p;
   aa.max_cols = maxn;
   launch_assemble(aa, s);
   cls_tol.ensure(NC, mt);
@@ -1163,10 +1188,11 @@ void Factorizer::sublevel(int lvl, int kind) {
     hipLaunchKernelGGL(k_gather_val, dim3(nblocks(nnz2)), dim3(kThreads), 0, s, sval2.p, sidx.p, nnz2, sval.p);
   }
   snnz = nnz2;
-  cnt.ensure(N, mt);
-  hipLaunchKernelGGL(k_fill_i64, dim3(nblocks(N)), dim3(kThreads), 0, s, cnt.p, N, int64_t(0));
-  if (snnz > 0) hipLaunchKernelGGL(k_row_count, dim3(nblocks(snnz)), dim3(kThreads), 0, s, skey.p, snnz, cnt.p);
-  exclusive_scan_i64(cnt.p, srow.p, N, s, prim, mt);
+  if (snnz > 0)
+    hipLaunchKernelGGL(k_csr_from_sorted, dim3(nblocks(snnz)), dim3(kThreads), 0, s, skey.p, snnz, 32, N,
+                       static_cast<const int64_t*>(nullptr), snnz, srow.p);
+  else
+    hipLaunchKernelGGL(k_fill_i64, dim3(nblocks(N + 1)), dim3(kThreads), 0, s, srow.p, N + 1, int64_t(0));
   HIF_HIP(hipGetLastError());
   // active list
   akeep.ensure(nact, mt);

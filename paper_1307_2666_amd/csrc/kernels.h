@@ -24,6 +24,8 @@ struct AsmArgs {
   const int64_t* aoff;          // [G] offset of A_cc / S_cc (row-major n x n)
   double *Y, *Acc, *Scc;
   double *colK2, *colS2;        // per cord position: squared norms of kernel / SCI part of Y
+  double* kpart;                // [row chunk][kstride]: partial squared norms of the kernel part
+  int64_t kstride = 0;          // = number of cord positions of the sub-level
   const int32_t* grp_of;        // per DOF: group of this sub-level (-1 inactive)
   const int32_t* pos_of;        // per DOF: position within its group (class order)
   const int64_t* srow;          // SCI store CSR row pointer [N+1]
