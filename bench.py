@@ -27,11 +27,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6  # MI355X: 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per factorization moved by the ID step kernel on this workload,
-# from rocprofv3 FETCH_SIZE + WRITE_SIZE runs of `bench.py --steps 1 --warmup 0
+# HBM bytes per factorization moved by the pivoted-QR kernels (k_bq_init,
+# k_bq_piv, k_bq_cols, k_bq_update, k_id) on this workload, from rocprofv3
+# FETCH_SIZE + WRITE_SIZE runs of `bench.py --steps 1 --warmup 0
 # --no-cpu-baseline --no-refine --calib-copy`, each scaled by what the counter
-# reads for a 256 MiB copy kernel.  Valid for the current k_idm_step_reg only.
-ID_STEP_TRAFFIC_BYTES = 4.231e+11
+# reads for a 256 MiB copy kernel.  None until measured for the current kernels.
+ID_STEP_TRAFFIC_BYTES = None
 
 
 def parse():
@@ -167,11 +168,12 @@ def main():
     st = F.stats()
     F.free()
 
-    # Dominant kernel: the pivoted-QR ID (k_idm_step, one launch per pivot step
-    # over all large classes, and k_id for many small ones).  Each step reads
-    # and writes the trailing block, so it is bound by HBM; algorithmic bytes
-    # from the realized rows, columns and ranks of every class, time from the
-    # HIP events the library records on its own stream around those launches.
+    # Dominant kernel family: the pivoted QR of the IDs (blocked: k_bq_piv +
+    # k_bq_cols per pivot step over all large classes, k_bq_update per block of
+    # 32 reflectors; k_id for many small classes).  Every step streams the
+    # trailing block, so it is bound by HBM; algorithmic bytes from the
+    # realized rows, columns and ranks of every class (sub_id_bytes), time from
+    # the HIP events the library records on its own stream around the launches.
     ph = {k: float(np.mean([s["t_phase_ms"][k] for s in stats])) for k in stats[0]["t_phase_ms"]}
     id_flops = float(np.sum(st["sub_id_flops"]))
     id_bytes = float(np.sum(st["sub_id_bytes"]))
@@ -203,7 +205,8 @@ def main():
         "sub_ms": [{k: round(v, 3) for k, v in d.items() if v > 0} for d in st["sub_t_ms"]],
         "top_size": st["top_size"],
         "factor_bytes": st["factor_bytes"],
-        "roofline": {"kernel": "k_idm_step + k_id (column-pivoted QR of the IDs, all launches of a step)",
+        "roofline": {"kernel": "k_bq_piv + k_bq_cols + k_bq_update + k_id (column-pivoted QR of the IDs, "
+                               "all launches of a step)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (ID_STEP_TRAFFIC_BYTES if ID_STEP_TRAFFIC_BYTES and wl.name == "sq512"

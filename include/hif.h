@@ -93,6 +93,14 @@ typedef struct {
  *  n_proxy:      proxy points, 0 = 64 (2D circle) / 512 (3D sphere) (Section 3.3).
  *  proxy_radius: proxy radius in units of the cell width, 0 = 1.5 (Section 3.3).
  *  max_bytes:    cap on device memory the factorization may hold, 0 = none.
+ *  row_compression: how the IDs of a sub-level with few large problems run
+ *                (Section 2.2 leaves the QR organization open):
+ *                1 = Householder QR of Y first, then the pivoted QR of its
+ *                n x n R factor; 0 = pivoted QR directly on Y; -1 = auto
+ *                (0 only when Y is nearly square: sum of m n over the
+ *                sub-level's problems at most 1.25 times the sum of n^2).
+ *                Either way the pivoted QR delays the updates of 32
+ *                reflectors; both give the same ID up to rounding.
  */
 typedef struct {
   int precision;
@@ -102,6 +110,7 @@ typedef struct {
   int n_proxy;
   double proxy_radius;
   size_t max_bytes;
+  int row_compression;
 } hif_opts;
 
 #define HIF_MAX_SUBLEVELS 64
@@ -127,9 +136,13 @@ typedef struct {
   double sub_id_flops[HIF_MAX_SUBLEVELS];  /* algorithmic flops of the IDs */
   double sub_elim_flops[HIF_MAX_SUBLEVELS];/* algorithmic flops of the eliminations */
   double sub_t_ms[HIF_MAX_SUBLEVELS][8];   /* per sub-level split of t_phase_ms */
-  double sub_id_bytes[HIF_MAX_SUBLEVELS];  /* pivoted-QR traffic: every step reads and writes the
-                                              trailing block, sum over classes and steps i < k of
-                                              16 (m' - i)(n - i), m' = rows after row compression */
+  double sub_id_bytes[HIF_MAX_SUBLEVELS];  /* pivoted-QR traffic, summed over classes: after row
+                                              compression every step i < k reads and writes the
+                                              trailing block of R0, 16 (m' - i)(n - i) with
+                                              m' = min(m, n); on Y directly every step reads it,
+                                              8 (m - i)(n - i), and every full block of 32
+                                              reflectors ending at step e < k reads and writes
+                                              the rows below it, 16 (m - e)(n - e) */
   double sub_rowqr_flops[HIF_MAX_SUBLEVELS]; /* row compression: 2 m n^2 - 2 n^3 / 3 per class with m > n */
 } hif_stats_t;
 

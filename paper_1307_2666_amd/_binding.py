@@ -37,7 +37,7 @@ class hif_kernel(ctypes.Structure):
 class hif_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("second_kind", ctypes.c_int), ("symmetric", ctypes.c_int),
                 ("variant", ctypes.c_int), ("n_proxy", ctypes.c_int), ("proxy_radius", ctypes.c_double),
-                ("max_bytes", ctypes.c_size_t)]
+                ("max_bytes", ctypes.c_size_t), ("row_compression", ctypes.c_int)]
 
 
 class hif_stats_t(ctypes.Structure):
@@ -211,7 +211,7 @@ class Factorization:
 
 def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, selfk=None,
            second_kind=-1, symmetric=-1, variant="hifie", n_proxy=0, proxy_radius=0.0,
-           max_bytes=0, precision=HIF_FP64, stream=None) -> Factorization:
+           max_bytes=0, precision=HIF_FP64, row_compression=-1, stream=None) -> Factorization:
     """``hif_factor``: build ``F ~ A`` for points ``(n, d)`` in the unit box."""
     lib = load_library()
     P = _dev(points)
@@ -229,6 +229,7 @@ def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, s
     o.n_proxy = n_proxy
     o.proxy_radius = proxy_radius
     o.max_bytes = max_bytes
+    o.row_compression = row_compression
     handle = ctypes.c_void_p()
     _check(lib.hif_factor(_ptr(P), n, d, ctypes.byref(k), _ptr(av), _ptr(bv), _ptr(cv), float(eps), int(leaf),
                           ctypes.byref(o), _stream(stream), ctypes.byref(handle)))

@@ -62,6 +62,7 @@ hif_status hif_opts_default(hif_opts* o) {
   o->n_proxy = 0;
   o->proxy_radius = 0.0;
   o->max_bytes = 0;
+  o->row_compression = -1;
   return HIF_OK;
 }
 
@@ -89,6 +90,8 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
   if (o.variant != HIF_VARIANT_HIFIE && o.variant != HIF_VARIANT_RSF)
     return fail(HIF_EINVAL, "opts.variant must be HIF_VARIANT_HIFIE or HIF_VARIANT_RSF");
   if (o.n_proxy < 0 || o.n_proxy > 8192) return fail(HIF_EINVAL, "opts.n_proxy must be in [0, 8192]");
+  if (o.row_compression < -1 || o.row_compression > 1)
+    return fail(HIF_EINVAL, "opts.row_compression must be -1, 0 or 1");
   if (!(o.proxy_radius == 0.0 || (std::isfinite(o.proxy_radius) && o.proxy_radius > 0.5)))
     return fail(HIF_EINVAL, "opts.proxy_radius must be 0 (default) or > 0.5 cell widths");
   // second-kind modification by default in FP64 only: in FP32 the SCI-scaled

@@ -410,280 +410,13 @@ __global__ __launch_bounds__(1024) void k_id(IdArgs A) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// Multi-workgroup ID for few large problems: the same column-pivoted
-// Householder QR as k_id (recomputed norms, ties to the lowest column, rank
-// rule of Section 2.2), one launch per pivot step.  Workgroup (b, q) owns
-// columns 64b..64b+63 of problem q; every workgroup finds the pivot from the
-// norms of the previous step (double-buffered, so no workgroup reads what
-// another writes in the same launch), applies the reflector to its columns
-// and recomputes their norms.  The pivot column keeps its Householder vector
-// below the diagonal and R_ii goes to alpha.  State of problem q lives at
-// q * stride.
-// ---------------------------------------------------------------------------
+// T = R11^{-1} R12 for the blocked pivoted QR below: R11[a][b] = M[a][perm[b]]
+// above the diagonal, R11[a][a] = alpha[a], R12 in rows 0..k-1 of the
+// redundant columns.  State of problem q lives at q * stride.
 struct IdmState {
-  double* nrm;    // [2][nprob * stride] squared norms of the rows below the step
-  int32_t* st;    // [2][nprob * stride] -2 absent, -1 trailing, >= 0 pivot step
   double* alpha;  // [nprob * stride] R_ii
-  double* r00;    // [nprob]
-  int32_t* done;  // [nprob]
   int64_t stride;
-  int64_t total;  // nprob * stride
 };
-constexpr int kIdmCols = 64;
-constexpr int kIdmThreads = 256;
-
-__global__ __launch_bounds__(kIdmThreads) void k_idm_init(IdArgs A, IdmState S) {
-  const int q = blockIdx.y;
-  const int m = A.rows[q], n = A.cols[q];
-  const int c0 = blockIdx.x * kIdmCols;
-  if (c0 >= n) return;
-  const double* M = A.base + A.moff[q];
-  const int ld = A.ld[q];
-  const int lc = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int col = c0 + lc;
-  __shared__ double sp[4][kIdmCols];
-  double s = 0.0;
-  if (col < n)
-    for (int r = rg; r < m; r += 4) {
-      const double y = M[int64_t(r) * ld + col];
-      s += y * y;
-    }
-  sp[rg][lc] = s;
-  __syncthreads();
-  if (rg == 0 && col < n) {
-    const int64_t o = q * S.stride + col;
-    S.nrm[o] = sp[0][lc] + sp[1][lc] + sp[2][lc] + sp[3][lc];
-    S.st[o] = -1;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    S.done[q] = 0;
-    A.rank[q] = min(m, n);
-  }
-}
-
-__global__ __launch_bounds__(kIdmThreads) void k_idm_step(IdArgs A, IdmState S, int i) {
-  const int q = blockIdx.y;
-  const int m = A.rows[q], n = A.cols[q];
-  const int c0 = blockIdx.x * kIdmCols;
-  if (c0 >= n || i >= min(m, n) || S.done[q]) return;
-  const int cur = i & 1, nxt = cur ^ 1;
-  const double* nrm = S.nrm + cur * S.total + q * S.stride;
-  const int32_t* st = S.st + cur * S.total + q * S.stride;
-  ArgMax loc{-1.0, INT_MAX};
-  for (int c = threadIdx.x; c < n; c += kIdmThreads)
-    if (st[c] == -1) loc = better(loc, ArgMax{nrm[c], c});
-  const ArgMax best = block_argmax(loc);
-  const double nb = sqrt(best.v > 0.0 ? best.v : 0.0);
-  const double r00 = i == 0 ? nb : S.r00[q];
-  if (!(best.v > 0.0) || !(nb > A.tol[q] * r00)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      A.rank[q] = i;
-      S.done[q] = 1;
-    }
-    return;
-  }
-  if (i == 0 && blockIdx.x == 0 && threadIdx.x == 0) S.r00[q] = nb;
-  const int p = best.i;
-  double* M = A.base + A.moff[q];
-  const int ld = A.ld[q];
-  const double x0 = M[int64_t(i) * ld + p];
-  const double alpha = -copysign(nb, x0);
-  const double v0 = x0 - alpha;
-  const double vtv = best.v - x0 * x0 + v0 * v0;
-  const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
-  const int lc = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int col = c0 + lc;
-  const int state = col < n ? st[col] : -2;
-  const bool upd = state == -1 && col != p;
-  __shared__ double sp[4][kIdmCols];
-  const double* vp = M + p;   // pivot column, rows > i hold the vector
-  double* yc = M + col;
-  double dot = 0.0;
-  if (upd) {
-    if (rg == 0) dot = v0 * yc[int64_t(i) * ld];
-    int r = i + 1 + rg;
-    for (; r + 28 < m; r += 32) {
-      double vv[8], yy[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        vv[u] = vp[int64_t(r + 4 * u) * ld];
-        yy[u] = yc[int64_t(r + 4 * u) * ld];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) dot += vv[u] * yy[u];
-    }
-    for (; r < m; r += 4) dot += vp[int64_t(r) * ld] * yc[int64_t(r) * ld];
-  }
-  sp[rg][lc] = dot;
-  __syncthreads();
-  const double w = beta * (sp[0][lc] + sp[1][lc] + sp[2][lc] + sp[3][lc]);
-  __syncthreads();
-  double s2 = 0.0;
-  if (upd) {
-    if (rg == 0) yc[int64_t(i) * ld] -= w * v0;
-    int r = i + 1 + rg;
-    for (; r + 28 < m; r += 32) {
-      double vv[8], yy[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        vv[u] = vp[int64_t(r + 4 * u) * ld];
-        yy[u] = yc[int64_t(r + 4 * u) * ld];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        yy[u] -= w * vv[u];
-        s2 += yy[u] * yy[u];
-        yc[int64_t(r + 4 * u) * ld] = yy[u];
-      }
-    }
-    for (; r < m; r += 4) {
-      const double y = yc[int64_t(r) * ld] - w * vp[int64_t(r) * ld];
-      yc[int64_t(r) * ld] = y;
-      s2 += y * y;
-    }
-  }
-  sp[rg][lc] = s2;
-  __syncthreads();
-  if (rg == 0 && col < n) {
-    const int64_t o = nxt * S.total + q * S.stride + col;
-    if (upd) {
-      S.nrm[o] = sp[0][lc] + sp[1][lc] + sp[2][lc] + sp[3][lc];
-      S.st[o] = -1;
-    } else if (col == p) {
-      S.st[o] = i;
-      S.alpha[q * S.stride + i] = alpha;
-      A.perm[A.poff[q] + i] = p;
-    } else {
-      S.st[o] = state;
-    }
-  }
-}
-
-// Same step when at most kIrRows * kIrGroups rows are left below it:
-// workgroup (b, q) owns 32 columns, thread (c, g) = (tid % 32, tid / 32)
-// keeps rows i + g + 32u (u < kIrRows) of column c in registers between the
-// dot product and the update, so every entry is read and written once per
-// step; the Householder vector is staged in LDS.
-constexpr int kIrCols = 32;
-constexpr int kIrGroups = 32;
-constexpr int kIrRows = 28;
-constexpr int kIrMaxRows = kIrRows * kIrGroups;
-
-__global__ __launch_bounds__(1024) void k_idm_step_reg(IdArgs A, IdmState S, int i) {
-  const int q = blockIdx.y;
-  const int m = A.rows[q], n = A.cols[q];
-  const int c0 = blockIdx.x * kIrCols;
-  if (c0 >= n || i >= min(m, n) || S.done[q]) return;
-  const int cur = i & 1, nxt = cur ^ 1;
-  const double* nrm = S.nrm + cur * S.total + q * S.stride;
-  const int32_t* st = S.st + cur * S.total + q * S.stride;
-  ArgMax loc{-1.0, INT_MAX};
-  for (int c = threadIdx.x; c < n; c += 1024)
-    if (st[c] == -1) loc = better(loc, ArgMax{nrm[c], c});
-  const ArgMax best = block_argmax(loc);
-  const double nb = sqrt(best.v > 0.0 ? best.v : 0.0);
-  const double r00 = i == 0 ? nb : S.r00[q];
-  if (!(best.v > 0.0) || !(nb > A.tol[q] * r00)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      A.rank[q] = i;
-      S.done[q] = 1;
-    }
-    return;
-  }
-  if (i == 0 && blockIdx.x == 0 && threadIdx.x == 0) S.r00[q] = nb;
-  const int p = best.i;
-  double* M = A.base + A.moff[q];
-  const int ld = A.ld[q];
-  const double x0 = M[int64_t(i) * ld + p];
-  const double alpha = -copysign(nb, x0);
-  const double v0 = x0 - alpha;
-  const double vtv = best.v - x0 * x0 + v0 * v0;
-  const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
-  const int mr = m - i;  // <= kIrMaxRows (checked on the host)
-  __shared__ double sv[kIrMaxRows];
-  __shared__ double sp[16][kIrCols];
-  const int tid = threadIdx.x, c = tid & 31, g = tid >> 5, wv = tid >> 6;
-  for (int rr = tid; rr < mr; rr += 1024) sv[rr] = rr == 0 ? v0 : M[int64_t(i + rr) * ld + p];
-  const int col = c0 + c;
-  const int state = col < n ? st[col] : -2;
-  const bool upd = state == -1 && col != p;
-  double* yc = M + int64_t(i) * ld + col;  // row i of this column
-  double y[kIrRows];
-#pragma unroll
-  for (int u = 0; u < kIrRows; ++u) {
-    const int rr = g + kIrGroups * u;
-    y[u] = (upd && rr < mr) ? yc[int64_t(rr) * ld] : 0.0;
-  }
-  __syncthreads();
-  double dot = 0.0;
-#pragma unroll
-  for (int u = 0; u < kIrRows; ++u) {
-    const int rr = g + kIrGroups * u;
-    if (rr < mr) dot += sv[rr] * y[u];
-  }
-  dot += __shfl_xor(dot, 32, 64);
-  if ((tid & 63) < 32) sp[wv][c] = dot;
-  __syncthreads();
-  double tdot = 0.0;
-#pragma unroll
-  for (int w2 = 0; w2 < 16; ++w2) tdot += sp[w2][c];
-  const double w = beta * tdot;
-  __syncthreads();
-  double s2 = 0.0;
-#pragma unroll
-  for (int u = 0; u < kIrRows; ++u) {
-    const int rr = g + kIrGroups * u;
-    if (rr < mr) {
-      y[u] -= w * sv[rr];
-      if (rr > 0) s2 += y[u] * y[u];
-    }
-  }
-  if (upd) {
-#pragma unroll
-    for (int u = 0; u < kIrRows; ++u) {
-      const int rr = g + kIrGroups * u;
-      if (rr < mr) yc[int64_t(rr) * ld] = y[u];
-    }
-  }
-  s2 += __shfl_xor(s2, 32, 64);
-  if ((tid & 63) < 32) sp[wv][c] = s2;
-  __syncthreads();
-  if (g == 0 && col < n) {
-    const int64_t o = nxt * S.total + q * S.stride + col;
-    if (upd) {
-      double t = 0.0;
-#pragma unroll
-      for (int w2 = 0; w2 < 16; ++w2) t += sp[w2][c];
-      S.nrm[o] = t;
-      S.st[o] = -1;
-    } else if (col == p) {
-      S.st[o] = i;
-      S.alpha[q * S.stride + i] = alpha;
-      A.perm[A.poff[q] + i] = p;
-    } else {
-      S.st[o] = state;
-    }
-  }
-}
-
-// Redundant columns in ascending order after the skeleton (one workgroup per problem).
-__global__ __launch_bounds__(1024) void k_idm_perm(IdArgs A, IdmState S) {
-  const int q = blockIdx.x;
-  const int n = A.cols[q];
-  const int k = A.rank[q];
-  const int32_t* st = S.st + (k & 1) * S.total + q * S.stride;
-  int32_t* perm = A.perm + A.poff[q];
-  int base = 0;
-  for (int c0 = 0; c0 < n; c0 += blockDim.x) {
-    const int c = c0 + threadIdx.x;
-    const int flag = (c < n && st[c] == -1) ? 1 : 0;
-    int tot = 0;
-    const int pre = block_excl_scan(flag, &tot);
-    if (flag) perm[k + base + pre] = c;
-    base += tot;
-  }
-}
 
 // T = R11^{-1} R12 in place over R12, by blocks of 64 rows from the bottom
 // (one launch per row block a0..a0+63): workgroup (tile, q) takes 64
@@ -784,58 +517,466 @@ __global__ __launch_bounds__(256) void k_idm_Tcopy(IdArgs A) {
   for (int a = 0; a < k; ++a) T[int64_t(a) * nr + b2] = M[int64_t(a) * ld + col];
 }
 
-static void launch_id_multi(const IdArgs& A, int max_cols, hipStream_t s) {
-  const int64_t stride = max_cols;
-  const int64_t total = stride * A.nprob;
-  DBuf<double> nrm, alpha, r00;
-  DBuf<int32_t> st, done;
-  nrm.alloc(2 * total, nullptr);
-  st.alloc(2 * total, nullptr);
-  alpha.alloc(total, nullptr);
-  r00.alloc(A.nprob, nullptr);
-  done.alloc(A.nprob, nullptr);
-  IdmState S{nrm.p, st.p, alpha.p, r00.p, done.p, stride, total};
-  const dim3 grid(unsigned((max_cols + kIdmCols - 1) / kIdmCols), unsigned(A.nprob));
-  const dim3 grid_reg(unsigned((max_cols + kIrCols - 1) / kIrCols), unsigned(A.nprob));
-  hipLaunchKernelGGL(k_idm_init, grid, dim3(kIdmThreads), 0, s, A, S);
-  std::vector<int32_t> hd(A.nprob);
-  // the ID runs on the compressed block (rows <= cols <= max_cols): steps
-  // with at most kIrMaxRows rows left keep the columns in registers
-  for (int i = 0; i < max_cols; ++i) {
-    if (max_cols - i <= kIrMaxRows)
-      hipLaunchKernelGGL(k_idm_step_reg, grid_reg, dim3(1024), 0, s, A, S, i);
-    else
-      hipLaunchKernelGGL(k_idm_step, grid, dim3(kIdmThreads), 0, s, A, S, i);
-    if ((i & 15) == 15) {  // stop launching once every problem has met the rank rule
-      HIF_HIP(hipMemcpyAsync(hd.data(), done.p, sizeof(int32_t) * A.nprob, hipMemcpyDeviceToHost, s));
-      HIF_HIP(hipStreamSynchronize(s));
-      bool all = true;
-      for (int v : hd) all = all && v;
-      if (all) break;
+// ---------------------------------------------------------------------------
+// Blocked column-pivoted QR on the uncompressed block (no row compression
+// first): the pivot sequence and rank rule of k_id, with the updates of up to
+// kBq reflectors delayed as in LAPACK's xLAQPS (Quintana-Orti, Sun and
+// Bischof's BLAS-3 QRP).  With Y0 the block at the start of a block of steps,
+// after j reflectors Y = Y0 - V F^T, V = [v_0 .. v_{j-1}] (zero above each
+// step row) and F(:, j) = beta_j (Y0^T v_j - F V^T v_j).  Per step:
+//  - k_bq_piv (one workgroup per problem) picks the column of largest
+//    downdated norm, brings it up to date from V and F, applies the rank rule
+//    to its exact norm, forms the reflector and aux = -beta V^T v;
+//  - k_bq_cols reads every trailing column once (rows at and below the step,
+//    still at their block-start values), forms its entry of F, finalizes its
+//    entry of R in the step row and downdates its norm.
+// After the block, k_bq_update applies Y -= V F^T to the rows below the block
+// on the matrix cores and recomputes the norms exactly.  A downdate that
+// leaves a squared norm at or below sqrt(eps) times its last exact value
+// ends the problem's block early (the xLAQPS safeguard): the problem idles
+// until the update.  Rows above the step are final R rows; T = R11^{-1} R12
+// comes from k_idm_T_block.
+// ---------------------------------------------------------------------------
+constexpr int kBq = 32;        // reflectors per block
+constexpr int kBqT = 512;      // threads of the pivot kernel
+constexpr int kBcGroups = 16;  // row groups of the column kernel (32 columns each)
+constexpr int kBcV = 2048;     // rows of v staged in LDS by the column kernel
+constexpr double kTol3z = 1.0536712127723509e-08;  // sqrt(2^-53)
+
+struct BqCtl {  // written by k_bq_piv only, except stale (k_bq_cols sets, k_bq_update clears)
+  int k;        // steps done
+  int i0;       // first step of the open block
+  int go;       // 1: k_bq_cols runs step cur
+  int cur;
+  int p;        // pivot column of step cur
+  int done;
+  int stale;
+  int pad;
+  double beta;
+  double r00;
+};
+
+struct BqState {
+  double* nrm;    // [nprob * stride] downdated squared norms (rows >= k)
+  double* nrm0;   // [nprob * stride] squared norms at the last exact computation
+  int32_t* st;    // [nprob * stride] -2 absent, -1 trailing, >= 0 pivot step
+  double* F;      // [nprob * stride][kBq]
+  double* V;      // [nprob][kBq][vld] reflectors of the open block, column-major
+  double* aux;    // [nprob][kBq]
+  double* alpha;  // [nprob * stride] R_ii
+  BqCtl* ctl;     // [nprob]
+  int64_t stride;
+  int64_t vld;
+};
+
+__global__ __launch_bounds__(256) void k_bq_init(IdArgs A, BqState S) {
+  const int q = blockIdx.y;
+  const int m = A.rows[q], n = A.cols[q];
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= n) return;
+  const double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const int lc = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int col = c0 + lc;
+  __shared__ double sp[4][64];
+  double s = 0.0;
+  if (col < n)
+    for (int r = rg; r < m; r += 4) {
+      const double y = M[int64_t(r) * ld + col];
+      s += y * y;
+    }
+  sp[rg][lc] = s;
+  __syncthreads();
+  if (rg == 0 && col < n) {
+    const int64_t o = q * S.stride + col;
+    const double t = sp[0][lc] + sp[1][lc] + sp[2][lc] + sp[3][lc];
+    S.nrm[o] = t;
+    S.nrm0[o] = t;
+    S.st[o] = -1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    BqCtl c{};
+    S.ctl[q] = c;
+    A.rank[q] = min(m, n);
+  }
+}
+
+// Slot j of the block: step k of problem blockIdx.x.
+__global__ __launch_bounds__(kBqT) void k_bq_piv(IdArgs A, BqState S, int j) {
+  const int q = blockIdx.x;
+  BqCtl* C = S.ctl + q;
+  const int m = A.rows[q], n = A.cols[q];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int k = C->k;
+  const int i0 = j == 0 ? k : C->i0;
+  if (C->done || C->stale || k >= min(m, n)) {
+    if (tid == 0) {
+      C->go = 0;
+      C->i0 = i0;
+      if (!C->done && k >= min(m, n)) {
+        C->done = 1;
+        A.rank[q] = k;
+      }
+    }
+    return;
+  }
+  const int i = k, jb = i - i0;  // reflectors already in the block
+  const double* nrm = S.nrm + q * S.stride;
+  int32_t* st = S.st + q * S.stride;
+  ArgMax loc{-1.0, INT_MAX};
+  for (int c = tid; c < n; c += kBqT)
+    if (st[c] == -1) loc = better(loc, ArgMax{nrm[c], c});
+  const ArgMax best = block_argmax(loc);
+  __shared__ double sf[kBq], sred[16][kBq], sx0[1], sss[16];
+  const int p = best.i;
+  if (p != INT_MAX && tid < jb) sf[tid] = S.F[(q * S.stride + p) * kBq + tid];
+  __syncthreads();
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  double* V = S.V + q * kBq * S.vld;
+  const int64_t vld = S.vld;
+  // One pass over the rows: the pivot column brought up to date (kept as
+  // column jb of V), its squared norm and P = V(i:, 0:jb)^T col.  With
+  // v = col - alpha e_i, aux = -beta V(i:, 0:jb)^T v = -beta (P - alpha V(i, 0:jb)).
+  double ss = 0.0;
+  double part[kBq];
+#pragma unroll
+  for (int jj = 0; jj < kBq; ++jj) part[jj] = 0.0;
+  if (p != INT_MAX)
+    for (int r = i + tid; r < m; r += kBqT) {
+      double x = M[int64_t(r) * ld + p];
+      double vv[kBq];  // all loads first
+#pragma unroll
+      for (int jj = 0; jj < kBq; ++jj) vv[jj] = jj < jb ? V[jj * vld + r] : 0.0;
+#pragma unroll
+      for (int jj = 0; jj < kBq; ++jj)
+        if (jj < jb) x -= vv[jj] * sf[jj];
+      V[jb * vld + r] = x;
+      ss += x * x;
+      if (r == i) sx0[0] = x;
+#pragma unroll
+      for (int jj = 0; jj < kBq; ++jj) part[jj] += vv[jj] * x;
+    }
+  ss = wave_sum(ss);
+  if (lane == 0) sss[wv] = ss;
+#pragma unroll
+  for (int jj = 0; jj < kBq; ++jj) {
+    if (jj < jb) {
+      const double t = wave_sum(part[jj]);
+      if (lane == 0) sred[wv][jj] = t;
     }
   }
-  hipLaunchKernelGGL(k_idm_perm, dim3(A.nprob), dim3(1024), 0, s, A, S);
-  // ranks bound the row blocks of the triangular solve
+  __syncthreads();
+  ss = 0.0;
+#pragma unroll
+  for (int w = 0; w < kBqT / 64; ++w) ss += sss[w];
+  const double nb = sqrt(ss);
+  const double r00 = i == 0 ? nb : C->r00;
+  if (p == INT_MAX || !(ss > 0.0) || !(nb > A.tol[q] * r00)) {
+    if (tid == 0) {
+      C->go = 0;
+      C->i0 = i0;
+      C->done = 1;
+      A.rank[q] = i;
+    }
+    return;
+  }
+  const double x0 = sx0[0];
+  const double alpha = -copysign(nb, x0);
+  const double v0 = x0 - alpha;
+  const double vtv = ss - x0 * x0 + v0 * v0;
+  const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+  if (tid == 0) V[jb * vld + i] = v0;
+  if (tid < jb) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBqT / 64; ++w) t += sred[w][tid];
+    S.aux[q * kBq + tid] = -beta * (t - alpha * V[tid * vld + i]);
+  }
+  if (tid == 0) {
+    st[p] = i;
+    S.alpha[q * S.stride + i] = alpha;
+    A.perm[A.poff[q] + i] = p;
+    C->i0 = i0;
+    C->k = i + 1;
+    C->cur = i;
+    C->p = p;
+    C->go = 1;
+    C->beta = beta;
+    if (i == 0) C->r00 = nb;
+  }
+}
+
+// Workgroup (b, q): columns 32b..32b+31 of problem q, thread (c, g) =
+// (tid % 32, tid / 32) sums rows i + g + 16u of column c.
+__global__ __launch_bounds__(32 * kBcGroups) void k_bq_cols(IdArgs A, BqState S) {
+  const int q = blockIdx.y;
+  const BqCtl* C = S.ctl + q;
+  if (!C->go) return;
+  const int n = A.cols[q];
+  const int c0 = blockIdx.x * 32;
+  if (c0 >= n) return;
+  const int m = A.rows[q];
+  const int i = C->cur, jb = i - C->i0;
+  const double beta = C->beta;
+  const int tid = threadIdx.x, c = tid & 31, g = tid >> 5;
+  const double* V = S.V + q * kBq * S.vld;
+  const int64_t vld = S.vld;
+  const int mr = m - i;
+  const double* vcol = V + jb * vld + i;  // v(i + rr)
+  __shared__ double sv[kBcV];
+  __shared__ double sp[kBcGroups][32];
+  __shared__ double saux[kBq], svi[kBq + 1];
+  __shared__ double sF[32][kBq + 1];  // F rows of the 32 columns (contiguous in F)
+  const bool lds = mr <= kBcV;
+  if (lds)
+    for (int rr = tid; rr < mr; rr += 32 * kBcGroups) sv[rr] = vcol[rr];
+  if (tid < jb) saux[tid] = S.aux[q * kBq + tid];
+  if (tid <= jb) svi[tid] = V[tid * vld + i];
+  {
+    const int n32 = min(32, n - c0);
+    const double* F0 = S.F + (q * S.stride + c0) * kBq;
+    for (int e = tid; e < 32 * kBq; e += 32 * kBcGroups) {
+      const int cc = e / kBq, jj = e % kBq;
+      sF[cc][jj] = (cc < n32 && jj < jb) ? F0[e] : 0.0;
+    }
+  }
+  __syncthreads();
+  const double* vs = lds ? sv : vcol;
+  const int col = c0 + c;
+  const int64_t o = q * S.stride + col;
+  const bool upd = col < n && S.st[o] == -1;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  double d = 0.0;
+  if (upd) {
+    const double* y = M + int64_t(i) * ld + col;
+    int rr = g;
+    for (; rr + 7 * kBcGroups < mr; rr += 8 * kBcGroups) {
+      double yy[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) yy[u] = y[int64_t(rr + u * kBcGroups) * ld];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) d += yy[u] * vs[rr + u * kBcGroups];
+    }
+    for (; rr < mr; rr += kBcGroups) d += y[int64_t(rr) * ld] * vs[rr];
+  }
+  sp[g][c] = d;
+  __syncthreads();
+  if (g == 0 && upd) {
+    double t = 0.0;
+#pragma unroll
+    for (int g2 = 0; g2 < kBcGroups; ++g2) t += sp[g2][c];
+    double* yi = M + int64_t(i) * ld + col;
+    double r = *yi;
+    double f = beta * t;
+    for (int jj = 0; jj < jb; ++jj) {
+      const double fj = sF[c][jj];
+      f += fj * saux[jj];
+      r -= svi[jj] * fj;
+    }
+    S.F[o * kBq + jb] = f;
+    r -= svi[jb] * f;
+    *yi = r;
+    const double old = S.nrm[o];
+    if (old > 0.0) {
+      const double nw = old - r * r;
+      if (nw <= kTol3z * S.nrm0[o]) S.ctl[q].stale = 1;
+      S.nrm[o] = nw > 0.0 ? nw : 0.0;
+    }
+  }
+}
+
+// Y(k:, c) -= V(k:, 0:ns) F(c, 0:ns)^T for the trailing columns, then exact
+// norms.  Workgroup (b, q): columns 64b..64b+63, wave w 16 of them; rows in
+// tiles of 16 on the matrix cores.
+__global__ __launch_bounds__(256) void k_bq_update(IdArgs A, BqState S) {
+  const int q = blockIdx.y;
+  BqCtl* C = S.ctl + q;
+  const int n = A.cols[q], m = A.rows[q];
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= n) return;
+  const int k = C->k, ns = k - C->i0;
+  if (C->done || ns <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  __shared__ double sF[64][kBq + 1];
+  __shared__ int sup[64];
+  for (int e = tid; e < 64 * kBq; e += 256) {
+    const int cc = e / kBq, jj = e % kBq;
+    const int col = c0 + cc;
+    const bool up = col < n && S.st[q * S.stride + col] == -1;
+    sF[cc][jj] = (up && jj < ns) ? S.F[(q * S.stride + col) * kBq + jj] : 0.0;
+    if (jj == 0) sup[cc] = up ? 1 : 0;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && tid == 0) C->stale = 0;
+  const int cw = 16 * wv + li;  // this lane's column (as B operand / output column)
+  const int col = c0 + cw;
+  const bool up = sup[cw] != 0;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const double* V = S.V + q * kBq * S.vld;
+  const int64_t vld = S.vld;
+  double bf[kBq / 4];
+#pragma unroll
+  for (int s = 0; s < kBq / 4; ++s) bf[s] = sF[cw][4 * s + lk];
+  double nsum = 0.0;
+  for (int r0 = k; r0 < m; r0 += 16) {
+    double a[kBq / 4], y[4];
+#pragma unroll
+    for (int s = 0; s < kBq / 4; ++s) {
+      const int jj = 4 * s + lk, r = r0 + li;
+      a[s] = (jj < ns && r < m) ? V[jj * vld + r] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + 4 * v + lk;
+      y[v] = (up && r < m) ? M[int64_t(r) * ld + col] : 0.0;
+    }
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kBq / 4; ++s) acc = mfma_f64(a[s], bf[s], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + 4 * v + lk;
+      if (up && r < m) {
+        const double t = y[v] - acc[v];
+        M[int64_t(r) * ld + col] = t;
+        nsum += t * t;
+      }
+    }
+  }
+  nsum += __shfl_xor(nsum, 16, 64);
+  nsum += __shfl_xor(nsum, 32, 64);
+  if (lk == 0 && up) {
+    const int64_t o = q * S.stride + col;
+    S.nrm[o] = nsum;
+    S.nrm0[o] = nsum;
+  }
+}
+
+// Redundant columns (state -1) in ascending order after the k pivots.
+__global__ __launch_bounds__(1024) void k_bq_perm(IdArgs A, BqState S) {
+  const int q = blockIdx.x;
+  const int n = A.cols[q];
+  const int k = A.rank[q];
+  const int32_t* st = S.st + q * S.stride;
+  int32_t* perm = A.perm + A.poff[q];
+  int base = 0;
+  for (int c0 = 0; c0 < n; c0 += blockDim.x) {
+    const int c = c0 + threadIdx.x;
+    const int flag = (c < n && st[c] == -1) ? 1 : 0;
+    int tot = 0;
+    const int pre = block_excl_scan(flag, &tot);
+    if (flag) perm[k + base + pre] = c;
+    base += tot;
+  }
+}
+
+// Copy rows [0, rows) of every problem between two layouts (rows = the
+// problem's row count, or its rank when `upto_rank`); workgroup (x, q) copies
+// rows 8x..8x+7.
+__global__ __launch_bounds__(256) void k_bq_copy(IdArgs src, IdArgs dst, int upto_rank) {
+  const int q = blockIdx.y;
+  const int n = src.cols[q];
+  const int rows = upto_rank ? dst.rank[q] : src.rows[q];
+  const double* S0 = src.base + src.moff[q];
+  double* D0 = dst.base + dst.moff[q];
+  const int lds = src.ld[q], ldd = dst.ld[q];
+  for (int r = blockIdx.x * 8; r < min(rows, int(blockIdx.x) * 8 + 8); ++r)
+    for (int c = threadIdx.x; c < n; c += 256) D0[int64_t(r) * ldd + c] = S0[int64_t(r) * lds + c];
+}
+
+void launch_id_blocked(const IdArgs& A0, int max_rows, int max_cols, hipStream_t s) {
+  if (A0.nprob == 0) return;
+  // The pivoted QR streams the trailing columns of every problem at every
+  // step, 32 columns (256 bytes of a row) per workgroup: it runs on a copy
+  // whose rows start on 128-byte lines (row stride padded to 16 doubles), so
+  // that each row segment spans two lines instead of three.  Only rows
+  // 0..k-1 (R11 and T) are copied back.
+  std::vector<int32_t> hr(A0.nprob), hcl(A0.nprob);
+  HIF_HIP(hipMemcpyAsync(hr.data(), A0.rows, sizeof(int32_t) * A0.nprob, hipMemcpyDeviceToHost, s));
+  HIF_HIP(hipMemcpyAsync(hcl.data(), A0.cols, sizeof(int32_t) * A0.nprob, hipMemcpyDeviceToHost, s));
+  HIF_HIP(hipStreamSynchronize(s));
+  std::vector<int64_t> hzo(A0.nprob);
+  std::vector<int32_t> hzl(A0.nprob);
+  int64_t ztot = 0;
+  for (int q = 0; q < A0.nprob; ++q) {
+    hzl[q] = (hcl[q] + 15) & ~15;
+    hzo[q] = ztot;
+    ztot += int64_t(hr[q]) * hzl[q];
+  }
+  DBuf<double> Z;
+  DBuf<int64_t> zoff;
+  DBuf<int32_t> zld;
+  Z.alloc(ztot + 16, nullptr);
+  zoff.alloc(A0.nprob, nullptr);
+  zld.alloc(A0.nprob, nullptr);
+  HIF_HIP(hipMemcpyAsync(zoff.p, hzo.data(), sizeof(int64_t) * A0.nprob, hipMemcpyHostToDevice, s));
+  HIF_HIP(hipMemcpyAsync(zld.p, hzl.data(), sizeof(int32_t) * A0.nprob, hipMemcpyHostToDevice, s));
+  IdArgs A = A0;
+  A.base = Z.p;
+  A.moff = zoff.p;
+  A.ld = zld.p;
+  hipLaunchKernelGGL(k_bq_copy, dim3(unsigned((max_rows + 7) / 8), unsigned(A0.nprob)), dim3(256), 0, s, A0, A, 0);
+  const int64_t stride = max_cols, vld = (max_rows + 15) & ~15;
+  const int64_t total = stride * A.nprob;
+  DBuf<double> nrm, nrm0, F, V, aux, alpha;
+  DBuf<int32_t> st;
+  DBuf<BqCtl> ctl;
+  nrm.alloc(total, nullptr);
+  nrm0.alloc(total, nullptr);
+  st.alloc(total, nullptr);
+  F.alloc(total * kBq, nullptr);
+  V.alloc(int64_t(A.nprob) * kBq * vld, nullptr);
+  aux.alloc(int64_t(A.nprob) * kBq, nullptr);
+  alpha.alloc(total, nullptr);
+  ctl.alloc(A.nprob, nullptr);
+  BqState S{nrm.p, nrm0.p, st.p, F.p, V.p, aux.p, alpha.p, ctl.p, stride, vld};
+  const unsigned np = unsigned(A.nprob);
+  hipLaunchKernelGGL(k_bq_init, dim3(unsigned((max_cols + 63) / 64), np), dim3(256), 0, s, A, S);
+  const dim3 gcols(unsigned((max_cols + 31) / 32), np), gupd(unsigned((max_cols + 63) / 64), np);
+  std::vector<BqCtl> hc(A.nprob);
+  // every block takes at least one step of each unfinished problem
+  bool all = false;
+  for (int blk = 0; blk <= max_cols && !all; ++blk) {
+    for (int j = 0; j < kBq; ++j) {
+      hipLaunchKernelGGL(k_bq_piv, dim3(np), dim3(kBqT), 0, s, A, S, j);
+      hipLaunchKernelGGL(k_bq_cols, gcols, dim3(32 * kBcGroups), 0, s, A, S);
+    }
+    hipLaunchKernelGGL(k_bq_update, gupd, dim3(256), 0, s, A, S);
+    HIF_HIP(hipMemcpyAsync(hc.data(), ctl.p, sizeof(BqCtl) * A.nprob, hipMemcpyDeviceToHost, s));
+    HIF_HIP(hipStreamSynchronize(s));
+    all = true;
+    for (const BqCtl& c : hc) all = all && c.done;
+  }
+  if (!all) throw Error{HIF_EDEVICE, "blocked pivoted QR did not finish"};
+  hipLaunchKernelGGL(k_bq_perm, dim3(np), dim3(1024), 0, s, A, S);
   std::vector<int32_t> hk(A.nprob);
   HIF_HIP(hipMemcpyAsync(hk.data(), A.rank, sizeof(int32_t) * A.nprob, hipMemcpyDeviceToHost, s));
   HIF_HIP(hipStreamSynchronize(s));
   int kmax = 0;
   for (int v : hk) kmax = std::max(kmax, v);
-  const dim3 tg(unsigned((max_cols + kTb64 - 1) / kTb64), unsigned(A.nprob));
+  IdmState T{alpha.p, stride};
+  const dim3 tg(unsigned((max_cols + kTb64 - 1) / kTb64), np);
   for (int a0 = ((kmax - 1) / kTb64) * kTb64; kmax > 0 && a0 >= 0; a0 -= kTb64)
-    hipLaunchKernelGGL(k_idm_T_block, tg, dim3(256), 0, s, A, S, a0);
+    hipLaunchKernelGGL(k_idm_T_block, tg, dim3(256), 0, s, A, T, a0);
   if (A.Tout)
-    hipLaunchKernelGGL(k_idm_Tcopy, dim3(unsigned((max_cols + 255) / 256), unsigned(A.nprob)), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_idm_Tcopy, dim3(unsigned((max_cols + 255) / 256), np), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_bq_copy, dim3(unsigned((max_rows + 7) / 8), np), dim3(256), 0, s, A, A0, 1);
   HIF_HIP(hipGetLastError());
   HIF_HIP(hipStreamSynchronize(s));  // the state buffers are released on return
 }
 
+bool id_blocked_fits(int nprob, int max_rows, int max_cols) {
+  // many small problems go to the one-workgroup ID after row compression
+  (void)max_rows;
+  return nprob <= 512 && max_cols >= 128;
+}
+
 void launch_id(const IdArgs& A, int max_cols, hipStream_t s) {
   if (A.nprob == 0) return;
-  if (A.nprob <= 2048 && max_cols >= 128) {
-    launch_id_multi(A, max_cols, s);
-    return;
-  }
   // the pivoted QR runs on min(m, n) <= max_cols rows, staged in LDS
   if (max_cols > kIdMaxRows) throw Error{HIF_EUNSUPPORTED, "ID problem with more than 4096 columns"};
   int block = 64;
@@ -1453,12 +1594,18 @@ void id_batched_impl(double* mats, const int64_t* off, const int32_t* rows, cons
   Q.scratch = scratch.p;
   Q.soff = soff.p;
   Q.nprob = batch;
-  launch_rowqr_auto(Q, max_rows, max_cols, s);
+  double smn = 0.0, snn = 0.0;
+  for (int p = 0; p < batch; ++p) {
+    smn += double(hr[p]) * hc[p];
+    snn += double(hc[p]) * hc[p];
+  }
+  const bool direct = id_blocked_fits(batch, max_rows, max_cols) && smn <= 1.25 * snn;
+  if (!direct) launch_rowqr_auto(Q, max_rows, max_cols, s);
   IdArgs A;
   A.base = mats;
   A.moff = off;
   A.ld = ld.p;
-  A.rows = rows2.p;
+  A.rows = direct ? rows : rows2.p;
   A.cols = cols;
   A.tol = tol;
   A.rank = rank;
@@ -1467,7 +1614,12 @@ void id_batched_impl(double* mats, const int64_t* off, const int32_t* rows, cons
   A.Tout = T;
   A.toff = off_t;
   A.nprob = batch;
-  launch_id(A, max_cols, s);
+  if (direct)
+    launch_id_blocked(A, max_rows, max_cols, s);
+  else if (id_blocked_fits(batch, max_cols, max_cols))
+    launch_id_blocked(A, max_cols, max_cols, s);  // on R0: rows <= columns
+  else
+    launch_id(A, max_cols, s);
   HIF_HIP(hipStreamSynchronize(s));
 }
 

@@ -956,7 +956,22 @@ void Factorizer::sublevel(int lvl, int kind) {
   cls_soff.ensure(NC, mt);
   to_dev(cls_rows2.p, h_rows2, s);
   to_dev(cls_soff.p, h_soff, s);
-  qr_scratch.ensure(qtot + 1, mt);
+  // blocked pivoted QR straight on Y, or row compression then the pivoted QR of R0
+  const int rc = H->opts.row_compression;
+  // auto: on Y directly only when Y is nearly square (every step then streams
+  // about as many rows as it would after compression, and the QR of Y is saved)
+  double smn = 0.0, snn = 0.0;
+  for (int g = 0; g < G; ++g) {
+    const int64_t nf = h_nf[g + 1] - h_nf[g];
+    const double m = double(sym ? nf + P : 2 * nf + 2 * P);
+    for (int q = h_cls_first[g]; q < h_cls_first[g + 1]; ++q) {
+      smn += m * h_cls_n[q];
+      snn += double(h_cls_n[q]) * h_cls_n[q];
+    }
+  }
+  const bool direct = id_blocked_fits(NC, maxm, maxq) && (rc == 0 || (rc < 0 && smn <= 1.25 * snn));
+  const bool blocked_r0 = !direct && id_blocked_fits(NC, maxq, maxq);
+  if (!direct) qr_scratch.ensure(qtot + 1, mt);
   tm.mark(PH_HOST);
   RowQrArgs qa{};
   qa.base = Y.p;
@@ -967,13 +982,13 @@ void Factorizer::sublevel(int lvl, int kind) {
   qa.scratch = qr_scratch.p;
   qa.soff = cls_soff.p;
   qa.nprob = NC;
-  launch_rowqr_auto(qa, maxm, maxq, s);
+  if (!direct) launch_rowqr_auto(qa, maxm, maxq, s);
   tm.mark(PH_QR);
   IdArgs ia{};
   ia.base = Y.p;
   ia.moff = cls_moff.p;
   ia.ld = cls_ld.p;
-  ia.rows = cls_rows2.p;
+  ia.rows = direct ? cls_rows.p : cls_rows2.p;
   ia.cols = cls_n.p;
   ia.tol = cls_tol.p;
   ia.rank = cls_rank.p;
@@ -982,7 +997,12 @@ void Factorizer::sublevel(int lvl, int kind) {
   ia.Tout = nullptr;
   ia.toff = nullptr;
   ia.nprob = NC;
-  launch_id(ia, maxq, s);
+  if (direct)
+    launch_id_blocked(ia, maxm, maxq, s);
+  else if (blocked_r0)
+    launch_id_blocked(ia, maxq, maxq, s);  // on R0: rows <= columns
+  else
+    launch_id(ia, maxq, s);
   tm.mark(PH_ID);
 
   // ---- records: sizes from the ranks ---------------------------------------
@@ -1004,10 +1024,26 @@ void Factorizer::sublevel(int lvl, int kind) {
       rr += h_cls_n[q] - h_rank[q];
       const double nq = h_cls_n[q], kq = h_rank[q];
       idfl += 4.0 * m * nq * kq - 2.0 * kq * kq * (m + nq) + 4.0 * kq * kq * kq / 3.0 + kq * kq * (nq - kq);
-      // sum_{i<k} (a - i)(b - i) with a = rows after compression, b = columns
-      const double a2 = double(std::min<int64_t>(m, h_cls_n[q]));
-      idby += 16.0 * (kq * a2 * nq - (a2 + nq) * kq * (kq - 1.0) / 2.0 + (kq - 1.0) * kq * (2.0 * kq - 1.0) / 6.0);
-      if (m > h_cls_n[q]) rqfl += 2.0 * m * nq * nq - 2.0 * nq * nq * nq / 3.0;
+      // sum_{i<k} (a - i)(b - i), b = columns and a = rows the pivoted QR runs on
+      const double a2 = direct ? double(m) : double(std::min<int64_t>(m, h_cls_n[q]));
+      const double sab = kq * a2 * nq - (a2 + nq) * kq * (kq - 1.0) / 2.0 + (kq - 1.0) * kq * (2.0 * kq - 1.0) / 6.0;
+      if (direct) {
+        // each step reads the trailing block once; each finished block of
+        // reflectors reads and writes the rows below it once
+        idby += 8.0 * sab;
+        for (int e = 32; e <= h_rank[q] && e < std::min<int64_t>(m, h_cls_n[q]); e += 32)
+          idby += 16.0 * (double(m) - e) * (nq - e);
+      } else {
+        // blocked on R0 (rows m' = min(m, n)) as on Y; unblocked: each step
+        // reads and writes the trailing block of R0
+        if (blocked_r0) {
+          idby += 8.0 * sab;
+          for (int e = 32; e <= h_rank[q] && e < a2; e += 32) idby += 16.0 * (a2 - e) * (nq - e);
+        } else {
+          idby += 16.0 * sab;
+        }
+        if (m > h_cls_n[q]) rqfl += 2.0 * m * nq * nq - 2.0 * nq * nq * nq / 3.0;
+      }
     }
     skel += kk;
     h_newoff[g] = ntot_new;

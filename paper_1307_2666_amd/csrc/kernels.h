@@ -51,6 +51,10 @@ struct IdArgs {
   int nprob = 0;
 };
 void launch_id(const IdArgs& A, int max_cols, hipStream_t s);
+// Blocked pivoted QR on the uncompressed problems (rows up to max_rows), same
+// outputs as launch_id; id_blocked_fits says whether a batch suits it.
+void launch_id_blocked(const IdArgs& A, int max_rows, int max_cols, hipStream_t s);
+bool id_blocked_fits(int nprob, int max_rows, int max_cols);
 
 // Row compression Y = Q R0 (blocked Householder, no pivoting) before the ID;
 // R0 overwrites the leading n x n block of each problem with m > n.

@@ -130,7 +130,7 @@ def test_id_batched_matches_oracle():
 
 
 def test_id_batched_large_matches_oracle():
-    # >= 384 columns: the multi-workgroup pivoted QR (one launch per pivot step)
+    # >= 128 columns and m >> n: row compression, then the blocked pivoted QR of R0
     rng = np.random.default_rng(9)
     cases = []
     Y = rng.standard_normal((900, 500)) * (1.05 ** -np.arange(500))[rng.permutation(500)]
@@ -151,6 +151,52 @@ def test_id_batched_large_matches_oracle():
         r00 = np.max(np.linalg.norm(Y, axis=0))
         err = np.linalg.norm(Y[:, rd] - Y[:, sk] @ T)
         assert err <= np.sqrt(rd.size) * tol * r00 * 1.01 + 1e-14 * r00
+
+
+def test_id_batched_direct_matches_oracle():
+    # nearly square blocks (sum m n <= 1.25 sum n^2): the blocked pivoted QR runs
+    # on Y itself, without row compression; includes m < n, an exactly low-rank
+    # block whose norms collapse inside a block of reflectors, and zero columns
+    rng = np.random.default_rng(11)
+    cases = []
+    Y = rng.standard_normal((520, 500)) * (1.04 ** -np.arange(500))[rng.permutation(500)]
+    cases.append((Y, 1e-6, True))
+    Y = rng.standard_normal((400, 600)) * (1.03 ** -np.arange(600))[rng.permutation(600)]
+    cases.append((Y, 1e-6, True))
+    Y = rng.standard_normal((300, 7)) @ rng.standard_normal((7, 290))
+    Y[:, ::9] = 0.0
+    cases.append((Y, 1e-8, False))
+    out = hif.id_batched([torch.tensor(Y) for Y, _, _ in cases], [t for _, t, _ in cases])
+    for (Y, tol, unique), (sk, rd, T) in zip(cases, out):
+        sk, rd, T = sk.numpy(), rd.numpy(), T.numpy()
+        osk, ord_, oT = interp_decomp(Y, tol)
+        assert abs(sk.size - osk.size) <= 1, (Y.shape, sk.size, osk.size)
+        assert np.array_equal(np.sort(np.concatenate([sk, rd])), np.arange(Y.shape[1]))
+        assert np.all(np.diff(rd) > 0)
+        if unique:
+            assert np.array_equal(sk, osk)
+            assert np.allclose(T, oT, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(oT).max()))
+        r00 = np.max(np.linalg.norm(Y, axis=0))
+        err = np.linalg.norm(Y[:, rd] - Y[:, sk] @ T)
+        assert err <= np.sqrt(rd.size) * tol * r00 * 1.01 + 1e-14 * r00
+
+
+@pytest.mark.parametrize("row_compression", [0, 1])
+def test_factor_sq64_row_compression_modes(row_compression):
+    # the upper levels of the 64 x 64 workload have classes of >= 128 columns:
+    # blocked pivoted QR on Y (0) or on the R factor of Y (1)
+    wl = workload("sq64")
+    op = Operator.uniform(wl.points(), wl.h, a=np.ones(wl.N))
+    F = hif.factor(_t(op.points), wl.eps, wl.leaf, a=_t(op.a), h=wl.h, row_compression=row_compression)
+    A = op.dense()
+    x = np.random.default_rng(12).standard_normal(wl.N)
+    y = _np(F.apply(_t(x)))
+    assert np.linalg.norm(y - A @ x) <= 10 * wl.eps * np.linalg.norm(A @ x)
+    u = _np(F.solve(_t(A @ x)))
+    assert np.linalg.norm(u - x) <= 10 * wl.eps * np.linalg.norm(x)
+    st = F.stats()
+    if row_compression == 0:  # cells of levels 1 and 2 (173 to 292 columns): no QR of Y
+        assert st["sub_t_ms"][2]["rowqr"] < 0.2 and st["sub_t_ms"][4]["rowqr"] < 0.2
 
 
 # ---------------------------------------------------------------------------
