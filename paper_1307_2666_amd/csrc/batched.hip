@@ -493,7 +493,7 @@ __device__ __forceinline__ void store_vrow(const double (&y)[kTb], int t, int jb
 
 // T of the compact WY form I - V T V^T (T upper triangular) from beta and
 // G = V^T V (matrix cores, 4 waves), V row-major rows x kTb in global memory.
-__device__ void build_T(const double* V, int rows, const double* sbeta, double* sG, double* sT, double* Tout) {
+__device__ void build_T(const double* V, int rows, const double* sbeta, double* sG, double* Tout) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nw = blockDim.x >> 6;
@@ -515,18 +515,25 @@ __device__ void build_T(const double* V, int rows, const double* sbeta, double* 
     for (int v = 0; v < 4; ++v) sG[(p0 + 4 * v + lk) * (kTb + 1) + p1 + li] = acc[v];
   }
   __syncthreads();
-  for (int i = 0; i < kTb; ++i) {
-    const int p = threadIdx.x;
-    if (p < i) {
+  // T(p, i) = -beta_i sum_{l < i} T(p, l) G(l, i) for p < i, T(i, i) = beta_i:
+  // one wave, lane p keeps row p of T in registers (no barriers)
+  if (wv == 0) {
+    const int p = lane & (kTb - 1);
+    double trow[kTb];
+#pragma unroll
+    for (int l = 0; l < kTb; ++l) trow[l] = 0.0;
+#pragma unroll
+    for (int i = 0; i < kTb; ++i) {
       double acc = 0.0;
-      for (int l = p; l < i; ++l) acc += sT[p * kTb + l] * sG[l * (kTb + 1) + i];
-      sT[p * kTb + i] = -sbeta[i] * acc;
-    } else if (p < kTb) {
-      sT[p * kTb + i] = p == i ? sbeta[i] : 0.0;
+#pragma unroll
+      for (int l = 0; l < i; ++l) acc += trow[l] * sG[l * (kTb + 1) + i];
+      const double b = sbeta[i];
+      trow[i] = p == i ? b : (p < i ? -b * acc : 0.0);
     }
-    __syncthreads();
+    if (lane < kTb)
+#pragma unroll
+      for (int l = 0; l < kTb; ++l) Tout[p * kTb + l] = trow[l];
   }
-  for (int e = threadIdx.x; e < kTb * kTb; e += blockDim.x) Tout[e] = sT[e];
 }
 
 // K1: QR of one chunk of the panel (chunks of at most cr = BS * RPT rows).
@@ -544,7 +551,7 @@ __global__ __launch_bounds__(BS) void k_tsqr_chunk(QrBatch A, int j0, int cr) {
   const TsqrLayout L = tsqr_layout(m);
   const int t0 = threadIdx.x;
   __shared__ double sred[2 * (BS / 64) * kTb], srow[2 * kTb], scf[2 * (kTb + 2)], sv0[kTb], sbeta[kTb];
-  __shared__ double sG[kTb * (kTb + 1)], sT[kTb * kTb];
+  __shared__ double sG[kTb * (kTb + 1)];
   double y[RPT][kTb];
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
@@ -573,7 +580,7 @@ __global__ __launch_bounds__(BS) void k_tsqr_chunk(QrBatch A, int j0, int cr) {
     for (int cc = 0; cc < kTb; ++cc) dst[cc] = (t0 < g.jb && cc >= t0 && cc < g.jb) ? y[0][cc] : 0.0;
   }
   __syncthreads();
-  build_T(V, rows, sbeta, sG, sT, S0 + L.Tc + int64_t(c) * kTb * kTb);
+  build_T(V, rows, sbeta, sG, S0 + L.Tc + int64_t(c) * kTb * kTb);
 }
 
 // K2: QR of the stacked chunk R factors (nck > 1); writes the panel's R.
@@ -591,7 +598,7 @@ __global__ __launch_bounds__(BS) void k_tsqr_stack(QrBatch A, int j0, int cr) {
   const TsqrLayout L = tsqr_layout(m);
   const int t = threadIdx.x;
   __shared__ double sred[2 * (BS / 64) * kTb], srow[2 * kTb], scf[2 * (kTb + 2)], sv0[kTb], sbeta[kTb];
-  __shared__ double sG[kTb * (kTb + 1)], sT[kTb * kTb];
+  __shared__ double sG[kTb * (kTb + 1)];
   double y[RPT][kTb];
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
@@ -614,58 +621,73 @@ __global__ __launch_bounds__(BS) void k_tsqr_stack(QrBatch A, int j0, int cr) {
       if (cc < g.jb) dst[cc] = cc >= t ? y[0][cc] : 0.0;
   }
   __syncthreads();
-  build_T(V, srows, sbeta, sG, sT, S0 + L.Ts);
+  build_T(V, srows, sbeta, sG, S0 + L.Ts);
 }
 
 // Y <- (I - V T V^T)^T Y for one 64-column tile: P = V^T Y, W = T^T P,
-// Y -= V W.  rowp(r) gives the address of row r of the tile.
+// Y -= V W.  rowp(r) gives the address of row r of the tile.  256 threads;
+// wave w owns columns 16w..16w+15 and needs nothing from the other waves:
+// in the 16x16x4 FP64 MFMA layout, element v of an accumulator tile holds
+// rows 4v + (lane / 16) of column lane % 16, which is exactly the B operand
+// of K-step v, so P feeds W = T^T P and W feeds Y -= V W from registers.
 template <class RowP>
-__device__ void apply_wy_tile(const double* V, int rows, const double* Tm, RowP rowp, int nt, double* sP, double* sW) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+__device__ void apply_wy_tile(const double* V, int rows, const double* Tm, RowP rowp, int nt) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  // 1. P (kTb x 64): 8 tiles of 16 x 16, K = rows
-  for (int tile = wv; tile < 8; tile += nw) {
-    const int p0 = (tile >> 2) * 16, ct = (tile & 3) * 16;
-    double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    for (int kb = 0; kb < rows; kb += 32) {  // 8 steps of 4 rows, loads issued first
-      double a[8], b[8];
+  const int ct = wv * 16;
+  const bool colok = ct + li < nt;
+  // 1. P (kTb x 16): rows 0-15 in p0, 16-31 in p1, from one read of Y
+  double4_t p0 = {0.0, 0.0, 0.0, 0.0}, p1 = {0.0, 0.0, 0.0, 0.0};
+  for (int kb = 0; kb < rows; kb += 32) {  // 8 steps of 4 rows, loads issued first
+    double a0[8], a1[8], b[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int r = kb + 4 * u + lk;
-        const bool ok = r < rows;
-        a[u] = ok ? V[int64_t(r) * kTb + p0 + li] : 0.0;
-        b[u] = (ok && ct + li < nt) ? rowp(r)[ct + li] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc = mfma_f64(a[u], b[u], acc);
+    for (int u = 0; u < 8; ++u) {
+      const int r = kb + 4 * u + lk;
+      const bool ok = r < rows;
+      a0[u] = ok ? V[int64_t(r) * kTb + li] : 0.0;
+      a1[u] = ok ? V[int64_t(r) * kTb + 16 + li] : 0.0;
+      b[u] = (ok && colok) ? rowp(r)[ct + li] : 0.0;
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sP[(p0 + 4 * v + lk) * 65 + ct + li] = acc[v];
-  }
-  __syncthreads();
-  // 2. W = T^T P, T upper triangular
-  for (int e = tid; e < kTb * 64; e += blockDim.x) {
-    const int i = e >> 6, c = e & 63;
-    double acc = 0.0;
-    for (int p = 0; p <= i; ++p) acc += Tm[p * kTb + i] * sP[p * 65 + c];
-    sW[i * 65 + c] = acc;
-  }
-  __syncthreads();
-  // 3. Y -= V W, 16 x 16 output tiles
-  const int ntr = (rows + 15) >> 4;
-  for (int tile = wv; tile < ntr * 4; tile += nw) {
-    const int rt = (tile >> 2) * 16, ct = (tile & 3) * 16;
-    double4_t d = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int ks = 0; ks < kTb; ks += 4) {
-      const int r = rt + li;
-      const double a = r < rows ? V[int64_t(r) * kTb + ks + lk] : 0.0;
-      d = mfma_f64(a, sW[(ks + lk) * 65 + ct + li], d);
+    for (int u = 0; u < 8; ++u) {
+      p0 = mfma_f64(a0[u], b[u], p0);
+      p1 = mfma_f64(a1[u], b[u], p1);
     }
+  }
+  // 2. W = T^T P (T upper triangular, zero below the diagonal): A(i, k) = T(k, i)
+  double4_t w0 = {0.0, 0.0, 0.0, 0.0}, w1 = {0.0, 0.0, 0.0, 0.0};
+  {
+    double t0[8], t1[8];
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      t0[s2] = Tm[(4 * s2 + lk) * kTb + li];
+      t1[s2] = Tm[(4 * s2 + lk) * kTb + 16 + li];
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      const double bp = s2 < 4 ? p0[s2 & 3] : p1[s2 & 3];
+      w0 = mfma_f64(t0[s2], bp, w0);
+      w1 = mfma_f64(t1[s2], bp, w1);
+    }
+  }
+  // 3. Y -= V W over 16-row tiles
+  for (int rt = 0; rt < rows; rt += 16) {
+    double a[8], y[4];
+    const int ra = rt + li;
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) a[s2] = ra < rows ? V[int64_t(ra) * kTb + 4 * s2 + lk] : 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = rt + 4 * v + lk, col = ct + li;
-      if (r < rows && col < nt) rowp(r)[col] -= d[v];
+      const int r = rt + 4 * v + lk;
+      y[v] = (r < rows && colok) ? rowp(r)[ct + li] : 0.0;
+    }
+    double4_t d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) d = mfma_f64(a[s2], s2 < 4 ? w0[s2 & 3] : w1[s2 & 3], d);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = rt + 4 * v + lk;
+      if (r < rows && colok) rowp(r)[ct + li] = y[v] - d[v];
     }
   }
 }
@@ -685,10 +707,9 @@ __global__ __launch_bounds__(256) void k_tsqr_apply_chunk(QrBatch A, int j0, int
   const int ld = A.ld[q];
   const double* S0 = A.scratch + A.soff[q];
   const TsqrLayout L = tsqr_layout(m);
-  __shared__ double sP[kTb * 65], sW[kTb * 65];
   double* Y0 = M + int64_t(j0 + lo) * ld + c0;
   apply_wy_tile(S0 + L.V + int64_t(lo) * kTb, rows, S0 + L.Tc + int64_t(c) * kTb * kTb,
-                [=](int r) { return Y0 + int64_t(r) * ld; }, nt, sP, sW);
+                [=](int r) { return Y0 + int64_t(r) * ld; }, nt);
 }
 
 // K4: trailing update of the chunk top rows with the stack's WY form.
@@ -705,11 +726,10 @@ __global__ __launch_bounds__(256) void k_tsqr_apply_stack(QrBatch A, int j0, int
   const int ld = A.ld[q];
   const double* S0 = A.scratch + A.soff[q];
   const TsqrLayout L = tsqr_layout(m);
-  __shared__ double sP[kTb * 65], sW[kTb * 65];
   const int mp = g.mp, nck = g.nck;
   double* Mc = M + int64_t(j0) * ld + c0;
   apply_wy_tile(S0 + L.Vs, nck * kTb, S0 + L.Ts,
-                [=](int r) { return Mc + int64_t(chunk_lo(r / kTb, mp, nck) + r % kTb) * ld; }, nt, sP, sW);
+                [=](int r) { return Mc + int64_t(chunk_lo(r / kTb, mp, nck) + r % kTb) * ld; }, nt);
 }
 
 // ---------------------------------------------------------------------------
