@@ -33,10 +33,11 @@ __host__ __device__ inline TsqrLayout tsqr_layout(int m) {
   L.total = L.Ts + b2;
   return L;
 }
-// Scratch doubles every row-compression path needs for an m x n problem (m > n).
+// Scratch doubles every row-compression path needs for an m x n problem
+// (m > n); the TSQR panels alternate between two copies of the layout.
 inline int64_t rowqr_scratch(int64_t m, int64_t n) {
   const int64_t fused = m * 16 + 16 * n + 256;
-  const int64_t tsqr = tsqr_layout(int(m)).total;
+  const int64_t tsqr = 2 * tsqr_layout(int(m)).total;
   return fused > tsqr ? fused : tsqr;
 }
 

@@ -538,7 +538,7 @@ __device__ void build_T(const double* V, int rows, const double* sbeta, double* 
 
 // K1: QR of one chunk of the panel (chunks of at most cr = BS * RPT rows).
 template <int BS, int RPT>
-__global__ __launch_bounds__(BS) void k_tsqr_chunk(QrBatch A, int j0, int cr) {
+__global__ __launch_bounds__(BS) void k_tsqr_chunk(QrBatch A, int j0, int cr, int half) {
   const int q = blockIdx.y, c = blockIdx.x;
   const int m = A.rows[q], n = A.cols[q];
   if (m <= n || j0 >= n) return;
@@ -547,8 +547,8 @@ __global__ __launch_bounds__(BS) void k_tsqr_chunk(QrBatch A, int j0, int cr) {
   const int lo = chunk_lo(c, g.mp, g.nck), rows = chunk_lo(c + 1, g.mp, g.nck) - lo;
   double* M = A.base + A.moff[q];
   const int ld = A.ld[q];
-  double* S0 = A.scratch + A.soff[q];
   const TsqrLayout L = tsqr_layout(m);
+  double* S0 = A.scratch + A.soff[q] + half * L.total;
   const int t0 = threadIdx.x;
   __shared__ double sred[2 * (BS / 64) * kTb], srow[2 * kTb], scf[2 * (kTb + 2)], sv0[kTb], sbeta[kTb];
   __shared__ double sG[kTb * (kTb + 1)];
@@ -585,7 +585,7 @@ __global__ __launch_bounds__(BS) void k_tsqr_chunk(QrBatch A, int j0, int cr) {
 
 // K2: QR of the stacked chunk R factors (nck > 1); writes the panel's R.
 template <int BS, int RPT>
-__global__ __launch_bounds__(BS) void k_tsqr_stack(QrBatch A, int j0, int cr) {
+__global__ __launch_bounds__(BS) void k_tsqr_stack(QrBatch A, int j0, int cr, int half) {
   const int q = blockIdx.x;
   const int m = A.rows[q], n = A.cols[q];
   if (m <= n || j0 >= n) return;
@@ -594,8 +594,8 @@ __global__ __launch_bounds__(BS) void k_tsqr_stack(QrBatch A, int j0, int cr) {
   const int srows = g.nck * kTb;
   double* M = A.base + A.moff[q];
   const int ld = A.ld[q];
-  double* S0 = A.scratch + A.soff[q];
   const TsqrLayout L = tsqr_layout(m);
+  double* S0 = A.scratch + A.soff[q] + half * L.total;
   const int t = threadIdx.x;
   __shared__ double sred[2 * (BS / 64) * kTb], srow[2 * kTb], scf[2 * (kTb + 2)], sv0[kTb], sbeta[kTb];
   __shared__ double sG[kTb * (kTb + 1)];
@@ -692,40 +692,129 @@ __device__ void apply_wy_tile(const double* V, int rows, const double* Tm, RowP 
   }
 }
 
+// The same update for chunks of at most 256 rows with the wave's 256 x 16
+// slice of Y held in registers from the first product to the write-back, so
+// that Y is read once and written once (element v of row tile t is row
+// 16t + 4v + lane / 16, column lane % 16: the B operand of K-step 4t + v).
+__device__ void apply_wy_tile_reg(const double* V, int rows, const double* Tm, double* Y0, int64_t ld, int nt) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ct = wv * 16;
+  const bool colok = ct + li < nt;
+  double yv[16][4];
+#pragma unroll
+  for (int t = 0; t < 16; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * t + 4 * v + lk;
+      yv[t][v] = (r < rows && colok) ? Y0[int64_t(r) * ld + ct + li] : 0.0;
+    }
+  // 1. P = V^T Y (rows past the chunk are zero in yv; V rows there are not read)
+  double4_t p0 = {0.0, 0.0, 0.0, 0.0}, p1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    if (16 * t >= rows) break;
+    double a0[4], a1[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * t + 4 * v + lk;
+      a0[v] = r < rows ? V[int64_t(r) * kTb + li] : 0.0;
+      a1[v] = r < rows ? V[int64_t(r) * kTb + 16 + li] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      p0 = mfma_f64(a0[v], yv[t][v], p0);
+      p1 = mfma_f64(a1[v], yv[t][v], p1);
+    }
+  }
+  // 2. W = T^T P
+  double4_t w0 = {0.0, 0.0, 0.0, 0.0}, w1 = {0.0, 0.0, 0.0, 0.0};
+  {
+    double t0[8], t1[8];
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      t0[s2] = Tm[(4 * s2 + lk) * kTb + li];
+      t1[s2] = Tm[(4 * s2 + lk) * kTb + 16 + li];
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      const double bp = s2 < 4 ? p0[s2 & 3] : p1[s2 & 3];
+      w0 = mfma_f64(t0[s2], bp, w0);
+      w1 = mfma_f64(t1[s2], bp, w1);
+    }
+  }
+  // 3. Y -= V W, written back
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    if (16 * t >= rows) break;
+    double a[8];
+    const int ra = 16 * t + li;
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) a[s2] = ra < rows ? V[int64_t(ra) * kTb + 4 * s2 + lk] : 0.0;
+    double4_t d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) d = mfma_f64(a[s2], s2 < 4 ? w0[s2 & 3] : w1[s2 & 3], d);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * t + 4 * v + lk;
+      if (r < rows && colok) Y0[int64_t(r) * ld + ct + li] = yv[t][v] - d[v];
+    }
+  }
+}
+
 // K3: trailing update of chunk blockIdx.y, column tile blockIdx.x.
-__global__ __launch_bounds__(256) void k_tsqr_apply_chunk(QrBatch A, int j0, int cr) {
+__global__ __launch_bounds__(256) void k_tsqr_apply_chunk(QrBatch A, int j0, int cr, int half, int cbeg, int cend) {
   const int q = blockIdx.z, c = blockIdx.y;
   const int m = A.rows[q], n = A.cols[q];
   if (m <= n || j0 >= n) return;
   const PanelGeom g = panel_geom(m, n, j0, cr);
   if (c >= g.nck) return;
-  const int c0 = j0 + g.jb + blockIdx.x * 64;
-  if (c0 >= n) return;
-  const int nt = min(64, n - c0);
+  const int c0 = cbeg + blockIdx.x * 64, ce = min(n, cend);
+  if (c0 >= ce) return;
+  const int nt = min(64, ce - c0);
   const int lo = chunk_lo(c, g.mp, g.nck), rows = chunk_lo(c + 1, g.mp, g.nck) - lo;
   double* M = A.base + A.moff[q];
   const int ld = A.ld[q];
-  const double* S0 = A.scratch + A.soff[q];
   const TsqrLayout L = tsqr_layout(m);
+  const double* S0 = A.scratch + A.soff[q] + half * L.total;
   double* Y0 = M + int64_t(j0 + lo) * ld + c0;
   apply_wy_tile(S0 + L.V + int64_t(lo) * kTb, rows, S0 + L.Tc + int64_t(c) * kTb * kTb,
                 [=](int r) { return Y0 + int64_t(r) * ld; }, nt);
 }
 
+// K3 for chunks of at most 256 rows, Y held in registers.
+__global__ __launch_bounds__(256, 2) void k_tsqr_apply_chunk_reg(QrBatch A, int j0, int cr, int half, int cbeg, int cend) {
+  const int q = blockIdx.z, c = blockIdx.y;
+  const int m = A.rows[q], n = A.cols[q];
+  if (m <= n || j0 >= n) return;
+  const PanelGeom g = panel_geom(m, n, j0, cr);
+  if (c >= g.nck) return;
+  const int c0 = cbeg + blockIdx.x * 64, ce = min(n, cend);
+  if (c0 >= ce) return;
+  const int nt = min(64, ce - c0);
+  const int lo = chunk_lo(c, g.mp, g.nck), rows = chunk_lo(c + 1, g.mp, g.nck) - lo;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const TsqrLayout L = tsqr_layout(m);
+  const double* S0 = A.scratch + A.soff[q] + half * L.total;
+  apply_wy_tile_reg(S0 + L.V + int64_t(lo) * kTb, rows, S0 + L.Tc + int64_t(c) * kTb * kTb,
+                    M + int64_t(j0 + lo) * ld + c0, ld, nt);
+}
+
 // K4: trailing update of the chunk top rows with the stack's WY form.
-__global__ __launch_bounds__(256) void k_tsqr_apply_stack(QrBatch A, int j0, int cr) {
+__global__ __launch_bounds__(256) void k_tsqr_apply_stack(QrBatch A, int j0, int cr, int half, int cbeg, int cend) {
   const int q = blockIdx.y;
   const int m = A.rows[q], n = A.cols[q];
   if (m <= n || j0 >= n) return;
   const PanelGeom g = panel_geom(m, n, j0, cr);
   if (g.nck < 2) return;
-  const int c0 = j0 + g.jb + blockIdx.x * 64;
-  if (c0 >= n) return;
-  const int nt = min(64, n - c0);
+  const int c0 = cbeg + blockIdx.x * 64, ce = min(n, cend);
+  if (c0 >= ce) return;
+  const int nt = min(64, ce - c0);
   double* M = A.base + A.moff[q];
   const int ld = A.ld[q];
-  const double* S0 = A.scratch + A.soff[q];
   const TsqrLayout L = tsqr_layout(m);
+  const double* S0 = A.scratch + A.soff[q] + half * L.total;
   const int mp = g.mp, nck = g.nck;
   double* Mc = M + int64_t(j0) * ld + c0;
   apply_wy_tile(S0 + L.Vs, nck * kTb, S0 + L.Ts,
@@ -1054,27 +1143,66 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
   if (rpt > 0) {
     const int cr = rpt == 1 ? kTsqrRows : 4 * kTsqrRows;
     const unsigned nckmax = unsigned((max_rows + cr - 1) / cr);
-    for (int j0 = 0; j0 < max_cols; j0 += kTsqrNb) {
+    // Look-ahead: panel p is factored on s; its update of the next panel's
+    // 32 columns also runs on s, and that of the remaining columns on a
+    // second stream, overlapping the factorization of panel p + 1.  Panels
+    // alternate between two scratch halves (p & 1), so that panel p + 1
+    // never overwrites the V and T that the update of panel p still reads.
+    // Orders: the update of panel p on any column follows that of panel
+    // p - 1 (s waits for the remaining-columns update of p - 1 before its
+    // own updates of panel p), and the remaining-columns update of p
+    // follows the factorization of p (it waits for an event recorded after
+    // the stack kernel).
+    hipStream_t s2;
+    hipEvent_t ev_fact, ev_rest;
+    HIF_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    HIF_HIP(hipEventCreateWithFlags(&ev_fact, hipEventDisableTiming));
+    HIF_HIP(hipEventCreateWithFlags(&ev_rest, hipEventDisableTiming));
+    bool rest_pending = false;
+    for (int j0 = 0, p = 0; j0 < max_cols; j0 += kTsqrNb, ++p) {
+      const int half = p & 1;
       // two rows per thread: 128 threads per 256-row chunk, 512 per 1024-row chunk
       if (rpt == 1)
-        hipLaunchKernelGGL((k_tsqr_chunk<128, 2>), dim3(nckmax, A.nprob), dim3(128), 0, s, A, j0, cr);
+        hipLaunchKernelGGL((k_tsqr_chunk<128, 2>), dim3(nckmax, A.nprob), dim3(128), 0, s, A, j0, cr, half);
       else
-        hipLaunchKernelGGL((k_tsqr_chunk<512, 2>), dim3(nckmax, A.nprob), dim3(512), 0, s, A, j0, cr);
+        hipLaunchKernelGGL((k_tsqr_chunk<512, 2>), dim3(nckmax, A.nprob), dim3(512), 0, s, A, j0, cr, half);
       if (nckmax * kTsqrNb <= 256)  // block sized to the tallest stack (two rows per thread)
-        hipLaunchKernelGGL((k_tsqr_stack<128, 2>), dim3(A.nprob), dim3(128), 0, s, A, j0, cr);
+        hipLaunchKernelGGL((k_tsqr_stack<128, 2>), dim3(A.nprob), dim3(128), 0, s, A, j0, cr, half);
       else if (nckmax * kTsqrNb <= 512)
-        hipLaunchKernelGGL((k_tsqr_stack<256, 2>), dim3(A.nprob), dim3(256), 0, s, A, j0, cr);
+        hipLaunchKernelGGL((k_tsqr_stack<256, 2>), dim3(A.nprob), dim3(256), 0, s, A, j0, cr, half);
       else
-        hipLaunchKernelGGL((k_tsqr_stack<512, 2>), dim3(A.nprob), dim3(512), 0, s, A, j0, cr);
-      const int rem = max_cols - j0 - kTsqrNb;
-      if (rem > 0) {
-        const unsigned tiles = unsigned((rem + 63) / 64);
-        hipLaunchKernelGGL(k_tsqr_apply_chunk, dim3(tiles, nckmax, A.nprob), dim3(256), 0, s, A, j0, cr);
-        hipLaunchKernelGGL(k_tsqr_apply_stack, dim3(tiles, A.nprob), dim3(256), 0, s, A, j0, cr);
+        hipLaunchKernelGGL((k_tsqr_stack<512, 2>), dim3(A.nprob), dim3(512), 0, s, A, j0, cr, half);
+      const int nb0 = j0 + kTsqrNb, nb1 = j0 + 2 * kTsqrNb;  // next panel: columns [nb0, nb1)
+      if (nb0 >= max_cols) break;
+      HIF_HIP(hipEventRecord(ev_fact, s));
+      if (rest_pending) HIF_HIP(hipStreamWaitEvent(s, ev_rest, 0));  // remaining-columns update of p - 1
+      rest_pending = false;
+      if (nb1 < max_cols) {
+        const unsigned tiles = unsigned((max_cols - nb1 + 63) / 64);
+        HIF_HIP(hipStreamWaitEvent(s2, ev_fact, 0));
+        if (cr <= 256)
+          hipLaunchKernelGGL(k_tsqr_apply_chunk_reg, dim3(tiles, nckmax, A.nprob), dim3(256), 0, s2, A, j0, cr,
+                             half, nb1, max_cols);
+        else
+          hipLaunchKernelGGL(k_tsqr_apply_chunk, dim3(tiles, nckmax, A.nprob), dim3(256), 0, s2, A, j0, cr, half,
+                             nb1, max_cols);
+        hipLaunchKernelGGL(k_tsqr_apply_stack, dim3(tiles, A.nprob), dim3(256), 0, s2, A, j0, cr, half, nb1, max_cols);
+        HIF_HIP(hipEventRecord(ev_rest, s2));
+        rest_pending = true;
       }
+      if (cr <= 256)
+        hipLaunchKernelGGL(k_tsqr_apply_chunk_reg, dim3(1, nckmax, A.nprob), dim3(256), 0, s, A, j0, cr, half, nb0,
+                           nb1);
+      else
+        hipLaunchKernelGGL(k_tsqr_apply_chunk, dim3(1, nckmax, A.nprob), dim3(256), 0, s, A, j0, cr, half, nb0, nb1);
+      hipLaunchKernelGGL(k_tsqr_apply_stack, dim3(1, A.nprob), dim3(256), 0, s, A, j0, cr, half, nb0, nb1);
     }
+    if (rest_pending) HIF_HIP(hipStreamWaitEvent(s, ev_rest, 0));
     hipLaunchKernelGGL(k_qr_clear_lower, dim3(64, A.nprob), dim3(256), 0, s, A);
     HIF_HIP(hipGetLastError());
+    HIF_HIP(hipEventDestroy(ev_fact));
+    HIF_HIP(hipEventDestroy(ev_rest));
+    HIF_HIP(hipStreamDestroy(s2));
     return;
   }
   // taller problems: one workgroup per problem for the panel
