@@ -115,6 +115,10 @@ struct SubLevel {
   // U_rs (r x k) | LU (r x r)], row-major.
   std::vector<GroupRec> hrec;
   DBuf<GroupRec> rec;
+  // Work offsets of the multi-workgroup solve: record i uses [nv][r] at
+  // nv * woff[i] in each of two work regions; sum_r = sum of r.
+  DBuf<int64_t> woff;
+  int64_t sum_r = 0;
   DBuf<int32_t> iarena;
   DBuf<double> darena;
 };

@@ -1074,6 +1074,16 @@ void Factorizer::sublevel(int lvl, int kind) {
   sub.nrec = int(sub.hrec.size());
   sub.rec.alloc(sub.nrec, mt);
   to_dev(sub.rec.p, sub.hrec, s);
+  {
+    std::vector<int64_t> hw(sub.nrec);
+    sub.sum_r = 0;
+    for (int i = 0; i < sub.nrec; ++i) {
+      hw[i] = sub.sum_r;
+      sub.sum_r += sub.hrec[i].r;
+    }
+    sub.woff.alloc(sub.nrec, mt);
+    to_dev(sub.woff.p, hw, s);
+  }
   sub.iarena.alloc(itot, mt);
   sub.darena.alloc(dtot, mt);
   grec.ensure(G, mt);

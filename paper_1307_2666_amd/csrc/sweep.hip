@@ -743,6 +743,315 @@ __global__ void k_copy(const double* x, double* y, int64_t n) {
     y[i] = x[i];
 }
 
+// ---------------------------------------------------------------------------
+// Solve (op 0) for sub-levels with few, large records: each record is spread
+// over many workgroups and all right-hand sides go through its factors in one
+// pass (the LDS kernel above holds 2r + k entries per right-hand side and so
+// rereads large factors once per right-hand side).  Per record, B holds the
+// right-hand sides of the triangular solve and X its solution, both [nv][r]
+// at nv * woff in the work buffer; a triangular solve is one launch per
+// 64-row block, every workgroup of which solves the diagonal block itself
+// (B rows of the block are only read in that launch) and then either writes
+// the block of X or updates its own 64 rows of B.
+// ---------------------------------------------------------------------------
+struct SpArgs {
+  const GroupRec* recs;
+  const int32_t* iarena;
+  const double* darena;
+  const int64_t* woff;
+  double* u;  // [nv][N]
+  double* B;
+  double* X;
+  int64_t N;
+  int nv;
+};
+
+struct SpRec {
+  int r, k;
+  const int32_t *rd, *sk, *perm;
+  const double *T, *Lsr, *Urs, *LU;
+  double *B, *X;
+};
+
+__device__ __forceinline__ SpRec sp_rec(const SpArgs& A, int i) {
+  const GroupRec R = A.recs[i];
+  SpRec v;
+  v.r = R.r;
+  v.k = R.k;
+  v.rd = A.iarena + R.idx;
+  v.sk = v.rd + R.r;
+  v.perm = v.sk + R.k + R.r;
+  v.T = A.darena + R.off;
+  v.Lsr = v.T + int64_t(R.k) * R.r;
+  v.Urs = v.Lsr + int64_t(R.k) * R.r;
+  v.LU = v.Urs + int64_t(R.r) * R.k;
+  v.B = A.B + A.nv * A.woff[i];
+  v.X = A.X + A.nv * A.woff[i];
+  return v;
+}
+
+constexpr int kSpChunk = 512;  // skeleton entries staged in LDS per pass
+
+// Up, first step: B(v, i) = (P (u_r - T^T u_s))(v, i), thread per i.
+__global__ __launch_bounds__(256) void k_sp_up_first(SpArgs A) {
+  const SpRec R = sp_rec(A, blockIdx.y);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x * 256 >= R.r) return;
+  const int nv = A.nv;
+  __shared__ double sus[kMaxV][kSpChunk];
+  const int c = i < R.r ? R.perm[i] : 0;
+  double acc[kMaxV];
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) acc[v] = (v < nv && i < R.r) ? A.u[v * A.N + R.rd[c]] : 0.0;
+  for (int j0 = 0; j0 < R.k; j0 += kSpChunk) {
+    const int nj = min(kSpChunk, R.k - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nv * nj; e += 256) sus[e / nj][e % nj] = A.u[(e / nj) * A.N + R.sk[j0 + e % nj]];
+    __syncthreads();
+    if (i < R.r) {
+      const double* tc = R.T + int64_t(j0) * R.r + c;
+      for (int j = 0; j < nj; j += kU) {
+        double t[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) t[u] = j + u < nj ? tc[int64_t(j + u) * R.r] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (j + u < nj)
+#pragma unroll
+            for (int v = 0; v < kMaxV; ++v)
+              if (v < nv) acc[v] -= t[u] * sus[v][j + u];
+      }
+    }
+  }
+  if (i < R.r)
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv) R.B[v * R.r + i] = acc[v];
+}
+
+// Down, first step: B(v, i) = (u_r - U_rs u_s)(v, i), one wave per row i.
+__global__ __launch_bounds__(256) void k_sp_down_first(SpArgs A) {
+  const SpRec R = sp_rec(A, blockIdx.y);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * 16;  // 16 rows per workgroup, 4 per wave
+  if (i0 >= R.r) return;
+  const int nv = A.nv;
+  __shared__ double sus[kMaxV][kSpChunk];
+  double acc[4][kMaxV];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v) acc[q][v] = 0.0;
+  for (int j0 = 0; j0 < R.k; j0 += kSpChunk) {
+    const int nj = min(kSpChunk, R.k - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nv * nj; e += 256) sus[e / nj][e % nj] = A.u[(e / nj) * A.N + R.sk[j0 + e % nj]];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + wv * 4 + q;
+      if (i >= R.r) break;
+      const double* mr = R.Urs + int64_t(i) * R.k + j0;
+      for (int j = lane; j < nj; j += 64) {
+        const double m = mr[j];
+#pragma unroll
+        for (int v = 0; v < kMaxV; ++v)
+          if (v < nv) acc[q][v] += m * sus[v][j];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = i0 + wv * 4 + q;
+    if (i >= R.r) break;
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv) {
+        const double t = wave_sum(acc[q][v]);
+        if (lane == 0) R.B[v * R.r + i] = A.u[v * A.N + R.rd[i]] - t;
+      }
+  }
+}
+
+// u_s -= M X (M = L_sr or T, k x r), one wave per skeleton row; X staged in
+// LDS by chunks of columns.
+__global__ __launch_bounds__(256) void k_sp_skel_update(SpArgs A, int which) {
+  const SpRec R = sp_rec(A, blockIdx.y);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j0 = blockIdx.x * 16;
+  if (j0 >= R.k) return;
+  const int nv = A.nv;
+  const double* M = which ? R.T : R.Lsr;
+  __shared__ double sx[kMaxV][kSpChunk];
+  double acc[4][kMaxV];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v) acc[q][v] = 0.0;
+  for (int c0 = 0; c0 < R.r; c0 += kSpChunk) {
+    const int nc = min(kSpChunk, R.r - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nv * nc; e += 256) sx[e / nc][e % nc] = R.X[(e / nc) * R.r + c0 + e % nc];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + wv * 4 + q;
+      if (j >= R.k) break;
+      const double* mr = M + int64_t(j) * R.r + c0;
+      for (int c = lane; c < nc; c += 64) {
+        const double m = mr[c];
+#pragma unroll
+        for (int v = 0; v < kMaxV; ++v)
+          if (v < nv) acc[q][v] += m * sx[v][c];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = j0 + wv * 4 + q;
+    if (j >= R.k) break;
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv) {
+        const double t = wave_sum(acc[q][v]);
+        if (lane == 0) A.u[v * A.N + R.sk[j]] -= t;
+      }
+  }
+}
+
+// u_r = X.
+__global__ __launch_bounds__(256) void k_sp_scatter(SpArgs A) {
+  const SpRec R = sp_rec(A, blockIdx.y);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= R.r) return;
+  for (int v = 0; v < A.nv; ++v) A.u[v * A.N + R.rd[i]] = R.X[v * R.r + i];
+}
+
+// Block b of x = L^{-1} x (unit lower L of the LU).  Workgroup 0 writes X of
+// the block; workgroup w >= 1 updates B rows 64(b + w) .. +63.
+__global__ __launch_bounds__(256) void k_sp_lsolve(SpArgs A, int b) {
+  const SpRec R = sp_rec(A, blockIdx.y);
+  const int j0 = b * kNbT;
+  if (j0 >= R.r) return;
+  const int w = blockIdx.x;
+  const int i0 = j0 + w * kNbT;
+  if (i0 >= R.r) return;
+  const int nb = min(kNbT, R.r - j0), nv = A.nv, r = R.r;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ double sL[kNbT][kNbT + 1];
+  __shared__ double sx[kMaxV][kNbT];
+  for (int e = tid; e < kNbT * kNbT; e += 256) {
+    const int a = e >> 6, c = e & 63;
+    sL[a][c] = (a < nb && c < nb) ? R.LU[int64_t(j0 + a) * r + j0 + c] : 0.0;
+  }
+  for (int e = tid; e < nv * kNbT; e += 256) {
+    const int v = e >> 6, a = e & 63;
+    sx[v][a] = a < nb ? R.B[v * r + j0 + a] : 0.0;
+  }
+  __syncthreads();
+  for (int v = wv; v < nv; v += 4) {  // wave per right-hand side, lane per row
+    double xi = sx[v][lane];
+    for (int c = 0; c < nb - 1; ++c) {
+      const double xc = __shfl(xi, c, 64);
+      if (lane > c) xi -= sL[lane][c] * xc;
+    }
+    sx[v][lane] = xi;
+  }
+  __syncthreads();
+  if (w == 0) {
+    for (int e = tid; e < nv * nb; e += 256) R.X[(e / nb) * r + j0 + e % nb] = sx[e / nb][e % nb];
+    return;
+  }
+  // rows i0 + tid / 4, four threads per row over 16 columns each
+  const int i = i0 + (tid >> 2), part = tid & 3;
+  double acc[kMaxV];
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+  if (i < r) {
+    const double* lr = R.LU + int64_t(i) * r + j0 + part * 16;
+    double l[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) l[c] = part * 16 + c < nb ? lr[c] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v)
+        if (v < nv) acc[v] += l[c] * sx[v][part * 16 + c];
+  }
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) {
+    acc[v] += __shfl_xor(acc[v], 1, 64);
+    acc[v] += __shfl_xor(acc[v], 2, 64);
+  }
+  if (i < r && part == 0)
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv) R.B[v * r + i] -= acc[v];
+}
+
+// Block b of x = U^{-1} x (upper U of the LU), blocks visited last to first.
+// Workgroup 0 writes X of the block; workgroup w >= 1 updates B rows
+// 64(w - 1) .. +63 above the block.
+__global__ __launch_bounds__(256) void k_sp_usolve(SpArgs A, int b) {
+  const SpRec R = sp_rec(A, blockIdx.y);
+  const int j0 = b * kNbT;
+  if (j0 >= R.r) return;
+  const int w = blockIdx.x;
+  const int i0 = (w - 1) * kNbT;
+  if (w > 0 && i0 >= j0) return;
+  const int nb = min(kNbT, R.r - j0), nv = A.nv, r = R.r;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ double sU[kNbT][kNbT + 1];
+  __shared__ double sx[kMaxV][kNbT];
+  for (int e = tid; e < kNbT * kNbT; e += 256) {
+    const int a = e >> 6, c = e & 63;
+    sU[a][c] = (a < nb && c < nb) ? R.LU[int64_t(j0 + a) * r + j0 + c] : (a == c ? 1.0 : 0.0);
+  }
+  for (int e = tid; e < nv * kNbT; e += 256) {
+    const int v = e >> 6, a = e & 63;
+    sx[v][a] = a < nb ? R.B[v * r + j0 + a] : 0.0;
+  }
+  __syncthreads();
+  for (int v = wv; v < nv; v += 4) {
+    double xi = sx[v][lane];
+    for (int c = nb - 1; c >= 0; --c) {
+      if (lane == c) xi /= sU[c][c];
+      const double xc = __shfl(xi, c, 64);
+      if (lane < c) xi -= sU[lane][c] * xc;
+    }
+    sx[v][lane] = xi;
+  }
+  __syncthreads();
+  if (w == 0) {
+    for (int e = tid; e < nv * nb; e += 256) R.X[(e / nb) * r + j0 + e % nb] = sx[e / nb][e % nb];
+    return;
+  }
+  const int i = i0 + (tid >> 2), part = tid & 3;
+  double acc[kMaxV];
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+  {
+    const double* ur = R.LU + int64_t(i) * r + j0 + part * 16;
+    double l[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) l[c] = part * 16 + c < nb ? ur[c] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v)
+        if (v < nv) acc[v] += l[c] * sx[v][part * 16 + c];
+  }
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) {
+    acc[v] += __shfl_xor(acc[v], 1, 64);
+    acc[v] += __shfl_xor(acc[v], 2, 64);
+  }
+  if (part == 0)
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv) R.B[v * r + i] -= acc[v];
+}
+
 }  // namespace
 
 void launch_make_perm(const GroupRec* recs, int nrec, int32_t* iarena, int max_r, hipStream_t s) {
@@ -770,9 +1079,32 @@ void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrh
     const int nv = int(std::min<int64_t>(8, nrhs - v0));
     double* u = y + v0 * N;
     double* wk = H->work.p + v0 * N;
-    // solve / solve_T of a sub-level go through LDS when a group fits
+    // solve / solve_T of a sub-level go through LDS when a group fits; solve
+    // of few large records is spread over many workgroups per record
     auto sweep = [&](const SubLevel& sub, int down) {
       SwArgs A{sub.rec.p, sub.iarena.p, sub.darena.p, u, wk, N, nv, op};
+      const bool split = op == 0 && 2 * sub.sum_r <= N &&
+                         (int64_t(sub.max_2rk) * nv > kCapL || (sub.nrec <= 16 && sub.max_r >= 256));
+      if (split) {
+        SpArgs P{sub.rec.p, sub.iarena.p, sub.darena.p, sub.woff.p, u, wk, wk + nv * sub.sum_r, N, nv};
+        const unsigned nr = unsigned(sub.nrec);
+        const int nbk = (sub.max_r + kNbT - 1) / kNbT;
+        const dim3 gr(unsigned((sub.max_r + 255) / 256), nr);
+        const dim3 gs(unsigned((sub.max_k + 15) / 16), nr);
+        if (!down) {
+          hipLaunchKernelGGL(k_sp_up_first, gr, dim3(256), 0, s, P);
+          for (int b = 0; b < nbk; ++b)
+            hipLaunchKernelGGL(k_sp_lsolve, dim3(unsigned(nbk - b), nr), dim3(256), 0, s, P, b);
+          if (sub.max_k > 0) hipLaunchKernelGGL(k_sp_skel_update, gs, dim3(256), 0, s, P, 0);
+        } else {
+          hipLaunchKernelGGL(k_sp_down_first, dim3(unsigned((sub.max_r + 15) / 16), nr), dim3(256), 0, s, P);
+          for (int b = nbk - 1; b >= 0; --b)
+            hipLaunchKernelGGL(k_sp_usolve, dim3(unsigned(b + 1), nr), dim3(256), 0, s, P, b);
+          if (sub.max_k > 0) hipLaunchKernelGGL(k_sp_skel_update, gs, dim3(256), 0, s, P, 1);
+        }
+        hipLaunchKernelGGL(k_sp_scatter, gr, dim3(256), 0, s, P);
+        return;
+      }
       if (op <= 1 && int64_t(sub.max_2rk) * nv <= kCapS)
         hipLaunchKernelGGL(k_sweep_lds<kCapS>, dim3(sub.nrec), dim3(kBlock), 0, s, A, down);
       else if (op <= 1 && sub.max_2rk <= kCapL)
