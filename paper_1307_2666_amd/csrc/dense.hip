@@ -263,6 +263,7 @@ __global__ __launch_bounds__(1024) void k_id(IdArgs A) {
   const int q = blockIdx.x;
   double* M = A.base + A.moff[q];
   const int ld = A.ld[q], m = A.rows[q], n = A.cols[q];
+  if (n <= A.skip_cols) return;
   const double tol = A.tol[q];
   int32_t* perm = A.perm + A.poff[q];
   const int tid = threadIdx.x, B = blockDim.x;
@@ -324,6 +325,7 @@ __global__ __launch_bounds__(1024) void k_id(IdArgs A) {
         s_beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
         s_p = p;
         perm[i] = p;
+        if (A.alpha) A.alpha[q * A.astride + i] = alpha;
       }
     __syncthreads();
     const double v0 = s_v0, beta = s_beta;
@@ -375,10 +377,11 @@ __global__ __launch_bounds__(1024) void k_id(IdArgs A) {
   if (tid == 0) s_k = k;
   __syncthreads();
   k = s_k;
-  // T = R11^{-1} R12, R11[a][b] = M[a][perm[b]]; written in place over R12.
+  // T = R11^{-1} R12, R11[a][b] = M[a][perm[b]]; written in place over R12
+  // (or left to the blocked triangular solve).
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    if (state[u] != -1) continue;
+    if (state[u] != -1 || A.alpha) continue;
     const int col = tid + u * B;
     for (int a = k - 1; a >= 0; --a) {
       double t = M[int64_t(a) * ld + col];
@@ -399,7 +402,7 @@ __global__ __launch_bounds__(1024) void k_id(IdArgs A) {
     if (u * B + B >= n) break;
   }
   if (tid == 0) A.rank[q] = k;
-  if (A.Tout) {
+  if (A.Tout && !A.alpha) {
     __syncthreads();
     const int r = n - k;
     double* T = A.Tout + A.toff[q];
@@ -975,8 +978,210 @@ bool id_blocked_fits(int nprob, int max_rows, int max_cols) {
   return nprob <= 512 && max_cols >= 128;
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident pivoted QR for many problems of at most 64 CB columns and
+// 16 RB rows (after row compression): one 1024-thread workgroup per problem,
+// thread (c, g) = (tid % 64, tid / 64) holds rows g + 16u (u < RB) of columns
+// c + 64j (j < CB) for the whole factorization; norms, the pivot column and
+// the column sums go through LDS.  Same pivots, norms (recomputed every step)
+// and rank rule as k_id; writes rows 0..k-1 (R) back, R_ii to alpha and the
+// permutation, and leaves T to k_idm_T_block.
+// ---------------------------------------------------------------------------
+template <int CB, int RB>
+__global__ __launch_bounds__(1024) void k_id_reg(IdArgs A, IdmState S) {
+  constexpr int NC = 64 * CB, NR = 16 * RB;
+  const int q = blockIdx.x;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q], m = A.rows[q], n = A.cols[q];
+  if (n > NC || min(m, n) > NR) return;  // left to k_id
+  const double tol = A.tol[q];
+  int32_t* perm = A.perm + A.poff[q];
+  const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
+  __shared__ double sred[16][NC];
+  __shared__ double snrm[NC], sw[NC], sv[NR];
+  __shared__ int sst[NC];
+  __shared__ int s_p;
+  double y[CB][RB];
+#pragma unroll
+  for (int j = 0; j < CB; ++j)
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int r = g + 16 * u, col = c + 64 * j;
+      y[j][u] = (r < m && col < n) ? M[int64_t(r) * ld + col] : 0.0;
+    }
+  // initial squared norms
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < RB; ++u) t += y[j][u] * y[j][u];
+    sred[g][c + 64 * j] = t;
+  }
+  __syncthreads();
+  for (int col = tid; col < NC; col += 1024) {
+    double t = 0.0;
+#pragma unroll
+    for (int g2 = 0; g2 < 16; ++g2) t += sred[g2][col];
+    snrm[col] = t;
+    sst[col] = col < n ? -1 : -2;
+  }
+  __syncthreads();
+  const int kmax = m < n ? m : n;
+  double r00 = 0.0;
+  int k = kmax;
+  for (int i = 0; i < kmax; ++i) {
+    // pivot: largest trailing norm, ties to the lowest column (wave 0)
+    if (g == 0) {
+      ArgMax loc{-1.0, INT_MAX};
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        const int col = c + 64 * j;
+        if (sst[col] == -1) loc = better(loc, ArgMax{snrm[col], col});
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        ArgMax y2{__shfl_xor(loc.v, o, 64), __shfl_xor(loc.i, o, 64)};
+        loc = better(loc, y2);
+      }
+      if (c == 0) s_p = loc.i;
+    }
+    __syncthreads();
+    const int p = s_p;
+    const double nv2 = p == INT_MAX ? 0.0 : snrm[p];
+    const double nb = sqrt(nv2 > 0.0 ? nv2 : 0.0);
+    if (i == 0) r00 = nb;
+    if (p == INT_MAX || !(nv2 > 0.0) || !(nb > tol * r00)) {
+      k = i;
+      break;
+    }
+    // the pivot column below the diagonal to LDS
+    if (c == (p & 63)) {
+#pragma unroll
+      for (int j = 0; j < CB; ++j)
+        if (j == (p >> 6))
+#pragma unroll
+          for (int u = 0; u < RB; ++u) sv[g + 16 * u] = y[j][u];
+    }
+    __syncthreads();
+    const double x0 = sv[i];
+    const double alpha = -copysign(nb, x0);
+    const double v0 = x0 - alpha;
+    const double vtv = nv2 - x0 * x0 + v0 * v0;
+    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    // column sums v^T y over rows >= i
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      double d = 0.0;
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int r = g + 16 * u;
+        if (r >= i) d += (r == i ? v0 : sv[r]) * y[j][u];
+      }
+      sred[g][c + 64 * j] = d;
+    }
+    __syncthreads();
+    for (int col = tid; col < NC; col += 1024) {
+      double t = 0.0;
+#pragma unroll
+      for (int g2 = 0; g2 < 16; ++g2) t += sred[g2][col];
+      sw[col] = beta * t;
+    }
+    __syncthreads();
+    // update of the trailing columns and their new norms (rows > i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const int col = c + 64 * j;
+      const bool upd = sst[col] == -1 && col != p;
+      const double w = sw[col];
+      double s2 = 0.0;
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int r = g + 16 * u;
+        if (upd && r >= i) {
+          y[j][u] -= w * (r == i ? v0 : sv[r]);
+          if (r > i) s2 += y[j][u] * y[j][u];
+        }
+      }
+      sred[g][col] = s2;
+    }
+    __syncthreads();
+    for (int col = tid; col < NC; col += 1024) {
+      if (sst[col] == -1 && col != p) {
+        double t = 0.0;
+#pragma unroll
+        for (int g2 = 0; g2 < 16; ++g2) t += sred[g2][col];
+        snrm[col] = t;
+      }
+    }
+    if (tid == 0) {
+      sst[p] = i;
+      perm[i] = p;
+      S.alpha[q * S.stride + i] = alpha;
+    }
+    __syncthreads();
+  }
+  // rows 0..k-1 back (R above the diagonal and R12), then the redundant
+  // columns in ascending order after the pivots
+#pragma unroll
+  for (int j = 0; j < CB; ++j)
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int r = g + 16 * u, col = c + 64 * j;
+      if (r < k && col < n) M[int64_t(r) * ld + col] = y[j][u];
+    }
+  if (tid == 0) A.rank[q] = k;
+  int base = 0;
+  for (int c0 = 0; c0 < NC; c0 += 1024) {
+    const int col = c0 + tid;
+    const int flag = (col < NC && sst[col] == -1) ? 1 : 0;
+    int tot = 0;
+    const int pre = block_excl_scan(flag, &tot);
+    if (flag) perm[k + base + pre] = col;
+    base += tot;
+  }
+}
+
+static void launch_id_small(const IdArgs& A, int max_cols, hipStream_t s);
+
+// Problems of at most 192 columns in registers, the others (up to max_cols)
+// by k_id without its triangular solve; T for all by row blocks.
+static void launch_id_reg(const IdArgs& A0, int max_cols, hipStream_t s) {
+  const int64_t stride = max_cols;
+  DBuf<double> alpha;
+  alpha.alloc(stride * A0.nprob, nullptr);
+  IdmState S{alpha.p, stride};
+  const unsigned np = unsigned(A0.nprob);
+  IdArgs A = A0;
+  A.alpha = alpha.p;
+  A.astride = stride;
+  A.skip_cols = 192;
+  hipLaunchKernelGGL((k_id_reg<3, 12>), dim3(np), dim3(1024), 0, s, A, S);
+  if (max_cols > 192) launch_id_small(A, max_cols, s);
+  std::vector<int32_t> hk(A.nprob);
+  HIF_HIP(hipMemcpyAsync(hk.data(), A.rank, sizeof(int32_t) * A.nprob, hipMemcpyDeviceToHost, s));
+  HIF_HIP(hipStreamSynchronize(s));
+  int kmax = 0;
+  for (int v : hk) kmax = std::max(kmax, v);
+  const dim3 tg(unsigned((max_cols + kTb64 - 1) / kTb64), np);
+  for (int a0 = ((kmax - 1) / kTb64) * kTb64; kmax > 0 && a0 >= 0; a0 -= kTb64)
+    hipLaunchKernelGGL(k_idm_T_block, tg, dim3(256), 0, s, A, S, a0);
+  if (A.Tout)
+    hipLaunchKernelGGL(k_idm_Tcopy, dim3(unsigned((max_cols + 255) / 256), np), dim3(256), 0, s, A);
+  HIF_HIP(hipGetLastError());
+  HIF_HIP(hipStreamSynchronize(s));  // alpha is released on return
+}
+
 void launch_id(const IdArgs& A, int max_cols, hipStream_t s) {
   if (A.nprob == 0) return;
+  // the pivoted QR runs on min(m, n) <= max_cols rows
+  if (max_cols > 128 && max_cols <= 256) {
+    launch_id_reg(A, max_cols, s);
+    return;
+  }
+  launch_id_small(A, max_cols, s);
+}
+
+static void launch_id_small(const IdArgs& A, int max_cols, hipStream_t s) {
   // the pivoted QR runs on min(m, n) <= max_cols rows, staged in LDS
   if (max_cols > kIdMaxRows) throw Error{HIF_EUNSUPPORTED, "ID problem with more than 4096 columns"};
   int block = 64;

@@ -49,6 +49,12 @@ struct IdArgs {
   double* Tout;          // optional compact copy of T (k x r row-major)
   const int64_t* toff;
   int nprob = 0;
+  // one-workgroup ID only: when alpha is set, R_ii goes to alpha[q * astride + i]
+  // and T is left to the blocked triangular solve; problems with at most
+  // skip_cols columns are left to another kernel
+  double* alpha = nullptr;
+  int64_t astride = 0;
+  int skip_cols = 0;
 };
 void launch_id(const IdArgs& A, int max_cols, hipStream_t s);
 // Blocked pivoted QR on the uncompressed problems (rows up to max_rows), same

@@ -153,6 +153,30 @@ def test_id_batched_large_matches_oracle():
         assert err <= np.sqrt(rd.size) * tol * r00 * 1.01 + 1e-14 * r00
 
 
+def test_id_batched_many_mid_size_matches_oracle():
+    # > 512 problems of 129..256 columns: up to 192 columns the whole pivoted QR
+    # runs in registers, larger ones on the one-workgroup kernel; T for both by
+    # the blocked triangular solve.  Column scales make the pivots unique.
+    rng = np.random.default_rng(13)
+    cases = []
+    for q in range(600):
+        n = int(rng.integers(129, 193)) if q % 6 else int(rng.integers(193, 251))
+        m = int(rng.integers(n // 2, 3 * n))
+        Y = rng.standard_normal((m, n)) * (1.06 ** -np.arange(n))[rng.permutation(n)]
+        cases.append((Y, 1e-6))
+    out = hif.id_batched([torch.tensor(Y) for Y, _ in cases], [t for _, t in cases])
+    for q, ((Y, tol), (sk, rd, T)) in enumerate(zip(cases, out)):
+        sk, rd, T = sk.numpy(), rd.numpy(), T.numpy()
+        osk, ord_, oT = interp_decomp(Y, tol)
+        assert np.array_equal(sk, osk), (q, Y.shape)
+        assert np.array_equal(rd, ord_)
+        if oT.size:
+            assert np.allclose(T, oT, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(oT).max())), q
+        r00 = np.max(np.linalg.norm(Y, axis=0))
+        err = np.linalg.norm(Y[:, rd] - Y[:, sk] @ T)
+        assert err <= np.sqrt(max(rd.size, 1)) * tol * r00 * 1.01 + 1e-14 * r00
+
+
 def test_id_batched_direct_matches_oracle():
     # nearly square blocks (sum m n <= 1.25 sum n^2): the blocked pivoted QR runs
     # on Y itself, without row compression; includes m < n, an exactly low-rank
