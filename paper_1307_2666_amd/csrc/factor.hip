@@ -392,6 +392,30 @@ struct ClsArgs {
   int32_t* cls_group;
 };
 
+// Exclusive scan of a 0/1 flag over the workgroup (wave64); sets *total.
+__device__ int cls_excl_scan(int flag, int* total) {
+  __shared__ int sw[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  const unsigned long long bal = __ballot(flag);
+  const int pre = __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+  if (lane == 0) sw[wv] = __popcll(bal);
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int k = 0; k < nw; ++k) {
+    if (k < wv) off += sw[k];
+    tot += sw[k];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + pre;
+}
+
+// Second-kind classes of group g (Section 4.4): columns with the same set of
+// SCI rows outside the group (hashed) form one class.  Classes are numbered
+// by their first column, columns keep their order within a class; one round
+// per class finds the first unassigned column, assigns every column with its
+// key and places them (work O(classes x n) per group).
 __global__ void k_class_prep(ClsArgs A) {
   const int g = blockIdx.x;
   const int64_t c0 = A.gstart[g];
@@ -413,40 +437,41 @@ __global__ void k_class_prep(ClsArgs A) {
     A.h1[c0 + p] = a;
     A.h2[c0 + p] = b;
     A.hc[c0 + p] = c;
+    A.rep[c0 + p] = -1;
   }
-  __syncthreads();
-  for (int p = threadIdx.x; p < n; p += blockDim.x) {
-    const uint64_t a = A.h1[c0 + p], b = A.h2[c0 + p];
-    const int c = A.hc[c0 + p];
-    int r = p;
-    for (int q = 0; q < p; ++q)
-      if (A.h1[c0 + q] == a && A.h2[c0 + q] == b && A.hc[c0 + q] == c) {
-        r = q;
-        break;
+  __shared__ int s_first;
+  int ncls = 0, placed = 0, from = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_first = INT_MAX;
+    __syncthreads();
+    for (int p = from + int(threadIdx.x); p < n; p += blockDim.x)
+      if (A.rep[c0 + p] < 0) atomicMin(&s_first, p);
+    __syncthreads();
+    const int p0 = s_first;
+    if (p0 == INT_MAX) break;
+    const uint64_t a = A.h1[c0 + p0], b = A.h2[c0 + p0];
+    const int cc = A.hc[c0 + p0];
+    // members in column order, placed after the classes found so far
+    for (int base = p0; base < n; base += blockDim.x) {
+      const int p = base + int(threadIdx.x);
+      const int flag = (p < n && A.rep[c0 + p] < 0 && A.h1[c0 + p] == a && A.h2[c0 + p] == b && A.hc[c0 + p] == cc)
+                           ? 1 : 0;
+      int tot = 0;
+      const int pre = cls_excl_scan(flag, &tot);
+      if (flag) {
+        const int np = placed + pre;
+        A.rep[c0 + p] = p0;
+        A.newpos[c0 + p] = np;
+        const int j = A.sdof[c0 + p];
+        A.cord[c0 + np] = j;
+        A.pos_of[j] = np;
       }
-    A.rep[c0 + p] = r;
-  }
-  __syncthreads();
-  int local = 0;
-  for (int p = threadIdx.x; p < n; p += blockDim.x) {
-    const int r = A.rep[c0 + p];
-    int np = 0;
-    for (int q = 0; q < n; ++q) {
-      const int rq = A.rep[c0 + q];
-      np += (rq < r) || (rq == r && q < p);
+      placed += tot;
     }
-    A.newpos[c0 + p] = np;
-    const int j = A.sdof[c0 + p];
-    A.cord[c0 + np] = j;
-    A.pos_of[j] = np;
-    local += (r == p);
+    ++ncls;
+    from = p0 + 1;
   }
-  __shared__ int s_n;
-  if (threadIdx.x == 0) s_n = 0;
-  __syncthreads();
-  atomicAdd(&s_n, local);
-  __syncthreads();
-  if (threadIdx.x == 0) A.ncls[g] = s_n;
+  if (threadIdx.x == 0) A.ncls[g] = ncls;
 }
 
 __global__ void k_class_fill(ClsArgs A) {
