@@ -2,8 +2,11 @@
 // lifecycle, error mapping.  No exception crosses the ABI.
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
+#include <set>
 
 #include "common.h"
 
@@ -23,10 +26,85 @@ hif_status fail(hif_status s, const std::string& msg) {
   return s;
 }
 
+void dbuf_pool_setup() {
+  static std::mutex mu;
+  static std::set<int> done;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count(dev)) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t keep = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+  (void)hipGetLastError();
+  done.insert(dev);
+}
+
+size_t dbuf_class(size_t bytes) {
+  if (bytes <= 256) return 256;
+  size_t p2 = 256;
+  while (p2 < bytes) p2 <<= 1;
+  if (p2 <= (size_t(1) << 20)) return p2;
+  const size_t step = p2 / 16;  // eighths between the powers of two p2 / 2 and p2
+  return (bytes + step - 1) / step * step;
+}
+
+namespace {
+struct CacheKey {
+  int dev;
+  hipStream_t s;
+  size_t cls;
+  bool operator<(const CacheKey& o) const {
+    if (dev != o.dev) return dev < o.dev;
+    if (s != o.s) return s < o.s;
+    return cls < o.cls;
+  }
+};
+// Process-wide and never destroyed (freeing at exit could run after the HIP
+// runtime is gone); the memory returns to the system with the process.
+struct DbufCache {
+  std::mutex mu;
+  std::multimap<CacheKey, void*> blocks;
+  size_t bytes = 0;
+};
+DbufCache& dbuf_cache() {
+  static DbufCache* c = new DbufCache;
+  return *c;
+}
+}  // namespace
+
+void* dbuf_take(size_t cls, hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  DbufCache& c = dbuf_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.blocks.find(CacheKey{dev, s, cls});
+  if (it == c.blocks.end()) return nullptr;
+  void* p = it->second;
+  c.blocks.erase(it);
+  c.bytes -= cls;
+  return p;
+}
+
+bool dbuf_give(void* p, size_t cls, hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  DbufCache& c = dbuf_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  if (c.bytes + cls > kDbufCacheBytes) return false;
+  c.blocks.emplace(CacheKey{dev, s, cls}, p);
+  c.bytes += cls;
+  return true;
+}
+
+// Runs f with DBuf memory ordered on stream s; errors become a status.
 template <class F>
-hif_status guarded(F&& f) {
+hif_status guarded(hipStream_t s, F&& f) {
   try {
     g_last_error.clear();
+    StreamScope scope(s);
     f();
     return HIF_OK;
   } catch (const Error& e) {
@@ -98,7 +176,7 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
   // tolerance rho * eps falls below single-precision resolution
   if (o.second_kind < 0) o.second_kind = o.precision == HIF_FP64 ? 1 : 0;
   hif_handle H = nullptr;
-  hif_status st = guarded([&] {
+  hif_status st = guarded(hipStream_t(stream), [&] {
     std::unique_ptr<hif_factor_s> h(new hif_factor_s());
     h->n = n;
     h->dim = dim;
@@ -119,7 +197,7 @@ static hif_status sweep(hif_handle h, int op, const double* x, double* y, int64_
   if (!h) return fail(HIF_EINVAL, "handle is NULL");
   if (!x || !y) return fail(HIF_EINVAL, "vector pointer is NULL");
   if (nrhs < 1) return fail(HIF_EINVAL, "nrhs must be >= 1");
-  return guarded([&] { sweep_impl(h, op, x, y, nrhs, hipStream_t(s)); });
+  return guarded(hipStream_t(s), [&] { sweep_impl(h, op, x, y, nrhs, hipStream_t(s)); });
 }
 
 hif_status hif_solve(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream s) {
@@ -143,7 +221,7 @@ hif_status hif_matvec(const double* points, int64_t n, int dim, const hif_kernel
   if (dim != 2 && dim != 3) return fail(HIF_EINVAL, "dim must be 2 or 3");
   if (nrhs < 1) return fail(HIF_EINVAL, "nrhs must be >= 1");
   if (hif_status st = check_kernel(k); st != HIF_OK) return st;
-  return guarded([&] {
+  return guarded(hipStream_t(s), [&] {
     const double wc = k->weights ? 0.0 : std::pow(k->h, dim);
     const double sc = k->self ? 0.0 : self_integral(k->h, dim);
     matvec_impl(points, n, dim, a, b, c, k->weights, wc, k->self, sc, x, y, nrhs, hipStream_t(s));
@@ -158,7 +236,7 @@ hif_status hif_gmres(hif_handle h, const double* f, double* u, int64_t nrhs, dou
   if (nrhs < 1 || nrhs > 64) return fail(HIF_EINVAL, "nrhs must be in [1, 64]");
   if (!(tol > 0.0 && tol < 1.0)) return fail(HIF_EINVAL, "tol must satisfy 0 < tol < 1");
   if (maxit < 1 || maxit > 200) return fail(HIF_EINVAL, "maxit must be in [1, 200]");
-  return guarded([&] { gmres_impl(h, f, u, nrhs, tol, maxit, iters, relres, hipStream_t(s)); });
+  return guarded(hipStream_t(s), [&] { gmres_impl(h, f, u, nrhs, tol, maxit, iters, relres, hipStream_t(s)); });
 }
 
 hif_status hif_stats(hif_handle h, hif_stats_t* out) {
@@ -169,7 +247,8 @@ hif_status hif_stats(hif_handle h, hif_stats_t* out) {
 
 void hif_free(hif_handle h) {
   if (!h) return;
-  (void)hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();  // the handle may have been used on any stream
+  StreamScope scope(nullptr);
   delete h;
 }
 
@@ -182,7 +261,7 @@ hif_status hif_id_batched(double* mats, const int64_t* off, const int32_t* rows,
     return fail(HIF_EINVAL, "NULL pointer argument");
   if ((T == nullptr) != (off_t == nullptr)) return fail(HIF_EINVAL, "T and off_t must both be given or both NULL");
   if (max_cols < 1 || max_cols > 4096) return fail(HIF_EINVAL, "max_cols must be in [1, 4096]");
-  return guarded([&] {
+  return guarded(hipStream_t(s), [&] {
     id_batched_impl(mats, off, rows, cols, tol, batch, max_cols, rank, perm, off_perm, T, off_t, hipStream_t(s));
   });
 }
@@ -194,7 +273,7 @@ hif_status hif_partition(const double* points, int64_t n, int dim, const uint8_t
   if (dim != 2 && dim != 3) return fail(HIF_EINVAL, "dim must be 2 or 3");
   if (kind < 0 || kind > 2 || (kind == 1 && dim != 3)) return fail(HIF_EINVAL, "kind must be 0 (cell), 1 (face, 3D) or 2 (edge)");
   if (S < 1 || S > (1 << 20)) return fail(HIF_EINVAL, "S must be in [1, 2^20]");
-  return guarded([&] { partition_impl(points, n, dim, active, kind, S, group, hipStream_t(s)); });
+  return guarded(hipStream_t(s), [&] { partition_impl(points, n, dim, active, kind, S, group, hipStream_t(s)); });
 }
 
 }  // extern "C"

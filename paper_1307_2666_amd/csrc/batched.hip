@@ -7,6 +7,7 @@
 // updates run on the matrix cores (v_mfma_f64_16x16x4f64) with operands read
 // straight from device memory in the instruction's lane layout.
 #include <algorithm>
+#include <map>
 #include <climits>
 #include <vector>
 
@@ -1131,6 +1132,21 @@ __global__ __launch_bounds__(256) void k_gemm_tiles(const GemmDesc* D, int nd) {
 
 }  // namespace
 
+// Second stream of the row compression's look-ahead, one per host thread and
+// device, created on first use and kept for the life of the thread (creating
+// and destroying it per call costs a host wait on its work each time).
+static hipStream_t aux_stream() {
+  thread_local std::map<int, hipStream_t> streams;
+  int dev = 0;
+  HIF_HIP(hipGetDevice(&dev));
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t s2;
+  HIF_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+  streams[dev] = s2;
+  return s2;
+}
+
 void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t s) {
   if (A.nprob == 0) return;
   // chunks of 256 rows (one per thread), or of 1024 rows (two per thread)
@@ -1153,9 +1169,8 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
     // own updates of panel p), and the remaining-columns update of p
     // follows the factorization of p (it waits for an event recorded after
     // the stack kernel).
-    hipStream_t s2;
+    hipStream_t s2 = aux_stream();
     hipEvent_t ev_fact, ev_rest;
-    HIF_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
     HIF_HIP(hipEventCreateWithFlags(&ev_fact, hipEventDisableTiming));
     HIF_HIP(hipEventCreateWithFlags(&ev_rest, hipEventDisableTiming));
     bool rest_pending = false;
@@ -1202,7 +1217,6 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
     HIF_HIP(hipGetLastError());
     HIF_HIP(hipEventDestroy(ev_fact));
     HIF_HIP(hipEventDestroy(ev_rest));
-    HIF_HIP(hipStreamDestroy(s2));
     return;
   }
   // taller problems: one workgroup per problem for the panel

@@ -46,23 +46,55 @@ struct MemTracker {
   size_t cap = 0;  // 0 = no cap
 };
 
+// DBuf memory comes from the device's stream-ordered pool: allocations and
+// frees are ordered on the stream of the ABI call that makes them (set per
+// thread by StreamScope), so a block freed on a stream is reused only after
+// the work queued before the free, and freeing does not synchronize the
+// device.  The pool keeps freed memory for later calls.
+inline hipStream_t& dbuf_stream() {
+  static thread_local hipStream_t s = nullptr;
+  return s;
+}
+void dbuf_pool_setup();  // once per device: keep freed memory in the pool
+// Host-side cache in front of the pool: a block freed on a stream is kept
+// (per device and stream, by size class) and handed to the next
+// allocation of that class on the same stream, which the stream orders after
+// the block's last use; it saves the allocator's per-call host cost between
+// the host's waits on the device.  At most kDbufCacheBytes stay cached (per
+// process); beyond that blocks go back to the pool.
+constexpr size_t kDbufCacheBytes = size_t(8) << 30;
+size_t dbuf_class(size_t bytes);                  // allocation size for a request
+void* dbuf_take(size_t cls, hipStream_t s);       // cached block or nullptr
+bool dbuf_give(void* p, size_t cls, hipStream_t s);  // true if cached
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : prev(dbuf_stream()) {
+    dbuf_pool_setup();
+    dbuf_stream() = s;
+  }
+  ~StreamScope() { dbuf_stream() = prev; }
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
+};
+
 template <class T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;        // elements allocated
+  size_t cls = 0;      // bytes of the underlying block
   MemTracker* mt = nullptr;
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), mt(o.mt) { o.p = nullptr; o.n = 0; }
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), cls(o.cls), mt(o.mt) { o.p = nullptr; o.n = 0; }
   DBuf& operator=(DBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; mt = o.mt; o.p = nullptr; o.n = 0; }
+    if (this != &o) { release(); p = o.p; n = o.n; cls = o.cls; mt = o.mt; o.p = nullptr; o.n = 0; }
     return *this;
   }
   ~DBuf() { release(); }
   void release() {
     if (p) {
-      (void)hipFree(p);
+      if (!dbuf_give(p, cls, dbuf_stream())) (void)hipFreeAsync(p, dbuf_stream());
       if (mt) mt->held -= n * sizeof(T);
     }
     p = nullptr;
@@ -76,12 +108,17 @@ struct DBuf {
     size_t bytes = cnt * sizeof(T);
     if (mt && mt->cap && mt->held + bytes > mt->cap)
       throw Error{HIF_ENOMEM, "device memory cap (opts.max_bytes) exceeded"};
-    hipError_t e = hipMalloc((void**)&p, bytes);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      throw Error{HIF_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    const size_t c = dbuf_class(bytes);
+    p = static_cast<T*>(dbuf_take(c, dbuf_stream()));
+    if (!p) {
+      hipError_t e = hipMallocAsync((void**)&p, c, dbuf_stream());
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        throw Error{HIF_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+      }
     }
+    cls = c;
     n = cnt;
     if (mt) { mt->held += bytes; if (mt->held > mt->peak) mt->peak = mt->held; }
   }
