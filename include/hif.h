@@ -136,13 +136,15 @@ typedef struct {
   double sub_id_flops[HIF_MAX_SUBLEVELS];  /* algorithmic flops of the IDs */
   double sub_elim_flops[HIF_MAX_SUBLEVELS];/* algorithmic flops of the eliminations */
   double sub_t_ms[HIF_MAX_SUBLEVELS][8];   /* per sub-level split of t_phase_ms */
-  double sub_id_bytes[HIF_MAX_SUBLEVELS];  /* pivoted-QR traffic, summed over classes: after row
-                                              compression every step i < k reads and writes the
-                                              trailing block of R0, 16 (m' - i)(n - i) with
-                                              m' = min(m, n); on Y directly every step reads it,
-                                              8 (m - i)(n - i), and every full block of 32
-                                              reflectors ending at step e < k reads and writes
-                                              the rows below it, 16 (m - e)(n - e) */
+  double sub_id_bytes[HIF_MAX_SUBLEVELS];  /* pivoted-QR traffic, summed over classes, m' rows
+                                              (m' = min(m, n) after row compression, m on Y):
+                                              blocked kernel: every step i < k reads the trailing
+                                              block, 8 (m' - i)(n - i), and every full block of 32
+                                              reflectors ending at step e < k reads and writes the
+                                              rows below it, 16 (m' - e)(n - e); block held in
+                                              registers: 8 (m' + k) n; one-workgroup streaming
+                                              kernel: every step reads and writes the trailing
+                                              block, 16 (m' - i)(n - i) */
   double sub_rowqr_flops[HIF_MAX_SUBLEVELS]; /* row compression: 2 m n^2 - 2 n^3 / 3 per class with m > n */
 } hif_stats_t;
 

@@ -993,7 +993,7 @@ __global__ __launch_bounds__(1024) void k_id_reg(IdArgs A, IdmState S) {
   const int q = blockIdx.x;
   double* M = A.base + A.moff[q];
   const int ld = A.ld[q], m = A.rows[q], n = A.cols[q];
-  if (n > NC || min(m, n) > NR) return;  // left to k_id
+  if (n > NC || min(m, n) > NR) return;  // left to k_id (id_in_registers says the same)
   const double tol = A.tol[q];
   int32_t* perm = A.perm + A.poff[q];
   const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;

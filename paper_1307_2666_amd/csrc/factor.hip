@@ -1059,11 +1059,14 @@ void Factorizer::sublevel(int lvl, int kind) {
         for (int e = 32; e <= h_rank[q] && e < std::min<int64_t>(m, h_cls_n[q]); e += 32)
           idby += 16.0 * (double(m) - e) * (nq - e);
       } else {
-        // blocked on R0 (rows m' = min(m, n)) as on Y; unblocked: each step
-        // reads and writes the trailing block of R0
+        // blocked on R0 (rows m' = min(m, n)) as on Y; in registers (k_id_reg):
+        // R0 read once and rows 0..k-1 written once; otherwise every step reads
+        // and writes the trailing block of R0
         if (blocked_r0) {
           idby += 8.0 * sab;
           for (int e = 32; e <= h_rank[q] && e < a2; e += 32) idby += 16.0 * (a2 - e) * (nq - e);
+        } else if (id_in_registers(maxq, int(a2), h_cls_n[q])) {
+          idby += 8.0 * (a2 + kq) * nq;
         } else {
           idby += 16.0 * sab;
         }

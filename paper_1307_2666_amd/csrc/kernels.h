@@ -61,6 +61,11 @@ void launch_id(const IdArgs& A, int max_cols, hipStream_t s);
 // outputs as launch_id; id_blocked_fits says whether a batch suits it.
 void launch_id_blocked(const IdArgs& A, int max_rows, int max_cols, hipStream_t s);
 bool id_blocked_fits(int nprob, int max_rows, int max_cols);
+// Whether launch_id runs a problem of rows x cols (after row compression) in
+// registers, in a batch whose widest problem has max_cols columns.
+inline bool id_in_registers(int max_cols, int rows, int cols) {
+  return max_cols > 128 && max_cols <= 256 && cols <= 192 && rows <= 192;
+}
 
 // Row compression Y = Q R0 (blocked Householder, no pivoting) before the ID;
 // R0 overwrites the leading n x n block of each problem with m > n.
