@@ -28,11 +28,12 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_VECTOR_TFLOPS = 78.6  # MI355X: 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per factorization moved by the pivoted-QR kernels (k_bq_init,
-# k_bq_piv, k_bq_cols, k_bq_update, k_id) on this workload, from rocprofv3
-# FETCH_SIZE + WRITE_SIZE runs of `bench.py --steps 1 --warmup 0
+# k_bq_piv, k_bq_cols, k_bq_update, k_id_reg, k_id) on this workload, from
+# rocprofv3 FETCH_SIZE + WRITE_SIZE runs of `bench.py --steps 1 --warmup 0
 # --no-cpu-baseline --no-refine --calib-copy`, each scaled by what the counter
-# reads for a 256 MiB copy kernel.  None until measured for the current kernels.
-ID_STEP_TRAFFIC_BYTES = None
+# reads for a 256 MiB copy kernel (160.3 GB read + 9.4 GB written).  Valid for
+# these kernels as they stand; set to None when they change.
+ID_STEP_TRAFFIC_BYTES = 1.697e+11
 
 
 def parse():
@@ -205,8 +206,8 @@ def main():
         "sub_ms": [{k: round(v, 3) for k, v in d.items() if v > 0} for d in st["sub_t_ms"]],
         "top_size": st["top_size"],
         "factor_bytes": st["factor_bytes"],
-        "roofline": {"kernel": "k_bq_piv + k_bq_cols + k_bq_update + k_id (column-pivoted QR of the IDs, "
-                               "all launches of a step)",
+        "roofline": {"kernel": "k_bq_piv + k_bq_cols + k_bq_update + k_id_reg + k_id (column-pivoted QR of "
+                               "the IDs, all launches of a step)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (ID_STEP_TRAFFIC_BYTES if ID_STEP_TRAFFIC_BYTES and wl.name == "sq512"
