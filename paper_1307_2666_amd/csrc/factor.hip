@@ -411,22 +411,18 @@ __device__ int cls_excl_scan(int flag, int* total) {
   return off + pre;
 }
 
-// Second-kind classes of group g (Section 4.4): columns with the same set of
-// SCI rows outside the group (hashed) form one class.  Classes are numbered
-// by their first column, columns keep their order within a class; one round
-// per class finds the first unassigned column, assigns every column with its
-// key and places them (work O(classes x n) per group).
-__global__ void k_class_prep(ClsArgs A) {
-  const int g = blockIdx.x;
-  const int64_t c0 = A.gstart[g];
-  const int n = int(A.gstart[g + 1] - c0);
-  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+// Key of every column (thread per column of all groups): a hash of the set of
+// its SCI rows outside its own group (Section 4.4 splits a group's columns by
+// that sparsity pattern).
+__global__ void k_class_hash(ClsArgs A, int64_t ncol) {
+  GRID_STRIDE(e, ncol) {
     uint64_t a = 0, b = 0;
     int c = 0;
     if (A.split) {
-      const int j = A.sdof[c0 + p];
-      for (int64_t e = A.srow[j]; e < A.srow[j + 1]; ++e) {
-        const int i = int(A.skey[e] & 0xffffffffu);
+      const int j = A.sdof[e];
+      const int g = A.grp_of[j];
+      for (int64_t t = A.srow[j]; t < A.srow[j + 1]; ++t) {
+        const int i = int(A.skey[t] & 0xffffffffu);
         if (A.grp_of[i] != g) {
           a += mix64(uint64_t(i));
           b ^= mix64(uint64_t(i) * 0x2545f4914f6cdd1dull + 17);
@@ -434,11 +430,22 @@ __global__ void k_class_prep(ClsArgs A) {
         }
       }
     }
-    A.h1[c0 + p] = a;
-    A.h2[c0 + p] = b;
-    A.hc[c0 + p] = c;
-    A.rep[c0 + p] = -1;
+    A.h1[e] = a;
+    A.h2[e] = b;
+    A.hc[e] = c;
+    A.rep[e] = -1;
   }
+}
+
+// Second-kind classes of group g (Section 4.4): columns with the same key
+// form one class.  Classes are numbered by their first column, columns keep
+// their order within a class; one round per class finds the first unassigned
+// column, assigns every column with its key and places them (work
+// O(classes x n) per group).
+__global__ void k_class_prep(ClsArgs A) {
+  const int g = blockIdx.x;
+  const int64_t c0 = A.gstart[g];
+  const int n = int(A.gstart[g + 1] - c0);
   __shared__ int s_first;
   int ncls = 0, placed = 0, from = 0;
   for (;;) {
@@ -856,6 +863,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   ca.pos_of = pos_of.p;
   ca.ncls = ncls.p;
   ca.split = split;
+  hipLaunchKernelGGL(k_class_hash, dim3(nblocks(nact)), dim3(kThreads), 0, s, ca, int64_t(nact));
   hipLaunchKernelGGL(k_class_prep, dim3(G), dim3(kThreads), 0, s, ca);
   HIF_HIP(hipGetLastError());
   tm.mark(PH_PART);
