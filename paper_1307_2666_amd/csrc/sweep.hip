@@ -1084,7 +1084,7 @@ void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrh
     auto sweep = [&](const SubLevel& sub, int down) {
       SwArgs A{sub.rec.p, sub.iarena.p, sub.darena.p, u, wk, N, nv, op};
       const bool split = op == 0 && 2 * sub.sum_r <= N &&
-                         (int64_t(sub.max_2rk) * nv > kCapL || (sub.nrec <= 16 && sub.max_r >= 256));
+                         (int64_t(sub.max_2rk) * nv > kCapL || (sub.nrec <= 64 && sub.max_r >= 256));
       if (split) {
         SpArgs P{sub.rec.p, sub.iarena.p, sub.darena.p, sub.woff.p, u, wk, wk + nv * sub.sum_r, N, nv};
         const unsigned nr = unsigned(sub.nrec);
