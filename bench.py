@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # --no-cpu-baseline --no-refine --calib-copy`, each scaled by what the counter
 # reads for a 256 MiB copy kernel (160.3 GB read + 9.4 GB written).  Valid for
 # these kernels as they stand; set to None when they change.
-ID_STEP_TRAFFIC_BYTES = 1.697e+11
+ID_STEP_TRAFFIC_BYTES = None
 
 
 def parse():

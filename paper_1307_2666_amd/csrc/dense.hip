@@ -980,16 +980,16 @@ bool id_blocked_fits(int nprob, int max_rows, int max_cols) {
 
 // ---------------------------------------------------------------------------
 // Register-resident pivoted QR for many problems of at most 64 CB columns and
-// 16 RB rows (after row compression): one 1024-thread workgroup per problem,
-// thread (c, g) = (tid % 64, tid / 64) holds rows g + 16u (u < RB) of columns
+// NW RB rows (after row compression): one workgroup of NW waves per problem,
+// thread (c, g) = (tid % 64, tid / 64) holds rows g + NW u (u < RB) of columns
 // c + 64j (j < CB) for the whole factorization; norms, the pivot column and
 // the column sums go through LDS.  Same pivots, norms (recomputed every step)
 // and rank rule as k_id; writes rows 0..k-1 (R) back, R_ii to alpha and the
 // permutation, and leaves T to k_idm_T_block.
 // ---------------------------------------------------------------------------
-template <int CB, int RB>
-__global__ __launch_bounds__(1024) void k_id_reg(IdArgs A, IdmState S) {
-  constexpr int NC = 64 * CB, NR = 16 * RB;
+template <int CB, int RB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_id_reg(IdArgs A, IdmState S) {
+  constexpr int NC = 64 * CB, NR = NW * RB, NT = 64 * NW;
   const int q = blockIdx.x;
   double* M = A.base + A.moff[q];
   const int ld = A.ld[q], m = A.rows[q], n = A.cols[q];
@@ -997,7 +997,7 @@ __global__ __launch_bounds__(1024) void k_id_reg(IdArgs A, IdmState S) {
   const double tol = A.tol[q];
   int32_t* perm = A.perm + A.poff[q];
   const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
-  __shared__ double sred[16][NC];
+  __shared__ double sred[NW][NC];
   __shared__ double snrm[NC], sw[NC], sv[NR];
   __shared__ int sst[NC];
   __shared__ int s_p;
@@ -1006,7 +1006,7 @@ __global__ __launch_bounds__(1024) void k_id_reg(IdArgs A, IdmState S) {
   for (int j = 0; j < CB; ++j)
 #pragma unroll
     for (int u = 0; u < RB; ++u) {
-      const int r = g + 16 * u, col = c + 64 * j;
+      const int r = g + NW * u, col = c + 64 * j;
       y[j][u] = (r < m && col < n) ? M[int64_t(r) * ld + col] : 0.0;
     }
   // initial squared norms
@@ -1018,10 +1018,10 @@ __global__ __launch_bounds__(1024) void k_id_reg(IdArgs A, IdmState S) {
     sred[g][c + 64 * j] = t;
   }
   __syncthreads();
-  for (int col = tid; col < NC; col += 1024) {
+  for (int col = tid; col < NC; col += NT) {
     double t = 0.0;
 #pragma unroll
-    for (int g2 = 0; g2 < 16; ++g2) t += sred[g2][col];
+    for (int g2 = 0; g2 < NW; ++g2) t += sred[g2][col];
     snrm[col] = t;
     sst[col] = col < n ? -1 : -2;
   }
@@ -1060,7 +1060,7 @@ __global__ __launch_bounds__(1024) void k_id_reg(IdArgs A, IdmState S) {
       for (int j = 0; j < CB; ++j)
         if (j == (p >> 6))
 #pragma unroll
-          for (int u = 0; u < RB; ++u) sv[g + 16 * u] = y[j][u];
+          for (int u = 0; u < RB; ++u) sv[g + NW * u] = y[j][u];
     }
     __syncthreads();
     const double x0 = sv[i];
@@ -1074,16 +1074,16 @@ __global__ __launch_bounds__(1024) void k_id_reg(IdArgs A, IdmState S) {
       double d = 0.0;
 #pragma unroll
       for (int u = 0; u < RB; ++u) {
-        const int r = g + 16 * u;
+        const int r = g + NW * u;
         if (r >= i) d += (r == i ? v0 : sv[r]) * y[j][u];
       }
       sred[g][c + 64 * j] = d;
     }
     __syncthreads();
-    for (int col = tid; col < NC; col += 1024) {
+    for (int col = tid; col < NC; col += NT) {
       double t = 0.0;
 #pragma unroll
-      for (int g2 = 0; g2 < 16; ++g2) t += sred[g2][col];
+      for (int g2 = 0; g2 < NW; ++g2) t += sred[g2][col];
       sw[col] = beta * t;
     }
     __syncthreads();
@@ -1096,7 +1096,7 @@ __global__ __launch_bounds__(1024) void k_id_reg(IdArgs A, IdmState S) {
       double s2 = 0.0;
 #pragma unroll
       for (int u = 0; u < RB; ++u) {
-        const int r = g + 16 * u;
+        const int r = g + NW * u;
         if (upd && r >= i) {
           y[j][u] -= w * (r == i ? v0 : sv[r]);
           if (r > i) s2 += y[j][u] * y[j][u];
@@ -1105,11 +1105,11 @@ __global__ __launch_bounds__(1024) void k_id_reg(IdArgs A, IdmState S) {
       sred[g][col] = s2;
     }
     __syncthreads();
-    for (int col = tid; col < NC; col += 1024) {
+    for (int col = tid; col < NC; col += NT) {
       if (sst[col] == -1 && col != p) {
         double t = 0.0;
 #pragma unroll
-        for (int g2 = 0; g2 < 16; ++g2) t += sred[g2][col];
+        for (int g2 = 0; g2 < NW; ++g2) t += sred[g2][col];
         snrm[col] = t;
       }
     }
@@ -1126,12 +1126,12 @@ __global__ __launch_bounds__(1024) void k_id_reg(IdArgs A, IdmState S) {
   for (int j = 0; j < CB; ++j)
 #pragma unroll
     for (int u = 0; u < RB; ++u) {
-      const int r = g + 16 * u, col = c + 64 * j;
+      const int r = g + NW * u, col = c + 64 * j;
       if (r < k && col < n) M[int64_t(r) * ld + col] = y[j][u];
     }
   if (tid == 0) A.rank[q] = k;
   int base = 0;
-  for (int c0 = 0; c0 < NC; c0 += 1024) {
+  for (int c0 = 0; c0 < NC; c0 += NT) {
     const int col = c0 + tid;
     const int flag = (col < NC && sst[col] == -1) ? 1 : 0;
     int tot = 0;
@@ -1143,8 +1143,9 @@ __global__ __launch_bounds__(1024) void k_id_reg(IdArgs A, IdmState S) {
 
 static void launch_id_small(const IdArgs& A, int max_cols, hipStream_t s);
 
-// Problems of at most 192 columns in registers, the others (up to max_cols)
-// by k_id without its triangular solve; T for all by row blocks.
+// Problems in registers (all of them up to 128 columns; up to 192 columns in
+// batches of up to 256), the others by k_id without its triangular solve; T
+// for all by row blocks.
 static void launch_id_reg(const IdArgs& A0, int max_cols, hipStream_t s) {
   const int64_t stride = max_cols;
   DBuf<double> alpha;
@@ -1155,8 +1156,14 @@ static void launch_id_reg(const IdArgs& A0, int max_cols, hipStream_t s) {
   A.alpha = alpha.p;
   A.astride = stride;
   A.skip_cols = 192;
-  hipLaunchKernelGGL((k_id_reg<3, 12>), dim3(np), dim3(1024), 0, s, A, S);
-  if (max_cols > 192) launch_id_small(A, max_cols, s);
+  if (max_cols <= 64) {
+    hipLaunchKernelGGL((k_id_reg<1, 16, 4>), dim3(np), dim3(256), 0, s, A, S);
+  } else if (max_cols <= 128) {
+    hipLaunchKernelGGL((k_id_reg<2, 16, 8>), dim3(np), dim3(512), 0, s, A, S);
+  } else {
+    hipLaunchKernelGGL((k_id_reg<3, 12, 16>), dim3(np), dim3(1024), 0, s, A, S);
+    if (max_cols > 192) launch_id_small(A, max_cols, s);
+  }
   std::vector<int32_t> hk(A.nprob);
   HIF_HIP(hipMemcpyAsync(hk.data(), A.rank, sizeof(int32_t) * A.nprob, hipMemcpyDeviceToHost, s));
   HIF_HIP(hipStreamSynchronize(s));
@@ -1174,7 +1181,7 @@ static void launch_id_reg(const IdArgs& A0, int max_cols, hipStream_t s) {
 void launch_id(const IdArgs& A, int max_cols, hipStream_t s) {
   if (A.nprob == 0) return;
   // the pivoted QR runs on min(m, n) <= max_cols rows
-  if (max_cols > 128 && max_cols <= 256) {
+  if (max_cols > 48 && max_cols <= 256) {  // tiny problems: one wave each in k_id
     launch_id_reg(A, max_cols, s);
     return;
   }

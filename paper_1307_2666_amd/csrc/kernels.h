@@ -64,7 +64,9 @@ bool id_blocked_fits(int nprob, int max_rows, int max_cols);
 // Whether launch_id runs a problem of rows x cols (after row compression) in
 // registers, in a batch whose widest problem has max_cols columns.
 inline bool id_in_registers(int max_cols, int rows, int cols) {
-  return max_cols > 128 && max_cols <= 256 && cols <= 192 && rows <= 192;
+  if (max_cols <= 48) return false;
+  if (max_cols <= 128) return true;
+  return max_cols <= 256 && cols <= 192 && rows <= 192;
 }
 
 // Row compression Y = Q R0 (blocked Householder, no pivoting) before the ID;
