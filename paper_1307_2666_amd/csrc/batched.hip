@@ -903,9 +903,9 @@ __global__ __launch_bounds__(256) void k_lu_panel(LuBatch A, int j0) {
 // columns for all kNb elimination steps; the pivot row is exchanged and
 // broadcast through LDS.  The row interchanges are then applied in order to
 // the columns outside the panel (one thread per column) and U12 is formed.
-constexpr int kLpThreads = 1024;
-constexpr int kLpRows = 2 * kLpThreads;
+constexpr int kLpRows = 2048;  // rows of the largest register panel (1024 threads)
 
+template <int kLpThreads>
 __global__ __launch_bounds__(kLpThreads) void k_lu_panel_reg(LuBatch A, int j0) {
   const int q = blockIdx.x;
   const int n = A.n[q], r = A.r[q];
@@ -1235,8 +1235,12 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
 void launch_lu_batched(const LuBatch& A, int max_r, int max_n, hipStream_t s) {
   if (A.nprob == 0) return;
   for (int j0 = 0; j0 < max_r; j0 += kNb) {
-    if (max_n - j0 <= kLpRows)
-      hipLaunchKernelGGL(k_lu_panel_reg, dim3(A.nprob), dim3(kLpThreads), 0, s, A, j0);
+    if (max_n - j0 <= kLpRows / 4)  // two rows per thread
+      hipLaunchKernelGGL(k_lu_panel_reg<256>, dim3(A.nprob), dim3(256), 0, s, A, j0);
+    else if (max_n - j0 <= kLpRows / 2)
+      hipLaunchKernelGGL(k_lu_panel_reg<512>, dim3(A.nprob), dim3(512), 0, s, A, j0);
+    else if (max_n - j0 <= kLpRows)
+      hipLaunchKernelGGL(k_lu_panel_reg<1024>, dim3(A.nprob), dim3(1024), 0, s, A, j0);
     else
       hipLaunchKernelGGL(k_lu_panel, dim3(A.nprob), dim3(256), 0, s, A, j0);
     const int rem = max_n - j0 - 1;
