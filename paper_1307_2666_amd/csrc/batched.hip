@@ -409,9 +409,13 @@ __device__ __forceinline__ double wave_rs32(double (&p)[kTb]) {
 // LDS: sred [2][NW][kTb], srow [2][kTb], scf [2][kTb + 2].
 template <int NW, int RPT>
 __device__ void rowblock_qr(double (&y)[RPT][kTb], int jb, double* sred, double* srow, double* scf, double* sv0,
-                            double* sbeta) {
+                            double* sbeta, double* sG) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t0 = threadIdx.x, B = blockDim.x;
+  if (t0 >= jb && t0 < kTb) {  // columns past a partial panel: no reflector
+    sv0[t0] = 0.0;
+    sbeta[t0] = 0.0;
+  }
   for (int jj = 0; jj < jb; ++jj) {
     const int b = jj & 1;  // double-buffered: one barrier pair per column
     double* red = sred + b * NW * kTb;
@@ -456,6 +460,9 @@ __device__ void rowblock_qr(double (&y)[RPT][kTb], int jb, double* sred, double*
       const double vtv = sj + v0 * v0;
       const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
       cf[c] = (c > jj && c < jb) ? beta * (v0 * row[c] + sc) : 0.0;
+      // column jj of G = V^T V above the diagonal: rows > jj of column c < jj
+      // hold its reflector, row jj its entry V(jj, c)
+      if (c < jj) sG[c * (kTb + 1) + jj] = sc + row[c] * v0;
       if (c == 0) {
         cf[kTb] = alpha;
         cf[kTb + 1] = v0;
@@ -492,30 +499,10 @@ __device__ __forceinline__ void store_vrow(const double (&y)[kTb], int t, int jb
   for (int c = 0; c < kTb; ++c) Vrow[c] = (c < jb && t > c) ? y[c] : ((c < jb && t == c) ? sv0[c] : 0.0);
 }
 
-// T of the compact WY form I - V T V^T (T upper triangular) from beta and
-// G = V^T V (matrix cores, 4 waves), V row-major rows x kTb in global memory.
-__device__ void build_T(const double* V, int rows, const double* sbeta, double* sG, double* Tout) {
+// T of the compact WY form I - V T V^T (T upper triangular) from beta and the
+// upper part of G = V^T V that rowblock_qr left in sG.
+__device__ void build_T(const double* sbeta, const double* sG, double* Tout) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int nw = blockDim.x >> 6;
-  for (int tile = wv; tile < 4; tile += nw) {
-    const int p0 = (tile >> 1) * 16, p1 = (tile & 1) * 16;
-    double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    for (int kb = 0; kb < rows; kb += 32) {  // 8 steps of 4 rows, loads issued first
-      double a[8], b[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int r = kb + 4 * u + lk;
-        a[u] = r < rows ? V[int64_t(r) * kTb + p0 + li] : 0.0;
-        b[u] = r < rows ? V[int64_t(r) * kTb + p1 + li] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc = mfma_f64(a[u], b[u], acc);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) sG[(p0 + 4 * v + lk) * (kTb + 1) + p1 + li] = acc[v];
-  }
-  __syncthreads();
   // T(p, i) = -beta_i sum_{l < i} T(p, l) G(l, i) for p < i, T(i, i) = beta_i:
   // one wave, lane p keeps row p of T in registers (no barriers)
   if (wv == 0) {
@@ -525,11 +512,12 @@ __device__ void build_T(const double* V, int rows, const double* sbeta, double* 
     for (int l = 0; l < kTb; ++l) trow[l] = 0.0;
 #pragma unroll
     for (int i = 0; i < kTb; ++i) {
-      double acc = 0.0;
-#pragma unroll
-      for (int l = 0; l < i; ++l) acc += trow[l] * sG[l * (kTb + 1) + i];
       const double b = sbeta[i];
-      trow[i] = p == i ? b : (p < i ? -b * acc : 0.0);
+      double acc = 0.0;
+      if (b != 0.0)
+#pragma unroll
+        for (int l = 0; l < i; ++l) acc += trow[l] * sG[l * (kTb + 1) + i];
+      trow[i] = p == i ? b : ((p < i && b != 0.0) ? -b * acc : 0.0);
     }
     if (lane < kTb)
 #pragma unroll
@@ -561,7 +549,7 @@ __global__ __launch_bounds__(BS) void k_tsqr_chunk(QrBatch A, int j0, int cr, in
 #pragma unroll
     for (int cc = 0; cc < kTb; ++cc) y[u][cc] = (t < rows && cc < g.jb) ? src[cc] : 0.0;
   }
-  rowblock_qr<BS / 64, RPT>(y, g.jb, sred, srow, scf, sv0, sbeta);
+  rowblock_qr<BS / 64, RPT>(y, g.jb, sred, srow, scf, sv0, sbeta, sG);
   double* V = S0 + L.V + int64_t(lo) * kTb;
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
@@ -581,7 +569,7 @@ __global__ __launch_bounds__(BS) void k_tsqr_chunk(QrBatch A, int j0, int cr, in
     for (int cc = 0; cc < kTb; ++cc) dst[cc] = (t0 < g.jb && cc >= t0 && cc < g.jb) ? y[0][cc] : 0.0;
   }
   __syncthreads();
-  build_T(V, rows, sbeta, sG, S0 + L.Tc + int64_t(c) * kTb * kTb);
+  build_T(sbeta, sG, S0 + L.Tc + int64_t(c) * kTb * kTb);
 }
 
 // K2: QR of the stacked chunk R factors (nck > 1); writes the panel's R.
@@ -608,7 +596,7 @@ __global__ __launch_bounds__(BS) void k_tsqr_stack(QrBatch A, int j0, int cr, in
 #pragma unroll
     for (int cc = 0; cc < kTb; ++cc) y[u][cc] = tu < srows ? src[cc] : 0.0;
   }
-  rowblock_qr<BS / 64, RPT>(y, g.jb, sred, srow, scf, sv0, sbeta);
+  rowblock_qr<BS / 64, RPT>(y, g.jb, sred, srow, scf, sv0, sbeta, sG);
   double* V = S0 + L.Vs;
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
@@ -622,7 +610,7 @@ __global__ __launch_bounds__(BS) void k_tsqr_stack(QrBatch A, int j0, int cr, in
       if (cc < g.jb) dst[cc] = cc >= t ? y[0][cc] : 0.0;
   }
   __syncthreads();
-  build_T(V, srows, sbeta, sG, S0 + L.Ts);
+  build_T(sbeta, sG, S0 + L.Ts);
 }
 
 // Y <- (I - V T V^T)^T Y for one 64-column tile: P = V^T Y, W = T^T P,
