@@ -88,6 +88,28 @@ void* dbuf_take(size_t cls, hipStream_t s) {
   return p;
 }
 
+void dbuf_trim() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  {
+    DbufCache& c = dbuf_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    for (auto it = c.blocks.begin(); it != c.blocks.end();) {
+      if (it->first.dev == dev) {
+        (void)hipFreeAsync(it->second, it->first.s);
+        c.bytes -= it->first.cls;
+        it = c.blocks.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  (void)hipDeviceSynchronize();
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+  (void)hipGetLastError();
+}
+
 bool dbuf_give(void* p, size_t cls, hipStream_t s) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return false;

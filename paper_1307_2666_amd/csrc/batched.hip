@@ -815,77 +815,6 @@ __global__ __launch_bounds__(256) void k_tsqr_apply_stack(QrBatch A, int j0, int
 // pivoting among rows < r: panel j0 = columns j0..j0+jb-1 with row swaps over
 // whole rows, then U12 = L11^{-1} A12 for the panel rows.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_lu_panel(LuBatch A, int j0) {
-  const int q = blockIdx.x;
-  const int n = A.n[q], r = A.r[q];
-  if (j0 >= r) return;
-  double* M = A.base + A.moff[q];
-  int32_t* piv = A.piv + A.poff[q];
-  const int jb = min(kNb, r - j0);
-  const int tid = threadIdx.x;
-  for (int j = j0; j < j0 + jb; ++j) {
-    AM loc{-1.0, INT_MAX};
-    for (int i = j + tid; i < r; i += 256) loc = am_better(loc, AM{fabs(M[int64_t(i) * n + j]), i});
-    const AM best = block_argmax256(loc);
-    if (!(best.v > 0.0)) {
-      if (tid == 0) atomicOr(A.status, 1);
-      return;
-    }
-    const int p = best.i;
-    if (tid == 0) piv[j] = p;
-    if (p != j)
-      for (int col = tid; col < n; col += 256) {
-        const double t = M[int64_t(j) * n + col];
-        M[int64_t(j) * n + col] = M[int64_t(p) * n + col];
-        M[int64_t(p) * n + col] = t;
-      }
-    __syncthreads();
-    const double inv = 1.0 / M[int64_t(j) * n + j];
-    const int w = j0 + jb - j - 1;
-    double prow[kNb];
-#pragma unroll
-    for (int c = 0; c < kNb; ++c) prow[c] = c < w ? M[int64_t(j) * n + j + 1 + c] : 0.0;
-    for (int i0 = j + 1 + tid; i0 < n; i0 += 4 * 256) {
-      double y[4][kNb + 1];
-#pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        const int i = i0 + qq * 256;
-#pragma unroll
-        for (int c = 0; c <= kNb; ++c) y[qq][c] = (i < n && c <= w) ? M[int64_t(i) * n + j + c] : 0.0;
-      }
-#pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        const int i = i0 + qq * 256;
-        if (i >= n) continue;
-        const double l = y[qq][0] * inv;
-        M[int64_t(i) * n + j] = l;
-#pragma unroll
-        for (int c = 0; c < kNb; ++c)
-          if (c < w) M[int64_t(i) * n + j + 1 + c] = y[qq][c + 1] - l * prow[c];
-      }
-    }
-    __syncthreads();
-  }
-  // U12 = L11^{-1} A12 (rows j0..j0+jb-1, columns j0+jb..n-1)
-  for (int c = j0 + jb + tid; c < n; c += 256) {
-    double x[kNb];
-#pragma unroll
-    for (int i = 0; i < kNb; ++i) x[i] = i < jb ? M[int64_t(j0 + i) * n + c] : 0.0;
-#pragma unroll
-    for (int i = 1; i < kNb; ++i) {
-      if (i >= jb) break;
-      double v = x[i];
-#pragma unroll
-      for (int p = 0; p < kNb; ++p)
-        if (p < i) v -= M[int64_t(j0 + i) * n + j0 + p] * x[p];
-      x[i] = v;
-    }
-#pragma unroll
-    for (int i = 1; i < kNb; ++i)
-      if (i < jb) M[int64_t(j0 + i) * n + c] = x[i];
-  }
-}
-
 // Register-resident panel for panels of at most kLpRows rows (rows j0..n-1):
 // thread t holds rows j0 + t and j0 + t + kLpThreads of the kNb panel
 // columns for all kNb elimination steps; the pivot row is exchanged and
@@ -1009,6 +938,181 @@ __global__ __launch_bounds__(kLpThreads) void k_lu_panel_reg(LuBatch A, int j0) 
     for (int i = 1; i < kNb; ++i)
       if (i < jb) M[int64_t(j0 + i) * n + c] = x[i];
   }
+}
+
+// ---------------------------------------------------------------------------
+// Multi-workgroup panel for panels taller than the register panels (the top
+// block and the largest redundant blocks in 3D): rows in blocks of kLmRows
+// per workgroup, one launch per column step.  Every workgroup reduces the
+// block maxima left by the previous launch to the pivot (largest |a(i, j)|
+// over unpivoted candidate rows i < r, ties to the lowest row), eliminates
+// column j from its own unpivoted rows and leaves its block maximum of
+// column j + 1 (double-buffered by step parity).  The pivot row is flagged,
+// not moved, so no workgroup reads a row that another writes in the same
+// launch; after the panel the interchanges go to piv in LAPACK order and are
+// applied as one permutation, with U12 = L11^{-1} A12.
+// ---------------------------------------------------------------------------
+constexpr int kLmRows = 256;
+
+struct LuPanelState {
+  double* pv;      // [2][nprob][nblk] block maxima
+  int32_t* pi;     // [2][nprob][nblk] their rows
+  int32_t* flag;   // [nprob][fstride] -1 unpivoted, else the step (rows j0..)
+  int32_t* prow;   // [nprob][kNb] pivot row of each step
+  int nblk;
+  int64_t fstride;
+};
+
+__global__ __launch_bounds__(256) void k_lum_init(LuBatch A, LuPanelState P, int j0) {
+  const int q = blockIdx.y, blk = blockIdx.x;
+  const int n = A.n[q], r = A.r[q];
+  if (j0 >= r || j0 + blk * kLmRows >= n) return;
+  const double* M = A.base + A.moff[q];
+  const int i = j0 + blk * kLmRows + threadIdx.x;
+  if (i < n) P.flag[q * P.fstride + (i - j0)] = -1;
+  AM loc{-1.0, INT_MAX};
+  if (i < r) loc = AM{fabs(M[int64_t(i) * n + j0]), i};
+  const AM b = block_argmax256(loc);
+  if (threadIdx.x == 0) {
+    P.pv[q * P.nblk + blk] = b.v;
+    P.pi[q * P.nblk + blk] = b.i;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lum_step(LuBatch A, LuPanelState P, int j0, int jj) {
+  const int q = blockIdx.y, blk = blockIdx.x;
+  const int n = A.n[q], r = A.r[q];
+  if (j0 >= r) return;
+  const int jb = min(kNb, r - j0);
+  const int rb0 = j0 + blk * kLmRows;
+  if (jj >= jb || rb0 >= n) return;
+  double* M = A.base + A.moff[q];
+  const int tid = threadIdx.x;
+  const int64_t cur = int64_t(jj & 1) * A.nprob * P.nblk, nxt = int64_t((jj + 1) & 1) * A.nprob * P.nblk;
+  const int nbr = (r - j0 + kLmRows - 1) / kLmRows;  // blocks holding candidate rows
+  AM loc{-1.0, INT_MAX};
+  for (int b = tid; b < nbr; b += 256) loc = am_better(loc, AM{P.pv[cur + q * P.nblk + b], P.pi[cur + q * P.nblk + b]});
+  const AM best = block_argmax256(loc);
+  if (!(best.v > 0.0)) {
+    if (blk == 0 && tid == 0) atomicOr(A.status, 1);
+    return;
+  }
+  const int rp = best.i;
+  __shared__ double sp[kNb];
+  if (tid < kNb) sp[tid] = tid < jb ? M[int64_t(rp) * n + j0 + tid] : 0.0;
+  __syncthreads();
+  if (blk == 0 && tid == 0) P.prow[q * kNb + jj] = rp;
+  const int i = rb0 + tid;
+  AM nx{-1.0, INT_MAX};
+  if (i < n && i != rp && P.flag[q * P.fstride + (i - j0)] < 0) {
+    double* row = M + int64_t(i) * n + j0;
+    double y[kNb];
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) y[c] = (c >= jj && c < jb) ? row[c] : 0.0;
+    const double l = pick16(y, jj) / sp[jj];
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) {
+      if (c == jj) row[c] = l;
+      else if (c > jj && c < jb) {
+        y[c] -= l * sp[c];
+        row[c] = y[c];
+      }
+    }
+    if (jj + 1 < jb && i < r) nx = AM{fabs(pick16(y, jj + 1)), i};
+  }
+  if (i == rp) P.flag[q * P.fstride + (i - j0)] = jj;
+  const AM b2 = block_argmax256(nx);
+  if (tid == 0) {
+    P.pv[nxt + q * P.nblk + blk] = b2.v;
+    P.pi[nxt + q * P.nblk + blk] = b2.i;
+  }
+}
+
+// The panel's interchanges as a permutation of at most 2 kNb rows (one wave,
+// lane a holds entry a: position dst receives physical row src), and piv.
+__device__ void lum_perm(const LuPanelState& P, int q, int j0, int jb, int* s_dst, int* s_src, int* s_na,
+                         int32_t* piv) {
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x >= 64) return;
+  int dst = lane < jb ? j0 + lane : -1, src = dst, na = jb;
+  for (int jj = 0; jj < jb; ++jj) {
+    const int rp = P.prow[q * kNb + jj];
+    const unsigned long long hit = __ballot(src == rp);
+    int ap;
+    if (hit) {
+      ap = __ffsll(hit) - 1;
+    } else {
+      ap = na++;
+      if (lane == ap) dst = src = rp;
+    }
+    const int pos = __shfl(dst, ap, 64);
+    if (piv && lane == 0) piv[j0 + jj] = pos;
+    const int s_jj = __shfl(src, jj, 64), s_ap = __shfl(src, ap, 64);
+    if (lane == jj) src = s_ap;
+    if (lane == ap) src = s_jj;
+  }
+  if (lane < na) {
+    s_dst[lane] = dst;
+    s_src[lane] = src;
+  }
+  if (lane == 0) *s_na = na;
+}
+
+// Columns outside the panel (mode 0): the interchanges, and right of the
+// panel U12 = L11^{-1} A12 with L11 from the pivot rows' panel columns (not
+// written here).  Mode 1: the interchanges of the panel columns.
+__global__ __launch_bounds__(256) void k_lum_finish(LuBatch A, LuPanelState P, int j0, int mode) {
+  const int q = blockIdx.y;
+  const int n = A.n[q], r = A.r[q];
+  if (j0 >= r) return;
+  const int jb = min(kNb, r - j0);
+  double* M = A.base + A.moff[q];
+  __shared__ int s_dst[2 * kNb], s_src[2 * kNb], s_na;
+  __shared__ double sL[kNb][kNb + 1];
+  lum_perm(P, q, j0, jb, s_dst, s_src, &s_na, (mode == 0 && blockIdx.x == 0) ? A.piv + A.poff[q] : nullptr);
+  __syncthreads();
+  const int na = s_na;
+  if (mode == 1) {
+    const int e = threadIdx.x;  // one thread per panel column
+    if (blockIdx.x != 0 || e >= jb) return;
+    const int col = j0 + e;
+    double v[2 * kNb];
+#pragma unroll
+    for (int a2 = 0; a2 < 2 * kNb; ++a2) v[a2] = a2 < na ? M[int64_t(s_src[a2]) * n + col] : 0.0;
+#pragma unroll
+    for (int a2 = 0; a2 < 2 * kNb; ++a2)
+      if (a2 < na && s_src[a2] != s_dst[a2]) M[int64_t(s_dst[a2]) * n + col] = v[a2];
+    return;
+  }
+  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, c = e % kNb;
+    sL[i][c] = (i < jb && c < jb) ? M[int64_t(s_src[i]) * n + j0 + c] : 0.0;
+  }
+  bool moved = false;
+  for (int a2 = 0; a2 < na; ++a2) moved = moved || s_src[a2] != s_dst[a2];
+  __syncthreads();
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= n || (col >= j0 && col < j0 + jb)) return;
+  const bool right = col >= j0 + jb;
+  if (!right && !moved) return;
+  double v[2 * kNb];
+#pragma unroll
+  for (int a2 = 0; a2 < 2 * kNb; ++a2)
+    v[a2] = (a2 < na && ((right && a2 < jb) || s_src[a2] != s_dst[a2])) ? M[int64_t(s_src[a2]) * n + col] : 0.0;
+  if (right) {
+#pragma unroll
+    for (int i = 1; i < kNb; ++i) {
+      if (i >= jb) break;
+      double t = v[i];
+#pragma unroll
+      for (int p2 = 0; p2 < kNb; ++p2)
+        if (p2 < i) t -= sL[i][p2] * v[p2];
+      v[i] = t;
+    }
+  }
+#pragma unroll
+  for (int a2 = 0; a2 < 2 * kNb; ++a2)
+    if (a2 < na && ((right && a2 < jb) || s_src[a2] != s_dst[a2])) M[int64_t(s_dst[a2]) * n + col] = v[a2];
 }
 
 // Trailing update A22 -= L21 U12 of one 64 x 64 tile (K = panel width).
@@ -1222,15 +1326,36 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
 
 void launch_lu_batched(const LuBatch& A, int max_r, int max_n, hipStream_t s) {
   if (A.nprob == 0) return;
+  // state of the multi-workgroup panel (panels taller than kLpRows)
+  DBuf<double> pv;
+  DBuf<int32_t> pi, flag, prow;
+  LuPanelState P{};
+  if (max_n > kLpRows) {
+    P.nblk = (max_n + kLmRows - 1) / kLmRows;
+    P.fstride = max_n;
+    pv.alloc(size_t(2) * A.nprob * P.nblk, nullptr);
+    pi.alloc(size_t(2) * A.nprob * P.nblk, nullptr);
+    flag.alloc(size_t(A.nprob) * max_n, nullptr);
+    prow.alloc(size_t(A.nprob) * kNb, nullptr);
+    P.pv = pv.p;
+    P.pi = pi.p;
+    P.flag = flag.p;
+    P.prow = prow.p;
+  }
   for (int j0 = 0; j0 < max_r; j0 += kNb) {
-    if (max_n - j0 <= kLpRows / 4)  // two rows per thread
+    if (max_n - j0 > kLpRows) {
+      const dim3 g(unsigned((max_n - j0 + kLmRows - 1) / kLmRows), unsigned(A.nprob));
+      hipLaunchKernelGGL(k_lum_init, g, dim3(256), 0, s, A, P, j0);
+      for (int jj = 0; jj < kNb; ++jj) hipLaunchKernelGGL(k_lum_step, g, dim3(256), 0, s, A, P, j0, jj);
+      hipLaunchKernelGGL(k_lum_finish, dim3(unsigned((max_n + 255) / 256), unsigned(A.nprob)), dim3(256), 0, s, A,
+                         P, j0, 0);
+      hipLaunchKernelGGL(k_lum_finish, dim3(1, unsigned(A.nprob)), dim3(256), 0, s, A, P, j0, 1);
+    } else if (max_n - j0 <= kLpRows / 4)  // two rows per thread
       hipLaunchKernelGGL(k_lu_panel_reg<256>, dim3(A.nprob), dim3(256), 0, s, A, j0);
     else if (max_n - j0 <= kLpRows / 2)
       hipLaunchKernelGGL(k_lu_panel_reg<512>, dim3(A.nprob), dim3(512), 0, s, A, j0);
-    else if (max_n - j0 <= kLpRows)
-      hipLaunchKernelGGL(k_lu_panel_reg<1024>, dim3(A.nprob), dim3(1024), 0, s, A, j0);
     else
-      hipLaunchKernelGGL(k_lu_panel, dim3(A.nprob), dim3(256), 0, s, A, j0);
+      hipLaunchKernelGGL(k_lu_panel_reg<1024>, dim3(A.nprob), dim3(1024), 0, s, A, j0);
     const int rem = max_n - j0 - 1;
     if (rem > 0) {
       const unsigned tiles = unsigned((rem + 63) / 64);

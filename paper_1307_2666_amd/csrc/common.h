@@ -62,10 +62,14 @@ void dbuf_pool_setup();  // once per device: keep freed memory in the pool
 // the block's last use; it saves the allocator's per-call host cost between
 // the host's waits on the device.  At most kDbufCacheBytes stay cached (per
 // process); beyond that blocks go back to the pool.
+// Blocks of kDbufDirectBytes or more bypass both (plain hipMalloc / hipFree):
+// few and large, they would otherwise stay reserved in the pool.
 constexpr size_t kDbufCacheBytes = size_t(8) << 30;
+constexpr size_t kDbufDirectBytes = size_t(1) << 30;
 size_t dbuf_class(size_t bytes);                  // allocation size for a request
 void* dbuf_take(size_t cls, hipStream_t s);       // cached block or nullptr
 bool dbuf_give(void* p, size_t cls, hipStream_t s);  // true if cached
+void dbuf_trim();  // return every cached and pooled free block to the device
 struct StreamScope {
   hipStream_t prev;
   explicit StreamScope(hipStream_t s) : prev(dbuf_stream()) {
@@ -94,7 +98,10 @@ struct DBuf {
   ~DBuf() { release(); }
   void release() {
     if (p) {
-      if (!dbuf_give(p, cls, dbuf_stream())) (void)hipFreeAsync(p, dbuf_stream());
+      if (cls >= kDbufDirectBytes)
+        (void)hipFree(p);
+      else if (!dbuf_give(p, cls, dbuf_stream()))
+        (void)hipFreeAsync(p, dbuf_stream());
       if (mt) mt->held -= n * sizeof(T);
     }
     p = nullptr;
@@ -109,9 +116,17 @@ struct DBuf {
     if (mt && mt->cap && mt->held + bytes > mt->cap)
       throw Error{HIF_ENOMEM, "device memory cap (opts.max_bytes) exceeded"};
     const size_t c = dbuf_class(bytes);
-    p = static_cast<T*>(dbuf_take(c, dbuf_stream()));
+    p = c >= kDbufDirectBytes ? nullptr : static_cast<T*>(dbuf_take(c, dbuf_stream()));
     if (!p) {
-      hipError_t e = hipMallocAsync((void**)&p, c, dbuf_stream());
+      auto get = [&]() {
+        return c >= kDbufDirectBytes ? hipMalloc((void**)&p, c) : hipMallocAsync((void**)&p, c, dbuf_stream());
+      };
+      hipError_t e = get();
+      if (e != hipSuccess) {  // once more after returning free blocks to the device
+        (void)hipGetLastError();
+        dbuf_trim();
+        e = get();
+      }
       if (e != hipSuccess) {
         (void)hipGetLastError();
         p = nullptr;

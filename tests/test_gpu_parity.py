@@ -439,3 +439,28 @@ def test_sq512_full_size_apply_and_solve():
     lhs = torch.dot(F.solve_T(g), f[0]).item()
     rhs = torch.dot(g, u[0]).item()
     assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
+
+
+def test_cube32_tall_lu_panels():
+    # 3D 32^3: the top block (about 9.9k unknowns) and the largest redundant
+    # blocks have LU panels taller than the register panels, factored by the
+    # multi-workgroup panel; solve residual and apply error against the exact
+    # operator, and the transposed-solve identity
+    wl = workload("cube32")
+    P = _t(wl.points())
+    a = torch.ones(wl.N, dtype=torch.float64, device=DEV)
+    F = hif.factor(P, wl.eps, wl.leaf, a=a, h=wl.h)
+    assert F.stats()["top_size"] > 2048
+    f = _t(wl.rhs())
+    u = F.solve(f)
+    r = f - hif.matvec(P, u, a=a, h=wl.h)
+    rel = (torch.linalg.norm(r) / torch.linalg.norm(f)).item()
+    assert rel <= 10 * wl.eps, rel
+    x = _t(np.random.default_rng(21).standard_normal(wl.N))
+    Ax = hif.matvec(P, x, a=a, h=wl.h)
+    e = (torch.linalg.norm(F.apply(x) - Ax) / torch.linalg.norm(Ax)).item()
+    assert e <= 10 * wl.eps, e
+    g = _t(np.random.default_rng(22).standard_normal(wl.N))
+    lhs = torch.dot(F.solve_T(g), f.reshape(-1)).item()
+    rhs = torch.dot(g, u.reshape(-1)).item()
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
