@@ -13,6 +13,10 @@ accuracy gate (error of the solution against the exact solution of the
 discretized system, estimated by one step of refinement with the exact
 on-the-fly matvec), a roofline entry for the dominant kernel and the CPU
 oracle's throughput on a bounded sample.
+
+``--workload diff256`` times the differentiated solve instead: 256 x 256 grid,
+a = 1 + 64 Gaussian bumps, one right-hand side, L = |u - u_target|^2 / 2; one
+step = forward (factor + solve) + backward (adjoint solve + dL/da, dL/df).
 """
 from __future__ import annotations
 
@@ -114,11 +118,122 @@ def refinement(hif, P, a, Fr, wl, tol=1e-10):
     return {"target_residual": tol, "runs": runs, "best": best, "mixed_vs_fp64_speedup": speedup}
 
 
+def id_roofline(st, ph):
+    """Roofline entry of the pivoted-QR kernel family from a factorization's statistics."""
+    import numpy as np
+
+    id_bytes = float(np.sum(st["sub_id_bytes"]))
+    id_ms = ph["id"]
+    achieved = id_bytes / (id_ms * 1e-3) / 1e9 if id_ms > 0 else 0.0
+    return {"kernel": "k_bq_piv + k_bq_cols + k_bq_update + k_id_reg + k_id (column-pivoted QR of "
+                      "the IDs, all launches of a step)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_step": id_bytes, "ms_per_step": id_ms}
+
+
+def cpu_baseline_diff(n: int, eps: float):
+    """The oracle as it stands (one BLAS thread): factor + solve + transposed solve + dL/da
+    of the differentiated-solve problem on an n x n grid."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.factor import factorize
+    from oracle.kernels import Operator
+    from workloads import diff_problem
+
+    p = diff_problem(n)
+    op = Operator.uniform(p.points, p.h, a=p.a)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        F = factorize(op, eps, 64)
+        u = F.solve(p.f)
+        lam = F.solve_T(u - p.u_target)
+        _ = -(lam * u)
+        dt = time.perf_counter() - t0
+    N = p.points.shape[0]
+    return {"value": N / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle hifie2x factor + solve + transposed solve of the {n}x{n} differentiated-solve "
+                      f"problem (N={N}, leaf 64, eps {eps:g}), {dt:.1f} s on 1 host core"}
+
+
+def bench_diff(args):
+    """Forward + backward of the differentiated solve on the 256 x 256 problem."""
+    import numpy as np
+    import torch
+
+    import paper_1307_2666_amd as hif
+    from workloads import diff_problem
+
+    eps = args.eps if args.eps is not None else 1e-6
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    p = diff_problem(256)
+    N = p.points.shape[0]
+    P = torch.tensor(p.points, device=dev)
+    a0 = torch.tensor(p.a, device=dev)
+    f0 = torch.tensor(p.f, device=dev)
+    t = torch.tensor(p.u_target, device=dev)
+
+    def step(prec=hif.HIF_FP64, refine=False):
+        a = a0.clone().requires_grad_(True)
+        f = f0.clone().requires_grad_(True)
+        u = hif.diff.solve(P, a, f, eps, 64, h=p.h, precision=prec, refine=refine, tol=1e-12)
+        st = u.grad_fn.fac.stats()
+        (0.5 * torch.sum((u - t) ** 2)).backward()
+        return a.grad, f.grad, st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ga, gf, st = step()
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    modes = {}
+    ref = None
+    for name, prec, refine in (("fp64_refined", hif.HIF_FP64, True), ("fp32_mixed_refined", hif.HIF_FP32_MIXED, True)):
+        step(prec, refine)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = step(prec, refine)
+        torch.cuda.synchronize()
+        modes[name] = {"ms_per_step": (time.perf_counter() - t1) * 1e3}
+        if ref is None:
+            ref = g
+        else:
+            modes[name]["grad_a_rel_diff_vs_fp64_refined"] = (torch.linalg.norm(g[0] - ref[0]) /
+                                                              torch.linalg.norm(ref[0])).item()
+    ga_err = (torch.linalg.norm(ga - ref[0]) / torch.linalg.norm(ref[0])).item()
+    gf_err = (torch.linalg.norm(gf - ref[1]) / torch.linalg.norm(ref[1])).item()
+    ph = {k: float(np.mean([s["t_phase_ms"][k] for s in stats])) for k in stats[0]["t_phase_ms"]}
+    line = {
+        "metric": "differentiated solve (forward + backward) unknowns/s",
+        "value": N / dt, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"diff256: 2D Laplace second-kind volume IE, 256x256 grid (N={N}), a = 1 + 64 "
+                               f"Gaussian bumps, 1 RHS, L = |u - u_target|^2/2, eps={eps:g}, leaf 64, FP64, "
+                               f"gradients of the factored map", "N": N, "eps": eps},
+        "accuracy": {"grad_a_rel_err_vs_refined": ga_err, "grad_f_rel_err_vs_refined": gf_err},
+        "factor_ms": float(np.mean([s["t_factor_ms"] for s in stats])),
+        "phase_ms": ph,
+        "modes": modes,
+        "roofline": id_roofline(stats[-1], ph),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_diff(128, eps)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "diff256":
+        return bench_diff(args)
     import numpy as np
     import torch
 

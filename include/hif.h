@@ -208,6 +208,33 @@ hif_status hif_matvec(const double* points, int64_t n, int dim, const hif_kernel
 hif_status hif_gmres(hif_handle h, const double* f, double* u, int64_t nrhs, double tol, int32_t maxit,
                      int32_t* iters, double* relres, hif_stream stream);
 
+/*
+ * The same refinement for the transposed system A^T u = f (the paper needs
+ * A^T and F^{-T} for its error estimates, Section 5; here they solve the
+ * adjoint equation of a differentiated solve): GMRES on A^T F^{-T} y = f,
+ * u = F^{-T} y, with A^T applied exactly (the matvec of hif_matvec with the
+ * row and column factors exchanged) and F^{-T} = hif_solve_T.
+ * Arguments, limits, memory and errors as hif_gmres; relres is
+ * |f - A^T u| / |f|.
+ */
+hif_status hif_gmres_T(hif_handle h, const double* f, double* u, int64_t nrhs, double tol, int32_t maxit,
+                       int32_t* iters, double* relres, hif_stream stream);
+
+/*
+ * Gradient with respect to the diagonal coefficient a of eqn 1.1 of a scalar
+ * loss L(u) of the solution of the linear system of Section 3.1,
+ * A u = f with A = diag(a) + diag(b) K diag(c).  (The paper does not
+ * differentiate its solver; this is the adjoint of that system.)  With
+ * lambda = A^{-T} dL/du (hif_solve_T, or hif_gmres_T for the refined
+ * system), dL/df = lambda and
+ *   grad[i] = dL/da_i = -sum_r lambda[r][i] u[r][i],
+ * summed over the nrhs right-hand sides that share the operator.
+ *   lambda, u: [nrhs][n] device; grad: [n] device, overwritten, must not
+ *   alias lambda or u.  Stream-ordered; HIF_EINVAL on NULL or sizes < 1.
+ */
+hif_status hif_diag_grad(const double* lambda, const double* u, double* grad, int64_t n, int64_t nrhs,
+                         hif_stream stream);
+
 /* Copy the statistics of a factorization into *out (host memory). */
 hif_status hif_stats(hif_handle h, hif_stats_t* out);
 

@@ -24,6 +24,6 @@ The oracle is a plain, slow, obviously correct NumPy/SciPy implementation:
 * ``estimators`` -- power-iteration error estimates e_a, e_s and
                     right-preconditioned GMRES (Section 5).
 
-Every function cites the passage of the paper it follows.  Readings of the
-paper where it is silent or ambiguous are listed in the design doc.
+Every function cites the passage of the paper it follows; where the paper is
+silent or ambiguous, the docstring states the reading taken.
 """

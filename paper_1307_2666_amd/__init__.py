@@ -3,10 +3,12 @@ equations, Ho & Ying, arXiv 1307.2666): Python binding of the HIP library.
 
 ``factor`` builds ``F ~ A`` on the GPU (Algorithms 4.1 / 4.2, or the RSF of
 Algorithm 3.1); the returned handle applies ``F``, ``F^T``, ``F^{-1}``,
-``F^{-T}``.  ``matvec`` is the exact on-the-fly ``A x``.
+``F^{-T}``.  ``matvec`` is the exact on-the-fly ``A x``.  ``diff.solve`` is
+the solve as a differentiable function of ``a`` and ``f``.
 """
 from ._binding import (EXPORTS, HIF_FP32_MIXED, HIF_FP64, Factorization, HifError, LIB_PATH,  # noqa: F401
-                       default_opts, factor, id_batched, load_library, matvec, partition)
+                       default_opts, diag_grad, factor, id_batched, load_library, matvec, partition)
+from . import diff  # noqa: F401
 
-__all__ = ["factor", "matvec", "id_batched", "partition", "Factorization", "HifError", "load_library",
-           "default_opts", "LIB_PATH", "EXPORTS"]
+__all__ = ["factor", "matvec", "id_batched", "partition", "diag_grad", "diff", "Factorization", "HifError",
+           "load_library", "default_opts", "LIB_PATH", "EXPORTS"]

@@ -73,6 +73,8 @@ EXPORTS = {
     "hif_id_batched": (_INT, [_VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP]),
     "hif_partition": (_INT, [_VP, _I64, _INT, _VP, _INT, _I32, _VP, _VP]),
     "hif_gmres": (_INT, [_VP, _VP, _VP, _I64, _DBL, _I32, _VP, _VP, _VP]),
+    "hif_gmres_T": (_INT, [_VP, _VP, _VP, _I64, _DBL, _I32, _VP, _VP, _VP]),
+    "hif_diag_grad": (_INT, [_VP, _VP, _VP, _I64, _I64, _VP]),
 }
 
 
@@ -163,9 +165,10 @@ class Factorization:
     def apply_T(self, x, out=None, stream=None):
         return self._run(load_library().hif_apply_T, x, out, stream)
 
-    def gmres(self, f, tol=1e-10, maxit=50, out=None, stream=None):
+    def gmres(self, f, tol=1e-10, maxit=50, out=None, stream=None, transpose=False):
         """Solve ``A u = f`` by GMRES right-preconditioned with ``F^{-1}`` and the exact
-        operator given to ``factor``; returns ``(u, iterations, true relative residuals)``."""
+        operator given to ``factor``; returns ``(u, iterations, true relative residuals)``.
+        With ``transpose`` it solves ``A^T u = f`` preconditioned with ``F^{-T}``."""
         if self._h is None:
             raise RuntimeError("factorization has been freed")
         f = _dev(f)
@@ -177,8 +180,9 @@ class Factorization:
         nr = Fm.shape[0]
         its = (ctypes.c_int32 * nr)()
         rr = (ctypes.c_double * nr)()
-        _check(load_library().hif_gmres(self._h, _ptr(Fm), _ptr(U), nr, float(tol), int(maxit),
-                                        ctypes.cast(its, _VP), ctypes.cast(rr, _VP), _stream(stream)))
+        fn = load_library().hif_gmres_T if transpose else load_library().hif_gmres
+        _check(fn(self._h, _ptr(Fm), _ptr(U), nr, float(tol), int(maxit),
+                  ctypes.cast(its, _VP), ctypes.cast(rr, _VP), _stream(stream)))
         return U.reshape(f.shape), list(its), list(rr)
 
     def stats(self) -> dict:
@@ -252,6 +256,20 @@ def matvec(points, x, *, a=None, b=None, c=None, h=None, weights=None, selfk=Non
     _check(lib.hif_matvec(_ptr(P), n, d, ctypes.byref(k), _ptr(av), _ptr(bv), _ptr(cv), _ptr(X), _ptr(Y),
                           X.shape[0], _stream(stream)))
     return Y.reshape(x.shape)
+
+
+def diag_grad(lam, u, out=None, stream=None):
+    """``hif_diag_grad``: ``-sum_r lam[r] * u[r]`` for ``(n,)`` or ``(nrhs, n)`` device arrays."""
+    L = _dev(lam)
+    U = _dev(u)
+    if L.shape != U.shape or L.dim() not in (1, 2):
+        raise ValueError("lam and u must have the same shape, (n,) or (nrhs, n)")
+    L2 = L.reshape(1, -1) if L.dim() == 1 else L
+    U2 = U.reshape(1, -1) if U.dim() == 1 else U
+    n = L2.shape[1]
+    G = torch.empty(n, dtype=torch.float64, device=L.device) if out is None else out
+    _check(load_library().hif_diag_grad(_ptr(L2), _ptr(U2), _ptr(G), n, L2.shape[0], _stream(stream)))
+    return G
 
 
 def id_batched(mats, tols, stream=None):

@@ -250,15 +250,35 @@ hif_status hif_matvec(const double* points, int64_t n, int dim, const hif_kernel
   });
 }
 
-hif_status hif_gmres(hif_handle h, const double* f, double* u, int64_t nrhs, double tol, int32_t maxit,
-                     int32_t* iters, double* relres, hif_stream s) {
+static hif_status gmres_any(hif_handle h, const double* f, double* u, int64_t nrhs, double tol, int32_t maxit,
+                            int32_t* iters, double* relres, bool trans, hif_stream s) {
   if (!h) return fail(HIF_EINVAL, "handle is NULL");
   if (!f || !u) return fail(HIF_EINVAL, "vector pointer is NULL");
   if (f == u) return fail(HIF_EINVAL, "u must not alias f");
   if (nrhs < 1 || nrhs > 64) return fail(HIF_EINVAL, "nrhs must be in [1, 64]");
   if (!(tol > 0.0 && tol < 1.0)) return fail(HIF_EINVAL, "tol must satisfy 0 < tol < 1");
   if (maxit < 1 || maxit > 200) return fail(HIF_EINVAL, "maxit must be in [1, 200]");
-  return guarded(hipStream_t(s), [&] { gmres_impl(h, f, u, nrhs, tol, maxit, iters, relres, hipStream_t(s)); });
+  return guarded(hipStream_t(s),
+                 [&] { gmres_impl(h, f, u, nrhs, tol, maxit, iters, relres, trans, hipStream_t(s)); });
+}
+
+hif_status hif_gmres(hif_handle h, const double* f, double* u, int64_t nrhs, double tol, int32_t maxit,
+                     int32_t* iters, double* relres, hif_stream s) {
+  return gmres_any(h, f, u, nrhs, tol, maxit, iters, relres, false, s);
+}
+
+hif_status hif_gmres_T(hif_handle h, const double* f, double* u, int64_t nrhs, double tol, int32_t maxit,
+                       int32_t* iters, double* relres, hif_stream s) {
+  return gmres_any(h, f, u, nrhs, tol, maxit, iters, relres, true, s);
+}
+
+hif_status hif_diag_grad(const double* lambda, const double* u, double* grad, int64_t n, int64_t nrhs,
+                         hif_stream s) {
+  if (!lambda || !u || !grad) return fail(HIF_EINVAL, "NULL pointer argument");
+  if (n < 1) return fail(HIF_EINVAL, "n must be >= 1");
+  if (nrhs < 1) return fail(HIF_EINVAL, "nrhs must be >= 1");
+  if (grad == lambda || grad == u) return fail(HIF_EINVAL, "grad must not alias lambda or u");
+  return guarded(hipStream_t(s), [&] { diag_grad_impl(lambda, u, grad, n, nrhs, hipStream_t(s)); });
 }
 
 hif_status hif_stats(hif_handle h, hif_stats_t* out) {

@@ -300,8 +300,12 @@ void launch_make_perm_top(const int32_t* piv, int32_t* perm, int n, hipStream_t 
 void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s);
 
 // Right-preconditioned GMRES with the factorization and the exact matvec (gmres.hip).
+// With trans, A^T u = f preconditioned by F^{-T}.
 void gmres_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, double tol, int maxit,
-                int32_t* iters, double* relres, hipStream_t s);
+                int32_t* iters, double* relres, bool trans, hipStream_t s);
+
+// grad = -sum over right-hand sides of lam (.) u (gmres.hip).
+void diag_grad_impl(const double* lam, const double* u, double* grad, int64_t n, int64_t nrhs, hipStream_t s);
 
 // Exact O(n^2) matvec (matvec.hip).
 void matvec_impl(const double* pts, int64_t n, int dim, const double* a, const double* b,

@@ -1,6 +1,7 @@
 // Right-preconditioned GMRES (Section 6, with the factorization F ~ A of
 // this handle as preconditioner): solve A u = f by GMRES on A F^{-1} y = f,
-// u = F^{-1} y, x_0 = 0, no restart.  A is the exact operator of eqn 1.1
+// u = F^{-1} y, x_0 = 0, no restart.  The transposed variant solves
+// A^T u = f on A^T F^{-T} y = f with the same machinery.  A is the exact operator of eqn 1.1
 // applied on the fly (hif_matvec), F^{-1} the solve sweep.  All right-hand
 // sides iterate in lockstep; the Arnoldi basis, the products, the
 // orthogonalization (classical Gram-Schmidt applied twice) and the norms run
@@ -77,10 +78,32 @@ __global__ void k_zero(double* x, int64_t n) {
 
 unsigned grid_for(int64_t N) { return unsigned(std::min<int64_t>(1024, (N + kThr - 1) / kThr)); }
 
+// Coefficients of A^T in the form the matvec evaluates.  With
+// A_ij = b_i G_ij w_j c_j (i != j) and A_ii = a_i + b_i s_i c_i, the transpose
+// is A^T_ij = (c_i w_i) G_ij b_j: row factor c w, column factor b, unit
+// weights, and the whole diagonal carried by the a term (self term zero).
+__global__ void k_transpose_coef(const double* a, const double* b, const double* c, const double* w,
+                                 const double* sf, double* aT, double* bT, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    aT[i] = a[i] + b[i] * sf[i] * c[i];
+    bT[i] = c[i] * w[i];
+  }
+}
+
+// grad[i] = -sum_v lam[v][i] * u[v][i]
+__global__ __launch_bounds__(kThr) void k_diag_grad(const double* lam, const double* u, double* grad, int64_t n,
+                                                    int nr) {
+  for (int64_t i = blockIdx.x * int64_t(kThr) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kThr) {
+    double t = 0.0;
+    for (int v = 0; v < nr; ++v) t += lam[int64_t(v) * n + i] * u[int64_t(v) * n + i];
+    grad[i] = -t;
+  }
+}
+
 }  // namespace
 
 void gmres_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, double tol, int maxit, int32_t* iters,
-                double* relres, hipStream_t s) {
+                double* relres, bool trans, hipStream_t s) {
   const int64_t N = H->n;
   const int R = int(nrhs);
   const int K = maxit;
@@ -104,8 +127,19 @@ void gmres_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, doubl
     HIF_HIP(hipMemcpyAsync(out.data(), hbuf.p, sizeof(double) * ne, hipMemcpyDeviceToHost, s));
     HIF_HIP(hipStreamSynchronize(s));
   };
+  DBuf<double> coefT;
+  if (trans) {
+    coefT.alloc(size_t(2) * N, nullptr);
+    hipLaunchKernelGGL(k_transpose_coef, dim3(gN), dim3(kThr), 0, s, H->a, H->b, H->c, H->w, H->selfk, coefT.p,
+                       coefT.p + N, N);
+    HIF_HIP(hipGetLastError());
+  }
+  const int pre = trans ? 1 : 0;  // sweep: F^{-1} or F^{-T}
   auto matvec = [&](const double* x, double* y) {
-    matvec_impl(H->pts, N, H->dim, H->a, H->b, H->c, H->w, 0.0, H->selfk, 0.0, x, y, nrhs, s);
+    if (trans)
+      matvec_impl(H->pts, N, H->dim, coefT.p, coefT.p + N, H->b, nullptr, 1.0, nullptr, 0.0, x, y, nrhs, s);
+    else
+      matvec_impl(H->pts, N, H->dim, H->a, H->b, H->c, H->w, 0.0, H->selfk, 0.0, x, y, nrhs, s);
   };
 
   // r_0 = f, beta = |f|, v_0 = f / beta
@@ -138,7 +172,7 @@ void gmres_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, doubl
     for (int v = 0; v < R; ++v)
       HIF_HIP(hipMemcpyAsync(W.p + v * N, V.p + v * vs + int64_t(it) * N, sizeof(double) * N,
                              hipMemcpyDeviceToDevice, s));
-    sweep_impl(H, 0, W.p, Z.p, nrhs, s);
+    sweep_impl(H, pre, W.p, Z.p, nrhs, s);
     matvec(Z.p, W.p);
     // classical Gram-Schmidt, twice
     const int nv = it + 1;
@@ -195,7 +229,7 @@ void gmres_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, doubl
   hipLaunchKernelGGL(k_zero, dim3(gN), dim3(kThr), 0, s, W.p, int64_t(R) * N);
   // only the basis vectors built so far (0..it-1 carry coefficients)
   hipLaunchKernelGGL(k_vcomb, dim3(gN, R), dim3(kThr), 0, s, V.p, vs, hbuf.p, K + 1, it, 1.0, W.p, N, N);
-  sweep_impl(H, 0, W.p, u, nrhs, s);
+  sweep_impl(H, pre, W.p, u, nrhs, s);
   // true residual |f - A u| / |f|
   matvec(u, W.p);
   std::vector<double> ones(R, -1.0);
@@ -208,6 +242,11 @@ void gmres_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, doubl
   if (relres)
     for (int v = 0; v < R; ++v) relres[v] = beta[v] > 0.0 ? std::sqrt(nrm[v]) / beta[v] : 0.0;
   HIF_HIP(hipStreamSynchronize(s));
+}
+
+void diag_grad_impl(const double* lam, const double* u, double* grad, int64_t n, int64_t nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_grad, dim3(grid_for(n)), dim3(kThr), 0, s, lam, u, grad, n, int(nrhs));
+  HIF_HIP(hipGetLastError());
 }
 
 }  // namespace hif

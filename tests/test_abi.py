@@ -96,6 +96,29 @@ def test_gmres_rejects_bad_arguments():
     q = ctypes.cast(ctypes.pointer(ctypes.c_double(0.0)), ctypes.c_void_p)
     assert lib.hif_gmres(None, p, q, 1, 1e-10, 10, None, None, None) == B.HIF_EINVAL
     assert b"handle" in lib.hif_last_error()
+    assert lib.hif_gmres_T(None, p, q, 1, 1e-10, 10, None, None, None) == B.HIF_EINVAL
+    assert b"handle" in lib.hif_last_error()
+
+
+def test_diag_grad_rejects_bad_arguments():
+    lib = hif.load_library()
+    x, y, z = (ctypes.c_void_p(0x1000 * k) for k in (1, 2, 3))
+    assert lib.hif_diag_grad(None, y, z, 4, 1, None) == B.HIF_EINVAL
+    assert lib.hif_diag_grad(x, y, z, 0, 1, None) == B.HIF_EINVAL
+    assert lib.hif_diag_grad(x, y, z, 4, 0, None) == B.HIF_EINVAL
+    assert lib.hif_diag_grad(x, y, x, 4, 1, None) == B.HIF_EINVAL
+    assert b"alias" in lib.hif_last_error()
+
+
+def test_diff_solve_checks_shapes_on_the_host():
+    import torch
+    P = torch.zeros(16, 2, dtype=torch.float64)
+    with pytest.raises(ValueError, match="a must"):
+        hif.diff.solve(P, torch.ones(15), torch.ones(16), 1e-6, 4, h=0.25)
+    with pytest.raises(ValueError, match="f must"):
+        hif.diff.solve(P, torch.ones(16), torch.ones(2, 15), 1e-6, 4, h=0.25)
+    with pytest.raises(ValueError, match="tol"):
+        hif.diff.solve(P, torch.ones(16), torch.ones(16), 1e-6, 4, h=0.25, refine=True, tol=0.0)
 
 
 def test_matvec_rejects_bad_arguments():

@@ -25,6 +25,8 @@ __all__ = [
     "workload",
     "rhs",
     "gaussian_bump_field",
+    "DiffProblem",
+    "diff_problem",
 ]
 
 
@@ -107,3 +109,25 @@ def gaussian_bump_field(points: np.ndarray, n_bumps: int, sigma: float, wmax: fl
         lo, hi = g.min(), g.max()
         g = (g - lo) / (hi - lo) if hi > lo else np.zeros_like(g)
     return g
+
+
+@dataclass(frozen=True)
+class DiffProblem:
+    """Inputs of a differentiated solve ``L = |u - u_target|^2 / 2`` with ``A(a) u = f``."""
+
+    n: int
+    h: float
+    points: np.ndarray
+    a: np.ndarray
+    f: np.ndarray
+    u_target: np.ndarray
+
+
+def diff_problem(n: int = 256, seed_a: int = 5, seed_target: int = 6, seed_f: int = 7) -> DiffProblem:
+    """2D grid ``n x n`` with ``a = 1 + sum_{k<64} w_k exp(-|x-c_k|^2 / (2 * 0.05^2))``,
+    ``w_k ~ U(0, 0.5)``, ``c_k ~ U[0,1]^2`` (seed ``seed_a``); ``f`` and ``u_target``
+    standard normal from their own seeds; ``b = c = 1``."""
+    P = grid_points(n, 2)
+    a = 1.0 + gaussian_bump_field(P, 64, 0.05, 0.5, seed_a)
+    N = P.shape[0]
+    return DiffProblem(n, 1.0 / n, P, a, rhs(N, 1, seed_f)[0], rhs(N, 1, seed_target)[0])
