@@ -2,6 +2,8 @@
 // problems.  Internal, not part of the ABI.
 #pragma once
 
+#include <vector>
+
 #include "kernels.h"
 
 namespace hif {
@@ -10,6 +12,22 @@ namespace hif {
 using QrBatch = RowQrArgs;
 // Few large problems: max_rows/max_cols bound rows/cols over the batch.
 void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t s);
+
+// Row compression of problems taller than one TSQR stack holds (more than
+// kTsqrSplitRows rows), from host copies of the problems' offsets (from
+// base), leading dimensions, rows and columns: each is cut into row blocks
+// factored as problems of their own, whose R factors are stacked and factored
+// again.  Leaves R0 in the leading n x n block of every problem with m > n,
+// as launch_qr_batched does.
+// Blocks have at least half kTsqrSplitRows rows, and at least twice the
+// columns for up to 16384 columns, so each round shrinks the stack.
+constexpr int kTsqrSplitRows = 32768;
+inline bool rowqr_split_fits(int max_rows, int max_cols) {
+  return max_rows > kTsqrSplitRows && max_cols <= kTsqrSplitRows / 2;
+}
+void launch_rowqr_split(double* base, const std::vector<int64_t>& moff, const std::vector<int32_t>& ld,
+                        const std::vector<int32_t>& rows, const std::vector<int32_t>& cols, MemTracker* mt,
+                        hipStream_t s);
 
 // Communication-avoiding panels of the row compression: panel width, rows per
 // chunk (one per thread) and the largest stack of chunk R factors.

@@ -1324,6 +1324,137 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
   HIF_HIP(hipGetLastError());
 }
 
+// One rectangle copy per blockIdx.y: dst[r * dld + c] = src[r * sld + c].
+struct BlockCopy {
+  const double* src;
+  double* dst;
+  int32_t sld, dld, rows, cols;
+};
+__global__ void k_copy_blocks(const BlockCopy* d) {
+  const BlockCopy c = d[blockIdx.y];
+  const int64_t ne = int64_t(c.rows) * c.cols;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < ne; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = e / c.cols, k = e % c.cols;
+    c.dst[r * c.dld + k] = c.src[r * c.sld + k];
+  }
+}
+
+static void copy_blocks(const std::vector<BlockCopy>& h, MemTracker* mt, hipStream_t s) {
+  if (h.empty()) return;
+  DBuf<BlockCopy> d;
+  d.alloc(h.size(), mt);
+  HIF_HIP(hipMemcpyAsync(d.p, h.data(), sizeof(BlockCopy) * h.size(), hipMemcpyHostToDevice, s));
+  for (size_t i = 0; i < h.size(); i += 65535) {
+    const unsigned cnt = unsigned(std::min<size_t>(65535, h.size() - i));
+    hipLaunchKernelGGL(k_copy_blocks, dim3(256, cnt), dim3(256), 0, s, d.p + i);
+  }
+  HIF_HIP(hipGetLastError());
+}
+
+void launch_rowqr_split(double* base, const std::vector<int64_t>& moff, const std::vector<int32_t>& ld,
+                        const std::vector<int32_t>& rows, const std::vector<int32_t>& cols, MemTracker* mt,
+                        hipStream_t s) {
+  // The R factor of [Y_1; ...; Y_b] is that of [R_1; ...; R_b] with
+  // Y_i = Q_i R_i (up to row signs, which the ID does not see), and only R
+  // is needed.  Blocks of 4096..8192 rows (n <= 2048) shrink the stack at
+  // least 2-fold a round; blocks of 16384..32768 rows (n <= 16384) leave a
+  // stack of nb n rows, which a round of 2 blocks brings to one block.
+  struct Prob {
+    int64_t off;
+    int32_t ld, rows, cols, orig;
+  };
+  int maxn = 1;
+  std::vector<Prob> cur;
+  for (size_t q = 0; q < rows.size(); ++q)
+    if (rows[q] > cols[q]) {
+      cur.push_back({moff[q], ld[q], rows[q], cols[q], int32_t(q)});
+      maxn = std::max(maxn, cols[q]);
+    }
+  HIF_REQUIRE(maxn <= kTsqrSplitRows / 2, HIF_EUNSUPPORTED, "row compression of more than 16384 columns");
+  const int B = maxn <= 2048 ? 8192 : kTsqrSplitRows;
+  double* rbase = base;     // buffer of this round's problems
+  DBuf<double> stack[2];    // stacks of R factors, alternating by round
+  for (int round = 0; !cur.empty(); ++round) {
+    std::vector<int64_t> h_off, h_soff;
+    std::vector<int32_t> h_ld, h_rows, h_cols;
+    std::vector<int32_t> nblk(cur.size());
+    int64_t stot = 0, next_tot = 0;
+    int maxr = 1, maxc = 1;
+    for (size_t i = 0; i < cur.size(); ++i) {
+      const Prob& p = cur[i];
+      const int nb = p.rows > B ? (p.rows + B - 1) / B : 1;
+      nblk[i] = nb;
+      for (int b = 0; b < nb; ++b) {
+        const int r0 = int(int64_t(p.rows) * b / nb), r1 = int(int64_t(p.rows) * (b + 1) / nb);
+        h_off.push_back(p.off + int64_t(r0) * p.ld);
+        h_ld.push_back(p.ld);
+        h_rows.push_back(r1 - r0);
+        h_cols.push_back(p.cols);
+        h_soff.push_back(stot);
+        stot += rowqr_scratch(r1 - r0, p.cols);
+        maxr = std::max(maxr, r1 - r0);
+        maxc = std::max(maxc, p.cols);
+      }
+      if (nb > 1) next_tot += int64_t(nb) * p.cols * p.cols;
+    }
+    const int np = int(h_off.size());
+    DBuf<int64_t> d_off, d_soff;
+    DBuf<int32_t> d_ld, d_rows, d_cols;
+    DBuf<double> scratch;
+    d_off.alloc(np, mt);
+    d_soff.alloc(np, mt);
+    d_ld.alloc(np, mt);
+    d_rows.alloc(np, mt);
+    d_cols.alloc(np, mt);
+    scratch.alloc(stot + 1, mt);
+    HIF_HIP(hipMemcpyAsync(d_off.p, h_off.data(), sizeof(int64_t) * np, hipMemcpyHostToDevice, s));
+    HIF_HIP(hipMemcpyAsync(d_soff.p, h_soff.data(), sizeof(int64_t) * np, hipMemcpyHostToDevice, s));
+    HIF_HIP(hipMemcpyAsync(d_ld.p, h_ld.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, s));
+    HIF_HIP(hipMemcpyAsync(d_rows.p, h_rows.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, s));
+    HIF_HIP(hipMemcpyAsync(d_cols.p, h_cols.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, s));
+    QrBatch A{};
+    A.base = rbase;
+    A.moff = d_off.p;
+    A.ld = d_ld.p;
+    A.rows = d_rows.p;
+    A.cols = d_cols.p;
+    A.scratch = scratch.p;
+    A.soff = d_soff.p;
+    A.nprob = np;
+    // every block has at most B <= kTsqrSplitRows rows: one TSQR stack
+    launch_qr_batched(A, maxr, maxc, s);
+    // Unsplit problems are done (copied home if they are stacks); split ones
+    // become stacks of their blocks' n x n R factors (lower parts cleared).
+    DBuf<double>& nxt = stack[round & 1];
+    if (next_tot > 0) nxt.alloc(next_tot, mt);
+    std::vector<Prob> next;
+    std::vector<BlockCopy> gather, back;
+    int64_t noff = 0;
+    size_t k = 0;
+    for (size_t i = 0; i < cur.size(); ++i) {
+      const Prob& p = cur[i];
+      const int nb = nblk[i];
+      if (nb == 1) {
+        if (round > 0)
+          back.push_back({rbase + p.off, base + moff[p.orig], p.ld, ld[p.orig], p.cols, p.cols});
+        ++k;
+        continue;
+      }
+      for (int b = 0; b < nb; ++b, ++k)
+        gather.push_back({rbase + h_off[k], nxt.p + noff + int64_t(b) * p.cols * p.cols, p.ld, p.cols, p.cols,
+                          p.cols});
+      next.push_back({noff, p.cols, nb * p.cols, p.cols, p.orig});
+      noff += int64_t(nb) * p.cols * p.cols;
+    }
+    // both copies read this round's buffer, which the round after next
+    // allocates over (stream-ordered)
+    copy_blocks(back, mt, s);
+    copy_blocks(gather, mt, s);
+    cur.swap(next);
+    rbase = nxt.p;
+  }
+}
+
 void launch_lu_batched(const LuBatch& A, int max_r, int max_n, hipStream_t s) {
   if (A.nprob == 0) return;
   // state of the multi-workgroup panel (panels taller than kLpRows)

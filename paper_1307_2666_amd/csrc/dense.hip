@@ -1812,7 +1812,14 @@ void id_batched_impl(double* mats, const int64_t* off, const int32_t* rows, cons
     snn += double(hc[p]) * hc[p];
   }
   const bool direct = id_blocked_fits(batch, max_rows, max_cols) && smn <= 1.25 * snn;
-  if (!direct) launch_rowqr_auto(Q, max_rows, max_cols, s);
+  if (!direct && rowqr_split_fits(max_rows, max_cols)) {
+    std::vector<int64_t> ho(batch);
+    HIF_HIP(hipMemcpyAsync(ho.data(), off, sizeof(int64_t) * batch, hipMemcpyDeviceToHost, s));
+    HIF_HIP(hipStreamSynchronize(s));
+    launch_rowqr_split(mats, ho, hc, hr, hc, nullptr, s);
+  } else if (!direct) {
+    launch_rowqr_auto(Q, max_rows, max_cols, s);
+  }
   IdArgs A;
   A.base = mats;
   A.moff = off;

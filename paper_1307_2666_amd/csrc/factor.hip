@@ -970,7 +970,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   to_host(h_cls_col0, cls_col0.p, NC, s);
   int maxq = 1;
   for (int q = 0; q < NC; ++q) maxq = std::max(maxq, h_cls_n[q]);
-  std::vector<int32_t> h_rows2(NC);
+  std::vector<int32_t> h_rows2(NC), h_rowsm(NC);
   std::vector<int64_t> h_soff(NC);
   int64_t qtot = 0;
   int maxm = 1;
@@ -980,6 +980,7 @@ void Factorizer::sublevel(int lvl, int kind) {
     maxm = std::max<int>(maxm, int(m));
     for (int q = h_cls_first[g]; q < h_cls_first[g + 1]; ++q) {
       const int64_t nq = h_cls_n[q];
+      h_rowsm[q] = int32_t(m);
       h_rows2[q] = int32_t(std::min<int64_t>(m, nq));
       h_soff[q] = qtot;
       if (m > nq) qtot += rowqr_scratch(m, nq);
@@ -1004,7 +1005,9 @@ void Factorizer::sublevel(int lvl, int kind) {
   }
   const bool direct = id_blocked_fits(NC, maxm, maxq) && (rc == 0 || (rc < 0 && smn <= 1.25 * snn));
   const bool blocked_r0 = !direct && id_blocked_fits(NC, maxq, maxq);
-  if (!direct) qr_scratch.ensure(qtot + 1, mt);
+  // problems taller than one TSQR stack: row blocks, then their stacked R factors
+  const bool tall_split = !direct && rowqr_split_fits(maxm, maxq);
+  if (!direct && !tall_split) qr_scratch.ensure(qtot + 1, mt);
   tm.mark(PH_HOST);
   RowQrArgs qa{};
   qa.base = Y.p;
@@ -1015,7 +1018,15 @@ void Factorizer::sublevel(int lvl, int kind) {
   qa.scratch = qr_scratch.p;
   qa.soff = cls_soff.p;
   qa.nprob = NC;
-  if (!direct) launch_rowqr_auto(qa, maxm, maxq, s);
+  if (tall_split) {
+    std::vector<int64_t> h_moff;
+    std::vector<int32_t> h_ld;
+    to_host(h_moff, cls_moff.p, NC, s);
+    to_host(h_ld, cls_ld.p, NC, s);
+    launch_rowqr_split(Y.p, h_moff, h_ld, h_rowsm, h_cls_n, mt, s);
+  } else if (!direct) {
+    launch_rowqr_auto(qa, maxm, maxq, s);
+  }
   tm.mark(PH_QR);
   IdArgs ia{};
   ia.base = Y.p;

@@ -153,6 +153,57 @@ def test_id_batched_large_matches_oracle():
         assert err <= np.sqrt(rd.size) * tol * r00 * 1.01 + 1e-14 * r00
 
 
+def _check_id(Y, tol, unique, sk, rd, T, osk, oT):
+    assert abs(sk.size - osk.size) <= 1, (Y.shape, sk.size, osk.size)
+    assert np.array_equal(np.sort(np.concatenate([sk, rd])), np.arange(Y.shape[1]))
+    assert np.all(np.diff(rd) > 0)
+    if unique:
+        assert np.array_equal(sk, osk)
+        if oT.size:
+            assert np.allclose(T, oT, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(oT).max()))
+    r00 = np.max(np.linalg.norm(Y, axis=0))
+    if rd.size:
+        err = np.linalg.norm(Y[:, rd] - Y[:, sk] @ T)
+        assert err <= np.sqrt(rd.size) * tol * r00 * 1.01 + 1e-14 * r00
+
+
+def test_id_batched_tall_row_blocks_match_oracle():
+    # More than 32768 rows: the row compression cuts each problem into row
+    # blocks (8192 rows here, all problems <= 2048 columns), factors them as
+    # problems of their own, then factors the stack of their R factors; a
+    # short problem in the same batch stays whole.
+    rng = np.random.default_rng(21)
+    cases = []
+    Y = rng.standard_normal((40000, 100)) * (1.06 ** -np.arange(100))[rng.permutation(100)]
+    cases.append((Y, 1e-6, True))
+    x = np.linspace(0, 1, 70000)
+    y = np.linspace(1.5, 2.5, 300)
+    cases.append((np.log(np.abs(x[:, None] - y[None, :])) + 1e-9 * rng.standard_normal((70000, 300)), 1e-7, False))
+    Y = rng.standard_normal((500, 80)) * (1.1 ** -np.arange(80))[rng.permutation(80)]
+    cases.append((Y, 1e-6, True))
+    out = hif.id_batched([torch.tensor(Y) for Y, _, _ in cases], [t for _, t, _ in cases])
+    for (Y, tol, unique), (sk, rd, T) in zip(cases, out):
+        osk, _, oT = interp_decomp(Y, tol)
+        _check_id(Y, tol, unique, sk.numpy(), rd.numpy(), T.numpy(), osk, oT)
+
+
+def test_id_batched_tall_wide_row_blocks_match_oracle():
+    # More than 2048 columns: row blocks of 32768 rows.  Singular values
+    # decay geometrically, so about half the columns are redundant at 1e-6.
+    # The oracle's ID is taken of LAPACK's R factor of Y (same ID: Y = Q R
+    # with Q orthonormal leaves column norms and the pivoted QR unchanged).
+    rng = np.random.default_rng(22)
+    m, n = 36000, 2060
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Y = (rng.standard_normal((m, n)) * 10.0 ** (-12.0 * np.arange(n) / n)) @ Q
+    tol = 1e-6
+    (sk, rd, T), = hif.id_batched([torch.tensor(Y)], [tol])
+    R = np.linalg.qr(Y, mode="r")
+    osk, _, oT = interp_decomp(R, tol)
+    _check_id(Y, tol, False, sk.numpy(), rd.numpy(), T.numpy(), osk, oT)
+    assert 700 <= sk.numel() <= 1500
+
+
 def test_id_batched_many_mid_size_matches_oracle():
     # > 512 problems of 129..256 columns: up to 192 columns the whole pivoted QR
     # runs in registers, larger ones on the one-workgroup kernel; T for both by
