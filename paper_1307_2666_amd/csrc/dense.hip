@@ -645,20 +645,34 @@ __global__ __launch_bounds__(kBqT) void k_bq_piv(IdArgs A, BqState S, int j) {
   double part[kBq];
 #pragma unroll
   for (int jj = 0; jj < kBq; ++jj) part[jj] = 0.0;
+  // The pivot column is a strided gather (one row per cache line): the
+  // gathers of kPivU rows per thread are issued before any of them is used.
+  constexpr int kPivU = 8;
   if (p != INT_MAX)
-    for (int r = i + tid; r < m; r += kBqT) {
-      double x = M[int64_t(r) * ld + p];
-      double vv[kBq];  // all loads first
+    for (int r0 = i + tid; r0 < m; r0 += kBqT * kPivU) {
+      double xs[kPivU];
 #pragma unroll
-      for (int jj = 0; jj < kBq; ++jj) vv[jj] = jj < jb ? V[jj * vld + r] : 0.0;
+      for (int u = 0; u < kPivU; ++u) {
+        const int r = r0 + u * kBqT;
+        xs[u] = r < m ? M[int64_t(r) * ld + p] : 0.0;
+      }
 #pragma unroll
-      for (int jj = 0; jj < kBq; ++jj)
-        if (jj < jb) x -= vv[jj] * sf[jj];
-      V[jb * vld + r] = x;
-      ss += x * x;
-      if (r == i) sx0[0] = x;
+      for (int u = 0; u < kPivU; ++u) {
+        const int r = r0 + u * kBqT;
+        if (r >= m) break;
+        double x = xs[u];
+        double vv[kBq];  // all loads first
 #pragma unroll
-      for (int jj = 0; jj < kBq; ++jj) part[jj] += vv[jj] * x;
+        for (int jj = 0; jj < kBq; ++jj) vv[jj] = jj < jb ? V[jj * vld + r] : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < kBq; ++jj)
+          if (jj < jb) x -= vv[jj] * sf[jj];
+        V[jb * vld + r] = x;
+        ss += x * x;
+        if (r == i) sx0[0] = x;
+#pragma unroll
+        for (int jj = 0; jj < kBq; ++jj) part[jj] += vv[jj] * x;
+      }
     }
   ss = wave_sum(ss);
   if (lane == 0) sss[wv] = ss;
