@@ -101,6 +101,10 @@ typedef struct {
  *                sub-level's problems at most 1.25 times the sum of n^2).
  *                Either way the pivoted QR delays the updates of 32
  *                reflectors; both give the same ID up to rounding.
+ *  fft_matvec:   products with the exact operator inside hif_gmres,
+ *                hif_gmres_T and hif_apply_A: -1 = by FFT convolution when
+ *                the points form the full uniform grid with constant weights
+ *                and self terms (see hif_apply_A), 0 = always pair by pair.
  */
 typedef struct {
   int precision;
@@ -111,6 +115,7 @@ typedef struct {
   double proxy_radius;
   size_t max_bytes;
   int row_compression;
+  int fft_matvec;
 } hif_opts;
 
 #define HIF_MAX_SUBLEVELS 64
@@ -219,6 +224,24 @@ hif_status hif_gmres(hif_handle h, const double* f, double* u, int64_t nrhs, dou
  */
 hif_status hif_gmres_T(hif_handle h, const double* f, double* u, int64_t nrhs, double tol, int32_t maxit,
                        int32_t* iters, double* relres, hif_stream stream);
+
+/*
+ * y = A x (transpose = 0) or y = A^T x (transpose = 1) with the exact
+ * operator of this handle (eqn 1.1 under the discretization of Section 3.1,
+ * from the points and coefficients given to hif_factor; the operator the
+ * hif_gmres refinements use).  When the points are the cell centres of the
+ * full n^d grid on the unit square/cube (any order) with constant weights and
+ * self terms, and opts.fft_matvec allowed it, K is a d-level Toeplitz matrix
+ * and the product runs as a zero-padded FFT convolution of size (2n)^d in
+ * O(n^d log n) (the acceleration the paper uses for its products with A);
+ * otherwise pair by pair as hif_matvec.  Both give the same product up to
+ * rounding.
+ *   x, y:     [nrhs][n] device, must not alias.  nrhs: 1..64.
+ *   used_fft: optional host int, set to 1 if the FFT path ran, else 0.
+ * Stream-ordered (the first call may block while it sets up the FFT).
+ */
+hif_status hif_apply_A(hif_handle h, const double* x, double* y, int64_t nrhs, int transpose, int32_t* used_fft,
+                       hif_stream stream);
 
 /*
  * Gradient with respect to the diagonal coefficient a of eqn 1.1 of a scalar

@@ -37,7 +37,7 @@ class hif_kernel(ctypes.Structure):
 class hif_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("second_kind", ctypes.c_int), ("symmetric", ctypes.c_int),
                 ("variant", ctypes.c_int), ("n_proxy", ctypes.c_int), ("proxy_radius", ctypes.c_double),
-                ("max_bytes", ctypes.c_size_t), ("row_compression", ctypes.c_int)]
+                ("max_bytes", ctypes.c_size_t), ("row_compression", ctypes.c_int), ("fft_matvec", ctypes.c_int)]
 
 
 class hif_stats_t(ctypes.Structure):
@@ -75,6 +75,7 @@ EXPORTS = {
     "hif_gmres": (_INT, [_VP, _VP, _VP, _I64, _DBL, _I32, _VP, _VP, _VP]),
     "hif_gmres_T": (_INT, [_VP, _VP, _VP, _I64, _DBL, _I32, _VP, _VP, _VP]),
     "hif_diag_grad": (_INT, [_VP, _VP, _VP, _I64, _I64, _VP]),
+    "hif_apply_A": (_INT, [_VP, _VP, _VP, _I64, _INT, _VP, _VP]),
 }
 
 
@@ -185,6 +186,20 @@ class Factorization:
                   ctypes.cast(its, _VP), ctypes.cast(rr, _VP), _stream(stream)))
         return U.reshape(f.shape), list(its), list(rr)
 
+    def apply_A(self, x, transpose=False, out=None, stream=None):
+        """``y = A x`` (or ``A^T x``) with the exact operator; returns ``(y, used_fft)``."""
+        if self._h is None:
+            raise RuntimeError("factorization has been freed")
+        x = _dev(x)
+        X = x.reshape(1, -1) if x.dim() == 1 else x
+        if X.shape[-1] != self.n:
+            raise ValueError(f"last dimension must be n = {self.n}")
+        Y = torch.empty_like(X) if out is None else out.reshape(X.shape)
+        used = ctypes.c_int32(0)
+        _check(load_library().hif_apply_A(self._h, _ptr(X), _ptr(Y), X.shape[0], int(bool(transpose)),
+                                          ctypes.byref(used), _stream(stream)))
+        return Y.reshape(x.shape), bool(used.value)
+
     def stats(self) -> dict:
         s = hif_stats_t()
         _check(load_library().hif_stats(self._h, ctypes.byref(s)))
@@ -215,7 +230,7 @@ class Factorization:
 
 def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, selfk=None,
            second_kind=-1, symmetric=-1, variant="hifie", n_proxy=0, proxy_radius=0.0,
-           max_bytes=0, precision=HIF_FP64, row_compression=-1, stream=None) -> Factorization:
+           max_bytes=0, precision=HIF_FP64, row_compression=-1, fft_matvec=-1, stream=None) -> Factorization:
     """``hif_factor``: build ``F ~ A`` for points ``(n, d)`` in the unit box."""
     lib = load_library()
     P = _dev(points)
@@ -234,6 +249,7 @@ def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, s
     o.proxy_radius = proxy_radius
     o.max_bytes = max_bytes
     o.row_compression = row_compression
+    o.fft_matvec = fft_matvec
     handle = ctypes.c_void_p()
     _check(lib.hif_factor(_ptr(P), n, d, ctypes.byref(k), _ptr(av), _ptr(bv), _ptr(cv), float(eps), int(leaf),
                           ctypes.byref(o), _stream(stream), ctypes.byref(handle)))

@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhif.so")
 
-SOURCES = ["api.hip", "factor.hip", "dense.hip", "batched.hip", "sweep.hip", "matvec.hip", "gmres.hip", "prim.hip"]
+SOURCES = ["api.hip", "factor.hip", "dense.hip", "batched.hip", "sweep.hip", "matvec.hip", "gmres.hip", "fftmv.hip",
+           "prim.hip"]
 
 ARCH = "gfx950"
 FLAGS = [
@@ -55,7 +56,8 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(workers) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs,
+           "-lhipfft"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"linking libhif.so failed:\n{res.stderr}")

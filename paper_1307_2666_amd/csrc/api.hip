@@ -163,6 +163,7 @@ hif_status hif_opts_default(hif_opts* o) {
   o->proxy_radius = 0.0;
   o->max_bytes = 0;
   o->row_compression = -1;
+  o->fft_matvec = -1;
   return HIF_OK;
 }
 
@@ -192,6 +193,7 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
   if (o.n_proxy < 0 || o.n_proxy > 8192) return fail(HIF_EINVAL, "opts.n_proxy must be in [0, 8192]");
   if (o.row_compression < -1 || o.row_compression > 1)
     return fail(HIF_EINVAL, "opts.row_compression must be -1, 0 or 1");
+  if (o.fft_matvec != -1 && o.fft_matvec != 0) return fail(HIF_EINVAL, "opts.fft_matvec must be -1 or 0");
   if (!(o.proxy_radius == 0.0 || (std::isfinite(o.proxy_radius) && o.proxy_radius > 0.5)))
     return fail(HIF_EINVAL, "opts.proxy_radius must be 0 (default) or > 0.5 cell widths");
   // second-kind modification by default in FP64 only: in FP32 the SCI-scaled
@@ -291,7 +293,21 @@ void hif_free(hif_handle h) {
   if (!h) return;
   (void)hipDeviceSynchronize();  // the handle may have been used on any stream
   StreamScope scope(nullptr);
+  fft_release(h);
   delete h;
+}
+
+hif_status hif_apply_A(hif_handle h, const double* x, double* y, int64_t nrhs, int transpose, int32_t* used_fft,
+                       hif_stream s) {
+  if (!h) return fail(HIF_EINVAL, "handle is NULL");
+  if (!x || !y) return fail(HIF_EINVAL, "vector pointer is NULL");
+  if (x == y) return fail(HIF_EINVAL, "y must not alias x");
+  if (nrhs < 1 || nrhs > 64) return fail(HIF_EINVAL, "nrhs must be in [1, 64]");
+  if (transpose != 0 && transpose != 1) return fail(HIF_EINVAL, "transpose must be 0 or 1");
+  return guarded(hipStream_t(s), [&] {
+    apply_A_impl(h, x, y, nrhs, transpose == 1, hipStream_t(s));
+    if (used_fft) *used_fft = h->fft_state > 0 ? 1 : 0;
+  });
 }
 
 hif_status hif_id_batched(double* mats, const int64_t* off, const int32_t* rows, const int32_t* cols,

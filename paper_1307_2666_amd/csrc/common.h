@@ -175,6 +175,8 @@ struct SubLevel {
   DBuf<double> darena;
 };
 
+struct FftOp;  // FFT form of the exact operator on a uniform grid (fftmv.hip)
+
 }  // namespace hif
 
 struct hif_factor_s {
@@ -199,6 +201,9 @@ struct hif_factor_s {
   // Sweep scratch.
   hif::DBuf<double> work;
   hif_stats_t stats{};
+  // Exact operator by FFT: 0 not set up yet, 1 ready (fft), -1 not applicable.
+  int fft_state = 0;
+  hif::FftOp* fft = nullptr;
 };
 
 namespace hif {
@@ -303,6 +308,15 @@ void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrh
 // With trans, A^T u = f preconditioned by F^{-T}.
 void gmres_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, double tol, int maxit,
                 int32_t* iters, double* relres, bool trans, hipStream_t s);
+
+// y = A^T x pair by pair (gmres.hip).
+void matvec_T_impl(hif_factor_s* H, const double* x, double* y, int64_t nrhs, hipStream_t s);
+
+// y = A x or A^T x with the handle's exact operator, by FFT convolution when
+// the points form the full uniform grid (fftmv.hip); fft_release frees it.
+void apply_A_impl(hif_factor_s* H, const double* x, double* y, int64_t nrhs, bool trans, hipStream_t s);
+bool fft_ready(hif_factor_s* H, hipStream_t s);
+void fft_release(hif_factor_s* H);
 
 // grad = -sum over right-hand sides of lam (.) u (gmres.hip).
 void diag_grad_impl(const double* lam, const double* u, double* grad, int64_t n, int64_t nrhs, hipStream_t s);

@@ -127,20 +127,8 @@ void gmres_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, doubl
     HIF_HIP(hipMemcpyAsync(out.data(), hbuf.p, sizeof(double) * ne, hipMemcpyDeviceToHost, s));
     HIF_HIP(hipStreamSynchronize(s));
   };
-  DBuf<double> coefT;
-  if (trans) {
-    coefT.alloc(size_t(2) * N, nullptr);
-    hipLaunchKernelGGL(k_transpose_coef, dim3(gN), dim3(kThr), 0, s, H->a, H->b, H->c, H->w, H->selfk, coefT.p,
-                       coefT.p + N, N);
-    HIF_HIP(hipGetLastError());
-  }
   const int pre = trans ? 1 : 0;  // sweep: F^{-1} or F^{-T}
-  auto matvec = [&](const double* x, double* y) {
-    if (trans)
-      matvec_impl(H->pts, N, H->dim, coefT.p, coefT.p + N, H->b, nullptr, 1.0, nullptr, 0.0, x, y, nrhs, s);
-    else
-      matvec_impl(H->pts, N, H->dim, H->a, H->b, H->c, H->w, 0.0, H->selfk, 0.0, x, y, nrhs, s);
-  };
+  auto matvec = [&](const double* x, double* y) { apply_A_impl(H, x, y, nrhs, trans, s); };
 
   // r_0 = f, beta = |f|, v_0 = f / beta
   std::vector<double> nrm;
@@ -242,6 +230,16 @@ void gmres_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, doubl
   if (relres)
     for (int v = 0; v < R; ++v) relres[v] = beta[v] > 0.0 ? std::sqrt(nrm[v]) / beta[v] : 0.0;
   HIF_HIP(hipStreamSynchronize(s));
+}
+
+void matvec_T_impl(hif_factor_s* H, const double* x, double* y, int64_t nrhs, hipStream_t s) {
+  const int64_t N = H->n;
+  DBuf<double> coefT;
+  coefT.alloc(size_t(2) * N, nullptr);
+  hipLaunchKernelGGL(k_transpose_coef, dim3(grid_for(N)), dim3(kThr), 0, s, H->a, H->b, H->c, H->w, H->selfk,
+                     coefT.p, coefT.p + N, N);
+  HIF_HIP(hipGetLastError());
+  matvec_impl(H->pts, N, H->dim, coefT.p, coefT.p + N, H->b, nullptr, 1.0, nullptr, 0.0, x, y, nrhs, s);
 }
 
 void diag_grad_impl(const double* lam, const double* u, double* grad, int64_t n, int64_t nrhs, hipStream_t s) {

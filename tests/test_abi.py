@@ -100,6 +100,18 @@ def test_gmres_rejects_bad_arguments():
     assert b"handle" in lib.hif_last_error()
 
 
+def test_apply_A_rejects_bad_arguments():
+    lib = hif.load_library()
+    x, y = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    assert lib.hif_apply_A(None, x, y, 1, 0, None, None) == B.HIF_EINVAL
+    assert b"handle" in lib.hif_last_error()
+    o = hif.default_opts()
+    assert o.fft_matvec == -1
+    o.fft_matvec = 2
+    st, msg, _ = _factor_raw(opts=o)
+    assert st == B.HIF_EINVAL and "fft_matvec" in msg
+
+
 def test_diag_grad_rejects_bad_arguments():
     lib = hif.load_library()
     x, y, z = (ctypes.c_void_p(0x1000 * k) for k in (1, 2, 3))

@@ -378,6 +378,64 @@ def test_factor_errors():
     assert e.value.status == -2
 
 
+@pytest.mark.parametrize("n,d,shuffle", [(64, 2, False), (48, 2, True), (16, 3, True)])
+def test_apply_A_fft_matches_matvec_and_dense(n, d, shuffle):
+    # On the full uniform grid (any point order) the exact operator runs as an
+    # FFT convolution: same product as the pair-by-pair matvec and dense A,
+    # for A and A^T, with non-symmetric b, c and a varying a.
+    rng = np.random.default_rng(30 + n)
+    pts = grid_points(n, d)
+    if shuffle:
+        pts = pts[rng.permutation(pts.shape[0])]
+    N = pts.shape[0]
+    a = 1.0 + rng.uniform(size=N)
+    b = 1.0 + 0.5 * rng.uniform(size=N)
+    c = 1.0 + 0.5 * rng.uniform(size=N)
+    op = Operator.uniform(pts, 1.0 / n, a=a, b=b, c=c)
+    F = hif.factor(_t(pts), 1e-3, 64, a=_t(a), b=_t(b), c=_t(c), h=1.0 / n)
+    x = rng.standard_normal((2, N))
+    y, fft = F.apply_A(_t(x))
+    yT, fftT = F.apply_A(_t(x), transpose=True)
+    assert fft and fftT
+    A = op.dense()
+    ref = x @ A.T
+    refT = x @ A
+    assert np.linalg.norm(_np(y) - ref) <= 1e-13 * np.linalg.norm(ref)
+    assert np.linalg.norm(_np(yT) - refT) <= 1e-13 * np.linalg.norm(refT)
+    ym = _np(hif.matvec(_t(pts), _t(x), a=_t(a), b=_t(b), c=_t(c), h=1.0 / n))
+    assert np.linalg.norm(_np(y) - ym) <= 1e-13 * np.linalg.norm(ym)
+    G = hif.factor(_t(pts), 1e-3, 64, a=_t(a), b=_t(b), c=_t(c), h=1.0 / n, fft_matvec=0)
+    y0, fft0 = G.apply_A(_t(x))
+    assert not fft0
+    assert np.linalg.norm(_np(y0) - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_apply_A_off_grid_runs_pair_by_pair():
+    # points shifted off the cell centres: no Toeplitz structure to use
+    rng = np.random.default_rng(41)
+    pts = grid_points(48, 2) + 0.2 / 48
+    op = Operator.uniform(pts, 1.0 / 48, a=np.ones(pts.shape[0]))
+    F = hif.factor(_t(pts), 1e-6, 64, a=_t(op.a), h=1.0 / 48)
+    x = rng.standard_normal(pts.shape[0])
+    y, fft = F.apply_A(_t(x))
+    assert not fft
+    ref = op.dense() @ x
+    assert np.linalg.norm(_np(y) - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_apply_A_fft_sq512_matches_matvec():
+    wl = workload("sq512")
+    P = _t(wl.points())
+    a = torch.ones(wl.N, dtype=torch.float64, device=DEV)
+    F = hif.factor(P, 1e-3, wl.leaf, a=a, h=wl.h)
+    X = _t(wl.rhs())
+    y, fft = F.apply_A(X)
+    assert fft
+    ym = hif.matvec(P, X, a=a, h=wl.h)
+    err = (torch.linalg.norm(y - ym, dim=1) / torch.linalg.norm(ym, dim=1)).max().item()
+    assert err <= 1e-13, err
+
+
 def test_gmres_with_gpu_preconditioner():
     # Right-preconditioned GMRES with F_gpu^{-1} against the exact on-the-fly
     # matvec reaches 1e-10 in a few iterations (Lemma 5.1), plain hifie2 (x off).
