@@ -15,6 +15,7 @@
 #include <cmath>
 #include <map>
 #include <memory>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -27,13 +28,6 @@ struct FftOp {
   int64_t Mh = 0;  // (2n)^(d-1) (n + 1) complex points of its half spectrum
   DBuf<int64_t> gidx;           // padded-grid position of every point
   DBuf<hipfftDoubleComplex> kh; // spectrum of the kernel array
-  std::map<int, std::pair<hipfftHandle, hipfftHandle>> plans;  // by batch: D2Z, Z2D
-  ~FftOp() {
-    for (auto& kv : plans) {
-      hipfftDestroy(kv.second.first);
-      hipfftDestroy(kv.second.second);
-    }
-  }
 };
 
 namespace {
@@ -45,6 +39,28 @@ unsigned grid1(int64_t n) { return unsigned(std::min<int64_t>(4096, (n + kThr - 
 void fft_check(hipfftResult r, const char* what) {
   if (r != HIPFFT_SUCCESS)
     throw Error{HIF_EDEVICE, std::string("hipFFT ") + what + " failed (" + std::to_string(int(r)) + ")"};
+}
+
+// Plans by (device, stream, dimension, size, batch, direction), per host
+// thread: creating a plan costs milliseconds, and a plan's work area must not
+// be shared by transforms that may run concurrently (other threads or
+// streams).  Kept for the life of the process.
+hipfftHandle cached_plan(int d, int n2, int batch, hipfftType type, hipStream_t s) {
+  using Key = std::tuple<int, hipStream_t, int, int, int, int>;
+  thread_local std::map<Key, hipfftHandle>* cache = new std::map<Key, hipfftHandle>();
+  int dev = 0;
+  HIF_HIP(hipGetDevice(&dev));
+  const Key key{dev, s, d, n2, batch, int(type)};
+  auto it = cache->find(key);
+  if (it != cache->end()) return it->second;
+  int dims[3] = {n2, n2, n2};
+  hipfftHandle p;
+  fft_check(hipfftPlanMany(&p, d, dims, nullptr, 1, 0, nullptr, 1, 0, type, batch), "plan");
+  const hipfftResult r = hipfftSetStream(p, s);
+  if (r != HIPFFT_SUCCESS) hipfftDestroy(p);
+  fft_check(r, "set stream");
+  cache->emplace(key, p);
+  return p;
 }
 
 // Kernel array over the padded grid: index o per dimension, offset o or
@@ -107,43 +123,43 @@ __global__ void k_fft_gather(const double* x, const double* a, const double* r, 
     y[v * N + i] = a[i] * x[v * N + i] + r[i] * (P[v * M + gidx[i]] * inv);
 }
 
-// Padded-grid positions of the points when they are the cell centres of the
-// full n^d grid (each cell once) and w, s are constant; else an empty vector.
-std::vector<int64_t> grid_positions(hif_factor_s* H, int& n_out, hipStream_t s) {
-  const int64_t N = H->n;
-  const int D = H->dim;
-  const int n = int(std::llround(std::pow(double(N), 1.0 / D)));
-  int64_t nd = 1;
-  for (int k = 0; k < D; ++k) nd *= n;
-  if (n < 1 || nd != N) return {};
-  std::vector<double> pts(size_t(N) * D), w(N), sf(N);
-  HIF_HIP(hipMemcpyAsync(pts.data(), H->pts, sizeof(double) * N * D, hipMemcpyDeviceToHost, s));
-  HIF_HIP(hipMemcpyAsync(w.data(), H->w, sizeof(double) * N, hipMemcpyDeviceToHost, s));
-  HIF_HIP(hipMemcpyAsync(sf.data(), H->selfk, sizeof(double) * N, hipMemcpyDeviceToHost, s));
-  HIF_HIP(hipStreamSynchronize(s));
-  for (int64_t i = 1; i < N; ++i)
-    if (w[i] != w[0] || sf[i] != sf[0]) return {};
-  const double h = 1.0 / n;
+// Grid cell of every point if it is a cell centre of the n^d grid with the
+// weight and self term of point 0 (else *bad = 1): owner[cell] = i, and the
+// padded-grid position in gidx.
+template <int D>
+__global__ void k_fft_locate(const double* pts, const double* w, const double* sf, int64_t N, int n,
+                             int32_t* owner, int64_t* cell_of, int64_t* gidx, int* bad) {
+  const double h = 1.0 / n, w0 = w[0], s0 = sf[0];
   const int64_t n2 = 2 * int64_t(n);
-  std::vector<int64_t> pos(N);
-  std::vector<uint8_t> seen(N, 0);
-  for (int64_t i = 0; i < N; ++i) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    bool ok = w[i] == w0 && sf[i] == s0;
     int64_t cell = 0, padded = 0, mul = 1, pmul = 1;
+#pragma unroll
     for (int k = 0; k < D; ++k) {
       const double t = pts[i * D + k] / h - 0.5;
-      const long g = std::lround(t);
-      if (g < 0 || g >= n || std::fabs(t - double(g)) > 1e-9) return {};
-      cell += g * mul;
-      padded += g * pmul;
+      const double g = rint(t);
+      ok = ok && g >= 0.0 && g < double(n) && fabs(t - g) <= 1e-9;
+      const int64_t gi = ok ? int64_t(g) : 0;
+      cell += gi * mul;
+      padded += gi * pmul;
       mul *= n;
       pmul *= n2;
     }
-    if (seen[cell]) return {};
-    seen[cell] = 1;
-    pos[i] = padded;
+    if (!ok) *bad = 1;
+    cell_of[i] = cell;
+    gidx[i] = padded;
+    if (ok) owner[cell] = int32_t(i);
   }
-  n_out = n;
-  return pos;
+}
+
+// Two points in one cell: one of them does not own it.
+__global__ void k_fft_unique(const int32_t* owner, const int64_t* cell_of, int64_t N, int* bad) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x)
+    if (owner[cell_of[i]] != int32_t(i)) *bad = 1;
+}
+
+__global__ void k_fft_flag_init(int* bad) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *bad = 0;
 }
 
 }  // namespace
@@ -152,17 +168,39 @@ bool fft_ready(hif_factor_s* H, hipStream_t s) {
   if (H->fft_state != 0) return H->fft_state > 0;
   H->fft_state = -1;
   if (H->opts.fft_matvec == 0) return false;
-  int n = 0;
-  std::vector<int64_t> pos = grid_positions(H, n, s);
-  if (pos.empty()) return false;
+  const int64_t N = H->n;
+  const int n = int(std::llround(std::pow(double(N), 1.0 / H->dim)));
+  int64_t nd = 1;
+  for (int k = 0; k < H->dim; ++k) nd *= n;
+  if (n < 1 || nd != N) return false;
   auto F = std::make_unique<FftOp>();
   F->n = n;
   F->d = H->dim;
   const int64_t n2 = 2 * int64_t(n);
   F->M = H->dim == 2 ? n2 * n2 : n2 * n2 * n2;
   F->Mh = (H->dim == 2 ? n2 : n2 * n2) * (int64_t(n) + 1);
-  F->gidx.alloc(pos.size(), &H->mem);
-  HIF_HIP(hipMemcpyAsync(F->gidx.p, pos.data(), sizeof(int64_t) * pos.size(), hipMemcpyHostToDevice, s));
+  F->gidx.alloc(N, &H->mem);
+  {
+    DBuf<int32_t> owner;
+    DBuf<int64_t> cell_of;
+    DBuf<int> bad;
+    owner.alloc(N, nullptr);
+    cell_of.alloc(N, nullptr);
+    bad.alloc(1, nullptr);
+    hipLaunchKernelGGL(k_fft_flag_init, dim3(1), dim3(64), 0, s, bad.p);
+    if (H->dim == 2)
+      hipLaunchKernelGGL(k_fft_locate<2>, dim3(grid1(N)), dim3(kThr), 0, s, H->pts, H->w, H->selfk, N, n, owner.p,
+                         cell_of.p, F->gidx.p, bad.p);
+    else
+      hipLaunchKernelGGL(k_fft_locate<3>, dim3(grid1(N)), dim3(kThr), 0, s, H->pts, H->w, H->selfk, N, n, owner.p,
+                         cell_of.p, F->gidx.p, bad.p);
+    hipLaunchKernelGGL(k_fft_unique, dim3(grid1(N)), dim3(kThr), 0, s, owner.p, cell_of.p, N, bad.p);
+    HIF_HIP(hipGetLastError());
+    int hb = 1;
+    HIF_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIF_HIP(hipStreamSynchronize(s));
+    if (hb) return false;
+  }
   double w0 = 0.0, s0 = 0.0;
   HIF_HIP(hipMemcpyAsync(&w0, H->w, sizeof(double), hipMemcpyDeviceToHost, s));
   HIF_HIP(hipMemcpyAsync(&s0, H->selfk, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -176,15 +214,7 @@ bool fft_ready(hif_factor_s* H, hipStream_t s) {
     hipLaunchKernelGGL(k_fft_kernel_array<3>, dim3(grid1(F->M)), dim3(kThr), 0, s, kr.p, n, h, w0, s0);
   HIF_HIP(hipGetLastError());
   F->kh.alloc(F->Mh, &H->mem);
-  hipfftHandle p;
-  int dims[3] = {int(n2), int(n2), int(n2)};
-  fft_check(hipfftPlanMany(&p, H->dim, dims, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_D2Z, 1), "plan");
-  fft_check(hipfftSetStream(p, s), "set stream");
-  const hipfftResult r = hipfftExecD2Z(p, kr.p, F->kh.p);
-  const hipError_t e = hipStreamSynchronize(s);  // the plan's work area is in use until then
-  hipfftDestroy(p);
-  fft_check(r, "kernel transform");
-  HIF_HIP(e);
+  fft_check(hipfftExecD2Z(cached_plan(H->dim, int(n2), 1, HIPFFT_D2Z, s), kr.p, F->kh.p), "kernel transform");
   H->fft = F.release();
   H->fft_state = 1;
   return true;
@@ -198,17 +228,8 @@ void fft_release(hif_factor_s* H) {
 void fft_apply(hif_factor_s* H, const double* x, double* y, int64_t nrhs, bool trans, hipStream_t s) {
   FftOp& F = *H->fft;
   const int nb = int(nrhs);
-  auto it = F.plans.find(nb);
-  if (it == F.plans.end()) {
-    const int n2 = 2 * F.n;
-    int dims[3] = {n2, n2, n2};
-    hipfftHandle pf, pi;
-    fft_check(hipfftPlanMany(&pf, F.d, dims, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_D2Z, nb), "plan");
-    const hipfftResult r = hipfftPlanMany(&pi, F.d, dims, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_Z2D, nb);
-    if (r != HIPFFT_SUCCESS) hipfftDestroy(pf);
-    fft_check(r, "plan");
-    it = F.plans.emplace(nb, std::make_pair(pf, pi)).first;
-  }
+  const hipfftHandle pf = cached_plan(F.d, 2 * F.n, nb, HIPFFT_D2Z, s);
+  const hipfftHandle pi = cached_plan(F.d, 2 * F.n, nb, HIPFFT_Z2D, s);
   const int64_t N = H->n;
   DBuf<double> P;
   DBuf<hipfftDoubleComplex> S;
@@ -220,12 +241,10 @@ void fft_apply(hif_factor_s* H, const double* x, double* y, int64_t nrhs, bool t
   hipLaunchKernelGGL(k_fft_zero, dim3(grid1(int64_t(nb) * F.M)), dim3(kThr), 0, s, P.p, int64_t(nb) * F.M);
   hipLaunchKernelGGL(k_fft_scatter, dim3(grid1(N), nb), dim3(kThr), 0, s, x, pre, F.gidx.p, P.p, N, F.M);
   HIF_HIP(hipGetLastError());
-  fft_check(hipfftSetStream(it->second.first, s), "set stream");
-  fft_check(hipfftExecD2Z(it->second.first, P.p, S.p), "forward transform");
+  fft_check(hipfftExecD2Z(pf, P.p, S.p), "forward transform");
   hipLaunchKernelGGL(k_fft_mul, dim3(grid1(F.Mh), nb), dim3(kThr), 0, s, S.p, F.kh.p, F.Mh);
   HIF_HIP(hipGetLastError());
-  fft_check(hipfftSetStream(it->second.second, s), "set stream");
-  fft_check(hipfftExecZ2D(it->second.second, S.p, P.p), "inverse transform");
+  fft_check(hipfftExecZ2D(pi, S.p, P.p), "inverse transform");
   hipLaunchKernelGGL(k_fft_gather, dim3(grid1(N), nb), dim3(kThr), 0, s, x, H->a, post, F.gidx.p, P.p, y, N, F.M,
                      1.0 / double(F.M));
   HIF_HIP(hipGetLastError());
