@@ -478,6 +478,31 @@ def test_gmres_native_matches_dense_solve(second_kind):
         assert abs(its[v] - it_o) <= 1, (its, it_o)
 
 
+def _golden_ni():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tables2_11_first_kind_ni.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    return {(int(d), int(n), float(e)): int(ni) for d, n, e, ni in rows}
+
+
+@pytest.mark.parametrize("d,n,eps", [(2, 512, 1e-3), (2, 512, 1e-6), (2, 512, 1e-9), (3, 32, 1e-3), (3, 32, 1e-6)])
+def test_first_kind_gmres_iterations_match_paper(d, n, eps):
+    # First kind (a = 0): F^{-1} preconditions GMRES to 1e-12 in about the
+    # number of iterations of the paper's Tables 2 and 11 (the paper's leaf
+    # sizes differ, so a difference of up to 2 iterations is allowed).
+    paper = _golden_ni()[(d, n, eps)]
+    P = _t(grid_points(n, d))
+    N = P.shape[0]
+    a = torch.zeros(N, dtype=torch.float64, device=DEV)
+    f = _t(np.random.default_rng(9).uniform(0.0, 1.0, N))
+    F = hif.factor(P, eps, 64, a=a, h=1.0 / n, second_kind=0)
+    u, its, rr = F.gmres(f, tol=1e-12, maxit=60)
+    y, _ = F.apply_A(u)
+    res = (torch.linalg.norm(y - f) / torch.linalg.norm(f)).item()
+    assert rr[0] <= 1.5e-12 and res <= 1.5e-12, (rr, res)
+    assert abs(its[0] - paper) <= 2, (its, paper)
+
+
 def test_gmres_native_zero_rhs_and_single_iteration():
     op = _op(32, 2)
     F = _gpu_factor(op, 1e-6, 16)
