@@ -261,6 +261,37 @@ hif_status hif_diag_grad(const double* lambda, const double* u, double* grad, in
 /* Copy the statistics of a factorization into *out (host memory). */
 hif_status hif_stats(hif_handle h, hif_stats_t* out);
 
+/*
+ * One problem of hif_factor_batch: the arguments of hif_factor for it.
+ */
+typedef struct {
+  const double* points;
+  int64_t n;
+  int dim;
+  hif_kernel kernel;
+  const double *a, *b, *c;
+  double eps;
+  int32_t leaf;
+} hif_problem;
+
+/*
+ * Factor independent problems concurrently (each as hif_factor would, with
+ * the same opts): nworkers host threads (1..16), each with a HIP stream of
+ * its own, take the problems largest first, so that small factorizations,
+ * whose launches cannot fill the GPU one at a time, overlap on the device.
+ * The paper factors one operator at a time; its sub-levels are independent
+ * across problems as they are across groups (Section 4).
+ *   problems: [count] host array; the arrays it points to are device arrays
+ *             as for hif_factor and must stay valid until the call returns.
+ *   out:      [count] host array of handles (NULL where a problem failed).
+ *   status:   optional [count] host array of per-problem statuses.
+ * Blocks until every factorization's device work is done; the handles then
+ * serve any stream.  Returns HIF_OK, or the first failing problem's status
+ * (hif_last_error names the problem); the other handles are still valid.
+ */
+hif_status hif_factor_batch(const hif_problem* problems, int32_t count, const hif_opts* opts, int32_t nworkers,
+                            hif_handle* out, hif_status* status);
+
 /* Release a handle and all its device memory (NULL is a no-op). */
 void hif_free(hif_handle h);
 

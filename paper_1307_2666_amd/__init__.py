@@ -7,8 +7,9 @@ Algorithm 3.1); the returned handle applies ``F``, ``F^T``, ``F^{-1}``,
 the solve as a differentiable function of ``a`` and ``f``.
 """
 from ._binding import (EXPORTS, HIF_FP32_MIXED, HIF_FP64, Factorization, HifError, LIB_PATH,  # noqa: F401
-                       default_opts, diag_grad, factor, id_batched, load_library, matvec, partition)
+                       default_opts, diag_grad, factor, factor_batch, id_batched, load_library, matvec,
+                       partition)
 from . import diff  # noqa: F401
 
-__all__ = ["factor", "matvec", "id_batched", "partition", "diag_grad", "diff", "Factorization", "HifError",
+__all__ = ["factor", "factor_batch", "matvec", "id_batched", "partition", "diag_grad", "diff", "Factorization", "HifError",
            "load_library", "default_opts", "LIB_PATH", "EXPORTS"]

@@ -40,6 +40,12 @@ class hif_opts(ctypes.Structure):
                 ("max_bytes", ctypes.c_size_t), ("row_compression", ctypes.c_int), ("fft_matvec", ctypes.c_int)]
 
 
+class hif_problem(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("dim", ctypes.c_int), ("kernel", hif_kernel),
+                ("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("c", ctypes.c_void_p), ("eps", ctypes.c_double),
+                ("leaf", ctypes.c_int32)]
+
+
 class hif_stats_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("n_sublevels", ctypes.c_int32), ("top_size", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
@@ -76,6 +82,7 @@ EXPORTS = {
     "hif_gmres_T": (_INT, [_VP, _VP, _VP, _I64, _DBL, _I32, _VP, _VP, _VP]),
     "hif_diag_grad": (_INT, [_VP, _VP, _VP, _I64, _I64, _VP]),
     "hif_apply_A": (_INT, [_VP, _VP, _VP, _I64, _INT, _VP, _VP]),
+    "hif_factor_batch": (_INT, [_VP, _I32, _VP, _I32, _VP, _VP]),
 }
 
 
@@ -254,6 +261,50 @@ def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, s
     _check(lib.hif_factor(_ptr(P), n, d, ctypes.byref(k), _ptr(av), _ptr(bv), _ptr(cv), float(eps), int(leaf),
                           ctypes.byref(o), _stream(stream), ctypes.byref(handle)))
     return Factorization(handle, n, d, None)
+
+
+def factor_batch(problems, *, nworkers=4, precision=HIF_FP64, second_kind=-1, symmetric=-1, variant="hifie",
+                 max_bytes=0, row_compression=-1, fft_matvec=-1):
+    """``hif_factor_batch``: factor independent problems concurrently.
+
+    ``problems`` is a list of dicts with the ``factor`` arguments ``points``, ``eps``,
+    ``leaf`` and optionally ``a``, ``b``, ``c``, ``h``, ``weights``, ``selfk``.  Returns
+    ``(factorizations, statuses)``; a failed problem's entry is ``None``."""
+    lib = load_library()
+    cnt = len(problems)
+    arr = (hif_problem * max(cnt, 1))()
+    keep = []
+    for i, pr in enumerate(problems):
+        P = _dev(pr["points"])
+        if P.dim() != 2 or P.shape[1] not in (2, 3):
+            raise ValueError("points must be (n, 2) or (n, 3)")
+        n, d = P.shape
+        av, bv, cv = (_dev(pr.get(k), n, k) for k in ("a", "b", "c"))
+        wv, sv = _dev(pr.get("weights"), n, "weights"), _dev(pr.get("selfk"), n, "selfk")
+        keep += [P, av, bv, cv, wv, sv]
+        arr[i] = hif_problem(_ptr(P), n, d, _kernel(pr.get("h"), wv, sv), _ptr(av), _ptr(bv), _ptr(cv),
+                             float(pr["eps"]), int(pr["leaf"]))
+    o = default_opts()
+    o.precision = precision
+    o.second_kind = second_kind
+    o.symmetric = symmetric
+    o.variant = HIF_VARIANT_RSF if variant == "rskel" else HIF_VARIANT_HIFIE
+    o.max_bytes = max_bytes
+    o.row_compression = row_compression
+    o.fft_matvec = fft_matvec
+    handles = (ctypes.c_void_p * max(cnt, 1))()
+    status = (ctypes.c_int * max(cnt, 1))()
+    torch.cuda.synchronize()  # the inputs were written on torch's stream
+    lib.hif_factor_batch(ctypes.cast(arr, _VP), cnt, ctypes.byref(o), int(nworkers), ctypes.cast(handles, _VP),
+                         ctypes.cast(status, _VP))
+    facs = []
+    for i in range(cnt):
+        if handles[i]:
+            n, d = arr[i].n, arr[i].dim
+            facs.append(Factorization(ctypes.c_void_p(handles[i]), n, d, None))
+        else:
+            facs.append(None)
+    return facs, list(status[:cnt])
 
 
 def matvec(points, x, *, a=None, b=None, c=None, h=None, weights=None, selfk=None, out=None, stream=None):

@@ -1,5 +1,7 @@
 // C ABI entry points (include/hif.h): argument checks on the host, handle
 // lifecycle, error mapping.  No exception crosses the ABI.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -7,6 +9,9 @@
 #include <mutex>
 #include <new>
 #include <set>
+#include <string>
+#include <thread>
+#include <vector>
 
 #include "common.h"
 
@@ -108,6 +113,22 @@ void dbuf_trim() {
   hipMemPool_t pool;
   if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
   (void)hipGetLastError();
+}
+
+void dbuf_drop_stream(hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  DbufCache& c = dbuf_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (auto it = c.blocks.begin(); it != c.blocks.end();) {
+    if (it->first.dev == dev && it->first.s == s) {
+      (void)hipFreeAsync(it->second, s);
+      c.bytes -= it->first.cls;
+      it = c.blocks.erase(it);
+    } else {
+      ++it;
+    }
+  }
 }
 
 bool dbuf_give(void* p, size_t cls, hipStream_t s) {
@@ -215,6 +236,79 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
   });
   if (st == HIF_OK) *out = H;
   return st;
+}
+
+hif_status hif_factor_batch(const hif_problem* problems, int32_t count, const hif_opts* opts, int32_t nworkers,
+                            hif_handle* out, hif_status* status) {
+  if (count < 0) return fail(HIF_EINVAL, "count must be >= 0");
+  if (count > 0 && (!problems || !out)) return fail(HIF_EINVAL, "problems and out must not be NULL");
+  if (nworkers < 1 || nworkers > 16) return fail(HIF_EINVAL, "nworkers must be in [1, 16]");
+  for (int32_t p = 0; p < count; ++p) {
+    out[p] = nullptr;
+    if (status) status[p] = HIF_OK;
+  }
+  if (count == 0) return HIF_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(HIF_EDEVICE, "no current HIP device");
+  // largest problems first, so that the last ones to start are short
+  std::vector<int32_t> order(count);
+  for (int32_t p = 0; p < count; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return problems[x].n > problems[y].n; });
+  std::vector<hif_status> st(count, HIF_OK);
+  std::vector<std::string> msg(count);
+  std::atomic<int32_t> next{0};
+  std::atomic<int> setup_failed{0};
+  auto work = [&]() {
+    if (hipSetDevice(dev) != hipSuccess) {
+      setup_failed = 1;
+      return;
+    }
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      setup_failed = 1;
+      return;
+    }
+    for (;;) {
+      const int32_t i = next++;
+      if (i >= count) break;
+      const int32_t p = order[i];
+      const hif_problem& q = problems[p];
+      hif_handle h = nullptr;
+      st[p] = hif_factor(q.points, q.n, q.dim, &q.kernel, q.a, q.b, q.c, q.eps, q.leaf, opts, s, &h);
+      if (st[p] != HIF_OK) msg[p] = g_last_error;
+      out[p] = h;
+    }
+    // every handle's device work is complete when the batch returns; the
+    // thread's streams and the blocks cached for them go back to the device
+    (void)hipStreamSynchronize(s);
+    release_thread_streams();
+    dbuf_drop_stream(s);
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  };
+  {
+    std::vector<std::thread> pool;
+    const int nw = std::min<int>(nworkers, count);
+    for (int w = 0; w < nw; ++w) pool.emplace_back(work);
+    for (auto& t : pool) t.join();
+  }
+  if (setup_failed) {
+    for (int32_t p = 0; p < count; ++p)
+      if (out[p] == nullptr && st[p] == HIF_OK) st[p] = HIF_EDEVICE;
+  }
+  hif_status first = HIF_OK;
+  std::string first_msg;
+  for (int32_t p = 0; p < count; ++p) {
+    if (status) status[p] = st[p];
+    if (st[p] != HIF_OK && first == HIF_OK) {
+      first = st[p];
+      first_msg = "problem " + std::to_string(p) + ": " + (msg[p].empty() ? "worker setup failed" : msg[p]);
+    }
+  }
+  if (first != HIF_OK) return fail(first, first_msg);
+  g_last_error.clear();
+  return HIF_OK;
 }
 
 static hif_status sweep(hif_handle h, int op, const double* x, double* y, int64_t nrhs, hif_stream s) {

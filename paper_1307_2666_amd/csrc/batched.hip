@@ -1226,9 +1226,15 @@ __global__ __launch_bounds__(256) void k_gemm_tiles(const GemmDesc* D, int nd) {
 
 // Second stream of the row compression's look-ahead, one per host thread and
 // device, created on first use and kept for the life of the thread (creating
-// and destroying it per call costs a host wait on its work each time).
-static hipStream_t aux_stream() {
+// and destroying it per call costs a host wait on its work each time), or
+// until release_thread_streams.
+static std::map<int, hipStream_t>& aux_streams() {
   thread_local std::map<int, hipStream_t> streams;
+  return streams;
+}
+
+static hipStream_t aux_stream() {
+  std::map<int, hipStream_t>& streams = aux_streams();
   int dev = 0;
   HIF_HIP(hipGetDevice(&dev));
   auto it = streams.find(dev);
@@ -1237,6 +1243,19 @@ static hipStream_t aux_stream() {
   HIF_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
   streams[dev] = s2;
   return s2;
+}
+
+void release_thread_streams() {
+  std::map<int, hipStream_t>& streams = aux_streams();
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto& kv : streams) {
+    (void)hipSetDevice(kv.first);
+    (void)hipStreamSynchronize(kv.second);
+    (void)hipStreamDestroy(kv.second);
+  }
+  streams.clear();
+  (void)hipSetDevice(cur);
 }
 
 void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t s) {

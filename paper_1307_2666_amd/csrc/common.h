@@ -309,6 +309,11 @@ void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrh
 void gmres_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, double tol, int maxit,
                 int32_t* iters, double* relres, bool trans, hipStream_t s);
 
+// Batch workers: destroy the calling thread's look-ahead streams
+// (batched.hip) and free the blocks cached for a stream (api.hip).
+void release_thread_streams();
+void dbuf_drop_stream(hipStream_t s);
+
 // y = A^T x pair by pair (gmres.hip).
 void matvec_T_impl(hif_factor_s* H, const double* x, double* y, int64_t nrhs, hipStream_t s);
 

@@ -112,6 +112,18 @@ def test_apply_A_rejects_bad_arguments():
     assert st == B.HIF_EINVAL and "fft_matvec" in msg
 
 
+def test_factor_batch_rejects_bad_arguments():
+    lib = hif.load_library()
+    h = ctypes.c_void_p(0x1000)
+    assert lib.hif_factor_batch(None, 0, None, 4, None, None) == B.HIF_OK  # empty batch
+    assert lib.hif_factor_batch(None, -1, None, 4, None, None) == B.HIF_EINVAL
+    assert lib.hif_factor_batch(None, 2, None, 4, h, None) == B.HIF_EINVAL
+    probs = (B.hif_problem * 1)()
+    assert lib.hif_factor_batch(ctypes.cast(probs, ctypes.c_void_p), 1, None, 0, h, None) == B.HIF_EINVAL
+    assert b"nworkers" in lib.hif_last_error()
+    assert lib.hif_factor_batch(ctypes.cast(probs, ctypes.c_void_p), 1, None, 17, h, None) == B.HIF_EINVAL
+
+
 def test_diag_grad_rejects_bad_arguments():
     lib = hif.load_library()
     x, y, z = (ctypes.c_void_p(0x1000 * k) for k in (1, 2, 3))

@@ -541,6 +541,37 @@ def test_factor_sizes_match_paper_tables_3_12(d, n, eps):
     assert tops["hifie"] < tops["hifie_x"] < tops["rskelf"]
 
 
+def test_factor_batch_matches_single_factorizations():
+    # Independent problems of uneven sizes and leaves factored concurrently on
+    # 3 worker streams give the same factorizations as one at a time; a
+    # problem with coincident points fails alone, reported at its index.
+    rng = np.random.default_rng(51)
+    specs = [(32, 64), (48, 36), (24, 36), (64, 64), (40, 64), (16, 64), (56, 64)]
+    probs = []
+    for n, leaf in specs:
+        pts = grid_points(n, 2)
+        probs.append(dict(points=_t(pts), a=_t(1.0 + rng.uniform(size=n * n)), h=1.0 / n, eps=1e-6, leaf=leaf))
+    bad = grid_points(16, 2)
+    bad[5] = bad[6]
+    probs.insert(3, dict(points=_t(bad), h=1.0 / 16, eps=1e-6, leaf=64))
+    facs, status = hif.factor_batch(probs, nworkers=3)
+    assert status[3] == -1 and facs[3] is None
+    for i, pr in enumerate(probs):
+        if i == 3:
+            continue
+        assert status[i] == 0 and facs[i] is not None
+        N = pr["points"].shape[0]
+        f = _t(rng.standard_normal((2, N)))
+        G = hif.factor(pr["points"], pr["eps"], pr["leaf"], a=pr["a"], h=pr["h"])
+        u_b, u_s = facs[i].solve(f), G.solve(f)
+        assert torch.equal(u_b, u_s), i
+        assert facs[i].stats()["top_size"] == G.stats()["top_size"]
+        y, _ = facs[i].apply_A(u_b)
+        assert (torch.linalg.norm(y - f) / torch.linalg.norm(f)).item() <= 1e-5
+        G.free()
+        facs[i].free()
+
+
 def test_gmres_native_zero_rhs_and_single_iteration():
     op = _op(32, 2)
     F = _gpu_factor(op, 1e-6, 16)

@@ -73,3 +73,16 @@ def test_diff_problem_inputs():
     assert not np.allclose(p.f, p.u_target)
     q = diff_problem(32)
     assert np.array_equal(p.a, q.a) and np.array_equal(p.f, q.f)
+
+
+def test_batch_problems_inputs():
+    from workloads import batch_problems
+    b = batch_problems()
+    assert len(b) == 48
+    assert {p["n"] for p in b} <= {64, 96, 128, 192, 256}
+    for p in b:
+        assert p["leaf"] == (36 if p["n"] in (96, 192) else 64)
+        assert p["points"].shape == (p["n"] ** 2, 2) and p["f"].shape == (4, p["n"] ** 2)
+        assert p["a"].min() == 1.0 and p["a"].max() == 2.0
+    c = batch_problems()
+    assert all(np.array_equal(x["a"], y["a"]) and np.array_equal(x["f"], y["f"]) for x, y in zip(b, c))

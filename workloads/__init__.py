@@ -27,6 +27,7 @@ __all__ = [
     "gaussian_bump_field",
     "DiffProblem",
     "diff_problem",
+    "batch_problems",
 ]
 
 
@@ -131,3 +132,23 @@ def diff_problem(n: int = 256, seed_a: int = 5, seed_target: int = 6, seed_f: in
     a = 1.0 + gaussian_bump_field(P, 64, 0.05, 0.5, seed_a)
     N = P.shape[0]
     return DiffProblem(n, 1.0 / n, P, a, rhs(N, 1, seed_f)[0], rhs(N, 1, seed_target)[0])
+
+
+def batch_problems(count: int = 48, seed: int = 4):
+    """Independent 2D problems of uneven sizes: sides drawn from
+    ``{64, 96, 128, 192, 256}`` (``default_rng(seed)``); leaves of 6 x 6 points
+    for sides 96 and 192 and 8 x 8 otherwise (uniform tree depth);
+    ``a = 1 + g`` with ``g`` a field of 16 Gaussian bumps (width 0.1, weights
+    ``U(0, 1)``, seed ``1000 + i``) min-max scaled to ``[0, 1]``; 4 standard
+    normal right-hand sides (seed ``2000 + i``); ``b = c = 1``, eps 1e-6.
+    Returns a list of dicts with ``n``, ``h``, ``leaf``, ``eps``, ``points``,
+    ``a``, ``f``."""
+    rng = np.random.default_rng(seed)
+    sides = rng.choice([64, 96, 128, 192, 256], count)
+    out = []
+    for i, n in enumerate(int(s) for s in sides):
+        P = grid_points(n, 2)
+        a = 1.0 + gaussian_bump_field(P, 16, 0.1, 1.0, 1000 + i, normalize=True)
+        out.append(dict(n=n, h=1.0 / n, leaf=36 if n in (96, 192) else 64, eps=1e-6, points=P, a=a,
+                        f=rhs(P.shape[0], 4, 2000 + i)))
+    return out
