@@ -10,6 +10,7 @@
 #include <new>
 #include <set>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -238,8 +239,8 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
   return st;
 }
 
-hif_status hif_factor_batch(const hif_problem* problems, int32_t count, const hif_opts* opts, int32_t nworkers,
-                            hif_handle* out, hif_status* status) {
+static hif_status factor_batch(const hif_problem* problems, int32_t count, const hif_opts* opts, int32_t nworkers,
+                               hif_handle* out, hif_status* status) {
   if (count < 0) return fail(HIF_EINVAL, "count must be >= 0");
   if (count > 0 && (!problems || !out)) return fail(HIF_EINVAL, "problems and out must not be NULL");
   if (nworkers < 1 || nworkers > 16) return fail(HIF_EINVAL, "nworkers must be in [1, 16]");
@@ -288,9 +289,19 @@ hif_status hif_factor_batch(const hif_problem* problems, int32_t count, const hi
     (void)hipStreamDestroy(s);
   };
   {
+    // workers that could not be started leave their share to the others
+    // (or to this thread), which drain the same queue
     std::vector<std::thread> pool;
     const int nw = std::min<int>(nworkers, count);
-    for (int w = 0; w < nw; ++w) pool.emplace_back(work);
+    pool.reserve(nw);
+    for (int w = 0; w < nw; ++w) {
+      try {
+        pool.emplace_back(work);
+      } catch (const std::system_error&) {
+        break;
+      }
+    }
+    if (pool.empty()) work();
     for (auto& t : pool) t.join();
   }
   if (setup_failed) {
@@ -309,6 +320,15 @@ hif_status hif_factor_batch(const hif_problem* problems, int32_t count, const hi
   if (first != HIF_OK) return fail(first, first_msg);
   g_last_error.clear();
   return HIF_OK;
+}
+
+hif_status hif_factor_batch(const hif_problem* problems, int32_t count, const hif_opts* opts, int32_t nworkers,
+                            hif_handle* out, hif_status* status) {
+  try {
+    return factor_batch(problems, count, opts, nworkers, out, status);
+  } catch (const std::exception& e) {  // thread creation or host allocation
+    return fail(HIF_EDEVICE, std::string("batch scheduling failed: ") + e.what());
+  }
 }
 
 static hif_status sweep(hif_handle h, int op, const double* x, double* y, int64_t nrhs, hif_stream s) {
