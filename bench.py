@@ -58,6 +58,8 @@ def parse():
                    help="after the timed region, run one plain 256 MiB device copy kernel (scale for HBM counters)")
     p.add_argument("--no-refine", action="store_true",
                    help="skip the FP64 vs FP32-mixed comparison with GMRES refinement")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the short runs of the differentiated-solve and batch workloads")
     return p.parse_args()
 
 
@@ -179,7 +181,7 @@ def cpu_baseline_batch(prob, eps: float):
                       f"(N={N}, leaf {prob['leaf']}, eps {eps:g}), {dt:.1f} s on 1 host core"}
 
 
-def bench_batch(args):
+def bench_batch(args, quiet=False):
     """48 independent problems: concurrent factorization (4 worker streams), then every solve."""
     import numpy as np
     import torch
@@ -267,10 +269,12 @@ def bench_batch(args):
     if not args.no_cpu_baseline:
         small = min(probs, key=lambda p: p["n"])
         line["cpu_baseline"] = cpu_baseline_batch(small, 1e-6)
+    if quiet:
+        return line
     print(json.dumps(line), flush=True)
 
 
-def bench_diff(args):
+def bench_diff(args, quiet=False):
     """Forward + backward of the differentiated solve on the 256 x 256 problem."""
     import numpy as np
     import torch
@@ -339,6 +343,8 @@ def bench_diff(args):
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_diff(128, eps)
+    if quiet:
+        return line
     print(json.dumps(line), flush=True)
 
 
@@ -466,6 +472,16 @@ def main():
         line["refinement"] = refinement(hif, P, a, Fr, wl)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample, eps)
+    if not args.no_extras and wl.name == "sq512":
+        # the two other workloads, briefly (their own bench lines: --workload diff256 / batch48)
+        class _A:
+            steps, warmup, eps, no_cpu_baseline = 2, 1, None, True
+        keep = ("metric", "value", "unit", "ms_per_step", "accuracy", "modes", "one_worker_ms_per_step",
+                "solve_latency_ms")
+        line["other_workloads"] = {
+            "diff256": {k: v for k, v in bench_diff(_A, quiet=True).items() if k in keep},
+            "batch48": {k: v for k, v in bench_batch(_A, quiet=True).items() if k in keep},
+        }
     print(json.dumps(line), flush=True)
 
 
