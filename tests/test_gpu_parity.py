@@ -410,6 +410,30 @@ def test_apply_A_fft_matches_matvec_and_dense(n, d, shuffle):
     assert np.linalg.norm(_np(y0) - ref) <= 1e-13 * np.linalg.norm(ref)
 
 
+def test_apply_A_fft_plans_reused_across_handles_and_batch_sizes():
+    # hipFFT plans are cached per thread, stream, size and batch: two handles
+    # of one grid size and several right-hand-side counts (1, 3, 8, 3 again)
+    # share them, and every product still matches the pair-by-pair one.
+    n = 40
+    pts = grid_points(n, 2)
+    N = pts.shape[0]
+    rng = np.random.default_rng(44)
+    P = _t(pts)
+    for rep in range(2):
+        a = _t(1.0 + rng.uniform(size=N))
+        F = hif.factor(P, 1e-4, 64, a=a, h=1.0 / n)
+        for nr in (1, 3, 8, 3):
+            x = _t(rng.standard_normal((nr, N)))
+            y, fft = F.apply_A(x)
+            assert fft
+            ym = hif.matvec(P, x, a=a, h=1.0 / n)
+            err = (torch.linalg.norm(y - ym, dim=1) / torch.linalg.norm(ym, dim=1)).max().item()
+            assert err <= 1e-13, (rep, nr, err)
+        z, _ = F.apply_A(torch.zeros(N, dtype=torch.float64, device=DEV))
+        assert torch.count_nonzero(z).item() == 0
+        F.free()
+
+
 def test_apply_A_off_grid_runs_pair_by_pair():
     # points shifted off the cell centres: no Toeplitz structure to use
     rng = np.random.default_rng(41)
