@@ -351,7 +351,7 @@ def bench_diff(args, quiet=False):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "diff256":
         return bench_diff(args)

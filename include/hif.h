@@ -54,7 +54,7 @@ typedef enum {
   HIF_ENOMEM = -2,        /* device allocation failed or opts.max_bytes exceeded */
   HIF_ESINGULAR = -3,     /* zero pivot in a redundant block B_rr or the top block (Lemma 2.1) */
   HIF_EDEVICE = -4,       /* HIP runtime error */
-  HIF_EUNSUPPORTED = -5   /* valid request this build does not handle (e.g. non-uniform tree depth) */
+  HIF_EUNSUPPORTED = -5   /* valid request the library does not handle (e.g. non-uniform tree depth) */
 } hif_status;
 
 enum { HIF_FP64 = 0, HIF_FP32_MIXED = 1 };
