@@ -198,6 +198,11 @@ struct hif_factor_s {
   int64_t ntop = 0;
   hif::DBuf<int32_t> top_idx, top_piv, top_perm;
   hif::DBuf<double> top_lu;
+  // The top block as one record of the many-workgroup solve (k = 0),
+  // built on the first solve that needs it: table, [idx | piv | perm], offsets.
+  hif::DBuf<hif::GroupRec> top_rec;
+  hif::DBuf<int32_t> top_iarena;
+  hif::DBuf<int64_t> top_woff;
   // Sweep scratch.
   hif::DBuf<double> work;
   hif_stats_t stats{};

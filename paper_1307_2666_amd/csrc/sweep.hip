@@ -1116,7 +1116,36 @@ void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrh
     };
     for (auto& sub : H->subs)
       if (sub.nrec > 0) sweep(sub, 0);
-    if (H->ntop > 0) {
+    // A top block too large for LDS is solved like a large record with no
+    // skeleton (k = 0): the same blocked triangular solves spread over many
+    // workgroups, with the up pass (P, L^{-1}) and the down pass (U^{-1}).
+    const bool top_split = op == 0 && H->ntop > 0 && 2 * H->ntop > kCapL && 2 * H->ntop <= N;
+    if (top_split) {
+      const int r = int(H->ntop);
+      if (!H->top_rec.p) {
+        H->top_iarena.alloc(size_t(3) * r, &H->mem);
+        HIF_HIP(hipMemcpyAsync(H->top_iarena.p, H->top_idx.p, sizeof(int32_t) * r, hipMemcpyDeviceToDevice, s));
+        HIF_HIP(hipMemcpyAsync(H->top_iarena.p + r, H->top_piv.p, sizeof(int32_t) * r, hipMemcpyDeviceToDevice, s));
+        HIF_HIP(hipMemcpyAsync(H->top_iarena.p + 2 * r, H->top_perm.p, sizeof(int32_t) * r, hipMemcpyDeviceToDevice,
+                               s));
+        const GroupRec rec{r, 0, 0, 0};
+        const int64_t wo = 0;
+        H->top_rec.alloc(1, &H->mem);
+        H->top_woff.alloc(1, &H->mem);
+        HIF_HIP(hipMemcpyAsync(H->top_rec.p, &rec, sizeof(GroupRec), hipMemcpyHostToDevice, s));
+        HIF_HIP(hipMemcpyAsync(H->top_woff.p, &wo, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        HIF_HIP(hipStreamSynchronize(s));  // the host values above are copied before they go out of scope
+      }
+      SpArgs P{H->top_rec.p, H->top_iarena.p, H->top_lu.p, H->top_woff.p, u, wk, wk + int64_t(nv) * r, N, nv};
+      const int nbk = (r + kNbT - 1) / kNbT;
+      const dim3 gr(unsigned((r + 255) / 256), 1);
+      hipLaunchKernelGGL(k_sp_up_first, gr, dim3(256), 0, s, P);
+      for (int b = 0; b < nbk; ++b) hipLaunchKernelGGL(k_sp_lsolve, dim3(unsigned(nbk - b), 1), dim3(256), 0, s, P, b);
+      hipLaunchKernelGGL(k_sp_scatter, gr, dim3(256), 0, s, P);
+      hipLaunchKernelGGL(k_sp_down_first, dim3(unsigned((r + 15) / 16), 1), dim3(256), 0, s, P);
+      for (int b = nbk - 1; b >= 0; --b) hipLaunchKernelGGL(k_sp_usolve, dim3(unsigned(b + 1), 1), dim3(256), 0, s, P, b);
+      hipLaunchKernelGGL(k_sp_scatter, gr, dim3(256), 0, s, P);
+    } else if (H->ntop > 0) {
       if (op <= 1 && 2 * H->ntop <= kCapL)
         hipLaunchKernelGGL(k_top_lds, dim3(1), dim3(1024), 0, s, H->top_lu.p, H->top_perm.p, int(H->ntop),
                            H->top_idx.p, u, N, nv, op);
