@@ -13,6 +13,7 @@
 
 #include "batched.h"
 #include "gemm.h"
+#include "wave.h"
 
 namespace hif {
 
@@ -326,6 +327,7 @@ __global__ void k_qr_clear_lower(QrBatch A) {
 // later steps read is R (the orthogonal factor is never formed).
 // ---------------------------------------------------------------------------
 constexpr int kTb = kTsqrNb;
+static_assert(kTb == kRs, "the panel width is the reduce-scatter width");
 
 struct PanelGeom {
   int mp, jb, nck;
@@ -347,55 +349,6 @@ __device__ __forceinline__ double pick(const double (&y)[kTb], int j) {
   return r;
 }
 
-// Sum of p[c] over the 64 lanes for all kTb = 32 indices at once
-// (reduce-scatter: at each step a lane keeps one half of its values, sends the
-// other half to its partner and adds what it receives).  Returns the total of
-// index lane >> 1; p is destroyed.
-template <int H>
-__device__ __forceinline__ void rs_step(double (&p)[kTb], int lane) {
-  const bool up = (lane & (2 * H)) != 0;
-#pragma unroll
-  for (int i = 0; i < H; ++i) {
-    const double send = up ? p[i] : p[i + H];
-    const double keep = up ? p[i + H] : p[i];
-    p[i] = keep + __shfl_xor(send, 2 * H, 64);
-  }
-}
-// Pair sums across lane halves with the gfx950 lane-swap instructions:
-// (a, b) = this lane's values of indices i and i + h; the result is the sum
-// of index i over lanes l and l ^ 2h for the lower lane of each pair and of
-// index i + h for the upper one (h = 16: halves of the wave, h = 8: rows of
-// 16 lanes).  The sum does not depend on which output holds which half.
-template <int H>
-__device__ __forceinline__ double swap_pair_sum(double a, double b) {
-  const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
-  const unsigned alo = unsigned(ua), ahi = unsigned(ua >> 32), blo = unsigned(ub), bhi = unsigned(ub >> 32);
-  unsigned r0l, r1l, r0h, r1h;
-  if constexpr (H == 16) {
-    const auto rl = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
-    const auto rh = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
-    r0l = rl[0]; r1l = rl[1]; r0h = rh[0]; r1h = rh[1];
-  } else {
-    const auto rl = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
-    const auto rh = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
-    r0l = rl[0]; r1l = rl[1]; r0h = rh[0]; r1h = rh[1];
-  }
-  const double r0 = __longlong_as_double((static_cast<long long>(r0h) << 32) | r0l);
-  const double r1 = __longlong_as_double((static_cast<long long>(r1h) << 32) | r1l);
-  return r0 + r1;
-}
-
-__device__ __forceinline__ double wave_rs32(double (&p)[kTb]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) p[i] = swap_pair_sum<16>(p[i], p[i + 16]);
-#pragma unroll
-  for (int i = 0; i < 8; ++i) p[i] = swap_pair_sum<8>(p[i], p[i + 8]);
-  rs_step<4>(p, lane);
-  rs_step<2>(p, lane);
-  rs_step<1>(p, lane);
-  return p[0] + __shfl_xor(p[0], 1, 64);
-}
 
 // Householder QR of a block of at most RPT * blockDim.x rows and jb <= kTb
 // columns held RPT rows per thread (thread t: rows t + u * blockDim.x; rows

@@ -11,6 +11,7 @@
 #include "batched.h"
 #include "gemm.h"
 #include "kernels.h"
+#include "wave.h"
 
 namespace hif {
 
@@ -541,6 +542,7 @@ __global__ __launch_bounds__(256) void k_idm_Tcopy(IdArgs A) {
 // comes from k_idm_T_block.
 // ---------------------------------------------------------------------------
 constexpr int kBq = 32;        // reflectors per block
+static_assert(kBq == kRs, "the pivot kernel reduces its kBq products with wave_rs32");
 constexpr int kBqT = 512;      // threads of the pivot kernel
 constexpr int kBcGroups = 16;  // row groups of the column kernel (32 columns each)
 constexpr int kBcV = 2048;     // rows of v staged in LDS by the column kernel
@@ -676,12 +678,11 @@ __global__ __launch_bounds__(kBqT) void k_bq_piv(IdArgs A, BqState S, int j) {
     }
   ss = wave_sum(ss);
   if (lane == 0) sss[wv] = ss;
-#pragma unroll
-  for (int jj = 0; jj < kBq; ++jj) {
-    if (jj < jb) {
-      const double t = wave_sum(part[jj]);
-      if (lane == 0) sred[wv][jj] = t;
-    }
+  {
+    // all jb products in one reduce-scatter (part[jj] is zero for jj >= jb):
+    // lanes 2c and 2c + 1 end with the wave's sum for column c
+    const double t = wave_rs32(part);
+    if ((lane & 1) == 0 && (lane >> 1) < jb) sred[wv][lane >> 1] = t;
   }
   __syncthreads();
   ss = 0.0;
