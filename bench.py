@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # reads for a 256 MiB copy kernel (159.7 GB read + 5.9 GB written; taken again
 # after the last change to k_bq_piv).  Valid for these kernels as they stand;
 # set to None when they change.
-ID_STEP_TRAFFIC_BYTES = 1.656e+11
+ID_STEP_TRAFFIC_BYTES = None
 
 
 def parse():

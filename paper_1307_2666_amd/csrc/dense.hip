@@ -729,14 +729,14 @@ __global__ __launch_bounds__(kBqT) void k_bq_piv(IdArgs A, BqState S, int j) {
 // (tid % 32, tid / 32) sums rows i + g + 16u of column c.
 __global__ __launch_bounds__(32 * kBcGroups) void k_bq_cols(IdArgs A, BqState S) {
   const int q = blockIdx.y;
-  const BqCtl* C = S.ctl + q;
-  if (!C->go) return;
+  const BqCtl ctl = S.ctl[q];  // one read of the whole control block
+  if (!ctl.go) return;
   const int n = A.cols[q];
   const int c0 = blockIdx.x * 32;
   if (c0 >= n) return;
   const int m = A.rows[q];
-  const int i = C->cur, jb = i - C->i0;
-  const double beta = C->beta;
+  const int i = ctl.cur, jb = i - ctl.i0;
+  const double beta = ctl.beta;
   const int tid = threadIdx.x, c = tid & 31, g = tid >> 5;
   const double* V = S.V + q * kBq * S.vld;
   const int64_t vld = S.vld;
@@ -767,6 +767,13 @@ __global__ __launch_bounds__(32 * kBcGroups) void k_bq_cols(IdArgs A, BqState S)
   double* M = A.base + A.moff[q];
   const int ld = A.ld[q];
   double d = 0.0;
+  // the finishing thread's own loads, issued before the pass and the stores
+  double r0 = 0.0, old = 0.0, old0 = 0.0;
+  if (g == 0 && upd) {
+    r0 = M[int64_t(i) * ld + col];
+    old = S.nrm[o];
+    old0 = S.nrm0[o];
+  }
   if (upd) {
     const double* y = M + int64_t(i) * ld + col;
     int rr = g;
@@ -786,7 +793,7 @@ __global__ __launch_bounds__(32 * kBcGroups) void k_bq_cols(IdArgs A, BqState S)
 #pragma unroll
     for (int g2 = 0; g2 < kBcGroups; ++g2) t += sp[g2][c];
     double* yi = M + int64_t(i) * ld + col;
-    double r = *yi;
+    double r = r0;
     double f = beta * t;
     for (int jj = 0; jj < jb; ++jj) {
       const double fj = sF[c][jj];
@@ -796,10 +803,9 @@ __global__ __launch_bounds__(32 * kBcGroups) void k_bq_cols(IdArgs A, BqState S)
     S.F[o * kBq + jb] = f;
     r -= svi[jb] * f;
     *yi = r;
-    const double old = S.nrm[o];
     if (old > 0.0) {
       const double nw = old - r * r;
-      if (nw <= kTol3z * S.nrm0[o]) S.ctl[q].stale = 1;
+      if (nw <= kTol3z * old0) S.ctl[q].stale = 1;
       S.nrm[o] = nw > 0.0 ? nw : 0.0;
     }
   }
