@@ -39,10 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # k_bq_piv, k_bq_cols, k_bq_update, k_id_reg, k_id) on this workload, from
 # rocprofv3 FETCH_SIZE + WRITE_SIZE runs of `bench.py --steps 1 --warmup 0
 # --no-cpu-baseline --no-refine --calib-copy`, each scaled by what the counter
-# reads for a 256 MiB copy kernel (159.7 GB read + 5.9 GB written; taken again
-# after the last change to k_bq_piv).  Valid for these kernels as they stand;
-# set to None when they change.
-ID_STEP_TRAFFIC_BYTES = None
+# reads for a 256 MiB copy kernel (159.5 GB read + 5.9 GB written; taken again
+# after the last change to k_bq_piv and k_bq_cols).  Valid for these kernels as
+# they stand; set to None when they change.
+ID_STEP_TRAFFIC_BYTES = 1.655e+11
 
 
 def parse():
