@@ -466,10 +466,11 @@ __device__ void build_T(const double* sbeta, const double* sG, double* Tout) {
 #pragma unroll
     for (int i = 0; i < kTb; ++i) {
       const double b = sbeta[i];
+      // no branch on b, so that the G reads can be issued ahead of the
+      // chain; for b == 0 (no reflector, G unset) acc is discarded below
       double acc = 0.0;
-      if (b != 0.0)
 #pragma unroll
-        for (int l = 0; l < i; ++l) acc += trow[l] * sG[l * (kTb + 1) + i];
+      for (int l = 0; l < i; ++l) acc += trow[l] * sG[l * (kTb + 1) + i];
       trow[i] = p == i ? b : ((p < i && b != 0.0) ? -b * acc : 0.0);
     }
     if (lane < kTb)
