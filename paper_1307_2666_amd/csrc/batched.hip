@@ -873,6 +873,13 @@ __global__ __launch_bounds__(kLpThreads) void k_lu_panel_reg(LuBatch A, int j0) 
       }
     }
   }
+  __syncthreads();  // the panel rows and the interchanges are in memory
+  // the unit lower L11 of the panel, read once into LDS for every column
+  __shared__ double sL11[kNb][kNb];
+  for (int e = tid; e < kNb * kNb; e += kLpThreads) {
+    const int a = e / kNb, b = e % kNb;
+    sL11[a][b] = (a < jb && b < a) ? M[int64_t(j0 + a) * n + j0 + b] : 0.0;
+  }
   __syncthreads();
   // U12 = L11^{-1} A12 (rows j0..j0+jb-1, columns j0+jb..n-1)
   for (int c = j0 + jb + tid; c < n; c += kLpThreads) {
@@ -885,7 +892,7 @@ __global__ __launch_bounds__(kLpThreads) void k_lu_panel_reg(LuBatch A, int j0) 
       double v = x[i];
 #pragma unroll
       for (int p2 = 0; p2 < kNb; ++p2)
-        if (p2 < i) v -= M[int64_t(j0 + i) * n + j0 + p2] * x[p2];
+        if (p2 < i) v -= sL11[i][p2] * x[p2];
       x[i] = v;
     }
 #pragma unroll
