@@ -39,6 +39,8 @@ __device__ __forceinline__ double pick16(const double (&y)[kNb], int j) {
 }
 
 // Block-wide argmax (larger value, ties to the lower index) for up to 1024 threads.
+// The caller must pass a barrier between two calls (the slots are
+// rewritten by the next call).
 __device__ AM block_argmax_n(AM x) {
   __shared__ double sv[16];
   __shared__ int si[16];
@@ -52,7 +54,6 @@ __device__ AM block_argmax_n(AM x) {
   __syncthreads();
   AM r{-1.0, INT_MAX};
   for (int k = 0; k < nw; ++k) r = am_better(r, AM{sv[k], si[k]});
-  __syncthreads();
   return r;
 }
 
@@ -847,8 +848,12 @@ __global__ __launch_bounds__(kLpThreads) void k_lu_panel_reg(LuBatch A, int j0) 
         }
       }
     }
-    __syncthreads();  // sA / sB are rewritten by the next step
+    // Two barriers per step: the argmax slots are read before this step's
+    // exchange barrier, which every thread passes before the next step
+    // writes them; sA / sB are read after that barrier and before the next
+    // step's argmax barrier, which precedes their next writes.
   }
+  __syncthreads();  // sA / sB of the last step, before the code below
   // panel back to memory
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
