@@ -102,9 +102,10 @@ typedef struct {
  *                Either way the pivoted QR delays the updates of 32
  *                reflectors; both give the same ID up to rounding.
  *  fft_matvec:   products with the exact operator inside hif_gmres,
- *                hif_gmres_T and hif_apply_A: -1 = by FFT convolution when
- *                the points form the full uniform grid with constant weights
- *                and self terms (see hif_apply_A), 0 = always pair by pair.
+ *                hif_gmres_T and hif_apply_A: 0 (default) = pair by pair,
+ *                evaluated on the fly as hif_matvec; 1 = by FFT convolution
+ *                when the points form the full uniform grid with constant
+ *                weights and self terms (see hif_apply_A), else pair by pair.
  */
 typedef struct {
   int precision;
@@ -175,13 +176,24 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
                       double eps, int32_t leaf, const hif_opts* opts,
                       hif_stream stream, hif_handle* out);
 
-/* y = F x (generalized FMM; eqn hifie2/hifie3 first line).  x, y: [nrhs][n]. Stream-ordered. */
+/*
+ * The four factored sweeps.  x, y (f, u): [nrhs][n] device, caller's point
+ * order, nrhs >= 1; in place (x == y) allowed.  Stream-ordered and
+ * asynchronous; the first call of a handle may allocate sweep scratch
+ * (nrhs * n doubles, kept until hif_free).  HIF_EINVAL on a NULL handle or
+ * vector or nrhs < 1.
+ */
+/* y = F x (generalized FMM; eqn hifie2/hifie3 first line: the product of the
+ * factors U_l^{-*}, D, V_l^{-1} of Lemma 2.4 / eqn rskelf). */
 hif_status hif_apply(hif_handle h, const double* x, double* y, int64_t nrhs, hif_stream stream);
-/* y = F^T x. */
+/* y = F^T x: the transpose of the same factored product, as the power
+ * iteration of Section 5 needs A^* and F^* to estimate e_a = |A - F| / |A|. */
 hif_status hif_apply_T(hif_handle h, const double* x, double* y, int64_t nrhs, hif_stream stream);
 /* u = F^{-1} f (direct solver / preconditioner; eqn hifie2/hifie3 second line). */
 hif_status hif_solve(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream stream);
-/* u = F^{-T} f. */
+/* u = F^{-T} f: the transposed inverse (eqn hifie2/hifie3 second line,
+ * transposed), used with A^* for e_s = |I - A F^{-1}| in Section 5 and for
+ * adjoint solves. */
 hif_status hif_solve_T(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream stream);
 
 /*
@@ -195,9 +207,12 @@ hif_status hif_matvec(const double* points, int64_t n, int dim, const hif_kernel
                       const double* x, double* y, int64_t nrhs, hif_stream stream);
 
 /*
- * Iterative refinement by GMRES (Section 6): solve A u = f with A the exact
- * operator of this handle (as hif_matvec, from the points and coefficients
- * given to hif_factor) and F^{-1} (hif_solve) as right preconditioner:
+ * Iterative refinement by GMRES with F^{-1} as preconditioner (Section 5,
+ * Example 3: Lemma 5.1 and its corollary bound the iteration count by the
+ * accuracy of F): solve A u = f with A the exact operator of this handle
+ * (pair by pair as hif_matvec, from the points and coefficients given to
+ * hif_factor; by FFT only with opts.fft_matvec = 1) and F^{-1} (hif_solve)
+ * as right preconditioner:
  * GMRES on A F^{-1} y = f, u = F^{-1} y, starting from zero, no restart.
  *   f, u:   [nrhs][n] device, must not alias; u receives the solution.
  *   nrhs:   1..64; all right-hand sides iterate together.
@@ -231,7 +246,7 @@ hif_status hif_gmres_T(hif_handle h, const double* f, double* u, int64_t nrhs, d
  * from the points and coefficients given to hif_factor; the operator the
  * hif_gmres refinements use).  When the points are the cell centres of the
  * full n^d grid on the unit square/cube (any order) with constant weights and
- * self terms, and opts.fft_matvec allowed it, K is a d-level Toeplitz matrix
+ * self terms, and opts.fft_matvec = 1 asked for it, K is a d-level Toeplitz matrix
  * and the product runs as a zero-padded FFT convolution of size (2n)^d in
  * O(n^d log n) (the acceleration the paper uses for its products with A);
  * otherwise pair by pair as hif_matvec.  Both give the same product up to

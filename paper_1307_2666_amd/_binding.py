@@ -237,7 +237,7 @@ class Factorization:
 
 def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, selfk=None,
            second_kind=-1, symmetric=-1, variant="hifie", n_proxy=0, proxy_radius=0.0,
-           max_bytes=0, precision=HIF_FP64, row_compression=-1, fft_matvec=-1, stream=None) -> Factorization:
+           max_bytes=0, precision=HIF_FP64, row_compression=-1, fft_matvec=0, stream=None) -> Factorization:
     """``hif_factor``: build ``F ~ A`` for points ``(n, d)`` in the unit box."""
     lib = load_library()
     P = _dev(points)
@@ -264,7 +264,7 @@ def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, s
 
 
 def factor_batch(problems, *, nworkers=4, precision=HIF_FP64, second_kind=-1, symmetric=-1, variant="hifie",
-                 max_bytes=0, row_compression=-1, fft_matvec=-1):
+                 max_bytes=0, row_compression=-1, fft_matvec=0):
     """``hif_factor_batch``: factor independent problems concurrently.
 
     ``problems`` is a list of dicts with the ``factor`` arguments ``points``, ``eps``,

@@ -185,7 +185,7 @@ hif_status hif_opts_default(hif_opts* o) {
   o->proxy_radius = 0.0;
   o->max_bytes = 0;
   o->row_compression = -1;
-  o->fft_matvec = -1;
+  o->fft_matvec = 0;
   return HIF_OK;
 }
 
@@ -215,7 +215,7 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
   if (o.n_proxy < 0 || o.n_proxy > 8192) return fail(HIF_EINVAL, "opts.n_proxy must be in [0, 8192]");
   if (o.row_compression < -1 || o.row_compression > 1)
     return fail(HIF_EINVAL, "opts.row_compression must be -1, 0 or 1");
-  if (o.fft_matvec != -1 && o.fft_matvec != 0) return fail(HIF_EINVAL, "opts.fft_matvec must be -1 or 0");
+  if (o.fft_matvec != 0 && o.fft_matvec != 1) return fail(HIF_EINVAL, "opts.fft_matvec must be 0 or 1");
   if (!(o.proxy_radius == 0.0 || (std::isfinite(o.proxy_radius) && o.proxy_radius > 0.5)))
     return fail(HIF_EINVAL, "opts.proxy_radius must be 0 (default) or > 0.5 cell widths");
   // second-kind modification by default in FP64 only: in FP32 the SCI-scaled

@@ -1191,34 +1191,48 @@ __global__ __launch_bounds__(256) void k_gemm_tiles(const GemmDesc* D, int nd) {
 }  // namespace
 
 // Second stream of the row compression's look-ahead, one per host thread and
-// device, created on first use and kept for the life of the thread (creating
-// and destroying it per call costs a host wait on its work each time), or
+// device, with the two events that order it against the caller's stream;
+// created on first use and kept for the life of the thread (creating and
+// destroying them per call costs a host wait on their work each time, and
+// an event must not be destroyed while a stream still waits on it), or
 // until release_thread_streams.
-static std::map<int, hipStream_t>& aux_streams() {
-  thread_local std::map<int, hipStream_t> streams;
+struct AuxStream {
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fact = nullptr, ev_rest = nullptr;
+};
+
+static std::map<int, AuxStream>& aux_streams() {
+  thread_local std::map<int, AuxStream> streams;
   return streams;
 }
 
-static hipStream_t aux_stream() {
-  std::map<int, hipStream_t>& streams = aux_streams();
+static const AuxStream& aux_stream() {
+  std::map<int, AuxStream>& streams = aux_streams();
   int dev = 0;
   HIF_HIP(hipGetDevice(&dev));
   auto it = streams.find(dev);
   if (it != streams.end()) return it->second;
-  hipStream_t s2;
-  HIF_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
-  streams[dev] = s2;
-  return s2;
+  AuxStream a;
+  HIF_HIP(hipStreamCreateWithFlags(&a.s2, hipStreamNonBlocking));
+  if (hipEventCreateWithFlags(&a.ev_fact, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&a.ev_rest, hipEventDisableTiming) != hipSuccess) {
+    if (a.ev_fact) (void)hipEventDestroy(a.ev_fact);
+    (void)hipStreamDestroy(a.s2);
+    throw Error{HIF_EDEVICE, "creating the look-ahead events failed"};
+  }
+  return streams[dev] = a;
 }
 
 void release_thread_streams() {
-  std::map<int, hipStream_t>& streams = aux_streams();
+  std::map<int, AuxStream>& streams = aux_streams();
   int cur = 0;
   (void)hipGetDevice(&cur);
   for (auto& kv : streams) {
     (void)hipSetDevice(kv.first);
-    (void)hipStreamSynchronize(kv.second);
-    (void)hipStreamDestroy(kv.second);
+    (void)hipStreamSynchronize(kv.second.s2);
+    (void)hipEventDestroy(kv.second.ev_fact);
+    (void)hipEventDestroy(kv.second.ev_rest);
+    (void)hipStreamDestroy(kv.second.s2);
   }
   streams.clear();
   (void)hipSetDevice(cur);
@@ -1246,10 +1260,9 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
     // own updates of panel p), and the remaining-columns update of p
     // follows the factorization of p (it waits for an event recorded after
     // the stack kernel).
-    hipStream_t s2 = aux_stream();
-    hipEvent_t ev_fact, ev_rest;
-    HIF_HIP(hipEventCreateWithFlags(&ev_fact, hipEventDisableTiming));
-    HIF_HIP(hipEventCreateWithFlags(&ev_rest, hipEventDisableTiming));
+    const AuxStream& aux = aux_stream();
+    hipStream_t s2 = aux.s2;
+    hipEvent_t ev_fact = aux.ev_fact, ev_rest = aux.ev_rest;
     bool rest_pending = false;
     for (int j0 = 0, p = 0; j0 < max_cols; j0 += kTsqrNb, ++p) {
       const int half = p & 1;
@@ -1292,8 +1305,6 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
     if (rest_pending) HIF_HIP(hipStreamWaitEvent(s, ev_rest, 0));
     hipLaunchKernelGGL(k_qr_clear_lower, dim3(64, A.nprob), dim3(256), 0, s, A);
     HIF_HIP(hipGetLastError());
-    HIF_HIP(hipEventDestroy(ev_fact));
-    HIF_HIP(hipEventDestroy(ev_rest));
     return;
   }
   // taller problems: one workgroup per problem for the panel

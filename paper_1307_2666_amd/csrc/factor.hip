@@ -633,33 +633,45 @@ T scalar_at(const T* d, hipStream_t s) {
   return v;
 }
 
+// Phase timing with HIP events recorded on the factorization's stream.  The
+// events come from a pool owned by the timer: created on first use, recorded
+// again after every flush and destroyed with the timer, so a factorization
+// creates a few dozen events instead of one per mark (thousands per
+// factorization, from every worker thread of a batch).
 struct Timer {
   hipStream_t s;
-  std::vector<hipEvent_t> ev;
+  std::vector<hipEvent_t> pool;  // every event created so far
+  size_t used = 0;               // events recorded since the last flush
   std::vector<int> phase;
   void mark(int ph) {
-    hipEvent_t e;
-    HIF_HIP(hipEventCreate(&e));
-    HIF_HIP(hipEventRecord(e, s));
-    ev.push_back(e);
+    if (used == pool.size()) {
+      hipEvent_t e;
+      HIF_HIP(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    HIF_HIP(hipEventRecord(pool[used], s));
+    ++used;
     phase.push_back(ph);
   }
   void flush(double* acc, double* acc2 = nullptr) {
-    if (ev.size() >= 2) {
-      HIF_HIP(hipEventSynchronize(ev.back()));
-      for (size_t i = 1; i < ev.size(); ++i) {
+    if (used >= 2) {
+      HIF_HIP(hipEventSynchronize(pool[used - 1]));
+      for (size_t i = 1; i < used; ++i) {
         float ms = 0.f;
-        HIF_HIP(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
+        HIF_HIP(hipEventElapsedTime(&ms, pool[i - 1], pool[i]));
         acc[phase[i]] += ms;
         if (acc2) acc2[phase[i]] += ms;
       }
+    } else if (used == 1) {
+      HIF_HIP(hipEventSynchronize(pool[0]));
     }
-    for (auto e : ev) (void)hipEventDestroy(e);
-    ev.clear();
+    used = 0;
     phase.clear();
   }
   ~Timer() {
-    for (auto e : ev) (void)hipEventDestroy(e);
+    // a pending record must complete before its event is destroyed
+    if (used > 0) (void)hipEventSynchronize(pool[used - 1]);
+    for (auto e : pool) (void)hipEventDestroy(e);
   }
 };
 

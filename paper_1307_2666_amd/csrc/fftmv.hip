@@ -167,7 +167,7 @@ __global__ void k_fft_flag_init(int* bad) {
 bool fft_ready(hif_factor_s* H, hipStream_t s) {
   if (H->fft_state != 0) return H->fft_state > 0;
   H->fft_state = -1;
-  if (H->opts.fft_matvec == 0) return false;
+  if (H->opts.fft_matvec != 1) return false;
   const int64_t N = H->n;
   const int n = int(std::llround(std::pow(double(N), 1.0 / H->dim)));
   int64_t nd = 1;

@@ -1,8 +1,10 @@
-// Right-preconditioned GMRES (Section 6, with the factorization F ~ A of
-// this handle as preconditioner): solve A u = f by GMRES on A F^{-1} y = f,
-// u = F^{-1} y, x_0 = 0, no restart.  The transposed variant solves
-// A^T u = f on A^T F^{-T} y = f with the same machinery.  A is the exact operator of eqn 1.1
-// applied on the fly (hif_matvec), F^{-1} the solve sweep.  All right-hand
+// Right-preconditioned GMRES (Section 5, Example 3: Lemma 5.1 and its
+// corollary, with the factorization F ~ A of this handle as preconditioner):
+// solve A u = f by GMRES on A F^{-1} y = f, u = F^{-1} y, x_0 = 0, no
+// restart.  The transposed variant solves A^T u = f on A^T F^{-T} y = f with
+// the same machinery.  A is the exact operator of eqn 1.1, applied pair by
+// pair on the fly (the hif_matvec kernel) unless the handle was built with
+// the FFT product enabled; F^{-1} is the solve sweep.  All right-hand
 // sides iterate in lockstep; the Arnoldi basis, the products, the
 // orthogonalization (classical Gram-Schmidt applied twice) and the norms run
 // on the device with fixed-order two-stage reductions; only the small

@@ -106,7 +106,7 @@ def test_apply_A_rejects_bad_arguments():
     assert lib.hif_apply_A(None, x, y, 1, 0, None, None) == B.HIF_EINVAL
     assert b"handle" in lib.hif_last_error()
     o = hif.default_opts()
-    assert o.fft_matvec == -1
+    assert o.fft_matvec == 0
     o.fft_matvec = 2
     st, msg, _ = _factor_raw(opts=o)
     assert st == B.HIF_EINVAL and "fft_matvec" in msg

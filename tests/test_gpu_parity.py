@@ -392,7 +392,7 @@ def test_apply_A_fft_matches_matvec_and_dense(n, d, shuffle):
     b = 1.0 + 0.5 * rng.uniform(size=N)
     c = 1.0 + 0.5 * rng.uniform(size=N)
     op = Operator.uniform(pts, 1.0 / n, a=a, b=b, c=c)
-    F = hif.factor(_t(pts), 1e-3, 64, a=_t(a), b=_t(b), c=_t(c), h=1.0 / n)
+    F = hif.factor(_t(pts), 1e-3, 64, a=_t(a), b=_t(b), c=_t(c), h=1.0 / n, fft_matvec=1)
     x = rng.standard_normal((2, N))
     y, fft = F.apply_A(_t(x))
     yT, fftT = F.apply_A(_t(x), transpose=True)
@@ -421,7 +421,7 @@ def test_apply_A_fft_plans_reused_across_handles_and_batch_sizes():
     P = _t(pts)
     for rep in range(2):
         a = _t(1.0 + rng.uniform(size=N))
-        F = hif.factor(P, 1e-4, 64, a=a, h=1.0 / n)
+        F = hif.factor(P, 1e-4, 64, a=a, h=1.0 / n, fft_matvec=1)
         for nr in (1, 3, 8, 3):
             x = _t(rng.standard_normal((nr, N)))
             y, fft = F.apply_A(x)
@@ -439,7 +439,7 @@ def test_apply_A_off_grid_runs_pair_by_pair():
     rng = np.random.default_rng(41)
     pts = grid_points(48, 2) + 0.2 / 48
     op = Operator.uniform(pts, 1.0 / 48, a=np.ones(pts.shape[0]))
-    F = hif.factor(_t(pts), 1e-6, 64, a=_t(op.a), h=1.0 / 48)
+    F = hif.factor(_t(pts), 1e-6, 64, a=_t(op.a), h=1.0 / 48, fft_matvec=1)
     x = rng.standard_normal(pts.shape[0])
     y, fft = F.apply_A(_t(x))
     assert not fft
@@ -451,7 +451,7 @@ def test_apply_A_fft_sq512_matches_matvec():
     wl = workload("sq512")
     P = _t(wl.points())
     a = torch.ones(wl.N, dtype=torch.float64, device=DEV)
-    F = hif.factor(P, 1e-3, wl.leaf, a=a, h=wl.h)
+    F = hif.factor(P, 1e-3, wl.leaf, a=a, h=wl.h, fft_matvec=1)
     X = _t(wl.rhs())
     y, fft = F.apply_A(X)
     assert fft
@@ -480,7 +480,7 @@ def test_gmres_native_matches_dense_solve(second_kind):
     # hif_gmres (a12): GMRES on A F^{-1} with the exact operator reaches the
     # requested true residual; the solution matches a dense FP64 solve, and
     # the iteration count matches the oracle's GMRES driven by the same
-    # preconditioner (Section 6, Lemma 5.1).
+    # preconditioner (Section 5, Lemma 5.1).
     op = _op(64, 2)
     F = _gpu_factor(op, 1e-3, 64, second_kind=second_kind)
     rng = np.random.default_rng(5)
