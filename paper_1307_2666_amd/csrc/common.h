@@ -306,8 +306,11 @@ void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* k, con
 void launch_make_perm(const GroupRec* recs, int nrec, int32_t* iarena, int max_r, hipStream_t s);
 void launch_make_perm_top(const int32_t* piv, int32_t* perm, int n, hipStream_t s);
 
-// Sweeps (sweep.hip): op 0 solve, 1 solve_T, 2 apply, 3 apply_T.
+// Sweeps (sweep.hip): op 0 solve, 1 solve_T, 2 apply, 3 apply_T; scratch in
+// the handle.  prepare_sweeps builds what the sweeps read besides the factor
+// records (called once by the factorization).
 void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s);
+void prepare_sweeps(hif_factor_s* H, hipStream_t s);
 
 // Right-preconditioned GMRES with the factorization and the exact matvec (gmres.hip).
 // With trans, A^T u = f preconditioned by F^{-T}.

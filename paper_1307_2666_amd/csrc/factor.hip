@@ -1577,6 +1577,7 @@ void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* kr, co
   }
   fb += 8 * H->ntop * H->ntop + 8 * H->ntop;
   st.factor_bytes = fb;
+  prepare_sweeps(H, s);
   HIF_HIP(hipStreamSynchronize(s));
   st.t_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }

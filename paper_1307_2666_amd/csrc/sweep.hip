@@ -1065,7 +1065,16 @@ void launch_make_perm_top(const int32_t* piv, int32_t* perm, int n, hipStream_t 
   HIF_HIP(hipGetLastError());
 }
 
-void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s) {
+// A top block too large for LDS is solved like a large record with no
+// skeleton through the many-workgroup triangular solves.
+static bool top_split_solve(const hif_factor_s* H) {
+  return H->ntop > 0 && 2 * H->ntop > kCapL && 2 * H->ntop <= H->n;
+}
+
+// The sweeps proper.  work: min(nrhs, 8) * N doubles of scratch, reused by
+// every group of 8 right-hand sides (all launches are ordered on s).
+static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s,
+                      double* work) {
   const int64_t N = H->n;
   const int64_t tot = N * nrhs;
   if (x != y) {
@@ -1074,11 +1083,10 @@ void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrh
     hipLaunchKernelGGL(k_copy, dim3(unsigned(blocks)), dim3(256), 0, s, x, y, tot);
     HIF_HIP(hipGetLastError());
   }
-  H->work.ensure(tot, &H->mem);
   for (int64_t v0 = 0; v0 < nrhs; v0 += 8) {
     const int nv = int(std::min<int64_t>(8, nrhs - v0));
     double* u = y + v0 * N;
-    double* wk = H->work.p + v0 * N;
+    double* wk = work;
     // solve / solve_T of a sub-level go through LDS when a group fits; solve
     // of few large records is spread over many workgroups per record
     auto sweep = [&](const SubLevel& sub, int down) {
@@ -1119,23 +1127,10 @@ void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrh
     // A top block too large for LDS is solved like a large record with no
     // skeleton (k = 0): the same blocked triangular solves spread over many
     // workgroups, with the up pass (P, L^{-1}) and the down pass (U^{-1}).
-    const bool top_split = op == 0 && H->ntop > 0 && 2 * H->ntop > kCapL && 2 * H->ntop <= N;
+    const bool top_split = op == 0 && top_split_solve(H);
     if (top_split) {
       const int r = int(H->ntop);
-      if (!H->top_rec.p) {
-        H->top_iarena.alloc(size_t(3) * r, &H->mem);
-        HIF_HIP(hipMemcpyAsync(H->top_iarena.p, H->top_idx.p, sizeof(int32_t) * r, hipMemcpyDeviceToDevice, s));
-        HIF_HIP(hipMemcpyAsync(H->top_iarena.p + r, H->top_piv.p, sizeof(int32_t) * r, hipMemcpyDeviceToDevice, s));
-        HIF_HIP(hipMemcpyAsync(H->top_iarena.p + 2 * r, H->top_perm.p, sizeof(int32_t) * r, hipMemcpyDeviceToDevice,
-                               s));
-        const GroupRec rec{r, 0, 0, 0};
-        const int64_t wo = 0;
-        H->top_rec.alloc(1, &H->mem);
-        H->top_woff.alloc(1, &H->mem);
-        HIF_HIP(hipMemcpyAsync(H->top_rec.p, &rec, sizeof(GroupRec), hipMemcpyHostToDevice, s));
-        HIF_HIP(hipMemcpyAsync(H->top_woff.p, &wo, sizeof(int64_t), hipMemcpyHostToDevice, s));
-        HIF_HIP(hipStreamSynchronize(s));  // the host values above are copied before they go out of scope
-      }
+      HIF_REQUIRE(H->top_rec.p, HIF_EDEVICE, "the top block's solve record was not built with the factors");
       SpArgs P{H->top_rec.p, H->top_iarena.p, H->top_lu.p, H->top_woff.p, u, wk, wk + int64_t(nv) * r, N, nv};
       const int nbk = (r + kNbT - 1) / kNbT;
       const dim3 gr(unsigned((r + 255) / 256), 1);
@@ -1157,6 +1152,29 @@ void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrh
       if (it->nrec > 0) sweep(*it, 1);
     HIF_HIP(hipGetLastError());
   }
+}
+
+
+
+void prepare_sweeps(hif_factor_s* H, hipStream_t s) {
+  if (!top_split_solve(H) || H->top_rec.p) return;
+  const int r = int(H->ntop);
+  H->top_iarena.alloc(size_t(3) * r, &H->mem);
+  HIF_HIP(hipMemcpyAsync(H->top_iarena.p, H->top_idx.p, sizeof(int32_t) * r, hipMemcpyDeviceToDevice, s));
+  HIF_HIP(hipMemcpyAsync(H->top_iarena.p + r, H->top_piv.p, sizeof(int32_t) * r, hipMemcpyDeviceToDevice, s));
+  HIF_HIP(hipMemcpyAsync(H->top_iarena.p + 2 * r, H->top_perm.p, sizeof(int32_t) * r, hipMemcpyDeviceToDevice, s));
+  const GroupRec rec{r, 0, 0, 0};
+  const int64_t wo = 0;
+  H->top_rec.alloc(1, &H->mem);
+  H->top_woff.alloc(1, &H->mem);
+  HIF_HIP(hipMemcpyAsync(H->top_rec.p, &rec, sizeof(GroupRec), hipMemcpyHostToDevice, s));
+  HIF_HIP(hipMemcpyAsync(H->top_woff.p, &wo, sizeof(int64_t), hipMemcpyHostToDevice, s));
+  HIF_HIP(hipStreamSynchronize(s));  // the host values above are copied before they go out of scope
+}
+
+void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s) {
+  H->work.ensure(std::min<int64_t>(nrhs, 8) * H->n, &H->mem);
+  sweep_run(H, op, x, y, nrhs, s, H->work.p);
 }
 
 }  // namespace hif
