@@ -62,6 +62,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="sq512")
     p.add_argument("--eps", type=float, default=None)
+    p.add_argument("--precision", choices=("fp64", "fp32_mixed"), default="fp64",
+                   help="precision of the timed factorization (fp32_mixed: FP32 entries and matrix-core GEMMs)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=256, help="grid side of the oracle's sample (2D)")
     p.add_argument("--calib-copy", action="store_true",
@@ -491,9 +493,11 @@ def main():
     a = torch.ones(N, dtype=torch.float64, device=dev)
     Fr = torch.tensor(wl.rhs(), device=dev)
     nrhs = Fr.shape[0]
+    mixed = args.precision == "fp32_mixed"
+    prec = hif.HIF_FP32_MIXED if mixed else hif.HIF_FP64
 
     def step():
-        F = hif.factor(P, eps, wl.leaf, a=a, h=wl.h)
+        F = hif.factor(P, eps, wl.leaf, a=a, h=wl.h, precision=prec)
         U = F.solve(Fr)
         return F, U
 
@@ -550,11 +554,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32/f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: 2D Laplace second-kind volume IE, {wl.n}x{wl.n} grid (N={N}), "
-                               f"{nrhs} RHS, eps={eps:g}, leaf {wl.leaf}, HIF-IE with second-kind "
-                               f"modification, FP64", "N": N, "nrhs": nrhs, "eps": eps, "leaf": wl.leaf},
+                               f"{nrhs} RHS, eps={eps:g}, leaf {wl.leaf}, " +
+                               ("HIF-IE without the second-kind modification, FP32 entries and matrix-core "
+                                "GEMMs, FP64 IDs, LU and sweeps" if mixed else
+                                "HIF-IE with second-kind modification, FP64"),
+                   "N": N, "nrhs": nrhs, "eps": eps, "leaf": wl.leaf, "precision": args.precision},
         "accuracy": {"rel_residual_max": res, "rel_err_est_max": err, "gate_1e-6": bool(err <= 1e-6 and res <= 1e-6),
                      "how": "residual f - A u with the exact pair-by-pair operator; error by one refinement "
                             "step F^{-1}(f - A u); oracle parity at this size is checked by the tests"},
