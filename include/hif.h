@@ -197,6 +197,24 @@ hif_status hif_solve(hif_handle h, const double* f, double* u, int64_t nrhs, hif
 hif_status hif_solve_T(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream stream);
 
 /*
+ * u = F^{-1} f exactly as hif_solve, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the sweep scratch is a static device array of the
+ * library, HIF_SOLVE_NOALLOC_MAX doubles per GPU (32 MiB, held by every GPU
+ * the library runs on until the process ends), instead of the handle's
+ * buffer.  The call allocates nothing and calls no allocating routine; the
+ * handle must come from hif_factor (the factors hold everything else the
+ * sweeps read).  Requires min(nrhs, 8) * n <= HIF_SOLVE_NOALLOC_MAX, else
+ * HIF_EINVAL before any device work.  Arguments, layouts and results as
+ * hif_solve.  Every call on one GPU shares that GPU's scratch: calls that
+ * overlap on one GPU (different streams or host threads without ordering)
+ * race and give wrong results.  The scratch needs no clearing (it is written
+ * before it is read).  Stream-ordered.
+ */
+#define HIF_SOLVE_NOALLOC_MAX (4u << 20)
+hif_status hif_solve_noalloc(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream stream);
+
+/*
  * y = A x evaluated exactly on the fly in O(n^2) (the operator of eqn 1.1
  * under the discretization of Section 3.1; no factorization involved).
  * Arguments as in hif_factor; x, y: [nrhs][n], y must not alias x.

@@ -83,7 +83,9 @@ EXPORTS = {
     "hif_diag_grad": (_INT, [_VP, _VP, _VP, _I64, _I64, _VP]),
     "hif_apply_A": (_INT, [_VP, _VP, _VP, _I64, _INT, _VP, _VP]),
     "hif_factor_batch": (_INT, [_VP, _I32, _VP, _I32, _VP, _VP]),
+    "hif_solve_noalloc": (_INT, [_VP, _VP, _VP, _I64, _VP]),
 }
+HIF_SOLVE_NOALLOC_MAX = 4 << 20
 
 
 def load_library():
@@ -162,6 +164,11 @@ class Factorization:
     def solve(self, f, out=None, stream=None):
         """``u = F^{-1} f``; ``f`` is ``(n,)`` or ``(nrhs, n)``."""
         return self._run(load_library().hif_solve, f, out, stream)
+
+    def solve_noalloc(self, f, out, stream=None):
+        """``hif_solve_noalloc``: ``F^{-1} f`` into the caller's ``out`` with the library's
+        static scratch (no device allocation in the library)."""
+        return self._run(load_library().hif_solve_noalloc, f, out, stream)
 
     def solve_T(self, f, out=None, stream=None):
         return self._run(load_library().hif_solve_T, f, out, stream)

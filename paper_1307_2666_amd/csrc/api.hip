@@ -351,6 +351,24 @@ hif_status hif_apply_T(hif_handle h, const double* x, double* y, int64_t nrhs, h
   return sweep(h, 3, x, y, nrhs, s);
 }
 
+hif_status hif_solve_noalloc(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream s) {
+  if (!h) return fail(HIF_EINVAL, "handle is NULL");
+  if (!f || !u) return fail(HIF_EINVAL, "vector pointer is NULL");
+  if (nrhs < 1) return fail(HIF_EINVAL, "nrhs must be >= 1");
+  // no StreamScope: this call never touches the handle's pooled buffers
+  try {
+    g_last_error.clear();
+    sweep_noalloc_impl(h, f, u, nrhs, hipStream_t(s));
+    return HIF_OK;
+  } catch (const Error& e) {
+    return fail(e.status, e.msg);
+  } catch (const std::exception& e) {
+    return fail(HIF_EDEVICE, e.what());
+  } catch (...) {
+    return fail(HIF_EDEVICE, "unknown error");
+  }
+}
+
 hif_status hif_matvec(const double* points, int64_t n, int dim, const hif_kernel* k, const double* a,
                       const double* b, const double* c, const double* x, double* y, int64_t nrhs, hif_stream s) {
   if (!points || !x || !y) return fail(HIF_EINVAL, "NULL pointer argument");

@@ -308,9 +308,12 @@ void launch_make_perm_top(const int32_t* piv, int32_t* perm, int n, hipStream_t 
 
 // Sweeps (sweep.hip): op 0 solve, 1 solve_T, 2 apply, 3 apply_T; scratch in
 // the handle.  prepare_sweeps builds what the sweeps read besides the factor
-// records (called once by the factorization).
+// records (called once by the factorization).  sweep_noalloc_impl solves with
+// the library's static device scratch of kSolveScratchDoubles doubles.
 void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s);
 void prepare_sweeps(hif_factor_s* H, hipStream_t s);
+constexpr size_t kSolveScratchDoubles = HIF_SOLVE_NOALLOC_MAX;  // 32 MiB
+void sweep_noalloc_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, hipStream_t s);
 
 // Right-preconditioned GMRES with the factorization and the exact matvec (gmres.hip).
 // With trans, A^T u = f preconditioned by F^{-T}.

@@ -17,6 +17,9 @@
 // sub-level touch disjoint DOFs and run as one launch, one workgroup each.
 // Vectors are [nrhs][N] in the caller's order; every product works in place
 // through the records' global DOF indices.
+#include <mutex>
+#include <string>
+
 #include "common.h"
 
 namespace hif {
@@ -1175,6 +1178,45 @@ void prepare_sweeps(hif_factor_s* H, hipStream_t s) {
 void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s) {
   H->work.ensure(std::min<int64_t>(nrhs, 8) * H->n, &H->mem);
   sweep_run(H, op, x, y, nrhs, s, H->work.p);
+}
+
+// ---------------------------------------------------------------------------
+// Solve without allocation (hif_solve_noalloc): the sweep scratch is this
+// file-scope device array instead of the handle's work buffer.  Each device
+// holds its own copy; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in).  Calls that overlap on one device share it and race.
+// ---------------------------------------------------------------------------
+namespace {
+__device__ __align__(256) double scratch[kSolveScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+double* scratch_ptr() {
+  int dev = 0;
+  HIF_HIP(hipGetDevice(&dev));
+  HIF_REQUIRE(dev >= 0 && dev < kMaxDevices, HIF_EDEVICE, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error{HIF_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+void sweep_noalloc_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, hipStream_t s) {
+  const int64_t need = std::min<int64_t>(nrhs, 8) * H->n;
+  HIF_REQUIRE(need <= int64_t(kSolveScratchDoubles), HIF_EINVAL,
+              "min(nrhs, 8) * n = " + std::to_string(need) + " exceeds the " +
+                  std::to_string(kSolveScratchDoubles) + " doubles of the solve scratch");
+  double* work = scratch_ptr();
+  sweep_run(H, 0, f, u, nrhs, s, work);
 }
 
 }  // namespace hif

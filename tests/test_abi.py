@@ -168,3 +168,14 @@ def test_partition_and_id_reject_bad_arguments():
     assert lib.hif_id_batched(p, p, p, p, p, 0, 4, p, p, p, None, None, None) == B.HIF_OK
     assert lib.hif_id_batched(p, p, p, p, p, 2, 5000, p, p, p, None, None, None) == B.HIF_EINVAL
     assert lib.hif_id_batched(p, p, p, p, p, 2, 4, p, p, p, p, None, None) == B.HIF_EINVAL
+
+
+def test_solve_noalloc_rejects_bad_arguments():
+    lib = hif.load_library()
+    x, y = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    assert lib.hif_solve_noalloc(None, x, y, 1, None) == B.HIF_EINVAL
+    assert b"handle" in lib.hif_last_error()
+    h = ctypes.c_void_p(0x3000)  # never dereferenced: the checks fail first
+    assert lib.hif_solve_noalloc(h, None, y, 1, None) == B.HIF_EINVAL
+    assert lib.hif_solve_noalloc(h, x, y, 0, None) == B.HIF_EINVAL
+    assert hif.HIF_SOLVE_NOALLOC_MAX == 4 << 20
