@@ -362,8 +362,13 @@ __global__ void k_top(const double* LU, const int32_t* piv, int n, const int32_t
 // ---------------------------------------------------------------------------
 constexpr int kNbT = 64;
 constexpr int kMaxV = 8;       // right-hand sides per pass
-constexpr int kCapS = 4096;    // LDS doubles, small groups
-constexpr int kCapL = 16384;   // LDS doubles, large groups and the top block
+constexpr int kCapL = 16384;   // LDS doubles, largest records and the top block
+// Sub-levels with at least this many records run 256 threads per record,
+// fewer records 1024 threads each.
+constexpr int kManyRecords = 1024;
+// Top blocks of at least this many unknowns are solved by the many-workgroup
+// blocked triangular solves (one workgroup is latency-bound there).
+constexpr int64_t kTopSplitMin = 512;
 
 // The helpers below issue their global loads eight at a time before using
 // them, so that a single workgroup (one per large group) keeps many requests
@@ -614,12 +619,13 @@ __device__ __forceinline__ void l_permute(const int32_t* perm, int n, double* x,
   __syncthreads();
 }
 
-// One group per workgroup; op 0 solve, 1 solve_T; down = 0 for the upward
-// sweep (finest sub-level first), 1 for the downward one.  The caller
-// guarantees 2r + k <= CAP.
-template <int CAP>
-__global__ __launch_bounds__(kBlock) void k_sweep_lds(SwArgs A, int down) {
-  __shared__ double sm[CAP];
+// One group per workgroup of BS threads; op 0 solve, 1 solve_T; down = 0 for
+// the upward sweep (finest sub-level first), 1 for the downward one.  The LDS
+// holds cap doubles (sized by the launch to the sub-level's largest record);
+// the caller guarantees 2r + k <= cap.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_sweep_lds(SwArgs A, int down, int cap) {
+  extern __shared__ double sm[];
   const GroupRec R = A.recs[blockIdx.x];
   const int r = R.r, k = R.k;
   const int32_t* rd = A.iarena + R.idx;
@@ -631,15 +637,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep_lds(SwArgs A, int down) {
   const double* LU = Urs + int64_t(r) * k;
   const int64_t N = A.N;
   const int tid = threadIdx.x;
-  const int nvb = max(1, min(A.nrhs, CAP / (2 * r + k)));
+  const int nvb = max(1, min(A.nrhs, cap / (2 * r + k)));
   for (int v0 = 0; v0 < A.nrhs; v0 += nvb) {
     const int nv = min(nvb, A.nrhs - v0);
     double* xr = sm;           // [nv][r]
     double* xs = sm + nv * r;  // [nv][k]
     double* tp = xs + nv * k;  // [nv][r]
     double* u = A.u + v0 * N;
-    for (int e = tid; e < nv * r; e += kBlock) xr[e] = u[(e / r) * N + rd[e % r]];
-    for (int e = tid; e < nv * k; e += kBlock) xs[e] = u[(e / k) * N + sk[e % k]];
+    for (int e = tid; e < nv * r; e += BS) xr[e] = u[(e / r) * N + rd[e % r]];
+    for (int e = tid; e < nv * k; e += BS) xs[e] = u[(e / k) * N + sk[e % k]];
     __syncthreads();
     if (A.op == 0 && !down) {
       if (k > 0) l_gemv_t(T, k, r, r, xs, k, xr, r, nv, -1.0);  // u_r -= T^T u_s
@@ -665,8 +671,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_lds(SwArgs A, int down) {
       if (k > 0) l_gemv_n(T, k, r, r, xr, r, xs, k, nv, -1.0);    // u_s -= T u_r
     }
     __syncthreads();
-    for (int e = tid; e < nv * r; e += kBlock) u[(e / r) * N + rd[e % r]] = xr[e];
-    for (int e = tid; e < nv * k; e += kBlock) u[(e / k) * N + sk[e % k]] = xs[e];
+    for (int e = tid; e < nv * r; e += BS) u[(e / r) * N + rd[e % r]] = xr[e];
+    for (int e = tid; e < nv * k; e += BS) u[(e / k) * N + sk[e % k]] = xs[e];
     __syncthreads();
   }
 }
@@ -1068,10 +1074,23 @@ void launch_make_perm_top(const int32_t* piv, int32_t* perm, int n, hipStream_t 
   HIF_HIP(hipGetLastError());
 }
 
+// Dynamic LDS of the staged sweeps goes up to kCapL doubles (128 KiB).
+static void allow_large_lds() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const int bytes = kCapL * int(sizeof(double));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_lds<256>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_lds<1024>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipGetLastError();
+  });
+}
+
 // A top block too large for LDS is solved like a large record with no
 // skeleton through the many-workgroup triangular solves.
 static bool top_split_solve(const hif_factor_s* H) {
-  return H->ntop > 0 && 2 * H->ntop > kCapL && 2 * H->ntop <= H->n;
+  return H->ntop >= kTopSplitMin && 2 * H->ntop <= H->n;
 }
 
 // The sweeps proper.  work: min(nrhs, 8) * N doubles of scratch, reused by
@@ -1116,11 +1135,19 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
         hipLaunchKernelGGL(k_sp_scatter, gr, dim3(256), 0, s, P);
         return;
       }
-      if (op <= 1 && int64_t(sub.max_2rk) * nv <= kCapS)
-        hipLaunchKernelGGL(k_sweep_lds<kCapS>, dim3(sub.nrec), dim3(kBlock), 0, s, A, down);
-      else if (op <= 1 && sub.max_2rk <= kCapL)
-        hipLaunchKernelGGL(k_sweep_lds<kCapL>, dim3(sub.nrec), dim3(kBlock), 0, s, A, down);
-      else if (down)
+      if (op <= 1 && sub.max_2rk <= kCapL) {
+        allow_large_lds();
+        // LDS for as many right-hand sides per pass as fit (all of them when
+        // the records are small); 1024 threads per record when the records
+        // are too few to give every CU several workgroups
+        const int nvb = std::max(1, std::min(nv, kCapL / sub.max_2rk));
+        const int cap = nvb * sub.max_2rk;
+        const size_t lds = size_t(cap) * sizeof(double);
+        if (sub.nrec >= kManyRecords)
+          hipLaunchKernelGGL(k_sweep_lds<256>, dim3(sub.nrec), dim3(256), lds, s, A, down, cap);
+        else
+          hipLaunchKernelGGL(k_sweep_lds<1024>, dim3(sub.nrec), dim3(1024), lds, s, A, down, cap);
+      } else if (down)
         hipLaunchKernelGGL(k_down, dim3(sub.nrec), dim3(kBlock), 0, s, A);
       else
         hipLaunchKernelGGL(k_up, dim3(sub.nrec), dim3(kBlock), 0, s, A);
@@ -1178,6 +1205,32 @@ void prepare_sweeps(hif_factor_s* H, hipStream_t s) {
 void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s) {
   H->work.ensure(std::min<int64_t>(nrhs, 8) * H->n, &H->mem);
   sweep_run(H, op, x, y, nrhs, s, H->work.p);
+}
+
+// The launches of one solve u = F^{-1} f recorded into a HIP graph by stream
+// capture on a private stream (kernel nodes only), then instantiated.  The
+// sweep scratch is allocated before the capture starts.
+void graph_solve_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, hipStream_t cs,
+                      hipGraph_t* graph, hipGraphExec_t* exec) {
+  H->work.ensure(std::min<int64_t>(nrhs, 8) * H->n, &H->mem);
+  allow_large_lds();
+  HIF_HIP(hipStreamSynchronize(cs));
+  HIF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  try {
+    sweep_run(H, 0, f, u, nrhs, cs, H->work.p);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(cs, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIF_HIP(hipStreamEndCapture(cs, graph));
+  const hipError_t e = hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(*graph);
+    *graph = nullptr;
+    throw Error{HIF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+  }
 }
 
 // ---------------------------------------------------------------------------
