@@ -303,7 +303,11 @@ def cpu_baseline_batch(prob, eps: float):
 
 
 def bench_batch(args, quiet=False):
-    """48 independent problems: concurrent factorization (4 worker streams), then every solve."""
+    """48 independent problems: one step = the level-synchronous batch factorization
+    (hif_factor_batch, nworkers = 0: every sub-level one launch sequence over all
+    problems) + every problem's 4-RHS solve.  Per-solve latency p50 / p99 from replays
+    of graph-captured solves (hif_solve_graph) and from eager solves; the factorization
+    on 4 concurrent worker threads for comparison."""
     import numpy as np
     import torch
 
@@ -317,23 +321,16 @@ def bench_batch(args, quiet=False):
     dp = [dict(points=torch.tensor(p["points"], device=dev), a=torch.tensor(p["a"], device=dev), h=p["h"],
                eps=p["eps"], leaf=p["leaf"]) for p in probs]
     fs = [torch.tensor(p["f"], device=dev) for p in probs]
-    nw = 4
 
-    def step(nworkers=nw, lat=None):
+    def factor(nworkers=0):
         facs, st = hif.factor_batch(dp, nworkers=nworkers)
         if any(x != 0 for x in st):
             raise RuntimeError(f"batch factorization failed: {st}")
-        us = []
-        for F, f in zip(facs, fs):
-            if lat is not None:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                us.append(F.solve(f))
-                e1.record()
-                lat.append((e0, e1))
-            else:
-                us.append(F.solve(f))
-        return facs, us
+        return facs
+
+    def step(nworkers=0):
+        facs = factor(nworkers)
+        return facs, [F.solve(f) for F, f in zip(facs, fs)]
 
     for _ in range(args.warmup):
         facs, _ = step()
@@ -345,29 +342,54 @@ def bench_batch(args, quiet=False):
     for _ in range(args.steps):
         facs, us = step()
         torch.cuda.synchronize()
-        stats.append([F.stats() for F in facs])
+        stats.append(facs[0].stats())
         for F in facs:
             F.free()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    # one worker (one factorization at a time) for comparison, and per-solve latency
+    # the same factorizations on 4 concurrent worker threads, for comparison
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    lat = []
-    facs, us = step(nworkers=1, lat=lat)
+    facs4 = factor(4)
     torch.cuda.synchronize()
-    dt1 = time.perf_counter() - t1
-    lat_ms = np.array([e0.elapsed_time(e1) for e0, e1 in lat])
+    dt4 = time.perf_counter() - t1
+    for F in facs4:
+        F.free()
+    # per-solve latency: eager solves, and replays of graph-captured solves
+    facs, us = step()
+    torch.cuda.synchronize()
     err = 0.0
     for F, u, f in zip(facs, us, fs):
         y, _ = F.apply_A(u)
         err = max(err, (torch.linalg.norm(y - f, dim=1) / torch.linalg.norm(f, dim=1)).max().item())
-    st = stats[-1]
-    id_bytes = float(sum(np.sum(s["sub_id_bytes"]) for s in st))
-    id_ms = float(sum(s["t_phase_ms"]["id"] for s in st))
+
+    def latencies(run):
+        out = []
+        for i in range(len(facs)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run(i)
+            e1.record()
+            out.append((e0, e1))
+        torch.cuda.synchronize()
+        return np.array([a.elapsed_time(b) for a, b in out])
+
+    outs = [torch.empty_like(f) for f in fs]
+    graphs = [F.solve_graph(f, o) for F, f, o in zip(facs, fs, outs)]
+    for g in graphs:  # one warm replay each
+        g.launch()
+    lat_eager = np.concatenate([latencies(lambda i: facs[i].solve(fs[i], out=outs[i])) for _ in range(3)])
+    lat_graph = np.concatenate([latencies(lambda i: graphs[i].launch()) for _ in range(3)])
+    same = all(torch.equal(o, u) for o, u in zip(outs, us))
+    for g in graphs:
+        g.free()
     for F in facs:
         F.free()
-    achieved = id_bytes / (id_ms * 1e-3) / 1e9 if id_ms > 0 else 0.0
+    ph = stats[-1]["t_phase_ms"]  # phase times of the whole batch
+
+    def pct(x):
+        return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99)), "max": float(x.max())}
+
     line = {
         "metric": "batch factor+solve unknowns/s (48 uneven problems)",
         "value": Ntot / dt, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -375,17 +397,12 @@ def bench_batch(args, quiet=False):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"batch48: 48 independent 2D second-kind Laplace volume IEs, sides from "
                                f"{{64, 96, 128, 192, 256}} (N total {Ntot}), a = 1 + scaled Gaussian bumps, "
-                               f"4 RHS each, eps 1e-6, leaves 36 or 64 points, FP64; hif_factor_batch with "
-                               f"{nw} worker streams, then every 4-RHS solve", "N_total": Ntot, "problems": 48},
-        "accuracy": {"rel_residual_max": err},
-        "one_worker_ms_per_step": dt1 * 1e3,
-        "solve_latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
-                             "max": float(lat_ms.max())},
-        "roofline": {"kernel": "k_bq_piv + k_bq_cols + k_bq_update + k_id_reg + k_id (column-pivoted QR of "
-                               "the IDs); per-problem HIP-event times summed, so concurrent problems overlap",
-                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_step": id_bytes,
-                     "ms_per_step": id_ms},
+                               f"4 RHS each, eps 1e-6, leaves 36 or 64 points, FP64; level-synchronous "
+                               f"hif_factor_batch, then every 4-RHS solve", "N_total": Ntot, "problems": 48},
+        "accuracy": {"rel_residual_max": err, "graph_replay_equals_eager": bool(same)},
+        "factor_ms_4_worker_threads": dt4 * 1e3,
+        "solve_latency_ms": {"graph_replay": pct(lat_graph), "eager": pct(lat_eager)},
+        "phase_ms": ph,
     }
     if not args.no_cpu_baseline:
         small = min(probs, key=lambda p: p["n"])
@@ -597,7 +614,7 @@ def main():
         # the two other workloads, briefly (their own bench lines: --workload diff256 / batch48)
         class _A:
             steps, warmup, eps, no_cpu_baseline = 2, 1, None, True
-        keep = ("metric", "value", "unit", "ms_per_step", "accuracy", "modes", "one_worker_ms_per_step",
+        keep = ("metric", "value", "unit", "ms_per_step", "accuracy", "modes", "factor_ms_4_worker_threads",
                 "solve_latency_ms")
         line["other_workloads"] = {
             "diff256": {k: v for k, v in bench_diff(_A, quiet=True).items() if k in keep},

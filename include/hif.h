@@ -197,6 +197,27 @@ hif_status hif_solve(hif_handle h, const double* f, double* u, int64_t nrhs, hif
 hif_status hif_solve_T(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream stream);
 
 /*
+ * Solve sweeps recorded once as a HIP graph and replayed (for repeated
+ * solves with the same factors, vectors and right-hand-side count, e.g. the
+ * solves of a batch of factorizations, where the launch overhead of the
+ * sweeps matters).  hif_solve_graph captures the launches hif_solve would
+ * make for u = F^{-1} f (eqn hifie2/hifie3 second line) on a private stream
+ * (kernel nodes only) and instantiates the graph; hif_graph_launch replays it
+ * on a stream, reading f and writing u at the addresses given at capture.
+ * f, u: [nrhs][n] device arrays that must stay valid while the graph is used;
+ * f == u allowed.  The graph uses the handle's factors and sweep scratch:
+ * free the graph before the handle, and do not overlap replays (or other
+ * sweeps) of one handle on different streams.  hif_solve_graph is
+ * host-blocking and allocates the sweep scratch before capturing;
+ * hif_graph_launch is stream-ordered.  HIF_EINVAL on NULL arguments or
+ * nrhs < 1, HIF_EDEVICE if capture or instantiation fails.
+ */
+typedef struct hif_graph_s* hif_graph;
+hif_status hif_solve_graph(hif_handle h, const double* f, double* u, int64_t nrhs, hif_graph* out);
+hif_status hif_graph_launch(hif_graph g, hif_stream stream);
+void hif_graph_free(hif_graph g);
+
+/*
  * u = F^{-1} f exactly as hif_solve, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid allocation): the sweep scratch is a static device array of the
@@ -308,12 +329,21 @@ typedef struct {
 } hif_problem;
 
 /*
- * Factor independent problems concurrently (each as hif_factor would, with
- * the same opts): nworkers host threads (1..16), each with a HIP stream of
- * its own, take the problems largest first, so that small factorizations,
- * whose launches cannot fill the GPU one at a time, overlap on the device.
- * The paper factors one operator at a time; its sub-levels are independent
- * across problems as they are across groups (Section 4).
+ * Factor independent problems together, with the same opts.  The paper
+ * factors one operator at a time; the groups of a sub-level are independent
+ * (Section 2.3: the products over a level can be taken in any order), across
+ * problems as within one.
+ *   nworkers = 0: level-synchronous: sub-level l of every problem (level
+ *             l counted from the leaves; problems with shallower trees drop
+ *             out first) runs as one launch sequence over the concatenated
+ *             groups of all problems, with one host read-back of the ranks
+ *             per stage for the whole batch; the top blocks are LU-factored
+ *             in one batched launch sequence.  Problems that share dim and
+ *             the symmetric compression are factored together.  Each handle
+ *             then owns its factors, as from hif_factor; its phase times
+ *             (hif_stats) are those of the whole batch.
+ *   nworkers = 1..16: that many host threads, each with a HIP stream of its
+ *             own, run hif_factor on the problems largest first.
  *   problems: [count] host array; the arrays it points to are device arrays
  *             as for hif_factor and must stay valid until the call returns.
  *   out:      [count] host array of handles (NULL where a problem failed).
@@ -321,9 +351,58 @@ typedef struct {
  * Blocks until every factorization's device work is done; the handles then
  * serve any stream.  Returns HIF_OK, or the first failing problem's status
  * (hif_last_error names the problem); the other handles are still valid.
+ * Invalid arguments of one problem fail that problem alone; in the
+ * level-synchronous mode a failure of the joint factorization (a singular
+ * block, the memory cap, which then applies to the whole set) is reported
+ * for every problem factored with it.
  */
 hif_status hif_factor_batch(const hif_problem* problems, int32_t count, const hif_opts* opts, int32_t nworkers,
                             hif_handle* out, hif_status* status);
+
+/*
+ * Launch shapes the factorization picks by problem size, per size bucket:
+ *   id_reg_waves[b]: waves (of 64 lanes) per problem of the register-resident
+ *     pivoted QR of the IDs, for problems of at most 64 (b = 0), 128 (b = 1)
+ *     and 192 (b = 2) columns after row compression; each wave holds
+ *     64 * (b + 1) / waves rows of every column.  Allowed: 4, 8 or 16 for
+ *     b = 0 and 1, 8 or 16 for b = 2.
+ *   lu_panel_threads[b]: threads of the register-resident LU panel (partial
+ *     pivoting, Lemma 2.1) for panels of at most 512 (b = 0) and 1024 (b = 1)
+ *     rows; allowed 256, 512 or 1024 for b = 0, 512 or 1024 for b = 1.
+ * The built-in table comes from paper_1307_2666_amd/tune.py, which times the
+ * candidates with hif_id_batched and hif_lu_batched.  hif_tuning_set(NULL)
+ * restores it; any other call replaces the table for the whole process (calls
+ * already queued keep the shapes they were launched with).  HIF_EINVAL for an
+ * entry outside the allowed values (the table is then unchanged).
+ */
+typedef struct {
+  int32_t id_reg_waves[3];
+  int32_t lu_panel_threads[2];
+} hif_tuning;
+hif_status hif_tuning_get(hif_tuning* out);
+hif_status hif_tuning_set(const hif_tuning* t);
+
+/*
+ * Batched partial LU with partial pivoting (Lemma 2.1): the kernel the
+ * factorization uses on the transformed blocks [B_rr B_rs; B_sr B_ss] of
+ * the skeletonized groups and on the top block, exposed on its own.  Matrix
+ * p is mats + off[p], n[p] x n[p] row-major; its first r[p] columns are
+ * eliminated with pivot rows chosen among rows < r[p] (the redundant block):
+ * on return rows/columns < r[p] hold the unit-lower L11 and upper U11 of
+ * P B_rr = L11 U11, the rows < r[p] of columns >= r[p] hold
+ * U12 = L11^{-1} P B_rs, the columns < r[p] of rows >= r[p] hold
+ * L21 = B_sr U11^{-1}, and the trailing block holds the Schur complement
+ * B_ss - L21 U12.  piv + poff[p] receives the r[p] row interchanges
+ * (row j swapped with row piv[j], in order j = 0..r-1).  off, poff (int64),
+ * n, r (int32): device arrays of length batch; max_n, max_r: the largest n
+ * and r.  status: device int32 that the caller clears; set to nonzero on a
+ * zero pivot (HIF_ESINGULAR is not returned: the call is asynchronous).
+ * Stream-ordered; allocates nothing.  HIF_EINVAL on NULL arrays, batch < 0,
+ * or max_r > max_n.
+ */
+hif_status hif_lu_batched(double* mats, const int64_t* off, const int32_t* n, const int32_t* r, int32_t* piv,
+                          const int64_t* poff, int32_t batch, int32_t max_n, int32_t max_r, int32_t* status,
+                          hif_stream stream);
 
 /* Release a handle and all its device memory (NULL is a no-op). */
 void hif_free(hif_handle h);

@@ -7,9 +7,9 @@ Algorithm 3.1); the returned handle applies ``F``, ``F^T``, ``F^{-1}``,
 the solve as a differentiable function of ``a`` and ``f``.
 """
 from ._binding import (EXPORTS, HIF_EDEVICE, HIF_EINVAL, HIF_ENOMEM, HIF_ESINGULAR, HIF_EUNSUPPORTED,  # noqa: F401
-                       HIF_FP32_MIXED, HIF_FP64, HIF_OK, HIF_SOLVE_NOALLOC_MAX, Factorization, HifError, LIB_PATH,
-                       default_opts, diag_grad, factor, factor_batch, id_batched, load_library, matvec,
-                       partition)
+                       HIF_FP32_MIXED, HIF_FP64, HIF_OK, HIF_SOLVE_NOALLOC_MAX, Factorization, HifError, LIB_PATH, SolveGraph,
+                       default_opts, diag_grad, factor, factor_batch, id_batched, load_library, lu_batched, matvec,
+                       partition, tuning_get, tuning_set)
 from . import diff  # noqa: F401
 
 __all__ = ["factor", "factor_batch", "matvec", "id_batched", "partition", "diag_grad", "diff", "Factorization", "HifError",

@@ -46,6 +46,10 @@ class hif_problem(ctypes.Structure):
                 ("leaf", ctypes.c_int32)]
 
 
+class hif_tuning(ctypes.Structure):
+    _fields_ = [("id_reg_waves", ctypes.c_int32 * 3), ("lu_panel_threads", ctypes.c_int32 * 2)]
+
+
 class hif_stats_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("n_sublevels", ctypes.c_int32), ("top_size", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
@@ -84,6 +88,12 @@ EXPORTS = {
     "hif_apply_A": (_INT, [_VP, _VP, _VP, _I64, _INT, _VP, _VP]),
     "hif_factor_batch": (_INT, [_VP, _I32, _VP, _I32, _VP, _VP]),
     "hif_solve_noalloc": (_INT, [_VP, _VP, _VP, _I64, _VP]),
+    "hif_solve_graph": (_INT, [_VP, _VP, _VP, _I64, _VP]),
+    "hif_graph_launch": (_INT, [_VP, _VP]),
+    "hif_graph_free": (None, [_VP]),
+    "hif_tuning_get": (_INT, [_VP]),
+    "hif_tuning_set": (_INT, [_VP]),
+    "hif_lu_batched": (_INT, [_VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP]),
 }
 HIF_SOLVE_NOALLOC_MAX = 4 << 20
 
@@ -170,6 +180,21 @@ class Factorization:
         static scratch (no device allocation in the library)."""
         return self._run(load_library().hif_solve_noalloc, f, out, stream)
 
+    def solve_graph(self, f, out):
+        """``hif_solve_graph``: record the solve ``out = F^{-1} f`` once as a HIP graph;
+        ``SolveGraph.launch()`` replays it (same vectors).  Keep ``f`` and ``out`` alive."""
+        if self._h is None:
+            raise RuntimeError("factorization has been freed")
+        X = f.reshape(1, -1) if f.dim() == 1 else f
+        if X.shape[-1] != self.n or not X.is_cuda or X.dtype != torch.float64 or not X.is_contiguous():
+            raise ValueError(f"f must be a contiguous float64 device array with last dimension n = {self.n}")
+        if out.shape != f.shape or not out.is_cuda or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device array shaped like f")
+        torch.cuda.synchronize()  # the capture stream is not ordered after torch's
+        g = ctypes.c_void_p()
+        _check(load_library().hif_solve_graph(self._h, _ptr(X), _ptr(out), X.shape[0], ctypes.byref(g)))
+        return SolveGraph(g, (f, out, self))
+
     def solve_T(self, f, out=None, stream=None):
         return self._run(load_library().hif_solve_T, f, out, stream)
 
@@ -242,6 +267,31 @@ class Factorization:
             pass
 
 
+class SolveGraph:
+    """A solve recorded as a HIP graph (``hif_solve_graph``); ``launch`` replays it."""
+
+    def __init__(self, g, keep):
+        self._g = g
+        self._keep = keep
+
+    def launch(self, stream=None):
+        if self._g is None:
+            raise RuntimeError("graph has been freed")
+        _check(load_library().hif_graph_launch(self._g, _stream(stream)))
+
+    def free(self):
+        if self._g is not None:
+            load_library().hif_graph_free(self._g)
+            self._g = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, selfk=None,
            second_kind=-1, symmetric=-1, variant="hifie", n_proxy=0, proxy_radius=0.0,
            max_bytes=0, precision=HIF_FP64, row_compression=-1, fft_matvec=0, stream=None) -> Factorization:
@@ -270,13 +320,15 @@ def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, s
     return Factorization(handle, n, d, None)
 
 
-def factor_batch(problems, *, nworkers=4, precision=HIF_FP64, second_kind=-1, symmetric=-1, variant="hifie",
+def factor_batch(problems, *, nworkers=0, precision=HIF_FP64, second_kind=-1, symmetric=-1, variant="hifie",
                  max_bytes=0, row_compression=-1, fft_matvec=0):
-    """``hif_factor_batch``: factor independent problems concurrently.
+    """``hif_factor_batch``: factor independent problems together.
 
     ``problems`` is a list of dicts with the ``factor`` arguments ``points``, ``eps``,
-    ``leaf`` and optionally ``a``, ``b``, ``c``, ``h``, ``weights``, ``selfk``.  Returns
-    ``(factorizations, statuses)``; a failed problem's entry is ``None``."""
+    ``leaf`` and optionally ``a``, ``b``, ``c``, ``h``, ``weights``, ``selfk``.
+    ``nworkers=0``: level-synchronous (every sub-level one launch sequence over all
+    problems); ``1..16``: that many worker threads running ``factor`` concurrently.
+    Returns ``(factorizations, statuses)``; a failed problem's entry is ``None``."""
     lib = load_library()
     cnt = len(problems)
     arr = (hif_problem * max(cnt, 1))()
@@ -392,3 +444,46 @@ def partition(points, active, kind, S, stream=None):
     grp = torch.empty(n, dtype=torch.int32, device="cuda")
     _check(lib.hif_partition(_ptr(P), n, d, _ptr(act), int(kind), int(S), _ptr(grp), _stream(stream)))
     return grp
+
+
+def tuning_get() -> dict:
+    """``hif_tuning_get``: the launch-shape table in use."""
+    t = hif_tuning()
+    _check(load_library().hif_tuning_get(ctypes.byref(t)))
+    return {"id_reg_waves": list(t.id_reg_waves), "lu_panel_threads": list(t.lu_panel_threads)}
+
+
+def tuning_set(table=None):
+    """``hif_tuning_set``: replace the launch-shape table (``None``: the built-in one)."""
+    if table is None:
+        _check(load_library().hif_tuning_set(None))
+        return
+    t = hif_tuning()
+    t.id_reg_waves[:] = list(table["id_reg_waves"])
+    t.lu_panel_threads[:] = list(table["lu_panel_threads"])
+    _check(load_library().hif_tuning_set(ctypes.byref(t)))
+
+
+def lu_batched(mats, rs, stream=None):
+    """``hif_lu_batched`` on a list of square matrices with the numbers of columns to
+    eliminate ``rs``; returns ``([factored matrix], [row interchanges], zero_pivot)`` on the CPU."""
+    lib = load_library()
+    ns = [int(m.shape[0]) for m in mats]
+    flat = torch.cat([_dev(m).reshape(-1) for m in mats])
+    offs, poffs = [0], [0]
+    for n, r in zip(ns, rs):
+        offs.append(offs[-1] + n * n)
+        poffs.append(poffs[-1] + int(r))
+    dev = dict(device="cuda")
+    off = torch.tensor(offs[:-1], dtype=torch.int64, **dev)
+    poff = torch.tensor(poffs[:-1], dtype=torch.int64, **dev)
+    n_t = torch.tensor(ns, dtype=torch.int32, **dev)
+    r_t = torch.tensor([int(r) for r in rs], dtype=torch.int32, **dev)
+    piv = torch.zeros(max(poffs[-1], 1), dtype=torch.int32, **dev)
+    status = torch.zeros(1, dtype=torch.int32, **dev)
+    _check(lib.hif_lu_batched(_ptr(flat), _ptr(off), _ptr(n_t), _ptr(r_t), _ptr(piv), _ptr(poff), len(mats),
+                              max(ns), max(int(r) for r in rs), _ptr(status), _stream(stream)))
+    flat, piv = flat.cpu(), piv.cpu()
+    out = [flat[offs[i]:offs[i + 1]].reshape(ns[i], ns[i]) for i in range(len(mats))]
+    pv = [piv[poffs[i]:poffs[i + 1]] for i in range(len(mats))]
+    return out, pv, bool(status.item())

@@ -14,7 +14,15 @@
 #include <thread>
 #include <vector>
 
+#include "batched.h"
 #include "common.h"
+#include "tuning_gfx950.h"
+
+// A captured solve: the graph and its executable instance.
+struct hif_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 namespace hif {
 
@@ -143,6 +151,35 @@ bool dbuf_give(void* p, size_t cls, hipStream_t s) {
   return true;
 }
 
+namespace {
+std::mutex g_tune_mu;
+hif_tuning builtin_tuning() {
+  hif_tuning t{HIF_TUNED_ID_REG_WAVES, HIF_TUNED_LU_PANEL_THREADS};
+  return t;
+}
+hif_tuning g_tune = builtin_tuning();
+}  // namespace
+
+hif_tuning tuning() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tune;
+}
+
+bool set_tuning(const hif_tuning* t) {
+  const hif_tuning v = t ? *t : builtin_tuning();
+  auto in = [](int x, std::initializer_list<int> ok) {
+    for (int o : ok)
+      if (x == o) return true;
+    return false;
+  };
+  if (!in(v.id_reg_waves[0], {4, 8, 16}) || !in(v.id_reg_waves[1], {4, 8, 16}) || !in(v.id_reg_waves[2], {8, 16}) ||
+      !in(v.lu_panel_threads[0], {256, 512, 1024}) || !in(v.lu_panel_threads[1], {512, 1024}))
+    return false;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune = v;
+  return true;
+}
+
 // Runs f with DBuf memory ordered on stream s; errors become a status.
 template <class F>
 hif_status guarded(hipStream_t s, F&& f) {
@@ -191,11 +228,11 @@ hif_status hif_opts_default(hif_opts* o) {
 
 const char* hif_last_error(void) { return g_last_error.c_str(); }
 
-hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel* k, const double* a,
-                      const double* b, const double* c, double eps, int32_t leaf, const hif_opts* opts,
-                      hif_stream stream, hif_handle* out) {
-  if (!out) return fail(HIF_EINVAL, "out is NULL");
-  *out = nullptr;
+}  // extern "C"
+
+// Checks of hif_factor's problem arguments (everything but the handle).
+static hif_status check_problem(const double* points, int64_t n, int dim, const hif_kernel* k, double eps,
+                                int32_t leaf) {
   if (!points) return fail(HIF_EINVAL, "points is NULL");
   if (n < 1) return fail(HIF_EINVAL, "n must be >= 1");
   if (n > int64_t(INT32_MAX) - 1) return fail(HIF_EINVAL, "n must fit in int32");
@@ -203,6 +240,11 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
   if (hif_status s = check_kernel(k); s != HIF_OK) return s;
   if (!(eps > 0.0 && eps < 1.0)) return fail(HIF_EINVAL, "eps must satisfy 0 < eps < 1");
   if (leaf < 1) return fail(HIF_EINVAL, "leaf must be >= 1");
+  return HIF_OK;
+}
+
+// Options with the defaults filled in and checked.
+static hif_status resolve_opts(const hif_opts* opts, hif_opts* out) {
   hif_opts o;
   hif_opts_default(&o);
   if (opts) o = *opts;
@@ -221,17 +263,36 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
   // second-kind modification by default in FP64 only: in FP32 the SCI-scaled
   // tolerance rho * eps falls below single-precision resolution
   if (o.second_kind < 0) o.second_kind = o.precision == HIF_FP64 ? 1 : 0;
+  *out = o;
+  return HIF_OK;
+}
+
+static std::unique_ptr<hif_factor_s> new_handle(int64_t n, int dim, double eps, int32_t leaf, const hif_opts& o) {
+  std::unique_ptr<hif_factor_s> h(new hif_factor_s());
+  h->n = n;
+  h->dim = dim;
+  h->eps = eps;
+  h->leaf = leaf;
+  h->opts = o;
+  h->nproxy = o.n_proxy ? o.n_proxy : (dim == 2 ? 64 : 512);
+  h->proxy_r = o.proxy_radius > 0.0 ? o.proxy_radius : 1.5;
+  h->mem.cap = o.max_bytes;
+  return h;
+}
+
+extern "C" {
+
+hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel* k, const double* a,
+                      const double* b, const double* c, double eps, int32_t leaf, const hif_opts* opts,
+                      hif_stream stream, hif_handle* out) {
+  if (!out) return fail(HIF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (hif_status st = check_problem(points, n, dim, k, eps, leaf); st != HIF_OK) return st;
+  hif_opts o;
+  if (hif_status st = resolve_opts(opts, &o); st != HIF_OK) return st;
   hif_handle H = nullptr;
   hif_status st = guarded(hipStream_t(stream), [&] {
-    std::unique_ptr<hif_factor_s> h(new hif_factor_s());
-    h->n = n;
-    h->dim = dim;
-    h->eps = eps;
-    h->leaf = leaf;
-    h->opts = o;
-    h->nproxy = o.n_proxy ? o.n_proxy : (dim == 2 ? 64 : 512);
-    h->proxy_r = o.proxy_radius > 0.0 ? o.proxy_radius : 1.5;
-    h->mem.cap = o.max_bytes;
+    std::unique_ptr<hif_factor_s> h = new_handle(n, dim, eps, leaf, o);
     factor_impl(h.get(), points, k, a, b, c, hipStream_t(stream));
     H = h.release();
   });
@@ -239,16 +300,95 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
   return st;
 }
 
+// Level-synchronous factorization of the whole batch (nworkers == 0): every
+// problem is checked and set up on its own (a failure stays with its
+// problem), then the problems that share dim and the symmetric compression
+// are factored together, each sub-level one launch sequence over all of
+// them; a failure there is reported for every problem of that set.
+static hif_status factor_batch_fused(const hif_problem* problems, int32_t count, const hif_opts* opts,
+                                     hif_handle* out, std::vector<hif_status>& st, std::vector<std::string>& msg) {
+  hif_opts o;
+  if (hif_status e = resolve_opts(opts, &o); e != HIF_OK) return e;
+  bool any = false;
+  for (int32_t p = 0; p < count; ++p) {
+    const hif_problem& q = problems[p];
+    st[p] = check_problem(q.points, q.n, q.dim, &q.kernel, q.eps, q.leaf);
+    if (st[p] != HIF_OK) msg[p] = g_last_error;
+    any = any || st[p] == HIF_OK;
+  }
+  if (!any) return HIF_OK;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+    return fail(HIF_EDEVICE, "creating the batch stream failed");
+  std::vector<std::unique_ptr<hif_factor_s>> hs(count);
+  for (int32_t p = 0; p < count; ++p) {
+    const hif_problem& q = problems[p];
+    if (st[p] == HIF_OK)
+      st[p] = guarded(s, [&] {
+        std::unique_ptr<hif_factor_s> h = new_handle(q.n, q.dim, q.eps, q.leaf, o);
+        prepare_problem(h.get(), q.points, &q.kernel, q.a, q.b, q.c, s);
+        hs[p] = std::move(h);
+      });
+    if (st[p] != HIF_OK) msg[p] = g_last_error;
+  }
+  // sets of problems that can share launches: same dim and symmetric compression
+  std::vector<char> done(count, 0);
+  for (int32_t p = 0; p < count; ++p) {
+    if (!hs[p] || done[p]) continue;
+    std::vector<int32_t> set;
+    for (int32_t q = p; q < count; ++q)
+      if (hs[q] && !done[q] && hs[q]->dim == hs[p]->dim && hs[q]->symmetric == hs[p]->symmetric) {
+        set.push_back(q);
+        done[q] = 1;
+      }
+    std::vector<hif_factor_s*> ptrs;
+    for (int32_t q : set) ptrs.push_back(hs[q].get());
+    const hif_status e = guarded(s, [&] { factor_fused_impl(ptrs, s); });
+    for (int32_t q : set) {
+      if (e == HIF_OK) {
+        out[q] = hs[q].release();
+      } else {
+        st[q] = e;
+        msg[q] = g_last_error;
+        guarded(s, [&] { hs[q].reset(); });
+      }
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  release_thread_streams();
+  dbuf_drop_stream(s);
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+  return HIF_OK;
+}
+
 static hif_status factor_batch(const hif_problem* problems, int32_t count, const hif_opts* opts, int32_t nworkers,
                                hif_handle* out, hif_status* status) {
   if (count < 0) return fail(HIF_EINVAL, "count must be >= 0");
   if (count > 0 && (!problems || !out)) return fail(HIF_EINVAL, "problems and out must not be NULL");
-  if (nworkers < 1 || nworkers > 16) return fail(HIF_EINVAL, "nworkers must be in [1, 16]");
+  if (nworkers < 0 || nworkers > 16) return fail(HIF_EINVAL, "nworkers must be in [0, 16]");
   for (int32_t p = 0; p < count; ++p) {
     out[p] = nullptr;
     if (status) status[p] = HIF_OK;
   }
   if (count == 0) return HIF_OK;
+  if (nworkers == 0) {
+    std::vector<hif_status> st(count, HIF_OK);
+    std::vector<std::string> msg(count);
+    if (hif_status e = factor_batch_fused(problems, count, opts, out, st, msg); e != HIF_OK) return e;
+    hif_status first = HIF_OK;
+    std::string first_msg;
+    for (int32_t p = 0; p < count; ++p) {
+      if (status) status[p] = st[p];
+      if (st[p] != HIF_OK && first == HIF_OK) {
+        first = st[p];
+        first_msg = "problem " + std::to_string(p) + ": " + msg[p];
+      }
+    }
+    if (first != HIF_OK) return fail(first, first_msg);
+    g_last_error.clear();
+    return HIF_OK;
+  }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(HIF_EDEVICE, "no current HIP device");
   // largest problems first, so that the last ones to start are short
@@ -349,6 +489,41 @@ hif_status hif_apply(hif_handle h, const double* x, double* y, int64_t nrhs, hif
 }
 hif_status hif_apply_T(hif_handle h, const double* x, double* y, int64_t nrhs, hif_stream s) {
   return sweep(h, 3, x, y, nrhs, s);
+}
+
+hif_status hif_solve_graph(hif_handle h, const double* f, double* u, int64_t nrhs, hif_graph* out) {
+  if (!out) return fail(HIF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!h) return fail(HIF_EINVAL, "handle is NULL");
+  if (!f || !u) return fail(HIF_EINVAL, "vector pointer is NULL");
+  if (nrhs < 1) return fail(HIF_EINVAL, "nrhs must be >= 1");
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    return fail(HIF_EDEVICE, "creating the capture stream failed");
+  std::unique_ptr<hif_graph_s> g(new (std::nothrow) hif_graph_s());
+  hif_status st = g ? guarded(cs, [&] { graph_solve_impl(h, f, u, nrhs, cs, &g->graph, &g->exec); })
+                    : fail(HIF_ENOMEM, "host allocation failed");
+  (void)hipStreamSynchronize(cs);
+  dbuf_drop_stream(cs);
+  (void)hipStreamSynchronize(cs);
+  (void)hipStreamDestroy(cs);
+  if (st == HIF_OK) *out = g.release();
+  return st;
+}
+
+hif_status hif_graph_launch(hif_graph g, hif_stream s) {
+  if (!g) return fail(HIF_EINVAL, "graph is NULL");
+  const hipError_t e = hipGraphLaunch(g->exec, hipStream_t(s));
+  if (e != hipSuccess) return fail(HIF_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+  return HIF_OK;
+}
+
+void hif_graph_free(hif_graph g) {
+  if (!g) return;
+  (void)hipDeviceSynchronize();  // the graph may still run on any stream
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 hif_status hif_solve_noalloc(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream s) {
@@ -453,6 +628,39 @@ hif_status hif_id_batched(double* mats, const int64_t* off, const int32_t* rows,
   if (max_cols < 1 || max_cols > 4096) return fail(HIF_EINVAL, "max_cols must be in [1, 4096]");
   return guarded(hipStream_t(s), [&] {
     id_batched_impl(mats, off, rows, cols, tol, batch, max_cols, rank, perm, off_perm, T, off_t, hipStream_t(s));
+  });
+}
+
+hif_status hif_tuning_get(hif_tuning* out) {
+  if (!out) return fail(HIF_EINVAL, "out is NULL");
+  *out = tuning();
+  return HIF_OK;
+}
+
+hif_status hif_tuning_set(const hif_tuning* t) {
+  if (!set_tuning(t)) return fail(HIF_EINVAL, "launch-shape table entry outside the allowed values");
+  return HIF_OK;
+}
+
+hif_status hif_lu_batched(double* mats, const int64_t* off, const int32_t* n, const int32_t* r, int32_t* piv,
+                          const int64_t* poff, int32_t batch, int32_t max_n, int32_t max_r, int32_t* status,
+                          hif_stream s) {
+  if (batch < 0) return fail(HIF_EINVAL, "batch must be >= 0");
+  if (batch == 0) return HIF_OK;
+  if (!mats || !off || !n || !r || !piv || !poff || !status) return fail(HIF_EINVAL, "NULL pointer argument");
+  if (max_n < 1 || max_r < 0 || max_r > max_n) return fail(HIF_EINVAL, "need 0 <= max_r <= max_n and max_n >= 1");
+  return guarded(hipStream_t(s), [&] {
+    int32_t* st = status;
+    LuBatch lb{};
+    lb.base = mats;
+    lb.moff = off;
+    lb.n = n;
+    lb.r = r;
+    lb.piv = piv;
+    lb.poff = poff;
+    lb.status = st;
+    lb.nprob = batch;
+    launch_lu_batched(lb, max_r, max_n, hipStream_t(s));
   });
 }
 

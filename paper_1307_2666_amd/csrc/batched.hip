@@ -1469,6 +1469,7 @@ void launch_lu_batched(const LuBatch& A, int max_r, int max_n, hipStream_t s) {
     P.flag = flag.p;
     P.prow = prow.p;
   }
+  const hif_tuning tu = tuning();
   for (int j0 = 0; j0 < max_r; j0 += kNb) {
     if (max_n - j0 > kLpRows) {
       const dim3 g(unsigned((max_n - j0 + kLmRows - 1) / kLmRows), unsigned(A.nprob));
@@ -1477,12 +1478,19 @@ void launch_lu_batched(const LuBatch& A, int max_r, int max_n, hipStream_t s) {
       hipLaunchKernelGGL(k_lum_finish, dim3(unsigned((max_n + 255) / 256), unsigned(A.nprob)), dim3(256), 0, s, A,
                          P, j0, 0);
       hipLaunchKernelGGL(k_lum_finish, dim3(1, unsigned(A.nprob)), dim3(256), 0, s, A, P, j0, 1);
-    } else if (max_n - j0 <= kLpRows / 4)  // two rows per thread
-      hipLaunchKernelGGL(k_lu_panel_reg<256>, dim3(A.nprob), dim3(256), 0, s, A, j0);
-    else if (max_n - j0 <= kLpRows / 2)
-      hipLaunchKernelGGL(k_lu_panel_reg<512>, dim3(A.nprob), dim3(512), 0, s, A, j0);
-    else
-      hipLaunchKernelGGL(k_lu_panel_reg<1024>, dim3(A.nprob), dim3(1024), 0, s, A, j0);
+    } else {
+      // two rows per thread: at least (panel rows) / 2 threads; within that,
+      // the thread count of the launch-shape table for the panel's size
+      const int rows = max_n - j0;
+      int threads = rows <= kLpRows / 4 ? tu.lu_panel_threads[0] : (rows <= kLpRows / 2 ? tu.lu_panel_threads[1] : 1024);
+      if (2 * threads < rows) threads = rows <= kLpRows / 2 ? 512 : 1024;
+      if (threads == 256)
+        hipLaunchKernelGGL(k_lu_panel_reg<256>, dim3(A.nprob), dim3(256), 0, s, A, j0);
+      else if (threads == 512)
+        hipLaunchKernelGGL(k_lu_panel_reg<512>, dim3(A.nprob), dim3(512), 0, s, A, j0);
+      else
+        hipLaunchKernelGGL(k_lu_panel_reg<1024>, dim3(A.nprob), dim3(1024), 0, s, A, j0);
+    }
     const int rem = max_n - j0 - 1;
     if (rem > 0) {
       const unsigned tiles = unsigned((rem + 63) / 64);

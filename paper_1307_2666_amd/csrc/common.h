@@ -301,6 +301,13 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, size_t n, hipStream_t s
 // Factorization driver (factor.hip).
 void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* k, const double* a,
                  const double* b, const double* c, hipStream_t s);
+// Level-synchronous factorization of independent problems together: every
+// sub-level runs one launch sequence over the groups of all problems.  The
+// handles hold their operators (prepare_problem) and share dim, symmetric
+// compression and options; on return each holds its own factors.
+void prepare_problem(hif_factor_s* H, const double* points, const hif_kernel* k, const double* a,
+                     const double* b, const double* c, hipStream_t s);
+void factor_fused_impl(const std::vector<hif_factor_s*>& hs, hipStream_t s);
 
 // Gather form of the LU row interchanges of every record (sweep.hip).
 void launch_make_perm(const GroupRec* recs, int nrec, int32_t* iarena, int max_r, hipStream_t s);
@@ -312,6 +319,8 @@ void launch_make_perm_top(const int32_t* piv, int32_t* perm, int n, hipStream_t 
 // the library's static device scratch of kSolveScratchDoubles doubles.
 void sweep_impl(hif_factor_s* H, int op, const double* x, double* y, int64_t nrhs, hipStream_t s);
 void prepare_sweeps(hif_factor_s* H, hipStream_t s);
+void graph_solve_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, hipStream_t cs,
+                      hipGraph_t* graph, hipGraphExec_t* exec);
 constexpr size_t kSolveScratchDoubles = HIF_SOLVE_NOALLOC_MAX;  // 32 MiB
 void sweep_noalloc_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, hipStream_t s);
 
@@ -351,6 +360,11 @@ void id_batched_impl(double* mats, const int64_t* off, const int32_t* rows, cons
 // Group assignment (factor.hip).
 void partition_impl(const double* pts, int64_t n, int dim, const uint8_t* active, int kind,
                     int32_t S, int32_t* group, hipStream_t s);
+
+// Launch-shape table (hif_tuning_set / hif_tuning_get): a snapshot for the
+// dispatching code, and the checked replacement.
+hif_tuning tuning();
+bool set_tuning(const hif_tuning* t);  // nullptr: the built-in table; false if invalid
 
 inline int ceil_log2(uint64_t v) {
   int b = 0;

@@ -116,8 +116,9 @@ __global__ __launch_bounds__(kAsmThreads) void k_asm_fill(AsmArgs A) {
     } else if (r < m) {
       const int p = A.sym ? r - roff : (r - roff) % P;
       kind = (A.sym || r - roff < P) ? 2 : 3;
+      const double R = A.gpid ? A.pR[A.gpid[g]] : A.R;
 #pragma unroll
-      for (int k = 0; k < D; ++k) xi[k] = A.zc[int64_t(g) * D + k] + A.R * A.proxy_u[p * D + k];
+      for (int k = 0; k < D; ++k) xi[k] = A.zc[int64_t(g) * D + k] + R * A.proxy_u[p * D + k];
     } else {
       kind = 4;
       i = cols[r - m];
@@ -1177,12 +1178,28 @@ static void launch_id_reg(const IdArgs& A0, int max_cols, hipStream_t s) {
   A.alpha = alpha.p;
   A.astride = stride;
   A.skip_cols = 192;
+  // waves per problem from the launch-shape table; a wave holds 64 * CB / NW
+  // rows of every column
+  const hif_tuning tu = tuning();
   if (max_cols <= 64) {
-    hipLaunchKernelGGL((k_id_reg<1, 16, 4>), dim3(np), dim3(256), 0, s, A, S);
+    if (tu.id_reg_waves[0] == 16)
+      hipLaunchKernelGGL((k_id_reg<1, 4, 16>), dim3(np), dim3(1024), 0, s, A, S);
+    else if (tu.id_reg_waves[0] == 8)
+      hipLaunchKernelGGL((k_id_reg<1, 8, 8>), dim3(np), dim3(512), 0, s, A, S);
+    else
+      hipLaunchKernelGGL((k_id_reg<1, 16, 4>), dim3(np), dim3(256), 0, s, A, S);
   } else if (max_cols <= 128) {
-    hipLaunchKernelGGL((k_id_reg<2, 16, 8>), dim3(np), dim3(512), 0, s, A, S);
+    if (tu.id_reg_waves[1] == 16)
+      hipLaunchKernelGGL((k_id_reg<2, 8, 16>), dim3(np), dim3(1024), 0, s, A, S);
+    else if (tu.id_reg_waves[1] == 4)
+      hipLaunchKernelGGL((k_id_reg<2, 32, 4>), dim3(np), dim3(256), 0, s, A, S);
+    else
+      hipLaunchKernelGGL((k_id_reg<2, 16, 8>), dim3(np), dim3(512), 0, s, A, S);
   } else {
-    hipLaunchKernelGGL((k_id_reg<3, 12, 16>), dim3(np), dim3(1024), 0, s, A, S);
+    if (tu.id_reg_waves[2] == 8)
+      hipLaunchKernelGGL((k_id_reg<3, 24, 8>), dim3(np), dim3(512), 0, s, A, S);
+    else
+      hipLaunchKernelGGL((k_id_reg<3, 12, 16>), dim3(np), dim3(1024), 0, s, A, S);
     if (max_cols > 192) launch_id_small(A, max_cols, s);
   }
   std::vector<int32_t> hk(A.nprob);

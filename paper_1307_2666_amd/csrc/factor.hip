@@ -186,12 +186,36 @@ __device__ void centre_of(int key, int kind, int S, double* z) {
   }
 }
 
+// Per-problem geometry of a sub-level when several independent problems are
+// factored together (their DOFs concatenated): pid[j] is the problem of DOF
+// j, and problem p has S[p] boxes per side, its group keys start at koff[p],
+// its cells at coff[p] in the cell table, its proxy radius is R[p] and its ID
+// precision eps[p].  With pid == nullptr there is one problem and the
+// sub-level's scalars apply.
+struct ProbGeo {
+  const int32_t* pid = nullptr;
+  const int32_t* S = nullptr;
+  const int32_t* koff = nullptr;
+  const int32_t* coff = nullptr;
+  const double* R = nullptr;
+  const double* eps = nullptr;
+  const int32_t* gpid = nullptr;  // [G] problem of each group
+};
+
+// key = the problem's key offset (coff for cells with cell_keys, koff
+// otherwise) + the point's group within its problem.
 template <int D>
 __global__ void k_group_key(const double* pts, const int32_t* act, int64_t nact, int kind, int S,
-                            int32_t* key, int32_t* dof) {
+                            int32_t* key, int32_t* dof, ProbGeo pg, int cell_keys) {
   GRID_STRIDE(i, nact) {
     const int j = act[i];
-    key[i] = group_key<D>(pts + int64_t(j) * D, kind, S);
+    int s = S, off = 0;
+    if (pg.pid) {
+      const int p = pg.pid[j];
+      s = pg.S[p];
+      off = cell_keys ? pg.coff[p] : pg.koff[p];
+    }
+    key[i] = off + group_key<D>(pts + int64_t(j) * D, kind, s);
     dof[i] = j;
   }
 }
@@ -208,12 +232,14 @@ __global__ void k_heads(const int32_t* skey, int64_t n, int32_t* head) {
 
 // After an exclusive scan of the heads: group index of every position.
 __global__ void k_group_setup(const int32_t* skey, const int32_t* sdof, int64_t n, const int32_t* head,
-                              const int32_t* hscan, int64_t* gstart, int32_t* gkey, int32_t* grp_of) {
+                              const int32_t* hscan, int64_t* gstart, int32_t* gkey, int32_t* grp_of,
+                              const int32_t* pid, int32_t* gpid) {
   GRID_STRIDE(i, n) {
     const int g = hscan[i] + head[i] - 1;
     if (head[i]) {
       gstart[g] = i;
       gkey[g] = skey[i];
+      if (pid) gpid[g] = pid[sdof[i]];
     }
     if (i == n - 1) gstart[g + 1] = n;
     grp_of[sdof[i]] = g;
@@ -221,8 +247,15 @@ __global__ void k_group_setup(const int32_t* skey, const int32_t* sdof, int64_t 
 }
 
 template <int D>
-__global__ void k_centres(const int32_t* gkey, int G, int kind, int S, double* zc) {
-  GRID_STRIDE(g, G) centre_of<D>(gkey[g], kind, S, zc + g * D);
+__global__ void k_centres(const int32_t* gkey, int G, int kind, int S, double* zc, ProbGeo pg) {
+  GRID_STRIDE(g, G) {
+    if (pg.pid) {
+      const int p = pg.gpid[g];
+      centre_of<D>(gkey[g] - pg.koff[p], kind, pg.S[p], zc + g * D);
+    } else {
+      centre_of<D>(gkey[g], kind, S, zc + g * D);
+    }
+  }
 }
 
 __global__ void k_cell_table(const int32_t* ckey, int64_t n, int32_t* lo, int32_t* hi) {
@@ -256,6 +289,7 @@ struct NfArgs {
   uint64_t* cand;
   const int64_t* cand_off;
   int shift;
+  ProbGeo pg;
 };
 
 template <int D, bool FILL>
@@ -267,14 +301,24 @@ __global__ void k_nearfield(NfArgs A) {
   // order of emission do not show in the result.
   const int g = blockIdx.y, part = blockIdx.x, NP = gridDim.x;
   const int64_t slot = int64_t(g) * NP + part;
+  // the group's problem: its boxes per side, proxy radius and cells
+  int S = A.S, coff = 0;
+  double R = A.R, R2 = A.R2;
+  if (A.pg.pid) {
+    const int p = A.pg.gpid[g];
+    S = A.pg.S[p];
+    R = A.pg.R[p];
+    R2 = R * R;
+    coff = A.pg.coff[p];
+  }
   double z[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) z[k] = A.zc[int64_t(g) * D + k];
   int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    lo[k] = max(0, int(floor((z[k] - A.R) * double(A.S))) - 1);
-    const int hi = min(A.S - 1, int(floor((z[k] + A.R) * double(A.S))) + 1);
+    lo[k] = max(0, int(floor((z[k] - R) * double(S))) - 1);
+    const int hi = min(S - 1, int(floor((z[k] + R) * double(S))) + 1);
     ext[k] = hi - lo[k] + 1;
   }
   __shared__ unsigned long long s_cnt;
@@ -296,12 +340,13 @@ __global__ void k_nearfield(NfArgs A) {
     const int cc[3] = {lo[0] + cl / (ext[1] * ext[2]), lo[1] + (cl / ext[2]) % ext[1], lo[2] + cl % ext[2]};
     int cid = 0;
 #pragma unroll
-    for (int k = 0; k < D; ++k) cid = cid * A.S + cc[k];
+    for (int k = 0; k < D; ++k) cid = cid * S + cc[k];
+    cid += coff;
     const int b = A.cell_lo[cid], e = A.cell_hi[cid];
     for (int i = b + threadIdx.x; i < e; i += blockDim.x) {
       const int j = A.cdof[i];
       if (A.grp_of[j] == g) continue;
-      if (dist2_exact<D>(A.pts + int64_t(j) * D, z) < A.R2) emit(j);
+      if (dist2_exact<D>(A.pts + int64_t(j) * D, z) < R2) emit(j);
     }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -505,9 +550,10 @@ __global__ void k_class_tol(int nc, const int32_t* cls_group, const int32_t* cls
                             const int64_t* gstart, const double* colK2, const double* colS2, double eps,
                             int second_kind, const int64_t* yoff, const int64_t* nf_start, int sym,
                             int nproxy, int64_t* moff, int32_t* ld, int32_t* rows, double* tol,
-                            int64_t* poff) {
+                            int64_t* poff, ProbGeo pg) {
   GRID_STRIDE(q, nc) {
     const int g = cls_group[q];
+    if (pg.pid) eps = pg.eps[pg.gpid[g]];
     const int64_t c0 = gstart[g];
     const int n = int(gstart[g + 1] - c0);
     const int col0 = cls_col0[q], nq = cls_n[q];
@@ -543,8 +589,9 @@ __global__ void k_sci_keep(const uint64_t* key, int64_t nnz, const uint8_t* acti
     const int i = int(key[e] >> 32), j = int(key[e] & 0xffffffffu);
     int kp = 0;
     if (active[i] && active[j]) {
+      // DOFs of a problem that sits this sub-level out have no group (-1)
       const int gi = grp_of[i], gj = grp_of[j];
-      kp = (gi != gj) || (grec[gi] < 0);
+      kp = (gi != gj) || gi < 0 || (grec[gi] < 0);
     }
     keep[e] = kp;
   }
@@ -583,6 +630,30 @@ __global__ void k_active_keep(const int32_t* act, int64_t nact, const uint8_t* a
 __global__ void k_active_compact(const int32_t* act, int64_t nact, const int32_t* keep, const int32_t* pos,
                                  int32_t* out) {
   GRID_STRIDE(i, nact) if (keep[i]) out[pos[i]] = act[i];
+}
+
+// Number of entries of the ascending list a[0..n) below v (one thread,
+// binary search).
+__global__ void k_count_below(const int32_t* a, int64_t n, int32_t v, int64_t* out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  *out = lo;
+}
+
+// Subtract off from the DOF indices (redundant, then skeleton) of every record.
+__global__ void k_rebase_records(const GroupRec* recs, int nrec, int32_t* iarena, int32_t off) {
+  const int ri = blockIdx.x;
+  if (ri >= nrec) return;
+  const GroupRec R = recs[ri];
+  for (int e = threadIdx.x; e < R.r + R.k; e += blockDim.x) iarena[R.idx + e] -= off;
+}
+
+__global__ void k_sub_i32(const int32_t* a, int64_t n, int32_t off, int32_t* out) {
+  GRID_STRIDE(i, n) out[i] = a[i] - off;
 }
 
 __global__ void k_pos_scatter(const int32_t* idx, int64_t n, int32_t* pos_of) {
@@ -717,9 +788,25 @@ struct Factorizer {
   DBuf<uint64_t> newkey;
   DBuf<double2> newval;
   DBuf<int32_t> akeep, apos;
+  // Several independent problems factored together (level-synchronous
+  // batch): their DOFs are concatenated, deepest tree first, so that the
+  // problems still taking part in a level hold a prefix of the ascending
+  // active list.  Problem p has tree depth pL[p], DOFs [poff[p], poff[p+1]),
+  // ID precision peps[p].  One problem: multi == false and none of this is used.
+  bool multi = false;
+  int nprob = 1;
+  std::vector<int> pL;
+  std::vector<int64_t> poff;
+  std::vector<double> peps;
+  DBuf<int32_t> pid, dS, dkoff, dcoff, gpid;
+  DBuf<int64_t> cut;
+  DBuf<double> dR, deps;
+  // per sub-level: problem of each record (host), for the split into handles
+  std::vector<std::vector<int32_t>> rec_prob;
 
   void sublevel(int lvl, int kind);
   void top();
+  void top_multi(const std::vector<hif_factor_s*>& hs);
 };
 
 void Factorizer::sublevel(int lvl, int kind) {
@@ -737,9 +824,64 @@ void Factorizer::sublevel(int lvl, int kind) {
   sub.kind = kind;
   hif_stats_t& st = H->stats;
   st.sub_kind[si] = kind;
+  // Several problems: the ones whose tree is deep enough take part; their
+  // active DOFs are the first nact of the list, and every DOF starts the
+  // sub-level without a group.
+  const int64_t nact_all = nact;
+  ProbGeo pg{};
+  int ncent = 1, ncell = 1;
+  for (int k = 0; k < D; ++k) {
+    ncent *= S;
+    ncell *= S;
+  }
+  ncent *= (kind == 0 ? 1 : 3);
+  if (multi) {
+    int np = 0;
+    while (np < nprob && pL[np] > lvl) ++np;
+    std::vector<int32_t> hS(np), hk(np + 1), hc(np + 1);
+    std::vector<double> hR(np), he(np);
+    hk[0] = hc[0] = 0;
+    for (int q = 0; q < np; ++q) {
+      const int Sq = 1 << (pL[q] - lvl);
+      int nc = 1;
+      for (int k = 0; k < D; ++k) nc *= Sq;
+      hS[q] = Sq;
+      hc[q + 1] = hc[q] + nc;
+      hk[q + 1] = hk[q] + nc * (kind == 0 ? 1 : 3);
+      hR[q] = H->proxy_r / double(Sq);
+      he[q] = peps[q];
+    }
+    ncent = hk[np];
+    ncell = hc[np];
+    dS.ensure(nprob, mt);
+    dkoff.ensure(nprob + 1, mt);
+    dcoff.ensure(nprob + 1, mt);
+    dR.ensure(nprob, mt);
+    deps.ensure(nprob, mt);
+    to_dev(dS.p, hS, s);
+    to_dev(dkoff.p, hk, s);
+    to_dev(dcoff.p, hc, s);
+    to_dev(dR.p, hR, s);
+    to_dev(deps.p, he, s);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(N)), dim3(kThreads), 0, s, grp_of.p, N, -1);
+    if (np < nprob) {
+      cut.ensure(1, mt);
+      hipLaunchKernelGGL(k_count_below, dim3(1), dim3(64), 0, s, act.p, nact, int32_t(poff[np]), cut.p);
+      HIF_HIP(hipGetLastError());
+      nact = scalar_at(cut.p, s);
+    }
+    pg.pid = pid.p;
+    pg.S = dS.p;
+    pg.koff = dkoff.p;
+    pg.coff = dcoff.p;
+    pg.R = dR.p;
+    pg.eps = deps.p;
+  }
   st.sub_active[si] = nact;
   if (nact == 0) {
+    nact = nact_all;
     H->subs.push_back(std::move(sub));
+    if (multi) rec_prob.emplace_back();
     return;
   }
   tm.mark(PH_HOST);
@@ -752,40 +894,43 @@ void Factorizer::sublevel(int lvl, int kind) {
   head.ensure(nact, mt);
   hscan.ensure(nact + 1, mt);
   if (D == 2)
-    hipLaunchKernelGGL(k_group_key<2>, dim3(nblocks(nact)), dim3(kThreads), 0, s, pts, act.p, nact, kind, S, key.p, dof.p);
+    hipLaunchKernelGGL(k_group_key<2>, dim3(nblocks(nact)), dim3(kThreads), 0, s, pts, act.p, nact, kind, S, key.p,
+                       dof.p, pg, 0);
   else
-    hipLaunchKernelGGL(k_group_key<3>, dim3(nblocks(nact)), dim3(kThreads), 0, s, pts, act.p, nact, kind, S, key.p, dof.p);
+    hipLaunchKernelGGL(k_group_key<3>, dim3(nblocks(nact)), dim3(kThreads), 0, s, pts, act.p, nact, kind, S, key.p,
+                       dof.p, pg, 0);
   HIF_HIP(hipGetLastError());
-  int ncent = 1;
-  for (int k = 0; k < D; ++k) ncent *= S;
-  ncent *= (kind == 0 ? 1 : 3);
   sort_i32_i32(key.p, ktmp.p, dof.p, vtmp.p, nact, ceil_log2(uint64_t(ncent) + 1), s, prim, mt);
   hipLaunchKernelGGL(k_heads, dim3(nblocks(nact)), dim3(kThreads), 0, s, key.p, nact, head.p);
   exclusive_scan_i32(head.p, hscan.p, nact, s, prim, mt);
   const int G = scalar_at(hscan.p + nact, s);
   gstart.ensure(G + 1, mt);
   gkey.ensure(G, mt);
+  if (multi) {
+    gpid.ensure(G, mt);
+    pg.gpid = gpid.p;
+  }
   hipLaunchKernelGGL(k_group_setup, dim3(nblocks(nact)), dim3(kThreads), 0, s, key.p, dof.p, nact, head.p, hscan.p,
-                     gstart.p, gkey.p, grp_of.p);
+                     gstart.p, gkey.p, grp_of.p, pg.pid, multi ? gpid.p : nullptr);
   zc.ensure(int64_t(G) * D, mt);
   if (D == 2)
-    hipLaunchKernelGGL(k_centres<2>, dim3(nblocks(G)), dim3(kThreads), 0, s, gkey.p, G, kind, S, zc.p);
+    hipLaunchKernelGGL(k_centres<2>, dim3(nblocks(G)), dim3(kThreads), 0, s, gkey.p, G, kind, S, zc.p, pg);
   else
-    hipLaunchKernelGGL(k_centres<3>, dim3(nblocks(G)), dim3(kThreads), 0, s, gkey.p, G, kind, S, zc.p);
+    hipLaunchKernelGGL(k_centres<3>, dim3(nblocks(G)), dim3(kThreads), 0, s, gkey.p, G, kind, S, zc.p, pg);
   HIF_HIP(hipGetLastError());
   st.sub_groups[si] = G;
 
   // ---- level-l cell binning of the active DOFs (geometric candidates) ----
   ckey.ensure(nact, mt);
   cdof.ensure(nact, mt);
-  int ncell = 1;
-  for (int k = 0; k < D; ++k) ncell *= S;
   cell_lo.ensure(ncell, mt);
   cell_hi.ensure(ncell, mt);
   if (D == 2)
-    hipLaunchKernelGGL(k_group_key<2>, dim3(nblocks(nact)), dim3(kThreads), 0, s, pts, act.p, nact, 0, S, ckey.p, cdof.p);
+    hipLaunchKernelGGL(k_group_key<2>, dim3(nblocks(nact)), dim3(kThreads), 0, s, pts, act.p, nact, 0, S, ckey.p,
+                       cdof.p, pg, 1);
   else
-    hipLaunchKernelGGL(k_group_key<3>, dim3(nblocks(nact)), dim3(kThreads), 0, s, pts, act.p, nact, 0, S, ckey.p, cdof.p);
+    hipLaunchKernelGGL(k_group_key<3>, dim3(nblocks(nact)), dim3(kThreads), 0, s, pts, act.p, nact, 0, S, ckey.p,
+                       cdof.p, pg, 1);
   sort_i32_i32(ckey.p, ktmp.p, cdof.p, vtmp.p, nact, ceil_log2(uint64_t(ncell) + 1), s, prim, mt);
   hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(ncell)), dim3(kThreads), 0, s, cell_lo.p, int64_t(ncell), 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(ncell)), dim3(kThreads), 0, s, cell_hi.p, int64_t(ncell), 0);
@@ -817,6 +962,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   cand_off.ensure(nslot + 1, mt);
   nfa.cnt = cnt.p;
   nfa.shift = shift;
+  nfa.pg = pg;
   if (D == 2)
     hipLaunchKernelGGL((k_nearfield<2, false>), dim3(NP, G), dim3(kThreads), 0, s, nfa);
   else
@@ -957,6 +1103,8 @@ void Factorizer::sublevel(int lvl, int kind) {
   aa.skey = skey.p;
   aa.sval = sval.p;
   aa.fp32 = H->opts.precision == HIF_FP32_MIXED;
+  aa.gpid = pg.gpid;
+  aa.pR = pg.R;
   aa.max_rows = maxmn;
   aa.kstride = nact;
   kpart.ensure(size_t((maxmn + 63) / 64) * size_t(nact), mt);
@@ -972,7 +1120,7 @@ void Factorizer::sublevel(int lvl, int kind) {
   perm.ensure(nact, mt);
   hipLaunchKernelGGL(k_class_tol, dim3(nblocks(NC)), dim3(kThreads), 0, s, NC, cls_group.p, cls_col0.p, cls_n.p,
                      gstart.p, colK2.p, colS2.p, H->eps, split, yoff.p, nf_start.p, sym, P, cls_moff.p, cls_ld.p,
-                     cls_rows.p, cls_tol.p, cls_poff.p);
+                     cls_rows.p, cls_tol.p, cls_poff.p, pg);
   HIF_HIP(hipGetLastError());
   tm.mark(PH_ASM);
 
@@ -1062,8 +1210,9 @@ void Factorizer::sublevel(int lvl, int kind) {
   tm.mark(PH_ID);
 
   // ---- records: sizes from the ranks ---------------------------------------
-  std::vector<int32_t> h_rank;
+  std::vector<int32_t> h_rank, h_gpid;
   to_host(h_rank, cls_rank.p, NC, s);
+  if (multi) to_host(h_gpid, gpid.p, G, s);
   std::vector<int32_t> h_grec(G, -1), h_skoff(NC), h_rdoff(NC);
   std::vector<int> rec_g;
   std::vector<int64_t> h_newoff(G, 0);
@@ -1124,6 +1273,10 @@ void Factorizer::sublevel(int lvl, int kind) {
       const double r3 = rr, k3 = kk;
       elfl += 6.0 * r3 * r3 * k3 + 4.0 * k3 * k3 * r3 + 2.0 / 3.0 * r3 * r3 * r3 + 4.0 * r3 * r3 * k3 + 2.0 * k3 * k3 * r3;
     }
+  }
+  if (multi) {
+    rec_prob.emplace_back();
+    for (int g : rec_g) rec_prob.back().push_back(h_gpid[g]);
   }
   st.sub_skel[si] = skel;
   st.sub_id_flops[si] = idfl;
@@ -1299,7 +1452,8 @@ void Factorizer::sublevel(int lvl, int kind) {
   else
     hipLaunchKernelGGL(k_fill_i64, dim3(nblocks(N + 1)), dim3(kThreads), 0, s, srow.p, N + 1, int64_t(0));
   HIF_HIP(hipGetLastError());
-  // active list
+  // active list (every problem's DOFs, also those of problems that sat out)
+  nact = nact_all;
   akeep.ensure(nact, mt);
   apos.ensure(nact + 1, mt);
   hipLaunchKernelGGL(k_active_keep, dim3(nblocks(nact)), dim3(kThreads), 0, s, act.p, nact, active.p, akeep.p);
@@ -1378,25 +1532,123 @@ void Factorizer::top() {
   HIF_REQUIRE(bad == 0, HIF_ESINGULAR, "zero pivot in the top block A_L (Lemma 2.1 needs it nonsingular)");
 }
 
+// Top blocks of several problems factored together: each problem's active
+// DOFs (a contiguous range of the ascending active list) form its A_L; the
+// blocks are assembled one by one, LU-factored together (one batched launch
+// sequence for all blocks above 256 unknowns) and handed to the problems'
+// handles with indices local to each problem.
+void Factorizer::top_multi(const std::vector<hif_factor_s*>& hs) {
+  tm.mark(PH_HOST);
+  std::vector<int64_t> bounds(nprob + 1, 0);
+  bounds[nprob] = nact;
+  cut.ensure(1, mt);
+  for (int q = 1; q < nprob; ++q) {
+    hipLaunchKernelGGL(k_count_below, dim3(1), dim3(64), 0, s, act.p, nact, int32_t(poff[q]), cut.p);
+    HIF_HIP(hipGetLastError());
+    bounds[q] = scalar_at(cut.p, s);
+  }
+  std::vector<int64_t> aoffs(nprob + 1, 0), ioffs(nprob + 1, 0);
+  for (int q = 0; q < nprob; ++q) {
+    const int64_t n = bounds[q + 1] - bounds[q];
+    aoffs[q + 1] = aoffs[q] + n * n;
+    ioffs[q + 1] = ioffs[q] + n;
+  }
+  DBuf<double> lu;
+  DBuf<int32_t> piv;
+  lu.alloc(aoffs[nprob], mt);
+  piv.alloc(ioffs[nprob], mt);
+  std::vector<int64_t> hm, hp;
+  std::vector<int32_t> hn;
+  int maxn = 0;
+  for (int q = 0; q < nprob; ++q) {
+    const int64_t n = bounds[q + 1] - bounds[q];
+    if (n == 0) continue;
+    const int32_t* gidx = act.p + bounds[q];
+    hipLaunchKernelGGL(k_pos_scatter, dim3(nblocks(n)), dim3(kThreads), 0, s, gidx, n, pos_of.p);
+    TopArgs ta{};
+    ta.dim = D;
+    ta.fp32 = H->opts.precision == HIF_FP32_MIXED;
+    ta.n = n;
+    ta.pts = pts;
+    ta.a = a;
+    ta.b = b;
+    ta.c = c;
+    ta.w = w;
+    ta.selfk = sf;
+    ta.idx = gidx;
+    ta.pos_of = pos_of.p;
+    ta.srow = srow.p;
+    ta.skey = skey.p;
+    ta.sval = sval.p;
+    ta.A = lu.p + aoffs[q];
+    ta.piv = piv.p + ioffs[q];
+    ta.status = status.p;
+    launch_top(ta, s);
+    if (n > 256) {
+      hm.push_back(aoffs[q]);
+      hp.push_back(ioffs[q]);
+      hn.push_back(int32_t(n));
+      maxn = std::max<int>(maxn, int(n));
+    }
+  }
+  if (!hn.empty()) {  // blocked LU of every block above 256 unknowns in one launch sequence
+    const int nb = int(hn.size());
+    lu_moff.ensure(nb, mt);
+    lu_poff.ensure(nb, mt);
+    lu_n.ensure(nb, mt);
+    lu_r.ensure(nb, mt);
+    to_dev(lu_moff.p, hm, s);
+    to_dev(lu_poff.p, hp, s);
+    to_dev(lu_n.p, hn, s);
+    to_dev(lu_r.p, hn, s);
+    LuBatch lb{};
+    lb.base = lu.p;
+    lb.moff = lu_moff.p;
+    lb.n = lu_n.p;
+    lb.r = lu_r.p;
+    lb.piv = piv.p;
+    lb.poff = lu_poff.p;
+    lb.status = status.p;
+    lb.nprob = nb;
+    launch_lu_batched(lb, maxn, maxn, s);
+    HIF_HIP(hipStreamSynchronize(s));
+  }
+  for (int q = 0; q < nprob; ++q) {
+    hif_factor_s* Hq = hs[q];
+    const int64_t n = bounds[q + 1] - bounds[q];
+    Hq->ntop = n;
+    Hq->top_idx.alloc(n, &Hq->mem);
+    Hq->top_piv.alloc(n, &Hq->mem);
+    Hq->top_perm.alloc(n, &Hq->mem);
+    Hq->top_lu.alloc(n * n, &Hq->mem);
+    if (n == 0) continue;
+    hipLaunchKernelGGL(k_sub_i32, dim3(nblocks(n)), dim3(kThreads), 0, s, act.p + bounds[q], n, int32_t(poff[q]),
+                       Hq->top_idx.p);
+    HIF_HIP(hipMemcpyAsync(Hq->top_lu.p, lu.p + aoffs[q], sizeof(double) * n * n, hipMemcpyDeviceToDevice, s));
+    HIF_HIP(hipMemcpyAsync(Hq->top_piv.p, piv.p + ioffs[q], sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    launch_make_perm_top(Hq->top_piv.p, Hq->top_perm.p, int(n), s);
+  }
+  HIF_HIP(hipGetLastError());
+  tm.mark(PH_TOP);
+  tm.flush(H->stats.t_phase_ms);
+  const int32_t bad = scalar_at(status.p, s);
+  HIF_REQUIRE(bad == 0, HIF_ESINGULAR, "zero pivot in a top block A_L (Lemma 2.1 needs it nonsingular)");
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
-void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* kr, const double* a_in,
-                 const double* b_in, const double* c_in, hipStream_t s) {
-  const auto t0 = std::chrono::steady_clock::now();
+// Copies the operator into the handle (points, then a (0 if absent), b, c
+// (1 if absent), weight (h^d) and self term), checks the inputs, decides the
+// symmetric compression (Section 5: b_i = s c_i w_i for one scalar s) and the
+// tree depth (boxes split while they hold more than leaf points; only trees
+// whose leaves all sit at one depth are handled, Section 3.1), and rejects
+// coincident points.
+void prepare_problem(hif_factor_s* H, const double* points, const hif_kernel* kr, const double* a_in,
+                     const double* b_in, const double* c_in, hipStream_t s) {
   const int D = H->dim;
   const int64_t N = H->n;
   MemTracker* mt = &H->mem;
-  Factorizer F{};
-  F.H = H;
-  F.s = s;
-  F.D = D;
-  F.N = N;
-  F.mt = mt;
-  F.tm.s = s;
-
-  // Operator copies, kept in the handle: a (0 if absent), b, c (1 if absent),
-  // w (h^d), self term.
   DBuf<double>& op = H->op;
   op.alloc(int64_t(N) * (D + 5), mt);
   double* pts = op.p;
@@ -1424,23 +1676,17 @@ void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* kr, co
   H->c = c;
   H->w = w;
   H->selfk = sf;
-  F.pts = pts;
-  F.a = a;
-  F.b = b;
-  F.c = c;
-  F.w = w;
-  F.sf = sf;
 
-  F.status.alloc(2, mt);
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, F.status.p, int64_t(2), 0);
-  hipLaunchKernelGGL(k_validate, dim3(nblocks(N)), dim3(kThreads), 0, s, pts, N, D, a, b, c, w, sf, F.status.p);
+  DBuf<int32_t> status;
+  status.alloc(2, mt);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, status.p, int64_t(2), 0);
+  hipLaunchKernelGGL(k_validate, dim3(nblocks(N)), dim3(kThreads), 0, s, pts, N, D, a, b, c, w, sf, status.p);
   HIF_HIP(hipGetLastError());
-  const int32_t vflags = scalar_at(F.status.p, s);
+  const int32_t vflags = scalar_at(status.p, s);
   HIF_REQUIRE(!(vflags & 1), HIF_EINVAL, "non-finite point coordinate");
   HIF_REQUIRE(!(vflags & 2), HIF_EINVAL, "point outside the unit box [0,1]^d");
   HIF_REQUIRE(!(vflags & 4), HIF_EINVAL, "non-finite a, b, c, weight or self term");
 
-  // Symmetric compression (Section 5) iff b_i = s c_i w_i for one scalar s.
   if (H->opts.symmetric < 0) {
     std::vector<double> hb, hc, hw;
     to_host(hb, b, N, s);
@@ -1454,8 +1700,6 @@ void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* kr, co
     H->symmetric = H->opts.symmetric;
   }
 
-  // Tree depth: split boxes holding more than leaf points; only trees whose
-  // leaves all sit at one depth are handled (Section 3.1, uniform grids).
   {
     DBuf<int32_t> counts, mm;
     mm.alloc(2, mt);
@@ -1494,92 +1738,281 @@ void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* kr, co
   }
   HIF_REQUIRE(H->L <= HIF_MAX_SUBLEVELS / 3, HIF_EUNSUPPORTED, "tree deeper than the statistics arrays allow");
 
-  // Coincident points: compare pairs inside every leaf box.
+  // coincident points: compare pairs inside every leaf box
+  {
+    const int S = 1 << H->L;
+    int ncell = 1;
+    for (int k = 0; k < D; ++k) ncell *= S;
+    DBuf<int32_t> iota, ckey, cdof, ktmp, vtmp, lo, hi;
+    DBuf<unsigned char> prim;
+    iota.alloc(N, mt);
+    ckey.alloc(N, mt);
+    cdof.alloc(N, mt);
+    ktmp.alloc(N, mt);
+    vtmp.alloc(N, mt);
+    lo.alloc(ncell, mt);
+    hi.alloc(ncell, mt);
+    hipLaunchKernelGGL(k_iota, dim3(nblocks(N)), dim3(kThreads), 0, s, iota.p, N);
+    if (D == 2)
+      hipLaunchKernelGGL(k_group_key<2>, dim3(nblocks(N)), dim3(kThreads), 0, s, pts, iota.p, N, 0, S, ckey.p,
+                         cdof.p, ProbGeo{}, 0);
+    else
+      hipLaunchKernelGGL(k_group_key<3>, dim3(nblocks(N)), dim3(kThreads), 0, s, pts, iota.p, N, 0, S, ckey.p,
+                         cdof.p, ProbGeo{}, 0);
+    sort_i32_i32(ckey.p, ktmp.p, cdof.p, vtmp.p, N, ceil_log2(uint64_t(ncell) + 1), s, prim, mt);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(ncell)), dim3(kThreads), 0, s, lo.p, int64_t(ncell), 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(ncell)), dim3(kThreads), 0, s, hi.p, int64_t(ncell), 0);
+    hipLaunchKernelGGL(k_cell_table, dim3(nblocks(N)), dim3(kThreads), 0, s, ckey.p, N, lo.p, hi.p);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, status.p, int64_t(2), 0);
+    hipLaunchKernelGGL(k_coincident, dim3(ncell), dim3(kThreads), 0, s, pts, D, cdof.p, lo.p, hi.p, status.p);
+    HIF_HIP(hipGetLastError());
+    const int32_t dup = scalar_at(status.p, s);
+    HIF_REQUIRE(dup == 0, HIF_EINVAL, "coincident points (the kernel is singular at r = 0)");
+  }
+}
+
+namespace {
+
+// Proxy directions (Section 3.3): circle p -> (cos 2 pi p / P, sin 2 pi p / P);
+// sphere: spherical Fibonacci points z = 1 - (2p+1)/P, phi = p pi (3 - sqrt 5).
+std::vector<double> proxy_directions(int D, int P) {
+  std::vector<double> u(size_t(P) * D);
+  for (int p = 0; p < P; ++p) {
+    if (D == 2) {
+      const double t = 2.0 * M_PI * double(p) / double(P);
+      u[2 * p] = std::cos(t);
+      u[2 * p + 1] = std::sin(t);
+    } else {
+      const double z = 1.0 - (2.0 * p + 1.0) / double(P);
+      const double rho = std::sqrt(1.0 - z * z);
+      const double phi = double(p) * M_PI * (3.0 - std::sqrt(5.0));
+      u[3 * p] = rho * std::cos(phi);
+      u[3 * p + 1] = rho * std::sin(phi);
+      u[3 * p + 2] = z;
+    }
+  }
+  return u;
+}
+
+// Sub-level kinds of one level: cells, then (faces and) edges; RSF: cells only.
+std::vector<int> level_kinds(const hif_factor_s* H) {
+  if (H->opts.variant == HIF_VARIANT_RSF) return {0};
+  if (H->dim == 2) return {0, 2};
+  return {0, 1, 2};
+}
+
+// Factorizer state for the DOFs of a handle whose operator is in place:
+// everything active, no SCIs, no groups.
+void init_state(Factorizer& F) {
+  const int64_t N = F.N;
+  MemTracker* mt = F.mt;
+  hipStream_t s = F.s;
+  F.status.alloc(2, mt);
   F.active.alloc(N, mt);
   F.act.alloc(N, mt);
   F.grp_of.alloc(N, mt);
   F.pos_of.alloc(N, mt);
   F.srow.alloc(N + 1, mt);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, F.status.p, int64_t(2), 0);
   hipLaunchKernelGGL(k_fill_u8, dim3(nblocks(N)), dim3(kThreads), 0, s, F.active.p, N, uint8_t(1));
   hipLaunchKernelGGL(k_iota, dim3(nblocks(N)), dim3(kThreads), 0, s, F.act.p, N);
   hipLaunchKernelGGL(k_fill_i64, dim3(nblocks(N + 1)), dim3(kThreads), 0, s, F.srow.p, N + 1, int64_t(0));
   hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(N)), dim3(kThreads), 0, s, F.grp_of.p, N, -1);
   HIF_HIP(hipGetLastError());
   F.nact = N;
-  {
-    const int S = 1 << H->L;
-    int ncell = 1;
-    for (int k = 0; k < D; ++k) ncell *= S;
-    F.ckey.ensure(N, mt);
-    F.cdof.ensure(N, mt);
-    F.ktmp.ensure(N, mt);
-    F.vtmp.ensure(N, mt);
-    F.cell_lo.ensure(ncell, mt);
-    F.cell_hi.ensure(ncell, mt);
-    if (D == 2)
-      hipLaunchKernelGGL(k_group_key<2>, dim3(nblocks(N)), dim3(kThreads), 0, s, pts, F.act.p, N, 0, S, F.ckey.p, F.cdof.p);
-    else
-      hipLaunchKernelGGL(k_group_key<3>, dim3(nblocks(N)), dim3(kThreads), 0, s, pts, F.act.p, N, 0, S, F.ckey.p, F.cdof.p);
-    sort_i32_i32(F.ckey.p, F.ktmp.p, F.cdof.p, F.vtmp.p, N, ceil_log2(uint64_t(ncell) + 1), s, F.prim, mt);
-    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(ncell)), dim3(kThreads), 0, s, F.cell_lo.p, int64_t(ncell), 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(ncell)), dim3(kThreads), 0, s, F.cell_hi.p, int64_t(ncell), 0);
-    hipLaunchKernelGGL(k_cell_table, dim3(nblocks(N)), dim3(kThreads), 0, s, F.ckey.p, N, F.cell_lo.p, F.cell_hi.p);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, F.status.p, int64_t(2), 0);
-    hipLaunchKernelGGL(k_coincident, dim3(ncell), dim3(kThreads), 0, s, pts, D, F.cdof.p, F.cell_lo.p, F.cell_hi.p,
-                       F.status.p);
-    HIF_HIP(hipGetLastError());
-    const int32_t dup = scalar_at(F.status.p, s);
-    HIF_REQUIRE(dup == 0, HIF_EINVAL, "coincident points (the kernel is singular at r = 0)");
-  }
+  const std::vector<double> u = proxy_directions(F.D, F.H->nproxy);
+  F.proxy_u.alloc(u.size(), mt);
+  to_dev(F.proxy_u.p, u, s);
+}
 
-  // Proxy directions (Section 3.3): circle p -> (cos 2 pi p / P, sin 2 pi p / P);
-  // sphere: spherical Fibonacci points z = 1 - (2p+1)/P, phi = p pi (3 - sqrt 5).
-  {
-    const int P = H->nproxy;
-    std::vector<double> u(size_t(P) * D);
-    for (int p = 0; p < P; ++p) {
-      if (D == 2) {
-        const double t = 2.0 * M_PI * double(p) / double(P);
-        u[2 * p] = std::cos(t);
-        u[2 * p + 1] = std::sin(t);
-      } else {
-        const double z = 1.0 - (2.0 * p + 1.0) / double(P);
-        const double rho = std::sqrt(1.0 - z * z);
-        const double phi = double(p) * M_PI * (3.0 - std::sqrt(5.0));
-        u[3 * p] = rho * std::cos(phi);
-        u[3 * p + 1] = rho * std::sin(phi);
-        u[3 * p + 2] = z;
-      }
-    }
-    F.proxy_u.alloc(u.size(), mt);
-    to_dev(F.proxy_u.p, u, s);
-  }
-
-  // Levels: cells, then (faces and) edges; RSF: cells only.
-  std::vector<int> kinds;
-  if (H->opts.variant == HIF_VARIANT_RSF) kinds = {0};
-  else if (D == 2) kinds = {0, 2};
-  else kinds = {0, 1, 2};
-  for (int lvl = 0; lvl < H->L; ++lvl)
-    for (int kind : kinds) F.sublevel(lvl, kind);
-  F.top();
-
-  // Statistics.
+// m_f and the per-handle statistics that follow from the records.
+void record_stats(hif_factor_s* H) {
   hif_stats_t& st = H->stats;
-  st.n = N;
-  st.dim = D;
+  st.n = H->n;
+  st.dim = H->dim;
   st.levels = H->L;
   st.n_sublevels = int32_t(H->subs.size());
   st.top_size = H->ntop;
   int64_t fb = 0;
-  for (auto& sub : H->subs) {
+  for (auto& sub : H->subs)
     for (auto& R : sub.hrec) fb += 8 * (3 * int64_t(R.k) * R.r + int64_t(R.r) * R.r) + 4 * (2 * int64_t(R.r) + R.k);
-  }
   fb += 8 * H->ntop * H->ntop + 8 * H->ntop;
   st.factor_bytes = fb;
+}
+
+}  // namespace
+
+void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* kr, const double* a_in,
+                 const double* b_in, const double* c_in, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  prepare_problem(H, points, kr, a_in, b_in, c_in, s);
+  Factorizer F{};
+  F.H = H;
+  F.s = s;
+  F.D = H->dim;
+  F.N = H->n;
+  F.mt = &H->mem;
+  F.tm.s = s;
+  F.pts = H->pts;
+  F.a = H->a;
+  F.b = H->b;
+  F.c = H->c;
+  F.w = H->w;
+  F.sf = H->selfk;
+  init_state(F);
+  const std::vector<int> kinds = level_kinds(H);
+  for (int lvl = 0; lvl < H->L; ++lvl)
+    for (int kind : kinds) F.sublevel(lvl, kind);
+  F.top();
+  record_stats(H);
   prepare_sweeps(H, s);
   HIF_HIP(hipStreamSynchronize(s));
-  st.t_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  H->stats.t_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void factor_fused_impl(const std::vector<hif_factor_s*>& hs_in, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int P = int(hs_in.size());
+  if (P == 0) return;
+  // deepest tree first: the problems that take part in a level then hold a
+  // prefix of the active list
+  std::vector<hif_factor_s*> hs(hs_in);
+  std::stable_sort(hs.begin(), hs.end(), [](const hif_factor_s* x, const hif_factor_s* y) { return x->L > y->L; });
+  const int D = hs[0]->dim;
+  std::vector<int64_t> poff(P + 1, 0);
+  for (int q = 0; q < P; ++q) poff[q + 1] = poff[q] + hs[q]->n;
+  const int64_t N = poff[P];
+  HIF_REQUIRE(N <= int64_t(INT32_MAX) - 1, HIF_EINVAL, "the problems of a fused batch must have fewer than 2^31 points in all");
+  // the batch as one operator: points and coefficients concatenated
+  hif_factor_s B;
+  B.n = N;
+  B.dim = D;
+  B.L = hs[0]->L;
+  B.eps = hs[0]->eps;
+  B.leaf = hs[0]->leaf;
+  B.opts = hs[0]->opts;
+  B.symmetric = hs[0]->symmetric;
+  B.nproxy = hs[0]->nproxy;
+  B.proxy_r = hs[0]->proxy_r;
+  B.mem.cap = hs[0]->opts.max_bytes;
+  MemTracker* mt = &B.mem;
+  B.op.alloc(N * (D + 5), mt);
+  double* pts = B.op.p;
+  double* co[5];
+  for (int t = 0; t < 5; ++t) co[t] = pts + N * D + int64_t(t) * N;
+  for (int q = 0; q < P; ++q) {
+    const hif_factor_s* Hq = hs[q];
+    const int64_t n = Hq->n;
+    HIF_HIP(hipMemcpyAsync(pts + poff[q] * D, Hq->pts, sizeof(double) * n * D, hipMemcpyDeviceToDevice, s));
+    const double* src[5] = {Hq->a, Hq->b, Hq->c, Hq->w, Hq->selfk};
+    for (int t = 0; t < 5; ++t)
+      HIF_HIP(hipMemcpyAsync(co[t] + poff[q], src[t], sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  }
+  B.pts = pts;
+  B.a = co[0];
+  B.b = co[1];
+  B.c = co[2];
+  B.w = co[3];
+  B.selfk = co[4];
+  Factorizer F{};
+  F.H = &B;
+  F.s = s;
+  F.D = D;
+  F.N = N;
+  F.mt = mt;
+  F.tm.s = s;
+  F.pts = B.pts;
+  F.a = B.a;
+  F.b = B.b;
+  F.c = B.c;
+  F.w = B.w;
+  F.sf = B.selfk;
+  F.multi = true;
+  F.nprob = P;
+  F.poff = poff;
+  for (int q = 0; q < P; ++q) {
+    F.pL.push_back(hs[q]->L);
+    F.peps.push_back(hs[q]->eps);
+  }
+  F.pid.alloc(N, mt);
+  for (int q = 0; q < P; ++q)
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(hs[q]->n)), dim3(kThreads), 0, s, F.pid.p + poff[q], hs[q]->n,
+                       int32_t(q));
+  init_state(F);
+  const std::vector<int> kinds = level_kinds(&B);
+  for (int lvl = 0; lvl < B.L; ++lvl)
+    for (int kind : kinds) F.sublevel(lvl, kind);
+  F.top_multi(hs);
+
+  // Each problem's records, copied out of the batch's sub-levels into its
+  // own handle with DOF indices local to the problem.
+  for (size_t si = 0; si < B.subs.size(); ++si) {
+    SubLevel& bs = B.subs[si];
+    const std::vector<int32_t>& rp = F.rec_prob[si];
+    int rb = 0;
+    for (int q = 0; q < P; ++q) {
+      if (hs[q]->L <= bs.level) continue;
+      int re = rb;
+      while (re < bs.nrec && rp[re] == q) ++re;
+      hif_factor_s* Hq = hs[q];
+      SubLevel out;
+      out.level = bs.level;
+      out.kind = bs.kind;
+      out.nrec = re - rb;
+      const int sq = int(Hq->subs.size());
+      Hq->stats.sub_kind[sq] = bs.kind;
+      if (out.nrec > 0) {
+        const GroupRec& R0 = bs.hrec[rb];
+        const GroupRec& R1 = bs.hrec[re - 1];
+        const int64_t i0 = R0.idx, i1 = R1.idx + 3 * int64_t(R1.r) + R1.k;
+        const int64_t d0 = R0.off, d1 = R1.off + 3 * int64_t(R1.k) * R1.r + int64_t(R1.r) * R1.r;
+        out.iarena.alloc(i1 - i0, &Hq->mem);
+        out.darena.alloc(d1 - d0, &Hq->mem);
+        HIF_HIP(hipMemcpyAsync(out.iarena.p, bs.iarena.p + i0, sizeof(int32_t) * (i1 - i0),
+                               hipMemcpyDeviceToDevice, s));
+        HIF_HIP(hipMemcpyAsync(out.darena.p, bs.darena.p + d0, sizeof(double) * (d1 - d0),
+                               hipMemcpyDeviceToDevice, s));
+        std::vector<int64_t> hw(out.nrec);
+        for (int i = rb; i < re; ++i) {
+          GroupRec R = bs.hrec[i];
+          R.idx -= i0;
+          R.off -= d0;
+          hw[i - rb] = out.sum_r;
+          out.sum_r += R.r;
+          out.max_r = std::max(out.max_r, R.r);
+          out.max_k = std::max(out.max_k, R.k);
+          out.max_2rk = std::max(out.max_2rk, 2 * R.r + R.k);
+          Hq->stats.sub_skel[sq] += R.k;
+          out.hrec.push_back(R);
+        }
+        out.rec.alloc(out.nrec, &Hq->mem);
+        to_dev(out.rec.p, out.hrec, s);
+        out.woff.alloc(out.nrec, &Hq->mem);
+        to_dev(out.woff.p, hw, s);
+        hipLaunchKernelGGL(k_rebase_records, dim3(out.nrec), dim3(64), 0, s, out.rec.p, out.nrec, out.iarena.p,
+                           int32_t(poff[q]));
+        HIF_HIP(hipGetLastError());
+        HIF_HIP(hipStreamSynchronize(s));  // the host tables above are copied before they go out of scope
+      }
+      Hq->stats.sub_groups[sq] = out.nrec;
+      Hq->subs.push_back(std::move(out));
+      rb = re;
+    }
+    // the batch's copy is no longer needed
+    bs.iarena.release();
+    bs.darena.release();
+  }
+  HIF_HIP(hipStreamSynchronize(s));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int q = 0; q < P; ++q) {
+    hif_factor_s* Hq = hs[q];
+    record_stats(Hq);
+    // phase times and the wall time are those of the whole batch
+    for (int k = 0; k < 8; ++k) Hq->stats.t_phase_ms[k] = B.stats.t_phase_ms[k];
+    Hq->stats.t_factor_ms = ms;
+    prepare_sweeps(Hq, s);
+  }
+  HIF_HIP(hipStreamSynchronize(s));
 }
 
 void partition_impl(const double* pts, int64_t n, int dim, const uint8_t* active, int kind, int32_t S,

@@ -31,6 +31,10 @@ struct AsmArgs {
   const int64_t* srow;          // SCI store CSR row pointer [N+1]
   const uint64_t* skey;         // (i << 32 | j)
   const double2* sval;          // (S_ij, S_ji)
+  // several problems factored together: problem of each group and proxy
+  // radius of each problem (nullptr: one problem, radius R)
+  const int32_t* gpid = nullptr;
+  const double* pR = nullptr;
 };
 void launch_assemble(const AsmArgs& A, hipStream_t s);
 

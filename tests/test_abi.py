@@ -119,9 +119,20 @@ def test_factor_batch_rejects_bad_arguments():
     assert lib.hif_factor_batch(None, -1, None, 4, None, None) == B.HIF_EINVAL
     assert lib.hif_factor_batch(None, 2, None, 4, h, None) == B.HIF_EINVAL
     probs = (B.hif_problem * 1)()
-    assert lib.hif_factor_batch(ctypes.cast(probs, ctypes.c_void_p), 1, None, 0, h, None) == B.HIF_EINVAL
+    assert lib.hif_factor_batch(ctypes.cast(probs, ctypes.c_void_p), 1, None, -1, h, None) == B.HIF_EINVAL
     assert b"nworkers" in lib.hif_last_error()
     assert lib.hif_factor_batch(ctypes.cast(probs, ctypes.c_void_p), 1, None, 17, h, None) == B.HIF_EINVAL
+    # level-synchronous mode (nworkers = 0): a problem with bad arguments fails
+    # alone, on the host, and is reported at its index
+    out = (ctypes.c_void_p * 2)(0x1, 0x1)
+    st = (ctypes.c_int * 2)(7, 7)
+    probs2 = (B.hif_problem * 2)()
+    probs2[1].points = 0x1000
+    probs2[1].n = 0
+    assert lib.hif_factor_batch(ctypes.cast(probs2, ctypes.c_void_p), 2, None, 0, ctypes.cast(out, ctypes.c_void_p),
+                                ctypes.cast(st, ctypes.c_void_p)) == B.HIF_EINVAL
+    assert list(st) == [B.HIF_EINVAL, B.HIF_EINVAL] and out[0] is None and out[1] is None
+    assert b"problem 0: points is NULL" in lib.hif_last_error()
 
 
 def test_diag_grad_rejects_bad_arguments():

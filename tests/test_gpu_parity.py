@@ -565,11 +565,7 @@ def test_factor_sizes_match_paper_tables_3_12(d, n, eps):
     assert tops["hifie"] < tops["hifie_x"] < tops["rskelf"]
 
 
-def test_factor_batch_matches_single_factorizations():
-    # Independent problems of uneven sizes and leaves factored concurrently on
-    # 3 worker streams give the same factorizations as one at a time; a
-    # problem with coincident points fails alone, reported at its index.
-    rng = np.random.default_rng(51)
+def _batch_specs(rng):
     specs = [(32, 64), (48, 36), (24, 36), (64, 64), (40, 64), (16, 64), (56, 64)]
     probs = []
     for n, leaf in specs:
@@ -578,6 +574,101 @@ def test_factor_batch_matches_single_factorizations():
     bad = grid_points(16, 2)
     bad[5] = bad[6]
     probs.insert(3, dict(points=_t(bad), h=1.0 / 16, eps=1e-6, leaf=64))
+    return probs
+
+
+def test_factor_batch_level_synchronous():
+    # The level-synchronous batch (every sub-level one launch sequence over
+    # the groups of all problems; trees of depth 1 to 3, leaves of 36 and 64
+    # points) against one-at-a-time factorizations: the same tree, about the
+    # same ranks, solves that agree to the factorization accuracy, and
+    # residuals through the exact operator within 10 eps; a problem with
+    # coincident points fails alone, reported at its index.
+    rng = np.random.default_rng(52)
+    probs = _batch_specs(rng)
+    facs, status = hif.factor_batch(probs, nworkers=0)
+    assert status[3] == -1 and facs[3] is None
+    for i, pr in enumerate(probs):
+        if i == 3:
+            continue
+        assert status[i] == 0 and facs[i] is not None
+        N = pr["points"].shape[0]
+        f = _t(rng.standard_normal((2, N)))
+        G = hif.factor(pr["points"], pr["eps"], pr["leaf"], a=pr["a"], h=pr["h"])
+        sb, sg = facs[i].stats(), G.stats()
+        assert sb["levels"] == sg["levels"] and sb["n_sublevels"] == sg["n_sublevels"]
+        assert abs(sb["top_size"] - sg["top_size"]) <= 0.05 * sg["top_size"] + 2, (i, sb["top_size"], sg["top_size"])
+        u_b, u_s = facs[i].solve(f), G.solve(f)
+        d = (torch.linalg.norm(u_b - u_s) / torch.linalg.norm(u_s)).item()
+        assert d <= 1e-6, (i, d)
+        y, _ = facs[i].apply_A(u_b)
+        assert (torch.linalg.norm(y - f) / torch.linalg.norm(f)).item() <= 1e-5
+        # transposed solve and apply of a batch handle
+        x = _t(rng.standard_normal(N))
+        lhs = torch.dot(facs[i].solve_T(x), f[0]).item()
+        assert abs(lhs - torch.dot(x, u_b[0]).item()) <= 1e-10 * abs(lhs)
+        Ax, _ = facs[i].apply_A(x)
+        assert (torch.linalg.norm(facs[i].apply(x) - Ax) / torch.linalg.norm(Ax)).item() <= 1e-5
+        G.free()
+        facs[i].free()
+
+
+def test_factor_batch_level_synchronous_3d_and_mixed():
+    # 3D problems of two depths together, and the FP32-mixed mode refined by
+    # GMRES, through the level-synchronous batch
+    rng = np.random.default_rng(53)
+    probs = [dict(points=_t(grid_points(n, 3)), a=_t(1.0 + rng.uniform(size=n ** 3)), h=1.0 / n, eps=1e-6, leaf=64)
+             for n in (16, 8, 12)]
+    facs, status = hif.factor_batch(probs, nworkers=0)
+    assert status == [0, 0, 0]
+    for F, pr in zip(facs, probs):
+        op = Operator.uniform(_np(pr["points"]), pr["h"], a=_np(pr["a"]))
+        A = op.dense()
+        f = rng.standard_normal(op.N)
+        u = _np(F.solve(_t(f)))
+        assert np.linalg.norm(A @ u - f) <= 1e-5 * np.linalg.norm(f)
+        F.free()
+    facs, status = hif.factor_batch(probs[:2], nworkers=0, precision=hif.HIF_FP32_MIXED)
+    assert status == [0, 0]
+    for F, pr in zip(facs, probs):
+        N = pr["points"].shape[0]
+        f = _t(rng.standard_normal((2, N)))
+        u, its, rr = F.gmres(f, tol=1e-10, maxit=30)
+        assert max(rr) <= 1.5e-10 and max(its) <= 10, (its, rr)
+        F.free()
+
+
+def test_solve_graph_replays_match_eager_solves():
+    # A solve recorded as a HIP graph and replayed three times, with eager
+    # work (new right-hand sides written by torch, an eager solve, device
+    # synchronization) between the replays; every replay equals the eager
+    # solve of the same right-hand sides bit for bit.  2D with a top block
+    # above the many-workgroup threshold, and 3D.
+    rng = np.random.default_rng(54)
+    for n, d, nrhs in ((96, 2, 3), (16, 3, 2)):
+        op = _op(n, d)
+        F = _gpu_factor(op, 1e-6, 64 if d == 2 else 27)
+        f = torch.empty((nrhs, op.N), dtype=torch.float64, device=DEV)
+        u = torch.empty_like(f)
+        f.copy_(_t(rng.standard_normal((nrhs, op.N))))
+        g = F.solve_graph(f, u)
+        for rep in range(3):
+            f.copy_(_t(rng.standard_normal((nrhs, op.N))))
+            ref = F.solve(f)
+            torch.cuda.synchronize()
+            g.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(u, ref), (n, d, rep)
+        g.free()
+        F.free()
+
+
+def test_factor_batch_matches_single_factorizations():
+    # Independent problems of uneven sizes and leaves factored concurrently on
+    # 3 worker streams give the same factorizations as one at a time; a
+    # problem with coincident points fails alone, reported at its index.
+    rng = np.random.default_rng(51)
+    probs = _batch_specs(rng)
     facs, status = hif.factor_batch(probs, nworkers=3)
     assert status[3] == -1 and facs[3] is None
     for i, pr in enumerate(probs):
