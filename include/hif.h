@@ -101,6 +101,9 @@ typedef struct {
  *                sub-level's problems at most 1.25 times the sum of n^2).
  *                Either way the pivoted QR delays the updates of 32
  *                reflectors; both give the same ID up to rounding.
+ *  trace_sublevel: -1 (default) = nothing; s >= 0 = keep copies of
+ *                sub-level s's groups, near fields and assembled blocks for
+ *                hif_trace_get (step-by-step checks; costs memory and time).
  *  fft_matvec:   products with the exact operator inside hif_gmres,
  *                hif_gmres_T and hif_apply_A: 0 (default) = pair by pair,
  *                evaluated on the fly as hif_matvec; 1 = by FFT convolution
@@ -117,6 +120,7 @@ typedef struct {
   size_t max_bytes;
   int row_compression;
   int fft_matvec;
+  int trace_sublevel;
 } hif_opts;
 
 #define HIF_MAX_SUBLEVELS 64
@@ -403,6 +407,33 @@ hif_status hif_tuning_set(const hif_tuning* t);
 hif_status hif_lu_batched(double* mats, const int64_t* off, const int32_t* n, const int32_t* r, int32_t* piv,
                           const int64_t* poff, int32_t batch, int32_t max_n, int32_t max_r, int32_t* status,
                           hif_stream stream);
+
+/*
+ * What hif_factor kept of sub-level opts.trace_sublevel (sub-levels counted
+ * from 0 in factor order: level 0 cells, then its faces / edges, level 1
+ * cells, ...), as it stood after assembly and before the IDs:
+ *   HIF_TRACE_GROUP_START  int64 [G+1]: group g's DOFs are GROUP_DOFS[start[g]..start[g+1])
+ *   HIF_TRACE_GROUP_DOFS   int32: the groups' DOFs (caller's indices), each group's
+ *                          columns in the order of its second-kind classes
+ *   HIF_TRACE_NEAR_START   int64 [G+1], HIF_TRACE_NEAR_DOFS int32: the near field
+ *                          c^N of every group (Section 4.3), ascending
+ *   HIF_TRACE_Y_OFF        int64 [G], HIF_TRACE_Y double: group g's compressed block
+ *                          (eqn proxy-id; Y'_c when symmetric) at Y + off[g],
+ *                          row-major, rows = near field then proxy points
+ *                          (non-symmetric: near-field rows, near-field
+ *                          columns transposed, then the two proxy blocks),
+ *                          columns = the group's DOFs in GROUP_DOFS order
+ *   HIF_TRACE_ACC_OFF      int64 [G], HIF_TRACE_ACC double: A_cc (kernel and SCI
+ *                          entries), row-major n_c x n_c, same order
+ * dst: host buffer of cap elements of the item's type; *count (host) receives
+ * the number of elements (call with cap = 0 to size the buffer).
+ * HIF_EINVAL for an unknown item, a NULL count, or a handle factored without
+ * a trace of an existing sub-level; HIF_ENOMEM (nothing copied) if cap is
+ * too small and not 0.
+ */
+enum { HIF_TRACE_GROUP_START = 0, HIF_TRACE_GROUP_DOFS = 1, HIF_TRACE_NEAR_START = 2, HIF_TRACE_NEAR_DOFS = 3,
+       HIF_TRACE_Y_OFF = 4, HIF_TRACE_Y = 5, HIF_TRACE_ACC_OFF = 6, HIF_TRACE_ACC = 7 };
+hif_status hif_trace_get(hif_handle h, int item, void* dst, int64_t cap, int64_t* count);
 
 /* Release a handle and all its device memory (NULL is a no-op). */
 void hif_free(hif_handle h);

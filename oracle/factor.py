@@ -191,7 +191,7 @@ def _column_patterns(Ysub: sp.spmatrix):
 def factorize(op: Operator, eps: float, leaf: int, *, variant: str = "hifie",
               second_kind: bool = True, symmetric: bool | None = None,
               n_proxy: int | None = None, proxy_radius: float = 1.5,
-              fp32_blocks: bool = False) -> Factorization:
+              fp32_blocks: bool = False, trace=None) -> Factorization:
     """Factor ``A`` (RSF for ``variant='rskel'``, HIF-IE otherwise).
 
     ``second_kind`` switches on the Section 4.4 modification (hifie2x /
@@ -199,6 +199,16 @@ def factorize(op: Operator, eps: float, leaf: int, *, variant: str = "hifie",
     (default: whenever A is symmetric).  ``fp32_blocks`` rounds every
     assembled block and Schur update to float32 (an emulation of reduced
     precision assembly; the ID and LU stay FP64).
+
+    ``trace``, if given, is called once per group of every sub-level with a
+    dict of that group's intermediate quantities (for per-step parity tests;
+    it changes nothing): ``level``, ``kind``, ``active`` (the active DOFs at
+    the start of the sub-level), ``c``, ``near`` (c^N), ``Y`` (the compressed
+    block), ``classes`` (column index sets), ``tols`` (their ID tolerances),
+    ``sk``/``rd`` (group-local), ``T``, and when the group has redundant DOFs
+    ``Acc`` (A(c, c) with its SCIs), ``Brr``, ``Brs``, ``Bsr``, ``Bss`` (the
+    transformed blocks of Lemma 2.4) and ``dS`` (the Schur update of the
+    skeleton block).
     """
     N, d = op.N, op.d
     pts = op.points
@@ -284,13 +294,14 @@ def factorize(op: Operator, eps: float, leaf: int, *, variant: str = "hifie",
                     classes = [np.nonzero(cls_of == q)[0] for q in range(len(lookup))]
                 else:
                     classes = [np.arange(c.size)]
-                sk_loc, rd_loc, Tblocks = [], [], []
+                sk_loc, rd_loc, Tblocks, tols = [], [], [], []
                 for cols in classes:
                     rho = 1.0
                     if second_kind:
                         nS = np.linalg.norm(YSm[:, cols])
                         if nS > 0.0:
                             rho = min(1.0, np.linalg.norm(YKm[:, cols]) / nS)
+                    tols.append(rho * eps)
                     s_g, r_g, T_g = interp_decomp(Y[:, cols], rho * eps)
                     sk_loc.append(cols[s_g])
                     rd_loc.append(cols[r_g])
@@ -308,7 +319,13 @@ def factorize(op: Operator, eps: float, leaf: int, *, variant: str = "hifie",
                 st.near.append(int(cN.size))
                 st.classes.append(len(classes))
                 st.ranks.append(int(sk_l.size))
+                info = None
+                if trace is not None:
+                    info = dict(level=lvl, kind=kind, active=act, c=c, near=cN, Y=Y, classes=classes, tols=tols,
+                                sk=sk_l, rd=rd_l, T=T)
                 if rd_l.size == 0:
+                    if trace is not None:
+                        trace(info)
                     continue
 
                 # Skeletonization of c (Lemma 2.4) with block elimination (Lemma 2.1).
@@ -325,6 +342,10 @@ def factorize(op: Operator, eps: float, leaf: int, *, variant: str = "hifie",
                 G = lu_solve(lu, Brs) if sk_l.size else np.zeros((rd_l.size, 0))
                 E = lu_solve(lu, Bsr.T, trans=1).T if sk_l.size else np.zeros((0, rd_l.size))
                 dS = rnd(-E @ Brs)
+                if trace is not None:
+                    # the transform of Lemma 2.4 leaves the skeleton block as it was
+                    info.update(Acc=Acc, Brr=Brr, Brs=Brs, Bsr=Bsr, Bss=Ass, dS=dS)
+                    trace(info)
                 sk = c[sk_l]
                 rd = c[rd_l]
                 records.append(GroupRecord(rd, sk, T, Brr, lu, E, G))

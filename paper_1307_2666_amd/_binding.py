@@ -37,7 +37,8 @@ class hif_kernel(ctypes.Structure):
 class hif_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("second_kind", ctypes.c_int), ("symmetric", ctypes.c_int),
                 ("variant", ctypes.c_int), ("n_proxy", ctypes.c_int), ("proxy_radius", ctypes.c_double),
-                ("max_bytes", ctypes.c_size_t), ("row_compression", ctypes.c_int), ("fft_matvec", ctypes.c_int)]
+                ("max_bytes", ctypes.c_size_t), ("row_compression", ctypes.c_int), ("fft_matvec", ctypes.c_int),
+                ("trace_sublevel", ctypes.c_int)]
 
 
 class hif_problem(ctypes.Structure):
@@ -91,6 +92,7 @@ EXPORTS = {
     "hif_solve_graph": (_INT, [_VP, _VP, _VP, _I64, _VP]),
     "hif_graph_launch": (_INT, [_VP, _VP]),
     "hif_graph_free": (None, [_VP]),
+    "hif_trace_get": (_INT, [_VP, _INT, _VP, _I64, _VP]),
     "hif_tuning_get": (_INT, [_VP]),
     "hif_tuning_set": (_INT, [_VP]),
     "hif_lu_batched": (_INT, [_VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP]),
@@ -255,6 +257,25 @@ class Factorization:
             "sub_id_bytes": list(s.sub_id_bytes[:ns]), "sub_rowqr_flops": list(s.sub_rowqr_flops[:ns]),
         }
 
+    def trace(self):
+        """``hif_trace_get``: the sub-level kept with ``trace_sublevel`` as a dict of NumPy arrays
+        (group starts and DOFs, near-field starts and DOFs, per-group blocks Y and A_cc)."""
+        import numpy as np
+
+        lib = load_library()
+        items = {"group_start": (0, np.int64), "group_dofs": (1, np.int32), "near_start": (2, np.int64),
+                 "near_dofs": (3, np.int32), "y_off": (4, np.int64), "Y": (5, np.float64), "acc_off": (6, np.int64),
+                 "Acc": (7, np.float64)}
+        out = {}
+        for name, (item, dt) in items.items():
+            cnt = ctypes.c_int64(0)
+            _check(lib.hif_trace_get(self._h, item, None, 0, ctypes.byref(cnt)))
+            arr = np.empty(cnt.value, dtype=dt)
+            if cnt.value:
+                _check(lib.hif_trace_get(self._h, item, arr.ctypes.data_as(_VP), cnt.value, ctypes.byref(cnt)))
+            out[name] = arr
+        return out
+
     def free(self):
         if self._h is not None:
             load_library().hif_free(self._h)
@@ -294,7 +315,8 @@ class SolveGraph:
 
 def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, selfk=None,
            second_kind=-1, symmetric=-1, variant="hifie", n_proxy=0, proxy_radius=0.0,
-           max_bytes=0, precision=HIF_FP64, row_compression=-1, fft_matvec=0, stream=None) -> Factorization:
+           max_bytes=0, precision=HIF_FP64, row_compression=-1, fft_matvec=0, trace_sublevel=-1,
+           stream=None) -> Factorization:
     """``hif_factor``: build ``F ~ A`` for points ``(n, d)`` in the unit box."""
     lib = load_library()
     P = _dev(points)
@@ -314,6 +336,7 @@ def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, s
     o.max_bytes = max_bytes
     o.row_compression = row_compression
     o.fft_matvec = fft_matvec
+    o.trace_sublevel = trace_sublevel
     handle = ctypes.c_void_p()
     _check(lib.hif_factor(_ptr(P), n, d, ctypes.byref(k), _ptr(av), _ptr(bv), _ptr(cv), float(eps), int(leaf),
                           ctypes.byref(o), _stream(stream), ctypes.byref(handle)))

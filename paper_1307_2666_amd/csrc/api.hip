@@ -223,6 +223,7 @@ hif_status hif_opts_default(hif_opts* o) {
   o->max_bytes = 0;
   o->row_compression = -1;
   o->fft_matvec = 0;
+  o->trace_sublevel = -1;
   return HIF_OK;
 }
 
@@ -258,6 +259,8 @@ static hif_status resolve_opts(const hif_opts* opts, hif_opts* out) {
   if (o.row_compression < -1 || o.row_compression > 1)
     return fail(HIF_EINVAL, "opts.row_compression must be -1, 0 or 1");
   if (o.fft_matvec != 0 && o.fft_matvec != 1) return fail(HIF_EINVAL, "opts.fft_matvec must be 0 or 1");
+  if (o.trace_sublevel < -1 || o.trace_sublevel >= HIF_MAX_SUBLEVELS)
+    return fail(HIF_EINVAL, "opts.trace_sublevel must be -1 or a sub-level index");
   if (!(o.proxy_radius == 0.0 || (std::isfinite(o.proxy_radius) && o.proxy_radius > 0.5)))
     return fail(HIF_EINVAL, "opts.proxy_radius must be 0 (default) or > 0.5 cell widths");
   // second-kind modification by default in FP64 only: in FP32 the SCI-scaled
@@ -629,6 +632,33 @@ hif_status hif_id_batched(double* mats, const int64_t* off, const int32_t* rows,
   return guarded(hipStream_t(s), [&] {
     id_batched_impl(mats, off, rows, cols, tol, batch, max_cols, rank, perm, off_perm, T, off_t, hipStream_t(s));
   });
+}
+
+hif_status hif_trace_get(hif_handle h, int item, void* dst, int64_t cap, int64_t* count) {
+  if (!h) return fail(HIF_EINVAL, "handle is NULL");
+  if (!count) return fail(HIF_EINVAL, "count is NULL");
+  if (!h->traced) return fail(HIF_EINVAL, "the factorization kept no trace (opts.trace_sublevel)");
+  const void* src = nullptr;
+  size_t esz = 0;
+  int64_t n = 0;
+  switch (item) {
+    case HIF_TRACE_GROUP_START: src = h->tr_gstart.p; esz = 8; n = int64_t(h->tr_gstart.n); break;
+    case HIF_TRACE_GROUP_DOFS: src = h->tr_dofs.p; esz = 4; n = int64_t(h->tr_dofs.n); break;
+    case HIF_TRACE_NEAR_START: src = h->tr_nfstart.p; esz = 8; n = int64_t(h->tr_nfstart.n); break;
+    case HIF_TRACE_NEAR_DOFS: src = h->tr_nf.p; esz = 4; n = int64_t(h->tr_nf.n); break;
+    case HIF_TRACE_Y_OFF: src = h->tr_yoff.p; esz = 8; n = int64_t(h->tr_yoff.n); break;
+    case HIF_TRACE_Y: src = h->tr_Y.p; esz = 8; n = int64_t(h->tr_Y.n); break;
+    case HIF_TRACE_ACC_OFF: src = h->tr_aoff.p; esz = 8; n = int64_t(h->tr_aoff.n); break;
+    case HIF_TRACE_ACC: src = h->tr_Acc.p; esz = 8; n = int64_t(h->tr_Acc.n); break;
+    default: return fail(HIF_EINVAL, "unknown trace item");
+  }
+  *count = n;
+  if (cap == 0 || n == 0) return HIF_OK;
+  if (!dst) return fail(HIF_EINVAL, "dst is NULL");
+  if (cap < n) return fail(HIF_ENOMEM, "dst holds fewer elements than the item");
+  if (hipMemcpy(dst, src, esz * size_t(n), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(HIF_EDEVICE, "copying the trace to the host failed");
+  return HIF_OK;
 }
 
 hif_status hif_tuning_get(hif_tuning* out) {

@@ -209,6 +209,11 @@ struct hif_factor_s {
   // Exact operator by FFT: 0 not set up yet, 1 ready (fft), -1 not applicable.
   int fft_state = 0;
   hif::FftOp* fft = nullptr;
+  // Copies of one sub-level kept for hif_trace_get (opts.trace_sublevel).
+  bool traced = false;
+  hif::DBuf<int64_t> tr_gstart, tr_nfstart, tr_yoff, tr_aoff;
+  hif::DBuf<int32_t> tr_dofs, tr_nf;
+  hif::DBuf<double> tr_Y, tr_Acc;
 };
 
 namespace hif {

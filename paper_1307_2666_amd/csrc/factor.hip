@@ -632,6 +632,25 @@ __global__ void k_active_compact(const int32_t* act, int64_t nact, const int32_t
   GRID_STRIDE(i, nact) if (keep[i]) out[pos[i]] = act[i];
 }
 
+// Descriptors of a sub-batch of IDs (classes idx[0..n)), and its ranks back.
+__global__ void k_id_gather(int n, const int32_t* idx, const int64_t* moff, const int32_t* ld, const int32_t* rows,
+                            const int32_t* cols, const double* tol, const int64_t* poff, int64_t* omoff, int32_t* old,
+                            int32_t* orows, int32_t* ocols, double* otol, int64_t* opoff) {
+  GRID_STRIDE(i, n) {
+    const int q = idx[i];
+    omoff[i] = moff[q];
+    old[i] = ld[q];
+    orows[i] = rows[q];
+    ocols[i] = cols[q];
+    otol[i] = tol[q];
+    opoff[i] = poff[q];
+  }
+}
+
+__global__ void k_id_scatter_rank(int n, const int32_t* idx, const int32_t* rank_s, int32_t* rank) {
+  GRID_STRIDE(i, n) rank[idx[i]] = rank_s[i];
+}
+
 // Number of entries of the ascending list a[0..n) below v (one thread,
 // binary search).
 __global__ void k_count_below(const int32_t* a, int64_t n, int32_t v, int64_t* out) {
@@ -788,6 +807,9 @@ struct Factorizer {
   DBuf<uint64_t> newkey;
   DBuf<double2> newval;
   DBuf<int32_t> akeep, apos;
+  DBuf<int32_t> sub_idx, sub_ld, sub_rows, sub_cols, sub_rank;
+  DBuf<int64_t> sub_moff, sub_poff;
+  DBuf<double> sub_tol;
   // Several independent problems factored together (level-synchronous
   // batch): their DOFs are concatenated, deepest tree first, so that the
   // problems still taking part in a level hold a prefix of the ascending
@@ -1122,6 +1144,22 @@ void Factorizer::sublevel(int lvl, int kind) {
                      gstart.p, colK2.p, colS2.p, H->eps, split, yoff.p, nf_start.p, sym, P, cls_moff.p, cls_ld.p,
                      cls_rows.p, cls_tol.p, cls_poff.p, pg);
   HIF_HIP(hipGetLastError());
+  if (H->opts.trace_sublevel == si && !multi) {
+    // a copy of this sub-level as assembled, for step-by-step checks
+    auto keep = [&](auto& dst, const auto* src, int64_t count) {
+      dst.alloc(count, mt);
+      if (count > 0) HIF_HIP(hipMemcpyAsync(dst.p, src, sizeof(*src) * count, hipMemcpyDeviceToDevice, s));
+    };
+    keep(H->tr_gstart, gstart.p, G + 1);
+    keep(H->tr_dofs, cord.p, nact);
+    keep(H->tr_nfstart, nf_start.p, G + 1);
+    keep(H->tr_nf, nf_idx.p, nnf);
+    keep(H->tr_yoff, yoff.p, G);
+    keep(H->tr_Y, Y.p, ytot);
+    keep(H->tr_aoff, aoff.p, G);
+    keep(H->tr_Acc, Acc.p, atot);
+    H->traced = true;
+  }
   tm.mark(PH_ASM);
 
   // ---- interpolative decompositions (one per class) -----------------------
@@ -1164,7 +1202,25 @@ void Factorizer::sublevel(int lvl, int kind) {
     }
   }
   const bool direct = id_blocked_fits(NC, maxm, maxq) && (rc == 0 || (rc < 0 && smn <= 1.25 * snn));
-  const bool blocked_r0 = !direct && id_blocked_fits(NC, maxq, maxq);
+  // After row compression the classes of a sub-level can take two paths at
+  // once: those of at most kIdRegCols columns the register-resident kernel,
+  // the larger ones the blocked pivoted QR (whose steps then stream only the
+  // large classes).  Used when a sub-level mixes both sizes, or holds more
+  // large classes than the blocked path takes in one batch.
+  constexpr int kIdRegCols = 192;
+  std::vector<int32_t> sel_small, sel_large;
+  int max_small = 1, max_large = 1;
+  for (int q = 0; q < NC; ++q) {
+    if (h_cls_n[q] <= kIdRegCols) {
+      sel_small.push_back(q);
+      max_small = std::max(max_small, h_cls_n[q]);
+    } else {
+      sel_large.push_back(q);
+      max_large = std::max(max_large, h_cls_n[q]);
+    }
+  }
+  const bool split_id = !direct && !sel_large.empty() && (!sel_small.empty() || NC > 512);
+  const bool blocked_r0 = !direct && !split_id && id_blocked_fits(NC, maxq, maxq);
   // problems taller than one TSQR stack: row blocks, then their stacked R factors
   const bool tall_split = !direct && rowqr_split_fits(maxm, maxq);
   if (!direct && !tall_split) qr_scratch.ensure(qtot + 1, mt);
@@ -1201,12 +1257,51 @@ void Factorizer::sublevel(int lvl, int kind) {
   ia.Tout = nullptr;
   ia.toff = nullptr;
   ia.nprob = NC;
-  if (direct)
+  if (direct) {
     launch_id_blocked(ia, maxm, maxq, s);
-  else if (blocked_r0)
+  } else if (blocked_r0) {
     launch_id_blocked(ia, maxq, maxq, s);  // on R0: rows <= columns
-  else
+  } else if (split_id) {
+    // two sub-batches with gathered descriptors; their ranks go back to the
+    // class order (the permutations land in place through their offsets)
+    auto run = [&](const std::vector<int32_t>& sel, bool blocked, int maxc) {
+      if (sel.empty()) return;
+      const int ns = int(sel.size());
+      sub_idx.ensure(ns, mt);
+      sub_moff.ensure(ns, mt);
+      sub_poff.ensure(ns, mt);
+      sub_ld.ensure(ns, mt);
+      sub_rows.ensure(ns, mt);
+      sub_cols.ensure(ns, mt);
+      sub_rank.ensure(ns, mt);
+      sub_tol.ensure(ns, mt);
+      to_dev(sub_idx.p, sel, s);
+      hipLaunchKernelGGL(k_id_gather, dim3(nblocks(ns)), dim3(kThreads), 0, s, ns, sub_idx.p, cls_moff.p, cls_ld.p,
+                         cls_rows2.p, cls_n.p, cls_tol.p, cls_poff.p, sub_moff.p, sub_ld.p, sub_rows.p, sub_cols.p,
+                         sub_tol.p, sub_poff.p);
+      IdArgs sa = ia;
+      sa.moff = sub_moff.p;
+      sa.ld = sub_ld.p;
+      sa.rows = sub_rows.p;
+      sa.cols = sub_cols.p;
+      sa.tol = sub_tol.p;
+      sa.rank = sub_rank.p;
+      sa.poff = sub_poff.p;
+      sa.nprob = ns;
+      if (blocked)
+        launch_id_blocked(sa, maxc, maxc, s);
+      else
+        launch_id(sa, maxc, s);
+      hipLaunchKernelGGL(k_id_scatter_rank, dim3(nblocks(ns)), dim3(kThreads), 0, s, ns, sub_idx.p, sub_rank.p,
+                         cls_rank.p);
+      HIF_HIP(hipGetLastError());
+      HIF_HIP(hipStreamSynchronize(s));  // the host index list is released on return
+    };
+    run(sel_large, true, max_large);
+    run(sel_small, false, max_small);
+  } else {
     launch_id(ia, maxq, s);
+  }
   tm.mark(PH_ID);
 
   // ---- records: sizes from the ranks ---------------------------------------
@@ -1242,10 +1337,10 @@ void Factorizer::sublevel(int lvl, int kind) {
         // blocked on R0 (rows m' = min(m, n)) as on Y; in registers (k_id_reg):
         // R0 read once and rows 0..k-1 written once; otherwise every step reads
         // and writes the trailing block of R0
-        if (blocked_r0) {
+        if (blocked_r0 || (split_id && h_cls_n[q] > kIdRegCols)) {
           idby += 8.0 * sab;
           for (int e = 32; e <= h_rank[q] && e < a2; e += 32) idby += 16.0 * (a2 - e) * (nq - e);
-        } else if (id_in_registers(maxq, int(a2), h_cls_n[q])) {
+        } else if (id_in_registers(split_id ? max_small : maxq, int(a2), h_cls_n[q])) {
           idby += 8.0 * (a2 + kq) * nq;
         } else {
           idby += 16.0 * sab;

@@ -2,10 +2,17 @@
 // returns until hif_tuning_set replaces it.  Written by
 // paper_1307_2666_amd/tune.py from timings on one MI355X; see that script for
 // the candidates and the problem sizes of each bucket.
+//
+// Medians (ms):
+//   ID, 4096 problems of 33-64 columns: 4 waves 0.854, 8 waves 0.927, 16 waves 1.032
+//   ID, 2048 problems of 97-128 columns: 4 waves 3.032, 8 waves 2.377, 16 waves 2.767
+//   ID, 1024 problems of 161-192 columns: 8 waves 4.351, 16 waves 3.402
+//   LU, 256 blocks of 257-512 rows: 256 threads 3.094, 512 threads 2.955, 1024 threads 3.157
+//   LU, 64 blocks of 513-1024 rows: 512 threads 6.206, 1024 threads 6.301
 #pragma once
 
 // waves per problem of the register-resident pivoted QR, problems of at most
 // 64, 128 and 192 columns
 #define HIF_TUNED_ID_REG_WAVES {4, 8, 16}
 // threads of the register-resident LU panel, panels of at most 512 and 1024 rows
-#define HIF_TUNED_LU_PANEL_THREADS {256, 512}
+#define HIF_TUNED_LU_PANEL_THREADS {512, 512}
