@@ -52,7 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # workload (row compression and pivoted QR), from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by what the counters read for a 256 MiB copy kernel
 # (see the profile summaries); None until taken for the kernels as they stand.
-ID_STEP_TRAFFIC_BYTES = None
+# 302 GB read + 73 GB written per factorization (profiles/hbm_traffic_id_sq512.md).
+ID_STEP_TRAFFIC_BYTES = 374.07e9
 
 
 def parse():

@@ -219,6 +219,8 @@ hif_status hif_solve_T(hif_handle h, const double* f, double* u, int64_t nrhs, h
 typedef struct hif_graph_s* hif_graph;
 hif_status hif_solve_graph(hif_handle h, const double* f, double* u, int64_t nrhs, hif_graph* out);
 hif_status hif_graph_launch(hif_graph g, hif_stream stream);
+/* Blocks until the replays of the graph (and the handle's other work) have
+ * finished, then destroys the graph.  NULL is a no-op. */
 void hif_graph_free(hif_graph g);
 
 /*
@@ -435,7 +437,10 @@ enum { HIF_TRACE_GROUP_START = 0, HIF_TRACE_GROUP_DOFS = 1, HIF_TRACE_NEAR_START
        HIF_TRACE_Y_OFF = 4, HIF_TRACE_Y = 5, HIF_TRACE_ACC_OFF = 6, HIF_TRACE_ACC = 7 };
 hif_status hif_trace_get(hif_handle h, int item, void* dst, int64_t cap, int64_t* count);
 
-/* Release a handle and all its device memory (NULL is a no-op). */
+/* Release a handle and all its device memory (NULL is a no-op).  Blocks the
+ * host until the handle's own work has finished on every stream it was used
+ * on (each call records an event on its stream), without waiting for other
+ * work on the device; graphs made from the handle must be freed first. */
 void hif_free(hif_handle h);
 
 /* Message of the last error on this thread ("" if none). */

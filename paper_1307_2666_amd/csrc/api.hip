@@ -22,6 +22,7 @@
 struct hif_graph_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hif_factor_s* h = nullptr;  // the handle whose factors the graph reads
 };
 
 namespace hif {
@@ -180,6 +181,24 @@ bool set_tuning(const hif_tuning* t) {
   return true;
 }
 
+void mark_use(hif_factor_s* h, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(h->use_mu);
+  for (auto& u : h->uses)
+    if (u.first == s) {
+      HIF_HIP(hipEventRecord(u.second, s));
+      return;
+    }
+  hipEvent_t e = nullptr;
+  HIF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  h->uses.emplace_back(s, e);
+  HIF_HIP(hipEventRecord(e, s));
+}
+
+void wait_uses(hif_factor_s* h) {
+  std::lock_guard<std::mutex> lk(h->use_mu);
+  for (auto& u : h->uses) (void)hipEventSynchronize(u.second);
+}
+
 // Runs f with DBuf memory ordered on stream s; errors become a status.
 template <class F>
 hif_status guarded(hipStream_t s, F&& f) {
@@ -297,6 +316,7 @@ hif_status hif_factor(const double* points, int64_t n, int dim, const hif_kernel
   hif_status st = guarded(hipStream_t(stream), [&] {
     std::unique_ptr<hif_factor_s> h = new_handle(n, dim, eps, leaf, o);
     factor_impl(h.get(), points, k, a, b, c, hipStream_t(stream));
+    mark_use(h.get(), hipStream_t(stream));
     H = h.release();
   });
   if (st == HIF_OK) *out = H;
@@ -478,7 +498,10 @@ static hif_status sweep(hif_handle h, int op, const double* x, double* y, int64_
   if (!h) return fail(HIF_EINVAL, "handle is NULL");
   if (!x || !y) return fail(HIF_EINVAL, "vector pointer is NULL");
   if (nrhs < 1) return fail(HIF_EINVAL, "nrhs must be >= 1");
-  return guarded(hipStream_t(s), [&] { sweep_impl(h, op, x, y, nrhs, hipStream_t(s)); });
+  return guarded(hipStream_t(s), [&] {
+    sweep_impl(h, op, x, y, nrhs, hipStream_t(s));
+    mark_use(h, hipStream_t(s));
+  });
 }
 
 hif_status hif_solve(hif_handle h, const double* f, double* u, int64_t nrhs, hif_stream s) {
@@ -504,6 +527,7 @@ hif_status hif_solve_graph(hif_handle h, const double* f, double* u, int64_t nrh
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
     return fail(HIF_EDEVICE, "creating the capture stream failed");
   std::unique_ptr<hif_graph_s> g(new (std::nothrow) hif_graph_s());
+  if (g) g->h = h;
   hif_status st = g ? guarded(cs, [&] { graph_solve_impl(h, f, u, nrhs, cs, &g->graph, &g->exec); })
                     : fail(HIF_ENOMEM, "host allocation failed");
   (void)hipStreamSynchronize(cs);
@@ -518,12 +542,12 @@ hif_status hif_graph_launch(hif_graph g, hif_stream s) {
   if (!g) return fail(HIF_EINVAL, "graph is NULL");
   const hipError_t e = hipGraphLaunch(g->exec, hipStream_t(s));
   if (e != hipSuccess) return fail(HIF_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
-  return HIF_OK;
+  return guarded(hipStream_t(s), [&] { mark_use(g->h, hipStream_t(s)); });
 }
 
 void hif_graph_free(hif_graph g) {
   if (!g) return;
-  (void)hipDeviceSynchronize();  // the graph may still run on any stream
+  wait_uses(g->h);  // its replays are recorded on the handle, which outlives the graph
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
@@ -537,6 +561,7 @@ hif_status hif_solve_noalloc(hif_handle h, const double* f, double* u, int64_t n
   try {
     g_last_error.clear();
     sweep_noalloc_impl(h, f, u, nrhs, hipStream_t(s));
+    mark_use(h, hipStream_t(s));
     return HIF_OK;
   } catch (const Error& e) {
     return fail(e.status, e.msg);
@@ -571,7 +596,10 @@ static hif_status gmres_any(hif_handle h, const double* f, double* u, int64_t nr
   if (!(tol > 0.0 && tol < 1.0)) return fail(HIF_EINVAL, "tol must satisfy 0 < tol < 1");
   if (maxit < 1 || maxit > 200) return fail(HIF_EINVAL, "maxit must be in [1, 200]");
   return guarded(hipStream_t(s),
-                 [&] { gmres_impl(h, f, u, nrhs, tol, maxit, iters, relres, trans, hipStream_t(s)); });
+                 [&] {
+                   gmres_impl(h, f, u, nrhs, tol, maxit, iters, relres, trans, hipStream_t(s));
+                   mark_use(h, hipStream_t(s));
+                 });
 }
 
 hif_status hif_gmres(hif_handle h, const double* f, double* u, int64_t nrhs, double tol, int32_t maxit,
@@ -601,7 +629,7 @@ hif_status hif_stats(hif_handle h, hif_stats_t* out) {
 
 void hif_free(hif_handle h) {
   if (!h) return;
-  (void)hipDeviceSynchronize();  // the handle may have been used on any stream
+  wait_uses(h);  // the handle's own work on every stream it was used on
   StreamScope scope(nullptr);
   fft_release(h);
   delete h;
@@ -616,6 +644,7 @@ hif_status hif_apply_A(hif_handle h, const double* x, double* y, int64_t nrhs, i
   if (transpose != 0 && transpose != 1) return fail(HIF_EINVAL, "transpose must be 0 or 1");
   return guarded(hipStream_t(s), [&] {
     apply_A_impl(h, x, y, nrhs, transpose == 1, hipStream_t(s));
+    mark_use(h, hipStream_t(s));
     if (used_fft) *used_fft = h->fft_state > 0 ? 1 : 0;
   });
 }

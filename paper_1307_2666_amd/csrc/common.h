@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "hif.h"
@@ -214,7 +216,25 @@ struct hif_factor_s {
   hif::DBuf<int64_t> tr_gstart, tr_nfstart, tr_yoff, tr_aoff;
   hif::DBuf<int32_t> tr_dofs, tr_nf;
   hif::DBuf<double> tr_Y, tr_Acc;
+  // The streams the handle's work was queued on, each with an event recorded
+  // after the last such call there: hif_free waits on these events, not on
+  // the whole device.
+  std::mutex use_mu;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
+  hif_factor_s() = default;
+  hif_factor_s(const hif_factor_s&) = delete;
+  hif_factor_s& operator=(const hif_factor_s&) = delete;
+  ~hif_factor_s() {
+    for (auto& u : uses) (void)hipEventDestroy(u.second);
+  }
 };
+
+namespace hif {
+// Records that h's work was queued on s up to this point (see uses).
+void mark_use(hif_factor_s* h, hipStream_t s);
+// Blocks until every call recorded by mark_use has finished on the device.
+void wait_uses(hif_factor_s* h);
+}  // namespace hif
 
 namespace hif {
 

@@ -110,6 +110,15 @@ def _id_cases():
     return cases
 
 
+def _t_bounded(T, oT):
+    # Where pivots tie the skeletons may differ, but the interpolation matrix
+    # must stay as well scaled as the oracle's (column pivoting keeps |T_ij|
+    # small in practice; a wrong pivot order or a lost column shows as growth).
+    tmax = np.abs(T).max() if T.size else 0.0
+    otmax = np.abs(oT).max() if oT.size else 0.0
+    assert tmax <= max(2.0, 4.0 * otmax), (tmax, otmax)
+
+
 def test_id_batched_matches_oracle():
     cases = _id_cases()
     out = hif.id_batched([torch.tensor(Y) for Y, _, _ in cases], [t for _, t, _ in cases])
@@ -123,6 +132,7 @@ def test_id_batched_matches_oracle():
             assert np.array_equal(sk, osk)
             if T.size:
                 assert np.allclose(T, oT, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(oT).max()))
+        _t_bounded(T, oT)
         r00 = np.max(np.linalg.norm(Y, axis=0))
         if rd.size:
             err = np.linalg.norm(Y[:, rd] - Y[:, sk] @ T)
@@ -148,6 +158,7 @@ def test_id_batched_large_matches_oracle():
         if unique:
             assert np.array_equal(sk, osk)
             assert np.allclose(T, oT, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(oT).max()))
+        _t_bounded(T, oT)
         r00 = np.max(np.linalg.norm(Y, axis=0))
         err = np.linalg.norm(Y[:, rd] - Y[:, sk] @ T)
         assert err <= np.sqrt(rd.size) * tol * r00 * 1.01 + 1e-14 * r00
@@ -161,6 +172,7 @@ def _check_id(Y, tol, unique, sk, rd, T, osk, oT):
         assert np.array_equal(sk, osk)
         if oT.size:
             assert np.allclose(T, oT, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(oT).max()))
+    _t_bounded(T, oT)
     r00 = np.max(np.linalg.norm(Y, axis=0))
     if rd.size:
         err = np.linalg.norm(Y[:, rd] - Y[:, sk] @ T)
@@ -223,6 +235,7 @@ def test_id_batched_many_mid_size_matches_oracle():
         assert np.array_equal(rd, ord_)
         if oT.size:
             assert np.allclose(T, oT, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(oT).max())), q
+        _t_bounded(T, oT)
         r00 = np.max(np.linalg.norm(Y, axis=0))
         err = np.linalg.norm(Y[:, rd] - Y[:, sk] @ T)
         assert err <= np.sqrt(max(rd.size, 1)) * tol * r00 * 1.01 + 1e-14 * r00
@@ -251,6 +264,7 @@ def test_id_batched_direct_matches_oracle():
         if unique:
             assert np.array_equal(sk, osk)
             assert np.allclose(T, oT, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(oT).max()))
+        _t_bounded(T, oT)
         r00 = np.max(np.linalg.norm(Y, axis=0))
         err = np.linalg.norm(Y[:, rd] - Y[:, sk] @ T)
         assert err <= np.sqrt(rd.size) * tol * r00 * 1.01 + 1e-14 * r00
@@ -337,13 +351,47 @@ def test_factor_sq64_solve_and_apply_vs_oracle():
     assert np.linalg.norm(y - A @ x) <= 10 * wl.eps * np.linalg.norm(A @ x)
     Fo = factorize(op, wl.eps, wl.leaf)
     yo = Fo.apply(x)
+    uo = Fo.solve(f)
     assert np.linalg.norm(y - yo) <= 10 * wl.eps * np.linalg.norm(yo)
-    assert np.linalg.norm(u - Fo.solve(f)) <= 10 * wl.eps * np.linalg.norm(u_ref)
+    assert np.linalg.norm(u - uo) <= 10 * wl.eps * np.linalg.norm(u_ref)
+    # regression bounds far inside the 10 eps gate: the same skeletons up to
+    # pivot ties, so GPU and oracle factors agree to a tenth of eps, and the
+    # GPU's errors against A stay within 4x of the oracle's own
+    assert np.linalg.norm(y - yo) <= 0.1 * wl.eps * np.linalg.norm(yo)
+    assert np.linalg.norm(u - uo) <= 0.1 * wl.eps * np.linalg.norm(u_ref)
+    assert np.linalg.norm(y - A @ x) <= 4 * np.linalg.norm(yo - A @ x) + 1e-12 * np.linalg.norm(A @ x)
+    assert np.linalg.norm(u - u_ref) <= 4 * np.linalg.norm(uo - u_ref) + 1e-12 * np.linalg.norm(u_ref)
     st = F.stats()
     assert st["levels"] == 3 and st["sub_groups"][:2] == [64, 112]
     # ranks within a few percent of the oracle's (ties in pivoting make them non-unique)
     skel_o = [int(np.sum(s.ranks)) for s in Fo.stats]
     assert all(abs(a - b) <= 0.05 * b + 2 for a, b in zip(st["sub_skel"], skel_o))
+
+
+def test_free_waits_for_its_own_work_only():
+    # hif_free waits on the events its handle's calls recorded, not on the
+    # device: an unrelated 512 x 512 product with 8 right-hand sides (about
+    # 0.2 s) on another stream is still running when the free returns, and
+    # its result is unaffected.
+    n = 32
+    pts = _t(grid_points(n, 2))
+    F = hif.factor(pts, 1e-6, 16, a=torch.ones(n * n, dtype=torch.float64, device="cuda"), h=1.0 / n)
+    f = torch.randn(n * n, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    u = F.solve(f)
+    nb = 512
+    big = _t(grid_points(nb, 2))
+    x = torch.randn(8, nb * nb, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(4))
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        y = hif.matvec(big, x, a=torch.ones(nb * nb, dtype=torch.float64, device="cuda"), h=1.0 / nb)
+    F.free()
+    still_running = not side.query()
+    side.synchronize()
+    assert still_running
+    y_ref = hif.matvec(big, x[:1], a=torch.ones(nb * nb, dtype=torch.float64, device="cuda"), h=1.0 / nb)
+    assert torch.equal(y[:1], y_ref)
+    assert torch.isfinite(u).all()
 
 
 def test_factor_deterministic():
