@@ -375,8 +375,14 @@ hif_status hif_factor_batch(const hif_problem* problems, int32_t count, const hi
  *   lu_panel_threads[b]: threads of the register-resident LU panel (partial
  *     pivoting, Lemma 2.1) for panels of at most 512 (b = 0) and 1024 (b = 1)
  *     rows; allowed 256, 512 or 1024 for b = 0, 512 or 1024 for b = 1.
+ *   rowqr_update_waves: waves (16 columns each) per workgroup of the
+ *     trailing update that the row compression (Householder QR of Y before
+ *     each ID) runs beside the factorization of the next panel; 4 or 8.
+ *   rowqr_update_lds: 1 stages each chunk's reflectors in LDS before that
+ *     update, 0 reads them from memory inside its products.
  * The built-in table comes from paper_1307_2666_amd/tune.py, which times the
- * candidates with hif_id_batched and hif_lu_batched.  hif_tuning_set(NULL)
+ * candidates with hif_id_batched and hif_lu_batched, and the row-compression
+ * shapes with hif_id_batched on tall blocks.  hif_tuning_set(NULL)
  * restores it; any other call replaces the table for the whole process (calls
  * already queued keep the shapes they were launched with).  HIF_EINVAL for an
  * entry outside the allowed values (the table is then unchanged).
@@ -384,6 +390,8 @@ hif_status hif_factor_batch(const hif_problem* problems, int32_t count, const hi
 typedef struct {
   int32_t id_reg_waves[3];
   int32_t lu_panel_threads[2];
+  int32_t rowqr_update_waves;
+  int32_t rowqr_update_lds;
 } hif_tuning;
 hif_status hif_tuning_get(hif_tuning* out);
 hif_status hif_tuning_set(const hif_tuning* t);

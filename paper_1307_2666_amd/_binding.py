@@ -48,7 +48,8 @@ class hif_problem(ctypes.Structure):
 
 
 class hif_tuning(ctypes.Structure):
-    _fields_ = [("id_reg_waves", ctypes.c_int32 * 3), ("lu_panel_threads", ctypes.c_int32 * 2)]
+    _fields_ = [("id_reg_waves", ctypes.c_int32 * 3), ("lu_panel_threads", ctypes.c_int32 * 2),
+                ("rowqr_update_waves", ctypes.c_int32), ("rowqr_update_lds", ctypes.c_int32)]
 
 
 class hif_stats_t(ctypes.Structure):
@@ -473,7 +474,8 @@ def tuning_get() -> dict:
     """``hif_tuning_get``: the launch-shape table in use."""
     t = hif_tuning()
     _check(load_library().hif_tuning_get(ctypes.byref(t)))
-    return {"id_reg_waves": list(t.id_reg_waves), "lu_panel_threads": list(t.lu_panel_threads)}
+    return {"id_reg_waves": list(t.id_reg_waves), "lu_panel_threads": list(t.lu_panel_threads),
+            "rowqr_update_waves": int(t.rowqr_update_waves), "rowqr_update_lds": int(t.rowqr_update_lds)}
 
 
 def tuning_set(table=None):
@@ -484,6 +486,8 @@ def tuning_set(table=None):
     t = hif_tuning()
     t.id_reg_waves[:] = list(table["id_reg_waves"])
     t.lu_panel_threads[:] = list(table["lu_panel_threads"])
+    t.rowqr_update_waves = int(table["rowqr_update_waves"])
+    t.rowqr_update_lds = int(table["rowqr_update_lds"])
     _check(load_library().hif_tuning_set(ctypes.byref(t)))
 
 

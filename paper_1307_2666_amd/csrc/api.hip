@@ -155,7 +155,8 @@ bool dbuf_give(void* p, size_t cls, hipStream_t s) {
 namespace {
 std::mutex g_tune_mu;
 hif_tuning builtin_tuning() {
-  hif_tuning t{HIF_TUNED_ID_REG_WAVES, HIF_TUNED_LU_PANEL_THREADS};
+  hif_tuning t{HIF_TUNED_ID_REG_WAVES, HIF_TUNED_LU_PANEL_THREADS, HIF_TUNED_ROWQR_UPDATE_WAVES,
+               HIF_TUNED_ROWQR_UPDATE_LDS};
   return t;
 }
 hif_tuning g_tune = builtin_tuning();
@@ -174,7 +175,8 @@ bool set_tuning(const hif_tuning* t) {
     return false;
   };
   if (!in(v.id_reg_waves[0], {4, 8, 16}) || !in(v.id_reg_waves[1], {4, 8, 16}) || !in(v.id_reg_waves[2], {8, 16}) ||
-      !in(v.lu_panel_threads[0], {256, 512, 1024}) || !in(v.lu_panel_threads[1], {512, 1024}))
+      !in(v.lu_panel_threads[0], {256, 512, 1024}) || !in(v.lu_panel_threads[1], {512, 1024}) ||
+      !in(v.rowqr_update_waves, {4, 8}) || !in(v.rowqr_update_lds, {0, 1}))
     return false;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune = v;

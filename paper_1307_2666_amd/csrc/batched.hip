@@ -640,7 +640,7 @@ __device__ void apply_wy_tile(const double* V, int rows, const double* Tm, RowP 
 // slice of Y held in registers from the first product to the write-back, so
 // that Y is read once and written once (element v of row tile t is row
 // 16t + 4v + lane / 16, column lane % 16: the B operand of K-step 4t + v).
-__device__ void apply_wy_tile_reg(const double* V, int rows, const double* Tm, double* Y0, int64_t ld, int nt) {
+__device__ __forceinline__ void apply_wy_tile_reg(const double* V, int rows, const double* Tm, double* Y0, int64_t ld, int nt) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int ct = wv * 16;
@@ -706,6 +706,132 @@ __device__ void apply_wy_tile_reg(const double* V, int rows, const double* Tm, d
   }
 }
 
+// The same update with the chunk's V and T staged in LDS first (one coalesced
+// pass per workgroup), so that the fragments the matrix cores consume come
+// from LDS rather than from scattered global loads inside the product loops.
+// sV holds V with row stride kVs = kTb + 1 doubles: a Y-phase fragment reads
+// 16 rows at one column offset, which then fall on different banks.
+constexpr int kVs = kTb + 1;
+constexpr size_t kApplyLds = (size_t(kTsqrRows) * kVs + kTb * kTb) * sizeof(double);
+__device__ __forceinline__ void apply_wy_tile_lds(const double* sV, int rows, const double* sT, double* Y0, int64_t ld, int nt) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ct = wv * 16;
+  const bool colok = ct + li < nt;
+  double yv[16][4];
+#pragma unroll
+  for (int t = 0; t < 16; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * t + 4 * v + lk;
+      yv[t][v] = (r < rows && colok) ? Y0[int64_t(r) * ld + ct + li] : 0.0;
+    }
+  // 1. P = V^T Y.  The fragments of row tile t + 1 are read while tile t is
+  // multiplied (one tile ahead, no further: the scheduling barrier keeps the
+  // compiler from hoisting every tile's reads and spilling).
+  double4_t p0 = {0.0, 0.0, 0.0, 0.0}, p1 = {0.0, 0.0, 0.0, 0.0};
+  double a0[4], a1[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = 4 * v + lk;
+    a0[v] = r < rows ? sV[r * kVs + li] : 0.0;
+    a1[v] = r < rows ? sV[r * kVs + 16 + li] : 0.0;
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    if (16 * t < rows) {  // guarded, not broken out of: the loop must unroll fully
+    double b0[4], b1[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * (t + 1) + 4 * v + lk;
+      b0[v] = (t < 15 && r < rows) ? sV[r * kVs + li] : 0.0;
+      b1[v] = (t < 15 && r < rows) ? sV[r * kVs + 16 + li] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      p0 = mfma_f64(a0[v], yv[t][v], p0);
+      p1 = mfma_f64(a1[v], yv[t][v], p1);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      a0[v] = b0[v];
+      a1[v] = b1[v];
+    }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // 2. W = T^T P
+  double4_t w0 = {0.0, 0.0, 0.0, 0.0}, w1 = {0.0, 0.0, 0.0, 0.0};
+  {
+    double t0[8], t1[8];
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      t0[s2] = sT[(4 * s2 + lk) * kTb + li];
+      t1[s2] = sT[(4 * s2 + lk) * kTb + 16 + li];
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      const double bp = s2 < 4 ? p0[s2 & 3] : p1[s2 & 3];
+      w0 = mfma_f64(t0[s2], bp, w0);
+      w1 = mfma_f64(t1[s2], bp, w1);
+    }
+  }
+  // 3. Y -= V W, written back; fragments one row tile ahead as in 1.
+  double a[8];
+#pragma unroll
+  for (int s2 = 0; s2 < 8; ++s2) a[s2] = li < rows ? sV[li * kVs + 4 * s2 + lk] : 0.0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    if (16 * t < rows) {
+    double b[8];
+    const int rb = 16 * (t + 1) + li;
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) b[s2] = (t < 15 && rb < rows) ? sV[rb * kVs + 4 * s2 + lk] : 0.0;
+    double4_t d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) d = mfma_f64(a[s2], s2 < 4 ? w0[s2 & 3] : w1[s2 & 3], d);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * t + 4 * v + lk;
+      if (r < rows && colok) Y0[int64_t(r) * ld + ct + li] = yv[t][v] - d[v];
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) a[s2] = b[s2];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// K3 for chunks of at most 256 rows, V and T in LDS (kApplyLds bytes of
+// dynamic LDS), NW waves of 16 columns each: workgroup (x, chunk, problem)
+// updates columns cbeg + 16 NW x .. + 16 NW - 1.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_tsqr_apply_chunk_lds(QrBatch A, int j0, int cr, int half, int cbeg,
+                                                                  int cend) {
+  const int q = blockIdx.z, c = blockIdx.y;
+  const int m = A.rows[q], n = A.cols[q];
+  if (m <= n || j0 >= n) return;
+  const PanelGeom g = panel_geom(m, n, j0, cr);
+  if (c >= g.nck) return;
+  const int c0 = cbeg + blockIdx.x * 16 * NW, ce = min(n, cend);
+  if (c0 >= ce) return;
+  const int nt = min(16 * NW, ce - c0);
+  const int lo = chunk_lo(c, g.mp, g.nck), rows = chunk_lo(c + 1, g.mp, g.nck) - lo;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const TsqrLayout L = tsqr_layout(m);
+  const double* S0 = A.scratch + A.soff[q] + half * L.total;
+  extern __shared__ double smem[];
+  double* sV = smem;
+  double* sT = smem + kTsqrRows * kVs;
+  const double* V = S0 + L.V + int64_t(lo) * kTb;
+  const double* Tm = S0 + L.Tc + int64_t(c) * kTb * kTb;
+  for (int e = threadIdx.x; e < rows * kTb; e += 64 * NW) sV[(e / kTb) * kVs + e % kTb] = V[e];
+  for (int e = threadIdx.x; e < kTb * kTb; e += 64 * NW) sT[e] = Tm[e];
+  __syncthreads();
+  apply_wy_tile_lds(sV, rows, sT, M + int64_t(j0 + lo) * ld + c0, ld, nt);
+}
+
 // K3: trailing update of chunk blockIdx.y, column tile blockIdx.x.
 __global__ __launch_bounds__(256) void k_tsqr_apply_chunk(QrBatch A, int j0, int cr, int half, int cbeg, int cend) {
   const int q = blockIdx.z, c = blockIdx.y;
@@ -726,16 +852,19 @@ __global__ __launch_bounds__(256) void k_tsqr_apply_chunk(QrBatch A, int j0, int
                 [=](int r) { return Y0 + int64_t(r) * ld; }, nt);
 }
 
-// K3 for chunks of at most 256 rows, Y held in registers.
-__global__ __launch_bounds__(256, 2) void k_tsqr_apply_chunk_reg(QrBatch A, int j0, int cr, int half, int cbeg, int cend) {
+// K3 for chunks of at most 256 rows, Y held in registers; NW waves of 16
+// columns each.
+template <int NW>
+__global__ __launch_bounds__(64 * NW, 8 / NW) void k_tsqr_apply_chunk_reg(QrBatch A, int j0, int cr, int half, int cbeg,
+                                                                          int cend) {
   const int q = blockIdx.z, c = blockIdx.y;
   const int m = A.rows[q], n = A.cols[q];
   if (m <= n || j0 >= n) return;
   const PanelGeom g = panel_geom(m, n, j0, cr);
   if (c >= g.nck) return;
-  const int c0 = cbeg + blockIdx.x * 64, ce = min(n, cend);
+  const int c0 = cbeg + blockIdx.x * 16 * NW, ce = min(n, cend);
   if (c0 >= ce) return;
-  const int nt = min(64, ce - c0);
+  const int nt = min(16 * NW, ce - c0);
   const int lo = chunk_lo(c, g.mp, g.nck), rows = chunk_lo(c + 1, g.mp, g.nck) - lo;
   double* M = A.base + A.moff[q];
   const int ld = A.ld[q];
@@ -1238,6 +1367,22 @@ void release_thread_streams() {
   (void)hipSetDevice(cur);
 }
 
+// The LDS-staged chunk update asks for more than the default 64 KiB of
+// dynamic LDS.
+static void allow_apply_lds() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const int bytes = int(kApplyLds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsqr_apply_chunk_lds<2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsqr_apply_chunk_lds<4>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsqr_apply_chunk_lds<8>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipGetLastError();
+  });
+}
+
 void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t s) {
   if (A.nprob == 0) return;
   // chunks of 256 rows (one per thread), or of 1024 rows (two per thread)
@@ -1260,6 +1405,8 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
     // own updates of panel p), and the remaining-columns update of p
     // follows the factorization of p (it waits for an event recorded after
     // the stack kernel).
+    allow_apply_lds();
+    const int uw = tuning().rowqr_update_waves, ulds = tuning().rowqr_update_lds;
     const AuxStream& aux = aux_stream();
     hipStream_t s2 = aux.s2;
     hipEvent_t ev_fact = aux.ev_fact, ev_rest = aux.ev_rest;
@@ -1285,9 +1432,15 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
       if (nb1 < max_cols) {
         const unsigned tiles = unsigned((max_cols - nb1 + 63) / 64);
         HIF_HIP(hipStreamWaitEvent(s2, ev_fact, 0));
-        if (cr <= 256)
-          hipLaunchKernelGGL(k_tsqr_apply_chunk_reg, dim3(tiles, nckmax, A.nprob), dim3(256), 0, s2, A, j0, cr,
-                             half, nb1, max_cols);
+        const dim3 g8(unsigned((max_cols - nb1 + 127) / 128), nckmax, A.nprob), g4(tiles, nckmax, A.nprob);
+        if (cr <= 256 && ulds && uw == 8)
+          hipLaunchKernelGGL(k_tsqr_apply_chunk_lds<8>, g8, dim3(512), kApplyLds, s2, A, j0, cr, half, nb1, max_cols);
+        else if (cr <= 256 && ulds)
+          hipLaunchKernelGGL(k_tsqr_apply_chunk_lds<4>, g4, dim3(256), kApplyLds, s2, A, j0, cr, half, nb1, max_cols);
+        else if (cr <= 256 && uw == 8)
+          hipLaunchKernelGGL(k_tsqr_apply_chunk_reg<8>, g8, dim3(512), 0, s2, A, j0, cr, half, nb1, max_cols);
+        else if (cr <= 256)
+          hipLaunchKernelGGL(k_tsqr_apply_chunk_reg<4>, g4, dim3(256), 0, s2, A, j0, cr, half, nb1, max_cols);
         else
           hipLaunchKernelGGL(k_tsqr_apply_chunk, dim3(tiles, nckmax, A.nprob), dim3(256), 0, s2, A, j0, cr, half,
                              nb1, max_cols);
@@ -1295,8 +1448,11 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
         HIF_HIP(hipEventRecord(ev_rest, s2));
         rest_pending = true;
       }
-      if (cr <= 256)
-        hipLaunchKernelGGL(k_tsqr_apply_chunk_reg, dim3(1, nckmax, A.nprob), dim3(256), 0, s, A, j0, cr, half, nb0,
+      if (cr <= 256 && ulds)  // the next panel's 32 columns: two waves
+        hipLaunchKernelGGL(k_tsqr_apply_chunk_lds<2>, dim3(1, nckmax, A.nprob), dim3(128), kApplyLds, s, A, j0, cr,
+                           half, nb0, nb1);
+      else if (cr <= 256)
+        hipLaunchKernelGGL(k_tsqr_apply_chunk_reg<4>, dim3(1, nckmax, A.nprob), dim3(256), 0, s, A, j0, cr, half, nb0,
                            nb1);
       else
         hipLaunchKernelGGL(k_tsqr_apply_chunk, dim3(1, nckmax, A.nprob), dim3(256), 0, s, A, j0, cr, half, nb0, nb1);

@@ -175,6 +175,12 @@ struct SubLevel {
   int64_t sum_r = 0;
   DBuf<int32_t> iarena;
   DBuf<double> darena;
+  // Inverses of the 64 x 64 diagonal blocks of every record's L and U, for
+  // the multi-workgroup solve: record i, block b at (i * dinv_nb + b) * 2 *
+  // 4096, [L^{-1} | U^{-1}] row-major (built by prepare_sweeps where that
+  // solve can run).
+  DBuf<double> dinv;
+  int dinv_nb = 0;
 };
 
 struct FftOp;  // FFT form of the exact operator on a uniform grid (fftmv.hip)
@@ -205,6 +211,7 @@ struct hif_factor_s {
   hif::DBuf<hif::GroupRec> top_rec;
   hif::DBuf<int32_t> top_iarena;
   hif::DBuf<int64_t> top_woff;
+  hif::DBuf<double> top_dinv;  // its diagonal-block inverses, as SubLevel::dinv
   // Sweep scratch.
   hif::DBuf<double> work;
   hif_stats_t stats{};

@@ -773,6 +773,8 @@ struct SpArgs {
   double* X;
   int64_t N;
   int nv;
+  const double* dinv;  // diagonal-block inverses (SubLevel::dinv layout)
+  int dnb;             // blocks per record in dinv
 };
 
 struct SpRec {
@@ -938,6 +940,59 @@ __global__ __launch_bounds__(256) void k_sp_scatter(SpArgs A) {
 
 // Block b of x = L^{-1} x (unit lower L of the LU).  Workgroup 0 writes X of
 // the block; workgroup w >= 1 updates B rows 64(b + w) .. +63.
+// x = D^{-1} x for the nv right-hand sides of one 64-row block, with D^{-1}
+// (the inverse of the block's diagonal block of L or U) in sD: row a per
+// lane, right-hand sides v = wave, wave + 4.  256 threads; ends synchronized.
+__device__ __forceinline__ void diag_apply(const double (*sD)[kNbT + 1], double (*sx)[kNbT], int nv) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double y[kMaxV / 4];
+#pragma unroll
+  for (int q = 0; q < kMaxV / 4; ++q) {
+    const int v = wv + 4 * q;
+    double acc = 0.0;
+    if (v < nv)
+#pragma unroll 16
+      for (int c = 0; c < kNbT; ++c) acc += sD[lane][c] * sx[v][c];
+    y[q] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kMaxV / 4; ++q)
+    if (wv + 4 * q < nv) sx[wv + 4 * q][lane] = y[q];
+  __syncthreads();
+}
+
+// Inverses of the diagonal blocks of the records' L (unit lower) and U
+// (upper) for the blocked solves below: workgroup (b, i) inverts block b of
+// record i; lane c builds column c of each inverse by substitution (L: down
+// the rows, U: up the rows), so no lane reads another's column.  Rows and
+// columns past a partial last block are the identity.
+__global__ __launch_bounds__(64) void k_sp_dinv(SpArgs A, double* dinv) {
+  const SpRec R = sp_rec(A, blockIdx.y);
+  const int b = blockIdx.x, j0 = b * kNbT;
+  if (j0 >= R.r) return;
+  const int nb = min(kNbT, R.r - j0), r = R.r, c = threadIdx.x;
+  __shared__ double sM[kNbT][kNbT + 1];
+  __shared__ double sX[kNbT][kNbT + 1];
+  for (int a = 0; a < kNbT; ++a)
+    sM[a][c] = (a < nb && c < nb) ? R.LU[int64_t(j0 + a) * r + j0 + c] : (a == c ? 1.0 : 0.0);
+  __syncthreads();
+  double* out = dinv + (int64_t(blockIdx.y) * A.dnb + b) * 2 * kNbT * kNbT;
+  for (int a = 0; a < kNbT; ++a) {  // L X = I, unit diagonal
+    double acc = 0.0;
+    for (int j = c; j < a; ++j) acc += sM[a][j] * sX[j][c];
+    sX[a][c] = a == c ? 1.0 : (a > c ? -acc : 0.0);
+  }
+  for (int a = 0; a < kNbT; ++a) out[a * kNbT + c] = sX[a][c];
+  for (int a = kNbT - 1; a >= 0; --a) {  // U X = I
+    double acc = 0.0;
+    for (int j = a + 1; j <= c; ++j) acc += sM[a][j] * sX[j][c];
+    const double d = sM[a][a];
+    sX[a][c] = a > c ? 0.0 : (a == c ? 1.0 / d : -acc / d);
+  }
+  for (int a = 0; a < kNbT; ++a) out[kNbT * kNbT + a * kNbT + c] = sX[a][c];
+}
+
 __global__ __launch_bounds__(256) void k_sp_lsolve(SpArgs A, int b) {
   const SpRec R = sp_rec(A, blockIdx.y);
   const int j0 = b * kNbT;
@@ -946,27 +1001,17 @@ __global__ __launch_bounds__(256) void k_sp_lsolve(SpArgs A, int b) {
   const int i0 = j0 + w * kNbT;
   if (i0 >= R.r) return;
   const int nb = min(kNbT, R.r - j0), nv = A.nv, r = R.r;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x;
   __shared__ double sL[kNbT][kNbT + 1];
   __shared__ double sx[kMaxV][kNbT];
-  for (int e = tid; e < kNbT * kNbT; e += 256) {
-    const int a = e >> 6, c = e & 63;
-    sL[a][c] = (a < nb && c < nb) ? R.LU[int64_t(j0 + a) * r + j0 + c] : 0.0;
-  }
+  const double* Li = A.dinv + (int64_t(blockIdx.y) * A.dnb + b) * 2 * kNbT * kNbT;
+  for (int e = tid; e < kNbT * kNbT; e += 256) sL[e >> 6][e & 63] = Li[e];
   for (int e = tid; e < nv * kNbT; e += 256) {
     const int v = e >> 6, a = e & 63;
     sx[v][a] = a < nb ? R.B[v * r + j0 + a] : 0.0;
   }
   __syncthreads();
-  for (int v = wv; v < nv; v += 4) {  // wave per right-hand side, lane per row
-    double xi = sx[v][lane];
-    for (int c = 0; c < nb - 1; ++c) {
-      const double xc = __shfl(xi, c, 64);
-      if (lane > c) xi -= sL[lane][c] * xc;
-    }
-    sx[v][lane] = xi;
-  }
-  __syncthreads();
+  diag_apply(sL, sx, nv);
   if (w == 0) {
     for (int e = tid; e < nv * nb; e += 256) R.X[(e / nb) * r + j0 + e % nb] = sx[e / nb][e % nb];
     return;
@@ -1009,28 +1054,17 @@ __global__ __launch_bounds__(256) void k_sp_usolve(SpArgs A, int b) {
   const int i0 = (w - 1) * kNbT;
   if (w > 0 && i0 >= j0) return;
   const int nb = min(kNbT, R.r - j0), nv = A.nv, r = R.r;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x;
   __shared__ double sU[kNbT][kNbT + 1];
   __shared__ double sx[kMaxV][kNbT];
-  for (int e = tid; e < kNbT * kNbT; e += 256) {
-    const int a = e >> 6, c = e & 63;
-    sU[a][c] = (a < nb && c < nb) ? R.LU[int64_t(j0 + a) * r + j0 + c] : (a == c ? 1.0 : 0.0);
-  }
+  const double* Ui = A.dinv + (int64_t(blockIdx.y) * A.dnb + b) * 2 * kNbT * kNbT + kNbT * kNbT;
+  for (int e = tid; e < kNbT * kNbT; e += 256) sU[e >> 6][e & 63] = Ui[e];
   for (int e = tid; e < nv * kNbT; e += 256) {
     const int v = e >> 6, a = e & 63;
     sx[v][a] = a < nb ? R.B[v * r + j0 + a] : 0.0;
   }
   __syncthreads();
-  for (int v = wv; v < nv; v += 4) {
-    double xi = sx[v][lane];
-    for (int c = nb - 1; c >= 0; --c) {
-      if (lane == c) xi /= sU[c][c];
-      const double xc = __shfl(xi, c, 64);
-      if (lane < c) xi -= sU[lane][c] * xc;
-    }
-    sx[v][lane] = xi;
-  }
-  __syncthreads();
+  diag_apply(sU, sx, nv);
   if (w == 0) {
     for (int e = tid; e < nv * nb; e += 256) R.X[(e / nb) * r + j0 + e % nb] = sx[e / nb][e % nb];
     return;
@@ -1087,6 +1121,13 @@ static void allow_large_lds() {
   });
 }
 
+// Sub-levels whose solve runs through the multi-workgroup path for nv
+// right-hand sides per pass: records too large for LDS with all of them, or
+// few large records.
+static bool split_solve(const SubLevel& sub, int64_t N, int nv) {
+  return 2 * sub.sum_r <= N && (int64_t(sub.max_2rk) * nv > kCapL || (sub.nrec <= 64 && sub.max_r >= 256));
+}
+
 // A top block too large for LDS is solved like a large record with no
 // skeleton through the many-workgroup triangular solves.
 static bool top_split_solve(const hif_factor_s* H) {
@@ -1113,10 +1154,11 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
     // of few large records is spread over many workgroups per record
     auto sweep = [&](const SubLevel& sub, int down) {
       SwArgs A{sub.rec.p, sub.iarena.p, sub.darena.p, u, wk, N, nv, op};
-      const bool split = op == 0 && 2 * sub.sum_r <= N &&
-                         (int64_t(sub.max_2rk) * nv > kCapL || (sub.nrec <= 64 && sub.max_r >= 256));
+      const bool split = op == 0 && split_solve(sub, N, nv);
       if (split) {
-        SpArgs P{sub.rec.p, sub.iarena.p, sub.darena.p, sub.woff.p, u, wk, wk + nv * sub.sum_r, N, nv};
+        HIF_REQUIRE(sub.dinv.p, HIF_EDEVICE, "the diagonal-block inverses of a sub-level were not built");
+        SpArgs P{sub.rec.p,  sub.iarena.p, sub.darena.p, sub.woff.p, u, wk, wk + nv * sub.sum_r, N, nv,
+                 sub.dinv.p, sub.dinv_nb};
         const unsigned nr = unsigned(sub.nrec);
         const int nbk = (sub.max_r + kNbT - 1) / kNbT;
         const dim3 gr(unsigned((sub.max_r + 255) / 256), nr);
@@ -1160,9 +1202,11 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
     const bool top_split = op == 0 && top_split_solve(H);
     if (top_split) {
       const int r = int(H->ntop);
-      HIF_REQUIRE(H->top_rec.p, HIF_EDEVICE, "the top block's solve record was not built with the factors");
-      SpArgs P{H->top_rec.p, H->top_iarena.p, H->top_lu.p, H->top_woff.p, u, wk, wk + int64_t(nv) * r, N, nv};
+      HIF_REQUIRE(H->top_rec.p && H->top_dinv.p, HIF_EDEVICE,
+                  "the top block's solve record was not built with the factors");
       const int nbk = (r + kNbT - 1) / kNbT;
+      SpArgs P{H->top_rec.p, H->top_iarena.p, H->top_lu.p,  H->top_woff.p, u, wk, wk + int64_t(nv) * r, N, nv,
+               H->top_dinv.p, nbk};
       const dim3 gr(unsigned((r + 255) / 256), 1);
       hipLaunchKernelGGL(k_sp_up_first, gr, dim3(256), 0, s, P);
       for (int b = 0; b < nbk; ++b) hipLaunchKernelGGL(k_sp_lsolve, dim3(unsigned(nbk - b), 1), dim3(256), 0, s, P, b);
@@ -1186,7 +1230,23 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
 
 
 
+// Diagonal-block inverses of the sub-levels (and the top block) whose solve
+// can take the multi-workgroup path, for any number of right-hand sides per
+// pass (at most kMaxV).
+static void build_dinv(hif_factor_s* H, hipStream_t s) {
+  for (SubLevel& sub : H->subs) {
+    if (sub.nrec == 0 || sub.dinv.p || !split_solve(sub, H->n, kMaxV)) continue;
+    sub.dinv_nb = (sub.max_r + kNbT - 1) / kNbT;
+    sub.dinv.alloc(size_t(sub.nrec) * sub.dinv_nb * 2 * kNbT * kNbT, &H->mem);
+    SpArgs P{sub.rec.p, sub.iarena.p, sub.darena.p, sub.woff.p, nullptr, nullptr, nullptr, H->n, 1,
+             nullptr, sub.dinv_nb};
+    hipLaunchKernelGGL(k_sp_dinv, dim3(unsigned(sub.dinv_nb), unsigned(sub.nrec)), dim3(64), 0, s, P, sub.dinv.p);
+  }
+  HIF_HIP(hipGetLastError());
+}
+
 void prepare_sweeps(hif_factor_s* H, hipStream_t s) {
+  build_dinv(H, s);
   if (!top_split_solve(H) || H->top_rec.p) return;
   const int r = int(H->ntop);
   H->top_iarena.alloc(size_t(3) * r, &H->mem);
@@ -1199,6 +1259,12 @@ void prepare_sweeps(hif_factor_s* H, hipStream_t s) {
   H->top_woff.alloc(1, &H->mem);
   HIF_HIP(hipMemcpyAsync(H->top_rec.p, &rec, sizeof(GroupRec), hipMemcpyHostToDevice, s));
   HIF_HIP(hipMemcpyAsync(H->top_woff.p, &wo, sizeof(int64_t), hipMemcpyHostToDevice, s));
+  const int nbk = (r + kNbT - 1) / kNbT;
+  H->top_dinv.alloc(size_t(nbk) * 2 * kNbT * kNbT, &H->mem);
+  SpArgs P{H->top_rec.p, H->top_iarena.p, H->top_lu.p, H->top_woff.p, nullptr, nullptr, nullptr, H->n, 1,
+           nullptr, nbk};
+  hipLaunchKernelGGL(k_sp_dinv, dim3(unsigned(nbk), 1), dim3(64), 0, s, P, H->top_dinv.p);
+  HIF_HIP(hipGetLastError());
   HIF_HIP(hipStreamSynchronize(s));  // the host values above are copied before they go out of scope
 }
 

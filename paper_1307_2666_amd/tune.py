@@ -13,6 +13,11 @@ Buckets and candidates (``hif_tuning`` in ``include/hif.h``):
   panels of at most 512 and 1024 rows.  Timed with ``hif_lu_batched`` on
   batches of well-conditioned n x n blocks with r = n / 2 eliminated columns
   (the redundant part of a transformed group block), n in the bucket.
+* ``rowqr_update_waves`` / ``rowqr_update_lds``: the shape of the row
+  compression's trailing update beside the next panel.  It competes with the
+  panel factorization for the CUs, so it is timed on whole factorizations:
+  ``hif_factor`` of the second-kind 2D problem on a 384 x 384 grid (eps 1e-6,
+  leaf 64), the row-compression phase time of the library's own events.
 
 Every candidate is timed with HIP events over 5 runs after a warm run, on the
 same inputs (the inputs are restored before each run); the fastest median
@@ -38,6 +43,8 @@ ID_BUCKETS = [(33, 64, 4096), (97, 128, 2048), (161, 192, 1024)]  # (n_c lo, n_c
 ID_CANDIDATES = [(4, 8, 16), (4, 8, 16), (8, 16)]
 LU_BUCKETS = [(257, 512, 256), (513, 1024, 64)]  # (n lo, n hi, problems)
 LU_CANDIDATES = [(256, 512, 1024), (512, 1024)]
+ROWQR_CANDIDATES = [(4, 0), (8, 0), (4, 1), (8, 1)]  # (waves, LDS staging)
+ROWQR_GRID = 384
 
 
 def _median_ms(run, reps=5):
@@ -129,16 +136,32 @@ def _time_lu(mats):
     return _median_ms(run)
 
 
+def _time_rowqr(reps=3):
+    factor = B.factor
+    n = ROWQR_GRID
+    g = (torch.arange(n, dtype=torch.float64, device="cuda") + 0.5) / n
+    pts = torch.stack([g.repeat(n), g.repeat_interleave(n)], dim=1).contiguous()
+    a = torch.ones(n * n, dtype=torch.float64, device="cuda")
+    F = factor(pts, 1e-6, 64, a=a, h=1.0 / n)  # warm
+    F.free()
+    ts = []
+    for _ in range(reps):
+        F = factor(pts, 1e-6, 64, a=a, h=1.0 / n)
+        ts.append(F.stats()["t_phase_ms"]["rowqr"])
+        F.free()
+    return float(np.median(ts))
+
+
 def tune(seed=0):
     """Time every candidate of every bucket; returns (table, timings)."""
     base = B.tuning_get()
-    table = {k: list(v) for k, v in base.items()}
+    table = {k: (list(v) if isinstance(v, list) else v) for k, v in base.items()}
     timings = {"id_reg_waves": [], "lu_panel_threads": []}
     for b, ((lo, hi, cnt), cands) in enumerate(zip(ID_BUCKETS, ID_CANDIDATES)):
         mats = _id_batch(lo, hi, cnt, seed + b)
         res = {}
         for w in cands:
-            t = {k: list(v) for k, v in table.items()}
+            t = {k: (list(v) if isinstance(v, list) else v) for k, v in table.items()}
             t["id_reg_waves"][b] = w
             B.tuning_set(t)
             res[w] = _time_id(mats)
@@ -148,12 +171,22 @@ def tune(seed=0):
         mats = _lu_batch(lo, hi, cnt, seed + 10 + b)
         res = {}
         for th in cands:
-            t = {k: list(v) for k, v in table.items()}
+            t = {k: (list(v) if isinstance(v, list) else v) for k, v in table.items()}
             t["lu_panel_threads"][b] = th
             B.tuning_set(t)
             res[th] = _time_lu(mats)
         table["lu_panel_threads"][b] = min(res, key=res.get)
         timings["lu_panel_threads"].append({"rows": [lo, hi], "problems": cnt, "ms": res})
+    res = {}
+    for w, lds in ROWQR_CANDIDATES:
+        t = {k: (list(v) if isinstance(v, list) else v) for k, v in table.items()}
+        t["rowqr_update_waves"], t["rowqr_update_lds"] = w, lds
+        B.tuning_set(t)
+        res[(w, lds)] = _time_rowqr()
+    best = min(res, key=res.get)
+    table["rowqr_update_waves"], table["rowqr_update_lds"] = best
+    timings["rowqr_update"] = {"grid": ROWQR_GRID, "ms": {f"{w} waves{' + LDS' if l else ''}": v
+                                                         for (w, l), v in res.items()}}
     B.tuning_set(table)
     return table, timings
 
@@ -169,12 +202,21 @@ def write_header(table, timings, path=HEADER):
     for e in timings["lu_panel_threads"]:
         lines.append(f"//   LU, {e['problems']} blocks of {e['rows'][0]}-{e['rows'][1]} rows: " +
                      ", ".join(f"{k} threads {v:.3f}" for k, v in e["ms"].items()))
+    ru = timings.get("rowqr_update")
+    if ru:
+        lines.append(f"//   row compression of a {ru['grid']} x {ru['grid']} factorization (eps 1e-6): " +
+                     ", ".join(f"{k} {v:.2f}" for k, v in ru["ms"].items()))
     lines += ["#pragma once", "",
               "// waves per problem of the register-resident pivoted QR, problems of at most",
               "// 64, 128 and 192 columns",
               "#define HIF_TUNED_ID_REG_WAVES {" + ", ".join(str(x) for x in table["id_reg_waves"]) + "}",
               "// threads of the register-resident LU panel, panels of at most 512 and 1024 rows",
-              "#define HIF_TUNED_LU_PANEL_THREADS {" + ", ".join(str(x) for x in table["lu_panel_threads"]) + "}", ""]
+              "#define HIF_TUNED_LU_PANEL_THREADS {" + ", ".join(str(x) for x in table["lu_panel_threads"]) + "}",
+              "// waves (16 columns each) per workgroup of the row compression's trailing",
+              "// update beside the next panel",
+              f"#define HIF_TUNED_ROWQR_UPDATE_WAVES {table['rowqr_update_waves']}",
+              "// 1: the chunk reflectors of that update staged in LDS",
+              f"#define HIF_TUNED_ROWQR_UPDATE_LDS {table['rowqr_update_lds']}", ""]
     with open(path, "w") as fh:
         fh.write("\n".join(lines))
 
