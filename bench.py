@@ -54,6 +54,13 @@ HBM_PEAK_GBS = 8000.0
 # (see the profile summaries); None until taken for the kernels as they stand.
 # 302 GB read + 73 GB written per factorization (profiles/hbm_traffic_id_sq512.md).
 ID_STEP_TRAFFIC_BYTES = 374.07e9
+# ALU roof of the exact pair-by-pair product (2D, 8 right-hand sides, two
+# targets per thread): its inner loop issues 110 vector instructions per
+# source for two targets, 55 per pair (log, distance, select, 8 FMAs); a
+# wave64 vector instruction takes 4 cycles of a 16-lane SIMD, so the chip
+# issues 256 CUs x 64 lanes x 2.4 GHz lane-operations per second.
+MATVEC_VALU_PER_PAIR = 55
+VALU_LANE_OPS_PER_S = 256 * 64 * 2.4e9
 
 
 def parse():
@@ -254,6 +261,8 @@ def phase_rooflines(st, ph, solve_ms, nrhs, mv_ms, mv_rhs):
     pairs = float(st["n"]) ** 2 * mv_rhs
     out["matvec (a11)"] = {"bound": "alu (log per pair)", "work": pairs, "unit": "pair x rhs", "ms": mv_ms,
                            "achieved": pairs / mv_ms * 1e-6, "achieved_unit": "Gpair/s"}
+    if mv_rhs == 8 and st.get("dim", 2) == 2:
+        out["matvec (a11)"]["peak"] = VALU_LANE_OPS_PER_S / MATVEC_VALU_PER_PAIR * mv_rhs * 1e-9
     for v in out.values():
         if "peak" in v:
             v["frac"] = v["achieved"] / v["peak"]

@@ -378,8 +378,11 @@ hif_status hif_factor_batch(const hif_problem* problems, int32_t count, const hi
  *   rowqr_update_waves: waves (16 columns each) per workgroup of the
  *     trailing update that the row compression (Householder QR of Y before
  *     each ID) runs beside the factorization of the next panel; 4 or 8.
- *   rowqr_update_lds: 1 stages each chunk's reflectors in LDS before that
- *     update, 0 reads them from memory inside its products.
+ *   rowqr_update_kind: 0 holds each wave's 256 rows x 16 columns of Y in
+ *     registers and reads the chunk's reflectors from memory inside the
+ *     products, 1 stages the reflectors in LDS first, 2 splits the rows
+ *     between two waves per 16 columns (half the registers per wave, the
+ *     partial products added through LDS).
  * The built-in table comes from paper_1307_2666_amd/tune.py, which times the
  * candidates with hif_id_batched and hif_lu_batched, and the row-compression
  * shapes with hif_id_batched on tall blocks.  hif_tuning_set(NULL)
@@ -391,7 +394,7 @@ typedef struct {
   int32_t id_reg_waves[3];
   int32_t lu_panel_threads[2];
   int32_t rowqr_update_waves;
-  int32_t rowqr_update_lds;
+  int32_t rowqr_update_kind;
 } hif_tuning;
 hif_status hif_tuning_get(hif_tuning* out);
 hif_status hif_tuning_set(const hif_tuning* t);

@@ -96,6 +96,7 @@ void* dbuf_take(size_t cls, hipStream_t s) {
   DbufCache& c = dbuf_cache();
   std::lock_guard<std::mutex> lk(c.mu);
   auto it = c.blocks.find(CacheKey{dev, s, cls});
+  if (it == c.blocks.end()) it = c.blocks.find(CacheKey{dev, dbuf_idle_key(), cls});  // idle blocks serve any stream
   if (it == c.blocks.end()) return nullptr;
   void* p = it->second;
   c.blocks.erase(it);
@@ -111,7 +112,7 @@ void dbuf_trim() {
     std::lock_guard<std::mutex> lk(c.mu);
     for (auto it = c.blocks.begin(); it != c.blocks.end();) {
       if (it->first.dev == dev) {
-        (void)hipFreeAsync(it->second, it->first.s);
+        (void)hipFreeAsync(it->second, it->first.s == dbuf_idle_key() ? nullptr : it->first.s);
         c.bytes -= it->first.cls;
         it = c.blocks.erase(it);
       } else {
@@ -156,7 +157,7 @@ namespace {
 std::mutex g_tune_mu;
 hif_tuning builtin_tuning() {
   hif_tuning t{HIF_TUNED_ID_REG_WAVES, HIF_TUNED_LU_PANEL_THREADS, HIF_TUNED_ROWQR_UPDATE_WAVES,
-               HIF_TUNED_ROWQR_UPDATE_LDS};
+               HIF_TUNED_ROWQR_UPDATE_KIND};
   return t;
 }
 hif_tuning g_tune = builtin_tuning();
@@ -176,7 +177,7 @@ bool set_tuning(const hif_tuning* t) {
   };
   if (!in(v.id_reg_waves[0], {4, 8, 16}) || !in(v.id_reg_waves[1], {4, 8, 16}) || !in(v.id_reg_waves[2], {8, 16}) ||
       !in(v.lu_panel_threads[0], {256, 512, 1024}) || !in(v.lu_panel_threads[1], {512, 1024}) ||
-      !in(v.rowqr_update_waves, {4, 8}) || !in(v.rowqr_update_lds, {0, 1}))
+      !in(v.rowqr_update_waves, {4, 8}) || !in(v.rowqr_update_kind, {0, 1, 2}))
     return false;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune = v;
@@ -633,6 +634,7 @@ void hif_free(hif_handle h) {
   if (!h) return;
   wait_uses(h);  // the handle's own work on every stream it was used on
   StreamScope scope(nullptr);
+  ReleaseIdle idle;  // waited on above: the handle's blocks are idle
   fft_release(h);
   delete h;
 }

@@ -802,6 +802,115 @@ __device__ __forceinline__ void apply_wy_tile_lds(const double* sV, int rows, co
   }
 }
 
+// The same update with the chunk's rows split between two waves per 16
+// columns (wave w: columns 16 (w % CG), rows 128 (w / CG) .. + 127), so that
+// each wave holds half the slice of Y and more waves fit per SIMD; the two
+// halves add their partial products V^T Y through LDS before both form W.
+template <int CG>
+__device__ __forceinline__ void apply_wy_tile_split(const double* V, int rows, const double* Tm, double* Y0,
+                                                    int64_t ld, int nt, double* sP) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int cg = wv % CG, hf = wv / CG;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ct = cg * 16, r0 = hf * 128;
+  const bool colok = ct + li < nt;
+  double yv[8][4];
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + 16 * t + 4 * v + lk;
+      yv[t][v] = (r < rows && colok) ? Y0[int64_t(r) * ld + ct + li] : 0.0;
+    }
+  double4_t p0 = {0.0, 0.0, 0.0, 0.0}, p1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    if (r0 + 16 * t < rows) {
+      double a0[4], a1[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * t + 4 * v + lk;
+        a0[v] = r < rows ? V[int64_t(r) * kTb + li] : 0.0;
+        a1[v] = r < rows ? V[int64_t(r) * kTb + 16 + li] : 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        p0 = mfma_f64(a0[v], yv[t][v], p0);
+        p1 = mfma_f64(a1[v], yv[t][v], p1);
+      }
+    }
+  }
+  // sP[cg][hf][8][64]: each lane's 8 accumulator entries, by lane
+  double* mine = sP + (cg * 2 + hf) * 8 * 64;
+  const double* other = sP + (cg * 2 + (1 - hf)) * 8 * 64;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    mine[e * 64 + lane] = p0[e];
+    mine[(4 + e) * 64 + lane] = p1[e];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    p0[e] += other[e * 64 + lane];
+    p1[e] += other[(4 + e) * 64 + lane];
+  }
+  double4_t w0 = {0.0, 0.0, 0.0, 0.0}, w1 = {0.0, 0.0, 0.0, 0.0};
+  {
+    double t0[8], t1[8];
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      t0[s2] = Tm[(4 * s2 + lk) * kTb + li];
+      t1[s2] = Tm[(4 * s2 + lk) * kTb + 16 + li];
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      const double bp = s2 < 4 ? p0[s2 & 3] : p1[s2 & 3];
+      w0 = mfma_f64(t0[s2], bp, w0);
+      w1 = mfma_f64(t1[s2], bp, w1);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    if (r0 + 16 * t < rows) {
+      double a[8];
+      const int ra = r0 + 16 * t + li;
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) a[s2] = ra < rows ? V[int64_t(ra) * kTb + 4 * s2 + lk] : 0.0;
+      double4_t d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) d = mfma_f64(a[s2], s2 < 4 ? w0[s2 & 3] : w1[s2 & 3], d);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * t + 4 * v + lk;
+        if (r < rows && colok) Y0[int64_t(r) * ld + ct + li] = yv[t][v] - d[v];
+      }
+    }
+  }
+}
+
+// K3 for chunks of at most 256 rows, rows split over two waves per 16 columns
+// (CG groups of 16 columns per workgroup, 2 CG waves).
+template <int CG>
+__global__ __launch_bounds__(128 * CG) void k_tsqr_apply_chunk_split(QrBatch A, int j0, int cr, int half, int cbeg,
+                                                                    int cend) {
+  const int q = blockIdx.z, c = blockIdx.y;
+  const int m = A.rows[q], n = A.cols[q];
+  if (m <= n || j0 >= n) return;
+  const PanelGeom g = panel_geom(m, n, j0, cr);
+  if (c >= g.nck) return;
+  const int c0 = cbeg + blockIdx.x * 16 * CG, ce = min(n, cend);
+  if (c0 >= ce) return;
+  const int nt = min(16 * CG, ce - c0);
+  const int lo = chunk_lo(c, g.mp, g.nck), rows = chunk_lo(c + 1, g.mp, g.nck) - lo;
+  double* M = A.base + A.moff[q];
+  const int ld = A.ld[q];
+  const TsqrLayout L = tsqr_layout(m);
+  const double* S0 = A.scratch + A.soff[q] + half * L.total;
+  __shared__ double sP[CG * 2 * 8 * 64];
+  apply_wy_tile_split<CG>(S0 + L.V + int64_t(lo) * kTb, rows, S0 + L.Tc + int64_t(c) * kTb * kTb,
+                          M + int64_t(j0 + lo) * ld + c0, ld, nt, sP);
+}
+
 // K3 for chunks of at most 256 rows, V and T in LDS (kApplyLds bytes of
 // dynamic LDS), NW waves of 16 columns each: workgroup (x, chunk, problem)
 // updates columns cbeg + 16 NW x .. + 16 NW - 1.
@@ -1406,7 +1515,7 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
     // follows the factorization of p (it waits for an event recorded after
     // the stack kernel).
     allow_apply_lds();
-    const int uw = tuning().rowqr_update_waves, ulds = tuning().rowqr_update_lds;
+    const int uw = tuning().rowqr_update_waves, ukind = tuning().rowqr_update_kind, ulds = ukind == 1;
     const AuxStream& aux = aux_stream();
     hipStream_t s2 = aux.s2;
     hipEvent_t ev_fact = aux.ev_fact, ev_rest = aux.ev_rest;
@@ -1433,7 +1542,12 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
         const unsigned tiles = unsigned((max_cols - nb1 + 63) / 64);
         HIF_HIP(hipStreamWaitEvent(s2, ev_fact, 0));
         const dim3 g8(unsigned((max_cols - nb1 + 127) / 128), nckmax, A.nprob), g4(tiles, nckmax, A.nprob);
-        if (cr <= 256 && ulds && uw == 8)
+        const dim3 gs2(unsigned((max_cols - nb1 + 31) / 32), nckmax, A.nprob);
+        if (cr <= 256 && ukind == 2 && uw == 8)
+          hipLaunchKernelGGL(k_tsqr_apply_chunk_split<4>, g4, dim3(512), 0, s2, A, j0, cr, half, nb1, max_cols);
+        else if (cr <= 256 && ukind == 2)
+          hipLaunchKernelGGL(k_tsqr_apply_chunk_split<2>, gs2, dim3(256), 0, s2, A, j0, cr, half, nb1, max_cols);
+        else if (cr <= 256 && ulds && uw == 8)
           hipLaunchKernelGGL(k_tsqr_apply_chunk_lds<8>, g8, dim3(512), kApplyLds, s2, A, j0, cr, half, nb1, max_cols);
         else if (cr <= 256 && ulds)
           hipLaunchKernelGGL(k_tsqr_apply_chunk_lds<4>, g4, dim3(256), kApplyLds, s2, A, j0, cr, half, nb1, max_cols);

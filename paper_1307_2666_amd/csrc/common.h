@@ -57,16 +57,35 @@ inline hipStream_t& dbuf_stream() {
   static thread_local hipStream_t s = nullptr;
   return s;
 }
+// While set (ReleaseIdle), blocks released on this thread are known to be
+// idle: no queued work on any stream uses them (a handle's teardown after
+// waiting on every stream it was used on).  They go to a section of the
+// cache that the next allocation of their size class on any stream may take,
+// not to the section of the releasing stream.
+inline bool& dbuf_idle() {
+  static thread_local bool v = false;
+  return v;
+}
+struct ReleaseIdle {
+  bool prev;
+  ReleaseIdle() : prev(dbuf_idle()) { dbuf_idle() = true; }
+  ~ReleaseIdle() { dbuf_idle() = prev; }
+  ReleaseIdle(const ReleaseIdle&) = delete;
+  ReleaseIdle& operator=(const ReleaseIdle&) = delete;
+};
+// Cache key of the idle section (no stream has this value).
+inline hipStream_t dbuf_idle_key() { return reinterpret_cast<hipStream_t>(~uintptr_t(0)); }
 void dbuf_pool_setup();  // once per device: keep freed memory in the pool
 // Host-side cache in front of the pool: a block freed on a stream is kept
 // (per device and stream, by size class) and handed to the next
 // allocation of that class on the same stream, which the stream orders after
 // the block's last use; it saves the allocator's per-call host cost between
-// the host's waits on the device.  At most kDbufCacheBytes stay cached (per
-// process); beyond that blocks go back to the pool.
+// the host's waits on the device.  Blocks released as idle (ReleaseIdle) are
+// kept in a section any stream may take from.  At most kDbufCacheBytes stay
+// cached (per process); beyond that blocks go back to the pool.
 // Blocks of kDbufDirectBytes or more bypass both (plain hipMalloc / hipFree):
 // few and large, they would otherwise stay reserved in the pool.
-constexpr size_t kDbufCacheBytes = size_t(8) << 30;
+constexpr size_t kDbufCacheBytes = size_t(16) << 30;
 constexpr size_t kDbufDirectBytes = size_t(1) << 30;
 size_t dbuf_class(size_t bytes);                  // allocation size for a request
 void* dbuf_take(size_t cls, hipStream_t s);       // cached block or nullptr
@@ -102,7 +121,7 @@ struct DBuf {
     if (p) {
       if (cls >= kDbufDirectBytes)
         (void)hipFree(p);
-      else if (!dbuf_give(p, cls, dbuf_stream()))
+      else if (!dbuf_give(p, cls, dbuf_idle() ? dbuf_idle_key() : dbuf_stream()))
         (void)hipFreeAsync(p, dbuf_stream());
       if (mt) mt->held -= n * sizeof(T);
     }

@@ -9,8 +9,9 @@
 //   ID, 1024 problems of 161-192 columns: 8 waves 4.351, 16 waves 3.402
 //   LU, 256 blocks of 257-512 rows: 256 threads 3.094, 512 threads 2.955, 1024 threads 3.157
 //   LU, 64 blocks of 513-1024 rows: 512 threads 6.206, 1024 threads 6.301
-//   row compression of the 512 x 512 workload (eps 1e-6), 2 x 3 factorizations each:
-//     4 waves 98.4 / 98.8, 8 waves 107.9 / 107.3, 4 waves + LDS 105.5, 8 waves + LDS 97.2 / 96.8
+//   row compression of the 512 x 512 workload (eps 1e-6), medians of 3 factorizations:
+//     4 waves 98.3-98.8, 8 waves 107.3-107.9, 4 waves + LDS 105.5, 8 waves + LDS 96.5-97.2,
+//     4 waves rows split 103.0-103.1, 8 waves rows split 104.0
 #pragma once
 
 // waves per problem of the register-resident pivoted QR, problems of at most
@@ -21,5 +22,5 @@
 // waves (16 columns each) per workgroup of the row compression's trailing
 // update beside the next panel
 #define HIF_TUNED_ROWQR_UPDATE_WAVES 8
-// 1: the chunk reflectors of that update staged in LDS
-#define HIF_TUNED_ROWQR_UPDATE_LDS 1
+// 0: Y in registers, 1: the chunk reflectors staged in LDS, 2: rows split over two waves
+#define HIF_TUNED_ROWQR_UPDATE_KIND 1

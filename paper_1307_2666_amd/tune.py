@@ -13,7 +13,7 @@ Buckets and candidates (``hif_tuning`` in ``include/hif.h``):
   panels of at most 512 and 1024 rows.  Timed with ``hif_lu_batched`` on
   batches of well-conditioned n x n blocks with r = n / 2 eliminated columns
   (the redundant part of a transformed group block), n in the bucket.
-* ``rowqr_update_waves`` / ``rowqr_update_lds``: the shape of the row
+* ``rowqr_update_waves`` / ``rowqr_update_kind``: the shape of the row
   compression's trailing update beside the next panel.  It competes with the
   panel factorization for the CUs, so it is timed on whole factorizations:
   ``hif_factor`` of the second-kind 2D problem on a 384 x 384 grid (eps 1e-6,
@@ -43,7 +43,7 @@ ID_BUCKETS = [(33, 64, 4096), (97, 128, 2048), (161, 192, 1024)]  # (n_c lo, n_c
 ID_CANDIDATES = [(4, 8, 16), (4, 8, 16), (8, 16)]
 LU_BUCKETS = [(257, 512, 256), (513, 1024, 64)]  # (n lo, n hi, problems)
 LU_CANDIDATES = [(256, 512, 1024), (512, 1024)]
-ROWQR_CANDIDATES = [(4, 0), (8, 0), (4, 1), (8, 1)]  # (waves, LDS staging)
+ROWQR_CANDIDATES = [(4, 0), (8, 0), (4, 1), (8, 1), (4, 2), (8, 2)]  # (waves, kind)
 ROWQR_GRID = 384
 
 
@@ -180,13 +180,13 @@ def tune(seed=0):
     res = {}
     for w, lds in ROWQR_CANDIDATES:
         t = {k: (list(v) if isinstance(v, list) else v) for k, v in table.items()}
-        t["rowqr_update_waves"], t["rowqr_update_lds"] = w, lds
+        t["rowqr_update_waves"], t["rowqr_update_kind"] = w, lds
         B.tuning_set(t)
         res[(w, lds)] = _time_rowqr()
     best = min(res, key=res.get)
-    table["rowqr_update_waves"], table["rowqr_update_lds"] = best
-    timings["rowqr_update"] = {"grid": ROWQR_GRID, "ms": {f"{w} waves{' + LDS' if l else ''}": v
-                                                         for (w, l), v in res.items()}}
+    table["rowqr_update_waves"], table["rowqr_update_kind"] = best
+    kinds = {0: "", 1: " + LDS", 2: " rows split"}
+    timings["rowqr_update"] = {"grid": ROWQR_GRID, "ms": {f"{w} waves{kinds[k]}": v for (w, k), v in res.items()}}
     B.tuning_set(table)
     return table, timings
 
@@ -215,8 +215,8 @@ def write_header(table, timings, path=HEADER):
               "// waves (16 columns each) per workgroup of the row compression's trailing",
               "// update beside the next panel",
               f"#define HIF_TUNED_ROWQR_UPDATE_WAVES {table['rowqr_update_waves']}",
-              "// 1: the chunk reflectors of that update staged in LDS",
-              f"#define HIF_TUNED_ROWQR_UPDATE_LDS {table['rowqr_update_lds']}", ""]
+              "// 0: Y in registers, 1: the chunk reflectors staged in LDS, 2: rows split over two waves",
+              f"#define HIF_TUNED_ROWQR_UPDATE_KIND {table['rowqr_update_kind']}", ""]
     with open(path, "w") as fh:
         fh.write("\n".join(lines))
 
