@@ -383,9 +383,12 @@ hif_status hif_factor_batch(const hif_problem* problems, int32_t count, const hi
  *     products, 1 stages the reflectors in LDS first, 2 splits the rows
  *     between two waves per 16 columns (half the registers per wave, the
  *     partial products added through LDS).
+ *   sweep_many_threads: threads per record of the solve's sweeps on
+ *     sub-levels of at least 1024 records (the many small records of the
+ *     lower levels); 64, 128 or 256.
  * The built-in table comes from paper_1307_2666_amd/tune.py, which times the
- * candidates with hif_id_batched and hif_lu_batched, and the row-compression
- * shapes with hif_id_batched on tall blocks.  hif_tuning_set(NULL)
+ * candidates with hif_id_batched and hif_lu_batched, the row-compression
+ * shapes on whole factorizations and the sweep shapes on solves.  hif_tuning_set(NULL)
  * restores it; any other call replaces the table for the whole process (calls
  * already queued keep the shapes they were launched with).  HIF_EINVAL for an
  * entry outside the allowed values (the table is then unchanged).
@@ -395,6 +398,7 @@ typedef struct {
   int32_t lu_panel_threads[2];
   int32_t rowqr_update_waves;
   int32_t rowqr_update_kind;
+  int32_t sweep_many_threads;
 } hif_tuning;
 hif_status hif_tuning_get(hif_tuning* out);
 hif_status hif_tuning_set(const hif_tuning* t);

@@ -49,7 +49,8 @@ class hif_problem(ctypes.Structure):
 
 class hif_tuning(ctypes.Structure):
     _fields_ = [("id_reg_waves", ctypes.c_int32 * 3), ("lu_panel_threads", ctypes.c_int32 * 2),
-                ("rowqr_update_waves", ctypes.c_int32), ("rowqr_update_kind", ctypes.c_int32)]
+                ("rowqr_update_waves", ctypes.c_int32), ("rowqr_update_kind", ctypes.c_int32),
+                ("sweep_many_threads", ctypes.c_int32)]
 
 
 class hif_stats_t(ctypes.Structure):
@@ -475,7 +476,8 @@ def tuning_get() -> dict:
     t = hif_tuning()
     _check(load_library().hif_tuning_get(ctypes.byref(t)))
     return {"id_reg_waves": list(t.id_reg_waves), "lu_panel_threads": list(t.lu_panel_threads),
-            "rowqr_update_waves": int(t.rowqr_update_waves), "rowqr_update_kind": int(t.rowqr_update_kind)}
+            "rowqr_update_waves": int(t.rowqr_update_waves), "rowqr_update_kind": int(t.rowqr_update_kind),
+            "sweep_many_threads": int(t.sweep_many_threads)}
 
 
 def tuning_set(table=None):
@@ -488,6 +490,7 @@ def tuning_set(table=None):
     t.lu_panel_threads[:] = list(table["lu_panel_threads"])
     t.rowqr_update_waves = int(table["rowqr_update_waves"])
     t.rowqr_update_kind = int(table["rowqr_update_kind"])
+    t.sweep_many_threads = int(table["sweep_many_threads"])
     _check(load_library().hif_tuning_set(ctypes.byref(t)))
 
 

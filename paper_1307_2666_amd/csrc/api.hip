@@ -157,7 +157,7 @@ namespace {
 std::mutex g_tune_mu;
 hif_tuning builtin_tuning() {
   hif_tuning t{HIF_TUNED_ID_REG_WAVES, HIF_TUNED_LU_PANEL_THREADS, HIF_TUNED_ROWQR_UPDATE_WAVES,
-               HIF_TUNED_ROWQR_UPDATE_KIND};
+               HIF_TUNED_ROWQR_UPDATE_KIND, HIF_TUNED_SWEEP_MANY_THREADS};
   return t;
 }
 hif_tuning g_tune = builtin_tuning();
@@ -177,7 +177,8 @@ bool set_tuning(const hif_tuning* t) {
   };
   if (!in(v.id_reg_waves[0], {4, 8, 16}) || !in(v.id_reg_waves[1], {4, 8, 16}) || !in(v.id_reg_waves[2], {8, 16}) ||
       !in(v.lu_panel_threads[0], {256, 512, 1024}) || !in(v.lu_panel_threads[1], {512, 1024}) ||
-      !in(v.rowqr_update_waves, {4, 8}) || !in(v.rowqr_update_kind, {0, 1, 2}))
+      !in(v.rowqr_update_waves, {4, 8}) || !in(v.rowqr_update_kind, {0, 1, 2}) ||
+      !in(v.sweep_many_threads, {64, 128, 256}))
     return false;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune = v;

@@ -363,8 +363,8 @@ __global__ void k_top(const double* LU, const int32_t* piv, int n, const int32_t
 constexpr int kNbT = 64;
 constexpr int kMaxV = 8;       // right-hand sides per pass
 constexpr int kCapL = 16384;   // LDS doubles, largest records and the top block
-// Sub-levels with at least this many records run 256 threads per record,
-// fewer records 1024 threads each.
+// Sub-levels with at least this many records run 64, 128 or 256 threads per
+// record (launch-shape table), fewer records 1024 threads each.
 constexpr int kManyRecords = 1024;
 // Top blocks of at least this many unknowns are solved by the many-workgroup
 // blocked triangular solves (one workgroup is latency-bound there).
@@ -758,10 +758,10 @@ __global__ void k_copy(const double* x, double* y, int64_t n) {
 // pass (the LDS kernel above holds 2r + k entries per right-hand side and so
 // rereads large factors once per right-hand side).  Per record, B holds the
 // right-hand sides of the triangular solve and X its solution, both [nv][r]
-// at nv * woff in the work buffer; a triangular solve is one launch per
-// 64-row block, every workgroup of which solves the diagonal block itself
-// (B rows of the block are only read in that launch) and then either writes
-// the block of X or updates its own 64 rows of B.
+// at nv * woff in the work buffer.  The products with T, L_sr and U_rs are
+// spread over many workgroups per record; each triangular solve takes one
+// launch per 64-row block and multiplies the block by the stored inverse of
+// its diagonal block.
 // ---------------------------------------------------------------------------
 struct SpArgs {
   const GroupRec* recs;
@@ -803,41 +803,52 @@ __device__ __forceinline__ SpRec sp_rec(const SpArgs& A, int i) {
 
 constexpr int kSpChunk = 512;  // skeleton entries staged in LDS per pass
 
-// Up, first step: B(v, i) = (P (u_r - T^T u_s))(v, i), thread per i.
+// Up, first step: B(v, i) = (P (u_r - T^T u_s))(v, i): 64 rows i per
+// workgroup, lane per row, the sum over the skeleton split between the 4 waves
+// and added through LDS.
 __global__ __launch_bounds__(256) void k_sp_up_first(SpArgs A) {
   const SpRec R = sp_rec(A, blockIdx.y);
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x * 256 >= R.r) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;  // 64 rows per workgroup
+  if (blockIdx.x * 64 >= R.r) return;
   const int nv = A.nv;
   __shared__ double sus[kMaxV][kSpChunk];
+  __shared__ double sred[4][kMaxV][64];
   const int c = i < R.r ? R.perm[i] : 0;
   double acc[kMaxV];
 #pragma unroll
-  for (int v = 0; v < kMaxV; ++v) acc[v] = (v < nv && i < R.r) ? A.u[v * A.N + R.rd[c]] : 0.0;
+  for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
   for (int j0 = 0; j0 < R.k; j0 += kSpChunk) {
     const int nj = min(kSpChunk, R.k - j0);
     __syncthreads();
     for (int e = threadIdx.x; e < nv * nj; e += 256) sus[e / nj][e % nj] = A.u[(e / nj) * A.N + R.sk[j0 + e % nj]];
     __syncthreads();
+    // wave wv takes the quarter [jb, je) of the chunk
+    const int jb = (nj * wv) / 4, je = (nj * (wv + 1)) / 4;
     if (i < R.r) {
       const double* tc = R.T + int64_t(j0) * R.r + c;
-      for (int j = 0; j < nj; j += kU) {
+      for (int j = jb; j < je; j += kU) {
         double t[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) t[u] = j + u < nj ? tc[int64_t(j + u) * R.r] : 0.0;
+        for (int u = 0; u < kU; ++u) t[u] = j + u < je ? tc[int64_t(j + u) * R.r] : 0.0;
 #pragma unroll
         for (int u = 0; u < kU; ++u)
-          if (j + u < nj)
+          if (j + u < je)
 #pragma unroll
             for (int v = 0; v < kMaxV; ++v)
-              if (v < nv) acc[v] -= t[u] * sus[v][j + u];
+              if (v < nv) acc[v] += t[u] * sus[v][j + u];
       }
     }
   }
-  if (i < R.r)
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) sred[wv][v][lane] = acc[v];
+  __syncthreads();
+  if (wv == 0 && i < R.r)
 #pragma unroll
     for (int v = 0; v < kMaxV; ++v)
-      if (v < nv) R.B[v * R.r + i] = acc[v];
+      if (v < nv)
+        R.B[v * R.r + i] =
+            A.u[v * A.N + R.rd[c]] - ((sred[0][v][lane] + sred[1][v][lane]) + (sred[2][v][lane] + sred[3][v][lane]));
 }
 
 // Down, first step: B(v, i) = (u_r - U_rs u_s)(v, i), one wave per row i.
@@ -938,8 +949,6 @@ __global__ __launch_bounds__(256) void k_sp_scatter(SpArgs A) {
   for (int v = 0; v < A.nv; ++v) A.u[v * A.N + R.rd[i]] = R.X[v * R.r + i];
 }
 
-// Block b of x = L^{-1} x (unit lower L of the LU).  Workgroup 0 writes X of
-// the block; workgroup w >= 1 updates B rows 64(b + w) .. +63.
 // x = D^{-1} x for the nv right-hand sides of one 64-row block, with D^{-1}
 // (the inverse of the block's diagonal block of L or U) in sD: row a per
 // lane, right-hand sides v = wave, wave + 4.  256 threads; ends synchronized.
@@ -993,6 +1002,11 @@ __global__ __launch_bounds__(64) void k_sp_dinv(SpArgs A, double* dinv) {
   for (int a = 0; a < kNbT; ++a) out[kNbT * kNbT + a * kNbT + c] = sX[a][c];
 }
 
+// Block b of x = L^{-1} x (unit lower L of the LU): workgroup 0 writes X of
+// the block, workgroup w >= 1 updates B rows 64(b + w) .. +63; every
+// workgroup first multiplies the block by the stored inverse of its diagonal
+// block (spread over many workgroups: one workgroup walking all blocks of a
+// large record is bound by the latency of its row updates).
 __global__ __launch_bounds__(256) void k_sp_lsolve(SpArgs A, int b) {
   const SpRec R = sp_rec(A, blockIdx.y);
   const int j0 = b * kNbT;
@@ -1113,6 +1127,10 @@ static void allow_large_lds() {
   static std::once_flag once;
   std::call_once(once, [] {
     const int bytes = kCapL * int(sizeof(double));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_lds<64>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_lds<128>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_lds<256>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_lds<1024>),
@@ -1132,6 +1150,15 @@ static bool split_solve(const SubLevel& sub, int64_t N, int nv) {
 // skeleton through the many-workgroup triangular solves.
 static bool top_split_solve(const hif_factor_s* H) {
   return H->ntop >= kTopSplitMin && 2 * H->ntop <= H->n;
+}
+
+// The triangular solves of the multi-workgroup path: one launch per 64-row
+// block.
+static void trsv(const SpArgs& P, unsigned nr, int nbk, bool lower, hipStream_t s) {
+  if (lower)
+    for (int b = 0; b < nbk; ++b) hipLaunchKernelGGL(k_sp_lsolve, dim3(unsigned(nbk - b), nr), dim3(256), 0, s, P, b);
+  else
+    for (int b = nbk - 1; b >= 0; --b) hipLaunchKernelGGL(k_sp_usolve, dim3(unsigned(b + 1), nr), dim3(256), 0, s, P, b);
 }
 
 // The sweeps proper.  work: min(nrhs, 8) * N doubles of scratch, reused by
@@ -1161,17 +1188,15 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
                  sub.dinv.p, sub.dinv_nb};
         const unsigned nr = unsigned(sub.nrec);
         const int nbk = (sub.max_r + kNbT - 1) / kNbT;
-        const dim3 gr(unsigned((sub.max_r + 255) / 256), nr);
+        const dim3 gr(unsigned((sub.max_r + 255) / 256), nr), gu(unsigned((sub.max_r + 63) / 64), nr);
         const dim3 gs(unsigned((sub.max_k + 15) / 16), nr);
         if (!down) {
-          hipLaunchKernelGGL(k_sp_up_first, gr, dim3(256), 0, s, P);
-          for (int b = 0; b < nbk; ++b)
-            hipLaunchKernelGGL(k_sp_lsolve, dim3(unsigned(nbk - b), nr), dim3(256), 0, s, P, b);
+          hipLaunchKernelGGL(k_sp_up_first, gu, dim3(256), 0, s, P);
+          trsv(P, nr, nbk, true, s);
           if (sub.max_k > 0) hipLaunchKernelGGL(k_sp_skel_update, gs, dim3(256), 0, s, P, 0);
         } else {
           hipLaunchKernelGGL(k_sp_down_first, dim3(unsigned((sub.max_r + 15) / 16), nr), dim3(256), 0, s, P);
-          for (int b = nbk - 1; b >= 0; --b)
-            hipLaunchKernelGGL(k_sp_usolve, dim3(unsigned(b + 1), nr), dim3(256), 0, s, P, b);
+          trsv(P, nr, nbk, false, s);
           if (sub.max_k > 0) hipLaunchKernelGGL(k_sp_skel_update, gs, dim3(256), 0, s, P, 1);
         }
         hipLaunchKernelGGL(k_sp_scatter, gr, dim3(256), 0, s, P);
@@ -1185,7 +1210,12 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
         const int nvb = std::max(1, std::min(nv, kCapL / sub.max_2rk));
         const int cap = nvb * sub.max_2rk;
         const size_t lds = size_t(cap) * sizeof(double);
-        if (sub.nrec >= kManyRecords)
+        const int many = tuning().sweep_many_threads;
+        if (sub.nrec >= kManyRecords && many == 64)
+          hipLaunchKernelGGL(k_sweep_lds<64>, dim3(sub.nrec), dim3(64), lds, s, A, down, cap);
+        else if (sub.nrec >= kManyRecords && many == 128)
+          hipLaunchKernelGGL(k_sweep_lds<128>, dim3(sub.nrec), dim3(128), lds, s, A, down, cap);
+        else if (sub.nrec >= kManyRecords)
           hipLaunchKernelGGL(k_sweep_lds<256>, dim3(sub.nrec), dim3(256), lds, s, A, down, cap);
         else
           hipLaunchKernelGGL(k_sweep_lds<1024>, dim3(sub.nrec), dim3(1024), lds, s, A, down, cap);
@@ -1208,11 +1238,11 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
       SpArgs P{H->top_rec.p, H->top_iarena.p, H->top_lu.p,  H->top_woff.p, u, wk, wk + int64_t(nv) * r, N, nv,
                H->top_dinv.p, nbk};
       const dim3 gr(unsigned((r + 255) / 256), 1);
-      hipLaunchKernelGGL(k_sp_up_first, gr, dim3(256), 0, s, P);
-      for (int b = 0; b < nbk; ++b) hipLaunchKernelGGL(k_sp_lsolve, dim3(unsigned(nbk - b), 1), dim3(256), 0, s, P, b);
+      hipLaunchKernelGGL(k_sp_up_first, dim3(unsigned((r + 63) / 64), 1), dim3(256), 0, s, P);
+      trsv(P, 1, nbk, true, s);
       hipLaunchKernelGGL(k_sp_scatter, gr, dim3(256), 0, s, P);
       hipLaunchKernelGGL(k_sp_down_first, dim3(unsigned((r + 15) / 16), 1), dim3(256), 0, s, P);
-      for (int b = nbk - 1; b >= 0; --b) hipLaunchKernelGGL(k_sp_usolve, dim3(unsigned(b + 1), 1), dim3(256), 0, s, P, b);
+      trsv(P, 1, nbk, false, s);
       hipLaunchKernelGGL(k_sp_scatter, gr, dim3(256), 0, s, P);
     } else if (H->ntop > 0) {
       if (op <= 1 && 2 * H->ntop <= kCapL)

@@ -12,6 +12,7 @@
 //   row compression of the 512 x 512 workload (eps 1e-6), medians of 3 factorizations:
 //     4 waves 98.3-98.8, 8 waves 107.3-107.9, 4 waves + LDS 105.5, 8 waves + LDS 96.5-97.2,
 //     4 waves rows split 103.0-103.1, 8 waves rows split 104.0
+//   8-RHS solve of the 512 x 512 workload: 256 threads 6.82, 128 threads 7.04-7.05, 64 threads 7.56-7.58
 #pragma once
 
 // waves per problem of the register-resident pivoted QR, problems of at most
@@ -24,3 +25,5 @@
 #define HIF_TUNED_ROWQR_UPDATE_WAVES 8
 // 0: Y in registers, 1: the chunk reflectors staged in LDS, 2: rows split over two waves
 #define HIF_TUNED_ROWQR_UPDATE_KIND 1
+// threads per record of the sweeps on sub-levels of at least 1024 records
+#define HIF_TUNED_SWEEP_MANY_THREADS 256

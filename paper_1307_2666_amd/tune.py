@@ -18,6 +18,9 @@ Buckets and candidates (``hif_tuning`` in ``include/hif.h``):
   panel factorization for the CUs, so it is timed on whole factorizations:
   ``hif_factor`` of the second-kind 2D problem on a 384 x 384 grid (eps 1e-6,
   leaf 64), the row-compression phase time of the library's own events.
+* ``sweep_many_threads``: threads per record of the solve on sub-levels of many
+  small records, timed by 8-RHS solves with one factorization of that
+  problem (HIP events, median of 5).
 
 Every candidate is timed with HIP events over 5 runs after a warm run, on the
 same inputs (the inputs are restored before each run); the fastest median
@@ -45,6 +48,7 @@ LU_BUCKETS = [(257, 512, 256), (513, 1024, 64)]  # (n lo, n hi, problems)
 LU_CANDIDATES = [(256, 512, 1024), (512, 1024)]
 ROWQR_CANDIDATES = [(4, 0), (8, 0), (4, 1), (8, 1), (4, 2), (8, 2)]  # (waves, kind)
 ROWQR_GRID = 384
+SWEEP_CANDIDATES = [64, 128, 256]
 
 
 def _median_ms(run, reps=5):
@@ -138,18 +142,26 @@ def _time_lu(mats):
 
 def _time_rowqr(reps=3):
     factor = B.factor
-    n = ROWQR_GRID
-    g = (torch.arange(n, dtype=torch.float64, device="cuda") + 0.5) / n
-    pts = torch.stack([g.repeat(n), g.repeat_interleave(n)], dim=1).contiguous()
-    a = torch.ones(n * n, dtype=torch.float64, device="cuda")
-    F = factor(pts, 1e-6, 64, a=a, h=1.0 / n)  # warm
+    pts, a, h = _grid_problem()
+    F = factor(pts, 1e-6, 64, a=a, h=h)  # warm
     F.free()
     ts = []
     for _ in range(reps):
-        F = factor(pts, 1e-6, 64, a=a, h=1.0 / n)
+        F = factor(pts, 1e-6, 64, a=a, h=h)
         ts.append(F.stats()["t_phase_ms"]["rowqr"])
         F.free()
     return float(np.median(ts))
+
+
+def _grid_problem():
+    n = ROWQR_GRID
+    g = (torch.arange(n, dtype=torch.float64, device="cuda") + 0.5) / n
+    pts = torch.stack([g.repeat(n), g.repeat_interleave(n)], dim=1).contiguous()
+    return pts, torch.ones(n * n, dtype=torch.float64, device="cuda"), 1.0 / n
+
+
+def _time_sweep(F, f):
+    return _median_ms(lambda: F.solve(f))
 
 
 def tune(seed=0):
@@ -185,6 +197,20 @@ def tune(seed=0):
         res[(w, lds)] = _time_rowqr()
     best = min(res, key=res.get)
     table["rowqr_update_waves"], table["rowqr_update_kind"] = best
+    B.tuning_set(dict(table, rowqr_update_waves=best[0], rowqr_update_kind=best[1]))
+    pts, a, h = _grid_problem()
+    F = B.factor(pts, 1e-6, 64, a=a, h=h)
+    f = torch.randn(8, pts.shape[0], dtype=torch.float64, device="cuda",
+                    generator=torch.Generator("cuda").manual_seed(seed))
+    sres = {}
+    for th in SWEEP_CANDIDATES:
+        t = {k: (list(v) if isinstance(v, list) else v) for k, v in table.items()}
+        t["sweep_many_threads"] = th
+        B.tuning_set(t)
+        sres[th] = _time_sweep(F, f)
+    F.free()
+    table["sweep_many_threads"] = min(sres, key=sres.get)
+    timings["sweep_many_threads"] = {"grid": ROWQR_GRID, "rhs": 8, "ms": sres}
     kinds = {0: "", 1: " + LDS", 2: " rows split"}
     timings["rowqr_update"] = {"grid": ROWQR_GRID, "ms": {f"{w} waves{kinds[k]}": v for (w, k), v in res.items()}}
     B.tuning_set(table)
@@ -202,6 +228,10 @@ def write_header(table, timings, path=HEADER):
     for e in timings["lu_panel_threads"]:
         lines.append(f"//   LU, {e['problems']} blocks of {e['rows'][0]}-{e['rows'][1]} rows: " +
                      ", ".join(f"{k} threads {v:.3f}" for k, v in e["ms"].items()))
+    sw = timings.get("sweep_many_threads")
+    if sw:
+        lines.append(f"//   8-RHS solve of a {sw['grid']} x {sw['grid']} factorization: " +
+                     ", ".join(f"{k} threads {v:.3f}" for k, v in sw["ms"].items()))
     ru = timings.get("rowqr_update")
     if ru:
         lines.append(f"//   row compression of a {ru['grid']} x {ru['grid']} factorization (eps 1e-6): " +
@@ -216,7 +246,9 @@ def write_header(table, timings, path=HEADER):
               "// update beside the next panel",
               f"#define HIF_TUNED_ROWQR_UPDATE_WAVES {table['rowqr_update_waves']}",
               "// 0: Y in registers, 1: the chunk reflectors staged in LDS, 2: rows split over two waves",
-              f"#define HIF_TUNED_ROWQR_UPDATE_KIND {table['rowqr_update_kind']}", ""]
+              f"#define HIF_TUNED_ROWQR_UPDATE_KIND {table['rowqr_update_kind']}",
+              "// threads per record of the sweeps on sub-levels of at least 1024 records",
+              f"#define HIF_TUNED_SWEEP_MANY_THREADS {table['sweep_many_threads']}", ""]
     with open(path, "w") as fh:
         fh.write("\n".join(lines))
 

@@ -269,3 +269,38 @@ def test_step_nearfield_and_assembly_on_first_sublevels(si, trace2d):
     # the level-0 edges of this grid eliminate nothing: no A_cc to compare there
     assert nacc > 0 or si == 1
     F.free()
+
+
+def test_sweep_and_rowqr_shapes_agree():
+    # The sweep's threads per record (sub-levels of >= 1024 records) change
+    # only which wave handles which row: every shape gives the same solve.
+    # The row compression's update shapes change the schedule of the same
+    # products: factorizations agree to rounding.
+    n = 256
+    pts = torch.tensor(grid_points(n, 2), device=DEV)
+    a = torch.ones(n * n, dtype=torch.float64, device=DEV)
+    f = torch.randn(8, n * n, dtype=torch.float64, device=DEV, generator=torch.Generator(DEV).manual_seed(5))
+    base = hif.tuning_get()
+    try:
+        F = hif.factor(pts, 1e-6, 64, a=a, h=1.0 / n)
+        assert F.stats()["sub_groups"][0] >= 1024
+        sols = []
+        for th in (64, 128, 256):
+            hif.tuning_set(dict(base, sweep_many_threads=th))
+            sols.append(F.solve(f))
+        for u in sols[1:]:
+            assert torch.equal(u, sols[0])
+        F.free()
+        outs = []
+        for w, kind in ((4, 0), (8, 1), (8, 2)):
+            hif.tuning_set(dict(base, rowqr_update_waves=w, rowqr_update_kind=kind))
+            G = hif.factor(pts, 1e-6, 64, a=a, h=1.0 / n)
+            outs.append((G.stats()["top_size"], G.apply(f[0])))
+            G.free()
+        for top, y in outs[1:]:
+            assert abs(top - outs[0][0]) <= 2
+            assert torch.linalg.norm(y - outs[0][1]) <= 1e-8 * torch.linalg.norm(outs[0][1])
+        with pytest.raises(hif.HifError):
+            hif.tuning_set(dict(base, sweep_many_threads=96))
+    finally:
+        hif.tuning_set(None)
