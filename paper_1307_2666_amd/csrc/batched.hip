@@ -983,24 +983,113 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void k_tsqr_apply_chunk_reg(QrBatc
                     M + int64_t(j0 + lo) * ld + c0, ld, nt);
 }
 
-// K4: trailing update of the chunk top rows with the stack's WY form.
-__global__ __launch_bounds__(256) void k_tsqr_apply_stack(QrBatch A, int j0, int cr, int half, int cbeg, int cend) {
+
+// The stack update with the rows split between RG waves per 16 columns
+// (wave w: columns 16 (w % CG), row blocks of 32 taken round-robin by the RG
+// waves w / CG): each wave forms a partial V^T Y over its rows, the RG
+// partials are added through LDS, and every wave then forms W and updates its
+// own rows.  rowp(r) gives the address of row r of the tile.
+template <int CG, int RG, class RowP>
+__device__ __forceinline__ void apply_wy_tile_rg(const double* V, int rows, const double* Tm, RowP rowp, int nt,
+                                                 double* sP) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int cg = wv % CG, rg = wv / CG;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ct = cg * 16;
+  const bool colok = ct + li < nt;
+  double4_t p0 = {0.0, 0.0, 0.0, 0.0}, p1 = {0.0, 0.0, 0.0, 0.0};
+  for (int kb = 32 * rg; kb < rows; kb += 32 * RG) {
+    double a0[8], a1[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int r = kb + 4 * u + lk;
+      const bool ok = r < rows;
+      a0[u] = ok ? V[int64_t(r) * kTb + li] : 0.0;
+      a1[u] = ok ? V[int64_t(r) * kTb + 16 + li] : 0.0;
+      b[u] = (ok && colok) ? rowp(r)[ct + li] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      p0 = mfma_f64(a0[u], b[u], p0);
+      p1 = mfma_f64(a1[u], b[u], p1);
+    }
+  }
+  double* mine = sP + (cg * RG + rg) * 8 * 64;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    mine[e * 64 + lane] = p0[e];
+    mine[(4 + e) * 64 + lane] = p1[e];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      s0 += sP[(cg * RG + g) * 8 * 64 + e * 64 + lane];
+      s1 += sP[(cg * RG + g) * 8 * 64 + (4 + e) * 64 + lane];
+    }
+    p0[e] = s0;
+    p1[e] = s1;
+  }
+  double4_t w0 = {0.0, 0.0, 0.0, 0.0}, w1 = {0.0, 0.0, 0.0, 0.0};
+  {
+    double t0[8], t1[8];
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      t0[s2] = Tm[(4 * s2 + lk) * kTb + li];
+      t1[s2] = Tm[(4 * s2 + lk) * kTb + 16 + li];
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      const double bp = s2 < 4 ? p0[s2 & 3] : p1[s2 & 3];
+      w0 = mfma_f64(t0[s2], bp, w0);
+      w1 = mfma_f64(t1[s2], bp, w1);
+    }
+  }
+  for (int rt = 16 * rg; rt < rows; rt += 16 * RG) {
+    double a[8], y[4];
+    const int ra = rt + li;
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) a[s2] = ra < rows ? V[int64_t(ra) * kTb + 4 * s2 + lk] : 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = rt + 4 * v + lk;
+      y[v] = (r < rows && colok) ? rowp(r)[ct + li] : 0.0;
+    }
+    double4_t d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) d = mfma_f64(a[s2], s2 < 4 ? w0[s2 & 3] : w1[s2 & 3], d);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = rt + 4 * v + lk;
+      if (r < rows && colok) rowp(r)[ct + li] = y[v] - d[v];
+    }
+  }
+}
+
+// K4 with the rows split between RG waves: the stack's WY form applied to the
+// chunk top rows of 16 CG columns per workgroup (CG RG waves).
+template <int CG, int RG>
+__global__ __launch_bounds__(64 * CG * RG) void k_tsqr_apply_stack_rg(QrBatch A, int j0, int cr, int half, int cbeg,
+                                                                     int cend) {
   const int q = blockIdx.y;
   const int m = A.rows[q], n = A.cols[q];
   if (m <= n || j0 >= n) return;
   const PanelGeom g = panel_geom(m, n, j0, cr);
   if (g.nck < 2) return;
-  const int c0 = cbeg + blockIdx.x * 64, ce = min(n, cend);
+  const int c0 = cbeg + blockIdx.x * 16 * CG, ce = min(n, cend);
   if (c0 >= ce) return;
-  const int nt = min(64, ce - c0);
+  const int nt = min(16 * CG, ce - c0);
   double* M = A.base + A.moff[q];
   const int ld = A.ld[q];
   const TsqrLayout L = tsqr_layout(m);
   const double* S0 = A.scratch + A.soff[q] + half * L.total;
   const int mp = g.mp, nck = g.nck;
   double* Mc = M + int64_t(j0) * ld + c0;
-  apply_wy_tile(S0 + L.Vs, nck * kTb, S0 + L.Ts,
-                [=](int r) { return Mc + int64_t(chunk_lo(r / kTb, mp, nck) + r % kTb) * ld; }, nt);
+  __shared__ double sP[CG * RG * 8 * 64];
+  apply_wy_tile_rg<CG, RG>(S0 + L.Vs, nck * kTb, S0 + L.Ts,
+                           [=](int r) { return Mc + int64_t(chunk_lo(r / kTb, mp, nck) + r % kTb) * ld; }, nt, sP);
 }
 
 // ---------------------------------------------------------------------------
@@ -1558,7 +1647,8 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
         else
           hipLaunchKernelGGL(k_tsqr_apply_chunk, dim3(tiles, nckmax, A.nprob), dim3(256), 0, s2, A, j0, cr, half,
                              nb1, max_cols);
-        hipLaunchKernelGGL(k_tsqr_apply_stack, dim3(tiles, A.nprob), dim3(256), 0, s2, A, j0, cr, half, nb1, max_cols);
+        hipLaunchKernelGGL((k_tsqr_apply_stack_rg<4, 2>), dim3(tiles, A.nprob), dim3(512), 0, s2, A, j0, cr, half, nb1,
+                           max_cols);
         HIF_HIP(hipEventRecord(ev_rest, s2));
         rest_pending = true;
       }
@@ -1570,7 +1660,7 @@ void launch_qr_batched(const QrBatch& A, int max_rows, int max_cols, hipStream_t
                            nb1);
       else
         hipLaunchKernelGGL(k_tsqr_apply_chunk, dim3(1, nckmax, A.nprob), dim3(256), 0, s, A, j0, cr, half, nb0, nb1);
-      hipLaunchKernelGGL(k_tsqr_apply_stack, dim3(1, A.nprob), dim3(256), 0, s, A, j0, cr, half, nb0, nb1);
+      hipLaunchKernelGGL((k_tsqr_apply_stack_rg<2, 4>), dim3(1, A.nprob), dim3(512), 0, s, A, j0, cr, half, nb0, nb1);
     }
     if (rest_pending) HIF_HIP(hipStreamWaitEvent(s, ev_rest, 0));
     hipLaunchKernelGGL(k_qr_clear_lower, dim3(64, A.nprob), dim3(256), 0, s, A);

@@ -4,15 +4,13 @@
 // the candidates and the problem sizes of each bucket.
 //
 // Medians (ms):
-//   ID, 4096 problems of 33-64 columns: 4 waves 0.854, 8 waves 0.927, 16 waves 1.032
-//   ID, 2048 problems of 97-128 columns: 4 waves 3.032, 8 waves 2.377, 16 waves 2.767
-//   ID, 1024 problems of 161-192 columns: 8 waves 4.351, 16 waves 3.402
-//   LU, 256 blocks of 257-512 rows: 256 threads 3.094, 512 threads 2.955, 1024 threads 3.157
-//   LU, 64 blocks of 513-1024 rows: 512 threads 6.206, 1024 threads 6.301
-//   row compression of the 512 x 512 workload (eps 1e-6), medians of 3 factorizations:
-//     4 waves 98.3-98.8, 8 waves 107.3-107.9, 4 waves + LDS 105.5, 8 waves + LDS 96.5-97.2,
-//     4 waves rows split 103.0-103.1, 8 waves rows split 104.0
-//   8-RHS solve of the 512 x 512 workload: 256 threads 6.82, 128 threads 7.04-7.05, 64 threads 7.56-7.58
+//   ID, 4096 problems of 33-64 columns: 4 waves 0.851, 8 waves 0.915, 16 waves 1.033
+//   ID, 2048 problems of 97-128 columns: 4 waves 3.013, 8 waves 2.362, 16 waves 2.730
+//   ID, 1024 problems of 161-192 columns: 8 waves 4.344, 16 waves 3.403
+//   LU, 256 blocks of 257-512 rows: 256 threads 3.092, 512 threads 2.959, 1024 threads 3.158
+//   LU, 64 blocks of 513-1024 rows: 512 threads 6.269, 1024 threads 6.340
+//   8-RHS solve of a 384 x 384 factorization: 64 threads 5.562, 128 threads 5.234, 256 threads 5.116
+//   row compression of a 384 x 384 factorization (eps 1e-6): 4 waves 54.97, 8 waves 59.47, 4 waves + LDS 56.60, 8 waves + LDS 54.56, 4 waves rows split 57.59, 8 waves rows split 57.01
 #pragma once
 
 // waves per problem of the register-resident pivoted QR, problems of at most
