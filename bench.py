@@ -53,7 +53,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE runs scaled by what the counters read for a 256 MiB copy kernel
 # (see the profile summaries); None until taken for the kernels as they stand.
 # 267 GB read + 73 GB written per factorization (profiles/hbm_traffic_id_sq512.md).
-ID_STEP_TRAFFIC_BYTES = 340.30e9
+ID_STEP_TRAFFIC_BYTES = 340.50e9
 # ALU roof of the exact pair-by-pair product (2D, 8 right-hand sides, two
 # targets per thread): its inner loop issues 110 vector instructions per
 # source for two targets, 55 per pair (log, distance, select, 8 FMAs); a
