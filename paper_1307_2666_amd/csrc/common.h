@@ -233,6 +233,9 @@ struct hif_factor_s {
   hif::DBuf<double> top_dinv;  // its diagonal-block inverses, as SubLevel::dinv
   // Sweep scratch.
   hif::DBuf<double> work;
+  // Ordering words of the chained triangular solves (sweep.hip), cleared by
+  // each pass before use.
+  hif::DBuf<uint32_t> sync;
   hif_stats_t stats{};
   // Exact operator by FFT: 0 not set up yet, 1 ready (fft), -1 not applicable.
   int fft_state = 0;

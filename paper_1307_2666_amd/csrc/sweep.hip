@@ -753,15 +753,16 @@ __global__ void k_copy(const double* x, double* y, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Solve (op 0) for sub-levels with few, large records: each record is spread
-// over many workgroups and all right-hand sides go through its factors in one
-// pass (the LDS kernel above holds 2r + k entries per right-hand side and so
-// rereads large factors once per right-hand side).  Per record, B holds the
-// right-hand sides of the triangular solve and X its solution, both [nv][r]
-// at nv * woff in the work buffer.  The products with T, L_sr and U_rs are
-// spread over many workgroups per record; each triangular solve takes one
-// launch per 64-row block and multiplies the block by the stored inverse of
-// its diagonal block.
+// Solve and transposed solve (op 0, 1) for sub-levels with few, large
+// records: each record is spread over many workgroups and all right-hand
+// sides go through its factors in one pass (the LDS kernel above holds
+// 2r + k entries per right-hand side and so rereads large factors once per
+// right-hand side).  Per record, B holds the right-hand sides of the
+// triangular solve and X its solution, both [nv][r] at nv * woff in the work
+// buffer.  The products with T, L_sr and U_rs are spread over many
+// workgroups per record; the triangular solve of every record of the pass is
+// one launch of workgroups that hand 64-row blocks of X to each other
+// (k_sp_chain).
 // ---------------------------------------------------------------------------
 struct SpArgs {
   const GroupRec* recs;
@@ -775,6 +776,10 @@ struct SpArgs {
   int nv;
   const double* dinv;  // diagonal-block inverses (SubLevel::dinv layout)
   int dnb;             // blocks per record in dinv
+  // Ordering words of the chained triangular solve: [0] ticket counter, then
+  // one flag per (record, 64-row block) at 1 + record * nbm + block.
+  uint32_t* sync = nullptr;
+  int nbm = 0;  // blocks of the largest record
 };
 
 struct SpRec {
@@ -801,20 +806,38 @@ __device__ __forceinline__ SpRec sp_rec(const SpArgs& A, int i) {
   return v;
 }
 
+// The first kernel of a pass clears the ordering words of the chained
+// solve that follows it: workgroup (0, i) the flags of record i, and
+// workgroup (0, 0) the ticket counter.  The next launch on the stream sees
+// the zeros.
+__device__ __forceinline__ void sp_clear_sync(const SpArgs& A) {
+  if (blockIdx.x != 0 || !A.sync) return;
+  uint32_t* f = A.sync + 1 + int64_t(blockIdx.y) * A.nbm;
+  for (int e = threadIdx.x; e < A.nbm; e += blockDim.x) f[e] = 0u;
+  if (blockIdx.y == 0 && threadIdx.x == 0) A.sync[0] = 0u;
+}
+
 constexpr int kSpChunk = 512;  // skeleton entries staged in LDS per pass
 
-// Up, first step: B(v, i) = (P (u_r - T^T u_s))(v, i): 64 rows i per
-// workgroup, lane per row, the sum over the skeleton split between the 4 waves
-// and added through LDS.
-__global__ __launch_bounds__(256) void k_sp_up_first(SpArgs A) {
+// First step of an up pass (and of the transposed solve's down pass), column
+// form: B(v, i) = u_r(v, c) - (M^T u_s)(v, c) with c = perm[i] (PERM: the
+// row interchanges of the solve, B = P(u_r - T^T u_s)) or c = i, and
+// M = T (k x r), or L_sr with LSR.  With ADD instead u_r(v, i) += (M^T u_s)(v, i)
+// in place (the last step of the apply sweeps' down pass).  64 rows i per
+// workgroup, lane per row, the sum over the skeleton split between the 4
+// waves and added through LDS.
+template <bool LSR, bool PERM, bool ADD = false>
+__global__ __launch_bounds__(256) void k_sp_first_cols(SpArgs A) {
+  sp_clear_sync(A);
   const SpRec R = sp_rec(A, blockIdx.y);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;  // 64 rows per workgroup
   if (blockIdx.x * 64 >= R.r) return;
   const int nv = A.nv;
+  const double* M = LSR ? R.Lsr : R.T;
   __shared__ double sus[kMaxV][kSpChunk];
   __shared__ double sred[4][kMaxV][64];
-  const int c = i < R.r ? R.perm[i] : 0;
+  const int c = i < R.r ? (PERM ? R.perm[i] : i) : 0;
   double acc[kMaxV];
 #pragma unroll
   for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
@@ -826,7 +849,7 @@ __global__ __launch_bounds__(256) void k_sp_up_first(SpArgs A) {
     // wave wv takes the quarter [jb, je) of the chunk
     const int jb = (nj * wv) / 4, je = (nj * (wv + 1)) / 4;
     if (i < R.r) {
-      const double* tc = R.T + int64_t(j0) * R.r + c;
+      const double* tc = M + int64_t(j0) * R.r + c;
       for (int j = jb; j < je; j += kU) {
         double t[kU];
 #pragma unroll
@@ -846,13 +869,19 @@ __global__ __launch_bounds__(256) void k_sp_up_first(SpArgs A) {
   if (wv == 0 && i < R.r)
 #pragma unroll
     for (int v = 0; v < kMaxV; ++v)
-      if (v < nv)
-        R.B[v * R.r + i] =
-            A.u[v * A.N + R.rd[c]] - ((sred[0][v][lane] + sred[1][v][lane]) + (sred[2][v][lane] + sred[3][v][lane]));
+      if (v < nv) {
+        const double t = (sred[0][v][lane] + sred[1][v][lane]) + (sred[2][v][lane] + sred[3][v][lane]);
+        if (ADD)
+          A.u[v * A.N + R.rd[c]] += t;
+        else
+          R.B[v * R.r + i] = A.u[v * A.N + R.rd[c]] - t;
+      }
 }
 
-// Down, first step: B(v, i) = (u_r - U_rs u_s)(v, i), one wave per row i.
+// Down, first step of the solve: B(v, i) = (u_r - U_rs u_s)(v, i), one wave
+// per row i.
 __global__ __launch_bounds__(256) void k_sp_down_first(SpArgs A) {
+  sp_clear_sync(A);
   const SpRec R = sp_rec(A, blockIdx.y);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i0 = blockIdx.x * 16;  // 16 rows per workgroup, 4 per wave
@@ -895,9 +924,11 @@ __global__ __launch_bounds__(256) void k_sp_down_first(SpArgs A) {
   }
 }
 
-// u_s -= M X (M = L_sr or T, k x r), one wave per skeleton row; X staged in
-// LDS by chunks of columns.
-__global__ __launch_bounds__(256) void k_sp_skel_update(SpArgs A, int which) {
+// u_s += sgn M x (M = L_sr or T, k x r), one wave per skeleton row; x is X,
+// or with GATHER the record's u_r read through its indices; staged in LDS by
+// chunks of columns.
+template <bool GATHER>
+__global__ __launch_bounds__(256) void k_sp_skel_update(SpArgs A, int which, double sgn) {
   const SpRec R = sp_rec(A, blockIdx.y);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int j0 = blockIdx.x * 16;
@@ -913,7 +944,8 @@ __global__ __launch_bounds__(256) void k_sp_skel_update(SpArgs A, int which) {
   for (int c0 = 0; c0 < R.r; c0 += kSpChunk) {
     const int nc = min(kSpChunk, R.r - c0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nv * nc; e += 256) sx[e / nc][e % nc] = R.X[(e / nc) * R.r + c0 + e % nc];
+    for (int e = threadIdx.x; e < nv * nc; e += 256)
+      sx[e / nc][e % nc] = GATHER ? A.u[(e / nc) * A.N + R.rd[c0 + e % nc]] : R.X[(e / nc) * R.r + c0 + e % nc];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -936,43 +968,235 @@ __global__ __launch_bounds__(256) void k_sp_skel_update(SpArgs A, int which) {
     for (int v = 0; v < kMaxV; ++v)
       if (v < nv) {
         const double t = wave_sum(acc[q][v]);
-        if (lane == 0) A.u[v * A.N + R.sk[j]] -= t;
+        if (lane == 0) A.u[v * A.N + R.sk[j]] += sgn * t;
       }
   }
 }
 
-// u_r = X.
-__global__ __launch_bounds__(256) void k_sp_scatter(SpArgs A) {
+// u_s += sgn U_rs^T x (U_rs r x k), x = X or with GATHER the record's u_r
+// read through its indices: lane per skeleton entry j, 64 per workgroup, the
+// sum over the rows of U_rs split between the 4 waves and added through LDS;
+// x staged in LDS by chunks.
+template <bool GATHER>
+__global__ __launch_bounds__(256) void k_sp_skel_update_T(SpArgs A, double sgn) {
+  const SpRec R = sp_rec(A, blockIdx.y);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  if (blockIdx.x * 64 >= R.k) return;
+  const int nv = A.nv;
+  __shared__ double sx[kMaxV][kSpChunk];
+  __shared__ double sred[4][kMaxV][64];
+  double acc[kMaxV];
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+  for (int i0 = 0; i0 < R.r; i0 += kSpChunk) {
+    const int ni = min(kSpChunk, R.r - i0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nv * ni; e += 256)
+      sx[e / ni][e % ni] = GATHER ? A.u[(e / ni) * A.N + R.rd[i0 + e % ni]] : R.X[(e / ni) * R.r + i0 + e % ni];
+    __syncthreads();
+    const int ib = (ni * wv) / 4, ie = (ni * (wv + 1)) / 4;
+    if (j < R.k) {
+      const double* mc = R.Urs + int64_t(i0) * R.k + j;
+      for (int i = ib; i < ie; i += kU) {
+        double m[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) m[u] = i + u < ie ? mc[int64_t(i + u) * R.k] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (i + u < ie)
+#pragma unroll
+            for (int v = 0; v < kMaxV; ++v)
+              if (v < nv) acc[v] += m[u] * sx[v][i + u];
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) sred[wv][v][lane] = acc[v];
+  __syncthreads();
+  if (wv == 0 && j < R.k)
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv)
+        A.u[v * A.N + R.sk[j]] += sgn * ((sred[0][v][lane] + sred[1][v][lane]) + (sred[2][v][lane] + sred[3][v][lane]));
+}
+
+// u_r = x, or with PERM u_r = P^T x (u_r[perm[i]] = x[i]); x = X (src 0) or
+// B (src 1).
+template <bool PERM>
+__global__ __launch_bounds__(256) void k_sp_scatter(SpArgs A, int src) {
   const SpRec R = sp_rec(A, blockIdx.y);
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= R.r) return;
-  for (int v = 0; v < A.nv; ++v) A.u[v * A.N + R.rd[i]] = R.X[v * R.r + i];
+  const double* x = src ? R.B : R.X;
+  const int d = R.rd[PERM ? R.perm[i] : i];
+  for (int v = 0; v < A.nv; ++v) A.u[v * A.N + d] = x[v * R.r + i];
 }
 
-// x = D^{-1} x for the nv right-hand sides of one 64-row block, with D^{-1}
-// (the inverse of the block's diagonal block of L or U) in sD: row a per
-// lane, right-hand sides v = wave, wave + 4.  256 threads; ends synchronized.
-__device__ __forceinline__ void diag_apply(const double (*sD)[kNbT + 1], double (*sx)[kNbT], int nv) {
+// B = u_r, or with PERM B = P u_r (B[i] = u_r[perm[i]]).
+template <bool PERM>
+__global__ __launch_bounds__(256) void k_sp_gather(SpArgs A) {
+  const SpRec R = sp_rec(A, blockIdx.y);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= R.r) return;
+  const int d = R.rd[PERM ? R.perm[i] : i];
+  for (int v = 0; v < A.nv; ++v) R.B[v * R.r + i] = A.u[v * A.N + d];
+}
+
+// The triangular products of the apply sweeps (and the rectangular ones
+// beside them), for few large records: x = B, out = X (io 0) or x = X,
+// out = B (io 1).  Row form: out(v, i) = (M x)(v, i) [+ (U_rs u_s)(v, i)]
+// with M the upper U of the record's LU (TRI 0, columns j >= i) or its unit
+// lower L (TRI 1, x_i plus the columns j < i); one wave per row i, 16 rows
+// per workgroup, x and u_s staged in LDS by chunks.
+template <int TRI, bool RECT>
+__global__ __launch_bounds__(256) void k_sp_rowmv(SpArgs A, int io) {
+  const SpRec R = sp_rec(A, blockIdx.y);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double y[kMaxV / 4];
+  const int i0 = blockIdx.x * 16;
+  if (i0 >= R.r) return;
+  const int nv = A.nv, r = R.r;
+  const double* x = io ? R.X : R.B;
+  double* out = io ? R.B : R.X;
+  __shared__ double sx[kMaxV][kSpChunk];
+  double acc[4][kMaxV];
 #pragma unroll
-  for (int q = 0; q < kMaxV / 4; ++q) {
-    const int v = wv + 4 * q;
-    double acc = 0.0;
-    if (v < nv)
-#pragma unroll 16
-      for (int c = 0; c < kNbT; ++c) acc += sD[lane][c] * sx[v][c];
-    y[q] = acc;
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v) acc[q][v] = 0.0;
+  // the columns the workgroup's rows reach
+  const int cb = TRI == 0 ? i0 : 0, ce = TRI == 0 ? r : min(r, i0 + 16);
+  for (int c0 = cb; c0 < ce; c0 += kSpChunk) {
+    const int nc = min(kSpChunk, ce - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nv * nc; e += 256) sx[e / nc][e % nc] = x[(e / nc) * r + c0 + e % nc];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + wv * 4 + q;
+      if (i < r) {
+        const double* mr = R.LU + int64_t(i) * r + c0;
+        for (int c = lane; c < nc; c += 64) {
+          const int j = c0 + c;
+          const double m = (TRI == 0 ? j >= i : j < i) ? mr[c] : 0.0;
+#pragma unroll
+          for (int v = 0; v < kMaxV; ++v)
+            if (v < nv) acc[q][v] += m * sx[v][c];
+        }
+      }
+    }
   }
-  __syncthreads();
+  if (RECT)
+    for (int j0 = 0; j0 < R.k; j0 += kSpChunk) {
+      const int nj = min(kSpChunk, R.k - j0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < nv * nj; e += 256) sx[e / nj][e % nj] = A.u[(e / nj) * A.N + R.sk[j0 + e % nj]];
+      __syncthreads();
 #pragma unroll
-  for (int q = 0; q < kMaxV / 4; ++q)
-    if (wv + 4 * q < nv) sx[wv + 4 * q][lane] = y[q];
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + wv * 4 + q;
+        if (i < r) {
+          const double* mr = R.Urs + int64_t(i) * R.k + j0;
+          for (int j = lane; j < nj; j += 64) {
+            const double m = mr[j];
+#pragma unroll
+            for (int v = 0; v < kMaxV; ++v)
+              if (v < nv) acc[q][v] += m * sx[v][j];
+          }
+        }
+      }
+    }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = i0 + wv * 4 + q;
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv) {
+        const double t = wave_sum(acc[q][v]);
+        if (lane == 0 && i < r) out[v * r + i] = t + (TRI == 1 ? x[v * r + i] : 0.0);
+      }
+  }
+}
+
+// Column form: out(v, i) = (M^T x)(v, i) [+ (L_sr^T u_s)(v, i)] with M^T the
+// unit upper L^T (TRI 2: x_i plus the rows j > i of L) or the lower U^T
+// (TRI 3: the rows j <= i of U); lane per i, 64 per workgroup, the sum over
+// j split between the 4 waves and added through LDS.
+template <int TRI, bool RECT>
+__global__ __launch_bounds__(256) void k_sp_colmv(SpArgs A, int io) {
+  const SpRec R = sp_rec(A, blockIdx.y);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ib = blockIdx.x * 64, i = ib + lane;
+  if (ib >= R.r) return;
+  const int nv = A.nv, r = R.r;
+  const double* x = io ? R.X : R.B;
+  double* out = io ? R.B : R.X;
+  __shared__ double sx[kMaxV][kSpChunk];
+  __shared__ double sred[4][kMaxV][64];
+  double acc[kMaxV];
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+  // the rows the workgroup's columns reach
+  const int jb = TRI == 2 ? ib : 0, je = TRI == 2 ? r : min(r, ib + 64);
+  for (int j0 = jb; j0 < je; j0 += kSpChunk) {
+    const int nj = min(kSpChunk, je - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nv * nj; e += 256) sx[e / nj][e % nj] = x[(e / nj) * r + j0 + e % nj];
+    __syncthreads();
+    const int qb = (nj * wv) / 4, qe = (nj * (wv + 1)) / 4;
+    if (i < r) {
+      const double* mc = R.LU + int64_t(j0) * r + i;
+      for (int j = qb; j < qe; j += kU) {
+        double m[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int jr = j0 + j + u;
+          m[u] = (j + u < qe && (TRI == 2 ? jr > i : jr <= i)) ? mc[int64_t(j + u) * r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (j + u < qe)
+#pragma unroll
+            for (int v = 0; v < kMaxV; ++v)
+              if (v < nv) acc[v] += m[u] * sx[v][j + u];
+      }
+    }
+  }
+  if (RECT)
+    for (int j0 = 0; j0 < R.k; j0 += kSpChunk) {
+      const int nj = min(kSpChunk, R.k - j0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < nv * nj; e += 256) sx[e / nj][e % nj] = A.u[(e / nj) * A.N + R.sk[j0 + e % nj]];
+      __syncthreads();
+      const int qb = (nj * wv) / 4, qe = (nj * (wv + 1)) / 4;
+      if (i < r) {
+        const double* mc = R.Lsr + int64_t(j0) * r + i;
+        for (int j = qb; j < qe; j += kU) {
+          double m[kU];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) m[u] = j + u < qe ? mc[int64_t(j + u) * r] : 0.0;
+#pragma unroll
+          for (int u = 0; u < kU; ++u)
+            if (j + u < qe)
+#pragma unroll
+              for (int v = 0; v < kMaxV; ++v)
+                if (v < nv) acc[v] += m[u] * sx[v][j + u];
+        }
+      }
+    }
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) sred[wv][v][lane] = acc[v];
   __syncthreads();
+  if (wv == 0 && i < r)
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv)
+        out[v * r + i] = ((sred[0][v][lane] + sred[1][v][lane]) + (sred[2][v][lane] + sred[3][v][lane])) +
+                         (TRI == 2 ? x[v * r + i] : 0.0);
 }
 
 // Inverses of the diagonal blocks of the records' L (unit lower) and U
-// (upper) for the blocked solves below: workgroup (b, i) inverts block b of
+// (upper) for the chained solves below: workgroup (b, i) inverts block b of
 // record i; lane c builds column c of each inverse by substitution (L: down
 // the rows, U: up the rows), so no lane reads another's column.  Rows and
 // columns past a partial last block are the identity.
@@ -1002,111 +1226,139 @@ __global__ __launch_bounds__(64) void k_sp_dinv(SpArgs A, double* dinv) {
   for (int a = 0; a < kNbT; ++a) out[kNbT * kNbT + a * kNbT + c] = sX[a][c];
 }
 
-// Block b of x = L^{-1} x (unit lower L of the LU): workgroup 0 writes X of
-// the block, workgroup w >= 1 updates B rows 64(b + w) .. +63; every
-// workgroup first multiplies the block by the stored inverse of its diagonal
-// block (spread over many workgroups: one workgroup walking all blocks of a
-// large record is bound by the latency of its row updates).
-__global__ __launch_bounds__(256) void k_sp_lsolve(SpArgs A, int b) {
-  const SpRec R = sp_rec(A, blockIdx.y);
-  const int j0 = b * kNbT;
-  if (j0 >= R.r) return;
-  const int w = blockIdx.x;
-  const int i0 = j0 + w * kNbT;
-  if (i0 >= R.r) return;
-  const int nb = min(kNbT, R.r - j0), nv = A.nv, r = R.r;
-  const int tid = threadIdx.x;
-  __shared__ double sL[kNbT][kNbT + 1];
-  __shared__ double sx[kMaxV][kNbT];
-  const double* Li = A.dinv + (int64_t(blockIdx.y) * A.dnb + b) * 2 * kNbT * kNbT;
-  for (int e = tid; e < kNbT * kNbT; e += 256) sL[e >> 6][e & 63] = Li[e];
-  for (int e = tid; e < nv * kNbT; e += 256) {
-    const int v = e >> 6, a = e & 63;
-    sx[v][a] = a < nb ? R.B[v * r + j0 + a] : 0.0;
+// ---------------------------------------------------------------------------
+// The blocked triangular solve X = M^{-1} B of every record of a pass in one
+// launch.  Workgroup (record, block j) owns rows 64j .. 64j + 63 of X: it
+// subtracts the products of its row of 64 x 64 blocks of M with the blocks
+// of X it depends on, each as soon as that block is published, multiplies
+// the result by the stored inverse of its diagonal block, writes its block
+// of X and publishes it with a flag (a release at device scope, which the
+// reader acquires).  The workgroups draw (record, block) from a ticket
+// counter in the order in which the blocks become ready, so a workgroup
+// only ever waits on one that has already started, and every wait ends
+// however many workgroups are resident at once.  Each wait is also bounded
+// in time; past the bound (not expected) the workgroup writes NaN in its
+// block, so that the failure shows in the result instead of stalling the
+// device.  Each next block of M is loaded into registers before its wait.
+//   MODE 0: L X = B    (unit lower L of the record's LU; blocks first to last)
+//   MODE 1: U X = B    (upper U; last to first)
+//   MODE 2: U^T X = B  (first to last; U read by columns)
+//   MODE 3: L^T X = B  (last to first; L read by columns)
+// Grid (A.nbm, records), 256 threads; the ordering words are zero at launch.
+// ---------------------------------------------------------------------------
+constexpr long long kWaitTicks = 20000000;  // 0.2 s of the 100 MHz constant clock
+
+__device__ __forceinline__ bool sp_wait_flag(const uint32_t* f) {
+  const long long t0 = wall_clock64();
+  while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+    __builtin_amdgcn_s_sleep(1);
+    if (wall_clock64() - t0 > kWaitTicks) return false;
   }
-  __syncthreads();
-  diag_apply(sL, sx, nv);
-  if (w == 0) {
-    for (int e = tid; e < nv * nb; e += 256) R.X[(e / nb) * r + j0 + e % nb] = sx[e / nb][e % nb];
-    return;
-  }
-  // rows i0 + tid / 4, four threads per row over 16 columns each
-  const int i = i0 + (tid >> 2), part = tid & 3;
-  double acc[kMaxV];
-#pragma unroll
-  for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
-  if (i < r) {
-    const double* lr = R.LU + int64_t(i) * r + j0 + part * 16;
-    double l[16];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) l[c] = part * 16 + c < nb ? lr[c] : 0.0;
-#pragma unroll
-    for (int c = 0; c < 16; ++c)
-#pragma unroll
-      for (int v = 0; v < kMaxV; ++v)
-        if (v < nv) acc[v] += l[c] * sx[v][part * 16 + c];
-  }
-#pragma unroll
-  for (int v = 0; v < kMaxV; ++v) {
-    acc[v] += __shfl_xor(acc[v], 1, 64);
-    acc[v] += __shfl_xor(acc[v], 2, 64);
-  }
-  if (i < r && part == 0)
-#pragma unroll
-    for (int v = 0; v < kMaxV; ++v)
-      if (v < nv) R.B[v * r + i] -= acc[v];
+  return true;
 }
 
-// Block b of x = U^{-1} x (upper U of the LU), blocks visited last to first.
-// Workgroup 0 writes X of the block; workgroup w >= 1 updates B rows
-// 64(w - 1) .. +63 above the block.
-__global__ __launch_bounds__(256) void k_sp_usolve(SpArgs A, int b) {
-  const SpRec R = sp_rec(A, blockIdx.y);
-  const int j0 = b * kNbT;
-  if (j0 >= R.r) return;
-  const int w = blockIdx.x;
-  const int i0 = (w - 1) * kNbT;
-  if (w > 0 && i0 >= j0) return;
-  const int nb = min(kNbT, R.r - j0), nv = A.nv, r = R.r;
-  const int tid = threadIdx.x;
-  __shared__ double sU[kNbT][kNbT + 1];
+template <int MODE>
+__global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
+  constexpr bool kFwd = MODE == 0 || MODE == 2;
+  constexpr bool kTrans = MODE >= 2;
+  constexpr bool kUseU = MODE == 1 || MODE == 2;
+  __shared__ unsigned s_ticket;
+  __shared__ int s_ok;
+  __shared__ double sM[kNbT][kNbT + 1];
   __shared__ double sx[kMaxV][kNbT];
-  const double* Ui = A.dinv + (int64_t(blockIdx.y) * A.dnb + b) * 2 * kNbT * kNbT + kNbT * kNbT;
-  for (int e = tid; e < kNbT * kNbT; e += 256) sU[e >> 6][e & 63] = Ui[e];
-  for (int e = tid; e < nv * kNbT; e += 256) {
-    const int v = e >> 6, a = e & 63;
-    sx[v][a] = a < nb ? R.B[v * r + j0 + a] : 0.0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) {
+    s_ticket = atomicAdd(A.sync, 1u);
+    s_ok = 1;
   }
   __syncthreads();
-  diag_apply(sU, sx, nv);
-  if (w == 0) {
-    for (int e = tid; e < nv * nb; e += 256) R.X[(e / nb) * r + j0 + e % nb] = sx[e / nb][e % nb];
-    return;
-  }
-  const int i = i0 + (tid >> 2), part = tid & 3;
-  double acc[kMaxV];
+  const unsigned t = s_ticket;
+  const int rec = int(t / unsigned(A.nbm)), jj = int(t % unsigned(A.nbm));
+  const SpRec R = sp_rec(A, rec);
+  const int r = R.r, nbk = (r + kNbT - 1) / kNbT;
+  if (jj >= nbk) return;
+  const int j = kFwd ? jj : nbk - 1 - jj;
+  const int j0 = j * kNbT, nb = min(kNbT, r - j0), nv = A.nv;
+  uint32_t* flags = A.sync + 1 + int64_t(rec) * A.nbm;
+  const int ndep = kFwd ? j : nbk - 1 - j;
+  // Element q of a thread is e = tid + 256 q of a 64 x 64 tile at (a, c):
+  // (e / 64, e % 64) for a row-major read, (e % 64, e / 64) for a column
+  // read, so consecutive threads read consecutive addresses either way.
+  double pre[16], dpre[16];
+  auto load_block = [&](int b) {
+    const int b0 = b * kNbT, nbb = min(kNbT, r - b0);
 #pragma unroll
-  for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q, hi = e >> 6, lo = e & 63;
+      const int a = kTrans ? lo : hi, c = kTrans ? hi : lo;
+      pre[q] = (a < nb && c < nbb)
+                   ? (kTrans ? R.LU[int64_t(b0 + c) * r + j0 + a] : R.LU[int64_t(j0 + a) * r + b0 + c])
+                   : 0.0;
+    }
+  };
+  auto store_tile = [&](const double* v) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q, hi = e >> 6, lo = e & 63;
+      sM[kTrans ? lo : hi][kTrans ? hi : lo] = v[q];
+    }
+  };
   {
-    const double* ur = R.LU + int64_t(i) * r + j0 + part * 16;
-    double l[16];
+    // the stored inverse of the diagonal block, row-major; transposed for U^T, L^T
+    const double* Dg = A.dinv + (int64_t(rec) * A.dnb + j) * 2 * kNbT * kNbT + (kUseU ? kNbT * kNbT : 0);
 #pragma unroll
-    for (int c = 0; c < 16; ++c) l[c] = part * 16 + c < nb ? ur[c] : 0.0;
-#pragma unroll
-    for (int c = 0; c < 16; ++c)
-#pragma unroll
-      for (int v = 0; v < kMaxV; ++v)
-        if (v < nv) acc[v] += l[c] * sx[v][part * 16 + c];
+    for (int q = 0; q < 16; ++q) dpre[q] = Dg[tid + 256 * q];
   }
+  double acc[kMaxV / 4];
 #pragma unroll
-  for (int v = 0; v < kMaxV; ++v) {
-    acc[v] += __shfl_xor(acc[v], 1, 64);
-    acc[v] += __shfl_xor(acc[v], 2, 64);
+  for (int q = 0; q < kMaxV / 4; ++q) {
+    const int v = wv + 4 * q;
+    acc[q] = (v < nv && lane < nb) ? R.B[v * r + j0 + lane] : 0.0;
   }
-  if (part == 0)
+  if (ndep > 0) load_block(kFwd ? 0 : nbk - 1);
+  for (int d = 0; d < ndep; ++d) {
+    const int b = kFwd ? d : nbk - 1 - d;
+    if (tid == 0 && !sp_wait_flag(flags + b)) s_ok = 0;
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int b0 = b * kNbT, nbb = min(kNbT, r - b0);
+    for (int e = tid; e < nv * kNbT; e += 256) {
+      const int v = e >> 6, c = e & 63;
+      sx[v][c] = c < nbb ? R.X[v * r + b0 + c] : 0.0;
+    }
+    store_tile(pre);
+    __syncthreads();
+    if (d + 1 < ndep) load_block(kFwd ? d + 1 : nbk - 2 - d);
 #pragma unroll
-    for (int v = 0; v < kMaxV; ++v)
-      if (v < nv) R.B[v * r + i] -= acc[v];
+    for (int q = 0; q < kMaxV / 4; ++q) {
+      const int v = wv + 4 * q;
+      if (v < nv) {
+        double sum = 0.0;
+#pragma unroll 16
+        for (int c = 0; c < kNbT; ++c) sum += sM[lane][c] * sx[v][c];
+        acc[q] -= sum;
+      }
+    }
+    __syncthreads();
+  }
+  store_tile(dpre);
+#pragma unroll
+  for (int q = 0; q < kMaxV / 4; ++q) sx[wv + 4 * q][lane] = acc[q];
+  __syncthreads();
+  const bool ok = s_ok != 0;
+#pragma unroll
+  for (int q = 0; q < kMaxV / 4; ++q) {
+    const int v = wv + 4 * q;
+    if (v < nv && lane < nb) {
+      double y = 0.0;
+#pragma unroll 16
+      for (int c = 0; c < kNbT; ++c) y += sM[lane][c] * sx[v][c];
+      R.X[v * r + j0 + lane] = ok ? y : __builtin_nan("");
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) __hip_atomic_store(flags + j, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace
@@ -1152,13 +1404,18 @@ static bool top_split_solve(const hif_factor_s* H) {
   return H->ntop >= kTopSplitMin && 2 * H->ntop <= H->n;
 }
 
-// The triangular solves of the multi-workgroup path: one launch per 64-row
-// block.
-static void trsv(const SpArgs& P, unsigned nr, int nbk, bool lower, hipStream_t s) {
-  if (lower)
-    for (int b = 0; b < nbk; ++b) hipLaunchKernelGGL(k_sp_lsolve, dim3(unsigned(nbk - b), nr), dim3(256), 0, s, P, b);
+// The blocked triangular solve X = M^{-1} B of every record of a pass, one
+// launch (k_sp_chain); mode as there.
+static void chain(const SpArgs& P, int mode, unsigned nr, hipStream_t s) {
+  const dim3 g(unsigned(P.nbm), nr);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_sp_chain<0>, g, dim3(256), 0, s, P);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_sp_chain<1>, g, dim3(256), 0, s, P);
+  else if (mode == 2)
+    hipLaunchKernelGGL(k_sp_chain<2>, g, dim3(256), 0, s, P);
   else
-    for (int b = nbk - 1; b >= 0; --b) hipLaunchKernelGGL(k_sp_usolve, dim3(unsigned(b + 1), nr), dim3(256), 0, s, P, b);
+    hipLaunchKernelGGL(k_sp_chain<3>, g, dim3(256), 0, s, P);
 }
 
 // The sweeps proper.  work: min(nrhs, 8) * N doubles of scratch, reused by
@@ -1177,29 +1434,74 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
     const int nv = int(std::min<int64_t>(8, nrhs - v0));
     double* u = y + v0 * N;
     double* wk = work;
-    // solve / solve_T of a sub-level go through LDS when a group fits; solve
-    // of few large records is spread over many workgroups per record
+    // solve / solve_T of a sub-level go through LDS when a group fits; the
+    // four sweeps of few large records are spread over many workgroups per
+    // record:
+    //   solve   up:   B = P(u_r - T^T u_s); X = L^{-1} B;   u_s -= L_sr X; u_r = X
+    //           down: B = u_r - U_rs u_s;   X = U^{-1} B;   u_s -= T X;    u_r = X
+    //   solve_T up:   B = u_r - T^T u_s;    X = U^{-T} B;   u_s -= U_rs^T X; u_r = X
+    //           down: B = u_r - L_sr^T u_s; X = L^{-T} B;   u_r = P^T X;   u_s -= T u_r
+    //   apply   up:   B = u_r; u_s += T u_r;      X = U B + U_rs u_s;       u_r = X
+    //           down: B = u_r; u_s += L_sr u_r;   X = L B; u_r = P^T X;     u_r += T^T u_s
+    //   apply_T up:   B = P u_r; u_s += T u_r;    X = L^T B + L_sr^T u_s;   u_r = X
+    //           down: B = u_r; u_s += U_rs^T u_r; X = U^T B; u_r = X;       u_r += T^T u_s
     auto sweep = [&](const SubLevel& sub, int down) {
       SwArgs A{sub.rec.p, sub.iarena.p, sub.darena.p, u, wk, N, nv, op};
-      const bool split = op == 0 && split_solve(sub, N, nv);
-      if (split) {
-        HIF_REQUIRE(sub.dinv.p, HIF_EDEVICE, "the diagonal-block inverses of a sub-level were not built");
+      if (split_solve(sub, N, nv)) {
+        HIF_REQUIRE(sub.dinv.p && H->sync.p, HIF_EDEVICE,
+                    "the diagonal-block inverses of a sub-level were not built");
         SpArgs P{sub.rec.p,  sub.iarena.p, sub.darena.p, sub.woff.p, u, wk, wk + nv * sub.sum_r, N, nv,
                  sub.dinv.p, sub.dinv_nb};
+        P.sync = H->sync.p;
+        P.nbm = (sub.max_r + kNbT - 1) / kNbT;
         const unsigned nr = unsigned(sub.nrec);
-        const int nbk = (sub.max_r + kNbT - 1) / kNbT;
         const dim3 gr(unsigned((sub.max_r + 255) / 256), nr), gu(unsigned((sub.max_r + 63) / 64), nr);
-        const dim3 gs(unsigned((sub.max_k + 15) / 16), nr);
-        if (!down) {
-          hipLaunchKernelGGL(k_sp_up_first, gu, dim3(256), 0, s, P);
-          trsv(P, nr, nbk, true, s);
-          if (sub.max_k > 0) hipLaunchKernelGGL(k_sp_skel_update, gs, dim3(256), 0, s, P, 0);
+        const dim3 gw(unsigned((sub.max_r + 15) / 16), nr);
+        const dim3 gs(unsigned((sub.max_k + 15) / 16), nr), gt(unsigned((sub.max_k + 63) / 64), nr);
+        const bool sk = sub.max_k > 0;
+        if (op == 0 && !down) {
+          hipLaunchKernelGGL((k_sp_first_cols<false, true>), gu, dim3(256), 0, s, P);
+          chain(P, 0, nr, s);
+          if (sk) hipLaunchKernelGGL(k_sp_skel_update<false>, gs, dim3(256), 0, s, P, 0, -1.0);
+          hipLaunchKernelGGL(k_sp_scatter<false>, gr, dim3(256), 0, s, P, 0);
+        } else if (op == 0) {
+          hipLaunchKernelGGL(k_sp_down_first, gw, dim3(256), 0, s, P);
+          chain(P, 1, nr, s);
+          if (sk) hipLaunchKernelGGL(k_sp_skel_update<false>, gs, dim3(256), 0, s, P, 1, -1.0);
+          hipLaunchKernelGGL(k_sp_scatter<false>, gr, dim3(256), 0, s, P, 0);
+        } else if (op == 1 && !down) {
+          hipLaunchKernelGGL((k_sp_first_cols<false, false>), gu, dim3(256), 0, s, P);
+          chain(P, 2, nr, s);
+          if (sk) hipLaunchKernelGGL(k_sp_skel_update_T<false>, gt, dim3(256), 0, s, P, -1.0);
+          hipLaunchKernelGGL(k_sp_scatter<false>, gr, dim3(256), 0, s, P, 0);
+        } else if (op == 1) {
+          hipLaunchKernelGGL((k_sp_first_cols<true, false>), gu, dim3(256), 0, s, P);
+          chain(P, 3, nr, s);
+          hipLaunchKernelGGL(k_sp_scatter<true>, gr, dim3(256), 0, s, P, 0);
+          if (sk) hipLaunchKernelGGL(k_sp_skel_update<true>, gs, dim3(256), 0, s, P, 1, -1.0);
+        } else if (op == 2 && !down) {
+          hipLaunchKernelGGL(k_sp_gather<false>, gr, dim3(256), 0, s, P);
+          if (sk) hipLaunchKernelGGL(k_sp_skel_update<true>, gs, dim3(256), 0, s, P, 1, 1.0);
+          hipLaunchKernelGGL((k_sp_rowmv<0, true>), gw, dim3(256), 0, s, P, 0);
+          hipLaunchKernelGGL(k_sp_scatter<false>, gr, dim3(256), 0, s, P, 0);
+        } else if (op == 2) {
+          hipLaunchKernelGGL(k_sp_gather<false>, gr, dim3(256), 0, s, P);
+          if (sk) hipLaunchKernelGGL(k_sp_skel_update<true>, gs, dim3(256), 0, s, P, 0, 1.0);
+          hipLaunchKernelGGL((k_sp_rowmv<1, false>), gw, dim3(256), 0, s, P, 0);
+          hipLaunchKernelGGL(k_sp_scatter<true>, gr, dim3(256), 0, s, P, 0);
+          if (sk) hipLaunchKernelGGL((k_sp_first_cols<false, false, true>), gu, dim3(256), 0, s, P);
+        } else if (!down) {
+          hipLaunchKernelGGL(k_sp_gather<true>, gr, dim3(256), 0, s, P);
+          if (sk) hipLaunchKernelGGL(k_sp_skel_update<true>, gs, dim3(256), 0, s, P, 1, 1.0);
+          hipLaunchKernelGGL((k_sp_colmv<2, true>), gu, dim3(256), 0, s, P, 0);
+          hipLaunchKernelGGL(k_sp_scatter<false>, gr, dim3(256), 0, s, P, 0);
         } else {
-          hipLaunchKernelGGL(k_sp_down_first, dim3(unsigned((sub.max_r + 15) / 16), nr), dim3(256), 0, s, P);
-          trsv(P, nr, nbk, false, s);
-          if (sub.max_k > 0) hipLaunchKernelGGL(k_sp_skel_update, gs, dim3(256), 0, s, P, 1);
+          hipLaunchKernelGGL(k_sp_gather<false>, gr, dim3(256), 0, s, P);
+          if (sk) hipLaunchKernelGGL(k_sp_skel_update_T<true>, gt, dim3(256), 0, s, P, 1.0);
+          hipLaunchKernelGGL((k_sp_colmv<3, false>), gu, dim3(256), 0, s, P, 0);
+          hipLaunchKernelGGL(k_sp_scatter<false>, gr, dim3(256), 0, s, P, 0);
+          if (sk) hipLaunchKernelGGL((k_sp_first_cols<false, false, true>), gu, dim3(256), 0, s, P);
         }
-        hipLaunchKernelGGL(k_sp_scatter, gr, dim3(256), 0, s, P);
         return;
       }
       if (op <= 1 && sub.max_2rk <= kCapL) {
@@ -1226,24 +1528,46 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
     };
     for (auto& sub : H->subs)
       if (sub.nrec > 0) sweep(sub, 0);
-    // A top block too large for LDS is solved like a large record with no
-    // skeleton (k = 0): the same blocked triangular solves spread over many
-    // workgroups, with the up pass (P, L^{-1}) and the down pass (U^{-1}).
-    const bool top_split = op == 0 && top_split_solve(H);
+    // A top block too large for LDS is swept like a large record with no
+    // skeleton (k = 0), through the same chained triangular solves and
+    // products: solve X = U^{-1} L^{-1} P u, solve_T X = P^T L^{-T} U^{-T} u,
+    // apply X = P^T L U u, apply_T X = U^T L^T P u.
+    const bool top_split = top_split_solve(H);
     if (top_split) {
       const int r = int(H->ntop);
-      HIF_REQUIRE(H->top_rec.p && H->top_dinv.p, HIF_EDEVICE,
+      HIF_REQUIRE(H->top_rec.p && H->top_dinv.p && H->sync.p, HIF_EDEVICE,
                   "the top block's solve record was not built with the factors");
       const int nbk = (r + kNbT - 1) / kNbT;
       SpArgs P{H->top_rec.p, H->top_iarena.p, H->top_lu.p,  H->top_woff.p, u, wk, wk + int64_t(nv) * r, N, nv,
                H->top_dinv.p, nbk};
-      const dim3 gr(unsigned((r + 255) / 256), 1);
-      hipLaunchKernelGGL(k_sp_up_first, dim3(unsigned((r + 63) / 64), 1), dim3(256), 0, s, P);
-      trsv(P, 1, nbk, true, s);
-      hipLaunchKernelGGL(k_sp_scatter, gr, dim3(256), 0, s, P);
-      hipLaunchKernelGGL(k_sp_down_first, dim3(unsigned((r + 15) / 16), 1), dim3(256), 0, s, P);
-      trsv(P, 1, nbk, false, s);
-      hipLaunchKernelGGL(k_sp_scatter, gr, dim3(256), 0, s, P);
+      P.sync = H->sync.p;
+      P.nbm = nbk;
+      const dim3 gr(unsigned((r + 255) / 256), 1), gu(unsigned((r + 63) / 64), 1), gw(unsigned((r + 15) / 16), 1);
+      if (op == 0) {
+        hipLaunchKernelGGL((k_sp_first_cols<false, true>), gu, dim3(256), 0, s, P);
+        chain(P, 0, 1, s);
+        hipLaunchKernelGGL(k_sp_scatter<false>, gr, dim3(256), 0, s, P, 0);
+        hipLaunchKernelGGL(k_sp_down_first, gw, dim3(256), 0, s, P);
+        chain(P, 1, 1, s);
+        hipLaunchKernelGGL(k_sp_scatter<false>, gr, dim3(256), 0, s, P, 0);
+      } else if (op == 1) {
+        hipLaunchKernelGGL((k_sp_first_cols<false, false>), gu, dim3(256), 0, s, P);
+        chain(P, 2, 1, s);
+        hipLaunchKernelGGL(k_sp_scatter<false>, gr, dim3(256), 0, s, P, 0);
+        hipLaunchKernelGGL((k_sp_first_cols<true, false>), gu, dim3(256), 0, s, P);
+        chain(P, 3, 1, s);
+        hipLaunchKernelGGL(k_sp_scatter<true>, gr, dim3(256), 0, s, P, 0);
+      } else if (op == 2) {
+        hipLaunchKernelGGL(k_sp_gather<false>, gr, dim3(256), 0, s, P);
+        hipLaunchKernelGGL((k_sp_rowmv<0, false>), gw, dim3(256), 0, s, P, 0);
+        hipLaunchKernelGGL((k_sp_rowmv<1, false>), gw, dim3(256), 0, s, P, 1);
+        hipLaunchKernelGGL(k_sp_scatter<true>, gr, dim3(256), 0, s, P, 1);
+      } else {
+        hipLaunchKernelGGL(k_sp_gather<true>, gr, dim3(256), 0, s, P);
+        hipLaunchKernelGGL((k_sp_colmv<2, false>), gu, dim3(256), 0, s, P, 0);
+        hipLaunchKernelGGL((k_sp_colmv<3, false>), gu, dim3(256), 0, s, P, 1);
+        hipLaunchKernelGGL(k_sp_scatter<false>, gr, dim3(256), 0, s, P, 1);
+      }
     } else if (H->ntop > 0) {
       if (op <= 1 && 2 * H->ntop <= kCapL)
         hipLaunchKernelGGL(k_top_lds, dim3(1), dim3(1024), 0, s, H->top_lu.p, H->top_perm.p, int(H->ntop),
@@ -1277,6 +1601,13 @@ static void build_dinv(hif_factor_s* H, hipStream_t s) {
 
 void prepare_sweeps(hif_factor_s* H, hipStream_t s) {
   build_dinv(H, s);
+  // ordering words of the chained triangular solves: a ticket counter and
+  // one flag per 64-row block of the largest pass
+  size_t words = 0;
+  for (const SubLevel& sub : H->subs)
+    if (sub.dinv.p) words = std::max(words, size_t(sub.nrec) * size_t((sub.max_r + kNbT - 1) / kNbT));
+  if (top_split_solve(H)) words = std::max(words, size_t((H->ntop + kNbT - 1) / kNbT));
+  if (words > 0 && H->sync.n < 1 + words) H->sync.alloc(1 + words, &H->mem);
   if (!top_split_solve(H) || H->top_rec.p) return;
   const int r = int(H->ntop);
   H->top_iarena.alloc(size_t(3) * r, &H->mem);

@@ -394,6 +394,38 @@ def test_free_waits_for_its_own_work_only():
     assert torch.isfinite(u).all()
 
 
+@pytest.mark.parametrize("name", ["sq512", "cube32"])
+def test_four_sweeps_inverse_and_adjoint_identities(name):
+    # The four sweeps of the 512 x 512 factorization (its large redundant
+    # blocks run through the multi-workgroup path) and of 32^3 (its top block
+    # too), checked by identities that hold at any size: F^{-1} (F x) = x,
+    # F^{-T} (F^T x) = x, <F^T x, y> = <x, F y> and <F^{-T} x, y> = <x, F^{-1} y>
+    # (Lemma 2.4: the factors of F and of F^{-1} are inverse to each other
+    # factor by factor).  9 right-hand sides: one pass of 8 and one of 1.
+    wl = workload(name)
+    P = _t(wl.points())
+    a = torch.ones(wl.N, dtype=torch.float64, device=DEV)
+    F = hif.factor(P, wl.eps, wl.leaf, a=a, h=wl.h)
+    rng = np.random.default_rng(61)
+    x = _t(rng.standard_normal((9, wl.N)))
+    y = _t(rng.standard_normal((9, wl.N)))
+    for fwd, inv in ((F.apply, F.solve), (F.apply_T, F.solve_T)):
+        e = (torch.linalg.norm(inv(fwd(x)) - x, dim=1) / torch.linalg.norm(x, dim=1)).max().item()
+        assert e <= 1e-10, (name, e)
+    for tr, op in ((F.apply_T, F.apply), (F.solve_T, F.solve)):
+        lhs = (tr(x) * y).sum(dim=1)
+        Oy = op(y)
+        rhs = (x * Oy).sum(dim=1)
+        scale = torch.linalg.norm(x, dim=1) * torch.linalg.norm(Oy, dim=1)
+        assert ((lhs - rhs).abs() / scale).max().item() <= 1e-12, name
+    # in place, one right-hand side: the same result as out of place
+    for op in (F.apply, F.apply_T, F.solve, F.solve_T):
+        z = x[:1].clone()
+        op(z, out=z)
+        assert torch.equal(z, op(x[:1])), name
+    F.free()
+
+
 def test_factor_deterministic():
     op = _op(32, 2)
     x = _t(np.random.default_rng(2).standard_normal(op.N))
