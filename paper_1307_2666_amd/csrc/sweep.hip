@@ -605,6 +605,71 @@ __device__ __forceinline__ void l_solve_LT(const double* __restrict__ LU, int n,
   }
 }
 
+// x = M x through the scratch tp (both [nv][n] in LDS), M a triangle of the
+// row-major n x n LU: mode 0 U (columns j >= i), 1 the unit lower L (x_i plus
+// columns j < i), both one wave per row; mode 2 the unit upper L^T (x_i plus
+// rows j > i of L), 3 U^T (rows j <= i of U), both one thread per column.
+__device__ __forceinline__ void l_trmv(const double* __restrict__ LU, int n, double* x, double* tp, int nv, int mode) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  if (mode <= 1) {
+    for (int i = wv; i < n; i += nw) {
+      const double* mr = LU + int64_t(i) * n;
+      const int jb = mode == 0 ? i : 0, je = mode == 0 ? n : i;
+      double acc[kMaxV];
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+      for (int j0 = jb; j0 < je; j0 += 64 * kU) {
+        double mv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int j = j0 + u * 64 + lane;
+          mv[u] = j < je ? mr[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int j = j0 + u * 64 + lane;
+          if (j < je) {
+#pragma unroll
+            for (int v = 0; v < kMaxV; ++v)
+              if (v < nv) acc[v] += mv[u] * x[v * n + j];
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v)
+        if (v < nv) {
+          const double t = wave_sum(acc[v]);
+          if (lane == 0) tp[v * n + i] = t + (mode == 1 ? x[v * n + i] : 0.0);
+        }
+    }
+  } else {
+    for (int i = tid; i < n; i += blockDim.x) {
+      const int jb = mode == 2 ? i + 1 : 0, je = mode == 2 ? n : i + 1;
+      double acc[kMaxV];
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+      for (int j0 = jb; j0 < je; j0 += kU) {
+        double mv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) mv[u] = j0 + u < je ? LU[int64_t(j0 + u) * n + i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (j0 + u < je) {
+#pragma unroll
+            for (int v = 0; v < kMaxV; ++v)
+              if (v < nv) acc[v] += mv[u] * x[v * n + j0 + u];
+          }
+      }
+#pragma unroll
+      for (int v = 0; v < kMaxV; ++v)
+        if (v < nv) tp[v * n + i] = acc[v] + (mode == 2 ? x[v * n + i] : 0.0);
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nv * n; e += blockDim.x) x[e] = tp[e];
+  __syncthreads();
+}
+
 // x = P x (fwd) or P^T x through the scratch tp, both [nv][n] in LDS.
 __device__ __forceinline__ void l_permute(const int32_t* perm, int n, double* x, double* tp, int nv, bool fwd) {
   for (int e = threadIdx.x; e < nv * n; e += blockDim.x) {
@@ -619,7 +684,8 @@ __device__ __forceinline__ void l_permute(const int32_t* perm, int n, double* x,
   __syncthreads();
 }
 
-// One group per workgroup of BS threads; op 0 solve, 1 solve_T; down = 0 for
+// One group per workgroup of BS threads; op 0 solve, 1 solve_T, 2 apply,
+// 3 apply_T (the per-group steps in the header of this file); down = 0 for
 // the upward sweep (finest sub-level first), 1 for the downward one.  The LDS
 // holds cap doubles (sized by the launch to the sub-level's largest record);
 // the caller guarantees 2r + k <= cap.
@@ -658,17 +724,39 @@ __global__ __launch_bounds__(BS) void k_sweep_lds(SwArgs A, int down, int cap) {
       __syncthreads();
       l_solve_U(LU, r, xr, r, nv);                                 // u_r = U^{-1} u_r
       if (k > 0) l_gemv_n(T, k, r, r, xr, r, xs, k, nv, -1.0);    // u_s -= T u_r
-    } else if (!down) {
+    } else if (A.op == 1 && !down) {
       if (k > 0) l_gemv_t(T, k, r, r, xs, k, xr, r, nv, -1.0);    // u_r -= T^T u_s
       __syncthreads();
       l_solve_UT(LU, r, xr, r, nv);                                // u_r = U^{-T} u_r
       if (k > 0) l_gemv_t(Urs, r, k, k, xr, r, xs, k, nv, -1.0);  // u_s -= U_rs^T u_r
-    } else {
+    } else if (A.op == 1) {
       if (k > 0) l_gemv_t(Lsr, k, r, r, xs, k, xr, r, nv, -1.0);  // u_r -= L_sr^T u_s
       __syncthreads();
       l_solve_LT(LU, r, xr, r, nv);                                // u_r = L^{-T} u_r
       l_permute(perm, r, xr, tp, nv, false);                       // u_r = P^T u_r
       if (k > 0) l_gemv_n(T, k, r, r, xr, r, xs, k, nv, -1.0);    // u_s -= T u_r
+    } else if (A.op == 2 && !down) {
+      if (k > 0) l_gemv_n(T, k, r, r, xr, r, xs, k, nv, 1.0);     // x_s += T x_r
+      __syncthreads();
+      l_trmv(LU, r, xr, tp, nv, 0);                                // x_r = U x_r
+      if (k > 0) l_gemv_n(Urs, r, k, k, xs, k, xr, r, nv, 1.0);   //     + U_rs x_s
+    } else if (A.op == 2) {
+      if (k > 0) l_gemv_n(Lsr, k, r, r, xr, r, xs, k, nv, 1.0);   // y_s += L_sr y_r
+      __syncthreads();
+      l_trmv(LU, r, xr, tp, nv, 1);                                // y_r = L y_r
+      l_permute(perm, r, xr, tp, nv, false);                       // y_r = P^T y_r
+      if (k > 0) l_gemv_t(T, k, r, r, xs, k, xr, r, nv, 1.0);     // y_r += T^T y_s
+    } else if (!down) {
+      if (k > 0) l_gemv_n(T, k, r, r, xr, r, xs, k, nv, 1.0);     // x_s += T x_r
+      __syncthreads();
+      l_permute(perm, r, xr, tp, nv, true);                        // x_r = P x_r
+      l_trmv(LU, r, xr, tp, nv, 2);                                // x_r = L^T x_r
+      if (k > 0) l_gemv_t(Lsr, k, r, r, xs, k, xr, r, nv, 1.0);   //     + L_sr^T x_s
+    } else {
+      if (k > 0) l_gemv_t(Urs, r, k, k, xr, r, xs, k, nv, 1.0);   // y_s += U_rs^T y_r
+      __syncthreads();
+      l_trmv(LU, r, xr, tp, nv, 3);                                // y_r = U^T y_r
+      if (k > 0) l_gemv_t(T, k, r, r, xs, k, xr, r, nv, 1.0);     // y_r += T^T y_s
     }
     __syncthreads();
     for (int e = tid; e < nv * r; e += BS) u[(e / r) * N + rd[e % r]] = xr[e];
@@ -677,7 +765,8 @@ __global__ __launch_bounds__(BS) void k_sweep_lds(SwArgs A, int down, int cap) {
   }
 }
 
-// Top block: x = A_L^{-1} x (op 0) or A_L^{-T} x (op 1); requires 2n <= kCapL.
+// Top block: x = A_L^{-1} x (op 0), A_L^{-T} x (op 1), A_L x (op 2) or
+// A_L^T x (op 3) with A_L = P^T L U; requires 2n <= kCapL.
 __global__ __launch_bounds__(1024) void k_top_lds(const double* LU, const int32_t* perm, int n, const int32_t* idx,
                                                   double* u, int64_t N, int nrhs, int op) {
   __shared__ double sm[kCapL];
@@ -694,10 +783,18 @@ __global__ __launch_bounds__(1024) void k_top_lds(const double* LU, const int32_
       l_permute(perm, n, x, tp, nv, true);
       l_solve_L(LU, n, x, n, nv);
       l_solve_U(LU, n, x, n, nv);
-    } else {
+    } else if (op == 1) {
       l_solve_UT(LU, n, x, n, nv);
       l_solve_LT(LU, n, x, n, nv);
       l_permute(perm, n, x, tp, nv, false);
+    } else if (op == 2) {
+      l_trmv(LU, n, x, tp, nv, 0);
+      l_trmv(LU, n, x, tp, nv, 1);
+      l_permute(perm, n, x, tp, nv, false);
+    } else {
+      l_permute(perm, n, x, tp, nv, true);
+      l_trmv(LU, n, x, tp, nv, 2);
+      l_trmv(LU, n, x, tp, nv, 3);
     }
     for (int e = tid; e < nv * n; e += B) uu[(e / n) * N + idx[e % n]] = x[e];
     __syncthreads();
@@ -1391,11 +1488,21 @@ static void allow_large_lds() {
   });
 }
 
-// Sub-levels whose solve runs through the multi-workgroup path for nv
+// Sub-levels whose sweeps run through the multi-workgroup path for nv
 // right-hand sides per pass: records too large for LDS with all of them, or
-// few large records.
+// few records (at most kSplitMaxRecords) of at least kSplitMinR redundant
+// unknowns, which one workgroup each would leave most of the chip idle.
+#ifndef HIF_SPLIT_MAX_RECORDS
+#define HIF_SPLIT_MAX_RECORDS 64
+#endif
+#ifndef HIF_SPLIT_MIN_R
+#define HIF_SPLIT_MIN_R 256
+#endif
+constexpr int kSplitMaxRecords = HIF_SPLIT_MAX_RECORDS;
+constexpr int kSplitMinR = HIF_SPLIT_MIN_R;
 static bool split_solve(const SubLevel& sub, int64_t N, int nv) {
-  return 2 * sub.sum_r <= N && (int64_t(sub.max_2rk) * nv > kCapL || (sub.nrec <= 64 && sub.max_r >= 256));
+  return 2 * sub.sum_r <= N &&
+         (int64_t(sub.max_2rk) * nv > kCapL || (sub.nrec <= kSplitMaxRecords && sub.max_r >= kSplitMinR));
 }
 
 // A top block too large for LDS is solved like a large record with no
@@ -1504,7 +1611,7 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
         }
         return;
       }
-      if (op <= 1 && sub.max_2rk <= kCapL) {
+      if (sub.max_2rk <= kCapL) {
         allow_large_lds();
         // LDS for as many right-hand sides per pass as fit (all of them when
         // the records are small); 1024 threads per record when the records
@@ -1569,7 +1676,7 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
         hipLaunchKernelGGL(k_sp_scatter<false>, gr, dim3(256), 0, s, P, 1);
       }
     } else if (H->ntop > 0) {
-      if (op <= 1 && 2 * H->ntop <= kCapL)
+      if (2 * H->ntop <= kCapL)
         hipLaunchKernelGGL(k_top_lds, dim3(1), dim3(1024), 0, s, H->top_lu.p, H->top_perm.p, int(H->ntop),
                            H->top_idx.p, u, N, nv, op);
       else
