@@ -1345,9 +1345,12 @@ __global__ __launch_bounds__(64) void k_sp_dinv(SpArgs A, double* dinv) {
 // ---------------------------------------------------------------------------
 constexpr long long kWaitTicks = 20000000;  // 0.2 s of the 100 MHz constant clock
 
+// Polls with relaxed device-scope loads, which are coherent across the chip
+// and invalidate no cache (an acquiring poll would invalidate this XCD's L2
+// on every try); the caller acquires once the flag is seen.
 __device__ __forceinline__ bool sp_wait_flag(const uint32_t* f) {
   const long long t0 = wall_clock64();
-  while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
     __builtin_amdgcn_s_sleep(1);
     if (wall_clock64() - t0 > kWaitTicks) return false;
   }
@@ -1417,7 +1420,7 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
     const int b = kFwd ? d : nbk - 1 - d;
     if (tid == 0 && !sp_wait_flag(flags + b)) s_ok = 0;
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every wave, before it reads X_b
     const int b0 = b * kNbT, nbb = min(kNbT, r - b0);
     for (int e = tid; e < nv * kNbT; e += 256) {
       const int v = e >> 6, c = e & 63;
@@ -1453,7 +1456,9 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
       R.X[v * r + j0 + lane] = ok ? y : __builtin_nan("");
     }
   }
-  __threadfence();
+  // every wave releases its own stores of X (the barrier alone does not wait
+  // for them), then one thread sets the flag
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (tid == 0) __hip_atomic_store(flags + j, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
