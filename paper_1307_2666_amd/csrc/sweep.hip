@@ -1418,13 +1418,16 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
   if (ndep > 0) load_block(kFwd ? 0 : nbk - 1);
   for (int d = 0; d < ndep; ++d) {
     const int b = kFwd ? d : nbk - 1 - d;
-    if (tid == 0 && !sp_wait_flag(flags + b)) s_ok = 0;
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every wave, before it reads X_b
-    const int b0 = b * kNbT, nbb = min(kNbT, r - b0);
-    for (int e = tid; e < nv * kNbT; e += 256) {
-      const int v = e >> 6, c = e & 63;
-      sx[v][c] = c < nbb ? R.X[v * r + b0 + c] : 0.0;
+    // wave 0 waits, acquires and stages X_b in LDS (one cache invalidation
+    // per block); the other waves store the prefetched tile meanwhile
+    if (wv == 0) {
+      if (lane == 0 && !sp_wait_flag(flags + b)) s_ok = 0;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int b0 = b * kNbT, nbb = min(kNbT, r - b0);
+      for (int e = lane; e < nv * kNbT; e += 64) {
+        const int v = e >> 6, c = e & 63;
+        sx[v][c] = c < nbb ? R.X[v * r + b0 + c] : 0.0;
+      }
     }
     store_tile(pre);
     __syncthreads();
@@ -1446,21 +1449,29 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
   for (int q = 0; q < kMaxV / 4; ++q) sx[wv + 4 * q][lane] = acc[q];
   __syncthreads();
   const bool ok = s_ok != 0;
+  double y[kMaxV / 4];
 #pragma unroll
   for (int q = 0; q < kMaxV / 4; ++q) {
     const int v = wv + 4 * q;
-    if (v < nv && lane < nb) {
-      double y = 0.0;
+    y[q] = 0.0;
+    if (v < nv)
 #pragma unroll 16
-      for (int c = 0; c < kNbT; ++c) y += sM[lane][c] * sx[v][c];
-      R.X[v * r + j0 + lane] = ok ? y : __builtin_nan("");
-    }
+      for (int c = 0; c < kNbT; ++c) y[q] += sM[lane][c] * sx[v][c];
   }
-  // every wave releases its own stores of X (the barrier alone does not wait
-  // for them), then one thread sets the flag
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  if (tid == 0) __hip_atomic_store(flags + j, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+  for (int q = 0; q < kMaxV / 4; ++q) sx[wv + 4 * q][lane] = ok ? y[q] : __builtin_nan("");
+  __syncthreads();
+  // wave 0 writes the block, releases it (one write-back of its XCD's L2)
+  // and sets the flag
+  if (wv == 0) {
+    for (int e = lane; e < nv * nb; e += 64) {
+      const int v = e / nb, a = e - v * nb;
+      R.X[v * r + j0 + a] = sx[v][a];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) __hip_atomic_store(flags + j, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 }  // namespace
