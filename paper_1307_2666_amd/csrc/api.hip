@@ -90,15 +90,24 @@ DbufCache& dbuf_cache() {
 }
 }  // namespace
 
-void* dbuf_take(size_t cls, hipStream_t s) {
+void* dbuf_take(size_t& cls, hipStream_t s) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
   DbufCache& c = dbuf_cache();
   std::lock_guard<std::mutex> lk(c.mu);
-  auto it = c.blocks.find(CacheKey{dev, s, cls});
-  if (it == c.blocks.end()) it = c.blocks.find(CacheKey{dev, dbuf_idle_key(), cls});  // idle blocks serve any stream
+  // the smallest cached block of at least cls bytes, up to a quarter more
+  // (classes above 1 MiB are sixteenths of a power of two apart; smaller
+  // ones are powers of two, so for them this is the exact class)
+  auto fit = [&](hipStream_t key) {
+    auto it = c.blocks.lower_bound(CacheKey{dev, key, cls});
+    const bool ok = it != c.blocks.end() && it->first.dev == dev && it->first.s == key && it->first.cls <= cls + cls / 4;
+    return ok ? it : c.blocks.end();
+  };
+  auto it = fit(s);
+  if (it == c.blocks.end()) it = fit(dbuf_idle_key());  // idle blocks serve any stream
   if (it == c.blocks.end()) return nullptr;
   void* p = it->second;
+  cls = it->first.cls;
   c.blocks.erase(it);
   c.bytes -= cls;
   return p;
@@ -112,7 +121,10 @@ void dbuf_trim() {
     std::lock_guard<std::mutex> lk(c.mu);
     for (auto it = c.blocks.begin(); it != c.blocks.end();) {
       if (it->first.dev == dev) {
-        (void)hipFreeAsync(it->second, it->first.s == dbuf_idle_key() ? nullptr : it->first.s);
+        if (it->first.cls >= kDbufDirectBytes)
+          (void)hipFree(it->second);
+        else
+          (void)hipFreeAsync(it->second, it->first.s == dbuf_idle_key() ? nullptr : it->first.s);
         c.bytes -= it->first.cls;
         it = c.blocks.erase(it);
       } else {
@@ -126,15 +138,14 @@ void dbuf_trim() {
   (void)hipGetLastError();
 }
 
-void dbuf_drop_stream(hipStream_t s) {
+void dbuf_retire_stream(hipStream_t s) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return;
   DbufCache& c = dbuf_cache();
   std::lock_guard<std::mutex> lk(c.mu);
   for (auto it = c.blocks.begin(); it != c.blocks.end();) {
     if (it->first.dev == dev && it->first.s == s) {
-      (void)hipFreeAsync(it->second, s);
-      c.bytes -= it->first.cls;
+      c.blocks.emplace(CacheKey{dev, dbuf_idle_key(), it->first.cls}, it->second);
       it = c.blocks.erase(it);
     } else {
       ++it;
@@ -383,8 +394,7 @@ static hif_status factor_batch_fused(const hif_problem* problems, int32_t count,
   }
   (void)hipStreamSynchronize(s);
   release_thread_streams();
-  dbuf_drop_stream(s);
-  (void)hipStreamSynchronize(s);
+  dbuf_retire_stream(s);
   (void)hipStreamDestroy(s);
   return HIF_OK;
 }
@@ -448,11 +458,11 @@ static hif_status factor_batch(const hif_problem* problems, int32_t count, const
       out[p] = h;
     }
     // every handle's device work is complete when the batch returns; the
-    // thread's streams and the blocks cached for them go back to the device
+    // thread's streams are destroyed and the blocks cached for them become
+    // idle blocks that any stream may take
     (void)hipStreamSynchronize(s);
     release_thread_streams();
-    dbuf_drop_stream(s);
-    (void)hipStreamSynchronize(s);
+    dbuf_retire_stream(s);
     (void)hipStreamDestroy(s);
   };
   {
@@ -535,8 +545,7 @@ hif_status hif_solve_graph(hif_handle h, const double* f, double* u, int64_t nrh
   hif_status st = g ? guarded(cs, [&] { graph_solve_impl(h, f, u, nrhs, cs, &g->graph, &g->exec); })
                     : fail(HIF_ENOMEM, "host allocation failed");
   (void)hipStreamSynchronize(cs);
-  dbuf_drop_stream(cs);
-  (void)hipStreamSynchronize(cs);
+  dbuf_retire_stream(cs);
   (void)hipStreamDestroy(cs);
   if (st == HIF_OK) *out = g.release();
   return st;

@@ -1557,6 +1557,7 @@ void release_thread_streams() {
   for (auto& kv : streams) {
     (void)hipSetDevice(kv.first);
     (void)hipStreamSynchronize(kv.second.s2);
+    dbuf_retire_stream(kv.second.s2);
     (void)hipEventDestroy(kv.second.ev_fact);
     (void)hipEventDestroy(kv.second.ev_rest);
     (void)hipStreamDestroy(kv.second.s2);

@@ -82,13 +82,22 @@ void dbuf_pool_setup();  // once per device: keep freed memory in the pool
 // the block's last use; it saves the allocator's per-call host cost between
 // the host's waits on the device.  Blocks released as idle (ReleaseIdle) are
 // kept in a section any stream may take from.  At most kDbufCacheBytes stay
-// cached (per process); beyond that blocks go back to the pool.
-// Blocks of kDbufDirectBytes or more bypass both (plain hipMalloc / hipFree):
-// few and large, they would otherwise stay reserved in the pool.
-constexpr size_t kDbufCacheBytes = size_t(16) << 30;
+// cached (per process); beyond that blocks go back to the pool, whose host
+// cost per call grows with the blocks it has seen, so the cap is sized to
+// hold a whole batch factorization's working set (its largest blocks alone
+// take about 16 GiB for 48 problems of up to 256 x 256): 64 GiB, under a
+// quarter of the 288 GB of an MI355X.  An allocation the device cannot serve returns
+// every cached block first (dbuf_trim) and tries again.
+// Blocks of kDbufDirectBytes or more bypass the pool (plain hipMalloc /
+// hipFree: few and large, they would otherwise stay reserved in it) but not
+// the cache: mapping and unmapping them takes the host up to hundreds of
+// milliseconds once device memory is fragmented, so they are kept for reuse
+// like the others and freed only when the cache is full or trimmed.
+constexpr size_t kDbufCacheBytes = size_t(64) << 30;
 constexpr size_t kDbufDirectBytes = size_t(1) << 30;
 size_t dbuf_class(size_t bytes);                  // allocation size for a request
-void* dbuf_take(size_t cls, hipStream_t s);       // cached block or nullptr
+// cached block of at least cls bytes (cls becomes its size) or nullptr
+void* dbuf_take(size_t& cls, hipStream_t s);
 bool dbuf_give(void* p, size_t cls, hipStream_t s);  // true if cached
 void dbuf_trim();  // return every cached and pooled free block to the device
 struct StreamScope {
@@ -119,10 +128,12 @@ struct DBuf {
   ~DBuf() { release(); }
   void release() {
     if (p) {
-      if (cls >= kDbufDirectBytes)
-        (void)hipFree(p);
-      else if (!dbuf_give(p, cls, dbuf_idle() ? dbuf_idle_key() : dbuf_stream()))
-        (void)hipFreeAsync(p, dbuf_stream());
+      if (!dbuf_give(p, cls, dbuf_idle() ? dbuf_idle_key() : dbuf_stream())) {
+        if (cls >= kDbufDirectBytes)
+          (void)hipFree(p);
+        else
+          (void)hipFreeAsync(p, dbuf_stream());
+      }
       if (mt) mt->held -= n * sizeof(T);
     }
     p = nullptr;
@@ -136,8 +147,8 @@ struct DBuf {
     size_t bytes = cnt * sizeof(T);
     if (mt && mt->cap && mt->held + bytes > mt->cap)
       throw Error{HIF_ENOMEM, "device memory cap (opts.max_bytes) exceeded"};
-    const size_t c = dbuf_class(bytes);
-    p = c >= kDbufDirectBytes ? nullptr : static_cast<T*>(dbuf_take(c, dbuf_stream()));
+    size_t c = dbuf_class(bytes);
+    p = static_cast<T*>(dbuf_take(c, dbuf_stream()));
     if (!p) {
       auto get = [&]() {
         return c >= kDbufDirectBytes ? hipMalloc((void**)&p, c) : hipMallocAsync((void**)&p, c, dbuf_stream());
@@ -384,9 +395,12 @@ void gmres_impl(hif_factor_s* H, const double* f, double* u, int64_t nrhs, doubl
                 int32_t* iters, double* relres, bool trans, hipStream_t s);
 
 // Batch workers: destroy the calling thread's look-ahead streams
-// (batched.hip) and free the blocks cached for a stream (api.hip).
+// (batched.hip), and move the blocks cached for a stream that has been
+// synchronized and is about to be destroyed to the idle section, where any
+// stream may take them (api.hip); a destroyed stream's own section would
+// never be asked for again.
 void release_thread_streams();
-void dbuf_drop_stream(hipStream_t s);
+void dbuf_retire_stream(hipStream_t s);
 
 // y = A^T x pair by pair (gmres.hip).
 void matvec_T_impl(hif_factor_s* H, const double* x, double* y, int64_t nrhs, hipStream_t s);
