@@ -693,6 +693,31 @@ def test_factor_batch_level_synchronous():
         facs[i].free()
 
 
+def test_factor_batch_repeated_steps_hold_their_time():
+    # Six batch factorizations of the 48-problem workload in a row, each
+    # followed by the frees: the library's device-memory cache must keep
+    # serving the same blocks (the large ones included), so that the last
+    # steps take as long as the second.  Before the cache kept large blocks
+    # and the blocks of destroyed streams, steps 4-6 took 1.5 to 6 times as
+    # long, the host mapping and unmapping memory.
+    import time
+    from workloads import batch_problems
+    probs = batch_problems()
+    dp = [dict(points=_t(p["points"]), a=_t(p["a"]), h=p["h"], eps=p["eps"], leaf=p["leaf"]) for p in probs]
+    times = []
+    for _ in range(6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        facs, st = hif.factor_batch(dp, nworkers=0)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        assert all(x == 0 for x in st), st
+        for F in facs:
+            F.free()
+    print("batch factorization seconds per step:", [round(t, 3) for t in times])
+    assert max(times[3:]) <= 1.3 * times[1], times
+
+
 def test_factor_batch_level_synchronous_3d_and_mixed():
     # 3D problems of two depths together, and the FP32-mixed mode refined by
     # GMRES, through the level-synchronous batch
