@@ -4,6 +4,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -79,14 +80,41 @@ struct CacheKey {
 };
 // Process-wide and never destroyed (freeing at exit could run after the HIP
 // runtime is gone); the memory returns to the system with the process.
+struct CacheEntry {
+  void* p;
+  uint64_t tick;  // when it was cached
+};
+using CacheMap = std::multimap<CacheKey, CacheEntry>;
 struct DbufCache {
   std::mutex mu;
-  std::multimap<CacheKey, void*> blocks;
+  CacheMap blocks;
+  // the idle blocks, oldest first: a release that would pass the cap frees
+  // these first (idle blocks have no pending work)
+  std::map<uint64_t, CacheMap::iterator> idle_age;
+  uint64_t tick = 0;
   size_t bytes = 0;
 };
 DbufCache& dbuf_cache() {
   static DbufCache* c = new DbufCache;
   return *c;
+}
+void cache_insert(DbufCache& c, const CacheKey& k, void* p, uint64_t tick) {
+  const CacheMap::iterator it = c.blocks.emplace(k, CacheEntry{p, tick});
+  if (k.s == dbuf_idle_key()) c.idle_age.emplace(tick, it);
+  c.bytes += k.cls;
+}
+void cache_erase(DbufCache& c, CacheMap::iterator it) {
+  if (it->first.s == dbuf_idle_key()) c.idle_age.erase(it->second.tick);
+  c.bytes -= it->first.cls;
+  c.blocks.erase(it);
+}
+// Returns a block to the device: blocks of a stream's section after the
+// stream's queued work, idle ones at once.
+void block_free(void* p, const CacheKey& k) {
+  if (k.cls >= kDbufDirectBytes)
+    (void)hipFree(p);
+  else
+    (void)hipFreeAsync(p, k.s == dbuf_idle_key() ? nullptr : k.s);
 }
 }  // namespace
 
@@ -106,10 +134,9 @@ void* dbuf_take(size_t& cls, hipStream_t s) {
   auto it = fit(s);
   if (it == c.blocks.end()) it = fit(dbuf_idle_key());  // idle blocks serve any stream
   if (it == c.blocks.end()) return nullptr;
-  void* p = it->second;
+  void* p = it->second.p;
   cls = it->first.cls;
-  c.blocks.erase(it);
-  c.bytes -= cls;
+  cache_erase(c, it);
   return p;
 }
 
@@ -120,16 +147,12 @@ void dbuf_trim() {
     DbufCache& c = dbuf_cache();
     std::lock_guard<std::mutex> lk(c.mu);
     for (auto it = c.blocks.begin(); it != c.blocks.end();) {
+      const auto nx = std::next(it);
       if (it->first.dev == dev) {
-        if (it->first.cls >= kDbufDirectBytes)
-          (void)hipFree(it->second);
-        else
-          (void)hipFreeAsync(it->second, it->first.s == dbuf_idle_key() ? nullptr : it->first.s);
-        c.bytes -= it->first.cls;
-        it = c.blocks.erase(it);
-      } else {
-        ++it;
+        block_free(it->second.p, it->first);
+        cache_erase(c, it);
       }
+      it = nx;
     }
   }
   (void)hipDeviceSynchronize();
@@ -143,14 +166,15 @@ void dbuf_retire_stream(hipStream_t s) {
   if (hipGetDevice(&dev) != hipSuccess) return;
   DbufCache& c = dbuf_cache();
   std::lock_guard<std::mutex> lk(c.mu);
-  for (auto it = c.blocks.begin(); it != c.blocks.end();) {
-    if (it->first.dev == dev && it->first.s == s) {
-      c.blocks.emplace(CacheKey{dev, dbuf_idle_key(), it->first.cls}, it->second);
-      it = c.blocks.erase(it);
-    } else {
-      ++it;
-    }
+  std::vector<std::pair<CacheKey, CacheEntry>> moved;
+  for (auto it = c.blocks.lower_bound(CacheKey{dev, s, 0});
+       it != c.blocks.end() && it->first.dev == dev && it->first.s == s;) {
+    const auto nx = std::next(it);
+    moved.push_back({CacheKey{dev, dbuf_idle_key(), it->first.cls}, it->second});
+    cache_erase(c, it);
+    it = nx;
   }
+  for (const auto& m : moved) cache_insert(c, m.first, m.second.p, m.second.tick);
 }
 
 bool dbuf_give(void* p, size_t cls, hipStream_t s) {
@@ -158,9 +182,19 @@ bool dbuf_give(void* p, size_t cls, hipStream_t s) {
   if (hipGetDevice(&dev) != hipSuccess) return false;
   DbufCache& c = dbuf_cache();
   std::lock_guard<std::mutex> lk(c.mu);
+  // past the cap, the oldest idle blocks of this device go back first: a
+  // block just released is the likelier to be asked for again
+  for (auto a = c.idle_age.begin(); c.bytes + cls > kDbufCacheBytes && a != c.idle_age.end();) {
+    const auto nx = std::next(a);
+    const CacheMap::iterator it = a->second;
+    if (it->first.dev == dev) {
+      block_free(it->second.p, it->first);
+      cache_erase(c, it);  // erases a
+    }
+    a = nx;
+  }
   if (c.bytes + cls > kDbufCacheBytes) return false;
-  c.blocks.emplace(CacheKey{dev, s, cls}, p);
-  c.bytes += cls;
+  cache_insert(c, CacheKey{dev, s, cls}, p, ++c.tick);
   return true;
 }
 

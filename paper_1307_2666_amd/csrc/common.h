@@ -82,12 +82,14 @@ void dbuf_pool_setup();  // once per device: keep freed memory in the pool
 // the block's last use; it saves the allocator's per-call host cost between
 // the host's waits on the device.  Blocks released as idle (ReleaseIdle) are
 // kept in a section any stream may take from.  At most kDbufCacheBytes stay
-// cached (per process); beyond that blocks go back to the pool, whose host
-// cost per call grows with the blocks it has seen, so the cap is sized to
-// hold a whole batch factorization's working set (its largest blocks alone
-// take about 16 GiB for 48 problems of up to 256 x 256): 64 GiB, under a
-// quarter of the 288 GB of an MI355X.  An allocation the device cannot serve returns
-// every cached block first (dbuf_trim) and tries again.
+// cached (per process): a release that would pass the cap first returns the
+// oldest idle blocks to the device, and goes back to the pool itself only
+// when no idle block is left.  The pool's host cost per call grows with the
+// blocks it has seen, so the cap is sized to hold a whole batch
+// factorization's working set (its largest blocks alone take about 16 GiB
+// for 48 problems of up to 256 x 256): 64 GiB, under a quarter of the 288 GB
+// of an MI355X.  An allocation the device cannot serve returns every cached
+// block first (dbuf_trim) and tries again.
 // Blocks of kDbufDirectBytes or more bypass the pool (plain hipMalloc /
 // hipFree: few and large, they would otherwise stay reserved in it) but not
 // the cache: mapping and unmapping them takes the host up to hundreds of

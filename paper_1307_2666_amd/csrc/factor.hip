@@ -1963,6 +1963,10 @@ void factor_impl(hif_factor_s* H, const double* points, const hif_kernel* kr, co
   prepare_sweeps(H, s);
   HIF_HIP(hipStreamSynchronize(s));
   H->stats.t_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  // the blocks this factorization released on the caller's stream are idle
+  // now: any stream may take them (and the oldest may be evicted), rather
+  // than only later work on this stream
+  dbuf_retire_stream(s);
 }
 
 void factor_fused_impl(const std::vector<hif_factor_s*>& hs_in, hipStream_t s) {
