@@ -21,6 +21,7 @@
 #include <string>
 
 #include "common.h"
+#include "wave.h"
 
 namespace hif {
 
@@ -362,6 +363,7 @@ __global__ void k_top(const double* LU, const int32_t* piv, int n, const int32_t
 // ---------------------------------------------------------------------------
 constexpr int kNbT = 64;
 constexpr int kMaxV = 8;       // right-hand sides per pass
+static_assert(kMaxV == 8, "the row products reduce their kMaxV sums with wave_rs8, 4 rows with wave_rs32");
 constexpr int kCapL = 16384;   // LDS doubles, largest records and the top block
 // Sub-levels with at least this many records run 64, 128 or 256 threads per
 // record (launch-shape table), fewer records 1024 threads each.
@@ -401,12 +403,10 @@ __device__ __forceinline__ void l_gemv_n(const double* __restrict__ M, int nrow,
         }
       }
     }
-#pragma unroll
-    for (int v = 0; v < kMaxV; ++v)
-      if (v < nv) {
-        const double t = wave_sum(acc[v]);
-        if (lane == 0) y[v * ys + i] += sgn * t;
-      }
+    // the 8 right-hand sides' sums at once: lane l holds that of l >> 3
+    const double t = wave_rs8(acc);
+    const int v = lane >> 3;
+    if ((lane & 7) == 0 && v < nv) y[v * ys + i] += sgn * t;
   }
 }
 
@@ -635,12 +635,9 @@ __device__ __forceinline__ void l_trmv(const double* __restrict__ LU, int n, dou
           }
         }
       }
-#pragma unroll
-      for (int v = 0; v < kMaxV; ++v)
-        if (v < nv) {
-          const double t = wave_sum(acc[v]);
-          if (lane == 0) tp[v * n + i] = t + (mode == 1 ? x[v * n + i] : 0.0);
-        }
+      const double t = wave_rs8(acc);
+      const int v = lane >> 3;
+      if ((lane & 7) == 0 && v < nv) tp[v * n + i] = t + (mode == 1 ? x[v * n + i] : 0.0);
     }
   } else {
     for (int i = tid; i < n; i += blockDim.x) {
@@ -916,6 +913,19 @@ __device__ __forceinline__ void sp_clear_sync(const SpArgs& A) {
 
 constexpr int kSpChunk = 512;  // skeleton entries staged in LDS per pass
 
+// The sums over the wave of acc[q][v] (4 rows q of the wave, kMaxV
+// right-hand sides) in one reduce-scatter: returns the total of row q =
+// lane >> 4, right-hand side v = (lane >> 1) & 7, held by lanes 2c and
+// 2c + 1 (c = 8q + v).
+__device__ __forceinline__ double sp_rows_sum(const double (&acc)[4][kMaxV]) {
+  double p[kRs];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v) p[q * kMaxV + v] = acc[q][v];
+  return wave_rs32(p);
+}
+
 // First step of an up pass (and of the transposed solve's down pass), column
 // form: B(v, i) = u_r(v, c) - (M^T u_s)(v, c) with c = perm[i] (PERM: the
 // row interchanges of the solve, B = P(u_r - T^T u_s)) or c = i, and
@@ -1008,16 +1018,10 @@ __global__ __launch_bounds__(256) void k_sp_down_first(SpArgs A) {
       }
     }
   }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = i0 + wv * 4 + q;
-    if (i >= R.r) break;
-#pragma unroll
-    for (int v = 0; v < kMaxV; ++v)
-      if (v < nv) {
-        const double t = wave_sum(acc[q][v]);
-        if (lane == 0) R.B[v * R.r + i] = A.u[v * A.N + R.rd[i]] - t;
-      }
+  {
+    const double t = sp_rows_sum(acc);
+    const int i = i0 + wv * 4 + (lane >> 4), v = (lane >> 1) & 7;
+    if ((lane & 1) == 0 && i < R.r && v < nv) R.B[v * R.r + i] = A.u[v * A.N + R.rd[i]] - t;
   }
 }
 
@@ -1057,16 +1061,10 @@ __global__ __launch_bounds__(256) void k_sp_skel_update(SpArgs A, int which, dou
       }
     }
   }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int j = j0 + wv * 4 + q;
-    if (j >= R.k) break;
-#pragma unroll
-    for (int v = 0; v < kMaxV; ++v)
-      if (v < nv) {
-        const double t = wave_sum(acc[q][v]);
-        if (lane == 0) A.u[v * A.N + R.sk[j]] += sgn * t;
-      }
+  {
+    const double t = sp_rows_sum(acc);
+    const int j = j0 + wv * 4 + (lane >> 4), v = (lane >> 1) & 7;
+    if ((lane & 1) == 0 && j < R.k && v < nv) A.u[v * A.N + R.sk[j]] += sgn * t;
   }
 }
 
@@ -1203,15 +1201,10 @@ __global__ __launch_bounds__(256) void k_sp_rowmv(SpArgs A, int io) {
         }
       }
     }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = i0 + wv * 4 + q;
-#pragma unroll
-    for (int v = 0; v < kMaxV; ++v)
-      if (v < nv) {
-        const double t = wave_sum(acc[q][v]);
-        if (lane == 0 && i < r) out[v * r + i] = t + (TRI == 1 ? x[v * r + i] : 0.0);
-      }
+  {
+    const double t = sp_rows_sum(acc);
+    const int i = i0 + wv * 4 + (lane >> 4), v = (lane >> 1) & 7;
+    if ((lane & 1) == 0 && i < r && v < nv) out[v * r + i] = t + (TRI == 1 ? x[v * r + i] : 0.0);
   }
 }
 

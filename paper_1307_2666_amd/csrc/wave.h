@@ -57,4 +57,21 @@ __device__ __forceinline__ double wave_rs32(double (&p)[kRs]) {
   return p[0] + __shfl_xor(p[0], 1, 64);
 }
 
+// Sum of p[c] over the 64 lanes for all 8 indices at once, the same
+// reduce-scatter on 8 values: the total of index lane >> 3 (held by all 8
+// lanes of the group); p is destroyed.
+__device__ __forceinline__ double wave_rs8(double (&p)[8]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) p[i] = swap_pair_sum<16>(p[i], p[i + 4]);  // index + 4 on the upper half
+#pragma unroll
+  for (int i = 0; i < 2; ++i) p[i] = swap_pair_sum<8>(p[i], p[i + 2]);  // index + 2 on odd rows of 16
+  const bool up = (lane & 8) != 0;
+  double t = (up ? p[1] : p[0]) + __shfl_xor(up ? p[0] : p[1], 8, 64);  // index + 1 on lanes with bit 3
+  t += __shfl_xor(t, 4, 64);
+  t += __shfl_xor(t, 2, 64);
+  t += __shfl_xor(t, 1, 64);
+  return t;
+}
+
 }  // namespace hif
