@@ -381,6 +381,34 @@ constexpr int kU = 8;
 __device__ __forceinline__ void l_gemv_n(const double* __restrict__ M, int nrow, int ncol, int ld, const double* x, int xs, double* y,
                          int ys, int nv, double sgn) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (ncol <= 64) {
+    // rows of at most one element per lane: x in registers, four rows of the
+    // wave at a time with their loads issued together
+    double xv[kMaxV];
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v) xv[v] = (v < nv && lane < ncol) ? x[v * xs + lane] : 0.0;
+    for (int i0 = wv; i0 < nrow; i0 += 4 * nw) {
+      double m[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + q * nw;
+        m[q] = (i < nrow && lane < ncol) ? M[int64_t(i) * ld + lane] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + q * nw;
+        if (i < nrow) {
+          double acc[kMaxV];
+#pragma unroll
+          for (int v = 0; v < kMaxV; ++v) acc[v] = m[q] * xv[v];
+          const double t = wave_rs8(acc);
+          const int v = lane >> 3;
+          if ((lane & 7) == 0 && v < nv) y[v * ys + i] += sgn * t;
+        }
+      }
+    }
+    return;
+  }
   for (int i = wv; i < nrow; i += nw) {
     const double* mr = M + int64_t(i) * ld;
     double acc[kMaxV];
@@ -410,29 +438,56 @@ __device__ __forceinline__ void l_gemv_n(const double* __restrict__ M, int nrow,
   }
 }
 
-// y[v*ys + j] += sgn * sum_i M[i*ld + j] x[v*xs + i]   (one thread per column)
+// y[v*ys + j] += sgn * sum_i M[i*ld + j] x[v*xs + i]   (one thread per column).
+// With few columns the waves split the rows: wave w takes column group
+// w % ncg (64 columns) and row slice w / ncg (at most 4 slices), and the
+// slices add their partial sums in slice order (deterministic).  Every
+// thread of the workgroup calls it; it ends synchronized.
 __device__ __forceinline__ void l_gemv_t(const double* __restrict__ M, int nrow, int ncol, int ld, const double* x, int xs, double* y,
                          int ys, int nv, double sgn) {
-  for (int j = threadIdx.x; j < ncol; j += blockDim.x) {
-    double acc[kMaxV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (ncol <= 0 || nrow <= 0) {
+    __syncthreads();
+    return;
+  }
+  const int ncg = (ncol + 63) / 64;
+  const int nrs = ncg <= nw ? min(4, nw / ncg) : 1;
+  const bool split = ncg <= nw;
+  const int cg = split ? wv % ncg : 0, rs = split ? wv / ncg : 0;
+  const bool active = !split || wv < ncg * nrs;
+  const int ib = split ? (nrow * rs) / nrs : 0, ie = split ? (nrow * (rs + 1)) / nrs : nrow;
+  double acc[kMaxV];
+  for (int j = split ? cg * 64 + lane : threadIdx.x; active && j < ncol; j += split ? ncol : blockDim.x) {
 #pragma unroll
     for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
-    for (int i0 = 0; i0 < nrow; i0 += kU) {
+    for (int i0 = ib; i0 < ie; i0 += kU) {
       double mv[kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) mv[u] = i0 + u < nrow ? M[int64_t(i0 + u) * ld + j] : 0.0;
+      for (int u = 0; u < kU; ++u) mv[u] = i0 + u < ie ? M[int64_t(i0 + u) * ld + j] : 0.0;
 #pragma unroll
       for (int u = 0; u < kU; ++u)
-        if (i0 + u < nrow) {
+        if (i0 + u < ie) {
 #pragma unroll
           for (int v = 0; v < kMaxV; ++v)
             if (v < nv) acc[v] += mv[u] * x[v * xs + i0 + u];
         }
     }
+    if (!split)
 #pragma unroll
-    for (int v = 0; v < kMaxV; ++v)
-      if (v < nv) y[v * ys + j] += sgn * acc[v];
+      for (int v = 0; v < kMaxV; ++v)
+        if (v < nv) y[v * ys + j] += sgn * acc[v];
   }
+  if (split) {
+    const int j = cg * 64 + lane;
+    for (int p = 0; p < nrs; ++p) {
+      __syncthreads();
+      if (active && rs == p && j < ncol)
+#pragma unroll
+        for (int v = 0; v < kMaxV; ++v)
+          if (v < nv) y[v * ys + j] += sgn * acc[v];
+    }
+  }
+  __syncthreads();
 }
 
 // acc[v] = sum_{c < nb} seg[c * cs] x[v*xs + x0 + c]  (a row or column segment of LU)

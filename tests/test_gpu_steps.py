@@ -273,7 +273,9 @@ def test_step_nearfield_and_assembly_on_first_sublevels(si, trace2d):
 
 def test_sweep_and_rowqr_shapes_agree():
     # The sweep's threads per record (sub-levels of >= 1024 records) change
-    # only which wave handles which row: every shape gives the same solve.
+    # which wave handles which row, and the transposed products sum their
+    # rows in as many slices as the shape has waves (up to 4): the solves
+    # agree to rounding (each shape is deterministic on its own).
     # The row compression's update shapes sum the same products in other
     # orders: rank decisions at the threshold may differ in a few classes
     # (ranks are not unique), so the factorizations agree to a tenth of eps,
@@ -291,7 +293,7 @@ def test_sweep_and_rowqr_shapes_agree():
             hif.tuning_set(dict(base, sweep_many_threads=th))
             sols.append(F.solve(f))
         for u in sols[1:]:
-            assert torch.equal(u, sols[0])
+            assert (u - sols[0]).abs().max().item() <= 1e-13 * sols[0].abs().max().item()
         F.free()
         outs = []
         for w, kind in ((4, 0), (8, 1), (8, 2)):
