@@ -246,7 +246,7 @@ struct hif_factor_s {
   hif::DBuf<double> top_dinv;  // its diagonal-block inverses, as SubLevel::dinv
   // Sweep scratch.
   hif::DBuf<double> work;
-  // Ordering words of the chained triangular solves (sweep.hip), cleared by
+  // Ticket counter of the chained triangular solves (sweep.hip), cleared by
   // each pass before use.
   hif::DBuf<uint32_t> sync;
   hif_stats_t stats{};

@@ -925,8 +925,7 @@ struct SpArgs {
   int nv;
   const double* dinv;  // diagonal-block inverses (SubLevel::dinv layout)
   int dnb;             // blocks per record in dinv
-  // Ordering words of the chained triangular solve: [0] ticket counter, then
-  // one flag per (record, 64-row block) at 1 + record * nbm + block.
+  // Ticket counter of the chained triangular solve.
   uint32_t* sync = nullptr;
   int nbm = 0;  // blocks of the largest record
 };
@@ -955,15 +954,17 @@ __device__ __forceinline__ SpRec sp_rec(const SpArgs& A, int i) {
   return v;
 }
 
-// The first kernel of a pass clears the ordering words of the chained
-// solve that follows it: workgroup (0, i) the flags of record i, and
-// workgroup (0, 0) the ticket counter.  The next launch on the stream sees
-// the zeros.
-__device__ __forceinline__ void sp_clear_sync(const SpArgs& A) {
-  if (blockIdx.x != 0 || !A.sync) return;
-  uint32_t* f = A.sync + 1 + int64_t(blockIdx.y) * A.nbm;
-  for (int e = threadIdx.x; e < A.nbm; e += blockDim.x) f[e] = 0u;
-  if (blockIdx.y == 0 && threadIdx.x == 0) A.sync[0] = 0u;
+// The first kernel of a pass readies the chained solve that follows it:
+// workgroup (0, 0) clears the ticket counter, and every workgroup marks its
+// rows of X pending (rows i0 .. i0 + nrow - 1 of each right-hand side).  The
+// next launch on the stream sees both.
+constexpr uint64_t kXPending = 0x7FF4A3B2C1D0E0F1ull;  // a signaling NaN: no arithmetic result
+__device__ __forceinline__ void sp_ready_chain(const SpArgs& A, const SpRec& R, int i0, int nrow) {
+  if (!A.sync) return;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) A.sync[0] = 0u;
+  const int n = min(nrow, R.r - i0);
+  uint64_t* X = reinterpret_cast<uint64_t*>(R.X);
+  for (int e = threadIdx.x; e < A.nv * n; e += blockDim.x) X[(e / n) * R.r + i0 + e % n] = kXPending;
 }
 
 constexpr int kSpChunk = 512;  // skeleton entries staged in LDS per pass
@@ -990,10 +991,10 @@ __device__ __forceinline__ double sp_rows_sum(const double (&acc)[4][kMaxV]) {
 // waves and added through LDS.
 template <bool LSR, bool PERM, bool ADD = false>
 __global__ __launch_bounds__(256) void k_sp_first_cols(SpArgs A) {
-  sp_clear_sync(A);
   const SpRec R = sp_rec(A, blockIdx.y);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;  // 64 rows per workgroup
+  if (!ADD) sp_ready_chain(A, R, blockIdx.x * 64, 64);
   if (blockIdx.x * 64 >= R.r) return;
   const int nv = A.nv;
   const double* M = LSR ? R.Lsr : R.T;
@@ -1043,10 +1044,10 @@ __global__ __launch_bounds__(256) void k_sp_first_cols(SpArgs A) {
 // Down, first step of the solve: B(v, i) = (u_r - U_rs u_s)(v, i), one wave
 // per row i.
 __global__ __launch_bounds__(256) void k_sp_down_first(SpArgs A) {
-  sp_clear_sync(A);
   const SpRec R = sp_rec(A, blockIdx.y);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i0 = blockIdx.x * 16;  // 16 rows per workgroup, 4 per wave
+  sp_ready_chain(A, R, i0, 16);
   if (i0 >= R.r) return;
   const int nv = A.nv;
   __shared__ double sus[kMaxV][kSpChunk];
@@ -1375,34 +1376,61 @@ __global__ __launch_bounds__(64) void k_sp_dinv(SpArgs A, double* dinv) {
 // The blocked triangular solve X = M^{-1} B of every record of a pass in one
 // launch.  Workgroup (record, block j) owns rows 64j .. 64j + 63 of X: it
 // subtracts the products of its row of 64 x 64 blocks of M with the blocks
-// of X it depends on, each as soon as that block is published, multiplies
-// the result by the stored inverse of its diagonal block, writes its block
-// of X and publishes it with a flag (a release at device scope, which the
-// reader acquires).  The workgroups draw (record, block) from a ticket
-// counter in the order in which the blocks become ready, so a workgroup
-// only ever waits on one that has already started, and every wait ends
-// however many workgroups are resident at once.  Each wait is also bounded
-// in time; past the bound (not expected) the workgroup writes NaN in its
-// block, so that the failure shows in the result instead of stalling the
-// device.  Each next block of M is loaded into registers before its wait.
+// of X it depends on, each as soon as that block is written, multiplies the
+// result by the stored inverse of its diagonal block and writes its block of
+// X.  The block's values are their own flag: the pass's first kernel marks
+// every entry of X pending (a signaling NaN, which no arithmetic produces),
+// the owner stores the entries with relaxed device-scope atomic stores, and
+// a reader polls them with relaxed device-scope atomic loads, both coherent
+// across the chip, until none is pending: one memory round trip per block,
+// with no cache write-back or invalidation.  The workgroups draw (record,
+// block) from a ticket counter in the order in which the blocks become
+// ready, so a workgroup only ever waits on one that has already started, and
+// every wait ends however many workgroups are resident at once.  Each wait
+// is also bounded in time; past the bound (not expected) the workgroup
+// writes NaN in its block, so that the failure shows in the result instead
+// of stalling the device.  Each next block of M is loaded into registers
+// before its wait.
 //   MODE 0: L X = B    (unit lower L of the record's LU; blocks first to last)
 //   MODE 1: U X = B    (upper U; last to first)
 //   MODE 2: U^T X = B  (first to last; U read by columns)
 //   MODE 3: L^T X = B  (last to first; L read by columns)
-// Grid (A.nbm, records), 256 threads; the ordering words are zero at launch.
+// Grid (A.nbm, records), 256 threads; the ticket is zero and X pending at
+// launch.
 // ---------------------------------------------------------------------------
 constexpr long long kWaitTicks = 20000000;  // 0.2 s of the 100 MHz constant clock
 
-// Polls with relaxed device-scope loads, which are coherent across the chip
-// and invalidate no cache (an acquiring poll would invalidate this XCD's L2
-// on every try); the caller acquires once the flag is seen.
-__device__ __forceinline__ bool sp_wait_flag(const uint32_t* f) {
+// Wave 0 of a reader: block b0 .. b0 + nbb - 1 of X, every right-hand side,
+// into sx (lane = row of the block), polled until no entry is pending.
+// Returns false past the time bound.
+__device__ __forceinline__ bool sp_read_block(const double* X, int r, int b0, int nbb, int nv,
+                                              double (*sx)[kNbT]) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t* X64 = reinterpret_cast<const uint64_t*>(X);
+  uint64_t got[kMaxV];
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) got[v] = kXPending;
   const long long t0 = wall_clock64();
-  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+  bool ok = true;
+  for (;;) {
+    int ready = 1;
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv && lane < nbb && got[v] == kXPending)
+        got[v] = __hip_atomic_load(X64 + int64_t(v) * r + b0 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv && lane < nbb && got[v] == kXPending) ready = 0;
+    if (__all(ready)) break;
+    if (wall_clock64() - t0 > kWaitTicks) {
+      ok = false;
+      break;
+    }
     __builtin_amdgcn_s_sleep(1);
-    if (wall_clock64() - t0 > kWaitTicks) return false;
   }
-  return true;
+#pragma unroll
+  for (int v = 0; v < kMaxV; ++v) sx[v][lane] = (v < nv && lane < nbb) ? __longlong_as_double((long long)got[v]) : 0.0;
+  return ok;
 }
 
 template <int MODE>
@@ -1427,7 +1455,6 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
   if (jj >= nbk) return;
   const int j = kFwd ? jj : nbk - 1 - jj;
   const int j0 = j * kNbT, nb = min(kNbT, r - j0), nv = A.nv;
-  uint32_t* flags = A.sync + 1 + int64_t(rec) * A.nbm;
   const int ndep = kFwd ? j : nbk - 1 - j;
   // Element q of a thread is e = tid + 256 q of a 64 x 64 tile at (a, c):
   // (e / 64, e % 64) for a row-major read, (e % 64, e / 64) for a column
@@ -1466,16 +1493,11 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
   if (ndep > 0) load_block(kFwd ? 0 : nbk - 1);
   for (int d = 0; d < ndep; ++d) {
     const int b = kFwd ? d : nbk - 1 - d;
-    // wave 0 waits, acquires and stages X_b in LDS (one cache invalidation
-    // per block); the other waves store the prefetched tile meanwhile
+    // wave 0 waits for X_b and stages it in LDS; the other waves store the
+    // prefetched tile meanwhile
     if (wv == 0) {
-      if (lane == 0 && !sp_wait_flag(flags + b)) s_ok = 0;
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      const int b0 = b * kNbT, nbb = min(kNbT, r - b0);
-      for (int e = lane; e < nv * kNbT; e += 64) {
-        const int v = e >> 6, c = e & 63;
-        sx[v][c] = c < nbb ? R.X[v * r + b0 + c] : 0.0;
-      }
+      const int b0 = b * kNbT;
+      if (!sp_read_block(R.X, r, b0, min(kNbT, r - b0), nv, sx) && lane == 0) s_ok = 0;
     }
     store_tile(pre);
     __syncthreads();
@@ -1510,15 +1532,14 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
 #pragma unroll
   for (int q = 0; q < kMaxV / 4; ++q) sx[wv + 4 * q][lane] = ok ? y[q] : __builtin_nan("");
   __syncthreads();
-  // wave 0 writes the block, releases it (one write-back of its XCD's L2)
-  // and sets the flag
+  // wave 0 writes the block, entry by entry visible to the readers
   if (wv == 0) {
+    uint64_t* X64 = reinterpret_cast<uint64_t*>(R.X);
     for (int e = lane; e < nv * nb; e += 64) {
       const int v = e / nb, a = e - v * nb;
-      R.X[v * r + j0 + a] = sx[v][a];
+      __hip_atomic_store(X64 + int64_t(v) * r + j0 + a, (uint64_t)__double_as_longlong(sx[v][a]), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (lane == 0) __hip_atomic_store(flags + j, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -1772,13 +1793,10 @@ static void build_dinv(hif_factor_s* H, hipStream_t s) {
 
 void prepare_sweeps(hif_factor_s* H, hipStream_t s) {
   build_dinv(H, s);
-  // ordering words of the chained triangular solves: a ticket counter and
-  // one flag per 64-row block of the largest pass
-  size_t words = 0;
-  for (const SubLevel& sub : H->subs)
-    if (sub.dinv.p) words = std::max(words, size_t(sub.nrec) * size_t((sub.max_r + kNbT - 1) / kNbT));
-  if (top_split_solve(H)) words = std::max(words, size_t((H->ntop + kNbT - 1) / kNbT));
-  if (words > 0 && H->sync.n < 1 + words) H->sync.alloc(1 + words, &H->mem);
+  // the ticket counter of the chained triangular solves
+  bool chained = top_split_solve(H);
+  for (const SubLevel& sub : H->subs) chained = chained || sub.dinv.p != nullptr;
+  if (chained && !H->sync.p) H->sync.alloc(1, &H->mem);
   if (!top_split_solve(H) || H->top_rec.p) return;
   const int r = int(H->ntop);
   H->top_iarena.alloc(size_t(3) * r, &H->mem);
