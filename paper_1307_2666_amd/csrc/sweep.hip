@@ -1581,7 +1581,7 @@ static void allow_large_lds() {
 #define HIF_SPLIT_MAX_RECORDS 64
 #endif
 #ifndef HIF_SPLIT_MIN_R
-#define HIF_SPLIT_MIN_R 256
+#define HIF_SPLIT_MIN_R 128
 #endif
 constexpr int kSplitMaxRecords = HIF_SPLIT_MAX_RECORDS;
 constexpr int kSplitMinR = HIF_SPLIT_MIN_R;
