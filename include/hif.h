@@ -109,6 +109,14 @@ typedef struct {
  *                evaluated on the fly as hif_matvec; 1 = by FFT convolution
  *                when the points form the full uniform grid with constant
  *                weights and self terms (see hif_apply_A), else pair by pair.
+ *  sweep_wait_us: bound, in microseconds, on each wait of the sweeps'
+ *                chained triangular solves (a workgroup waiting for a block
+ *                of the solution another one computes); 0 (default) =
+ *                200000.  A workgroup whose wait passes the bound writes NaN
+ *                into its block and finishes, so that the failure shows in
+ *                the result instead of stalling the device.  Waits are never
+ *                expected to come near the default; a tiny bound is for
+ *                testing that path.
  */
 typedef struct {
   int precision;
@@ -121,6 +129,7 @@ typedef struct {
   int row_compression;
   int fft_matvec;
   int trace_sublevel;
+  int sweep_wait_us;
 } hif_opts;
 
 #define HIF_MAX_SUBLEVELS 64

@@ -38,7 +38,7 @@ class hif_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("second_kind", ctypes.c_int), ("symmetric", ctypes.c_int),
                 ("variant", ctypes.c_int), ("n_proxy", ctypes.c_int), ("proxy_radius", ctypes.c_double),
                 ("max_bytes", ctypes.c_size_t), ("row_compression", ctypes.c_int), ("fft_matvec", ctypes.c_int),
-                ("trace_sublevel", ctypes.c_int)]
+                ("trace_sublevel", ctypes.c_int), ("sweep_wait_us", ctypes.c_int)]
 
 
 class hif_problem(ctypes.Structure):
@@ -318,7 +318,7 @@ class SolveGraph:
 def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, selfk=None,
            second_kind=-1, symmetric=-1, variant="hifie", n_proxy=0, proxy_radius=0.0,
            max_bytes=0, precision=HIF_FP64, row_compression=-1, fft_matvec=0, trace_sublevel=-1,
-           stream=None) -> Factorization:
+           sweep_wait_us=0, stream=None) -> Factorization:
     """``hif_factor``: build ``F ~ A`` for points ``(n, d)`` in the unit box."""
     lib = load_library()
     P = _dev(points)
@@ -339,6 +339,7 @@ def factor(points, eps, leaf, *, a=None, b=None, c=None, h=None, weights=None, s
     o.row_compression = row_compression
     o.fft_matvec = fft_matvec
     o.trace_sublevel = trace_sublevel
+    o.sweep_wait_us = sweep_wait_us
     handle = ctypes.c_void_p()
     _check(lib.hif_factor(_ptr(P), n, d, ctypes.byref(k), _ptr(av), _ptr(bv), _ptr(cv), float(eps), int(leaf),
                           ctypes.byref(o), _stream(stream), ctypes.byref(handle)))

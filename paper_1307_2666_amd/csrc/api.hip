@@ -292,6 +292,7 @@ hif_status hif_opts_default(hif_opts* o) {
   o->row_compression = -1;
   o->fft_matvec = 0;
   o->trace_sublevel = -1;
+  o->sweep_wait_us = 0;
   return HIF_OK;
 }
 
@@ -327,6 +328,7 @@ static hif_status resolve_opts(const hif_opts* opts, hif_opts* out) {
   if (o.row_compression < -1 || o.row_compression > 1)
     return fail(HIF_EINVAL, "opts.row_compression must be -1, 0 or 1");
   if (o.fft_matvec != 0 && o.fft_matvec != 1) return fail(HIF_EINVAL, "opts.fft_matvec must be 0 or 1");
+  if (o.sweep_wait_us < 0) return fail(HIF_EINVAL, "opts.sweep_wait_us must be >= 0");
   if (o.trace_sublevel < -1 || o.trace_sublevel >= HIF_MAX_SUBLEVELS)
     return fail(HIF_EINVAL, "opts.trace_sublevel must be -1 or a sub-level index");
   if (!(o.proxy_radius == 0.0 || (std::isfinite(o.proxy_radius) && o.proxy_radius > 0.5)))

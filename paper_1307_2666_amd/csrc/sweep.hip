@@ -928,6 +928,7 @@ struct SpArgs {
   // Ticket counter of the chained triangular solve.
   uint32_t* sync = nullptr;
   int nbm = 0;  // blocks of the largest record
+  long long wait_ticks = 0;  // bound on each wait, in ticks of the 100 MHz constant clock
 };
 
 struct SpRec {
@@ -1398,13 +1399,13 @@ __global__ __launch_bounds__(64) void k_sp_dinv(SpArgs A, double* dinv) {
 // Grid (A.nbm, records), 256 threads; the ticket is zero and X pending at
 // launch.
 // ---------------------------------------------------------------------------
-constexpr long long kWaitTicks = 20000000;  // 0.2 s of the 100 MHz constant clock
+constexpr long long kWaitTicks = 20000000;  // 0.2 s of the 100 MHz constant clock (default bound)
 
 // Wave 0 of a reader: block b0 .. b0 + nbb - 1 of X, every right-hand side,
 // into sx (lane = row of the block), polled until no entry is pending.
-// Returns false past the time bound.
+// Returns false past the time bound (wait ticks of the constant clock).
 __device__ __forceinline__ bool sp_read_block(const double* X, int r, int b0, int nbb, int nv,
-                                              double (*sx)[kNbT]) {
+                                              double (*sx)[kNbT], long long wait) {
   const int lane = threadIdx.x & 63;
   const uint64_t* X64 = reinterpret_cast<const uint64_t*>(X);
   uint64_t got[kMaxV];
@@ -1422,7 +1423,7 @@ __device__ __forceinline__ bool sp_read_block(const double* X, int r, int b0, in
     for (int v = 0; v < kMaxV; ++v)
       if (v < nv && lane < nbb && got[v] == kXPending) ready = 0;
     if (__all(ready)) break;
-    if (wall_clock64() - t0 > kWaitTicks) {
+    if (wall_clock64() - t0 > wait) {
       ok = false;
       break;
     }
@@ -1497,7 +1498,7 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
     // prefetched tile meanwhile
     if (wv == 0) {
       const int b0 = b * kNbT;
-      if (!sp_read_block(R.X, r, b0, min(kNbT, r - b0), nv, sx) && lane == 0) s_ok = 0;
+      if (!sp_read_block(R.X, r, b0, min(kNbT, r - b0), nv, sx, A.wait_ticks) && lane == 0) s_ok = 0;
     }
     store_tile(pre);
     __syncthreads();
@@ -1622,6 +1623,7 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
     hipLaunchKernelGGL(k_copy, dim3(unsigned(blocks)), dim3(256), 0, s, x, y, tot);
     HIF_HIP(hipGetLastError());
   }
+  const long long wait_ticks = H->opts.sweep_wait_us > 0 ? 100ll * H->opts.sweep_wait_us : kWaitTicks;
   for (int64_t v0 = 0; v0 < nrhs; v0 += 8) {
     const int nv = int(std::min<int64_t>(8, nrhs - v0));
     double* u = y + v0 * N;
@@ -1645,6 +1647,7 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
         SpArgs P{sub.rec.p,  sub.iarena.p, sub.darena.p, sub.woff.p, u, wk, wk + nv * sub.sum_r, N, nv,
                  sub.dinv.p, sub.dinv_nb};
         P.sync = H->sync.p;
+        P.wait_ticks = wait_ticks;
         P.nbm = (sub.max_r + kNbT - 1) / kNbT;
         const unsigned nr = unsigned(sub.nrec);
         const dim3 gr(unsigned((sub.max_r + 255) / 256), nr), gu(unsigned((sub.max_r + 63) / 64), nr);
@@ -1733,6 +1736,7 @@ static void sweep_run(hif_factor_s* H, int op, const double* x, double* y, int64
       SpArgs P{H->top_rec.p, H->top_iarena.p, H->top_lu.p,  H->top_woff.p, u, wk, wk + int64_t(nv) * r, N, nv,
                H->top_dinv.p, nbk};
       P.sync = H->sync.p;
+      P.wait_ticks = wait_ticks;
       P.nbm = nbk;
       const dim3 gr(unsigned((r + 255) / 256), 1), gu(unsigned((r + 63) / 64), 1), gw(unsigned((r + 15) / 16), 1);
       if (op == 0) {

@@ -110,6 +110,11 @@ def test_apply_A_rejects_bad_arguments():
     o.fft_matvec = 2
     st, msg, _ = _factor_raw(opts=o)
     assert st == B.HIF_EINVAL and "fft_matvec" in msg
+    o = hif.default_opts()
+    assert o.sweep_wait_us == 0
+    o.sweep_wait_us = -1
+    st, msg, _ = _factor_raw(opts=o)
+    assert st == B.HIF_EINVAL and "sweep_wait_us" in msg
 
 
 def test_factor_batch_rejects_bad_arguments():
