@@ -195,3 +195,44 @@ def test_solve_noalloc_rejects_bad_arguments():
     assert lib.hif_solve_noalloc(h, None, y, 1, None) == B.HIF_EINVAL
     assert lib.hif_solve_noalloc(h, x, y, 0, None) == B.HIF_EINVAL
     assert hif.HIF_SOLVE_NOALLOC_MAX == 4 << 20
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # Every ctypes mirror of an include/hif.h struct has the C compiler's size
+    # and field offsets (a field added on one side only would shift the rest).
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [("hif_kernel", B.hif_kernel), ("hif_opts", B.hif_opts), ("hif_problem", B.hif_problem),
+               ("hif_tuning", B.hif_tuning), ("hif_stats_t", B.hif_stats_t)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hif.h"', "int main(void) {"]
+    want = []
+    for cname, py in structs:
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(py))
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {fname}));')
+            want.append(getattr(py, fname).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c11", "-I", inc, "-o", str(exe), str(src)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == want
+    # and the same members in the same order (a C-only field could hide in padding)
+    with open(os.path.join(inc, "hif.h")) as f:
+        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+    for cname, py in structs:
+        body = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + cname + r"\s*;", text)
+        assert body, cname
+        members = []
+        for decl in body.group(1).split(";"):
+            for d in decl.split(","):  # several declarators: "const double *a, *b, *c"
+                d = re.sub(r"\[[^\]]*\]", "", d).strip()
+                if d:
+                    members.append(re.findall(r"\w+", d)[-1])
+        assert members == [fname for fname, _ in py._fields_], cname
