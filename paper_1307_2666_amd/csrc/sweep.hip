@@ -1442,6 +1442,7 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
   __shared__ unsigned s_ticket;
   __shared__ int s_ok;
   __shared__ double sM[kNbT][kNbT + 1];
+  __shared__ double sD[kNbT][kNbT + 1];  // the diagonal block's inverse, staged before any wait
   __shared__ double sx[kMaxV][kNbT];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (tid == 0) {
@@ -1472,11 +1473,11 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
                    : 0.0;
     }
   };
-  auto store_tile = [&](const double* v) {
+  auto store_tile = [&](double (*dst)[kNbT + 1], const double* v) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int e = tid + 256 * q, hi = e >> 6, lo = e & 63;
-      sM[kTrans ? lo : hi][kTrans ? hi : lo] = v[q];
+      dst[kTrans ? lo : hi][kTrans ? hi : lo] = v[q];
     }
   };
   {
@@ -1485,6 +1486,9 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) dpre[q] = Dg[tid + 256 * q];
   }
+  // into LDS now: it depends on no other block, and the barriers below order
+  // these stores before the product that reads them
+  store_tile(sD, dpre);
   double acc[kMaxV / 4];
 #pragma unroll
   for (int q = 0; q < kMaxV / 4; ++q) {
@@ -1500,7 +1504,7 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
       const int b0 = b * kNbT;
       if (!sp_read_block(R.X, r, b0, min(kNbT, r - b0), nv, sx, A.wait_ticks) && lane == 0) s_ok = 0;
     }
-    store_tile(pre);
+    store_tile(sM, pre);
     __syncthreads();
     if (d + 1 < ndep) load_block(kFwd ? d + 1 : nbk - 2 - d);
 #pragma unroll
@@ -1515,31 +1519,23 @@ __global__ __launch_bounds__(256) void k_sp_chain(SpArgs A) {
     }
     __syncthreads();
   }
-  store_tile(dpre);
 #pragma unroll
   for (int q = 0; q < kMaxV / 4; ++q) sx[wv + 4 * q][lane] = acc[q];
   __syncthreads();
   const bool ok = s_ok != 0;
-  double y[kMaxV / 4];
+  // X_j = D_j^{-1} B_j: each thread its row (lane) of its right-hand sides,
+  // written straight from registers, entry by entry visible to the readers
+  uint64_t* X64 = reinterpret_cast<uint64_t*>(R.X);
 #pragma unroll
   for (int q = 0; q < kMaxV / 4; ++q) {
     const int v = wv + 4 * q;
-    y[q] = 0.0;
-    if (v < nv)
+    if (v < nv) {
+      double y = 0.0;
 #pragma unroll 16
-      for (int c = 0; c < kNbT; ++c) y[q] += sM[lane][c] * sx[v][c];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kMaxV / 4; ++q) sx[wv + 4 * q][lane] = ok ? y[q] : __builtin_nan("");
-  __syncthreads();
-  // wave 0 writes the block, entry by entry visible to the readers
-  if (wv == 0) {
-    uint64_t* X64 = reinterpret_cast<uint64_t*>(R.X);
-    for (int e = lane; e < nv * nb; e += 64) {
-      const int v = e / nb, a = e - v * nb;
-      __hip_atomic_store(X64 + int64_t(v) * r + j0 + a, (uint64_t)__double_as_longlong(sx[v][a]), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      for (int c = 0; c < kNbT; ++c) y += sD[lane][c] * sx[v][c];
+      if (lane < nb)
+        __hip_atomic_store(X64 + int64_t(v) * r + j0 + lane, (uint64_t)__double_as_longlong(ok ? y : __builtin_nan("")),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
