@@ -983,6 +983,41 @@ __device__ __forceinline__ double sp_rows_sum(const double (&acc)[4][kMaxV]) {
   return wave_rs32(p);
 }
 
+// acc[q][v] += sum_{c < nc} mr[q][c] s[v][c] for a wave's 4 rows q (mr[q] null
+// past the record; its sums are then never used), lane c = lane, lane + 64, ...
+// The loads of the 4 rows and of two column steps are issued together before
+// any is used; each acc[q][v] still adds its terms in increasing c.  TRI >= 0
+// keeps one triangle of rows iq[q] (column c0 + c): 0 the upper one with the
+// diagonal, 1 the strictly lower one; the other entries count as zero.
+template <int TRI = -1>
+__device__ __forceinline__ void sp_rows4_acc(const double* const (&mr)[4], int nc, const double (*s)[kSpChunk], int nv,
+                                             double (&acc)[4][kMaxV], int c0 = 0, const int* iq = nullptr) {
+  const int lane = threadIdx.x & 63;
+  for (int c = lane; c < nc; c += 128) {
+    double m[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cc = c + 64 * u;
+        bool keep = mr[q] && cc < nc;
+        if constexpr (TRI == 0) keep = keep && c0 + cc >= iq[q];
+        if constexpr (TRI == 1) keep = keep && c0 + cc < iq[q];
+        m[u][q] = keep ? mr[q][cc] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int cc = c + 64 * u;
+      if (cc < nc)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int v = 0; v < kMaxV; ++v)
+            if (v < nv) acc[q][v] += m[u][q] * s[v][cc];
+    }
+  }
+}
+
 // First step of an up pass (and of the transposed solve's down pass), column
 // form: B(v, i) = u_r(v, c) - (M^T u_s)(v, c) with c = perm[i] (PERM: the
 // row interchanges of the solve, B = P(u_r - T^T u_s)) or c = i, and
@@ -1062,18 +1097,13 @@ __global__ __launch_bounds__(256) void k_sp_down_first(SpArgs A) {
     __syncthreads();
     for (int e = threadIdx.x; e < nv * nj; e += 256) sus[e / nj][e % nj] = A.u[(e / nj) * A.N + R.sk[j0 + e % nj]];
     __syncthreads();
+    const double* mr[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = i0 + wv * 4 + q;
-      if (i >= R.r) break;
-      const double* mr = R.Urs + int64_t(i) * R.k + j0;
-      for (int j = lane; j < nj; j += 64) {
-        const double m = mr[j];
-#pragma unroll
-        for (int v = 0; v < kMaxV; ++v)
-          if (v < nv) acc[q][v] += m * sus[v][j];
-      }
+      mr[q] = i < R.r ? R.Urs + int64_t(i) * R.k + j0 : nullptr;
     }
+    sp_rows4_acc(mr, nj, sus, nv, acc);
   }
   {
     const double t = sp_rows_sum(acc);
@@ -1105,18 +1135,13 @@ __global__ __launch_bounds__(256) void k_sp_skel_update(SpArgs A, int which, dou
     for (int e = threadIdx.x; e < nv * nc; e += 256)
       sx[e / nc][e % nc] = GATHER ? A.u[(e / nc) * A.N + R.rd[c0 + e % nc]] : R.X[(e / nc) * R.r + c0 + e % nc];
     __syncthreads();
+    const double* mr[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = j0 + wv * 4 + q;
-      if (j >= R.k) break;
-      const double* mr = M + int64_t(j) * R.r + c0;
-      for (int c = lane; c < nc; c += 64) {
-        const double m = mr[c];
-#pragma unroll
-        for (int v = 0; v < kMaxV; ++v)
-          if (v < nv) acc[q][v] += m * sx[v][c];
-      }
+      mr[q] = j < R.k ? M + int64_t(j) * R.r + c0 : nullptr;
     }
+    sp_rows4_acc(mr, nc, sx, nv, acc);
   }
   {
     const double t = sp_rows_sum(acc);
@@ -1223,20 +1248,14 @@ __global__ __launch_bounds__(256) void k_sp_rowmv(SpArgs A, int io) {
     __syncthreads();
     for (int e = threadIdx.x; e < nv * nc; e += 256) sx[e / nc][e % nc] = x[(e / nc) * r + c0 + e % nc];
     __syncthreads();
+    const double* mr[4];
+    int iq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = i0 + wv * 4 + q;
-      if (i < r) {
-        const double* mr = R.LU + int64_t(i) * r + c0;
-        for (int c = lane; c < nc; c += 64) {
-          const int j = c0 + c;
-          const double m = (TRI == 0 ? j >= i : j < i) ? mr[c] : 0.0;
-#pragma unroll
-          for (int v = 0; v < kMaxV; ++v)
-            if (v < nv) acc[q][v] += m * sx[v][c];
-        }
-      }
+      iq[q] = i0 + wv * 4 + q;
+      mr[q] = iq[q] < r ? R.LU + int64_t(iq[q]) * r + c0 : nullptr;
     }
+    sp_rows4_acc<TRI == 0 ? 0 : 1>(mr, nc, sx, nv, acc, c0, iq);
   }
   if (RECT)
     for (int j0 = 0; j0 < R.k; j0 += kSpChunk) {
@@ -1244,19 +1263,13 @@ __global__ __launch_bounds__(256) void k_sp_rowmv(SpArgs A, int io) {
       __syncthreads();
       for (int e = threadIdx.x; e < nv * nj; e += 256) sx[e / nj][e % nj] = A.u[(e / nj) * A.N + R.sk[j0 + e % nj]];
       __syncthreads();
+      const double* mr[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = i0 + wv * 4 + q;
-        if (i < r) {
-          const double* mr = R.Urs + int64_t(i) * R.k + j0;
-          for (int j = lane; j < nj; j += 64) {
-            const double m = mr[j];
-#pragma unroll
-            for (int v = 0; v < kMaxV; ++v)
-              if (v < nv) acc[q][v] += m * sx[v][j];
-          }
-        }
+        mr[q] = i < r ? R.Urs + int64_t(i) * R.k + j0 : nullptr;
       }
+      sp_rows4_acc(mr, nj, sx, nv, acc);
     }
   {
     const double t = sp_rows_sum(acc);
