@@ -969,6 +969,7 @@ __device__ __forceinline__ void sp_ready_chain(const SpArgs& A, const SpRec& R, 
 }
 
 constexpr int kSpChunk = 512;  // skeleton entries staged in LDS per pass
+constexpr int kUc = 16;         // loads in flight per lane in the column-form products
 
 // The sums over the wave of acc[q][v] (4 rows q of the wave, kMaxV
 // right-hand sides) in one reduce-scatter: returns the total of row q =
@@ -1049,12 +1050,12 @@ __global__ __launch_bounds__(256) void k_sp_first_cols(SpArgs A) {
     const int jb = (nj * wv) / 4, je = (nj * (wv + 1)) / 4;
     if (i < R.r) {
       const double* tc = M + int64_t(j0) * R.r + c;
-      for (int j = jb; j < je; j += kU) {
-        double t[kU];
+      for (int j = jb; j < je; j += kUc) {
+        double t[kUc];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) t[u] = j + u < je ? tc[int64_t(j + u) * R.r] : 0.0;
+        for (int u = 0; u < kUc; ++u) t[u] = j + u < je ? tc[int64_t(j + u) * R.r] : 0.0;
 #pragma unroll
-        for (int u = 0; u < kU; ++u)
+        for (int u = 0; u < kUc; ++u)
           if (j + u < je)
 #pragma unroll
             for (int v = 0; v < kMaxV; ++v)
@@ -1175,12 +1176,12 @@ __global__ __launch_bounds__(256) void k_sp_skel_update_T(SpArgs A, double sgn) 
     const int ib = (ni * wv) / 4, ie = (ni * (wv + 1)) / 4;
     if (j < R.k) {
       const double* mc = R.Urs + int64_t(i0) * R.k + j;
-      for (int i = ib; i < ie; i += kU) {
-        double m[kU];
+      for (int i = ib; i < ie; i += kUc) {
+        double m[kUc];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) m[u] = i + u < ie ? mc[int64_t(i + u) * R.k] : 0.0;
+        for (int u = 0; u < kUc; ++u) m[u] = i + u < ie ? mc[int64_t(i + u) * R.k] : 0.0;
 #pragma unroll
-        for (int u = 0; u < kU; ++u)
+        for (int u = 0; u < kUc; ++u)
           if (i + u < ie)
 #pragma unroll
             for (int v = 0; v < kMaxV; ++v)
@@ -1306,15 +1307,15 @@ __global__ __launch_bounds__(256) void k_sp_colmv(SpArgs A, int io) {
     const int qb = (nj * wv) / 4, qe = (nj * (wv + 1)) / 4;
     if (i < r) {
       const double* mc = R.LU + int64_t(j0) * r + i;
-      for (int j = qb; j < qe; j += kU) {
-        double m[kU];
+      for (int j = qb; j < qe; j += kUc) {
+        double m[kUc];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < kUc; ++u) {
           const int jr = j0 + j + u;
           m[u] = (j + u < qe && (TRI == 2 ? jr > i : jr <= i)) ? mc[int64_t(j + u) * r] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kU; ++u)
+        for (int u = 0; u < kUc; ++u)
           if (j + u < qe)
 #pragma unroll
             for (int v = 0; v < kMaxV; ++v)
@@ -1331,12 +1332,12 @@ __global__ __launch_bounds__(256) void k_sp_colmv(SpArgs A, int io) {
       const int qb = (nj * wv) / 4, qe = (nj * (wv + 1)) / 4;
       if (i < r) {
         const double* mc = R.Lsr + int64_t(j0) * r + i;
-        for (int j = qb; j < qe; j += kU) {
-          double m[kU];
+        for (int j = qb; j < qe; j += kUc) {
+          double m[kUc];
 #pragma unroll
-          for (int u = 0; u < kU; ++u) m[u] = j + u < qe ? mc[int64_t(j + u) * r] : 0.0;
+          for (int u = 0; u < kUc; ++u) m[u] = j + u < qe ? mc[int64_t(j + u) * r] : 0.0;
 #pragma unroll
-          for (int u = 0; u < kU; ++u)
+          for (int u = 0; u < kUc; ++u)
             if (j + u < qe)
 #pragma unroll
               for (int v = 0; v < kMaxV; ++v)
