@@ -409,6 +409,45 @@ __device__ __forceinline__ void l_gemv_n(const double* __restrict__ M, int nrow,
     }
     return;
   }
+  if (ncol <= 128) {
+    // rows of at most two entries per lane: four rows of the wave at a time,
+    // their eight loads issued together, x read from LDS (no more registers
+    // than one row at a time); each sum in the order of the general path
+    for (int i0 = wv; i0 < nrow; i0 += 4 * nw) {
+      double m[4][2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + q * nw;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int j = 64 * h + lane;
+          m[q][h] = (i < nrow && j < ncol) ? M[int64_t(i) * ld + j] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + q * nw;
+        if (i < nrow) {
+          double acc[kMaxV];
+#pragma unroll
+          for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int j = 64 * h + lane;
+            if (j < ncol) {
+#pragma unroll
+              for (int v = 0; v < kMaxV; ++v)
+                if (v < nv) acc[v] += m[q][h] * x[v * xs + j];
+            }
+          }
+          const double t = wave_rs8(acc);
+          const int v = lane >> 3;
+          if ((lane & 7) == 0 && v < nv) y[v * ys + i] += sgn * t;
+        }
+      }
+    }
+    return;
+  }
   for (int i = wv; i < nrow; i += nw) {
     const double* mr = M + int64_t(i) * ld;
     double acc[kMaxV];
@@ -741,8 +780,10 @@ __device__ __forceinline__ void l_permute(const int32_t* perm, int n, double* x,
 // the upward sweep (finest sub-level first), 1 for the downward one.  The LDS
 // holds cap doubles (sized by the launch to the sub-level's largest record);
 // the caller guarantees 2r + k <= cap.
+// Registers are capped for 4 waves per SIMD (a few bytes spill): the
+// 1024 records of a 512^2 level-1 sub-level then all run at once, 4 per CU.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_sweep_lds(SwArgs A, int down, int cap) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_lds(SwArgs A, int down, int cap) {
   extern __shared__ double sm[];
   const GroupRec R = A.recs[blockIdx.x];
   const int r = R.r, k = R.k;
