@@ -529,25 +529,6 @@ __device__ __forceinline__ void l_gemv_t(const double* __restrict__ M, int nrow,
   __syncthreads();
 }
 
-// acc[v] = sum_{c < nb} seg[c * cs] x[v*xs + x0 + c]  (a row or column segment of LU)
-__device__ __forceinline__ void seg_dot(const double* seg, int64_t cs, int nb, const double* x, int xs, int x0, int nv,
-                                        double (&acc)[kMaxV]) {
-#pragma unroll
-  for (int v = 0; v < kMaxV; ++v) acc[v] = 0.0;
-  for (int c0 = 0; c0 < nb; c0 += kU) {
-    double l[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) l[u] = c0 + u < nb ? seg[(c0 + u) * cs] : 0.0;
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (c0 + u < nb) {
-#pragma unroll
-        for (int v = 0; v < kMaxV; ++v)
-          if (v < nv) acc[v] += l[u] * x[v * xs + x0 + c0 + u];
-      }
-  }
-}
-
 // x = L^{-1} x, L the unit lower triangle of the row-major n x n LU.
 __device__ __forceinline__ void l_solve_L(const double* __restrict__ LU, int n, double* x, int xs, int nv) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
@@ -572,13 +553,8 @@ __device__ __forceinline__ void l_solve_L(const double* __restrict__ LU, int n, 
       if (lane < nb) x[v * xs + j0 + lane] = xi;
     }
     __syncthreads();
-    for (int i = j0 + nb + tid; i < n; i += blockDim.x) {
-      double acc[kMaxV];
-      seg_dot(LU + int64_t(i) * n + j0, 1, nb, x, xs, j0, nv, acc);
-#pragma unroll
-      for (int v = 0; v < kMaxV; ++v)
-        if (v < nv) x[v * xs + i] -= acc[v];
-    }
+    // the rows below: x_i -= L(i, block) x_block, four rows of a wave at a time
+    if (j0 + nb < n) l_gemv_n(LU + int64_t(j0 + nb) * n + j0, n - j0 - nb, nb, n, x + j0, xs, x + j0 + nb, xs, nv, -1.0);
     __syncthreads();
   }
 }
@@ -609,13 +585,8 @@ __device__ __forceinline__ void l_solve_U(const double* __restrict__ LU, int n, 
       if (lane < nb) x[v * xs + j0 + lane] = xi;
     }
     __syncthreads();
-    for (int i = tid; i < j0; i += blockDim.x) {
-      double acc[kMaxV];
-      seg_dot(LU + int64_t(i) * n + j0, 1, nb, x, xs, j0, nv, acc);
-#pragma unroll
-      for (int v = 0; v < kMaxV; ++v)
-        if (v < nv) x[v * xs + i] -= acc[v];
-    }
+    // the rows above: x_i -= U(i, block) x_block
+    if (j0 > 0) l_gemv_n(LU + j0, j0, nb, n, x + j0, xs, x, xs, nv, -1.0);
     __syncthreads();
   }
 }
@@ -649,13 +620,8 @@ __device__ __forceinline__ void l_solve_UT(const double* __restrict__ LU, int n,
       if (lane < nb) x[v * xs + j0 + lane] = xi;
     }
     __syncthreads();
-    for (int i = j0 + nb + tid; i < n; i += blockDim.x) {
-      double acc[kMaxV];
-      seg_dot(LU + int64_t(j0) * n + i, n, nb, x, xs, j0, nv, acc);
-#pragma unroll
-      for (int v = 0; v < kMaxV; ++v)
-        if (v < nv) x[v * xs + i] -= acc[v];
-    }
+    // the entries below: x_i -= sum_c U(j0 + c, i) x_{j0 + c} (rows of the block, read by columns)
+    if (j0 + nb < n) l_gemv_t(LU + int64_t(j0) * n + j0 + nb, nb, n - j0 - nb, n, x + j0, xs, x + j0 + nb, xs, nv, -1.0);
     __syncthreads();
   }
 }
@@ -688,13 +654,8 @@ __device__ __forceinline__ void l_solve_LT(const double* __restrict__ LU, int n,
       if (lane < nb) x[v * xs + j0 + lane] = xi;
     }
     __syncthreads();
-    for (int i = tid; i < j0; i += blockDim.x) {
-      double acc[kMaxV];
-      seg_dot(LU + int64_t(j0) * n + i, n, nb, x, xs, j0, nv, acc);
-#pragma unroll
-      for (int v = 0; v < kMaxV; ++v)
-        if (v < nv) x[v * xs + i] -= acc[v];
-    }
+    // the entries above: x_i -= sum_c L(j0 + c, i) x_{j0 + c}
+    if (j0 > 0) l_gemv_t(LU + int64_t(j0) * n, nb, j0, n, x + j0, xs, x, xs, nv, -1.0);
     __syncthreads();
   }
 }
