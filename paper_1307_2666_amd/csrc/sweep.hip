@@ -741,8 +741,9 @@ __device__ __forceinline__ void l_permute(const int32_t* perm, int n, double* x,
 // the upward sweep (finest sub-level first), 1 for the downward one.  The LDS
 // holds cap doubles (sized by the launch to the sub-level's largest record);
 // the caller guarantees 2r + k <= cap.
-// Registers are capped for 4 waves per SIMD (a few bytes spill): the
-// 1024 records of a 512^2 level-1 sub-level then all run at once, 4 per CU.
+// Registers are capped for 4 waves per SIMD (only the 64-thread shape
+// spills, a few bytes): the 1024 records of a 512^2 level-1 sub-level then
+// all run at once, 4 per CU.
 template <int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_lds(SwArgs A, int down, int cap) {
   extern __shared__ double sm[];
