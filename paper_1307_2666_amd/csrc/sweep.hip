@@ -987,6 +987,23 @@ __device__ __forceinline__ double sp_rows_sum(const double (&acc)[4][kMaxV]) {
   return wave_rs32(p);
 }
 
+// dst[v][e] = src(v, e) for e < n, v < nv, with src(v, e) = base[v ld + idx[e]]
+// (idx given) or base[v ld + e]: an entry per thread and step, its index
+// loaded once and its right-hand sides' loads issued together before any is
+// stored (the caller synchronizes before the block is read).
+__device__ __forceinline__ void sp_stage(const double* base, int64_t ld, const int32_t* idx, int n, int nv,
+                                         double (*dst)[kSpChunk]) {
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int64_t g = idx ? int64_t(idx[e]) : int64_t(e);
+    double t[kMaxV];
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v) t[v] = v < nv ? base[v * ld + g] : 0.0;
+#pragma unroll
+    for (int v = 0; v < kMaxV; ++v)
+      if (v < nv) dst[v][e] = t[v];
+  }
+}
+
 // acc[q][v] += sum_{c < nc} mr[q][c] s[v][c] for a wave's 4 rows q (mr[q] null
 // past the record; its sums are then never used), lane c = lane, lane + 64, ...
 // The loads of the 4 rows and of two column steps are issued together before
@@ -1047,7 +1064,7 @@ __global__ __launch_bounds__(256) void k_sp_first_cols(SpArgs A) {
   for (int j0 = 0; j0 < R.k; j0 += kSpChunk) {
     const int nj = min(kSpChunk, R.k - j0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nv * nj; e += 256) sus[e / nj][e % nj] = A.u[(e / nj) * A.N + R.sk[j0 + e % nj]];
+    sp_stage(A.u, A.N, R.sk + j0, nj, nv, sus);
     __syncthreads();
     // wave wv takes the quarter [jb, je) of the chunk
     const int jb = (nj * wv) / 4, je = (nj * (wv + 1)) / 4;
@@ -1099,7 +1116,7 @@ __global__ __launch_bounds__(256) void k_sp_down_first(SpArgs A) {
   for (int j0 = 0; j0 < R.k; j0 += kSpChunk) {
     const int nj = min(kSpChunk, R.k - j0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nv * nj; e += 256) sus[e / nj][e % nj] = A.u[(e / nj) * A.N + R.sk[j0 + e % nj]];
+    sp_stage(A.u, A.N, R.sk + j0, nj, nv, sus);
     __syncthreads();
     const double* mr[4];
 #pragma unroll
@@ -1136,8 +1153,10 @@ __global__ __launch_bounds__(256) void k_sp_skel_update(SpArgs A, int which, dou
   for (int c0 = 0; c0 < R.r; c0 += kSpChunk) {
     const int nc = min(kSpChunk, R.r - c0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nv * nc; e += 256)
-      sx[e / nc][e % nc] = GATHER ? A.u[(e / nc) * A.N + R.rd[c0 + e % nc]] : R.X[(e / nc) * R.r + c0 + e % nc];
+    if (GATHER)
+      sp_stage(A.u, A.N, R.rd + c0, nc, nv, sx);
+    else
+      sp_stage(R.X + c0, R.r, nullptr, nc, nv, sx);
     __syncthreads();
     const double* mr[4];
 #pragma unroll
@@ -1173,8 +1192,10 @@ __global__ __launch_bounds__(256) void k_sp_skel_update_T(SpArgs A, double sgn) 
   for (int i0 = 0; i0 < R.r; i0 += kSpChunk) {
     const int ni = min(kSpChunk, R.r - i0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nv * ni; e += 256)
-      sx[e / ni][e % ni] = GATHER ? A.u[(e / ni) * A.N + R.rd[i0 + e % ni]] : R.X[(e / ni) * R.r + i0 + e % ni];
+    if (GATHER)
+      sp_stage(A.u, A.N, R.rd + i0, ni, nv, sx);
+    else
+      sp_stage(R.X + i0, R.r, nullptr, ni, nv, sx);
     __syncthreads();
     const int ib = (ni * wv) / 4, ie = (ni * (wv + 1)) / 4;
     if (j < R.k) {
@@ -1250,7 +1271,7 @@ __global__ __launch_bounds__(256) void k_sp_rowmv(SpArgs A, int io) {
   for (int c0 = cb; c0 < ce; c0 += kSpChunk) {
     const int nc = min(kSpChunk, ce - c0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nv * nc; e += 256) sx[e / nc][e % nc] = x[(e / nc) * r + c0 + e % nc];
+    sp_stage(x + c0, r, nullptr, nc, nv, sx);
     __syncthreads();
     const double* mr[4];
     int iq[4];
@@ -1265,7 +1286,7 @@ __global__ __launch_bounds__(256) void k_sp_rowmv(SpArgs A, int io) {
     for (int j0 = 0; j0 < R.k; j0 += kSpChunk) {
       const int nj = min(kSpChunk, R.k - j0);
       __syncthreads();
-      for (int e = threadIdx.x; e < nv * nj; e += 256) sx[e / nj][e % nj] = A.u[(e / nj) * A.N + R.sk[j0 + e % nj]];
+      sp_stage(A.u, A.N, R.sk + j0, nj, nv, sx);
       __syncthreads();
       const double* mr[4];
 #pragma unroll
@@ -1305,7 +1326,7 @@ __global__ __launch_bounds__(256) void k_sp_colmv(SpArgs A, int io) {
   for (int j0 = jb; j0 < je; j0 += kSpChunk) {
     const int nj = min(kSpChunk, je - j0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nv * nj; e += 256) sx[e / nj][e % nj] = x[(e / nj) * r + j0 + e % nj];
+    sp_stage(x + j0, r, nullptr, nj, nv, sx);
     __syncthreads();
     const int qb = (nj * wv) / 4, qe = (nj * (wv + 1)) / 4;
     if (i < r) {
@@ -1330,7 +1351,7 @@ __global__ __launch_bounds__(256) void k_sp_colmv(SpArgs A, int io) {
     for (int j0 = 0; j0 < R.k; j0 += kSpChunk) {
       const int nj = min(kSpChunk, R.k - j0);
       __syncthreads();
-      for (int e = threadIdx.x; e < nv * nj; e += 256) sx[e / nj][e % nj] = A.u[(e / nj) * A.N + R.sk[j0 + e % nj]];
+      sp_stage(A.u, A.N, R.sk + j0, nj, nv, sx);
       __syncthreads();
       const int qb = (nj * wv) / 4, qe = (nj * (wv + 1)) / 4;
       if (i < r) {
