@@ -583,7 +583,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32/f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: 2D Laplace second-kind volume IE, {wl.n}x{wl.n} grid (N={N}), "
+        "config": {"workload": f"{wl.name}: {wl.d}D Laplace second-kind volume IE, "
+                               f"{'x'.join([str(wl.n)] * wl.d)} grid (N={N}), "
                                f"{nrhs} RHS, eps={eps:g}, leaf {wl.leaf}, " +
                                ("HIF-IE without the second-kind modification, FP32 entries and matrix-core "
                                 "GEMMs, FP64 IDs, LU and sweeps" if mixed else
