@@ -19,6 +19,7 @@
 // through the records' global DOF indices.
 #include <mutex>
 #include <string>
+#include <type_traits>
 
 #include "common.h"
 #include "wave.h"
@@ -535,22 +536,39 @@ __device__ __forceinline__ void l_solve_L(const double* __restrict__ LU, int n, 
   for (int j0 = 0; j0 < n; j0 += kNbT) {
     const int nb = min(kNbT, n - j0);
     const double* Lr = LU + int64_t(j0 + min(lane, nb - 1)) * n + j0;
-    for (int v = wv; v < nv; v += nw) {
-      double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
-      for (int c0 = 0; c0 < nb - 1; c0 += kU) {
-        double lr[kU];
+    // a wave takes right-hand sides v and v + nw together: one load of each
+    // entry of L for both
+    for (int v = wv; v < nv; v += 2 * nw) {
+      auto pass = [&](auto two_c) {
+        constexpr bool TWO = decltype(two_c)::value;
+        double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
+        double xj = TWO && lane < nb ? x[(v + nw) * xs + j0 + lane] : 0.0;
+        for (int c0 = 0; c0 < nb - 1; c0 += kU) {
+          double lr[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) lr[u] = c0 + u < nb ? Lr[c0 + u] : 0.0;
+          for (int u = 0; u < kU; ++u) lr[u] = c0 + u < nb ? Lr[c0 + u] : 0.0;
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int c = c0 + u;
-          if (c < nb - 1) {
-            const double xc = __shfl(xi, c, 64);
-            if (lane > c && lane < nb) xi -= lr[u] * xc;
+          for (int u = 0; u < kU; ++u) {
+            const int c = c0 + u;
+            if (c < nb - 1) {
+              const double xc = __shfl(xi, c, 64);
+              if (lane > c && lane < nb) xi -= lr[u] * xc;
+              if constexpr (TWO) {
+                const double xd = __shfl(xj, c, 64);
+                if (lane > c && lane < nb) xj -= lr[u] * xd;
+              }
+            }
           }
         }
-      }
-      if (lane < nb) x[v * xs + j0 + lane] = xi;
+        if (lane < nb) {
+          x[v * xs + j0 + lane] = xi;
+          if constexpr (TWO) x[(v + nw) * xs + j0 + lane] = xj;
+        }
+      };
+      if (v + nw < nv)
+        pass(std::true_type{});
+      else
+        pass(std::false_type{});
     }
     __syncthreads();
     // the rows below: x_i -= L(i, block) x_block, four rows of a wave at a time
@@ -566,23 +584,39 @@ __device__ __forceinline__ void l_solve_U(const double* __restrict__ LU, int n, 
   for (int j0 = ((n - 1) / kNbT) * kNbT; j0 >= 0; j0 -= kNbT) {
     const int nb = min(kNbT, n - j0);
     const double* Ur = LU + int64_t(j0 + min(lane, nb - 1)) * n + j0;
-    for (int v = wv; v < nv; v += nw) {
-      double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
-      for (int cb = ((nb - 1) / kU) * kU; cb >= 0; cb -= kU) {
-        double ur[kU];
+    for (int v = wv; v < nv; v += 2 * nw) {  // two right-hand sides per pass, as in l_solve_L
+      auto pass = [&](auto two_c) {
+        constexpr bool TWO = decltype(two_c)::value;
+        double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
+        double xj = TWO && lane < nb ? x[(v + nw) * xs + j0 + lane] : 0.0;
+        for (int cb = ((nb - 1) / kU) * kU; cb >= 0; cb -= kU) {
+          double ur[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) ur[u] = cb + u < nb ? Ur[cb + u] : 1.0;
+          for (int u = 0; u < kU; ++u) ur[u] = cb + u < nb ? Ur[cb + u] : 1.0;
 #pragma unroll
-        for (int u = kU - 1; u >= 0; --u) {
-          const int c = cb + u;
-          if (c < nb) {
-            if (lane == c) xi = xi / ur[u];
-            const double xc = __shfl(xi, c, 64);
-            if (lane < c) xi -= ur[u] * xc;
+          for (int u = kU - 1; u >= 0; --u) {
+            const int c = cb + u;
+            if (c < nb) {
+              if (lane == c) xi = xi / ur[u];
+              const double xc = __shfl(xi, c, 64);
+              if (lane < c) xi -= ur[u] * xc;
+              if constexpr (TWO) {
+                if (lane == c) xj = xj / ur[u];
+                const double xd = __shfl(xj, c, 64);
+                if (lane < c) xj -= ur[u] * xd;
+              }
+            }
           }
         }
-      }
-      if (lane < nb) x[v * xs + j0 + lane] = xi;
+        if (lane < nb) {
+          x[v * xs + j0 + lane] = xi;
+          if constexpr (TWO) x[(v + nw) * xs + j0 + lane] = xj;
+        }
+      };
+      if (v + nw < nv)
+        pass(std::true_type{});
+      else
+        pass(std::false_type{});
     }
     __syncthreads();
     // the rows above: x_i -= U(i, block) x_block
@@ -597,27 +631,43 @@ __device__ __forceinline__ void l_solve_UT(const double* __restrict__ LU, int n,
   for (int j0 = 0; j0 < n; j0 += kNbT) {
     const int nb = min(kNbT, n - j0);
     const int cl = j0 + min(lane, nb - 1);
-    for (int v = wv; v < nv; v += nw) {
-      double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
-      for (int c0 = 0; c0 < nb; c0 += kU) {
-        double uc[kU], ud[kU];
+    for (int v = wv; v < nv; v += 2 * nw) {  // two right-hand sides per pass, as in l_solve_L
+      auto pass = [&](auto two_c) {
+        constexpr bool TWO = decltype(two_c)::value;
+        double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
+        double xj = TWO && lane < nb ? x[(v + nw) * xs + j0 + lane] : 0.0;
+        for (int c0 = 0; c0 < nb; c0 += kU) {
+          double uc[kU], ud[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int c = c0 + u < nb ? c0 + u : nb - 1;
-          uc[u] = LU[int64_t(j0 + c) * n + cl];
-          ud[u] = LU[int64_t(j0 + c) * n + j0 + c];
-        }
+          for (int u = 0; u < kU; ++u) {
+            const int c = c0 + u < nb ? c0 + u : nb - 1;
+            uc[u] = LU[int64_t(j0 + c) * n + cl];
+            ud[u] = LU[int64_t(j0 + c) * n + j0 + c];
+          }
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int c = c0 + u;
-          if (c < nb) {
-            if (lane == c) xi = xi / ud[u];
-            const double xc = __shfl(xi, c, 64);
-            if (lane > c && lane < nb) xi -= uc[u] * xc;
+          for (int u = 0; u < kU; ++u) {
+            const int c = c0 + u;
+            if (c < nb) {
+              if (lane == c) xi = xi / ud[u];
+              const double xc = __shfl(xi, c, 64);
+              if (lane > c && lane < nb) xi -= uc[u] * xc;
+              if constexpr (TWO) {
+                if (lane == c) xj = xj / ud[u];
+                const double xd = __shfl(xj, c, 64);
+                if (lane > c && lane < nb) xj -= uc[u] * xd;
+              }
+            }
           }
         }
-      }
-      if (lane < nb) x[v * xs + j0 + lane] = xi;
+        if (lane < nb) {
+          x[v * xs + j0 + lane] = xi;
+          if constexpr (TWO) x[(v + nw) * xs + j0 + lane] = xj;
+        }
+      };
+      if (v + nw < nv)
+        pass(std::true_type{});
+      else
+        pass(std::false_type{});
     }
     __syncthreads();
     // the entries below: x_i -= sum_c U(j0 + c, i) x_{j0 + c} (rows of the block, read by columns)
@@ -633,25 +683,40 @@ __device__ __forceinline__ void l_solve_LT(const double* __restrict__ LU, int n,
   for (int j0 = ((n - 1) / kNbT) * kNbT; j0 >= 0; j0 -= kNbT) {
     const int nb = min(kNbT, n - j0);
     const int cl = j0 + min(lane, nb - 1);
-    for (int v = wv; v < nv; v += nw) {
-      double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
-      for (int cb = ((nb - 1) / kU) * kU; cb >= 0; cb -= kU) {
-        double lc[kU];
+    for (int v = wv; v < nv; v += 2 * nw) {  // two right-hand sides per pass, as in l_solve_L
+      auto pass = [&](auto two_c) {
+        constexpr bool TWO = decltype(two_c)::value;
+        double xi = lane < nb ? x[v * xs + j0 + lane] : 0.0;
+        double xj = TWO && lane < nb ? x[(v + nw) * xs + j0 + lane] : 0.0;
+        for (int cb = ((nb - 1) / kU) * kU; cb >= 0; cb -= kU) {
+          double lc[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int c = cb + u < nb ? cb + u : nb - 1;
-          lc[u] = LU[int64_t(j0 + c) * n + cl];
-        }
+          for (int u = 0; u < kU; ++u) {
+            const int c = cb + u < nb ? cb + u : nb - 1;
+            lc[u] = LU[int64_t(j0 + c) * n + cl];
+          }
 #pragma unroll
-        for (int u = kU - 1; u >= 0; --u) {
-          const int c = cb + u;
-          if (c < nb && c > 0) {
-            const double xc = __shfl(xi, c, 64);
-            if (lane < c) xi -= lc[u] * xc;
+          for (int u = kU - 1; u >= 0; --u) {
+            const int c = cb + u;
+            if (c < nb && c > 0) {
+              const double xc = __shfl(xi, c, 64);
+              if (lane < c) xi -= lc[u] * xc;
+              if constexpr (TWO) {
+                const double xd = __shfl(xj, c, 64);
+                if (lane < c) xj -= lc[u] * xd;
+              }
+            }
           }
         }
-      }
-      if (lane < nb) x[v * xs + j0 + lane] = xi;
+        if (lane < nb) {
+          x[v * xs + j0 + lane] = xi;
+          if constexpr (TWO) x[(v + nw) * xs + j0 + lane] = xj;
+        }
+      };
+      if (v + nw < nv)
+        pass(std::true_type{});
+      else
+        pass(std::false_type{});
     }
     __syncthreads();
     // the entries above: x_i -= sum_c L(j0 + c, i) x_{j0 + c}
